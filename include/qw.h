@@ -1,0 +1,145 @@
+/*
+ * qw.h -- C ABI of the MI355X (gfx950) Dirac quantum-walk library (libqw.so).
+ *
+ * The library evolves the spinor field of the discrete-time Dirac quantum
+ * walk of D'Ariano, Mosco, Perinotti and Tosini, "Discrete Time Dirac Quantum
+ * Walk in 3+1 Dimensions", on a periodic lattice, in the two ways Sec. 4 of
+ * the paper names: step by step in position space, and in one jump through
+ * the Fourier representation. It also computes the position and overlap
+ * reductions of Sec. 5.
+ *
+ * Lattices (Sec. 3.1): d = 1 (the line), d = 2 (the square lattice), d = 3
+ * (the BCC lattice). Sites are stored in primitive-cell coordinates
+ * n = (n_1, .., n_d), 0 <= n_i < N_i, periodic; the Cartesian site is
+ * x = sum_j n_j h_j with h_j the generators: 3D h1 = (1,1,1), h2 = (1,-1,-1),
+ * h3 = (-1,1,-1); 2D h1 = (1,1), h2 = (1,-1); 1D h = 1.
+ *
+ * Field layout (all field pointers are DEVICE pointers owned by the caller):
+ *   component-major planes, psi[c * V + lin(n)], V = N_1 * .. * N_d,
+ *   lin(n) row-major with n_d fastest; each entry is an interleaved complex
+ *   number (re, im): two floats for QW_C64, two doubles for QW_C128.
+ *   The spinor has s = 2 components for d = 1 and s = 4 for d = 2, 3, in the
+ *   row order of the matrix D_k printed in Sec. 3.2.
+ *   One field occupies s * V * (8 or 16) bytes and must be 16-byte aligned.
+ *
+ * Execution: every call is enqueued on `stream` (a hipStream_t; NULL is the
+ * null stream) and returns without waiting, except qw_observables and
+ * qw_prepare_state, which wait for their results. A plan may be used by one
+ * stream at a time; distinct plans are independent.
+ *
+ * Errors: every call returns a qw_status; nothing throws across the ABI.
+ * qw_last_error() returns a message for the last failing call of the calling
+ * thread. Arguments are validated before any work is enqueued, so a call
+ * that returns QW_ERR_INVALID or QW_ERR_UNSUPPORTED has changed nothing.
+ */
+#ifndef QW_H
+#define QW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qw_plan_s* qw_plan_t;
+
+typedef enum {
+  QW_OK = 0,
+  QW_ERR_INVALID = 1,      /* bad argument (null pointer, m outside [0,1], ...) */
+  QW_ERR_UNSUPPORTED = 2,  /* valid but not provided (N not a power of two, too large) */
+  QW_ERR_NOMEM = 3,        /* device or host allocation failed */
+  QW_ERR_DEVICE = 4        /* a HIP call or kernel launch failed */
+} qw_status;
+
+typedef enum { QW_C64 = 0, QW_C128 = 1 } qw_dtype;
+
+/* Reductions of one field (Sec. 5.2: position operator X and <psi|X|psi>;
+ * Sec. 5.1: the overlap <phi|psi>). Positions are taken about a caller origin
+ * c with the minimum image w_i = ((n_i - c_i + N_i/2) mod N_i) - N_i/2 in
+ * [-N_i/2, N_i/2) per primitive axis; unused axes are 0. */
+typedef struct {
+  double norm2;        /* sum over sites and components of |psi|^2 */
+  double mean[3];      /* c_i + sum w_i |psi|^2 / norm2 (primitive coordinates) */
+  double second[6];    /* sum w_i w_j |psi|^2 / norm2 for ij = 00,11,22,01,02,12 */
+  double mean_cart[3]; /* sum_j mean_j h_j (Cartesian) */
+  double overlap_re;   /* Re sum conj(ref) psi   (0 if ref is NULL) */
+  double overlap_im;   /* Im sum conj(ref) psi   (0 if ref is NULL) */
+  double ref_norm2;    /* sum |ref|^2            (0 if ref is NULL) */
+} qw_obs;
+
+/* Create a plan for one lattice shape and mass (Sec. 3.2: the Dirac walk
+ * D_k = [[n W_k, i m], [i m, n W_k^dag]], n = sqrt(1 - m^2); in 1D the
+ * two-component form [[n e^{-ik}, i m], [i m, n e^{ik}]]).
+ *   dim    1, 2 or 3.
+ *   N      dim entries, each a power of two: 1D 2..65536; 2D 2..1024 per axis;
+ *          3D 2..512 per axis. Other values give QW_ERR_UNSUPPORTED.
+ *   m      mass, 0 <= m <= 1 (QW_ERR_INVALID otherwise, NaN included).
+ *   dtype  arithmetic of the field: QW_C64 (complex FP32; the phase
+ *          omega(k) t is still formed and reduced in FP64) or QW_C128.
+ *   stream stream for the set-up uploads.
+ * The plan derives the transition matrices U_h of the update rule from the
+ * symbol (Sec. 2.1, U_k = sum_h e^{-ik.h} U_h) in FP64 and checks the
+ * unitarity conditions of Sec. 2 on them; it owns its device tables and
+ * scratch memory, released by qw_destroy. */
+qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype dtype,
+                  void* stream);
+
+/* Release a plan and everything it owns. Waits for the plan's work. NULL is a no-op. */
+qw_status qw_destroy(qw_plan_t plan);
+
+/* nsteps >= 0 applications of the update rule psi(x,t+1) = sum_h U_h psi(x+h,t)
+ * (Sec. 2, update rule and walk operator), in place on psi. The plan's
+ * scratch holds the second buffer of the ping-pong. */
+qw_status qw_step(qw_plan_t plan, void* psi, int64_t nsteps, void* stream);
+
+/* psi_t = U^t psi0 in one jump through the Fourier representation (Sec. 4):
+ * forward DFT with the sign of Sec. 4, per wave-vector the closed form
+ * D_q^t = cos(omega t) I - i sin(omega t)/sin(omega) M_q (from
+ * D_q = cos(omega) I - i M_q, Sec. 3.2 gamma-matrix form and interpolating
+ * Hamiltonian), inverse DFT. Any int64 t; t < 0 gives U^{-|t|}. psi_t may
+ * equal psi0 (in place); partial overlap is invalid. */
+qw_status qw_evolve_fft(qw_plan_t plan, const void* psi0, void* psi_t, int64_t t, void* stream);
+
+/* B independent instances of one plan shape, each with its own mass and time:
+ * in and out hold B fields back to back (instance b at byte offset
+ * b * s * V * sizeof(complex)); m[b] and t[b] are HOST arrays. out may equal in. */
+qw_status qw_evolve_fft_batched(qw_plan_t plan, int B, const void* in, void* out,
+                                const double* m, const int64_t* t, void* stream);
+
+/* The unnormalised DFT of every component of a field (Sec. 4):
+ * direction +1: out(q) = sum_n e^{+i q.n} psi(n); direction -1:
+ * out(n) = sum_q e^{-i q.n} in(q) (no 1/V). q_i = 2 pi j_i / N_i with the
+ * unshifted index j_i in [0, N_i). out may equal in. */
+qw_status qw_transform(qw_plan_t plan, const void* in, void* out, int direction, void* stream);
+
+/* Reductions of psi (see qw_obs). origin: dim HOST doubles. ref: NULL or a
+ * DEVICE field of the same shape. out: HOST. Waits for the result. */
+qw_status qw_observables(qw_plan_t plan, const void* psi, const double* origin, const void* ref,
+                         qw_obs* out, void* stream);
+
+/* Write a Gaussian particle/antiparticle state into psi (Sec. 5.1,
+ * Definition 1; Sec. 5.2, superposition c+ psi+ + c- psi-):
+ *   hat psi(q) = c+ a+(q)/|a+| + c- a-(q)/|a-|,
+ *   a_s(q) = exp(-sigma^2 |dq|^2 / 2) e^{+i q.c} P_s(q) chi_s,
+ * with dq_j = q_j - q'_j wrapped to [-pi, pi), q' = H^T k0 the lattice image
+ * of the Cartesian k0, P_+ / P_- the projectors of D_q on its eigenvalues
+ * e^{-i omega} / e^{+i omega} (I/2 where sin omega < 1e-12), chi_s the
+ * normalised column of P_s(q') of largest norm (lowest index on ties); then
+ * psi = inverse DFT scaled to unit 2-norm.
+ *   k0: dim HOST doubles (Cartesian); sigma > 0 in lattice cells;
+ *   center: dim HOST doubles; c_plus, c_minus real, not both 0.
+ * Waits for completion. */
+qw_status qw_prepare_state(qw_plan_t plan, void* psi, const double* k0, double sigma,
+                           const double* center, double c_plus, double c_minus, void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* qw_last_error(void);
+
+/* Library version string. */
+const char* qw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QW_H */

@@ -31,7 +31,7 @@ def idft(phat):
 
 
 def symbol_grid(table, N, d):
-    """U_q[N,...,N, s, s] on the DFT grid, by direct summation."""
+    """U_q[N_1,...,N_d, s, s] on the DFT grid, by direct summation."""
     return walk.symbol_from_table(table, walk.lattice_q(N, d))
 
 
@@ -62,6 +62,5 @@ def apply_symbol(Dt, phat):
 def evolve_fourier(psi, table, t):
     """U^t psi by DFT, per-q binary powering of U_q, inverse DFT."""
     d = psi.ndim - 1
-    N = psi.shape[1]
-    Dt = matpow(symbol_grid(table, N, d), t)
+    Dt = matpow(symbol_grid(table, psi.shape[1:], d), t)
     return idft(apply_symbol(Dt, dft(psi)))

@@ -19,19 +19,20 @@ PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
 
 
 def min_image(N, d, center):
-    """w[d, N..N]: per-axis minimum-image displacement of every site from c."""
-    grids = np.meshgrid(*([np.arange(N, dtype=np.float64)] * d), indexing="ij")
+    """w[d, N_1..N_d]: per-axis minimum-image displacement of every site from c."""
+    Ns = (int(N),) * d if np.isscalar(N) else tuple(int(x) for x in N)
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in Ns], indexing="ij")
     c = np.asarray(center, dtype=np.float64).reshape(d)
-    return np.stack([np.mod(g - c[i] + N / 2.0, N) - N / 2.0 for i, g in enumerate(grids)])
+    return np.stack([np.mod(g - c[i] + Ns[i] / 2.0, Ns[i]) - Ns[i] / 2.0
+                     for i, g in enumerate(grids)])
 
 
 def observables(psi, center, ref=None):
     """Norm, position moments about c (primitive and Cartesian), overlap."""
     d = psi.ndim - 1
-    N = psi.shape[1]
     p = np.sum(np.abs(psi) ** 2, axis=0)
     norm2 = float(np.sum(p))
-    w = min_image(N, d, center)
+    w = min_image(psi.shape[1:], d, center)
     c = np.asarray(center, dtype=np.float64).reshape(d)
     mean = np.zeros(3)
     second = np.zeros(6)
@@ -93,7 +94,7 @@ def drift_prediction(psi, table, t):
     Returns a length-d vector in primitive coordinates.
     """
     d = psi.ndim - 1
-    N = psi.shape[1]
+    N = psi.shape[1:]
     _, grad = omega_and_grad(table, N, d)
     phat = fourier.dft(psi)
     Pp, Pm = states.sector_projectors(walk.symbol_from_table(table, walk.lattice_q(N, d)))
@@ -118,8 +119,8 @@ def mean_position_kspace(psi, table, center, times, parts=False):
     ``parts`` also the drift per step and x_int(t)[len(times), d].
     """
     d = psi.ndim - 1
-    N = psi.shape[1]
-    V = N ** d
+    N = psi.shape[1:]
+    V = int(np.prod(N))
     omega, grad = omega_and_grad(table, N, d)
     phat = fourier.dft(psi)
     Pp, Pm = states.sector_projectors(walk.symbol_from_table(table, walk.lattice_q(N, d)))

@@ -208,11 +208,13 @@ def unitarity_defect(table):
 
 
 def lattice_q(N, d):
-    """DFT frequencies q[N,...,N,d] = 2 pi j / N on the unshifted index set.
+    """DFT frequencies q[N_1,...,N_d, d] = 2 pi j_i / N_i on the unshifted
+    index set (N an int for a cubic torus, or a tuple of d sizes).
 
     The paper shifts the index set by floor(N/2) so frequencies lie in
     [-pi, pi) (Sec. 4); the symbol is 2 pi periodic, so the unshifted set
     describes the same samples.
     """
-    j = np.stack(np.meshgrid(*([np.arange(N)] * d), indexing="ij"), axis=-1)
-    return 2.0 * np.pi * j.astype(np.float64) / N
+    Ns = (int(N),) * d if np.isscalar(N) else tuple(int(x) for x in N)
+    j = np.stack(np.meshgrid(*[np.arange(n) for n in Ns], indexing="ij"), axis=-1)
+    return 2.0 * np.pi * j.astype(np.float64) / np.array(Ns, dtype=np.float64)

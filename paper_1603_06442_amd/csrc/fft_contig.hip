@@ -1,0 +1,246 @@
+// FFT pass along the contiguous lattice axis, fused with the per-wave-vector
+// evolution of Sec. 4 of the paper.
+//
+// A team of L/E threads owns one pencil (all s spinor components of one row
+// of the lattice), E elements per component per thread. MODE_EVOLVE does, in
+// one read and one write of the field:
+//   forward FFT along the axis (sign +, Sec. 4)  ->  per q: hat psi(q) <-
+//   V^-1 [cos(omega t) I - i sin(omega t)/sin(omega) M_q] hat psi(q)  ->
+//   inverse FFT along the axis (sign -).
+// The forward transform leaves each thread holding the spectrum at the same
+// positions the inverse starts from, so the apply needs no data exchange.
+// MODE_FWD / MODE_INV do only the forward / inverse transform.
+//
+// Per-q symbol (Sec. 3.1, 3.2): u, n~ of the Weyl walk at the Cartesian k of
+// the lattice frequency q (3D: k = ((q1+q2)/2, (q1+q3)/2, -(q2+q3)/2); 2D:
+// k = ((q1+q2)/2, (q1-q2)/2); 1D: k = q), cos(omega) = n u,
+// sin(omega) = sqrt(n^2 |n~|^2 + m^2), omega = atan2(sin, cos) and
+//   M_q = [[n sigma.n~, -m I], [-m I, -n sigma.n~]]   (d = 2, 3),
+//   M_q = n sin(q) sigma_z - m sigma_x                 (d = 1),
+// so that D_q = cos(omega) I - i M_q and M_q^2 = sin^2(omega) I. The phase
+// omega, omega t and its sine/cosine are FP64 in both precisions.
+//
+// 1D four-step (N = N1 * L): the strided pass has already transformed along
+// n1 (rows k1); here each pencil is one row, pre-multiplied by
+// e^{+2 pi i n2 k1 / N} before the forward transform and by the conjugate
+// after the inverse. The spectrum sits at row k1, column k2 for q index
+// k1 + N1 k2 (never transposed back: the inverse undoes the order).
+#include "qw_internal.h"
+
+namespace qw {
+
+template <typename T, int DIM>
+__device__ __forceinline__ void apply_q(cx<T> (&y)[DIM == 1 ? 2 : 4], const PassGeom& g,
+                                        const InstParam& ip, int64_t j1, int64_t j2, int64_t j3) {
+  double u, n1, n2, n3;
+  weyl_un(DIM, g.cs, g.Nc, g.shift, j1, j2, j3, u, n1, n2, n3);
+  const double nn = ip.n, m = ip.m;
+  const double cosw = nn * u;
+  const double sin2 = nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m;
+  const double sinw = sqrt(sin2);
+  const double w = atan2(sinw, cosw);
+  double S, C;
+  sincos(w * (double)ip.t, &S, &C);
+  const double St = sinw > 0.0 ? S / sinw : 0.0;
+  const T c = (T)(C * g.inv_scale);
+  const T st = (T)(St * g.inv_scale);
+  if constexpr (DIM == 1) {
+    const T a = (T)(nn * n3) * st;
+    const T gg = (T)m * st;
+    // z = St M psi
+    const cx<T> z0 = mk(a * y[0].x - gg * y[1].x, a * y[0].y - gg * y[1].y);
+    const cx<T> z1 = mk(-gg * y[0].x - a * y[1].x, -gg * y[0].y - a * y[1].y);
+    // out = C psi - i z
+    y[0] = mk(c * y[0].x + z0.y, c * y[0].y - z0.x);
+    y[1] = mk(c * y[1].x + z1.y, c * y[1].y - z1.x);
+  } else {
+    const T a = (T)(nn * n3) * st;
+    const T b = (T)(nn * n1) * st;
+    const T e = (T)(nn * n2) * st;
+    const T gg = (T)m * st;
+    const cx<T> p0 = y[0], p1 = y[1], p2 = y[2], p3 = y[3];
+    // (b - i e) p = (b p.x + e p.y, b p.y - e p.x); (b + i e) p = (b p.x - e p.y, b p.y + e p.x)
+    const cx<T> z0 = mk(a * p0.x + (b * p1.x + e * p1.y) - gg * p2.x,
+                        a * p0.y + (b * p1.y - e * p1.x) - gg * p2.y);
+    const cx<T> z1 = mk((b * p0.x - e * p0.y) - a * p1.x - gg * p3.x,
+                        (b * p0.y + e * p0.x) - a * p1.y - gg * p3.y);
+    const cx<T> z2 = mk(-gg * p0.x - a * p2.x - (b * p3.x + e * p3.y),
+                        -gg * p0.y - a * p2.y - (b * p3.y - e * p3.x));
+    const cx<T> z3 = mk(-gg * p1.x - (b * p2.x - e * p2.y) + a * p3.x,
+                        -gg * p1.y - (b * p2.y + e * p2.x) + a * p3.y);
+    y[0] = mk(c * p0.x + z0.y, c * p0.y - z0.x);
+    y[1] = mk(c * p1.x + z1.y, c * p1.y - z1.x);
+    y[2] = mk(c * p2.x + z2.y, c * p2.y - z2.x);
+    y[3] = mk(c * p3.x + z3.y, c * p3.y - z3.x);
+  }
+}
+
+template <typename T, int L, int E, int DIM, int MODE>
+__global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
+                                                    const cx<T>* __restrict__ in, PassGeom g,
+                                                    const cx<T>* __restrict__ tw) {
+  constexpr int S = DIM == 1 ? 2 : 4;
+  constexpr int TT = L / E;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int t = tid & (TT - 1);
+  const int p = tid / TT;
+  const int P = blockDim.x / TT;
+  const int64_t gp = (int64_t)blockIdx.x * P + p;
+  const bool valid = gp < g.pencils;
+  const int64_t gpc = valid ? gp : 0;
+  const int64_t b = gpc / g.ppi;
+  const int64_t pen = gpc - b * g.ppi;
+  const int64_t base = b * S * g.V + pen * L;
+  cx<T>* my = lds + p * L;
+
+  cx<T> v[S][E];
+#pragma unroll
+  for (int c = 0; c < S; ++c)
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[c][e] = valid ? in[base + c * g.V + t + TT * e] : mk((T)0, (T)0);
+
+  const cx<T>* tw4 = (const cx<T>*)g.tw4;
+  const int64_t N = g.N[0];
+  if constexpr (MODE != MODE_INV) {
+    if (DIM == 1 && g.fourstep) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const cx<T> w = tw4[((int64_t)(t + TT * e) * pen) & (N - 1)];
+#pragma unroll
+        for (int c = 0; c < S; ++c) v[c][e] = cmulc(v[c][e], w);  // times e^{+2 pi i n2 k1 / N}
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < S; ++c) fft_team<T, L, E, 1>(v[c], my, 1, t, tw);
+  }
+  if constexpr (MODE == MODE_EVOLVE) {
+    const InstParam ip = g.inst ? g.inst[b] : g.single;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t z = t + TT * e;
+      int64_t j1, j2 = 0, j3 = 0;
+      if constexpr (DIM == 3) {
+        j1 = pen / g.N[1];
+        j2 = pen - j1 * g.N[1];
+        j3 = z;
+      } else if constexpr (DIM == 2) {
+        j1 = pen;
+        j2 = z;
+      } else {
+        j1 = g.fourstep ? pen + g.N1 * z : z;
+      }
+      cx<T> y[S];
+#pragma unroll
+      for (int c = 0; c < S; ++c) y[c] = v[c][e];
+      apply_q<T, DIM>(y, g, ip, j1, j2, j3);
+#pragma unroll
+      for (int c = 0; c < S; ++c) v[c][e] = y[c];
+    }
+  }
+  if constexpr (MODE != MODE_FWD) {
+#pragma unroll
+    for (int c = 0; c < S; ++c) fft_team<T, L, E, -1>(v[c], my, 1, t, tw);
+    if (DIM == 1 && g.fourstep) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const cx<T> w = tw4[((int64_t)(t + TT * e) * pen) & (N - 1)];
+#pragma unroll
+        for (int c = 0; c < S; ++c) v[c][e] = cmul(v[c][e], w);  // times e^{-2 pi i n2 k1 / N}
+      }
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < S; ++c)
+#pragma unroll
+      for (int e = 0; e < E; ++e) out[base + c * g.V + t + TT * e] = v[c][e];
+  }
+}
+
+template <typename T, int L, int DIM, int MODE>
+static hipError_t run_contig(cx<T>* out, const cx<T>* in, const PassGeom& g, const cx<T>* tw,
+                             hipStream_t st) {
+  constexpr int E = L < 8 ? L : 8;
+  constexpr int TT = L / E;
+  int P = 256 / TT;
+  if (P < 1) P = 1;
+  if ((int64_t)P > g.pencils) {
+    int q = 1;
+    while ((int64_t)q < g.pencils) q <<= 1;
+    P = q;
+  }
+  const int threads = TT * P;
+  if (threads > 512) return hipErrorInvalidValue;
+  const size_t lds = (size_t)P * L * sizeof(cx<T>);
+  auto kern = k_fft_contig<T, L, E, DIM, MODE>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t nblk = (g.pencils + P - 1) / P;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(threads), lds, st, out, in, g, tw);
+  return hipGetLastError();
+}
+
+template <typename T, int DIM, int MODE>
+static hipError_t dispatch_contig(int64_t L, cx<T>* out, const cx<T>* in, const PassGeom& g,
+                                  const cx<T>* tw, hipStream_t st) {
+  switch (L) {
+    case 2: return run_contig<T, 2, DIM, MODE>(out, in, g, tw, st);
+    case 4: return run_contig<T, 4, DIM, MODE>(out, in, g, tw, st);
+    case 8: return run_contig<T, 8, DIM, MODE>(out, in, g, tw, st);
+    case 16: return run_contig<T, 16, DIM, MODE>(out, in, g, tw, st);
+    case 32: return run_contig<T, 32, DIM, MODE>(out, in, g, tw, st);
+    case 64: return run_contig<T, 64, DIM, MODE>(out, in, g, tw, st);
+    case 128: return run_contig<T, 128, DIM, MODE>(out, in, g, tw, st);
+    case 256: return run_contig<T, 256, DIM, MODE>(out, in, g, tw, st);
+    case 512: return run_contig<T, 512, DIM, MODE>(out, in, g, tw, st);
+    case 1024:
+      if constexpr (DIM <= 2) return run_contig<T, 1024, DIM, MODE>(out, in, g, tw, st);
+      return hipErrorInvalidValue;
+    case 2048:
+      if constexpr (DIM == 1) return run_contig<T, 2048, DIM, MODE>(out, in, g, tw, st);
+      return hipErrorInvalidValue;
+    case 4096:
+      if constexpr (DIM == 1) return run_contig<T, 4096, DIM, MODE>(out, in, g, tw, st);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int MODE>
+static hipError_t dispatch_dim(int64_t L, cx<T>* out, const cx<T>* in, const PassGeom& g,
+                               const cx<T>* tw, hipStream_t st) {
+  switch (g.dim) {
+    case 1: return dispatch_contig<T, 1, MODE>(L, out, in, g, tw, st);
+    case 2: return dispatch_contig<T, 2, MODE>(L, out, in, g, tw, st);
+    case 3: return dispatch_contig<T, 3, MODE>(L, out, in, g, tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in,
+                                const PassGeom& g, const cx<T>* tw, hipStream_t st) {
+  switch (mode) {
+    case MODE_EVOLVE: return dispatch_dim<T, MODE_EVOLVE>(L, out, in, g, tw, st);
+    case MODE_FWD: return dispatch_dim<T, MODE_FWD>(L, out, in, g, tw, st);
+    case MODE_INV: return dispatch_dim<T, MODE_INV>(L, out, in, g, tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const void* in,
+                             const PassGeom& g, const void* tw, hipStream_t st) {
+  if (dbl)
+    return dispatch_mode<double>(mode, L, (cx<double>*)out, (const cx<double>*)in, g,
+                                 (const cx<double>*)tw, st);
+  return dispatch_mode<float>(mode, L, (cx<float>*)out, (const cx<float>*)in, g,
+                              (const cx<float>*)tw, st);
+}
+
+}  // namespace qw

@@ -1,0 +1,144 @@
+// FFT passes along a strided lattice axis, and the transpose used by the 1D
+// four-step transform when a natural-order spectrum is asked for.
+//
+// Data is viewed as [O][L][I]: the transform runs along the middle axis of
+// length L (stride I elements) for every (o, i). A workgroup takes P
+// consecutive columns i0..i0+P-1 of one o, so each of its global loads and
+// stores touches P contiguous elements (P * 8 or 16 bytes, at least one
+// 128-byte line), and keeps the P pencils in registers (E per thread) with
+// LDS for the exchanges between radix stages. The column index is the
+// fastest-varying thread index, so LDS is addressed [pos][column]: the lanes
+// of a wave touch consecutive words.
+#include "qw_internal.h"
+
+namespace qw {
+
+template <typename T, int L, int E, int SIGN>
+__global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
+                                                      const cx<T>* __restrict__ in, int64_t I,
+                                                      int lgP, int64_t nblk_i,
+                                                      const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int TT = L / E;
+  const int P = 1 << lgP;
+  const int tid = threadIdx.x;
+  const int p = tid & (P - 1);
+  const int t = tid >> lgP;
+  const int64_t blk = blockIdx.x;
+  const int64_t o = blk / nblk_i;
+  const int64_t i0 = (blk - o * nblk_i) << lgP;
+  const int64_t base = o * (int64_t)L * I + i0 + p;
+  cx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = in[base + (int64_t)(t + TT * e) * I];
+  fft_team<T, L, E, SIGN>(v, lds + p, P, t, tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) out[base + (int64_t)(t + TT * e) * I] = v[e];
+}
+
+template <typename T, int L, int SIGN>
+static hipError_t run_strided(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
+                              const cx<T>* tw, hipStream_t st) {
+  constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
+  constexpr int E = L < Emax ? L : Emax;
+  constexpr int TT = L / E;
+  const int Pmin = sizeof(T) == 8 ? 8 : 16;
+  int P = 256 / TT;
+  if (P < Pmin) P = Pmin;
+  if (P > I) P = (int)I;
+  if (TT * P > 1024) return hipErrorInvalidValue;
+  const int lgP = ilog2(P);
+  const size_t lds = (size_t)P * L * sizeof(cx<T>);
+  auto kern = k_fft_strided<T, L, E, SIGN>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t nblk_i = I / P;
+  const int64_t nblk = O * nblk_i;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(TT * P), lds, st, out, in, I, lgP, nblk_i,
+                     tw);
+  return hipGetLastError();
+}
+
+template <typename T, int SIGN>
+static hipError_t dispatch_strided(int64_t L, cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
+                                   const cx<T>* tw, hipStream_t st) {
+  switch (L) {
+    case 1:
+      if (out != in) return hipMemcpyAsync(out, in, sizeof(cx<T>) * O * I, hipMemcpyDeviceToDevice, st);
+      return hipSuccess;
+    case 2: return run_strided<T, 2, SIGN>(out, in, O, I, tw, st);
+    case 4: return run_strided<T, 4, SIGN>(out, in, O, I, tw, st);
+    case 8: return run_strided<T, 8, SIGN>(out, in, O, I, tw, st);
+    case 16: return run_strided<T, 16, SIGN>(out, in, O, I, tw, st);
+    case 32: return run_strided<T, 32, SIGN>(out, in, O, I, tw, st);
+    case 64: return run_strided<T, 64, SIGN>(out, in, O, I, tw, st);
+    case 128: return run_strided<T, 128, SIGN>(out, in, O, I, tw, st);
+    case 256: return run_strided<T, 256, SIGN>(out, in, O, I, tw, st);
+    case 512: return run_strided<T, 512, SIGN>(out, in, O, I, tw, st);
+    case 1024: return run_strided<T, 1024, SIGN>(out, in, O, I, tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
+                              int64_t I, const void* tw, hipStream_t st) {
+  if (dbl) {
+    auto o = (cx<double>*)out;
+    auto i = (const cx<double>*)in;
+    auto w = (const cx<double>*)tw;
+    return sign > 0 ? dispatch_strided<double, 1>(L, o, i, O, I, w, st)
+                    : dispatch_strided<double, -1>(L, o, i, O, I, w, st);
+  }
+  auto o = (cx<float>*)out;
+  auto i = (const cx<float>*)in;
+  auto w = (const cx<float>*)tw;
+  return sign > 0 ? dispatch_strided<float, 1>(L, o, i, O, I, w, st)
+                  : dispatch_strided<float, -1>(L, o, i, O, I, w, st);
+}
+
+// out[p][c][r] = in[p][r][c] for planes p of an R x C matrix (32 x 32 tiles).
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(cx<T>* __restrict__ out,
+                                                   const cx<T>* __restrict__ in, int64_t R,
+                                                   int64_t C, int64_t tiles_c, int64_t tiles_r) {
+  __shared__ cx<T> tile[32][33];
+  const int64_t blk = blockIdx.x;
+  const int64_t per_plane = tiles_c * tiles_r;
+  const int64_t plane = blk / per_plane;
+  const int64_t rem = blk - plane * per_plane;
+  const int64_t tr = rem / tiles_c;
+  const int64_t tc = rem - tr * tiles_c;
+  const cx<T>* src = in + plane * R * C;
+  cx<T>* dst = out + plane * R * C;
+  const int tx = threadIdx.x & 31;
+  const int ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t r = tr * 32 + yy, c = tc * 32 + tx;
+    if (r < R && c < C) tile[yy][tx] = src[r * C + c];
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t c = tc * 32 + yy, r = tr * 32 + tx;
+    if (r < R && c < C) dst[c * R + r] = tile[tx][yy];
+  }
+}
+
+hipError_t launch_transpose(bool dbl, void* out, const void* in, int64_t planes, int64_t R,
+                            int64_t C, hipStream_t st) {
+  const int64_t tc = (C + 31) / 32, tr = (R + 31) / 32;
+  const int64_t nblk = planes * tc * tr;
+  if (dbl)
+    hipLaunchKernelGGL(k_transpose<double>, dim3((unsigned)nblk), dim3(256), 0, st,
+                       (cx<double>*)out, (const cx<double>*)in, R, C, tc, tr);
+  else
+    hipLaunchKernelGGL(k_transpose<float>, dim3((unsigned)nblk), dim3(256), 0, st,
+                       (cx<float>*)out, (const cx<float>*)in, R, C, tc, tr);
+  return hipGetLastError();
+}
+
+}  // namespace qw

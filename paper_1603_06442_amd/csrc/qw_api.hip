@@ -1,0 +1,895 @@
+// C ABI of libqw: plans, argument validation, the pass schedule of the
+// Fourier evolution, stepping, reductions and state preparation.
+//
+// Host-side arithmetic of the walk (FP64): the Weyl/Dirac symbols of
+// Sec. 3.1-3.2 of the paper, the transition matrices U_h of the update rule
+// obtained from the symbol by an exact inverse DFT on a 4^d grid (Sec. 2.1:
+// U_k = sum_h e^{-ik.h} U_h; the symbol's support is within one cell, so a
+// grid of 4 points per axis separates the offsets -1, 0, 1), the check of
+// the unitarity conditions of Sec. 2 on them, and the spinors chi_s of the
+// particle states.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <complex>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "qw_internal.h"
+
+using namespace qw;
+typedef std::complex<double> zc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qw_status fail(qw_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+qw_status fail(qw_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? QW_ERR_NOMEM : QW_ERR_DEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                         \
+  } while (0)
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int lg2(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << r) < v) ++r;
+  return r;
+}
+
+// --- symbols (Sec. 3.1, 3.2) ------------------------------------------------
+
+// u_k and n~_k of the Weyl walk at Cartesian k.
+void weyl_un_host(int dim, const double k[3], double& u, double nt[3]) {
+  if (dim == 1) {
+    u = cos(k[0]);
+    nt[0] = 0.0;
+    nt[1] = 0.0;
+    nt[2] = sin(k[0]);
+    return;
+  }
+  const double cx = cos(k[0]), sx = sin(k[0]), cy = cos(k[1]), sy = sin(k[1]);
+  if (dim == 2) {
+    u = cx * cy;
+    nt[0] = sx * cy;
+    nt[1] = cx * sy;
+    nt[2] = sx * sy;
+    return;
+  }
+  const double cz = cos(k[2]), sz = sin(k[2]);
+  u = cx * cy * cz + sx * sy * sz;
+  nt[0] = sx * cy * cz - cx * sy * sz;
+  nt[1] = cx * sy * cz + sx * cy * sz;
+  nt[2] = cx * cy * sz - sx * sy * cz;
+}
+
+// Cartesian k of lattice q (q_j = k . h_j).
+void k_of_q(int dim, const double q[3], double k[3]) {
+  k[0] = k[1] = k[2] = 0.0;
+  if (dim == 1) {
+    k[0] = q[0];
+  } else if (dim == 2) {
+    k[0] = 0.5 * (q[0] + q[1]);
+    k[1] = 0.5 * (q[0] - q[1]);
+  } else {
+    k[0] = 0.5 * (q[0] + q[1]);
+    k[1] = 0.5 * (q[0] + q[2]);
+    k[2] = -0.5 * (q[1] + q[2]);
+  }
+}
+
+// Lattice q of Cartesian k.
+void q_of_k(int dim, const double k[3], double q[3]) {
+  q[0] = q[1] = q[2] = 0.0;
+  if (dim == 1) {
+    q[0] = k[0];
+  } else if (dim == 2) {
+    q[0] = k[0] + k[1];
+    q[1] = k[0] - k[1];
+  } else {
+    q[0] = k[0] + k[1] + k[2];
+    q[1] = k[0] - k[1] - k[2];
+    q[2] = -k[0] + k[1] - k[2];
+  }
+}
+
+// M of D = cos(omega) I - i M at Cartesian k (block form of Sec. 3.2), and sin(omega).
+void dirac_M(int dim, const double k[3], double m, zc M[4][4], double& cosw, double& sinw) {
+  const double n = sqrt(1.0 - m * m);
+  double u, nt[3];
+  weyl_un_host(dim, k, u, nt);
+  cosw = n * u;
+  sinw = sqrt(n * n * (nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]) + m * m);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) M[i][j] = 0.0;
+  if (dim == 1) {
+    M[0][0] = n * nt[2];
+    M[1][1] = -n * nt[2];
+    M[0][1] = -m;
+    M[1][0] = -m;
+    return;
+  }
+  const zc sn[2][2] = {{nt[2], zc(nt[0], -nt[1])}, {zc(nt[0], nt[1]), -nt[2]}};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      M[i][j] = n * sn[i][j];
+      M[i + 2][j + 2] = -n * sn[i][j];
+    }
+  for (int i = 0; i < 2; ++i) {
+    M[i][i + 2] = -m;
+    M[i + 2][i] = -m;
+  }
+}
+
+// The Dirac symbol D(q) at lattice q: [[n W, i m], [i m, n W^dag]] (1D: 2x2 form).
+void dirac_symbol(int dim, const double q[3], double m, zc D[4][4]) {
+  double k[3];
+  k_of_q(dim, q, k);
+  const double n = sqrt(1.0 - m * m);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) D[i][j] = 0.0;
+  if (dim == 1) {
+    D[0][0] = n * std::exp(zc(0.0, -k[0]));
+    D[1][1] = n * std::exp(zc(0.0, k[0]));
+    D[0][1] = zc(0.0, m);
+    D[1][0] = zc(0.0, m);
+    return;
+  }
+  double u, nt[3];
+  weyl_un_host(dim, k, u, nt);
+  // W = u I - i sigma . n~
+  const zc W[2][2] = {{zc(u, -nt[2]), zc(-nt[1], -nt[0])}, {zc(nt[1], -nt[0]), zc(u, nt[2])}};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      D[i][j] = n * W[i][j];
+      D[i + 2][j + 2] = n * std::conj(W[j][i]);
+    }
+  for (int i = 0; i < 2; ++i) {
+    D[i][i + 2] = zc(0.0, m);
+    D[i + 2][i] = zc(0.0, m);
+  }
+}
+
+// --- transition matrices ----------------------------------------------------
+
+struct Table {
+  int dim, s;
+  // offsets in {-1,0,1}^d, index = sum (o_i + 1) 3^(d-1-i)
+  zc U[27][4][4];
+};
+
+int off_index(int dim, const int* o) {
+  int idx = 0;
+  for (int i = 0; i < dim; ++i) idx = idx * 3 + (o[i] + 1);
+  return idx;
+}
+
+// U_h = 4^-d sum_{q in grid} e^{+i q.h} D(q); also reports any weight at offset 2.
+double derive_table(int dim, double m, Table& T) {
+  const int s = dim == 1 ? 2 : 4;
+  T.dim = dim;
+  T.s = s;
+  const int L = 4;
+  int npts = 1;
+  for (int i = 0; i < dim; ++i) npts *= L;
+  double leak = 0.0;
+  std::vector<zc> acc(4 * 4 * 64, zc(0.0));  // offsets in {-1,0,1,2}^d -> 4^d slots
+  for (int p = 0; p < npts; ++p) {
+    double q[3] = {0, 0, 0};
+    int j[3] = {0, 0, 0};
+    int r = p;
+    for (int i = dim - 1; i >= 0; --i) {
+      j[i] = r % L;
+      r /= L;
+      q[i] = 2.0 * M_PI * j[i] / L;
+    }
+    zc D[4][4];
+    dirac_symbol(dim, q, m, D);
+    for (int o = 0; o < npts; ++o) {
+      int off[3] = {0, 0, 0};
+      int rr = o;
+      for (int i = dim - 1; i >= 0; --i) {
+        off[i] = rr % L - 1;  // -1, 0, 1, 2
+        rr /= L;
+      }
+      double ph = 0.0;
+      for (int i = 0; i < dim; ++i) ph += q[i] * off[i];
+      const zc e = std::exp(zc(0.0, ph));
+      for (int a = 0; a < s; ++a)
+        for (int b = 0; b < s; ++b) acc[(o * 4 + a) * 4 + b] += e * D[a][b];
+    }
+  }
+  for (int i = 0; i < 27; ++i)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) T.U[i][a][b] = 0.0;
+  for (int o = 0; o < npts; ++o) {
+    int off[3] = {0, 0, 0};
+    int rr = o;
+    bool far = false;
+    for (int i = dim - 1; i >= 0; --i) {
+      off[i] = rr % L - 1;
+      rr /= L;
+      if (off[i] == 2) far = true;
+    }
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) {
+        zc v = acc[(o * 4 + a) * 4 + b] / (double)npts;
+        if (std::abs(v.real()) < 1e-15) v.real(0.0);
+        if (std::abs(v.imag()) < 1e-15) v.imag(0.0);
+        if (far)
+          leak = fmax(leak, std::abs(v));
+        else
+          T.U[off_index(dim, off)][a][b] = v;
+      }
+  }
+  return leak;
+}
+
+// Largest violation of the unitarity conditions (Sec. 2) over the table.
+double unitarity_defect(const Table& T) {
+  const int dim = T.dim, s = T.s;
+  int n = 1;
+  for (int i = 0; i < dim; ++i) n *= 3;
+  double worst = 0.0;
+  // sum_h U_h^dag U_{h + d} and sum_h U_{h + d} U_h^dag for every shift d in {-2..2}^dim
+  int nd = 1;
+  for (int i = 0; i < dim; ++i) nd *= 5;
+  for (int di = 0; di < nd; ++di) {
+    int dd[3] = {0, 0, 0};
+    int r = di;
+    bool zero = true;
+    for (int i = dim - 1; i >= 0; --i) {
+      dd[i] = r % 5 - 2;
+      r /= 5;
+      if (dd[i]) zero = false;
+    }
+    zc A[4][4], B[4][4];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) A[a][b] = B[a][b] = 0.0;
+    for (int h = 0; h < n; ++h) {
+      int o[3] = {0, 0, 0}, o2[3] = {0, 0, 0};
+      int rr = h;
+      bool ok = true;
+      for (int i = dim - 1; i >= 0; --i) {
+        o[i] = rr % 3 - 1;
+        rr /= 3;
+        o2[i] = o[i] + dd[i];
+        if (o2[i] < -1 || o2[i] > 1) ok = false;
+      }
+      if (!ok) continue;
+      const int h2 = off_index(dim, o2);
+      for (int a = 0; a < s; ++a)
+        for (int b = 0; b < s; ++b)
+          for (int c = 0; c < s; ++c) {
+            A[a][b] += std::conj(T.U[h][c][a]) * T.U[h2][c][b];
+            B[a][b] += T.U[h2][a][c] * std::conj(T.U[h][b][c]);
+          }
+    }
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) {
+        const double id = (zero && a == b) ? 1.0 : 0.0;
+        worst = fmax(worst, std::abs(A[a][b] - id));
+        worst = fmax(worst, std::abs(B[a][b] - id));
+      }
+  }
+  return worst;
+}
+
+const int kOff2h[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+const int kOff3h[8][3] = {{1, 0, 0},  {0, -1, 0}, {0, 0, -1}, {-1, -1, -1},
+                          {-1, 0, 0}, {0, 1, 0},  {0, 0, 1},  {1, 1, 1}};
+
+// Fill the kernel coefficient struct; check that everything the kernel does
+// not read is zero (block-diagonal neighbours, mass coupling on site).
+template <typename T>
+bool pack_coef(const Table& Tb, double m, StencilCoef<T>& C, std::string& why) {
+  memset(&C, 0, sizeof C);
+  const int dim = Tb.dim;
+  std::vector<bool> used(27, false);
+  auto put = [](cx<T>& dst, zc v) {
+    dst.x = (T)v.real();
+    dst.y = (T)v.imag();
+  };
+  const double tol = 1e-14;
+  if (dim == 1) {
+    const int op[1] = {1}, om[1] = {-1}, o0[1] = {0};
+    const int ip = off_index(1, op), im = off_index(1, om), i0 = off_index(1, o0);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        put(C.up[0][a][b], Tb.U[ip][a][b]);
+        put(C.up[1][a][b], Tb.U[im][a][b]);
+        put(C.onsite[a][b], Tb.U[i0][a][b]);
+      }
+    return true;
+  }
+  const int K = dim == 3 ? 8 : 4;
+  for (int k = 0; k < K; ++k) {
+    const int* o = dim == 3 ? kOff3h[k] : kOff2h[k];
+    const int idx = off_index(dim, o);
+    used[idx] = true;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        put(C.up[k][a][b], Tb.U[idx][a][b]);
+        put(C.lo[k][a][b], Tb.U[idx][a + 2][b + 2]);
+        if (std::abs(Tb.U[idx][a][b + 2]) > tol || std::abs(Tb.U[idx][a + 2][b]) > tol) {
+          why = "neighbour matrix is not block diagonal";
+          return false;
+        }
+      }
+  }
+  const int o0[3] = {0, 0, 0};
+  const int i0 = off_index(dim, o0);
+  used[i0] = true;
+  const zc mass = Tb.U[i0][0][2];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const zc want = (b == (a ^ 2)) ? mass : zc(0.0);
+      if (std::abs(Tb.U[i0][a][b] - want) > tol) {
+        why = "on-site matrix is not mass * I between the two halves";
+        return false;
+      }
+    }
+  put(C.onsite[0][0], mass);
+  (void)m;
+  int n = 1;
+  for (int i = 0; i < dim; ++i) n *= 3;
+  for (int h = 0; h < n; ++h) {
+    if (used[h]) continue;
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        if (std::abs(Tb.U[h][a][b]) > tol) {
+          why = "transition matrix outside the expected neighbourhood";
+          return false;
+        }
+  }
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct qw_plan_s {
+  int dim = 0, s = 0;
+  int64_t N[3] = {1, 1, 1};
+  int lg[3] = {0, 0, 0};
+  int64_t V = 0;
+  double m = 0.0, n = 1.0;
+  qw_dtype dtype = QW_C64;
+  bool dbl = false;
+  size_t elem = 8;        // bytes per complex entry
+  size_t field_bytes = 0;
+  int device = 0;
+
+  Table table;
+  StencilCoef<double> coef_d;
+  StencilCoef<float> coef_f;
+
+  // FFT schedule
+  int Nc = 1;
+  int shift[3] = {0, 0, 0};
+  bool fourstep = false;
+  int64_t fs_N1 = 1, fs_N2 = 1;
+
+  // device memory
+  void* d_tw = nullptr;     // exp(-2 pi i j / 4096), field precision
+  void* d_tw4 = nullptr;    // exp(-2 pi i j / N) for the 1D four-step, field precision
+  double* d_cs = nullptr;   // (cos, sin)(pi j / Nc), j < 2 Nc
+  double* d_partials = nullptr;
+  double* d_result = nullptr;
+  double* h_result = nullptr;  // pinned
+  void* d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+  InstParam* d_inst = nullptr;
+  InstParam* h_inst = nullptr;  // pinned
+  int inst_cap = 0;
+
+  ~qw_plan_s() {
+    if (d_tw) (void)hipFree(d_tw);
+    if (d_tw4) (void)hipFree(d_tw4);
+    if (d_cs) (void)hipFree(d_cs);
+    if (d_partials) (void)hipFree(d_partials);
+    if (d_result) (void)hipFree(d_result);
+    if (h_result) (void)hipHostFree(h_result);
+    if (d_scratch) (void)hipFree(d_scratch);
+    if (d_inst) (void)hipFree(d_inst);
+    if (h_inst) (void)hipHostFree(h_inst);
+  }
+};
+
+namespace {
+
+qw_status ensure_scratch(qw_plan_t p, size_t bytes) {
+  if (p->scratch_bytes >= bytes) return QW_OK;
+  if (p->d_scratch) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(p->d_scratch));
+    p->d_scratch = nullptr;
+    p->scratch_bytes = 0;
+  }
+  HIP_TRY(hipMalloc(&p->d_scratch, bytes));
+  p->scratch_bytes = bytes;
+  return QW_OK;
+}
+
+qw_status ensure_inst(qw_plan_t p, int B) {
+  if (p->inst_cap >= B) return QW_OK;
+  if (p->d_inst) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(p->d_inst));
+    HIP_TRY(hipHostFree(p->h_inst));
+    p->d_inst = nullptr;
+    p->h_inst = nullptr;
+    p->inst_cap = 0;
+  }
+  int cap = 64;
+  while (cap < B) cap <<= 1;
+  HIP_TRY(hipMalloc(&p->d_inst, sizeof(InstParam) * cap));
+  HIP_TRY(hipHostMalloc((void**)&p->h_inst, sizeof(InstParam) * cap, hipHostMallocDefault));
+  p->inst_cap = cap;
+  return QW_OK;
+}
+
+template <typename T>
+std::vector<cx<T>> make_twiddles(int64_t n) {
+  std::vector<cx<T>> v((size_t)n);
+  for (int64_t j = 0; j < n; ++j) {
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
+    v[(size_t)j].x = (T)cosl(a);
+    v[(size_t)j].y = (T)sinl(a);
+  }
+  return v;
+}
+
+qw_status check_plan(qw_plan_t p) {
+  if (!p) return fail(QW_ERR_INVALID, "plan is NULL");
+  return QW_OK;
+}
+
+PassGeom pass_geom(qw_plan_t p, int64_t L, int B) {
+  PassGeom g;
+  memset(&g, 0, sizeof g);
+  g.dim = p->dim;
+  g.s = p->s;
+  g.V = p->V;
+  for (int i = 0; i < 3; ++i) g.N[i] = p->N[i];
+  g.ppi = p->V / L;
+  g.pencils = g.ppi * B;
+  g.Nc = p->Nc;
+  for (int i = 0; i < 3; ++i) g.shift[i] = p->shift[i];
+  g.fourstep = p->fourstep ? 1 : 0;
+  g.N1 = p->fs_N1;
+  g.cs = p->d_cs;
+  g.tw4 = p->d_tw4;
+  g.inv_scale = 1.0 / (double)p->V;
+  g.single.m = p->m;
+  g.single.n = p->n;
+  g.single.t = 0;
+  g.inst = nullptr;
+  return g;
+}
+
+// Forward (+) strided passes of the schedule: all axes but the contiguous one.
+qw_status strided_passes(qw_plan_t p, int sign, void* out, const void* in, int B,
+                         hipStream_t st) {
+  const int s = p->s;
+  if (p->dim == 3) {
+    const int64_t N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
+    if (sign > 0) {
+      HIP_TRY(launch_fft_strided(p->dbl, 1, N1, out, in, (int64_t)s * B, N2 * N3, p->d_tw, st));
+      HIP_TRY(launch_fft_strided(p->dbl, 1, N2, out, out, (int64_t)s * B * N1, N3, p->d_tw, st));
+    } else {
+      HIP_TRY(launch_fft_strided(p->dbl, -1, N2, out, in, (int64_t)s * B * N1, N3, p->d_tw, st));
+      HIP_TRY(launch_fft_strided(p->dbl, -1, N1, out, out, (int64_t)s * B, N2 * N3, p->d_tw, st));
+    }
+  } else if (p->dim == 2) {
+    HIP_TRY(launch_fft_strided(p->dbl, sign, p->N[0], out, in, (int64_t)s * B, p->N[1], p->d_tw, st));
+  } else if (p->fourstep) {
+    HIP_TRY(launch_fft_strided(p->dbl, sign, p->fs_N1, out, in, (int64_t)s * B, p->fs_N2, p->d_tw, st));
+  } else if (out != in) {
+    HIP_TRY(hipMemcpyAsync(out, in, p->field_bytes * B, hipMemcpyDeviceToDevice, st));
+  }
+  return QW_OK;
+}
+
+int64_t contig_len(qw_plan_t p) {
+  if (p->dim == 3) return p->N[2];
+  if (p->dim == 2) return p->N[1];
+  return p->fourstep ? p->fs_N2 : p->N[0];
+}
+
+bool has_strided(qw_plan_t p) { return p->dim > 1 || p->fourstep; }
+
+qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstParam* dinst,
+                      const InstParam& single, hipStream_t st) {
+  const int64_t L = contig_len(p);
+  PassGeom g = pass_geom(p, L, B);
+  g.single = single;
+  g.inst = dinst;
+  if (has_strided(p)) {
+    qw_status r = strided_passes(p, +1, out, in, B, st);
+    if (r != QW_OK) return r;
+    HIP_TRY(launch_fft_contig(p->dbl, MODE_EVOLVE, L, out, out, g, p->d_tw, st));
+    return strided_passes(p, -1, out, out, B, st);
+  }
+  HIP_TRY(launch_fft_contig(p->dbl, MODE_EVOLVE, L, out, in, g, p->d_tw, st));
+  return QW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qw_last_error(void) { return g_last_error.c_str(); }
+
+const char* qw_version(void) { return "qw-mi355x 0.1 (gfx950)"; }
+
+qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype dtype,
+                  void* stream) {
+  if (!out) return fail(QW_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (dim < 1 || dim > 3) return fail(QW_ERR_INVALID, "dim must be 1, 2 or 3 (got %d)", dim);
+  if (!N) return fail(QW_ERR_INVALID, "N is NULL");
+  if (!(m >= 0.0 && m <= 1.0)) return fail(QW_ERR_INVALID, "m must lie in [0, 1]");
+  if (dtype != QW_C64 && dtype != QW_C128) return fail(QW_ERR_INVALID, "unknown dtype %d", (int)dtype);
+  const int64_t maxN = dim == 1 ? 65536 : (dim == 2 ? 1024 : 512);
+  for (int i = 0; i < dim; ++i) {
+    if (N[i] < 1) return fail(QW_ERR_INVALID, "N[%d] = %lld is not positive", i, (long long)N[i]);
+    if (!is_pow2(N[i]) || N[i] < 2 || N[i] > maxN)
+      return fail(QW_ERR_UNSUPPORTED, "N[%d] = %lld: need a power of two in [2, %lld] for dim %d",
+                  i, (long long)N[i], (long long)maxN, dim);
+  }
+  qw_plan_t p = new (std::nothrow) qw_plan_s();
+  if (!p) return fail(QW_ERR_NOMEM, "host allocation failed");
+  p->dim = dim;
+  p->s = dim == 1 ? 2 : 4;
+  p->V = 1;
+  for (int i = 0; i < dim; ++i) {
+    p->N[i] = N[i];
+    p->lg[i] = lg2(N[i]);
+    p->V *= N[i];
+  }
+  p->m = m;
+  p->n = sqrt(1.0 - m * m);
+  p->dtype = dtype;
+  p->dbl = dtype == QW_C128;
+  p->elem = p->dbl ? 16 : 8;
+  p->field_bytes = (size_t)p->s * p->V * p->elem;
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetDevice(&p->device);
+
+  // Transition matrices from the symbol, unitarity checked (Sec. 2).
+  const double leak = derive_table(dim, m, p->table);
+  const double defect = unitarity_defect(p->table);
+  if (leak > 1e-14 || defect > 1e-13) {
+    delete p;
+    return fail(QW_ERR_DEVICE, "derived transition matrices fail checks (leak %g, unitarity %g)",
+                leak, defect);
+  }
+  std::string why;
+  if (!pack_coef<double>(p->table, m, p->coef_d, why) || !pack_coef<float>(p->table, m, p->coef_f, why)) {
+    delete p;
+    return fail(QW_ERR_DEVICE, "transition matrices: %s", why.c_str());
+  }
+
+  // Fourier schedule.
+  if (dim == 1 && N[0] > 4096) {
+    p->fourstep = true;
+    p->fs_N2 = 4096;
+    p->fs_N1 = N[0] / 4096;
+  }
+  int64_t Nc = 1;
+  for (int i = 0; i < dim; ++i) Nc = N[i] > Nc ? N[i] : Nc;
+  p->Nc = (int)Nc;
+  for (int i = 0; i < dim; ++i) p->shift[i] = lg2(Nc / N[i]);
+
+  qw_status r = QW_OK;
+  auto upload = [&](void** dst, const void* src, size_t bytes) -> qw_status {
+    HIP_TRY(hipMalloc(dst, bytes));
+    HIP_TRY(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st));
+    return QW_OK;
+  };
+  {
+    std::vector<double> cs((size_t)4 * Nc);
+    for (int64_t j = 0; j < 2 * Nc; ++j) {
+      const long double a = 3.14159265358979323846264338327950288L * (long double)j / (long double)Nc;
+      cs[(size_t)2 * j] = (double)cosl(a);
+      cs[(size_t)2 * j + 1] = (double)sinl(a);
+    }
+    if (p->dbl) {
+      auto tw = make_twiddles<double>(TWN);
+      r = upload(&p->d_tw, tw.data(), tw.size() * sizeof(tw[0]));
+      if (r == QW_OK && p->fourstep) {
+        auto t4 = make_twiddles<double>(N[0]);
+        r = upload(&p->d_tw4, t4.data(), t4.size() * sizeof(t4[0]));
+      }
+    } else {
+      auto tw = make_twiddles<float>(TWN);
+      r = upload(&p->d_tw, tw.data(), tw.size() * sizeof(tw[0]));
+      if (r == QW_OK && p->fourstep) {
+        auto t4 = make_twiddles<float>(N[0]);
+        r = upload(&p->d_tw4, t4.data(), t4.size() * sizeof(t4[0]));
+      }
+    }
+    if (r == QW_OK) r = upload((void**)&p->d_cs, cs.data(), cs.size() * sizeof(double));
+    if (r == QW_OK) {
+      hipError_t e = hipMalloc(&p->d_partials, sizeof(double) * kObsFields * kObsBlocks);
+      if (e == hipSuccess) e = hipMalloc(&p->d_result, sizeof(double) * 16);
+      if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_result, sizeof(double) * 16, hipHostMallocDefault);
+      // the host vectors above are released at scope end: wait for the uploads
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess)
+        r = fail(e == hipErrorOutOfMemory ? QW_ERR_NOMEM : QW_ERR_DEVICE, "plan set-up: %s",
+                 hipGetErrorString(e));
+    } else {
+      (void)hipStreamSynchronize(st);
+    }
+  }
+  if (r != QW_OK) {
+    delete p;
+    return r;
+  }
+  *out = p;
+  return QW_OK;
+}
+
+qw_status qw_destroy(qw_plan_t p) {
+  if (!p) return QW_OK;
+  (void)hipDeviceSynchronize();
+  delete p;
+  return QW_OK;
+}
+
+qw_status qw_step(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi) return fail(QW_ERR_INVALID, "psi is NULL");
+  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+  if (nsteps == 0) return QW_OK;
+  hipStream_t st = (hipStream_t)stream;
+  r = ensure_scratch(p, p->field_bytes);
+  if (r != QW_OK) return r;
+  StencilGeom g;
+  g.dim = p->dim;
+  for (int i = 0; i < 3; ++i) {
+    g.N[i] = p->N[i];
+    g.lg[i] = p->lg[i];
+  }
+  g.V = p->V;
+  const void* coef = p->dbl ? (const void*)&p->coef_d : (const void*)&p->coef_f;
+  void* a = psi;
+  void* b = p->d_scratch;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    HIP_TRY(launch_step(p->dbl, g, b, a, coef, st));
+    void* t = a;
+    a = b;
+    b = t;
+  }
+  if (a != psi) HIP_TRY(hipMemcpyAsync(psi, a, p->field_bytes, hipMemcpyDeviceToDevice, st));
+  return QW_OK;
+}
+
+qw_status qw_evolve_fft(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi0 || !psi_t) return fail(QW_ERR_INVALID, "field pointer is NULL");
+  InstParam ip;
+  ip.m = p->m;
+  ip.n = p->n;
+  ip.t = t;
+  return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
+}
+
+qw_status qw_evolve_fft_batched(qw_plan_t p, int B, const void* in, void* out, const double* m,
+                                const int64_t* t, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (B < 0) return fail(QW_ERR_INVALID, "B must be >= 0");
+  if (B == 0) return QW_OK;
+  if (!in || !out || !m || !t) return fail(QW_ERR_INVALID, "NULL argument");
+  for (int b = 0; b < B; ++b)
+    if (!(m[b] >= 0.0 && m[b] <= 1.0)) return fail(QW_ERR_INVALID, "m[%d] outside [0, 1]", b);
+  hipStream_t st = (hipStream_t)stream;
+  r = ensure_inst(p, B);
+  if (r != QW_OK) return r;
+  // The pinned staging area may still feed an earlier batched call's copy.
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int b = 0; b < B; ++b) {
+    p->h_inst[b].m = m[b];
+    p->h_inst[b].n = sqrt(1.0 - m[b] * m[b]);
+    p->h_inst[b].t = t[b];
+  }
+  HIP_TRY(hipMemcpyAsync(p->d_inst, p->h_inst, sizeof(InstParam) * B, hipMemcpyHostToDevice, st));
+  InstParam ip;
+  ip.m = p->m;
+  ip.n = p->n;
+  ip.t = 0;
+  return evolve_impl(p, B, in, out, p->d_inst, ip, st);
+}
+
+qw_status qw_transform(qw_plan_t p, const void* in, void* out, int direction, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!in || !out) return fail(QW_ERR_INVALID, "field pointer is NULL");
+  if (direction != 1 && direction != -1) return fail(QW_ERR_INVALID, "direction must be +1 or -1");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t L = contig_len(p);
+  PassGeom g = pass_geom(p, L, 1);
+  if (p->fourstep) {
+    r = ensure_scratch(p, p->field_bytes);
+    if (r != QW_OK) return r;
+  }
+  if (direction > 0) {
+    if (has_strided(p)) {
+      r = strided_passes(p, +1, out, in, 1, st);
+      if (r != QW_OK) return r;
+      HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, out, out, g, p->d_tw, st));
+    } else {
+      HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, out, in, g, p->d_tw, st));
+    }
+    if (p->fourstep) {
+      // row k1, column k2 holds q index k1 + N1 k2: transpose to natural order.
+      HIP_TRY(launch_transpose(p->dbl, p->d_scratch, out, p->s, p->fs_N1, p->fs_N2, st));
+      HIP_TRY(hipMemcpyAsync(out, p->d_scratch, p->field_bytes, hipMemcpyDeviceToDevice, st));
+    }
+    return QW_OK;
+  }
+  const void* src = in;
+  if (p->fourstep) {
+    HIP_TRY(launch_transpose(p->dbl, p->d_scratch, in, p->s, p->fs_N2, p->fs_N1, st));
+    src = p->d_scratch;
+  }
+  HIP_TRY(launch_fft_contig(p->dbl, MODE_INV, L, out, src, g, p->d_tw, st));
+  if (has_strided(p)) return strided_passes(p, -1, out, out, 1, st);
+  return QW_OK;
+}
+
+qw_status qw_observables(qw_plan_t p, const void* psi, const double* origin, const void* ref,
+                         qw_obs* out, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  ObsGeom g;
+  memset(&g, 0, sizeof g);
+  g.dim = p->dim;
+  g.s = p->s;
+  g.V = p->V;
+  for (int i = 0; i < 3; ++i) {
+    g.N[i] = p->N[i];
+    g.lg[i] = p->lg[i];
+    g.c[i] = i < p->dim ? origin[i] : 0.0;
+    if (i < p->dim && !isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+  }
+  HIP_TRY(launch_observables(p->dbl, g, psi, ref, p->d_partials, p->d_result, st));
+  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double* R = p->h_result;
+  memset(out, 0, sizeof *out);
+  out->norm2 = R[0];
+  const double inv = R[0] > 0.0 ? 1.0 / R[0] : 0.0;
+  for (int i = 0; i < p->dim; ++i) out->mean[i] = g.c[i] + R[1 + i] * inv;
+  static const int pr[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+  for (int k = 0; k < 6; ++k)
+    if (pr[k][0] < p->dim && pr[k][1] < p->dim) out->second[k] = R[4 + k] * inv;
+  if (p->dim == 1) {
+    out->mean_cart[0] = out->mean[0];
+  } else if (p->dim == 2) {
+    out->mean_cart[0] = out->mean[0] + out->mean[1];
+    out->mean_cart[1] = out->mean[0] - out->mean[1];
+  } else {
+    const double a = out->mean[0], b = out->mean[1], c = out->mean[2];
+    out->mean_cart[0] = a + b - c;
+    out->mean_cart[1] = a - b + c;
+    out->mean_cart[2] = a - b - c;
+  }
+  if (ref) {
+    out->overlap_re = R[10];
+    out->overlap_im = R[11];
+    out->ref_norm2 = R[12];
+  }
+  return QW_OK;
+}
+
+qw_status qw_prepare_state(qw_plan_t p, void* psi, const double* k0, double sigma,
+                           const double* center, double c_plus, double c_minus, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi || !k0 || !center) return fail(QW_ERR_INVALID, "NULL argument");
+  if (!(sigma > 0.0) || !isfinite(sigma)) return fail(QW_ERR_INVALID, "sigma must be > 0");
+  if (!isfinite(c_plus) || !isfinite(c_minus) || (c_plus == 0.0 && c_minus == 0.0))
+    return fail(QW_ERR_INVALID, "c_plus, c_minus must be finite and not both zero");
+  for (int i = 0; i < p->dim; ++i)
+    if (!isfinite(k0[i]) || !isfinite(center[i])) return fail(QW_ERR_INVALID, "k0/center not finite");
+  hipStream_t st = (hipStream_t)stream;
+  StateGeom g;
+  memset(&g, 0, sizeof g);
+  g.dim = p->dim;
+  g.s = p->s;
+  g.V = p->V;
+  for (int i = 0; i < 3; ++i) {
+    g.N[i] = p->N[i];
+    g.lg[i] = p->lg[i];
+    g.shift[i] = p->shift[i];
+  }
+  g.m = p->m;
+  g.n = p->n;
+  g.sigma = sigma;
+  g.Nc = p->Nc;
+  g.cs = p->d_cs;
+  double kk[3] = {0, 0, 0}, q0[3];
+  for (int i = 0; i < p->dim; ++i) {
+    kk[i] = k0[i];
+    g.center[i] = center[i];
+  }
+  q_of_k(p->dim, kk, q0);
+  for (int i = 0; i < 3; ++i) g.q0[i] = q0[i];
+  // chi_s: normalised column of largest norm of P_s(q0) = (I + s M / sin(omega)) / 2.
+  zc M[4][4];
+  double cosw, sinw;
+  double kq0[3];
+  k_of_q(p->dim, q0, kq0);
+  dirac_M(p->dim, kq0, p->m, M, cosw, sinw);
+  const int s = p->s;
+  for (int sec = 0; sec < 2; ++sec) {
+    const double sg = sec == 0 ? 1.0 : -1.0;
+    zc P[4][4];
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) {
+        const zc mh = sinw >= 1e-12 ? M[a][b] / sinw : zc(0.0);
+        P[a][b] = 0.5 * ((a == b ? 1.0 : 0.0) + sg * mh);
+      }
+    int best = 0;
+    double bn = -1.0;
+    for (int b = 0; b < s; ++b) {
+      double nrm = 0.0;
+      for (int a = 0; a < s; ++a) nrm += std::norm(P[a][b]);
+      nrm = sqrt(nrm);
+      if (nrm > bn) {
+        bn = nrm;
+        best = b;
+      }
+    }
+    double (*chi)[2] = sec == 0 ? g.chi_p : g.chi_m;
+    for (int a = 0; a < s; ++a) {
+      chi[a][0] = P[a][best].real() / bn;
+      chi[a][1] = P[a][best].imag() / bn;
+    }
+  }
+  HIP_TRY(launch_state_norms(g, p->d_partials, p->d_result, st));
+  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double np = p->h_result[0], nm = p->h_result[1];
+  if ((c_plus != 0.0 && !(np > 0.0)) || (c_minus != 0.0 && !(nm > 0.0)))
+    return fail(QW_ERR_INVALID, "state has zero weight in a requested sector");
+  // Unnormalised inverse DFT multiplies the norm by V (Parseval): scale so |psi| = 1.
+  const double total = sqrt((double)p->V * (c_plus * c_plus + c_minus * c_minus));
+  g.coef_p = c_plus != 0.0 ? c_plus / sqrt(np) / total : 0.0;
+  g.coef_m = c_minus != 0.0 ? c_minus / sqrt(nm) / total : 0.0;
+  HIP_TRY(launch_state_fill(p->dbl, g, psi, st));
+  r = qw_transform(p, psi, psi, -1, stream);
+  if (r != QW_OK) return r;
+  HIP_TRY(hipStreamSynchronize(st));
+  return QW_OK;
+}
+
+}  // extern "C"

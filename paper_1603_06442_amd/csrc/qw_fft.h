@@ -1,0 +1,184 @@
+// Radix-2/4/8/16 FFT building blocks for gfx950 (device code).
+//
+// Pencil FFTs of power-of-two length L are done by a team of L/E threads,
+// each holding E elements in registers: thread t holds x[t + (L/E) e],
+// e = 0..E-1. The transform runs as Stockham autosort stages of radix R <= E
+// (each thread does E/R radix-R butterflies per stage, in registers); between
+// stages the team exchanges data through LDS. Both the first stage's input
+// and the last stage's output sit at the positions t + (L/E) e, so global
+// loads and stores are coalesced across the team, and a forward transform
+// leaves in registers exactly the elements the inverse transform starts
+// from (the per-wave-vector apply is done there, with no exchange).
+//
+// The DFT sign is a template argument: SIGN = +1 computes
+// X_k = sum_n x_n e^{+2 pi i n k / L} (the forward sign of Sec. 4 of the
+// paper), SIGN = -1 the inverse sign. Transforms are unnormalised.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qw {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) {
+  cx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
+
+// cos(2 pi k / 16), k = 0..15, and sin(2 pi k / 16) = cos(2 pi (k - 4) / 16).
+__device__ constexpr double kCos16[16] = {
+    1.0,
+    0.92387953251128675613,
+    0.70710678118654752440,
+    0.38268343236508977173,
+    0.0,
+    -0.38268343236508977173,
+    -0.70710678118654752440,
+    -0.92387953251128675613,
+    -1.0,
+    -0.92387953251128675613,
+    -0.70710678118654752440,
+    -0.38268343236508977173,
+    0.0,
+    0.38268343236508977173,
+    0.70710678118654752440,
+    0.92387953251128675613};
+
+// d * exp(SIGN * 2 pi i idx / 16) for a compile-time-foldable idx.
+template <int SIGN, typename T>
+__device__ __forceinline__ cx<T> rot16(cx<T> d, int idx) {
+  if (idx == 0) return d;
+  if (idx == 8) return mk(-d.x, -d.y);
+  if (idx == 4) return SIGN > 0 ? mk(-d.y, d.x) : mk(d.y, -d.x);
+  if (idx == 12) return SIGN > 0 ? mk(d.y, -d.x) : mk(-d.y, d.x);
+  const T c = (T)kCos16[idx];
+  const T s = (T)(SIGN * kCos16[(idx + 12) & 15]);
+  return mk(d.x * c - d.y * s, d.x * s + d.y * c);
+}
+
+__host__ __device__ constexpr int bitrev(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b)
+    if (i & (1 << b)) r |= 1 << (bits - 1 - b);
+  return r;
+}
+__host__ __device__ constexpr int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+// In-register DFT of size R (2, 4, 8 or 16), natural order in and out.
+// Decimation in frequency, then a compile-time bit-reversal (register renaming).
+template <int R, int SIGN, typename T>
+__device__ __forceinline__ void dft_reg(cx<T>* a) {
+  static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16, "radix");
+  if constexpr (R > 1) {
+#pragma unroll
+    for (int span = R / 2; span >= 1; span >>= 1) {
+#pragma unroll
+      for (int start = 0; start < R; start += 2 * span) {
+#pragma unroll
+        for (int k = 0; k < span; ++k) {
+          const cx<T> x = a[start + k];
+          const cx<T> y = a[start + k + span];
+          a[start + k] = x + y;
+          a[start + k + span] = rot16<SIGN>(x - y, k * (16 / (2 * span)));
+        }
+      }
+    }
+    cx<T> t[R];
+    constexpr int B = ilog2(R);
+#pragma unroll
+    for (int i = 0; i < R; ++i) t[i] = a[bitrev(i, B)];
+#pragma unroll
+    for (int i = 0; i < R; ++i) a[i] = t[i];
+  }
+}
+
+// Twiddle table: tw[j] = exp(-2 pi i j / TWN), generated in FP64 on the host.
+constexpr int TWN = 4096;
+
+template <int SIGN, typename T>
+__device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int j) {
+  const cx<T> w = tw[j];
+  return SIGN > 0 ? mk(w.x, -w.y) : w;
+}
+
+// One Stockham stage (and, recursively, the rest). NS = product of the radices
+// already done. LDS addressing: element at pencil position `pos` lives at
+// lds[pos * ls] (the caller offsets lds to its pencil).
+template <typename T, int L, int E, int SIGN, int NS>
+struct Stages {
+  static constexpr int REM = L / NS;
+  static constexpr int R = REM >= E ? E : REM;
+  static constexpr bool LAST = (NS * R == L);
+  static constexpr int TT = L / E;
+  static constexpr int NB = E / R;
+
+  __device__ __forceinline__ static void run(cx<T> (&v)[E], cx<T>* lds, int ls, int t,
+                                             const cx<T>* __restrict__ tw) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = t + b * TT;
+      const int k = j & (NS - 1);
+      cx<T> a[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] = v[b + r * NB];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) a[r] = cmul(a[r], twiddle<SIGN>(tw, r * k * (TWN / (NS * R))));
+      }
+      dft_reg<R, SIGN>(a);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b + r * NB] = a[r];
+      } else {
+        const int base = (j / NS) * (NS * R) + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[(base + r * NS) * ls] = a[r];
+      }
+    }
+    if constexpr (!LAST) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = lds[(t + TT * e) * ls];
+      __syncthreads();
+      Stages<T, L, E, SIGN, NS * R>::run(v, lds, ls, t, tw);
+    }
+  }
+};
+
+// Full length-L transform of the team's registers (see the file comment).
+template <typename T, int L, int E, int SIGN>
+__device__ __forceinline__ void fft_team(cx<T> (&v)[E], cx<T>* lds, int ls, int t,
+                                         const cx<T>* __restrict__ tw) {
+  static_assert((L & (L - 1)) == 0 && L >= 1 && L <= TWN, "length");
+  static_assert(E <= L && (E & (E - 1)) == 0, "elements per thread");
+  Stages<T, L, E, SIGN, 1>::run(v, lds, ls, t, tw);
+}
+
+}  // namespace qw

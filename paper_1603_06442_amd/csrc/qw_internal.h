@@ -1,0 +1,155 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/qw.h"
+#include "qw_fft.h"
+
+namespace qw {
+
+// ---------------------------------------------------------------------------
+// Per-wave-vector apply parameters (fused contiguous FFT pass).
+// ---------------------------------------------------------------------------
+struct InstParam {  // per batch instance, device resident for batched calls
+  double m, n;      // mass and n = sqrt(1 - m^2)
+  int64_t t;        // time
+};
+
+struct PassGeom {
+  int dim;           // 1, 2, 3
+  int s;             // spinor components
+  int64_t V;         // sites per instance
+  int64_t N[3];      // lattice sizes
+  int64_t pencils;   // pencils (of all s components) over all instances
+  int64_t ppi;       // pencils per instance = V / L
+  int Nc;            // common denominator for the cos/sin(pi j / Nc) table
+  int shift[3];      // log2(Nc / N_i)
+  int fourstep;      // 1D four-step: N = N1 * L, pencil = row k1
+  int64_t N1;        // four-step rows
+  const double* cs;  // cos/sin(pi j / Nc), j in [0, 2 Nc), as (cos, sin) pairs
+  const void* tw4;   // four-step twiddles exp(-2 pi i j / N), j in [0, N)
+  double inv_scale;  // 1 / V
+  InstParam single;  // used when inst == nullptr
+  const InstParam* inst;
+};
+
+enum { MODE_EVOLVE = 0, MODE_FWD = 1, MODE_INV = 2 };
+
+// ---------------------------------------------------------------------------
+// Stencil coefficients, in the kernel's precision. Offsets per dimension:
+//   1D: +1, -1                    (2 neighbours, full 2x2 matrices)
+//   2D: (1,0), (-1,0), (0,1), (0,-1)
+//   3D: (1,0,0), (0,-1,0), (0,0,-1), (-1,-1,-1),  (-1,0,0), (0,1,0), (0,0,1), (1,1,1)
+// For d = 2, 3 each neighbour matrix is block diagonal: `up` acts on
+// components 0,1 and `lo` on components 2,3. The on-site matrix couples the
+// two halves as mass * I (components 0<->2, 1<->3); in 1D the on-site
+// matrix is a full 2x2.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StencilCoef {
+  cx<T> up[8][2][2];
+  cx<T> lo[8][2][2];
+  cx<T> onsite[2][2];  // 1D on-site matrix; for d = 2, 3 onsite[0][0] = mass coupling
+};
+
+struct StencilGeom {
+  int dim;
+  int64_t N[3];
+  int lg[3];  // log2 N_i
+  int64_t V;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the kernel translation units).
+// ---------------------------------------------------------------------------
+hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
+                              int64_t I, const void* tw, hipStream_t st);
+hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const void* in,
+                             const PassGeom& g, const void* tw, hipStream_t st);
+hipError_t launch_transpose(bool dbl, void* out, const void* in, int64_t planes, int64_t R,
+                            int64_t C, hipStream_t st);
+hipError_t launch_step(bool dbl, const StencilGeom& g, void* out, const void* in,
+                       const void* coef, hipStream_t st);
+
+struct ObsGeom {
+  int dim;
+  int s;
+  int64_t N[3];
+  int lg[3];
+  int64_t V;
+  double c[3];
+};
+constexpr int kObsFields = 13;  // norm2, s1[3], s2[6], ov_re, ov_im, ref_norm2
+constexpr int kObsBlocks = 1024;
+hipError_t launch_observables(bool dbl, const ObsGeom& g, const void* psi, const void* ref,
+                              double* partials, double* result, hipStream_t st);
+
+struct StateGeom {
+  int dim;
+  int s;
+  int64_t N[3];
+  int lg[3];
+  int64_t V;
+  double m, n;
+  double q0[3];
+  double center[3];
+  double sigma;
+  double chi_p[4][2];  // chi_+ (re, im)
+  double chi_m[4][2];  // chi_-
+  double coef_p, coef_m;  // c+/|a+|, c-/|a-| times the overall scale (fill pass)
+  int Nc;
+  int shift[3];
+  const double* cs;
+};
+hipError_t launch_state_norms(const StateGeom& g, double* partials, double* result,
+                              hipStream_t st);
+hipError_t launch_state_fill(bool dbl, const StateGeom& g, void* out, hipStream_t st);
+
+// Kernel-side helpers shared by the apply and the state preparation:
+// u_k and n~_k of the Weyl symbol at lattice frequency indices (j1, j2, j3),
+// q_i = 2 pi j_i / N_i, read from the (cos, sin)(pi j / Nc) table.
+__device__ __forceinline__ void weyl_un(int dim, const double* __restrict__ cs, int Nc,
+                                        const int* shift, int64_t j1, int64_t j2, int64_t j3,
+                                        double& u, double& n1, double& n2, double& n3) {
+  const int64_t twoNc = 2 * (int64_t)Nc;
+  const int64_t a1 = j1 << shift[0];
+  if (dim == 1) {
+    const int64_t jj = (2 * a1) & (twoNc - 1);
+    u = cs[2 * jj];
+    n1 = 0.0;
+    n2 = 0.0;
+    n3 = cs[2 * jj + 1];
+    return;
+  }
+  const int64_t a2 = j2 << shift[1];
+  if (dim == 2) {
+    // k_x = (q1 + q2) / 2, k_y = (q1 - q2) / 2.
+    const int64_t jx = (a1 + a2) & (twoNc - 1);
+    const int64_t jy = (a1 - a2 + twoNc) & (twoNc - 1);
+    const double cx_ = cs[2 * jx], sx = cs[2 * jx + 1];
+    const double cy = cs[2 * jy], sy = cs[2 * jy + 1];
+    u = cx_ * cy;
+    n1 = sx * cy;
+    n2 = cx_ * sy;
+    n3 = sx * sy;
+    return;
+  }
+  // 3D: k_x = (q1 + q2)/2, k_y = (q1 + q3)/2, k_z = -(q2 + q3)/2.
+  const int64_t a3 = j3 << shift[2];
+  const int64_t jx = (a1 + a2) & (twoNc - 1);
+  const int64_t jy = (a1 + a3) & (twoNc - 1);
+  const int64_t jz = (a2 + a3) & (twoNc - 1);
+  const double cx_ = cs[2 * jx], sx = cs[2 * jx + 1];
+  const double cy = cs[2 * jy], sy = cs[2 * jy + 1];
+  const double cz = cs[2 * jz], sz = -cs[2 * jz + 1];
+  u = cx_ * cy * cz + sx * sy * sz;
+  n1 = sx * cy * cz - cx_ * sy * sz;
+  n2 = cx_ * sy * cz + sx * cy * sz;
+  n3 = cx_ * cy * sz - sx * sy * cz;
+}
+
+}  // namespace qw

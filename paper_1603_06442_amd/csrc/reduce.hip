@@ -1,0 +1,237 @@
+// Reductions over a field (Sec. 5.2 position expectation, Sec. 5.1 overlap)
+// and the particle-state preparation of Sec. 5.1 (Definition 1) and Sec. 5.2
+// (particle/antiparticle superposition). Accumulation is FP64 for both field
+// precisions; each workgroup writes one partial vector, a second one-block
+// kernel adds the partials in a fixed order (deterministic results).
+#include "qw_internal.h"
+
+namespace qw {
+
+template <int NF>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NF], double* __restrict__ dst) {
+  __shared__ double red[NF][256 / 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    double v = acc[f];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[f][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NF) {
+    double s = 0.0;
+    for (int w = 0; w < 4; ++w) s += red[threadIdx.x][w];
+    dst[threadIdx.x] = s;
+  }
+}
+
+template <int NF>
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partials, int nblk,
+                                                      double* __restrict__ result) {
+  double acc[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] += partials[(int64_t)b * NF + f];
+  block_reduce_store<NF>(acc, result);
+}
+
+__device__ __forceinline__ double min_image(double n, double c, double N) {
+  const double d = n - c;
+  return d - N * floor((d + 0.5 * N) / N);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_observables(const cx<T>* __restrict__ psi,
+                                                     const cx<T>* __restrict__ ref, ObsGeom g,
+                                                     double* __restrict__ partials) {
+  double acc[kObsFields];
+#pragma unroll
+  for (int f = 0; f < kObsFields; ++f) acc[f] = 0.0;
+  const int64_t V = g.V;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < V; idx += stride) {
+    double p = 0.0, ore = 0.0, oim = 0.0, rn = 0.0;
+    for (int c = 0; c < g.s; ++c) {
+      const cx<T> a = psi[c * V + idx];
+      const double ax = (double)a.x, ay = (double)a.y;
+      p += ax * ax + ay * ay;
+      if (ref) {
+        const cx<T> r = ref[c * V + idx];
+        const double rx = (double)r.x, ry = (double)r.y;
+        ore += rx * ax + ry * ay;
+        oim += rx * ay - ry * ax;
+        rn += rx * rx + ry * ry;
+      }
+    }
+    double w[3] = {0.0, 0.0, 0.0};
+    int64_t rem = idx;
+    for (int i = g.dim - 1; i >= 0; --i) {
+      const int64_t ni = rem & (g.N[i] - 1);
+      rem >>= g.lg[i];
+      w[i] = min_image((double)ni, g.c[i], (double)g.N[i]);
+    }
+    acc[0] += p;
+    acc[1] += w[0] * p;
+    acc[2] += w[1] * p;
+    acc[3] += w[2] * p;
+    acc[4] += w[0] * w[0] * p;
+    acc[5] += w[1] * w[1] * p;
+    acc[6] += w[2] * w[2] * p;
+    acc[7] += w[0] * w[1] * p;
+    acc[8] += w[0] * w[2] * p;
+    acc[9] += w[1] * w[2] * p;
+    acc[10] += ore;
+    acc[11] += oim;
+    acc[12] += rn;
+  }
+  block_reduce_store<kObsFields>(acc, partials + (int64_t)blockIdx.x * kObsFields);
+}
+
+hipError_t launch_observables(bool dbl, const ObsGeom& g, const void* psi, const void* ref,
+                              double* partials, double* result, hipStream_t st) {
+  int64_t nb = (g.V + 255) / 256;
+  if (nb > kObsBlocks) nb = kObsBlocks;
+  if (dbl)
+    hipLaunchKernelGGL(k_observables<double>, dim3((unsigned)nb), dim3(256), 0, st,
+                       (const cx<double>*)psi, (const cx<double>*)ref, g, partials);
+  else
+    hipLaunchKernelGGL(k_observables<float>, dim3((unsigned)nb), dim3(256), 0, st,
+                       (const cx<float>*)psi, (const cx<float>*)ref, g, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final<kObsFields>, dim3(1), dim3(256), 0, st, partials, (int)nb,
+                     result);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Particle states. For every q on the grid:
+//   a_s(q) = exp(-sigma^2 |dq|^2 / 2) e^{+i q.c} P_s(q) chi_s,
+//   P_s = (I + s M_q / sin(omega)) / 2  (I/2 where sin(omega) < 1e-12),
+// with M_q and sin(omega) as in the per-q evolution, dq_j = q_j - q'_j wrapped
+// to [-pi, pi).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void state_amplitudes(const StateGeom& g, int64_t idx, double ap[4][2],
+                                                 double am[4][2]) {
+  int64_t j[3] = {0, 0, 0};
+  int64_t rem = idx;
+  for (int i = g.dim - 1; i >= 0; --i) {
+    j[i] = rem & (g.N[i] - 1);
+    rem >>= g.lg[i];
+  }
+  double e2 = 0.0, ph = 0.0;
+  const double twopi = 2.0 * M_PI;
+  for (int i = 0; i < g.dim; ++i) {
+    const double q = twopi * (double)j[i] / (double)g.N[i];
+    double d = q - g.q0[i] + M_PI;
+    d = d - twopi * floor(d / twopi) - M_PI;
+    e2 += d * d;
+    ph += q * g.center[i];
+  }
+  const double amp = exp(-0.5 * g.sigma * g.sigma * e2);
+  double sp, cp;
+  sincos(ph, &sp, &cp);
+  const double gr = amp * cp, gi = amp * sp;
+
+  double u, n1, n2, n3;
+  weyl_un(g.dim, g.cs, g.Nc, g.shift, j[0], j[1], j[2], u, n1, n2, n3);
+  (void)u;
+  const double nn = g.n, m = g.m;
+  const double sinw = sqrt(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
+  const double inv = sinw >= 1e-12 ? 1.0 / sinw : 0.0;
+  // Mh = M / sin(omega), applied to chi (complex) for both sectors.
+  auto apply_mh = [&](const double chi[4][2], double out[4][2]) {
+    if (g.dim == 1) {
+      const double a = nn * n3 * inv, gg = -m * inv;
+      out[0][0] = a * chi[0][0] + gg * chi[1][0];
+      out[0][1] = a * chi[0][1] + gg * chi[1][1];
+      out[1][0] = gg * chi[0][0] - a * chi[1][0];
+      out[1][1] = gg * chi[0][1] - a * chi[1][1];
+      return;
+    }
+    const double a = nn * n3 * inv, b = nn * n1 * inv, e = nn * n2 * inv, gg = -m * inv;
+    // sigma.n~ = [[n3, n1 - i n2], [n1 + i n2, -n3]] scaled by n / sin(omega)
+    // upper: a c0 + (b - i e) c1 + gg c2 ; a c0.. with c complex
+    const double* c0 = chi[0];
+    const double* c1 = chi[1];
+    const double* c2 = chi[2];
+    const double* c3 = chi[3];
+    out[0][0] = a * c0[0] + (b * c1[0] + e * c1[1]) + gg * c2[0];
+    out[0][1] = a * c0[1] + (b * c1[1] - e * c1[0]) + gg * c2[1];
+    out[1][0] = (b * c0[0] - e * c0[1]) - a * c1[0] + gg * c3[0];
+    out[1][1] = (b * c0[1] + e * c0[0]) - a * c1[1] + gg * c3[1];
+    out[2][0] = gg * c0[0] - a * c2[0] - (b * c3[0] + e * c3[1]);
+    out[2][1] = gg * c0[1] - a * c2[1] - (b * c3[1] - e * c3[0]);
+    out[3][0] = gg * c1[0] - (b * c2[0] - e * c2[1]) + a * c3[0];
+    out[3][1] = gg * c1[1] - (b * c2[1] + e * c2[0]) + a * c3[1];
+  };
+  double mp[4][2], mm[4][2];
+  apply_mh(g.chi_p, mp);
+  apply_mh(g.chi_m, mm);
+  for (int c = 0; c < g.s; ++c) {
+    // P_+ chi = (chi + Mh chi)/2, P_- chi = (chi - Mh chi)/2, times g(q).
+    const double pr = 0.5 * (g.chi_p[c][0] + mp[c][0]), pi = 0.5 * (g.chi_p[c][1] + mp[c][1]);
+    const double mr = 0.5 * (g.chi_m[c][0] - mm[c][0]), mi = 0.5 * (g.chi_m[c][1] - mm[c][1]);
+    ap[c][0] = gr * pr - gi * pi;
+    ap[c][1] = gr * pi + gi * pr;
+    am[c][0] = gr * mr - gi * mi;
+    am[c][1] = gr * mi + gi * mr;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_state_norms(StateGeom g, double* __restrict__ partials) {
+  double acc[2] = {0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < g.V; idx += stride) {
+    double ap[4][2], am[4][2];
+    state_amplitudes(g, idx, ap, am);
+    for (int c = 0; c < g.s; ++c) {
+      acc[0] += ap[c][0] * ap[c][0] + ap[c][1] * ap[c][1];
+      acc[1] += am[c][0] * am[c][0] + am[c][1] * am[c][1];
+    }
+  }
+  block_reduce_store<2>(acc, partials + (int64_t)blockIdx.x * 2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_state_fill(StateGeom g, cx<T>* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < g.V; idx += stride) {
+    double ap[4][2], am[4][2];
+    state_amplitudes(g, idx, ap, am);
+    for (int c = 0; c < g.s; ++c) {
+      const double re = g.coef_p * ap[c][0] + g.coef_m * am[c][0];
+      const double im = g.coef_p * ap[c][1] + g.coef_m * am[c][1];
+      out[c * g.V + idx] = mk((T)re, (T)im);
+    }
+  }
+}
+
+hipError_t launch_state_norms(const StateGeom& g, double* partials, double* result,
+                              hipStream_t st) {
+  int64_t nb = (g.V + 255) / 256;
+  if (nb > kObsBlocks) nb = kObsBlocks;
+  hipLaunchKernelGGL(k_state_norms, dim3((unsigned)nb), dim3(256), 0, st, g, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final<2>, dim3(1), dim3(256), 0, st, partials, (int)nb, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_fill(bool dbl, const StateGeom& g, void* out, hipStream_t st) {
+  int64_t nb = (g.V + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  if (dbl)
+    hipLaunchKernelGGL(k_state_fill<double>, dim3((unsigned)nb), dim3(256), 0, st, g,
+                       (cx<double>*)out);
+  else
+    hipLaunchKernelGGL(k_state_fill<float>, dim3((unsigned)nb), dim3(256), 0, st, g,
+                       (cx<float>*)out);
+  return hipGetLastError();
+}
+
+}  // namespace qw

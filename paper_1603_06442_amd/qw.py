@@ -1,0 +1,192 @@
+"""Python binding of libqw (ctypes). Argument marshalling only.
+
+Every computation runs in the HIP library; PyTorch supplies device memory
+and the current stream. The names mirror the C ABI of include/qw.h:
+``Plan`` wraps qw_plan / qw_destroy, and its methods call qw_step,
+qw_evolve_fft, qw_evolve_fft_batched, qw_transform, qw_observables and
+qw_prepare_state.
+
+Importing this module loads libqw.so and fails loudly if it is missing.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqw.so")
+
+QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE = range(5)
+QW_C64, QW_C128 = 0, 1
+DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
+EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_evolve_fft", "qw_evolve_fft_batched",
+           "qw_transform", "qw_observables", "qw_prepare_state", "qw_last_error", "qw_version")
+
+
+class QwError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("qw status %d: %s" % (status, message))
+        self.status = status
+
+
+class QwObs(ctypes.Structure):
+    _fields_ = [("norm2", ctypes.c_double), ("mean", ctypes.c_double * 3),
+                ("second", ctypes.c_double * 6), ("mean_cart", ctypes.c_double * 3),
+                ("overlap_re", ctypes.c_double), ("overlap_im", ctypes.c_double),
+                ("ref_norm2", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqw.so is not built (%s): run __graft_entry__.build() or "
+                          "python -m paper_1603_06442_amd.build" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, cint = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    sig = {
+        "qw_plan": [ctypes.POINTER(vp), cint, ctypes.POINTER(i64), dbl, cint, vp],
+        "qw_destroy": [vp],
+        "qw_step": [vp, vp, i64, vp],
+        "qw_evolve_fft": [vp, vp, vp, i64, vp],
+        "qw_evolve_fft_batched": [vp, cint, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), vp],
+        "qw_transform": [vp, vp, vp, cint, vp],
+        "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
+        "qw_prepare_state": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = cint
+    lib.qw_last_error.restype = ctypes.c_char_p
+    lib.qw_last_error.argtypes = []
+    lib.qw_version.restype = ctypes.c_char_p
+    lib.qw_version.argtypes = []
+    return lib
+
+
+LIB = _load()
+
+
+def _check(status):
+    if status != QW_OK:
+        raise QwError(status, LIB.qw_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _darr(vals, n):
+    vals = [float(v) for v in vals]
+    if len(vals) != n:
+        raise ValueError("expected %d values, got %d" % (n, len(vals)))
+    return (ctypes.c_double * n)(*vals)
+
+
+class Plan:
+    """A lattice shape, mass and precision (qw_plan)."""
+
+    def __init__(self, dim, N, m, dtype="c64", stream=None):
+        if dtype not in DTYPES:
+            raise ValueError("dtype must be 'c64' or 'c128'")
+        self.dim = int(dim)
+        Ns = [int(N)] * self.dim if isinstance(N, int) else [int(x) for x in N]
+        if len(Ns) != self.dim:
+            raise ValueError("need %d lattice sizes" % self.dim)
+        self.N = tuple(Ns)
+        self.m = float(m)
+        self.dtype = dtype
+        self.s = 2 if self.dim == 1 else 4
+        self.torch_dtype = DTYPES[dtype][1]
+        self.shape = (self.s,) + self.N
+        self._h = ctypes.c_void_p()
+        arr = (ctypes.c_int64 * self.dim)(*Ns)
+        _check(LIB.qw_plan(ctypes.byref(self._h), self.dim, arr, self.m, DTYPES[dtype][0],
+                           _stream(stream)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            LIB.qw_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------
+    def empty(self, batch=None, device="cuda"):
+        shape = self.shape if batch is None else (batch,) + self.shape
+        return torch.empty(shape, dtype=self.torch_dtype, device=device)
+
+    def _field(self, x, batch=1, name="field"):
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+        if x.dtype != self.torch_dtype:
+            raise TypeError("%s has dtype %s, plan needs %s" % (name, x.dtype, self.torch_dtype))
+        if not x.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        want = batch * self.s
+        for n in self.N:
+            want *= n
+        if x.numel() != want:
+            raise ValueError("%s has %d elements, expected %d" % (name, x.numel(), want))
+        return ctypes.c_void_p(x.data_ptr())
+
+    # -- C ABI calls ----------------------------------------------------------
+    def step(self, psi, nsteps, stream=None):
+        """qw_step: nsteps position-space steps, in place."""
+        _check(LIB.qw_step(self._h, self._field(psi, name="psi"), int(nsteps), _stream(stream)))
+        return psi
+
+    def evolve_fft(self, psi0, t, out=None, stream=None):
+        """qw_evolve_fft: U^t psi0 by one Fourier jump (out may be psi0)."""
+        if out is None:
+            out = torch.empty_like(psi0)
+        _check(LIB.qw_evolve_fft(self._h, self._field(psi0, name="psi0"),
+                                 self._field(out, name="out"), int(t), _stream(stream)))
+        return out
+
+    def evolve_fft_batched(self, x, m, t, out=None, stream=None):
+        """qw_evolve_fft_batched over x[B, s, N..]: per-instance mass and time."""
+        B = int(x.shape[0])
+        if out is None:
+            out = torch.empty_like(x)
+        ma = (ctypes.c_double * B)(*[float(v) for v in m])
+        ta = (ctypes.c_int64 * B)(*[int(v) for v in t])
+        _check(LIB.qw_evolve_fft_batched(self._h, B, self._field(x, B, "x"),
+                                         self._field(out, B, "out"), ma, ta, _stream(stream)))
+        return out
+
+    def transform(self, x, direction, out=None, stream=None):
+        """qw_transform: unnormalised DFT, +1 = e^{+iq.n} forward, -1 inverse."""
+        if out is None:
+            out = torch.empty_like(x)
+        _check(LIB.qw_transform(self._h, self._field(x, name="x"), self._field(out, name="out"),
+                                int(direction), _stream(stream)))
+        return out
+
+    def observables(self, psi, origin, ref=None, stream=None):
+        """qw_observables: norm, positions about origin, overlap with ref."""
+        o = QwObs()
+        refp = self._field(ref, name="ref") if ref is not None else ctypes.c_void_p(0)
+        _check(LIB.qw_observables(self._h, self._field(psi, name="psi"),
+                                  _darr(origin, self.dim), refp, ctypes.byref(o), _stream(stream)))
+        return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
+                "mean_cart": list(o.mean_cart),
+                "overlap": complex(o.overlap_re, o.overlap_im), "ref_norm2": o.ref_norm2}
+
+    def prepare_state(self, psi, k0, sigma, center, c_plus=1.0, c_minus=0.0, stream=None):
+        """qw_prepare_state: Gaussian particle/antiparticle state, unit norm."""
+        _check(LIB.qw_prepare_state(self._h, self._field(psi, name="psi"), _darr(k0, self.dim),
+                                    float(sigma), _darr(center, self.dim), float(c_plus),
+                                    float(c_minus), _stream(stream)))
+        return psi
+
+
+def version():
+    return LIB.qw_version().decode()

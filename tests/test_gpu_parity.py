@@ -1,0 +1,226 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Inputs come from the seeded generators or from the oracle; nothing the oracle
+sees comes from the GPU. Tolerances (relative L2 over all entries, no phase
+alignment):
+* complex128: 1e-12 for t <= 1e3 and 1e-15 t beyond (the phase omega t
+  carries an absolute error ~ t * eps64);
+* complex64: 2e-5 for the Fourier jump (FP32 transforms, FP64 phase); the
+  FP32 stencil accumulates ~sqrt(steps) * 2^-24 per entry, bounded here by
+  max(2e-5, 4 sqrt(steps) 2^-24).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fourier, observables as ob, states, stepper, walk
+from paper_1603_06442_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1603_06442_amd import qw as mod
+    return mod
+
+
+def to_dev(x, plan):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(plan.torch_dtype).cuda()
+
+
+def to_np(x):
+    torch.cuda.synchronize()
+    return x.cpu().numpy().astype(np.complex128)
+
+
+def tol_fft(dtype, t):
+    return 2e-5 if dtype == "c64" else max(1e-12, 1e-15 * abs(t))
+
+
+def tol_step(dtype, steps):
+    return max(2e-5, 4 * math.sqrt(steps) * 2.0 ** -24) if dtype == "c64" else 1e-12
+
+
+def table(d, m):
+    return walk.stencil_table(d, m)
+
+
+SHAPES = [(1, (64,)), (1, (256,)), (2, (8, 16)), (2, (32, 32)), (3, (4, 8, 16)), (3, (16, 16, 16))]
+
+
+def rand_field(d, shape, seed):
+    rng = np.random.default_rng(seed)
+    s = walk.spinor_dim(d)
+    psi = rng.standard_normal((s,) + shape) + 1j * rng.standard_normal((s,) + shape)
+    return psi / np.linalg.norm(psi)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", SHAPES)
+@pytest.mark.parametrize("m", [0.0, 0.13, 1.0])
+def test_step_matches_oracle(qw, d, shape, m, dtype):
+    psi0 = rand_field(d, shape, 100 + d)
+    plan = qw.Plan(d, list(shape), m, dtype)
+    x = to_dev(psi0, plan)
+    plan.step(x, 7)
+    ref = stepper.evolve_steps(psi0, table(d, m), 7)
+    assert ob.rel_l2(to_np(x), ref) < tol_step(dtype, 7)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", SHAPES + [(1, (8192,)), (1, (65536,)), (1, (2,)), (3, (2, 2, 2))])
+def test_transform_matches_dft(qw, d, shape, dtype):
+    psi0 = rand_field(d, shape, 7)
+    plan = qw.Plan(d, list(shape), 0.2, dtype)
+    x = to_dev(psi0, plan)
+    fw = plan.transform(x, +1)
+    ref = fourier.dft(psi0)
+    tol = 1e-6 if dtype == "c64" else 1e-13
+    assert ob.rel_l2(to_np(fw), ref) < tol
+    back = plan.transform(fw, -1)
+    assert ob.rel_l2(to_np(back) / np.prod(shape), psi0) < tol
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", SHAPES + [(1, (8192,))])
+@pytest.mark.parametrize("t", [0, 1, 5, -3, 1000, 100000])
+def test_evolve_fft_matches_oracle(qw, d, shape, t, dtype):
+    m = 0.21
+    psi0 = rand_field(d, shape, 200 + d)
+    plan = qw.Plan(d, list(shape), m, dtype)
+    out = plan.evolve_fft(to_dev(psi0, plan), t)
+    ref = fourier.evolve_fourier(psi0, table(d, m), t)
+    assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", [(1, (128,)), (2, (16, 16)), (3, (8, 8, 8))])
+@pytest.mark.parametrize("m", [0.0, 1.0])
+def test_evolve_fft_degenerate_masses(qw, d, shape, m, dtype):
+    """m = 0 (sin omega = 0 at the band centre) and m = 1 (n = 0)."""
+    psi0 = rand_field(d, shape, 5)
+    plan = qw.Plan(d, list(shape), m, dtype)
+    for t in (1, 2, 7, 64):
+        out = plan.evolve_fft(to_dev(psi0, plan), t)
+        ref = fourier.evolve_fourier(psi0, table(d, m), t)
+        assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_evolve_in_place_and_reversible(qw, dtype):
+    d, shape, m = 3, (16, 16, 16), 0.3
+    psi0 = rand_field(d, shape, 9)
+    plan = qw.Plan(d, list(shape), m, dtype)
+    x = to_dev(psi0, plan)
+    plan.evolve_fft(x, 12345, out=x)
+    plan.evolve_fft(x, -12345, out=x)
+    assert ob.rel_l2(to_np(x), psi0) < (4e-5 if dtype == "c64" else 1e-11)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_fft_jump_equals_steps_on_gpu(qw, dtype):
+    d, shape, m = 3, (16, 16, 16), 0.05
+    psi0 = rand_field(d, shape, 3)
+    plan = qw.Plan(d, list(shape), m, dtype)
+    a = to_dev(psi0, plan)
+    plan.step(a, 20)
+    b = plan.evolve_fft(to_dev(psi0, plan), 20)
+    assert ob.rel_l2(to_np(a), to_np(b)) < (4e-5 if dtype == "c64" else 1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", [(1, (512,)), (2, (32, 16)), (3, (16, 16, 16))])
+def test_observables_match_oracle(qw, d, shape, dtype):
+    psi = rand_field(d, shape, 11)
+    refp = rand_field(d, shape, 12)
+    plan = qw.Plan(d, list(shape), 0.1, dtype)
+    c = [n // 3 + 0.0 for n in shape]
+    got = plan.observables(to_dev(psi, plan), c, ref=to_dev(refp, plan))
+    # the oracle sees the field rounded to the GPU's precision
+    if dtype == "c64":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+        refp = refp.astype(np.complex64).astype(np.complex128)
+    want = ob.observables(psi, c, refp)
+    assert abs(got["norm2"] - want["norm2"]) < 1e-12
+    assert np.allclose(got["mean"], want["mean"], atol=1e-10)
+    assert np.allclose(got["second"], want["second"], atol=1e-9)
+    assert np.allclose(got["mean_cart"], want["mean_cart"], atol=1e-10)
+    assert abs(got["overlap"] - want["overlap"]) < 1e-12
+    assert abs(got["ref_norm2"] - want["ref_norm2"]) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,N,k0,sigma,cp,cm", [
+    (1, 1024, [0.3], 10.0, 1.0, 0.0),
+    (1, 8192, [-0.2], 40.0, 0.6, 0.8),
+    (2, 64, [0.2, -0.1], 4.0, 1 / math.sqrt(2), 1 / math.sqrt(2)),
+    (3, 32, [0.1, 0.1, 0.1], 3.0, 1 / math.sqrt(2), 1 / math.sqrt(2)),
+    (3, 32, [0.3, -0.2, 0.1], 2.5, 0.0, 1.0),
+])
+def test_prepare_state_matches_oracle(qw, d, N, k0, sigma, cp, cm, dtype):
+    m = 0.1
+    c = [N // 2] * d
+    plan = qw.Plan(d, N, m, dtype)
+    x = plan.empty()
+    plan.prepare_state(x, k0, sigma, c, cp, cm)
+    want = states.particle_state(d, N, m, k0, sigma, c, cp, cm)
+    assert ob.rel_l2(to_np(x), want) < (2e-6 if dtype == "c64" else 1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batched_matches_single_and_oracle(qw, dtype):
+    d, shape = 3, (8, 8, 16)
+    plan = qw.Plan(d, list(shape), 0.1, dtype)
+    B = 5
+    ms = [0.0, 0.05, 0.1, 0.3, 1.0]
+    ts = [1, 17, -4, 100000, 3]
+    xs = np.stack([rand_field(d, shape, 50 + b) for b in range(B)])
+    x = to_dev(xs, plan)
+    out = plan.evolve_fft_batched(x, ms, ts)
+    outn = to_np(out)
+    for b in range(B):
+        single = qw.Plan(d, list(shape), ms[b], dtype)
+        one = single.evolve_fft(to_dev(xs[b], single), ts[b])
+        assert torch.equal(out[b], one), "batched result differs from the single call"
+        ref = fourier.evolve_fourier(xs[b], table(d, ms[b]), ts[b])
+        assert ob.rel_l2(outn[b], ref) < tol_fft(dtype, ts[b])
+
+
+def test_workload_line_4096_c128(qw):
+    """The 1D workload: N = 4096, complex128, m = 0.1, packet at k0 = 0.3,
+    width 40: 1000 steps and the t = 1000 jump vs the oracle, drift law."""
+    w = inputs.workload(0)
+    psi0 = states.particle_state(1, w["N"], w["m"], w["k0"], w["sigma"], w["center"])
+    plan = qw.Plan(1, w["N"], w["m"], "c128")
+    ref = stepper.evolve_steps(psi0, table(1, w["m"]), w["steps"])
+    x = to_dev(psi0, plan)
+    plan.step(x, w["steps"])
+    assert ob.rel_l2(to_np(x), ref) < 1e-12
+    y = plan.evolve_fft(to_dev(psi0, plan), w["t"])
+    assert ob.rel_l2(to_np(y), ref) < 1e-12
+    o0 = plan.observables(to_dev(psi0, plan), w["center"])
+    o1 = plan.observables(y, w["center"])
+    drift = ob.drift_prediction(psi0, table(1, w["m"]), w["t"])[0]
+    assert abs((o1["mean"][0] - o0["mean"][0]) - drift) < 1e-8
+    assert abs(o1["norm2"] - 1.0) < 1e-12
+
+
+def test_workload_bcc_64_c64(qw):
+    """The 64^3 BCC workload (complex64 on the GPU vs complex128 oracle):
+    t = 128 by the stencil and by one Fourier jump."""
+    w = inputs.workload(1)
+    psi0 = states.particle_state(3, w["N"], w["m"], w["k0"], w["sigma"], w["center"])
+    ref = fourier.evolve_fourier(psi0, table(3, w["m"]), w["t"])
+    plan = qw.Plan(3, w["N"], w["m"], "c64")
+    x = to_dev(psi0, plan)
+    plan.step(x, w["steps"])
+    assert ob.rel_l2(to_np(x), ref) < tol_step("c64", w["steps"])
+    y = plan.evolve_fft(to_dev(psi0, plan), w["t"])
+    assert ob.rel_l2(to_np(y), ref) < 2e-5
+    o = plan.observables(y, w["center"])
+    assert abs(o["norm2"] - 1.0) < 1e-5

@@ -1,0 +1,77 @@
+"""CPU-side checks of the C-ABI library: it loads, and exports every entry
+point that include/qw.h declares. No compute calls (no GPU here)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qw.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qw_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("qw_plan", "qw_step", "qw_evolve_fft", "qw_observables", "qw_destroy"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1603_06442_amd import qw
+    out = subprocess.run(["nm", "-D", "--defined-only", qw.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [s for s in declared_symbols() if s not in exported]
+    assert not missing, missing
+    assert set(qw.EXPORTS) <= exported
+
+
+def test_library_loads_and_reports_version():
+    from paper_1603_06442_amd import qw
+    assert "gfx950" in qw.version()
+
+
+def test_binding_validates_before_the_library():
+    from paper_1603_06442_amd import qw
+    with pytest.raises(ValueError):
+        qw.Plan(3, [8, 8], 0.1)
+    with pytest.raises(ValueError):
+        qw.Plan(1, 16, 0.1, dtype="f16")
+
+
+@pytest.mark.parametrize("dim,N,m,status", [
+    (4, [8], 0.1, 1),            # dimension
+    (0, [8], 0.1, 1),
+    (1, [8], -0.1, 1),           # mass outside [0, 1]
+    (1, [8], 1.5, 1),
+    (1, [8], float("nan"), 1),
+    (1, [12], 0.1, 2),           # not a power of two
+    (1, [131072], 0.1, 2),       # beyond the 1D limit
+    (2, [2048, 2048], 0.1, 2),   # beyond the 2D limit
+    (3, [8, 8, 1024], 0.1, 2),   # beyond the 3D limit
+    (3, [8, 0, 8], 0.1, 1),      # non-positive size
+])
+def test_plan_rejects_bad_arguments_on_the_host(dim, N, m, status):
+    """Argument validation happens on the host, before any device call."""
+    import ctypes
+    from paper_1603_06442_amd import qw
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int64 * len(N))(*N)
+    got = qw.LIB.qw_plan(ctypes.byref(h), dim, arr, m, 0, None)
+    assert got == status
+    assert h.value is None
+    assert qw.LIB.qw_last_error().decode()
+
+
+def test_calls_reject_null_plan():
+    import ctypes
+    from paper_1603_06442_amd import qw
+    assert qw.LIB.qw_step(None, ctypes.c_void_p(1), 1, None) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_evolve_fft(None, None, None, 1, None) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_destroy(None) == qw.QW_OK
