@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark of the Dirac quantum-walk hot path on one MI355X.
+
+Workload: the 3D walk on the BCC lattice stored as a 256^3 primitive-cell
+torus, 4-component complex64 spinor (FP32 transforms and stencil, FP64
+phase), m = 0.02, an equal-weight particle/antiparticle Gaussian state at
+k0 = (0.1, 0.1, 0.1) with width 20 cells, prepared on the GPU. One timed
+step is one pass over the whole hot path:
+  * one Fourier jump psi_t = U^t psi_0 (t cycling through the 64 times
+    log-spaced in [1, 1e5]),
+  * the position/norm reduction of psi_t (the Zitterbewegung observable),
+  * two position-space steps of a second field.
+`value` is steps per second, i.e. Fourier evolutions per second with the
+reduction and the two stencil steps included in each. The JSON line also
+carries the stencil's own site-steps/s, the roofline of the dominant kernel
+measured with HIP events on the launch stream, and the FP64 CPU oracle timed
+on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --copy-calib   (a plain copy of one field, for counters)
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bcc256_c64.json")
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle's Fourier evaluation (numpy DFT + per-q binary powering
+    of the symbol) on the 64^3 sub-lattice of the workload, timed on the host
+    and scaled by 64^3/256^3 to evolutions of the 256^3 lattice."""
+    import numpy as np
+    from oracle import fourier, states, walk
+    Ns = 64
+    table = walk.stencil_table(3, w["m"])
+    psi = states.particle_state(3, Ns, w["m"], w["k0"], w["sigma"] * Ns / 256.0, [Ns // 2] * 3,
+                                w["c_plus"], w["c_minus"])
+    times = w["times"]
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        fourier.evolve_fourier(psi, table, times[(7 * done + 40) % len(times)])
+        done += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or done >= 64:
+            break
+    rate64 = done / el
+    scale = (Ns / 256.0) ** 3
+    return {"value": rate64 * scale, "unit": "evolutions/s", "cores": 1, "kind": "oracle",
+            "sample": "%d oracle Fourier evolutions (numpy FFT + binary powering, complex128, "
+                      "single thread) of the 64^3 sub-lattice at t from the 1..1e5 schedule in "
+                      "%.1f s, scaled by (64/256)^3 to the 256^3 unit" % (done, el),
+            "host_threads_available": os.cpu_count()}
+
+
+def copy_calib(steps):
+    import torch
+    n = 4 * 256 ** 3
+    x = torch.ones(n, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(steps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calib_bytes_read": 8 * n, "copy_calib_bytes_written": 8 * n,
+                      "launches": steps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calib:
+        copy_calib(max(1, args.steps))
+        return
+    from paper_1603_06442_amd import inputs, qw
+
+    w = inputs.workload(2)
+    N = w["N"]
+    torch.cuda.set_device(0)
+    plan = qw.Plan(3, N, w["m"], "c64")
+    psi0 = plan.empty()
+    plan.prepare_state(psi0, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
+    psit = plan.empty()
+    psis = psi0.clone()
+    times = w["times"]
+    V = N ** 3
+    field_bytes = psi0.numel() * psi0.element_size()
+
+    def step(i):
+        plan.evolve_fft(psi0, times[i % len(times)], out=psit)
+        o = plan.observables(psit, w["center"])
+        plan.step(psis, 2)
+        return o
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        obs = step(i)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / args.steps
+
+    # Per-kernel durations, HIP events on the launch stream.
+    reps = 10
+    acc = None
+    for r in range(reps):
+        _, ms = plan.evolve_fft_timed(psi0, times[(5 * r) % len(times)], out=psit)
+        acc = ms if acc is None else [a + b for a, b in zip(acc, ms)]
+    pass_ms = [a / reps for a in acc]
+    names = ["fft_strided n1 fwd", "fft_strided n2 fwd", "fft_contig n3 fwd+apply+inv",
+             "fft_strided n2 inv", "fft_strided n1 inv"]
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        plan.step(psis, 2)
+    e1.record(st)
+    e1.synchronize()
+    stencil_ms = e0.elapsed_time(e1) / (2 * reps)
+    evo_ms = sum(pass_ms)
+
+    dom = max(range(len(pass_ms)), key=lambda i: pass_ms[i])
+    alg_bytes = 2 * field_bytes
+    achieved = alg_bytes / (pass_ms[dom] * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        traffic = tr.get(names[dom])
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": names[dom], "kernel_ms": round(pass_ms[dom], 4),
+                "algorithmic_bytes_per_launch": alg_bytes}
+    stencil_gbs = 2 * field_bytes / (stencil_ms * 1e-3) / 1e9
+
+    line = {
+        "metric": "lattice site-steps/s and FFT evolutions/s at 256^3 4-spinor; p99 request latency",
+        "value": round(1e3 / ms_per_step, 3),
+        "unit": "evolutions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "bcc256_zb: 3D Dirac walk, 256^3 BCC primitive-cell torus, "
+                               "4-spinor complex64, m=0.02, particle+antiparticle Gaussian "
+                               "k0=(0.1,0.1,0.1) sigma=20, t over 64 log-spaced times in [1,1e5]",
+                   "step": "1 Fourier jump + 1 position/norm reduction + 2 stencil steps",
+                   "lattice": [N, N, N], "spinor": 4, "global_batch": 1},
+        "fft_evolutions_per_s_kernels": round(1e3 / evo_ms, 2),
+        "fft_pass_ms": {n: round(v, 4) for n, v in zip(names, pass_ms)},
+        "stencil_site_steps_per_s": round(V / (stencil_ms * 1e-3), 1),
+        "stencil_ms_per_step": round(stencil_ms, 4),
+        "stencil_gbs": round(stencil_gbs, 1),
+        "roofline": roofline,
+        "last_obs": {"norm2": obs["norm2"], "mean_cart": obs["mean_cart"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

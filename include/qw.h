@@ -124,13 +124,20 @@ qw_status qw_observables(qw_plan_t plan, const void* psi, const double* origin, 
  * with dq_j = q_j - q'_j wrapped to [-pi, pi), q' = H^T k0 the lattice image
  * of the Cartesian k0, P_+ / P_- the projectors of D_q on its eigenvalues
  * e^{-i omega} / e^{+i omega} (I/2 where sin omega < 1e-12), chi_s the
- * normalised column of P_s(q') of largest norm (lowest index on ties); then
+ * normalised column of P_s(q') of largest norm (the lowest index whose norm
+ * is within a relative 1e-12 of the largest: projector columns tie in pairs); then
  * psi = inverse DFT scaled to unit 2-norm.
  *   k0: dim HOST doubles (Cartesian); sigma > 0 in lattice cells;
  *   center: dim HOST doubles; c_plus, c_minus real, not both 0.
  * Waits for completion. */
 qw_status qw_prepare_state(qw_plan_t plan, void* psi, const double* k0, double sigma,
                            const double* center, double c_plus, double c_minus, void* stream);
+
+/* qw_evolve_fft with a HIP event recorded on `stream` around every kernel
+ * pass; waits, then writes the duration of each pass (ms) to pass_ms and
+ * their count to *npass (at most 8; 5 for d = 3). For measurement. */
+qw_status qw_evolve_fft_timed(qw_plan_t plan, const void* psi0, void* psi_t, int64_t t,
+                              void* stream, float* pass_ms, int* npass);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* qw_last_error(void);

@@ -13,7 +13,9 @@ Readings (listed in the design notes):
   the carrier e^{+i q.c} that centres the packet at site c.
 * "Projected on the eigenvector" is taken gauge-free: the sector projector
   P_s(q) applied to a fixed spinor chi_s, the normalised column of P_s(q')
-  with the largest 2-norm (lowest index on ties). P_+ is the spectral
+  with the largest 2-norm. The column norms of a projector come in exact
+  structural pairs (P_jj = P_kk), so the tie rule takes the lowest index
+  whose norm is within a relative 1e-12 of the largest. P_+ is the spectral
   projector of U_q on its eigenvalue e^{-i omega} (positive frequency,
   particle), P_- the one on e^{+i omega}.
 """
@@ -43,9 +45,13 @@ def sector_projectors(D):
     return 0.5 * (eye + Mh), 0.5 * (eye - Mh)
 
 
+CHI_TIE = 1e-12
+
+
 def _chi(P0):
     norms = np.sqrt(np.sum(np.abs(P0) ** 2, axis=0))
-    j = int(np.argmax(norms))  # argmax takes the lowest index on ties
+    top = norms.max()
+    j = int(np.flatnonzero(norms >= top * (1.0 - CHI_TIE))[0])
     return P0[:, j] / norms[j]
 
 

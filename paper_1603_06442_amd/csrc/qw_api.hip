@@ -417,6 +417,18 @@ struct qw_plan_s {
 
 namespace {
 
+// Optional per-pass event recorder (measurement entry point only).
+struct PassTimer {
+  hipEvent_t ev[9];
+  int n = 0;
+  hipStream_t st = nullptr;
+};
+thread_local PassTimer* g_timer = nullptr;
+
+inline void mark() {
+  if (g_timer && g_timer->n < 9) (void)hipEventRecord(g_timer->ev[g_timer->n++], g_timer->st);
+}
+
 qw_status ensure_scratch(qw_plan_t p, size_t bytes) {
   if (p->scratch_bytes >= bytes) return QW_OK;
   if (p->d_scratch) {
@@ -495,15 +507,21 @@ qw_status strided_passes(qw_plan_t p, int sign, void* out, const void* in, int B
     const int64_t N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
     if (sign > 0) {
       HIP_TRY(launch_fft_strided(p->dbl, 1, N1, out, in, (int64_t)s * B, N2 * N3, p->d_tw, st));
+      mark();
       HIP_TRY(launch_fft_strided(p->dbl, 1, N2, out, out, (int64_t)s * B * N1, N3, p->d_tw, st));
+      mark();
     } else {
       HIP_TRY(launch_fft_strided(p->dbl, -1, N2, out, in, (int64_t)s * B * N1, N3, p->d_tw, st));
+      mark();
       HIP_TRY(launch_fft_strided(p->dbl, -1, N1, out, out, (int64_t)s * B, N2 * N3, p->d_tw, st));
+      mark();
     }
   } else if (p->dim == 2) {
     HIP_TRY(launch_fft_strided(p->dbl, sign, p->N[0], out, in, (int64_t)s * B, p->N[1], p->d_tw, st));
+    mark();
   } else if (p->fourstep) {
     HIP_TRY(launch_fft_strided(p->dbl, sign, p->fs_N1, out, in, (int64_t)s * B, p->fs_N2, p->d_tw, st));
+    mark();
   } else if (out != in) {
     HIP_TRY(hipMemcpyAsync(out, in, p->field_bytes * B, hipMemcpyDeviceToDevice, st));
   }
@@ -528,9 +546,11 @@ qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstP
     qw_status r = strided_passes(p, +1, out, in, B, st);
     if (r != QW_OK) return r;
     HIP_TRY(launch_fft_contig(p->dbl, MODE_EVOLVE, L, out, out, g, p->d_tw, st));
+    mark();
     return strided_passes(p, -1, out, out, B, st);
   }
   HIP_TRY(launch_fft_contig(p->dbl, MODE_EVOLVE, L, out, in, g, p->d_tw, st));
+  mark();
   return QW_OK;
 }
 
@@ -698,6 +718,36 @@ qw_status qw_evolve_fft(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, v
   return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
 }
 
+qw_status qw_evolve_fft_timed(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, void* stream,
+                              float* pass_ms, int* npass) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi0 || !psi_t || !pass_ms || !npass) return fail(QW_ERR_INVALID, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  PassTimer tm;
+  tm.st = st;
+  for (int i = 0; i < 9; ++i) HIP_TRY(hipEventCreate(&tm.ev[i]));
+  HIP_TRY(hipEventRecord(tm.ev[tm.n++], st));
+  InstParam ip;
+  ip.m = p->m;
+  ip.n = p->n;
+  ip.t = t;
+  g_timer = &tm;
+  r = evolve_impl(p, 1, psi0, psi_t, nullptr, ip, st);
+  g_timer = nullptr;
+  hipError_t e = hipEventSynchronize(tm.ev[tm.n - 1]);
+  *npass = tm.n - 1;
+  for (int i = 0; i + 1 < tm.n && i < 8; ++i) {
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, tm.ev[i], tm.ev[i + 1]);
+    pass_ms[i] = ms;
+  }
+  for (int i = 0; i < 9; ++i) (void)hipEventDestroy(tm.ev[i]);
+  if (r != QW_OK) return r;
+  if (e != hipSuccess) return fail(QW_ERR_DEVICE, "event timing: %s", hipGetErrorString(e));
+  return QW_OK;
+}
+
 qw_status qw_evolve_fft_batched(qw_plan_t p, int B, const void* in, void* out, const double* m,
                                 const int64_t* t, void* stream) {
   qw_status r = check_plan(p);
@@ -858,17 +908,17 @@ qw_status qw_prepare_state(qw_plan_t p, void* psi, const double* k0, double sigm
         const zc mh = sinw >= 1e-12 ? M[a][b] / sinw : zc(0.0);
         P[a][b] = 0.5 * ((a == b ? 1.0 : 0.0) + sg * mh);
       }
-    int best = 0;
-    double bn = -1.0;
+    // Column norms of a projector come in exact pairs (P_jj = P_kk): take the
+    // lowest index within a relative 1e-12 of the largest norm.
+    double nrm[4] = {0.0, 0.0, 0.0, 0.0}, top = 0.0;
     for (int b = 0; b < s; ++b) {
-      double nrm = 0.0;
-      for (int a = 0; a < s; ++a) nrm += std::norm(P[a][b]);
-      nrm = sqrt(nrm);
-      if (nrm > bn) {
-        bn = nrm;
-        best = b;
-      }
+      for (int a = 0; a < s; ++a) nrm[b] += std::norm(P[a][b]);
+      nrm[b] = sqrt(nrm[b]);
+      top = fmax(top, nrm[b]);
     }
+    int best = 0;
+    while (best < s - 1 && !(nrm[best] >= top * (1.0 - 1e-12))) ++best;
+    const double bn = nrm[best];
     double (*chi)[2] = sec == 0 ? g.chi_p : g.chi_m;
     for (int a = 0; a < s; ++a) {
       chi[a][0] = P[a][best].real() / bn;

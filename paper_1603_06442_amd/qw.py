@@ -20,7 +20,8 @@ QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE = range(5
 QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_evolve_fft", "qw_evolve_fft_batched",
-           "qw_transform", "qw_observables", "qw_prepare_state", "qw_last_error", "qw_version")
+           "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_prepare_state",
+           "qw_last_error", "qw_version")
 
 
 class QwError(RuntimeError):
@@ -47,6 +48,8 @@ def _load():
         "qw_destroy": [vp],
         "qw_step": [vp, vp, i64, vp],
         "qw_evolve_fft": [vp, vp, vp, i64, vp],
+        "qw_evolve_fft_timed": [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(cint)],
         "qw_evolve_fft_batched": [vp, cint, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), vp],
         "qw_transform": [vp, vp, vp, cint, vp],
         "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
@@ -150,6 +153,17 @@ class Plan:
         _check(LIB.qw_evolve_fft(self._h, self._field(psi0, name="psi0"),
                                  self._field(out, name="out"), int(t), _stream(stream)))
         return out
+
+    def evolve_fft_timed(self, psi0, t, out=None, stream=None):
+        """qw_evolve_fft_timed: the jump plus the duration (ms) of each pass."""
+        if out is None:
+            out = torch.empty_like(psi0)
+        ms = (ctypes.c_float * 8)()
+        n = ctypes.c_int(0)
+        _check(LIB.qw_evolve_fft_timed(self._h, self._field(psi0, name="psi0"),
+                                       self._field(out, name="out"), int(t), _stream(stream), ms,
+                                       ctypes.byref(n)))
+        return out, [ms[i] for i in range(n.value)]
 
     def evolve_fft_batched(self, x, m, t, out=None, stream=None):
         """qw_evolve_fft_batched over x[B, s, N..]: per-instance mass and time."""
