@@ -17,8 +17,9 @@
 // sin(omega) = sqrt(n^2 |n~|^2 + m^2), omega = atan2(sin, cos) and
 //   M_q = [[n sigma.n~, -m I], [-m I, -n sigma.n~]]   (d = 2, 3),
 //   M_q = n sin(q) sigma_z - m sigma_x                 (d = 1),
-// so that D_q = cos(omega) I - i M_q and M_q^2 = sin^2(omega) I. The phase
-// omega, omega t and its sine/cosine are FP64 in both precisions.
+// so that D_q = cos(omega) I - i M_q and M_q^2 = sin^2(omega) I. omega,
+// omega t and its reduction modulo 2 pi are FP64 in both precisions; the
+// sine and cosine of the reduced angle are FP32 for complex64 fields.
 //
 // 1D four-step (N = N1 * L): the strided pass has already transformed along
 // n1 (rows k1); here each pencil is one row, pre-multiplied by
@@ -29,23 +30,73 @@
 
 namespace qw {
 
-template <typename T, int DIM>
+// omega t reduced to [-pi, pi] in FP64: the product is split exactly into
+// p + pl (FMA remainder), then 2 pi is removed in two parts (Cody-Waite:
+// 2 pi = HI + LO with HI the double nearest 2 pi). For |k| < 2^20 the first
+// FMA is exact, so the reduced angle keeps the accuracy of omega itself.
+__device__ __forceinline__ double reduced_phase(double w, int64_t t) {
+  const double tt = (double)t;
+  const double p = w * tt;
+  const double pl = fma(w, tt, -p);
+  const double k = rint(p * 0.15915494309189533577);
+  double r = fma(-k, 6.283185307179586232, p);
+  r = fma(-k, 2.4492935982947063545e-16, r);
+  return r + pl;
+}
+
+// omega(q) = atan2(sin(omega), cos(omega)) with cos(omega) = n u and
+// sin(omega) = sqrt(n^2 |n~|^2 + m^2), in FP64.
+__device__ __forceinline__ double omega_q(int dim, const PassGeom& g, double nn, double m,
+                                          int64_t j1, int64_t j2, int64_t j3) {
+  double u, n1, n2, n3;
+  weyl_un(dim, g.cs, g.Nc, g.shift, j1, j2, j3, u, n1, n2, n3);
+  const double sinw = sqrt(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
+  return atan2(sinw, nn * u);
+}
+
+// hat psi(q) <- V^-1 [cos(omega t) I - i sin(omega t)/sin(omega) M_q] hat psi(q).
+// With TAB, omega comes from the plan's table and everything except the
+// phase reduction runs in the field precision.
+template <typename T, int DIM, bool TAB>
 __device__ __forceinline__ void apply_q(cx<T> (&y)[DIM == 1 ? 2 : 4], const PassGeom& g,
-                                        const InstParam& ip, int64_t j1, int64_t j2, int64_t j3) {
+                                        const InstParam& ip, int64_t j1, int64_t j2, int64_t j3,
+                                        int64_t qidx) {
   double u, n1, n2, n3;
   weyl_un(DIM, g.cs, g.Nc, g.shift, j1, j2, j3, u, n1, n2, n3);
   const double nn = ip.n, m = ip.m;
-  const double cosw = nn * u;
-  const double sin2 = nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m;
-  const double sinw = sqrt(sin2);
-  const double w = atan2(sinw, cosw);
-  double S, C;
-  sincos(w * (double)ip.t, &S, &C);
-  const double St = sinw > 0.0 ? S / sinw : 0.0;
-  const T c = (T)(C * g.inv_scale);
-  const T st = (T)(St * g.inv_scale);
+  double w;
+  T tn1, tn2, tn3, sinw_t;
+  if constexpr (TAB) {
+    w = g.omega[qidx];
+    tn1 = (T)n1;
+    tn2 = (T)n2;
+    tn3 = (T)n3;
+    const T tnn = (T)nn, tm = (T)m;
+    sinw_t = sqrt(tnn * tnn * (tn1 * tn1 + tn2 * tn2 + tn3 * tn3) + tm * tm);
+  } else {
+    const double sinw = sqrt(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
+    w = atan2(sinw, nn * u);
+    tn1 = (T)n1;
+    tn2 = (T)n2;
+    tn3 = (T)n3;
+    const T tnn = (T)nn, tm = (T)m;
+    sinw_t = sqrt(tnn * tnn * (tn1 * tn1 + tn2 * tn2 + tn3 * tn3) + tm * tm);
+  }
+  const double r = reduced_phase(w, ip.t);
+  T C, S, isw;
+  if constexpr (sizeof(T) == 4) {
+    sincosf((float)r, &S, &C);
+    isw = sinw_t > 1e-30f ? 1.0f / sinw_t : 0.0f;
+  } else {
+    sincos(r, &S, &C);
+    isw = sinw_t > 0.0 ? 1.0 / sinw_t : 0.0;
+  }
+  const T sc = (T)g.inv_scale;
+  const T c = C * sc;
+  const T st = S * isw * sc;  // V^-1 sin(omega t) / sin(omega)
+  const T tnn = (T)nn;
   if constexpr (DIM == 1) {
-    const T a = (T)(nn * n3) * st;
+    const T a = tnn * tn3 * st;
     const T gg = (T)m * st;
     // z = St M psi
     const cx<T> z0 = mk(a * y[0].x - gg * y[1].x, a * y[0].y - gg * y[1].y);
@@ -54,9 +105,9 @@ __device__ __forceinline__ void apply_q(cx<T> (&y)[DIM == 1 ? 2 : 4], const Pass
     y[0] = mk(c * y[0].x + z0.y, c * y[0].y - z0.x);
     y[1] = mk(c * y[1].x + z1.y, c * y[1].y - z1.x);
   } else {
-    const T a = (T)(nn * n3) * st;
-    const T b = (T)(nn * n1) * st;
-    const T e = (T)(nn * n2) * st;
+    const T a = tnn * tn3 * st;
+    const T b = tnn * tn1 * st;
+    const T e = tnn * tn2 * st;
     const T gg = (T)m * st;
     const cx<T> p0 = y[0], p1 = y[1], p2 = y[2], p3 = y[3];
     // (b - i e) p = (b p.x + e p.y, b p.y - e p.x); (b + i e) p = (b p.x - e p.y, b p.y + e p.x)
@@ -72,6 +123,24 @@ __device__ __forceinline__ void apply_q(cx<T> (&y)[DIM == 1 ? 2 : 4], const Pass
     y[1] = mk(c * p1.x + z1.y, c * p1.y - z1.x);
     y[2] = mk(c * p2.x + z2.y, c * p2.y - z2.x);
     y[3] = mk(c * p3.x + z3.y, c * p3.y - z3.x);
+  }
+}
+
+// Map (pencil, position) of the contiguous pass to lattice frequency indices.
+template <int DIM>
+__device__ __forceinline__ void q_index(const PassGeom& g, int64_t pen, int64_t z, int64_t& j1,
+                                        int64_t& j2, int64_t& j3) {
+  j2 = 0;
+  j3 = 0;
+  if constexpr (DIM == 3) {
+    j1 = pen / g.N[1];
+    j2 = pen - j1 * g.N[1];
+    j3 = z;
+  } else if constexpr (DIM == 2) {
+    j1 = pen;
+    j2 = z;
+  } else {
+    j1 = g.fourstep ? pen + g.N1 * z : z;
   }
 }
 
@@ -93,7 +162,8 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
   const int64_t b = gpc / g.ppi;
   const int64_t pen = gpc - b * g.ppi;
   const int64_t base = b * S * g.V + pen * L;
-  cx<T>* my = lds + p * L;
+  constexpr int LP = lds_len<true>(L);
+  cx<T>* my = lds + p * S * LP;
 
   cx<T> v[S][E];
 #pragma unroll
@@ -112,36 +182,34 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
         for (int c = 0; c < S; ++c) v[c][e] = cmulc(v[c][e], w);  // times e^{+2 pi i n2 k1 / N}
       }
     }
-#pragma unroll
-    for (int c = 0; c < S; ++c) fft_team<T, L, E, 1>(v[c], my, 1, t, tw);
+    fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
   }
-  if constexpr (MODE == MODE_EVOLVE) {
+  if constexpr (MODE == MODE_EVOLVE || MODE == MODE_EVOLVE_TAB) {
     const InstParam ip = g.inst ? g.inst[b] : g.single;
-#pragma unroll
+    // One wave-vector per iteration, deliberately not unrolled (an unrolled
+    // loop lets the compiler hoist every element's table reads and keep
+    // them live across the transforms). The register array is rotated by
+    // one position per iteration so the body only uses static indices; after
+    // E iterations every element is back in place.
+#pragma unroll 1
     for (int e = 0; e < E; ++e) {
       const int64_t z = t + TT * e;
-      int64_t j1, j2 = 0, j3 = 0;
-      if constexpr (DIM == 3) {
-        j1 = pen / g.N[1];
-        j2 = pen - j1 * g.N[1];
-        j3 = z;
-      } else if constexpr (DIM == 2) {
-        j1 = pen;
-        j2 = z;
-      } else {
-        j1 = g.fourstep ? pen + g.N1 * z : z;
-      }
+      int64_t j1, j2, j3;
+      q_index<DIM>(g, pen, z, j1, j2, j3);
       cx<T> y[S];
 #pragma unroll
-      for (int c = 0; c < S; ++c) y[c] = v[c][e];
-      apply_q<T, DIM>(y, g, ip, j1, j2, j3);
+      for (int c = 0; c < S; ++c) y[c] = v[c][0];
+      apply_q<T, DIM, MODE == MODE_EVOLVE_TAB>(y, g, ip, j1, j2, j3, pen * L + z);
 #pragma unroll
-      for (int c = 0; c < S; ++c) v[c][e] = y[c];
+      for (int c = 0; c < S; ++c) {
+#pragma unroll
+        for (int k = 0; k + 1 < E; ++k) v[c][k] = v[c][k + 1];
+        v[c][E - 1] = y[c];
+      }
     }
   }
   if constexpr (MODE != MODE_FWD) {
-#pragma unroll
-    for (int c = 0; c < S; ++c) fft_team<T, L, E, -1>(v[c], my, 1, t, tw);
+    fft_team_multi<T, L, E, -1, S>(v, my, LP, t, tw);
     if (DIM == 1 && g.fourstep) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -173,7 +241,7 @@ static hipError_t run_contig(cx<T>* out, const cx<T>* in, const PassGeom& g, con
   }
   const int threads = TT * P;
   if (threads > 512) return hipErrorInvalidValue;
-  const size_t lds = (size_t)P * L * sizeof(cx<T>);
+  const size_t lds = (size_t)P * (g.dim == 1 ? 2 : 4) * lds_len<true>(L) * sizeof(cx<T>);
   auto kern = k_fft_contig<T, L, E, DIM, MODE>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -230,8 +298,29 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
     case MODE_EVOLVE: return dispatch_dim<T, MODE_EVOLVE>(L, out, in, g, tw, st);
     case MODE_FWD: return dispatch_dim<T, MODE_FWD>(L, out, in, g, tw, st);
     case MODE_INV: return dispatch_dim<T, MODE_INV>(L, out, in, g, tw, st);
+    case MODE_EVOLVE_TAB: return dispatch_dim<T, MODE_EVOLVE_TAB>(L, out, in, g, tw, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// omega(q) for every wave-vector, in the storage order of the contiguous pass
+// (pencil-major; for the 1D four-step the order k1 + N1 k2 of its rows).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_omega_table(PassGeom g, int64_t L, double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.V) return;
+  const int64_t pen = idx / L, z = idx - pen * L;
+  int64_t j1, j2, j3;
+  q_index<DIM>(g, pen, z, j1, j2, j3);
+  out[idx] = omega_q(DIM, g, g.single.n, g.single.m, j1, j2, j3);
+}
+
+hipError_t launch_omega_table(const PassGeom& g, int64_t L, double* omega, hipStream_t st) {
+  const unsigned nblk = (unsigned)((g.V + 255) / 256);
+  if (g.dim == 1) hipLaunchKernelGGL(k_omega_table<1>, dim3(nblk), dim3(256), 0, st, g, L, omega);
+  else if (g.dim == 2) hipLaunchKernelGGL(k_omega_table<2>, dim3(nblk), dim3(256), 0, st, g, L, omega);
+  else hipLaunchKernelGGL(k_omega_table<3>, dim3(nblk), dim3(256), 0, st, g, L, omega);
+  return hipGetLastError();
 }
 
 hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const void* in,

@@ -401,6 +401,8 @@ struct qw_plan_s {
   InstParam* d_inst = nullptr;
   InstParam* h_inst = nullptr;  // pinned
   int inst_cap = 0;
+  double* d_omega = nullptr;    // omega(q) at the plan's mass, built on first use
+  bool omega_failed = false;
 
   ~qw_plan_s() {
     if (d_tw) (void)hipFree(d_tw);
@@ -412,6 +414,7 @@ struct qw_plan_s {
     if (d_scratch) (void)hipFree(d_scratch);
     if (d_inst) (void)hipFree(d_inst);
     if (h_inst) (void)hipHostFree(h_inst);
+    if (d_omega) (void)hipFree(d_omega);
   }
 };
 
@@ -496,6 +499,7 @@ PassGeom pass_geom(qw_plan_t p, int64_t L, int B) {
   g.single.n = p->n;
   g.single.t = 0;
   g.inst = nullptr;
+  g.omega = nullptr;
   return g;
 }
 
@@ -536,20 +540,46 @@ int64_t contig_len(qw_plan_t p) {
 
 bool has_strided(qw_plan_t p) { return p->dim > 1 || p->fourstep; }
 
+// The FP64 table of omega(q) at the plan's mass (V doubles), built on first
+// use by one kernel. If it cannot be allocated the evolution evaluates omega
+// per wave-vector instead.
+const double* omega_table(qw_plan_t p, hipStream_t st) {
+  if (p->d_omega || p->omega_failed) return p->d_omega;
+  if (hipMalloc((void**)&p->d_omega, sizeof(double) * p->V) != hipSuccess) {
+    p->d_omega = nullptr;
+    p->omega_failed = true;
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  const int64_t L = contig_len(p);
+  PassGeom g = pass_geom(p, L, 1);
+  if (launch_omega_table(g, L, p->d_omega, st) != hipSuccess) {
+    (void)hipFree(p->d_omega);
+    p->d_omega = nullptr;
+    p->omega_failed = true;
+  }
+  return p->d_omega;
+}
+
 qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstParam* dinst,
                       const InstParam& single, hipStream_t st) {
   const int64_t L = contig_len(p);
   PassGeom g = pass_geom(p, L, B);
   g.single = single;
   g.inst = dinst;
+  int mode = MODE_EVOLVE;
+  if (!dinst && B == 1) {
+    g.omega = omega_table(p, st);
+    if (g.omega) mode = MODE_EVOLVE_TAB;
+  }
   if (has_strided(p)) {
     qw_status r = strided_passes(p, +1, out, in, B, st);
     if (r != QW_OK) return r;
-    HIP_TRY(launch_fft_contig(p->dbl, MODE_EVOLVE, L, out, out, g, p->d_tw, st));
+    HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, out, g, p->d_tw, st));
     mark();
     return strided_passes(p, -1, out, out, B, st);
   }
-  HIP_TRY(launch_fft_contig(p->dbl, MODE_EVOLVE, L, out, in, g, p->d_tw, st));
+  HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, in, g, p->d_tw, st));
   mark();
   return QW_OK;
 }

@@ -128,10 +128,21 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int j) {
   return SIGN > 0 ? mk(w.x, -w.y) : w;
 }
 
+// LDS slot of pencil position `pos`. With PAD one slot is skipped after every
+// 16, which spreads the stride-R writes of the early stages over the banks.
+template <bool PAD>
+__device__ __forceinline__ int lds_slot(int pos) {
+  return PAD ? pos + (pos >> 4) : pos;
+}
+template <bool PAD>
+__host__ __device__ constexpr int lds_len(int L) {
+  return PAD ? L + L / 16 : L;
+}
+
 // One Stockham stage (and, recursively, the rest). NS = product of the radices
 // already done. LDS addressing: element at pencil position `pos` lives at
-// lds[pos * ls] (the caller offsets lds to its pencil).
-template <typename T, int L, int E, int SIGN, int NS>
+// lds[lds_slot<PAD>(pos) * ls] (the caller offsets lds to its pencil).
+template <typename T, int L, int E, int SIGN, int NS, bool PAD>
 struct Stages {
   static constexpr int REM = L / NS;
   static constexpr int R = REM >= E ? E : REM;
@@ -159,26 +170,88 @@ struct Stages {
       } else {
         const int base = (j / NS) * (NS * R) + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[(base + r * NS) * ls] = a[r];
+        for (int r = 0; r < R; ++r) lds[lds_slot<PAD>(base + r * NS) * ls] = a[r];
       }
     }
     if constexpr (!LAST) {
       __syncthreads();
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = lds[(t + TT * e) * ls];
+      for (int e = 0; e < E; ++e) v[e] = lds[lds_slot<PAD>(t + TT * e) * ls];
       __syncthreads();
-      Stages<T, L, E, SIGN, NS * R>::run(v, lds, ls, t, tw);
+      Stages<T, L, E, SIGN, NS * R, PAD>::run(v, lds, ls, t, tw);
     }
   }
 };
 
 // Full length-L transform of the team's registers (see the file comment).
-template <typename T, int L, int E, int SIGN>
+template <typename T, int L, int E, int SIGN, bool PAD = false>
 __device__ __forceinline__ void fft_team(cx<T> (&v)[E], cx<T>* lds, int ls, int t,
                                          const cx<T>* __restrict__ tw) {
   static_assert((L & (L - 1)) == 0 && L >= 1 && L <= TWN, "length");
   static_assert(E <= L && (E & (E - 1)) == 0, "elements per thread");
-  Stages<T, L, E, SIGN, 1>::run(v, lds, ls, t, tw);
+  Stages<T, L, E, SIGN, 1, PAD>::run(v, lds, ls, t, tw);
+}
+
+// The same transform applied to S pencils in lockstep (the spinor components
+// of one lattice row): twiddles and LDS slots are computed once per stage and
+// shared, and each exchange is one write/barrier/read/barrier for all S.
+// Component c of the team's pencil lives at lds + c * cstride.
+template <typename T, int L, int E, int SIGN, int NS, bool PAD, int S>
+struct StagesMulti {
+  static constexpr int REM = L / NS;
+  static constexpr int R = REM >= E ? E : REM;
+  static constexpr bool LAST = (NS * R == L);
+  static constexpr int TT = L / E;
+  static constexpr int NB = E / R;
+
+  __device__ __forceinline__ static void run(cx<T> (&v)[S][E], cx<T>* lds, int cstride, int t,
+                                             const cx<T>* __restrict__ tw) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = t + b * TT;
+      const int k = j & (NS - 1);
+      cx<T> w[R];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[r] = twiddle<SIGN>(tw, r * k * (TWN / (NS * R)));
+      }
+      const int base = (j / NS) * (NS * R) + k;
+#pragma unroll
+      for (int c = 0; c < S; ++c) {
+        cx<T> a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = v[c][b + r * NB];
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) a[r] = cmul(a[r], w[r]);
+        }
+        dft_reg<R, SIGN>(a);
+        if constexpr (LAST) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[c][b + r * NB] = a[r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) lds[c * cstride + lds_slot<PAD>(base + r * NS)] = a[r];
+        }
+      }
+    }
+    if constexpr (!LAST) {
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < S; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[c][e] = lds[c * cstride + lds_slot<PAD>(t + TT * e)];
+      __syncthreads();
+      StagesMulti<T, L, E, SIGN, NS * R, PAD, S>::run(v, lds, cstride, t, tw);
+    }
+  }
+};
+
+template <typename T, int L, int E, int SIGN, int S, bool PAD = true>
+__device__ __forceinline__ void fft_team_multi(cx<T> (&v)[S][E], cx<T>* lds, int cstride, int t,
+                                               const cx<T>* __restrict__ tw) {
+  static_assert((L & (L - 1)) == 0 && L >= 1 && L <= TWN, "length");
+  StagesMulti<T, L, E, SIGN, 1, PAD, S>::run(v, lds, cstride, t, tw);
 }
 
 }  // namespace qw

@@ -35,9 +35,12 @@ struct PassGeom {
   double inv_scale;  // 1 / V
   InstParam single;  // used when inst == nullptr
   const InstParam* inst;
+  const double* omega;  // MODE_EVOLVE_TAB: omega(q) of the plan's mass, q in storage order
 };
 
-enum { MODE_EVOLVE = 0, MODE_FWD = 1, MODE_INV = 2 };
+// MODE_EVOLVE evaluates omega(q) per wave-vector (any per-instance mass);
+// MODE_EVOLVE_TAB reads it from the plan's FP64 table (the plan's mass).
+enum { MODE_EVOLVE = 0, MODE_FWD = 1, MODE_INV = 2, MODE_EVOLVE_TAB = 3 };
 
 // ---------------------------------------------------------------------------
 // Stencil coefficients, in the kernel's precision. Offsets per dimension:
@@ -70,6 +73,7 @@ hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const vo
                               int64_t I, const void* tw, hipStream_t st);
 hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const void* in,
                              const PassGeom& g, const void* tw, hipStream_t st);
+hipError_t launch_omega_table(const PassGeom& g, int64_t L, double* omega, hipStream_t st);
 hipError_t launch_transpose(bool dbl, void* out, const void* in, int64_t planes, int64_t R,
                             int64_t C, hipStream_t st);
 hipError_t launch_step(bool dbl, const StencilGeom& g, void* out, const void* in,

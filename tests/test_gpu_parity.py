@@ -186,7 +186,9 @@ def test_batched_matches_single_and_oracle(qw, dtype):
     for b in range(B):
         single = qw.Plan(d, list(shape), ms[b], dtype)
         one = single.evolve_fft(to_dev(xs[b], single), ts[b])
-        assert torch.equal(out[b], one), "batched result differs from the single call"
+        # same arithmetic, except that the single call reads omega from the
+        # plan's table: equal up to rounding of the FP64 phase
+        assert ob.rel_l2(outn[b], to_np(one)) < (1e-6 if dtype == "c64" else tol_fft(dtype, ts[b]))
         ref = fourier.evolve_fourier(xs[b], table(d, ms[b]), ts[b])
         assert ob.rel_l2(outn[b], ref) < tol_fft(dtype, ts[b])
 
