@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="print the evolution time of every schedule and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -100,6 +102,23 @@ def main():
     plan.prepare_state(psi0, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
     psit = plan.empty()
     psis = psi0.clone()
+    if args.sweep:
+        out = {}
+        for slab in (0, 32, 64):
+            for ce in (4, 8):
+                for cb in (64, 128, 256):
+                    plan.set_schedule(slab, ce, cb)
+                    plan.evolve_fft(psi0, 1000, out=psit)
+                    tot = 0.0
+                    for r in range(5):
+                        _, ms = plan.evolve_fft_timed(psi0, 1000 + r, out=psit)
+                        tot += sum(ms)
+                    out["slab%d_e%d_b%d" % (slab, ce, cb)] = [round(tot / 5, 4)] + [
+                        round(x, 4) for x in ms]
+        print(json.dumps({"sweep_ms_per_evolution": out}))
+        return
+    tuned_ms = plan.autotune()
+    schedule = plan.schedule()
     times = w["times"]
     V = N ** 3
     field_bytes = psi0.numel() * psi0.element_size()
@@ -127,8 +146,16 @@ def main():
         _, ms = plan.evolve_fft_timed(psi0, times[(5 * r) % len(times)], out=psit)
         acc = ms if acc is None else [a + b for a, b in zip(acc, ms)]
     pass_ms = [a / reps for a in acc]
-    names = ["fft_strided n1 fwd", "fft_strided n2 fwd", "fft_contig n3 fwd+apply+inv",
-             "fft_strided n2 inv", "fft_strided n1 inv"]
+    if len(pass_ms) == 5:
+        names = ["fft_strided n1 fwd", "fft_strided n2 fwd", "fft_contig n3 fwd+apply+inv",
+                 "fft_strided n2 inv", "fft_strided n1 inv"]
+        launches = [1, 1, 1, 1, 1]
+    else:
+        nslab = -(-N // schedule[0])
+        names = ["fft_strided n1 fwd",
+                 "slabs: fft_strided n2 fwd + fft_contig n3 fwd+apply+inv + fft_strided n2 inv",
+                 "fft_strided n1 inv"]
+        launches = [1, 3 * nslab, 1]
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -151,7 +178,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": names[dom], "kernel_ms": round(pass_ms[dom], 4),
-                "algorithmic_bytes_per_launch": alg_bytes}
+                "launches": launches[dom], "algorithmic_bytes": alg_bytes}
     stencil_gbs = 2 * field_bytes / (stencil_ms * 1e-3) / 1e9
 
     line = {
@@ -168,6 +195,9 @@ def main():
                    "step": "1 Fourier jump + 1 position/norm reduction + 2 stencil steps",
                    "lattice": [N, N, N], "spinor": 4, "global_batch": 1},
         "fft_evolutions_per_s_kernels": round(1e3 / evo_ms, 2),
+        "schedule": {"slab_planes": schedule[0], "contig_elems": schedule[1],
+                     "contig_threads": schedule[2],
+                     "autotune_ms_per_evolution": round(tuned_ms, 4)},
         "fft_pass_ms": {n: round(v, 4) for n, v in zip(names, pass_ms)},
         "stencil_site_steps_per_s": round(V / (stencil_ms * 1e-3), 1),
         "stencil_ms_per_step": round(stencil_ms, 4),

@@ -139,6 +139,21 @@ qw_status qw_prepare_state(qw_plan_t plan, void* psi, const double* k0, double s
 qw_status qw_evolve_fft_timed(qw_plan_t plan, const void* psi0, void* psi_t, int64_t t,
                               void* stream, float* pass_ms, int* npass);
 
+/* Schedule of the Fourier evolution. slab_planes = 0 runs the n2 and fused
+ * n3 passes over the whole field; slab_planes = k runs the n2 forward, fused
+ * n3 and n2 inverse passes on slabs of k planes of n1 in turn, so that a slab
+ * stays in the last-level cache between those passes (ignored for d < 3).
+ * contig_elems (4 or 8; 4 only for d = 2, 3) is the number of elements per
+ * thread and contig_threads (64, 128, 256 or 512) the target workgroup size
+ * of the fused contiguous pass. Every schedule computes the same result. */
+qw_status qw_set_schedule(qw_plan_t plan, int slab_planes, int contig_elems, int contig_threads);
+qw_status qw_get_schedule(qw_plan_t plan, int* slab_planes, int* contig_elems,
+                          int* contig_threads);
+
+/* Time the candidate schedules on the plan's scratch field and keep the
+ * fastest; *best_ms (nullable) receives its time per evolution. Waits. */
+qw_status qw_autotune(qw_plan_t plan, void* stream, double* best_ms);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* qw_last_error(void);
 

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
   const bool valid = gp < g.pencils;
   const int64_t gpc = valid ? gp : 0;
   const int64_t b = gpc / g.ppi;
-  const int64_t pen = gpc - b * g.ppi;
+  const int64_t pen = g.pen0 + (gpc - b * g.ppi);
   const int64_t base = b * S * g.V + pen * L;
   constexpr int LP = lds_len<true>(L);
   cx<T>* my = lds + p * S * LP;
@@ -227,12 +227,12 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
   }
 }
 
-template <typename T, int L, int DIM, int MODE>
+template <typename T, int L, int DIM, int MODE, int EE>
 static hipError_t run_contig(cx<T>* out, const cx<T>* in, const PassGeom& g, const cx<T>* tw,
                              hipStream_t st) {
-  constexpr int E = L < 8 ? L : 8;
+  constexpr int E = L < EE ? L : EE;
   constexpr int TT = L / E;
-  int P = 256 / TT;
+  int P = (g.block_threads > 0 ? g.block_threads : 256) / TT;
   if (P < 1) P = 1;
   if ((int64_t)P > g.pencils) {
     int q = 1;
@@ -254,51 +254,58 @@ static hipError_t run_contig(cx<T>* out, const cx<T>* in, const PassGeom& g, con
   return hipGetLastError();
 }
 
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, int EE>
 static hipError_t dispatch_contig(int64_t L, cx<T>* out, const cx<T>* in, const PassGeom& g,
                                   const cx<T>* tw, hipStream_t st) {
   switch (L) {
-    case 2: return run_contig<T, 2, DIM, MODE>(out, in, g, tw, st);
-    case 4: return run_contig<T, 4, DIM, MODE>(out, in, g, tw, st);
-    case 8: return run_contig<T, 8, DIM, MODE>(out, in, g, tw, st);
-    case 16: return run_contig<T, 16, DIM, MODE>(out, in, g, tw, st);
-    case 32: return run_contig<T, 32, DIM, MODE>(out, in, g, tw, st);
-    case 64: return run_contig<T, 64, DIM, MODE>(out, in, g, tw, st);
-    case 128: return run_contig<T, 128, DIM, MODE>(out, in, g, tw, st);
-    case 256: return run_contig<T, 256, DIM, MODE>(out, in, g, tw, st);
-    case 512: return run_contig<T, 512, DIM, MODE>(out, in, g, tw, st);
+    case 2: return run_contig<T, 2, DIM, MODE, EE>(out, in, g, tw, st);
+    case 4: return run_contig<T, 4, DIM, MODE, EE>(out, in, g, tw, st);
+    case 8: return run_contig<T, 8, DIM, MODE, EE>(out, in, g, tw, st);
+    case 16: return run_contig<T, 16, DIM, MODE, EE>(out, in, g, tw, st);
+    case 32: return run_contig<T, 32, DIM, MODE, EE>(out, in, g, tw, st);
+    case 64: return run_contig<T, 64, DIM, MODE, EE>(out, in, g, tw, st);
+    case 128: return run_contig<T, 128, DIM, MODE, EE>(out, in, g, tw, st);
+    case 256: return run_contig<T, 256, DIM, MODE, EE>(out, in, g, tw, st);
+    case 512: return run_contig<T, 512, DIM, MODE, EE>(out, in, g, tw, st);
     case 1024:
-      if constexpr (DIM <= 2) return run_contig<T, 1024, DIM, MODE>(out, in, g, tw, st);
+      if constexpr (DIM <= 2) return run_contig<T, 1024, DIM, MODE, EE>(out, in, g, tw, st);
       return hipErrorInvalidValue;
     case 2048:
-      if constexpr (DIM == 1) return run_contig<T, 2048, DIM, MODE>(out, in, g, tw, st);
+      if constexpr (DIM == 1) return run_contig<T, 2048, DIM, MODE, EE>(out, in, g, tw, st);
       return hipErrorInvalidValue;
     case 4096:
-      if constexpr (DIM == 1) return run_contig<T, 4096, DIM, MODE>(out, in, g, tw, st);
+      if constexpr (DIM == 1 && EE >= 8) return run_contig<T, 4096, DIM, MODE, EE>(out, in, g, tw, st);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int EE>
 static hipError_t dispatch_dim(int64_t L, cx<T>* out, const cx<T>* in, const PassGeom& g,
                                const cx<T>* tw, hipStream_t st) {
   switch (g.dim) {
-    case 1: return dispatch_contig<T, 1, MODE>(L, out, in, g, tw, st);
-    case 2: return dispatch_contig<T, 2, MODE>(L, out, in, g, tw, st);
-    case 3: return dispatch_contig<T, 3, MODE>(L, out, in, g, tw, st);
+    case 1: return dispatch_contig<T, 1, MODE, EE>(L, out, in, g, tw, st);
+    case 2: return dispatch_contig<T, 2, MODE, EE>(L, out, in, g, tw, st);
+    case 3: return dispatch_contig<T, 3, MODE, EE>(L, out, in, g, tw, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
 static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in,
-                                const PassGeom& g, const cx<T>* tw, hipStream_t st) {
+                                const PassGeom& g, const cx<T>* tw, hipStream_t st, int E) {
+  // Four elements per thread only for the evolution modes of d = 2, 3 (the
+  // autotuner's alternative); everything else uses eight.
+  const bool e4 = E == 4 && g.dim >= 2;
   switch (mode) {
-    case MODE_EVOLVE: return dispatch_dim<T, MODE_EVOLVE>(L, out, in, g, tw, st);
-    case MODE_FWD: return dispatch_dim<T, MODE_FWD>(L, out, in, g, tw, st);
-    case MODE_INV: return dispatch_dim<T, MODE_INV>(L, out, in, g, tw, st);
-    case MODE_EVOLVE_TAB: return dispatch_dim<T, MODE_EVOLVE_TAB>(L, out, in, g, tw, st);
+    case MODE_EVOLVE:
+      return e4 ? dispatch_dim<T, MODE_EVOLVE, 4>(L, out, in, g, tw, st)
+                : dispatch_dim<T, MODE_EVOLVE, 8>(L, out, in, g, tw, st);
+    case MODE_FWD: return dispatch_dim<T, MODE_FWD, 8>(L, out, in, g, tw, st);
+    case MODE_INV: return dispatch_dim<T, MODE_INV, 8>(L, out, in, g, tw, st);
+    case MODE_EVOLVE_TAB:
+      return e4 ? dispatch_dim<T, MODE_EVOLVE_TAB, 4>(L, out, in, g, tw, st)
+                : dispatch_dim<T, MODE_EVOLVE_TAB, 8>(L, out, in, g, tw, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -324,12 +331,12 @@ hipError_t launch_omega_table(const PassGeom& g, int64_t L, double* omega, hipSt
 }
 
 hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const void* in,
-                             const PassGeom& g, const void* tw, hipStream_t st) {
+                             const PassGeom& g, const void* tw, hipStream_t st, int E) {
   if (dbl)
     return dispatch_mode<double>(mode, L, (cx<double>*)out, (const cx<double>*)in, g,
-                                 (const cx<double>*)tw, st);
+                                 (const cx<double>*)tw, st, E);
   return dispatch_mode<float>(mode, L, (cx<float>*)out, (const cx<float>*)in, g,
-                              (const cx<float>*)tw, st);
+                              (const cx<float>*)tw, st, E);
 }
 
 }  // namespace qw

@@ -13,10 +13,17 @@
 
 namespace qw {
 
+// Outer index o of a launch covers `ocount` consecutive planes o0.. of each
+// of several components, components `ostride` elements apart (a slab of the
+// lattice); a whole-field launch has ocount = O, o0 = 0.
+struct OuterMap {
+  int64_t ocount, o0, ostride;
+};
+
 template <typename T, int L, int E, int SIGN>
 __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
                                                       const cx<T>* __restrict__ in, int64_t I,
-                                                      int lgP, int64_t nblk_i,
+                                                      int lgP, int64_t nblk_i, OuterMap om,
                                                       const cx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -28,7 +35,9 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
   const int64_t blk = blockIdx.x;
   const int64_t o = blk / nblk_i;
   const int64_t i0 = (blk - o * nblk_i) << lgP;
-  const int64_t base = o * (int64_t)L * I + i0 + p;
+  const int64_t comp = o / om.ocount;
+  const int64_t plane = om.o0 + (o - comp * om.ocount);
+  const int64_t base = comp * om.ostride + plane * (int64_t)L * I + i0 + p;
   cx<T> v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = in[base + (int64_t)(t + TT * e) * I];
@@ -39,7 +48,7 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
 
 template <typename T, int L, int SIGN>
 static hipError_t run_strided(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
-                              const cx<T>* tw, hipStream_t st) {
+                              const OuterMap& om, const cx<T>* tw, hipStream_t st) {
   constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
   constexpr int E = L < Emax ? L : Emax;
   constexpr int TT = L / E;
@@ -59,46 +68,58 @@ static hipError_t run_strided(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
   const int64_t nblk_i = I / P;
   const int64_t nblk = O * nblk_i;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(TT * P), lds, st, out, in, I, lgP, nblk_i,
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(TT * P), lds, st, out, in, I, lgP, nblk_i, om,
                      tw);
   return hipGetLastError();
 }
 
 template <typename T, int SIGN>
 static hipError_t dispatch_strided(int64_t L, cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
-                                   const cx<T>* tw, hipStream_t st) {
+                                   const OuterMap& om, const cx<T>* tw, hipStream_t st) {
   switch (L) {
     case 1:
-      if (out != in) return hipMemcpyAsync(out, in, sizeof(cx<T>) * O * I, hipMemcpyDeviceToDevice, st);
-      return hipSuccess;
-    case 2: return run_strided<T, 2, SIGN>(out, in, O, I, tw, st);
-    case 4: return run_strided<T, 4, SIGN>(out, in, O, I, tw, st);
-    case 8: return run_strided<T, 8, SIGN>(out, in, O, I, tw, st);
-    case 16: return run_strided<T, 16, SIGN>(out, in, O, I, tw, st);
-    case 32: return run_strided<T, 32, SIGN>(out, in, O, I, tw, st);
-    case 64: return run_strided<T, 64, SIGN>(out, in, O, I, tw, st);
-    case 128: return run_strided<T, 128, SIGN>(out, in, O, I, tw, st);
-    case 256: return run_strided<T, 256, SIGN>(out, in, O, I, tw, st);
-    case 512: return run_strided<T, 512, SIGN>(out, in, O, I, tw, st);
-    case 1024: return run_strided<T, 1024, SIGN>(out, in, O, I, tw, st);
+      return hipErrorInvalidValue;
+    case 2: return run_strided<T, 2, SIGN>(out, in, O, I, om, tw, st);
+    case 4: return run_strided<T, 4, SIGN>(out, in, O, I, om, tw, st);
+    case 8: return run_strided<T, 8, SIGN>(out, in, O, I, om, tw, st);
+    case 16: return run_strided<T, 16, SIGN>(out, in, O, I, om, tw, st);
+    case 32: return run_strided<T, 32, SIGN>(out, in, O, I, om, tw, st);
+    case 64: return run_strided<T, 64, SIGN>(out, in, O, I, om, tw, st);
+    case 128: return run_strided<T, 128, SIGN>(out, in, O, I, om, tw, st);
+    case 256: return run_strided<T, 256, SIGN>(out, in, O, I, om, tw, st);
+    case 512: return run_strided<T, 512, SIGN>(out, in, O, I, om, tw, st);
+    case 1024: return run_strided<T, 1024, SIGN>(out, in, O, I, om, tw, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
-                              int64_t I, const void* tw, hipStream_t st) {
+hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, const void* in,
+                                   int64_t ncomp, int64_t ocount, int64_t o0, int64_t ostride,
+                                   int64_t I, const void* tw, hipStream_t st) {
+  const OuterMap om{ocount, o0, ostride};
+  const int64_t O = ncomp * ocount;
   if (dbl) {
     auto o = (cx<double>*)out;
     auto i = (const cx<double>*)in;
     auto w = (const cx<double>*)tw;
-    return sign > 0 ? dispatch_strided<double, 1>(L, o, i, O, I, w, st)
-                    : dispatch_strided<double, -1>(L, o, i, O, I, w, st);
+    return sign > 0 ? dispatch_strided<double, 1>(L, o, i, O, I, om, w, st)
+                    : dispatch_strided<double, -1>(L, o, i, O, I, om, w, st);
   }
   auto o = (cx<float>*)out;
   auto i = (const cx<float>*)in;
   auto w = (const cx<float>*)tw;
-  return sign > 0 ? dispatch_strided<float, 1>(L, o, i, O, I, w, st)
-                  : dispatch_strided<float, -1>(L, o, i, O, I, w, st);
+  return sign > 0 ? dispatch_strided<float, 1>(L, o, i, O, I, om, w, st)
+                  : dispatch_strided<float, -1>(L, o, i, O, I, om, w, st);
+}
+
+hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
+                              int64_t I, const void* tw, hipStream_t st) {
+  if (L == 1) {
+    if (out != in)
+      return hipMemcpyAsync(out, in, (dbl ? 16 : 8) * O * I, hipMemcpyDeviceToDevice, st);
+    return hipSuccess;
+  }
+  return launch_fft_strided_slab(dbl, sign, L, out, in, 1, O, 0, 0, I, tw, st);
 }
 
 // out[p][c][r] = in[p][r][c] for planes p of an R x C matrix (32 x 32 tiles).

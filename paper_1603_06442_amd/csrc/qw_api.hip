@@ -14,6 +14,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <complex>
 #include <mutex>
 #include <new>
@@ -404,6 +405,11 @@ struct qw_plan_s {
   double* d_omega = nullptr;    // omega(q) at the plan's mass, built on first use
   bool omega_failed = false;
 
+  // Schedule of the 3D Fourier evolution (see qw_set_schedule / qw_autotune).
+  int slab = 0;  // n1 planes per slab of the middle passes (0 = whole field)
+  int ce = 8;    // elements per thread of the fused contiguous pass (4 or 8)
+  int cb = 256;  // target workgroup size of the fused contiguous pass
+
   ~qw_plan_s() {
     if (d_tw) (void)hipFree(d_tw);
     if (d_tw4) (void)hipFree(d_tw4);
@@ -427,9 +433,11 @@ struct PassTimer {
   hipStream_t st = nullptr;
 };
 thread_local PassTimer* g_timer = nullptr;
+thread_local bool g_mark_off = false;  // inside a slab loop: one mark for the group
 
 inline void mark() {
-  if (g_timer && g_timer->n < 9) (void)hipEventRecord(g_timer->ev[g_timer->n++], g_timer->st);
+  if (g_timer && !g_mark_off && g_timer->n < 9)
+    (void)hipEventRecord(g_timer->ev[g_timer->n++], g_timer->st);
 }
 
 qw_status ensure_scratch(qw_plan_t p, size_t bytes) {
@@ -488,6 +496,8 @@ PassGeom pass_geom(qw_plan_t p, int64_t L, int B) {
   for (int i = 0; i < 3; ++i) g.N[i] = p->N[i];
   g.ppi = p->V / L;
   g.pencils = g.ppi * B;
+  g.pen0 = 0;
+  g.block_threads = p->cb;
   g.Nc = p->Nc;
   for (int i = 0; i < 3; ++i) g.shift[i] = p->shift[i];
   g.fourstep = p->fourstep ? 1 : 0;
@@ -572,14 +582,46 @@ qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstP
     g.omega = omega_table(p, st);
     if (g.omega) mode = MODE_EVOLVE_TAB;
   }
+  if (p->dim == 3 && p->slab > 0 && p->slab < p->N[0]) {
+    // n1 forward over the whole field; then, slab by slab of n1 planes, the
+    // n2 forward, fused n3 and n2 inverse passes (a slab stays in the
+    // last-level cache between them); then n1 inverse.
+    const int64_t N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
+    const int64_t nc = (int64_t)p->s * B;
+    HIP_TRY(launch_fft_strided(p->dbl, 1, N1, out, in, nc, N2 * N3, p->d_tw, st));
+    mark();
+    g_mark_off = true;
+    for (int64_t a = 0; a < N1; a += p->slab) {
+      const int64_t k = std::min<int64_t>(p->slab, N1 - a);
+      hipError_t e = launch_fft_strided_slab(p->dbl, 1, N2, out, out, nc, k, a, p->V, N3, p->d_tw, st);
+      if (e == hipSuccess) {
+        PassGeom gs = g;
+        gs.pen0 = a * N2;
+        gs.ppi = k * N2;
+        gs.pencils = gs.ppi * B;
+        e = launch_fft_contig(p->dbl, mode, L, out, out, gs, p->d_tw, st, p->ce);
+      }
+      if (e == hipSuccess)
+        e = launch_fft_strided_slab(p->dbl, -1, N2, out, out, nc, k, a, p->V, N3, p->d_tw, st);
+      if (e != hipSuccess) {
+        g_mark_off = false;
+        HIP_TRY(e);
+      }
+    }
+    g_mark_off = false;
+    mark();
+    HIP_TRY(launch_fft_strided(p->dbl, -1, N1, out, out, nc, N2 * N3, p->d_tw, st));
+    mark();
+    return QW_OK;
+  }
   if (has_strided(p)) {
     qw_status r = strided_passes(p, +1, out, in, B, st);
     if (r != QW_OK) return r;
-    HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, out, g, p->d_tw, st));
+    HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, out, g, p->d_tw, st, p->ce));
     mark();
     return strided_passes(p, -1, out, out, B, st);
   }
-  HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, in, g, p->d_tw, st));
+  HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, in, g, p->d_tw, st, p->ce));
   mark();
   return QW_OK;
 }
@@ -746,6 +788,94 @@ qw_status qw_evolve_fft(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, v
   ip.n = p->n;
   ip.t = t;
   return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
+}
+
+qw_status qw_set_schedule(qw_plan_t p, int slab_planes, int contig_elems, int contig_threads) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (slab_planes < 0) return fail(QW_ERR_INVALID, "slab_planes must be >= 0");
+  if (contig_elems != 4 && contig_elems != 8)
+    return fail(QW_ERR_INVALID, "contig_elems must be 4 or 8");
+  if (contig_threads != 64 && contig_threads != 128 && contig_threads != 256 && contig_threads != 512)
+    return fail(QW_ERR_INVALID, "contig_threads must be 64, 128, 256 or 512");
+  p->slab = p->dim == 3 ? slab_planes : 0;
+  p->ce = contig_elems;
+  p->cb = contig_threads;
+  return QW_OK;
+}
+
+qw_status qw_get_schedule(qw_plan_t p, int* slab_planes, int* contig_elems, int* contig_threads) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!slab_planes || !contig_elems || !contig_threads) return fail(QW_ERR_INVALID, "NULL argument");
+  *slab_planes = p->slab;
+  *contig_elems = p->ce;
+  *contig_threads = p->cb;
+  return QW_OK;
+}
+
+qw_status qw_autotune(qw_plan_t p, void* stream, double* best_ms) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  r = ensure_scratch(p, p->field_bytes);
+  if (r != QW_OK) return r;
+  HIP_TRY(hipMemsetAsync(p->d_scratch, 0, p->field_bytes, st));
+  std::vector<int> slabs = {0};
+  if (p->dim == 3) {
+    const size_t plane = p->field_bytes / (size_t)p->N[0];
+    for (size_t target : {size_t(16) << 20, size_t(32) << 20, size_t(64) << 20, size_t(128) << 20}) {
+      int64_t k = (int64_t)(target / plane);
+      if (k >= 1 && k < p->N[0]) {
+        int64_t kk = 1;
+        while (kk * 2 <= k) kk *= 2;
+        if (std::find(slabs.begin(), slabs.end(), (int)kk) == slabs.end()) slabs.push_back((int)kk);
+      }
+    }
+  }
+  const int ces[2] = {8, 4};
+  const int cbs[3] = {64, 128, 256};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  InstParam ip;
+  ip.m = p->m;
+  ip.n = p->n;
+  ip.t = 12345;
+  double best = 1e30;
+  int bs = 0, bc = 8, bb = 256;
+  for (int sl : slabs)
+    for (int ce : ces)
+      for (int cb : cbs) {
+      if (ce == 4 && p->dim < 2) continue;
+      p->slab = sl;
+      p->ce = ce;
+      p->cb = cb;
+      r = evolve_impl(p, 1, p->d_scratch, p->d_scratch, nullptr, ip, st);  // warm-up
+      if (r != QW_OK) break;
+      (void)hipEventRecord(e0, st);
+      const int reps = 3;
+      for (int k = 0; k < reps && r == QW_OK; ++k)
+        r = evolve_impl(p, 1, p->d_scratch, p->d_scratch, nullptr, ip, st);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (r == QW_OK && ms / reps < best) {
+        best = ms / reps;
+        bs = sl;
+        bc = ce;
+        bb = cb;
+      }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->slab = bs;
+  p->ce = bc;
+  p->cb = bb;
+  if (r != QW_OK) return r;
+  if (best_ms) *best_ms = best;
+  return QW_OK;
 }
 
 qw_status qw_evolve_fft_timed(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, void* stream,

@@ -24,8 +24,10 @@ struct PassGeom {
   int s;             // spinor components
   int64_t V;         // sites per instance
   int64_t N[3];      // lattice sizes
-  int64_t pencils;   // pencils (of all s components) over all instances
-  int64_t ppi;       // pencils per instance = V / L
+  int64_t pencils;   // pencils (of all s components) in this launch, over all instances
+  int64_t ppi;       // pencils per instance in this launch
+  int64_t pen0;      // first pencil of each instance in this launch (slabs)
+  int block_threads; // target workgroup size of the contiguous pass (0 = 256)
   int Nc;            // common denominator for the cos/sin(pi j / Nc) table
   int shift[3];      // log2(Nc / N_i)
   int fourstep;      // 1D four-step: N = N1 * L, pencil = row k1
@@ -71,8 +73,13 @@ struct StencilGeom {
 // ---------------------------------------------------------------------------
 hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
                               int64_t I, const void* tw, hipStream_t st);
+// Planes o0 .. o0+ocount-1 of each of ncomp components (ostride elements apart).
+hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, const void* in,
+                                   int64_t ncomp, int64_t ocount, int64_t o0, int64_t ostride,
+                                   int64_t I, const void* tw, hipStream_t st);
+// E: elements per thread of the contiguous pass (4 or 8; 0 = default 8).
 hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const void* in,
-                             const PassGeom& g, const void* tw, hipStream_t st);
+                             const PassGeom& g, const void* tw, hipStream_t st, int E = 0);
 hipError_t launch_omega_table(const PassGeom& g, int64_t L, double* omega, hipStream_t st);
 hipError_t launch_transpose(bool dbl, void* out, const void* in, int64_t planes, int64_t R,
                             int64_t C, hipStream_t st);

@@ -1,8 +1,9 @@
 // Position-space step of the walk (Sec. 2 of the paper, update rule):
 //   psi(n, t+1) = sum_h U_h psi(n + h, t)   on the periodic N^d torus,
 // with the transition matrices U_h derived by the plan from the symbol.
-// One thread per output site computes all s components; neighbour reads are
-// served by L1/L2 (each input is used by up to 2d+3 sites).
+// The generic kernels use one thread per output site for all s components,
+// with neighbour reads served by L1/L2; large 3D lattices use the LDS-ring
+// kernel below.
 #include "qw_internal.h"
 
 namespace qw {
@@ -89,8 +90,204 @@ __global__ __launch_bounds__(256) void k_step_nd(cx<T>* __restrict__ out, const 
   out[3 * V + idx] = a3;
 }
 
+
+// ---------------------------------------------------------------------------
+// 3D step with an LDS ring of lattice planes. A workgroup owns a TN2 x TN3
+// tile of (n2, n3) and marches along n1 through a chunk of planes. Each input
+// plane of the tile, with a one-site halo in n2 and n3, is read from global
+// memory once into a ring of three LDS planes (n1-1, n1, n1+1), from which
+// all nine terms of the output plane n1 are formed. The next plane's loads
+// are issued before the current plane is computed. Workgroups are numbered
+// so that the tiles handled by one XCD (workgroup index mod 8) are adjacent,
+// which keeps the halos that neighbouring tiles share in that XCD's L2.
+// ---------------------------------------------------------------------------
+constexpr int kTN2 = 8, kTN3 = 64;
+constexpr int kH2 = kTN2 + 2, kH3 = kTN3 + 2;
+constexpr int kPlaneSites = kH2 * kH3;               // tile + halo
+constexpr int kHalo = kPlaneSites - kTN2 * kTN3;     // 148 halo sites
+constexpr int kStepThreads = kTN2 * kTN3 / 2;        // two tile sites per thread
+
+template <typename T>
+struct PlaneRegs {
+  cx<T> own[2][4];
+  cx<T> halo[4];
+};
+
+// Site (i2, i3) of the halo'd tile, i2 in [0, kH2), i3 in [0, kH3), for the
+// k-th halo site (k < kHalo): rows 0 and kH2-1 in full, then columns 0 and kH3-1.
+__device__ __forceinline__ void halo_site(int k, int& i2, int& i3) {
+  if (k < 2 * kH3) {
+    i2 = k < kH3 ? 0 : kH2 - 1;
+    i3 = k < kH3 ? k : k - kH3;
+  } else {
+    const int r = k - 2 * kH3;  // 0 .. 2*kTN2-1
+    i2 = 1 + (r >> 1);
+    i3 = (r & 1) ? kH3 - 1 : 0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_plane(PlaneRegs<T>& R, const cx<T>* __restrict__ in,
+                                           int64_t V, int64_t plane_off, int64_t m2, int64_t m3,
+                                           int lg3, int64_t b2, int64_t b3, int tid) {
+  // own sites: rows tid / kTN3 and tid / kTN3 + kTN2 / 2, column tid % kTN3
+  const int c3 = tid & (kTN3 - 1);
+  const int r0 = tid / kTN3;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t n2 = (b2 + r0 + h * (kTN2 / 2)) & m2;
+    const int64_t n3 = (b3 + c3) & m3;
+    const int64_t idx = plane_off + (n2 << lg3) + n3;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) R.own[h][c] = in[c * V + idx];
+  }
+  if (tid < kHalo) {
+    int i2, i3;
+    halo_site(tid, i2, i3);
+    const int64_t n2 = (b2 + i2 - 1) & m2;
+    const int64_t n3 = (b3 + i3 - 1) & m3;
+    const int64_t idx = plane_off + (n2 << lg3) + n3;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) R.halo[c] = in[c * V + idx];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_plane(const PlaneRegs<T>& R, cx<T>* ring, int tid) {
+  const int c3 = tid & (kTN3 - 1);
+  const int r0 = tid / kTN3;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i2 = 1 + r0 + h * (kTN2 / 2), i3 = 1 + c3;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ring[(c * kH2 + i2) * kH3 + i3] = R.own[h][c];
+  }
+  if (tid < kHalo) {
+    int i2, i3;
+    halo_site(tid, i2, i3);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ring[(c * kH2 + i2) * kH3 + i3] = R.halo[c];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kStepThreads) void k_step3d_ring(cx<T>* __restrict__ out,
+                                                             const cx<T>* __restrict__ in,
+                                                             StencilGeom g, StencilCoef<T> C,
+                                                             int chunk, int64_t tiles2,
+                                                             int64_t tiles3, int64_t nchunks) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int PL = 4 * kPlaneSites;  // elements per ring plane
+  const int tid = threadIdx.x;
+  // XCD-aware numbering: workgroup b runs on XCD b % 8; give each XCD a
+  // contiguous range of (chunk, tile) indices.
+  const int64_t nblk = (int64_t)gridDim.x;
+  const int64_t b = blockIdx.x;
+  int64_t w = b;
+  if ((nblk & 7) == 0) w = (b & 7) * (nblk >> 3) + (b >> 3);
+  const int64_t t3 = w % tiles3;
+  const int64_t t2 = (w / tiles3) % tiles2;
+  const int64_t ch = w / (tiles3 * tiles2);
+  (void)nchunks;
+  const int64_t b2 = t2 * kTN2, b3 = t3 * kTN3;
+  const int64_t m1 = g.N[0] - 1, m2 = g.N[1] - 1, m3 = g.N[2] - 1;
+  const int lg3 = g.lg[2];
+  const int64_t planeN = g.N[1] * g.N[2];
+  const int64_t V = g.V;
+  const int64_t a = ch * chunk;
+
+  // Ring slot of (unwrapped) plane p is (p - a + 1) mod 3.
+  PlaneRegs<T> R;
+  load_plane(R, in, V, ((a - 1) & m1) * planeN, m2, m3, lg3, b2, b3, tid);
+  store_plane(R, lds, tid);  // plane a-1 -> slot 0
+  load_plane(R, in, V, (a & m1) * planeN, m2, m3, lg3, b2, b3, tid);
+  store_plane(R, lds + PL, tid);  // plane a -> slot 1
+  load_plane(R, in, V, ((a + 1) & m1) * planeN, m2, m3, lg3, b2, b3, tid);
+
+  const int c3 = tid & (kTN3 - 1);
+  const int r0 = tid / kTN3;
+  for (int64_t n1 = a; n1 < a + chunk; ++n1) {
+    const int64_t n0 = n1 & m1;
+    const int sm = (int)((n1 - a) % 3), s0 = (int)((n1 - a + 1) % 3), sp = (int)((n1 - a + 2) % 3);
+    store_plane(R, lds + sp * PL, tid);  // plane n1+1 into its slot
+    __syncthreads();
+    if (n1 + 1 < a + chunk)  // issue the loads of plane n1+2 now
+      load_plane(R, in, V, ((n1 + 2) & m1) * planeN, m2, m3, lg3, b2, b3, tid);
+    const cx<T>* Pm = lds + sm * PL;
+    const cx<T>* P0 = lds + s0 * PL;
+    const cx<T>* Pp = lds + sp * PL;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i2 = 1 + r0 + h * (kTN2 / 2), i3 = 1 + c3;
+      const int site = i2 * kH3 + i3;
+      constexpr int CS = kH2 * kH3;  // component stride in a ring plane
+      cx<T> a0 = mk((T)0, (T)0), a1 = a0, a2 = a0, a3 = a0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int o1 = kOff3[k][0], o2 = kOff3[k][1], o3 = kOff3[k][2];
+        const cx<T>* P = (o1 > 0 ? Pp : (o1 < 0 ? Pm : P0)) + site + o2 * kH3 + o3;
+        const cx<T> q0 = P[0], q1 = P[CS], q2 = P[2 * CS], q3 = P[3 * CS];
+        a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+        a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+        a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
+        a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
+      }
+      const cx<T> mass = C.onsite[0][0];
+      a0 = fma_c(a0, mass, P0[site + 2 * CS]);
+      a1 = fma_c(a1, mass, P0[site + 3 * CS]);
+      a2 = fma_c(a2, mass, P0[site]);
+      a3 = fma_c(a3, mass, P0[site + CS]);
+      const int64_t n2 = b2 + r0 + h * (kTN2 / 2), n3 = b3 + c3;
+      const int64_t idx = n0 * planeN + (n2 << lg3) + n3;
+      out[idx] = a0;
+      out[V + idx] = a1;
+      out[2 * V + idx] = a2;
+      out[3 * V + idx] = a3;
+    }
+    __syncthreads();  // slot of plane n1-1 is rewritten next iteration
+  }
+}
+
+bool step3d_ring_ok(const StencilGeom& g) {
+  return g.dim == 3 && g.N[1] >= kTN2 && g.N[2] >= kTN3 && g.N[0] >= 4;
+}
+
+hipError_t launch_step3d_ring(bool dbl, const StencilGeom& g, void* out, const void* in,
+                              const void* coef, hipStream_t st) {
+  const int64_t tiles2 = g.N[1] / kTN2, tiles3 = g.N[2] / kTN3;
+  int chunk = 16;
+  while (chunk > 1 && g.N[0] % chunk) chunk >>= 1;
+  if (chunk > g.N[0]) chunk = (int)g.N[0];
+  const int64_t nchunks = g.N[0] / chunk;
+  const int64_t nblk = tiles2 * tiles3 * nchunks;
+  if (dbl) {
+    const size_t lds = 3 * 4 * kPlaneSites * sizeof(cx<double>);
+    auto kern = k_step3d_ring<double>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kStepThreads), lds, st, (cx<double>*)out,
+                       (const cx<double>*)in, g, *(const StencilCoef<double>*)coef, chunk, tiles2,
+                       tiles3, nchunks);
+  } else {
+    const size_t lds = 3 * 4 * kPlaneSites * sizeof(cx<float>);
+    auto kern = k_step3d_ring<float>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kStepThreads), lds, st, (cx<float>*)out,
+                       (const cx<float>*)in, g, *(const StencilCoef<float>*)coef, chunk, tiles2,
+                       tiles3, nchunks);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_step(bool dbl, const StencilGeom& g, void* out, const void* in,
                        const void* coef, hipStream_t st) {
+  if (step3d_ring_ok(g)) return launch_step3d_ring(dbl, g, out, in, coef, st);
   const unsigned nblk = (unsigned)((g.V + 255) / 256);
   if (dbl) {
     const StencilCoef<double>& C = *(const StencilCoef<double>*)coef;

@@ -21,7 +21,7 @@ QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_evolve_fft", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_prepare_state",
-           "qw_last_error", "qw_version")
+           "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version")
 
 
 class QwError(RuntimeError):
@@ -54,6 +54,9 @@ def _load():
         "qw_transform": [vp, vp, vp, cint, vp],
         "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
         "qw_prepare_state": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl, vp],
+        "qw_set_schedule": [vp, cint, cint, cint],
+        "qw_get_schedule": [vp, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint)],
+        "qw_autotune": [vp, vp, ctypes.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -193,6 +196,25 @@ class Plan:
         return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
                 "mean_cart": list(o.mean_cart),
                 "overlap": complex(o.overlap_re, o.overlap_im), "ref_norm2": o.ref_norm2}
+
+    def set_schedule(self, slab_planes, contig_elems=8, contig_threads=256):
+        """qw_set_schedule: slab size (n1 planes, 0 = whole field), the fused
+        pass's elements per thread (4 or 8) and workgroup size."""
+        _check(LIB.qw_set_schedule(self._h, int(slab_planes), int(contig_elems),
+                                   int(contig_threads)))
+
+    def schedule(self):
+        """qw_get_schedule: (slab_planes, contig_elems, contig_threads)."""
+        a, b, c = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(LIB.qw_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def autotune(self, stream=None):
+        """qw_autotune: time the candidate schedules, keep the fastest.
+        Returns the best time per evolution in ms."""
+        ms = ctypes.c_double(0.0)
+        _check(LIB.qw_autotune(self._h, _stream(stream), ctypes.byref(ms)))
+        return ms.value
 
     def prepare_state(self, psi, k0, sigma, center, c_plus=1.0, c_minus=0.0, stream=None):
         """qw_prepare_state: Gaussian particle/antiparticle state, unit norm."""

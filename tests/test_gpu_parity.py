@@ -73,6 +73,20 @@ def test_step_matches_oracle(qw, d, shape, m, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("shape", [(8, 8, 64), (4, 16, 128), (32, 8, 64)])
+@pytest.mark.parametrize("m", [0.0, 0.3])
+def test_step_3d_plane_ring_matches_oracle(qw, shape, m, dtype):
+    """Lattices with N2 >= 8 and N3 >= 64 take the LDS plane-ring kernel
+    (tiles of 8 x 64, chunks along n1, periodic wrap in all three axes)."""
+    psi0 = rand_field(3, shape, 31)
+    plan = qw.Plan(3, list(shape), m, dtype)
+    x = to_dev(psi0, plan)
+    plan.step(x, 5)
+    ref = stepper.evolve_steps(psi0, table(3, m), 5)
+    assert ob.rel_l2(to_np(x), ref) < tol_step(dtype, 5)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("d,shape", SHAPES + [(1, (8192,)), (1, (65536,)), (1, (2,)), (3, (2, 2, 2))])
 def test_transform_matches_dft(qw, d, shape, dtype):
     psi0 = rand_field(d, shape, 7)
@@ -226,3 +240,35 @@ def test_workload_bcc_64_c64(qw):
     assert ob.rel_l2(to_np(y), ref) < 2e-5
     o = plan.observables(y, w["center"])
     assert abs(o["norm2"] - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_every_schedule_gives_the_same_evolution(qw, dtype):
+    """Slabbed middle passes and both fused-pass widths vs the oracle, on a
+    non-cubic torus, including a slab size that does not divide N1."""
+    d, shape, m, t = 3, (16, 8, 32), 0.07, 777
+    psi0 = rand_field(d, shape, 21)
+    ref = fourier.evolve_fourier(psi0, table(d, m), t)
+    plan = qw.Plan(d, list(shape), m, dtype)
+    for slab in (0, 1, 3, 4, 16):
+        for ce in (4, 8):
+            for cb in (64, 256):
+                plan.set_schedule(slab, ce, cb)
+                out = plan.evolve_fft(to_dev(psi0, plan), t)
+                assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t), (slab, ce, cb)
+    ms = plan.autotune()
+    assert ms > 0 and plan.schedule()[1] in (4, 8)
+    out = plan.evolve_fft(to_dev(psi0, plan), t)
+    assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
+
+
+def test_batched_with_slabs(qw):
+    d, shape = 3, (8, 8, 16)
+    plan = qw.Plan(d, list(shape), 0.1, "c64")
+    plan.set_schedule(2, 4, 128)
+    ms, ts = [0.02, 0.2, 0.5], [3, 999, -70]
+    xs = np.stack([rand_field(d, shape, 70 + b) for b in range(3)])
+    outn = to_np(plan.evolve_fft_batched(to_dev(xs, plan), ms, ts))
+    for b in range(3):
+        ref = fourier.evolve_fourier(xs[b], table(d, ms[b]), ts[b])
+        assert ob.rel_l2(outn[b], ref) < 2e-5
