@@ -34,6 +34,18 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bcc256_c64.json")
 
 
+def _source_hash(rel):
+    """sha256 of a committed kernel source (to tell stale counter data)."""
+    import hashlib
+    if not rel:
+        return None
+    path = os.path.join(ROOT, rel)
+    if not os.path.exists(path):
+        return None
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle's Fourier evaluation (numpy DFT + per-q binary powering
     of the symbol) on the 64^3 sub-lattice of the workload, timed on the host
@@ -104,17 +116,18 @@ def main():
     psis = psi0.clone()
     if args.sweep:
         out = {}
-        for slab in (0, 32, 64):
+        for slab in (0, 64):
             for ce in (4, 8):
                 for cb in (64, 128, 256):
-                    plan.set_schedule(slab, ce, cb)
-                    plan.evolve_fft(psi0, 1000, out=psit)
-                    tot = 0.0
-                    for r in range(5):
-                        _, ms = plan.evolve_fft_timed(psi0, 1000 + r, out=psit)
-                        tot += sum(ms)
-                    out["slab%d_e%d_b%d" % (slab, ce, cb)] = [round(tot / 5, 4)] + [
-                        round(x, 4) for x in ms]
+                    for gw in ((1, 4) if ce == 4 else (1,)):
+                        plan.set_schedule(slab, ce, cb, gw)
+                        plan.evolve_fft(psi0, 1000, out=psit)
+                        tot = 0.0
+                        for r in range(5):
+                            _, ms = plan.evolve_fft_timed(psi0, 1000 + r, out=psit)
+                            tot += sum(ms)
+                        out["slab%d_e%d_b%d_g%d" % (slab, ce, cb, gw)] = [round(tot / 5, 4)] + [
+                            round(x, 4) for x in ms]
         print(json.dumps({"sweep_ms_per_evolution": out}))
         return
     tuned_ms = plan.autotune()
@@ -165,20 +178,34 @@ def main():
     e1.record(st)
     e1.synchronize()
     stencil_ms = e0.elapsed_time(e1) / (2 * reps)
+    e0.record(st)
+    for _ in range(reps):
+        plan.observables(psit, w["center"])
+    e1.record(st)
+    e1.synchronize()
+    obs_ms = e0.elapsed_time(e1) / reps  # includes the small D2H copy and host wait
     evo_ms = sum(pass_ms)
 
-    dom = max(range(len(pass_ms)), key=lambda i: pass_ms[i])
-    alg_bytes = 2 * field_bytes
-    achieved = alg_bytes / (pass_ms[dom] * 1e-3) / 1e9
+    # Dominant kernel of a step: the one with the largest time per step among
+    # single kernels (the slab group is several kernels and is not a candidate).
+    cands = [("k_step3d_ring (stencil step)", stencil_ms, 2)]
+    for n, v, k in zip(names, pass_ms, launches):
+        if k == 1:
+            cands.append((n, v, 1))
+    dom_name, dom_ms, dom_launches = max(cands, key=lambda c: c[1] * c[2])
+    alg_bytes = 2 * field_bytes  # read the field once, write it once, per launch
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        traffic = tr.get(names[dom])
+        ent = tr.get("kernels", {}).get(dom_name)
+        if ent and ent.get("source_sha256") == _source_hash(ent.get("source")):
+            traffic = ent.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": names[dom], "kernel_ms": round(pass_ms[dom], 4),
-                "launches": launches[dom], "algorithmic_bytes": alg_bytes}
+                "kernel": dom_name, "kernel_ms": round(dom_ms, 4), "launches_per_step": dom_launches,
+                "algorithmic_bytes_per_launch": alg_bytes}
     stencil_gbs = 2 * field_bytes / (stencil_ms * 1e-3) / 1e9
 
     line = {
@@ -196,12 +223,13 @@ def main():
                    "lattice": [N, N, N], "spinor": 4, "global_batch": 1},
         "fft_evolutions_per_s_kernels": round(1e3 / evo_ms, 2),
         "schedule": {"slab_planes": schedule[0], "contig_elems": schedule[1],
-                     "contig_threads": schedule[2],
+                     "contig_threads": schedule[2], "contig_groups": schedule[3],
                      "autotune_ms_per_evolution": round(tuned_ms, 4)},
         "fft_pass_ms": {n: round(v, 4) for n, v in zip(names, pass_ms)},
         "stencil_site_steps_per_s": round(V / (stencil_ms * 1e-3), 1),
         "stencil_ms_per_step": round(stencil_ms, 4),
         "stencil_gbs": round(stencil_gbs, 1),
+        "observables_ms": round(obs_ms, 4),
         "roofline": roofline,
         "last_obs": {"norm2": obs["norm2"], "mean_cart": obs["mean_cart"]},
     }

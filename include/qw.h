@@ -145,10 +145,14 @@ qw_status qw_evolve_fft_timed(qw_plan_t plan, const void* psi0, void* psi_t, int
  * stays in the last-level cache between those passes (ignored for d < 3).
  * contig_elems (4 or 8; 4 only for d = 2, 3) is the number of elements per
  * thread and contig_threads (64, 128, 256 or 512) the target workgroup size
- * of the fused contiguous pass. Every schedule computes the same result. */
-qw_status qw_set_schedule(qw_plan_t plan, int slab_planes, int contig_elems, int contig_threads);
+ * of the fused contiguous pass; contig_groups (1..64; > 1 only used for
+ * d = 3 with contig_elems = 4) lets each of its workgroups transform up to
+ * that many pencil groups in turn, loading the next while computing the
+ * current one. Every schedule computes the same result. */
+qw_status qw_set_schedule(qw_plan_t plan, int slab_planes, int contig_elems, int contig_threads,
+                          int contig_groups);
 qw_status qw_get_schedule(qw_plan_t plan, int* slab_planes, int* contig_elems,
-                          int* contig_threads);
+                          int* contig_threads, int* contig_groups);
 
 /* Time the candidate schedules on the plan's scratch field and keep the
  * fastest; *best_ms (nullable) receives its time per evolution. Waits. */

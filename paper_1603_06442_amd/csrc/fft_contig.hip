@@ -26,6 +26,8 @@
 // e^{+2 pi i n2 k1 / N} before the forward transform and by the conjugate
 // after the inverse. The spectrum sits at row k1, column k2 for q index
 // k1 + N1 k2 (never transposed back: the inverse undoes the order).
+#include <algorithm>
+
 #include "qw_internal.h"
 
 namespace qw {
@@ -133,8 +135,8 @@ __device__ __forceinline__ void q_index(const PassGeom& g, int64_t pen, int64_t 
   j2 = 0;
   j3 = 0;
   if constexpr (DIM == 3) {
-    j1 = pen / g.N[1];
-    j2 = pen - j1 * g.N[1];
+    j1 = pen >> g.lgN1;
+    j2 = pen & (g.N[1] - 1);
     j3 = z;
   } else if constexpr (DIM == 2) {
     j1 = pen;
@@ -144,7 +146,31 @@ __device__ __forceinline__ void q_index(const PassGeom& g, int64_t pen, int64_t 
   }
 }
 
-template <typename T, int L, int E, int DIM, int MODE>
+// Pencil groups: group r holds the P pencils r*P .. r*P+P-1 of the launch.
+// A workgroup walks the groups blockIdx.x, blockIdx.x + gridDim.x, ... and
+// issues the global loads of its next group before transforming the current
+// one, so that memory traffic of one group overlaps the arithmetic of the
+// previous one.
+template <typename T, int S, int E, int L>
+__device__ __forceinline__ void load_group(cx<T> (&dst)[S][E], const cx<T>* __restrict__ in,
+                                           const PassGeom& g, int64_t grp, int P, int p, int t) {
+  constexpr int TT = L / E;
+  const int64_t gp = grp * P + p;
+  const bool valid = gp < g.pencils;
+  const int64_t gpc = valid ? gp : 0;
+  const int64_t b = gpc / g.ppi;
+  const int64_t pen = g.pen0 + (gpc - b * g.ppi);
+  const int64_t base = b * S * g.V + pen * L;
+  // Lanes past the last pencil read pencil 0 (in bounds) and never store:
+  // unconditional loads keep the whole group's loads in flight together.
+  (void)valid;
+#pragma unroll
+  for (int c = 0; c < S; ++c)
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[c][e] = in[base + c * g.V + t + TT * e];
+}
+
+template <typename T, int L, int E, int DIM, int MODE, bool PIPE>
 __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
                                                     const cx<T>* __restrict__ in, PassGeom g,
                                                     const cx<T>* __restrict__ tw) {
@@ -156,80 +182,107 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
   const int t = tid & (TT - 1);
   const int p = tid / TT;
   const int P = blockDim.x / TT;
-  const int64_t gp = (int64_t)blockIdx.x * P + p;
-  const bool valid = gp < g.pencils;
-  const int64_t gpc = valid ? gp : 0;
-  const int64_t b = gpc / g.ppi;
-  const int64_t pen = g.pen0 + (gpc - b * g.ppi);
-  const int64_t base = b * S * g.V + pen * L;
   constexpr int LP = lds_len<true>(L);
   cx<T>* my = lds + p * S * LP;
-
-  cx<T> v[S][E];
-#pragma unroll
-  for (int c = 0; c < S; ++c)
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[c][e] = valid ? in[base + c * g.V + t + TT * e] : mk((T)0, (T)0);
-
+  const int64_t ngroups = (g.pencils + P - 1) / P;
   const cx<T>* tw4 = (const cx<T>*)g.tw4;
   const int64_t N = g.N[0];
-  if constexpr (MODE != MODE_INV) {
-    if (DIM == 1 && g.fourstep) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const cx<T> w = tw4[((int64_t)(t + TT * e) * pen) & (N - 1)];
-#pragma unroll
-        for (int c = 0; c < S; ++c) v[c][e] = cmulc(v[c][e], w);  // times e^{+2 pi i n2 k1 / N}
-      }
-    }
-    fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
-  }
-  if constexpr (MODE == MODE_EVOLVE || MODE == MODE_EVOLVE_TAB) {
-    const InstParam ip = g.inst ? g.inst[b] : g.single;
-    // One wave-vector per iteration, deliberately not unrolled (an unrolled
-    // loop lets the compiler hoist every element's table reads and keep
-    // them live across the transforms). The register array is rotated by
-    // one position per iteration so the body only uses static indices; after
-    // E iterations every element is back in place.
-#pragma unroll 1
-    for (int e = 0; e < E; ++e) {
-      const int64_t z = t + TT * e;
-      int64_t j1, j2, j3;
-      q_index<DIM>(g, pen, z, j1, j2, j3);
-      cx<T> y[S];
-#pragma unroll
-      for (int c = 0; c < S; ++c) y[c] = v[c][0];
-      apply_q<T, DIM, MODE == MODE_EVOLVE_TAB>(y, g, ip, j1, j2, j3, pen * L + z);
-#pragma unroll
-      for (int c = 0; c < S; ++c) {
-#pragma unroll
-        for (int k = 0; k + 1 < E; ++k) v[c][k] = v[c][k + 1];
-        v[c][E - 1] = y[c];
-      }
-    }
-  }
-  if constexpr (MODE != MODE_FWD) {
-    fft_team_multi<T, L, E, -1, S>(v, my, LP, t, tw);
-    if (DIM == 1 && g.fourstep) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const cx<T> w = tw4[((int64_t)(t + TT * e) * pen) & (N - 1)];
-#pragma unroll
-        for (int c = 0; c < S; ++c) v[c][e] = cmul(v[c][e], w);  // times e^{-2 pi i n2 k1 / N}
-      }
-    }
-  }
-  if (valid) {
+
+  cx<T> nx[S][E];
+  int64_t grp = blockIdx.x;
+  if (grp < ngroups) load_group<T, S, E, L>(nx, in, g, grp, P, p, t);
+  for (; grp < ngroups; grp += gridDim.x) {
+    cx<T> v[S][E];
 #pragma unroll
     for (int c = 0; c < S; ++c)
 #pragma unroll
-      for (int e = 0; e < E; ++e) out[base + c * g.V + t + TT * e] = v[c][e];
+      for (int e = 0; e < E; ++e) v[c][e] = nx[c][e];
+    if constexpr (PIPE) {
+      if (grp + gridDim.x < ngroups) load_group<T, S, E, L>(nx, in, g, grp + gridDim.x, P, p, t);
+    }
+
+    const int64_t gp = grp * P + p;
+    const bool valid = gp < g.pencils;
+    const int64_t gpc = valid ? gp : 0;
+    const int64_t b = gpc / g.ppi;
+    const int64_t pen = g.pen0 + (gpc - b * g.ppi);
+    const int64_t base = b * S * g.V + pen * L;
+
+    if constexpr (MODE != MODE_INV) {
+      if (DIM == 1 && g.fourstep) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const cx<T> w = tw4[((int64_t)(t + TT * e) * pen) & (N - 1)];
+#pragma unroll
+          for (int c = 0; c < S; ++c) v[c][e] = cmulc(v[c][e], w);  // times e^{+2 pi i n2 k1 / N}
+        }
+      }
+      fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
+    }
+    if constexpr (MODE == MODE_EVOLVE || MODE == MODE_EVOLVE_TAB) {
+      const InstParam ip = g.inst ? g.inst[b] : g.single;
+      // One wave-vector per iteration, deliberately not unrolled (an unrolled
+      // loop lets the compiler hoist every element's table reads and keep
+      // them live across the transforms). The register array is rotated by
+      // one position per iteration so the body only uses static indices;
+      // after E iterations every element is back in place.
+#pragma unroll 1
+      for (int e = 0; e < E; ++e) {
+        const int64_t z = t + TT * e;
+        int64_t j1, j2, j3;
+        q_index<DIM>(g, pen, z, j1, j2, j3);
+        cx<T> y[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) y[c] = v[c][0];
+        apply_q<T, DIM, MODE == MODE_EVOLVE_TAB>(y, g, ip, j1, j2, j3, pen * L + z);
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+#pragma unroll
+          for (int k = 0; k + 1 < E; ++k) v[c][k] = v[c][k + 1];
+          v[c][E - 1] = y[c];
+        }
+      }
+    }
+    if constexpr (MODE != MODE_FWD) {
+      fft_team_multi<T, L, E, -1, S>(v, my, LP, t, tw);
+      if (DIM == 1 && g.fourstep) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const cx<T> w = tw4[((int64_t)(t + TT * e) * pen) & (N - 1)];
+#pragma unroll
+          for (int c = 0; c < S; ++c) v[c][e] = cmul(v[c][e], w);  // times e^{-2 pi i n2 k1 / N}
+        }
+      }
+    }
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < S; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) out[base + c * g.V + t + TT * e] = v[c][e];
+    }
   }
 }
+
+template <typename T, int L, int DIM, int MODE, int EE, bool PIPE>
+static hipError_t run_contig_k(cx<T>* out, const cx<T>* in, const PassGeom& g, const cx<T>* tw,
+                               hipStream_t st);
 
 template <typename T, int L, int DIM, int MODE, int EE>
 static hipError_t run_contig(cx<T>* out, const cx<T>* in, const PassGeom& g, const cx<T>* tw,
                              hipStream_t st) {
+  // The prefetching variant is built for the 3D evolution with four elements
+  // per thread only (the autotuner's candidate); elsewhere one group per
+  // workgroup.
+  constexpr bool kPipe = DIM == 3 && EE == 4 && MODE == MODE_EVOLVE_TAB;
+  if constexpr (kPipe) {
+    if (g.groups_per_wg > 1) return run_contig_k<T, L, DIM, MODE, EE, true>(out, in, g, tw, st);
+  }
+  return run_contig_k<T, L, DIM, MODE, EE, false>(out, in, g, tw, st);
+}
+
+template <typename T, int L, int DIM, int MODE, int EE, bool PIPE>
+static hipError_t run_contig_k(cx<T>* out, const cx<T>* in, const PassGeom& g, const cx<T>* tw,
+                               hipStream_t st) {
   constexpr int E = L < EE ? L : EE;
   constexpr int TT = L / E;
   int P = (g.block_threads > 0 ? g.block_threads : 256) / TT;
@@ -242,13 +295,36 @@ static hipError_t run_contig(cx<T>* out, const cx<T>* in, const PassGeom& g, con
   const int threads = TT * P;
   if (threads > 512) return hipErrorInvalidValue;
   const size_t lds = (size_t)P * (g.dim == 1 ? 2 : 4) * lds_len<true>(L) * sizeof(cx<T>);
-  auto kern = k_fft_contig<T, L, E, DIM, MODE>;
+  auto kern = k_fft_contig<T, L, E, DIM, MODE, PIPE>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const int64_t nblk = (g.pencils + P - 1) / P;
+  const int64_t ngroups = (g.pencils + P - 1) / P;
+  // Enough workgroups to fill the chip g.groups_per_wg times over at most;
+  // each then walks ngroups / nblk pencil groups with its loads one ahead.
+  int64_t nblk = ngroups;
+  if (PIPE && g.groups_per_wg > 1) {
+    static int occ[2][8] = {};  // cached occupancy per (precision, log2 threads)
+    int& o = occ[sizeof(T) == 8][ilog2(threads) & 7];
+    if (o == 0) {
+      int v = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, (const void*)kern, threads, lds) !=
+              hipSuccess ||
+          v < 1)
+        v = 1;
+      o = v;
+    }
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus < 1) cus = 1;
+    const int64_t resident = (int64_t)o * cus;
+    const int64_t want = (ngroups + g.groups_per_wg - 1) / g.groups_per_wg;
+    nblk = std::max<int64_t>(resident, want);
+    if (nblk > ngroups) nblk = ngroups;
+  }
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(threads), lds, st, out, in, g, tw);
   return hipGetLastError();

@@ -409,6 +409,8 @@ struct qw_plan_s {
   int slab = 0;  // n1 planes per slab of the middle passes (0 = whole field)
   int ce = 8;    // elements per thread of the fused contiguous pass (4 or 8)
   int cb = 256;  // target workgroup size of the fused contiguous pass
+  int gw = 1;    // pencil groups per workgroup of the fused pass (prefetch when > 1)
+  bool sparse3 = false;  // 3D transition matrices have the rank-one block pattern
 
   ~qw_plan_s() {
     if (d_tw) (void)hipFree(d_tw);
@@ -498,8 +500,10 @@ PassGeom pass_geom(qw_plan_t p, int64_t L, int B) {
   g.pencils = g.ppi * B;
   g.pen0 = 0;
   g.block_threads = p->cb;
+  g.groups_per_wg = p->gw;
   g.Nc = p->Nc;
   for (int i = 0; i < 3; ++i) g.shift[i] = p->shift[i];
+  g.lgN1 = p->lg[1];
   g.fourstep = p->fourstep ? 1 : 0;
   g.N1 = p->fs_N1;
   g.cs = p->d_cs;
@@ -682,6 +686,19 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
     return fail(QW_ERR_DEVICE, "transition matrices: %s", why.c_str());
   }
 
+  // Rank-one pattern of the 3D neighbour blocks (lets the stencil skip zeros).
+  if (dim == 3) {
+    bool ok = true;
+    for (int k = 0; k < 8; ++k) {
+      const int ur = k < 4 ? 1 : 0, lc = k < 4 ? 0 : 1;
+      for (int j = 0; j < 2; ++j) {
+        const cx<double> a = p->coef_d.up[k][ur][j], b = p->coef_d.lo[k][j][lc];
+        if (a.x != 0.0 || a.y != 0.0 || b.x != 0.0 || b.y != 0.0) ok = false;
+      }
+    }
+    p->sparse3 = ok;
+  }
+
   // Fourier schedule.
   if (dim == 1 && N[0] > 4096) {
     p->fourstep = true;
@@ -766,6 +783,7 @@ qw_status qw_step(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
     g.lg[i] = p->lg[i];
   }
   g.V = p->V;
+  g.sparse3 = p->sparse3 ? 1 : 0;
   const void* coef = p->dbl ? (const void*)&p->coef_d : (const void*)&p->coef_f;
   void* a = psi;
   void* b = p->d_scratch;
@@ -790,7 +808,8 @@ qw_status qw_evolve_fft(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, v
   return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
 }
 
-qw_status qw_set_schedule(qw_plan_t p, int slab_planes, int contig_elems, int contig_threads) {
+qw_status qw_set_schedule(qw_plan_t p, int slab_planes, int contig_elems, int contig_threads,
+                          int contig_groups) {
   qw_status r = check_plan(p);
   if (r != QW_OK) return r;
   if (slab_planes < 0) return fail(QW_ERR_INVALID, "slab_planes must be >= 0");
@@ -798,19 +817,25 @@ qw_status qw_set_schedule(qw_plan_t p, int slab_planes, int contig_elems, int co
     return fail(QW_ERR_INVALID, "contig_elems must be 4 or 8");
   if (contig_threads != 64 && contig_threads != 128 && contig_threads != 256 && contig_threads != 512)
     return fail(QW_ERR_INVALID, "contig_threads must be 64, 128, 256 or 512");
+  if (contig_groups < 1 || contig_groups > 64)
+    return fail(QW_ERR_INVALID, "contig_groups must lie in [1, 64]");
   p->slab = p->dim == 3 ? slab_planes : 0;
   p->ce = contig_elems;
   p->cb = contig_threads;
+  p->gw = contig_groups;
   return QW_OK;
 }
 
-qw_status qw_get_schedule(qw_plan_t p, int* slab_planes, int* contig_elems, int* contig_threads) {
+qw_status qw_get_schedule(qw_plan_t p, int* slab_planes, int* contig_elems, int* contig_threads,
+                          int* contig_groups) {
   qw_status r = check_plan(p);
   if (r != QW_OK) return r;
-  if (!slab_planes || !contig_elems || !contig_threads) return fail(QW_ERR_INVALID, "NULL argument");
+  if (!slab_planes || !contig_elems || !contig_threads || !contig_groups)
+    return fail(QW_ERR_INVALID, "NULL argument");
   *slab_planes = p->slab;
   *contig_elems = p->ce;
   *contig_threads = p->cb;
+  *contig_groups = p->gw;
   return QW_OK;
 }
 
@@ -842,15 +867,19 @@ qw_status qw_autotune(qw_plan_t p, void* stream, double* best_ms) {
   ip.m = p->m;
   ip.n = p->n;
   ip.t = 12345;
+  const int gws[2] = {1, 4};
   double best = 1e30;
-  int bs = 0, bc = 8, bb = 256;
+  int bs = 0, bc = 8, bb = 256, bg = 1;
   for (int sl : slabs)
     for (int ce : ces)
-      for (int cb : cbs) {
+      for (int cb : cbs)
+        for (int gw : gws) {
       if (ce == 4 && p->dim < 2) continue;
+      if (gw > 1 && !(p->dim == 3 && ce == 4)) continue;
       p->slab = sl;
       p->ce = ce;
       p->cb = cb;
+      p->gw = gw;
       r = evolve_impl(p, 1, p->d_scratch, p->d_scratch, nullptr, ip, st);  // warm-up
       if (r != QW_OK) break;
       (void)hipEventRecord(e0, st);
@@ -866,13 +895,15 @@ qw_status qw_autotune(qw_plan_t p, void* stream, double* best_ms) {
         bs = sl;
         bc = ce;
         bb = cb;
+        bg = gw;
       }
-      }
+        }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   p->slab = bs;
   p->ce = bc;
   p->cb = bb;
+  p->gw = bg;
   if (r != QW_OK) return r;
   if (best_ms) *best_ms = best;
   return QW_OK;

@@ -28,8 +28,10 @@ struct PassGeom {
   int64_t ppi;       // pencils per instance in this launch
   int64_t pen0;      // first pencil of each instance in this launch (slabs)
   int block_threads; // target workgroup size of the contiguous pass (0 = 256)
+  int groups_per_wg; // pencil groups per workgroup (loads one group ahead); 1 = none
   int Nc;            // common denominator for the cos/sin(pi j / Nc) table
   int shift[3];      // log2(Nc / N_i)
+  int lgN1;          // log2 N[1] (3D pencil index -> (j1, j2))
   int fourstep;      // 1D four-step: N = N1 * L, pencil = row k1
   int64_t N1;        // four-step rows
   const double* cs;  // cos/sin(pi j / Nc), j in [0, 2 Nc), as (cos, sin) pairs
@@ -61,11 +63,17 @@ struct StencilCoef {
   cx<T> onsite[2][2];  // 1D on-site matrix; for d = 2, 3 onsite[0][0] = mass coupling
 };
 
+// 3D sparsity the plan verifies on the derived matrices: for the first four
+// offsets (1,0,0), (0,-1,0), (0,0,-1), (-1,-1,-1) only row 0 of `up` and
+// column 1 of `lo` are non-zero; for the other four only row 1 of `up` and
+// column 0 of `lo`. (Every Weyl block of the BCC walk has rank one.)
+
 struct StencilGeom {
   int dim;
   int64_t N[3];
   int lg[3];  // log2 N_i
   int64_t V;
+  int sparse3;  // the 3D coefficients have the rank-one pattern above
 };
 
 // ---------------------------------------------------------------------------
@@ -95,7 +103,7 @@ struct ObsGeom {
   double c[3];
 };
 constexpr int kObsFields = 13;  // norm2, s1[3], s2[6], ov_re, ov_im, ref_norm2
-constexpr int kObsBlocks = 1024;
+constexpr int kObsBlocks = 4096;
 hipError_t launch_observables(bool dbl, const ObsGeom& g, const void* psi, const void* ref,
                               double* partials, double* result, hipStream_t st);
 

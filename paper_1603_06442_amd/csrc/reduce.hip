@@ -39,68 +39,135 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
   block_reduce_store<NF>(acc, result);
 }
 
-__device__ __forceinline__ double min_image(double n, double c, double N) {
-  const double d = n - c;
-  return d - N * floor((d + 0.5 * N) / N);
+// Minimum image of n - c in [-N/2, N/2) for integer n, written with integer
+// arithmetic: c = ci + cf with ci = floor(c), cf in [0, 1); for cf = 0 the
+// image is ((n - ci + N/2) mod N) - N/2, otherwise
+// ((n - ci + N/2 - 1) mod N) + 1 - cf - N/2.
+struct AxisImage {
+  int64_t ci;
+  double cf;
+  int64_t half, mask;
+};
+
+__device__ __forceinline__ double min_image(int64_t n, const AxisImage& a) {
+  if (a.cf == 0.0) return (double)(((n - a.ci + a.half) & a.mask) - a.half);
+  return (double)(((n - a.ci + a.half - 1) & a.mask) - a.half) + (1.0 - a.cf);
 }
 
-template <typename T>
+// Each thread takes UNR sites per round, all loads of a round issued before
+// any arithmetic; FP64 accumulation.
+template <typename T, int DIM, bool REF>
 __global__ __launch_bounds__(256) void k_observables(const cx<T>* __restrict__ psi,
                                                      const cx<T>* __restrict__ ref, ObsGeom g,
                                                      double* __restrict__ partials) {
+  constexpr int S = DIM == 1 ? 2 : 4;
+  constexpr int UNR = 4;
   double acc[kObsFields];
 #pragma unroll
   for (int f = 0; f < kObsFields; ++f) acc[f] = 0.0;
+  AxisImage ax[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double fl = floor(g.c[i]);
+    ax[i].ci = (int64_t)fl;
+    ax[i].cf = g.c[i] - fl;
+    ax[i].half = g.N[i] / 2;
+    ax[i].mask = g.N[i] - 1;
+  }
   const int64_t V = g.V;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < V; idx += stride) {
+  auto site = [&](int64_t idx, const cx<T> (&a)[S], const cx<T> (&r)[S]) {
     double p = 0.0, ore = 0.0, oim = 0.0, rn = 0.0;
-    for (int c = 0; c < g.s; ++c) {
-      const cx<T> a = psi[c * V + idx];
-      const double ax = (double)a.x, ay = (double)a.y;
-      p += ax * ax + ay * ay;
-      if (ref) {
-        const cx<T> r = ref[c * V + idx];
-        const double rx = (double)r.x, ry = (double)r.y;
-        ore += rx * ax + ry * ay;
-        oim += rx * ay - ry * ax;
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      const double ax_ = (double)a[c].x, ay = (double)a[c].y;
+      p += ax_ * ax_ + ay * ay;
+      if constexpr (REF) {
+        const double rx = (double)r[c].x, ry = (double)r[c].y;
+        ore += rx * ax_ + ry * ay;
+        oim += rx * ay - ry * ax_;
         rn += rx * rx + ry * ry;
       }
     }
-    double w[3] = {0.0, 0.0, 0.0};
-    int64_t rem = idx;
-    for (int i = g.dim - 1; i >= 0; --i) {
-      const int64_t ni = rem & (g.N[i] - 1);
-      rem >>= g.lg[i];
-      w[i] = min_image((double)ni, g.c[i], (double)g.N[i]);
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+    if constexpr (DIM == 1) {
+      w0 = min_image(idx, ax[0]);
+    } else if constexpr (DIM == 2) {
+      w1 = min_image(idx & (g.N[1] - 1), ax[1]);
+      w0 = min_image(idx >> g.lg[1], ax[0]);
+    } else {
+      w2 = min_image(idx & (g.N[2] - 1), ax[2]);
+      w1 = min_image((idx >> g.lg[2]) & (g.N[1] - 1), ax[1]);
+      w0 = min_image(idx >> (g.lg[2] + g.lg[1]), ax[0]);
     }
     acc[0] += p;
-    acc[1] += w[0] * p;
-    acc[2] += w[1] * p;
-    acc[3] += w[2] * p;
-    acc[4] += w[0] * w[0] * p;
-    acc[5] += w[1] * w[1] * p;
-    acc[6] += w[2] * w[2] * p;
-    acc[7] += w[0] * w[1] * p;
-    acc[8] += w[0] * w[2] * p;
-    acc[9] += w[1] * w[2] * p;
-    acc[10] += ore;
-    acc[11] += oim;
-    acc[12] += rn;
+    acc[1] += w0 * p;
+    acc[2] += w1 * p;
+    acc[3] += w2 * p;
+    acc[4] += w0 * w0 * p;
+    acc[5] += w1 * w1 * p;
+    acc[6] += w2 * w2 * p;
+    acc[7] += w0 * w1 * p;
+    acc[8] += w0 * w2 * p;
+    acc[9] += w1 * w2 * p;
+    if constexpr (REF) {
+      acc[10] += ore;
+      acc[11] += oim;
+      acc[12] += rn;
+    }
+  };
+  int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // Full rounds: every load unconditional, all issued before any use.
+  for (; i0 + (UNR - 1) * stride < V; i0 += UNR * stride) {
+    cx<T> a[UNR][S], r[UNR][S];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int c = 0; c < S; ++c) {
+        a[u][c] = psi[c * V + i0 + u * stride];
+        if constexpr (REF) r[u][c] = ref[c * V + i0 + u * stride];
+      }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) site(i0 + u * stride, a[u], r[u]);
+  }
+  // Tail: at most UNR - 1 sites per thread.
+  for (; i0 < V; i0 += stride) {
+    cx<T> a[S], r[S];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      a[c] = psi[c * V + i0];
+      if constexpr (REF) r[c] = ref[c * V + i0];
+    }
+    site(i0, a, r);
   }
   block_reduce_store<kObsFields>(acc, partials + (int64_t)blockIdx.x * kObsFields);
 }
 
+template <typename T>
+static void launch_obs_t(const ObsGeom& g, const void* psi, const void* ref, double* partials,
+                         unsigned nb, hipStream_t st) {
+  auto p = (const cx<T>*)psi;
+  auto r = (const cx<T>*)ref;
+#define QW_OBS(D, R) \
+  hipLaunchKernelGGL((k_observables<T, D, R>), dim3(nb), dim3(256), 0, st, p, r, g, partials)
+  if (g.dim == 1) {
+    if (ref) QW_OBS(1, true); else QW_OBS(1, false);
+  } else if (g.dim == 2) {
+    if (ref) QW_OBS(2, true); else QW_OBS(2, false);
+  } else {
+    if (ref) QW_OBS(3, true); else QW_OBS(3, false);
+  }
+#undef QW_OBS
+}
+
 hipError_t launch_observables(bool dbl, const ObsGeom& g, const void* psi, const void* ref,
                               double* partials, double* result, hipStream_t st) {
-  int64_t nb = (g.V + 255) / 256;
+  int64_t nb = (g.V + 1023) / 1024;
   if (nb > kObsBlocks) nb = kObsBlocks;
   if (dbl)
-    hipLaunchKernelGGL(k_observables<double>, dim3((unsigned)nb), dim3(256), 0, st,
-                       (const cx<double>*)psi, (const cx<double>*)ref, g, partials);
+    launch_obs_t<double>(g, psi, ref, partials, (unsigned)nb, st);
   else
-    hipLaunchKernelGGL(k_observables<float>, dim3((unsigned)nb), dim3(256), 0, st,
-                       (const cx<float>*)psi, (const cx<float>*)ref, g, partials);
+    launch_obs_t<float>(g, psi, ref, partials, (unsigned)nb, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_final<kObsFields>, dim3(1), dim3(256), 0, st, partials, (int)nb,

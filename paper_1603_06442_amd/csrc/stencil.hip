@@ -141,9 +141,11 @@ __device__ __forceinline__ void load_plane(PlaneRegs<T>& R, const cx<T>* __restr
 #pragma unroll
     for (int c = 0; c < 4; ++c) R.own[h][c] = in[c * V + idx];
   }
-  if (tid < kHalo) {
+  // Every thread loads (threads past the halo repeat halo site 0 and never
+  // store it): unconditional loads keep the wait counts exact.
+  {
     int i2, i3;
-    halo_site(tid, i2, i3);
+    halo_site(tid < kHalo ? tid : 0, i2, i3);
     const int64_t n2 = (b2 + i2 - 1) & m2;
     const int64_t n3 = (b3 + i3 - 1) & m3;
     const int64_t idx = plane_off + (n2 << lg3) + n3;
@@ -170,7 +172,7 @@ __device__ __forceinline__ void store_plane(const PlaneRegs<T>& R, cx<T>* ring, 
   }
 }
 
-template <typename T>
+template <typename T, int PF, bool SPARSE>
 __global__ __launch_bounds__(kStepThreads) void k_step3d_ring(cx<T>* __restrict__ out,
                                                              const cx<T>* __restrict__ in,
                                                              StencilGeom g, StencilCoef<T> C,
@@ -197,23 +199,30 @@ __global__ __launch_bounds__(kStepThreads) void k_step3d_ring(cx<T>* __restrict_
   const int64_t V = g.V;
   const int64_t a = ch * chunk;
 
-  // Ring slot of (unwrapped) plane p is (p - a + 1) mod 3.
-  PlaneRegs<T> R;
-  load_plane(R, in, V, ((a - 1) & m1) * planeN, m2, m3, lg3, b2, b3, tid);
-  store_plane(R, lds, tid);  // plane a-1 -> slot 0
-  load_plane(R, in, V, (a & m1) * planeN, m2, m3, lg3, b2, b3, tid);
-  store_plane(R, lds + PL, tid);  // plane a -> slot 1
-  load_plane(R, in, V, ((a + 1) & m1) * planeN, m2, m3, lg3, b2, b3, tid);
+  // Ring slot of (unwrapped) plane p is (p - a + 1) mod 3. The register sets
+  // R[0..PF-1] hold the next PF planes in flight: at iteration n1, set
+  // (n1 - a) mod PF holds plane n1+1; once it is in LDS it is refilled with
+  // plane n1+1+PF. The loop is unrolled by PF so every set is addressed
+  // statically.
+  PlaneRegs<T> R[PF];
+  load_plane(R[0], in, V, ((a - 1) & m1) * planeN, m2, m3, lg3, b2, b3, tid);
+  store_plane(R[0], lds, tid);  // plane a-1 -> slot 0
+  load_plane(R[0], in, V, (a & m1) * planeN, m2, m3, lg3, b2, b3, tid);
+  store_plane(R[0], lds + PL, tid);  // plane a -> slot 1
+#pragma unroll
+  for (int u = 0; u < PF; ++u)
+    load_plane(R[u], in, V, ((a + 1 + u) & m1) * planeN, m2, m3, lg3, b2, b3, tid);
 
   const int c3 = tid & (kTN3 - 1);
   const int r0 = tid / kTN3;
-  for (int64_t n1 = a; n1 < a + chunk; ++n1) {
+  // One output plane n1 from ring slots; set u of the registers holds plane
+  // n1+1 on entry and, with REFILL, plane n1+1+PF on exit.
+  auto plane_step = [&](int64_t n1, int u, bool refill) {
     const int64_t n0 = n1 & m1;
     const int sm = (int)((n1 - a) % 3), s0 = (int)((n1 - a + 1) % 3), sp = (int)((n1 - a + 2) % 3);
-    store_plane(R, lds + sp * PL, tid);  // plane n1+1 into its slot
+    store_plane(R[u], lds + sp * PL, tid);  // plane n1+1 into its slot
     __syncthreads();
-    if (n1 + 1 < a + chunk)  // issue the loads of plane n1+2 now
-      load_plane(R, in, V, ((n1 + 2) & m1) * planeN, m2, m3, lg3, b2, b3, tid);
+    if (refill) load_plane(R[u], in, V, ((n1 + 1 + PF) & m1) * planeN, m2, m3, lg3, b2, b3, tid);
     const cx<T>* Pm = lds + sm * PL;
     const cx<T>* P0 = lds + s0 * PL;
     const cx<T>* Pp = lds + sp * PL;
@@ -227,11 +236,26 @@ __global__ __launch_bounds__(kStepThreads) void k_step3d_ring(cx<T>* __restrict_
       for (int k = 0; k < 8; ++k) {
         const int o1 = kOff3[k][0], o2 = kOff3[k][1], o3 = kOff3[k][2];
         const cx<T>* P = (o1 > 0 ? Pp : (o1 < 0 ? Pm : P0)) + site + o2 * kH3 + o3;
-        const cx<T> q0 = P[0], q1 = P[CS], q2 = P[2 * CS], q3 = P[3 * CS];
-        a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
-        a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
-        a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
-        a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
+        const cx<T> q0 = P[0], q1 = P[CS];
+        if constexpr (SPARSE) {
+          // rank-one blocks: offsets 0..3 feed output 0 and read component 3,
+          // offsets 4..7 feed output 1 and read component 2
+          if (k < 4) {
+            const cx<T> q3 = P[3 * CS];
+            a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+            a2 = fma_c(a2, C.lo[k][0][1], q3); a3 = fma_c(a3, C.lo[k][1][1], q3);
+          } else {
+            const cx<T> q2 = P[2 * CS];
+            a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+            a2 = fma_c(a2, C.lo[k][0][0], q2); a3 = fma_c(a3, C.lo[k][1][0], q2);
+          }
+        } else {
+          const cx<T> q2 = P[2 * CS], q3 = P[3 * CS];
+          a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+          a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+          a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
+          a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
+        }
       }
       const cx<T> mass = C.onsite[0][0];
       a0 = fma_c(a0, mass, P0[site + 2 * CS]);
@@ -246,7 +270,15 @@ __global__ __launch_bounds__(kStepThreads) void k_step3d_ring(cx<T>* __restrict_
       out[3 * V + idx] = a3;
     }
     __syncthreads();  // slot of plane n1-1 is rewritten next iteration
+  };
+  // chunk is a multiple of PF: all but the last PF planes refill their set
+  // unconditionally; the last PF planes load nothing.
+  for (int64_t nb = a; nb < a + chunk - PF; nb += PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) plane_step(nb + u, u, true);
   }
+#pragma unroll
+  for (int u = 0; u < PF; ++u) plane_step(a + chunk - PF + u, u, false);
 }
 
 bool step3d_ring_ok(const StencilGeom& g) {
@@ -256,14 +288,15 @@ bool step3d_ring_ok(const StencilGeom& g) {
 hipError_t launch_step3d_ring(bool dbl, const StencilGeom& g, void* out, const void* in,
                               const void* coef, hipStream_t st) {
   const int64_t tiles2 = g.N[1] / kTN2, tiles3 = g.N[2] / kTN3;
-  int chunk = 16;
-  while (chunk > 1 && g.N[0] % chunk) chunk >>= 1;
-  if (chunk > g.N[0]) chunk = (int)g.N[0];
+  // Chunks of 32 planes where that leaves at least ~2 workgroups per CU slot.
+  int chunk = g.N[0] * tiles2 * tiles3 >= 32 * 1024 ? 32 : 16;
+  while (chunk > 2 && g.N[0] % chunk) chunk >>= 1;
+  if (chunk > g.N[0]) chunk = (int)g.N[0];  // N1 >= 4 is a power of two: chunk >= 2 = PF
   const int64_t nchunks = g.N[0] / chunk;
   const int64_t nblk = tiles2 * tiles3 * nchunks;
   if (dbl) {
     const size_t lds = 3 * 4 * kPlaneSites * sizeof(cx<double>);
-    auto kern = k_step3d_ring<double>;
+    auto kern = g.sparse3 ? k_step3d_ring<double, 1, true> : k_step3d_ring<double, 1, false>;
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -272,7 +305,7 @@ hipError_t launch_step3d_ring(bool dbl, const StencilGeom& g, void* out, const v
                        tiles3, nchunks);
   } else {
     const size_t lds = 3 * 4 * kPlaneSites * sizeof(cx<float>);
-    auto kern = k_step3d_ring<float>;
+    auto kern = g.sparse3 ? k_step3d_ring<float, 2, true> : k_step3d_ring<float, 2, false>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)kern,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

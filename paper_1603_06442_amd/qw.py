@@ -54,8 +54,9 @@ def _load():
         "qw_transform": [vp, vp, vp, cint, vp],
         "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
         "qw_prepare_state": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl, vp],
-        "qw_set_schedule": [vp, cint, cint, cint],
-        "qw_get_schedule": [vp, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint)],
+        "qw_set_schedule": [vp, cint, cint, cint, cint],
+        "qw_get_schedule": [vp, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint),
+                            ctypes.POINTER(cint)],
         "qw_autotune": [vp, vp, ctypes.POINTER(dbl)],
     }
     for name, args in sig.items():
@@ -197,17 +198,19 @@ class Plan:
                 "mean_cart": list(o.mean_cart),
                 "overlap": complex(o.overlap_re, o.overlap_im), "ref_norm2": o.ref_norm2}
 
-    def set_schedule(self, slab_planes, contig_elems=8, contig_threads=256):
+    def set_schedule(self, slab_planes, contig_elems=8, contig_threads=256, contig_groups=1):
         """qw_set_schedule: slab size (n1 planes, 0 = whole field), the fused
-        pass's elements per thread (4 or 8) and workgroup size."""
+        pass's elements per thread (4 or 8), workgroup size and pencil groups
+        per workgroup."""
         _check(LIB.qw_set_schedule(self._h, int(slab_planes), int(contig_elems),
-                                   int(contig_threads)))
+                                   int(contig_threads), int(contig_groups)))
 
     def schedule(self):
-        """qw_get_schedule: (slab_planes, contig_elems, contig_threads)."""
-        a, b, c = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
-        _check(LIB.qw_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
+        """qw_get_schedule: (slab_planes, contig_elems, contig_threads, contig_groups)."""
+        a, b, c, d = (ctypes.c_int(0) for _ in range(4))
+        _check(LIB.qw_get_schedule(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                   ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
 
     def autotune(self, stream=None):
         """qw_autotune: time the candidate schedules, keep the fastest.

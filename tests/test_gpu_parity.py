@@ -153,15 +153,22 @@ def test_observables_match_oracle(qw, d, shape, dtype):
     psi = rand_field(d, shape, 11)
     refp = rand_field(d, shape, 12)
     plan = qw.Plan(d, list(shape), 0.1, dtype)
-    c = [n // 3 + 0.0 for n in shape]
-    got = plan.observables(to_dev(psi, plan), c, ref=to_dev(refp, plan))
+    _check_observables(plan, psi, refp, [n // 3 + 0.0 for n in shape], dtype)
+    _check_observables(plan, psi, refp, [n / 3 + 0.37 for n in shape], dtype)
+    _check_observables(plan, psi, None, [n - 1.5 for n in shape], dtype)
+
+
+def _check_observables(plan, psi, refp, c, dtype):
+    got = plan.observables(to_dev(psi, plan), c,
+                           ref=to_dev(refp, plan) if refp is not None else None)
     # the oracle sees the field rounded to the GPU's precision
     if dtype == "c64":
         psi = psi.astype(np.complex64).astype(np.complex128)
-        refp = refp.astype(np.complex64).astype(np.complex128)
+        if refp is not None:
+            refp = refp.astype(np.complex64).astype(np.complex128)
     want = ob.observables(psi, c, refp)
     assert abs(got["norm2"] - want["norm2"]) < 1e-12
-    assert np.allclose(got["mean"], want["mean"], atol=1e-10)
+    assert np.allclose(got["mean"][:plan.dim], want["mean"][:plan.dim], atol=1e-10)
     assert np.allclose(got["second"], want["second"], atol=1e-9)
     assert np.allclose(got["mean_cart"], want["mean_cart"], atol=1e-10)
     assert abs(got["overlap"] - want["overlap"]) < 1e-12
@@ -252,12 +259,12 @@ def test_every_schedule_gives_the_same_evolution(qw, dtype):
     plan = qw.Plan(d, list(shape), m, dtype)
     for slab in (0, 1, 3, 4, 16):
         for ce in (4, 8):
-            for cb in (64, 256):
-                plan.set_schedule(slab, ce, cb)
+            for cb, gw in ((64, 1), (256, 1), (64, 4), (128, 3)):
+                plan.set_schedule(slab, ce, cb, gw)
                 out = plan.evolve_fft(to_dev(psi0, plan), t)
-                assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t), (slab, ce, cb)
+                assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t), (slab, ce, cb, gw)
     ms = plan.autotune()
-    assert ms > 0 and plan.schedule()[1] in (4, 8)
+    assert ms > 0 and plan.schedule()[1] in (4, 8) and plan.schedule()[3] >= 1
     out = plan.evolve_fft(to_dev(psi0, plan), t)
     assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
 
@@ -265,7 +272,7 @@ def test_every_schedule_gives_the_same_evolution(qw, dtype):
 def test_batched_with_slabs(qw):
     d, shape = 3, (8, 8, 16)
     plan = qw.Plan(d, list(shape), 0.1, "c64")
-    plan.set_schedule(2, 4, 128)
+    plan.set_schedule(2, 4, 128, 2)
     ms, ts = [0.02, 0.2, 0.5], [3, 999, -70]
     xs = np.stack([rand_field(d, shape, 70 + b) for b in range(3)])
     outn = to_np(plan.evolve_fft_batched(to_dev(xs, plan), ms, ts))
