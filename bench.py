@@ -233,6 +233,22 @@ def main():
         "roofline": roofline,
         "last_obs": {"norm2": obs["norm2"], "mean_cart": obs["mean_cart"]},
     }
+    # Accuracy beside the speed: the complex64 path (FP32 transforms, FP64
+    # phase) against the complex128 GPU path on the same state, at the
+    # largest time of the schedule; norm drift of both.
+    p128 = qw.Plan(3, N, w["m"], "c128")
+    x128 = p128.empty()
+    p128.prepare_state(x128, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
+    tmax = times[-1]
+    y128 = p128.evolve_fft(x128, tmax)
+    y64 = plan.evolve_fft(psi0, tmax, out=psit)
+    diff = (y64.to(torch.complex128) - y128)
+    rel = float(torch.linalg.vector_norm(diff) / torch.linalg.vector_norm(y128))
+    line["accuracy"] = {
+        "t": tmax, "c64_vs_c128_rel_l2": rel,
+        "norm_drift_c64": abs(plan.observables(y64, w["center"])["norm2"] - 1.0),
+        "norm_drift_c128": abs(p128.observables(y128, w["center"])["norm2"] - 1.0)}
+    del p128, x128, y128, diff
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line))

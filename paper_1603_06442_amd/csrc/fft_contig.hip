@@ -128,6 +128,99 @@ __device__ __forceinline__ void apply_q(cx<T> (&y)[DIM == 1 ? 2 : 4], const Pass
   }
 }
 
+
+// complex64 with the plan's omega table: omega and the phase reduction stay
+// FP64; n~, sin(omega) and M_q are FP32 (they only scale the result), read
+// from the FP32 (cos, sin)(pi j / Nc) table; the sine and cosine of the
+// reduced angle use the hardware FP32 units.
+struct PencilTrig {  // cos/sin of the pencil's fixed Cartesian component(s)
+  float c, s;
+  int a1, a2;
+};
+
+template <int DIM>
+__device__ __forceinline__ PencilTrig pencil_trig(const PassGeom& g, int64_t pen) {
+  PencilTrig pt;
+  pt.c = 1.0f;
+  pt.s = 0.0f;
+  pt.a1 = pt.a2 = 0;
+  if constexpr (DIM == 3) {
+    const int j1 = (int)(pen >> g.lgN1), j2 = (int)(pen & (g.N[1] - 1));
+    pt.a1 = j1 << g.shift[0];
+    pt.a2 = j2 << g.shift[1];
+    const int jx = (pt.a1 + pt.a2) & (2 * g.Nc - 1);  // k_x = (q1 + q2) / 2
+    pt.c = g.csf[2 * jx];
+    pt.s = g.csf[2 * jx + 1];
+  } else if constexpr (DIM == 2) {
+    pt.a1 = (int)pen << g.shift[0];
+  }
+  return pt;
+}
+
+template <int DIM>
+__device__ __forceinline__ void apply_q_f32(cx<float> (&y)[DIM == 1 ? 2 : 4], const PassGeom& g,
+                                            const InstParam& ip, const PencilTrig& pt, int64_t pen,
+                                            int z, int64_t qidx) {
+  const int twoNc1 = 2 * g.Nc - 1;
+  float n1, n2, n3;
+  if constexpr (DIM == 3) {
+    const int a3 = z << g.shift[2];
+    const int jy = (pt.a1 + a3) & twoNc1;  // k_y = (q1 + q3) / 2
+    const int jz = (pt.a2 + a3) & twoNc1;  // k_z = -(q2 + q3) / 2
+    const float2 ty = *reinterpret_cast<const float2*>(g.csf + 2 * jy);
+    const float2 tz = *reinterpret_cast<const float2*>(g.csf + 2 * jz);
+    const float cx_ = pt.c, sx = pt.s, cy = ty.x, sy = ty.y, cz = tz.x, sz = -tz.y;
+    const float cycz = cy * cz, sysz = sy * sz, sycz = sy * cz, cysz = cy * sz;
+    n1 = sx * cycz - cx_ * sysz;
+    n2 = cx_ * sycz + sx * cysz;
+    n3 = cx_ * cysz - sx * sycz;
+  } else if constexpr (DIM == 2) {
+    const int a2 = z << g.shift[1];
+    const int jx = (pt.a1 + a2) & twoNc1, jy = (pt.a1 - a2 + 2 * g.Nc) & twoNc1;
+    const float2 tx = *reinterpret_cast<const float2*>(g.csf + 2 * jx);
+    const float2 ty = *reinterpret_cast<const float2*>(g.csf + 2 * jy);
+    n1 = tx.y * ty.x;
+    n2 = tx.x * ty.y;
+    n3 = tx.y * ty.y;
+  } else {
+    const int64_t j1 = g.fourstep ? pen + g.N1 * z : z;
+    const int jj = (int)((2 * (j1 << g.shift[0])) & twoNc1);
+    n1 = 0.0f;
+    n2 = 0.0f;
+    n3 = g.csf[2 * jj + 1];
+  }
+  const float nn = (float)ip.n, m = (float)ip.m;
+  const float sinw = sqrtf(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
+  const float r = (float)reduced_phase(g.omega[qidx], ip.t);
+  float S, C;
+  __sincosf(r, &S, &C);
+  const float sc = (float)g.inv_scale;
+  const float c = C * sc;
+  const float st = sinw > 1e-30f ? S * sc / sinw : 0.0f;  // V^-1 sin(omega t) / sin(omega)
+  if constexpr (DIM == 1) {
+    const float a = nn * n3 * st, gg = m * st;
+    const cx<float> z0 = mk(a * y[0].x - gg * y[1].x, a * y[0].y - gg * y[1].y);
+    const cx<float> z1 = mk(-gg * y[0].x - a * y[1].x, -gg * y[0].y - a * y[1].y);
+    y[0] = mk(c * y[0].x + z0.y, c * y[0].y - z0.x);
+    y[1] = mk(c * y[1].x + z1.y, c * y[1].y - z1.x);
+  } else {
+    const float a = nn * n3 * st, b = nn * n1 * st, e = nn * n2 * st, gg = m * st;
+    const cx<float> p0 = y[0], p1 = y[1], p2 = y[2], p3 = y[3];
+    const cx<float> z0 = mk(a * p0.x + (b * p1.x + e * p1.y) - gg * p2.x,
+                            a * p0.y + (b * p1.y - e * p1.x) - gg * p2.y);
+    const cx<float> z1 = mk((b * p0.x - e * p0.y) - a * p1.x - gg * p3.x,
+                            (b * p0.y + e * p0.x) - a * p1.y - gg * p3.y);
+    const cx<float> z2 = mk(-gg * p0.x - a * p2.x - (b * p3.x + e * p3.y),
+                            -gg * p0.y - a * p2.y - (b * p3.y - e * p3.x));
+    const cx<float> z3 = mk(-gg * p1.x - (b * p2.x - e * p2.y) + a * p3.x,
+                            -gg * p1.y - (b * p2.y + e * p2.x) + a * p3.y);
+    y[0] = mk(c * p0.x + z0.y, c * p0.y - z0.x);
+    y[1] = mk(c * p1.x + z1.y, c * p1.y - z1.x);
+    y[2] = mk(c * p2.x + z2.y, c * p2.y - z2.x);
+    y[3] = mk(c * p3.x + z3.y, c * p3.y - z3.x);
+  }
+}
+
 // Map (pencil, position) of the contiguous pass to lattice frequency indices.
 template <int DIM>
 __device__ __forceinline__ void q_index(const PassGeom& g, int64_t pen, int64_t z, int64_t& j1,
@@ -219,7 +312,24 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
       }
       fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
     }
-    if constexpr (MODE == MODE_EVOLVE || MODE == MODE_EVOLVE_TAB) {
+    if constexpr (MODE == MODE_EVOLVE_TAB && sizeof(T) == 4) {
+      const InstParam ip = g.single;
+      const PencilTrig pt = pencil_trig<DIM>(g, pen);
+#pragma unroll 1
+      for (int e = 0; e < E; ++e) {
+        const int z = t + TT * e;
+        cx<T> y[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) y[c] = v[c][0];
+        apply_q_f32<DIM>(y, g, ip, pt, pen, z, pen * L + z);
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+#pragma unroll
+          for (int k = 0; k + 1 < E; ++k) v[c][k] = v[c][k + 1];
+          v[c][E - 1] = y[c];
+        }
+      }
+    } else if constexpr (MODE == MODE_EVOLVE || MODE == MODE_EVOLVE_TAB) {
       const InstParam ip = g.inst ? g.inst[b] : g.single;
       // One wave-vector per iteration, deliberately not unrolled (an unrolled
       // loop lets the compiler hoist every element's table reads and keep

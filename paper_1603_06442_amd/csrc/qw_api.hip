@@ -394,6 +394,7 @@ struct qw_plan_s {
   void* d_tw = nullptr;     // exp(-2 pi i j / 4096), field precision
   void* d_tw4 = nullptr;    // exp(-2 pi i j / N) for the 1D four-step, field precision
   double* d_cs = nullptr;   // (cos, sin)(pi j / Nc), j < 2 Nc
+  float* d_csf = nullptr;   // the same, FP32
   double* d_partials = nullptr;
   double* d_result = nullptr;
   double* h_result = nullptr;  // pinned
@@ -416,6 +417,7 @@ struct qw_plan_s {
     if (d_tw) (void)hipFree(d_tw);
     if (d_tw4) (void)hipFree(d_tw4);
     if (d_cs) (void)hipFree(d_cs);
+    if (d_csf) (void)hipFree(d_csf);
     if (d_partials) (void)hipFree(d_partials);
     if (d_result) (void)hipFree(d_result);
     if (h_result) (void)hipHostFree(h_result);
@@ -507,6 +509,7 @@ PassGeom pass_geom(qw_plan_t p, int64_t L, int B) {
   g.fourstep = p->fourstep ? 1 : 0;
   g.N1 = p->fs_N1;
   g.cs = p->d_cs;
+  g.csf = p->d_csf;
   g.tw4 = p->d_tw4;
   g.inv_scale = 1.0 / (double)p->V;
   g.single.m = p->m;
@@ -738,7 +741,9 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
         r = upload(&p->d_tw4, t4.data(), t4.size() * sizeof(t4[0]));
       }
     }
+    std::vector<float> csf(cs.begin(), cs.end());
     if (r == QW_OK) r = upload((void**)&p->d_cs, cs.data(), cs.size() * sizeof(double));
+    if (r == QW_OK) r = upload((void**)&p->d_csf, csf.data(), csf.size() * sizeof(float));
     if (r == QW_OK) {
       hipError_t e = hipMalloc(&p->d_partials, sizeof(double) * kObsFields * kObsBlocks);
       if (e == hipSuccess) e = hipMalloc(&p->d_result, sizeof(double) * 16);

@@ -35,6 +35,7 @@ struct PassGeom {
   int fourstep;      // 1D four-step: N = N1 * L, pencil = row k1
   int64_t N1;        // four-step rows
   const double* cs;  // cos/sin(pi j / Nc), j in [0, 2 Nc), as (cos, sin) pairs
+  const float* csf;  // the same table rounded to FP32 (complex64 evolution with the omega table)
   const void* tw4;   // four-step twiddles exp(-2 pi i j / N), j in [0, N)
   double inv_scale;  // 1 / V
   InstParam single;  // used when inst == nullptr

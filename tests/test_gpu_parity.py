@@ -279,3 +279,31 @@ def test_batched_with_slabs(qw):
     for b in range(3):
         ref = fourier.evolve_fourier(xs[b], table(d, ms[b]), ts[b])
         assert ob.rel_l2(outn[b], ref) < 2e-5
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_workload_512_subcase_t_1e6(qw, dtype):
+    """The 512^3 workload's oracle sub-case: 32^3, m = 0.1, k0 from the
+    workload's seed, width 2.5 cells, t = 1e6 by one Fourier jump vs the
+    oracle's binary powering (complex128 bound 1e-15 t = 1e-9)."""
+    w = inputs.workload(4)
+    N, t = w["sub_N"], w["t"]
+    psi0 = states.particle_state(3, N, w["m"], w["k0"], w["sub_sigma"], [N // 2] * 3)
+    ref = fourier.evolve_fourier(psi0, table(3, w["m"]), t)
+    plan = qw.Plan(3, N, w["m"], dtype)
+    out = plan.evolve_fft(to_dev(psi0, plan), t)
+    assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
+    assert abs(plan.observables(out, [N // 2] * 3)["norm2"] - 1.0) < (1e-5 if dtype == "c64" else 1e-12)
+
+
+def test_fp32_path_vs_fp64_path_large_t(qw):
+    """complex64 (FP32 transforms, FP64 phase) vs complex128 on the GPU, 64^3,
+    at t = 1e6: within the FP32 tolerance."""
+    N, m = 64, 0.1
+    psi0 = rand_field(3, (N, N, N), 41)
+    p64 = qw.Plan(3, N, m, "c64")
+    p128 = qw.Plan(3, N, m, "c128")
+    for t in (1, 999999, 1000000):
+        a = to_np(p64.evolve_fft(to_dev(psi0, p64), t))
+        b = to_np(p128.evolve_fft(to_dev(psi0, p128), t))
+        assert ob.rel_l2(a, b) < 2e-5
