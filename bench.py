@@ -16,7 +16,12 @@ carries the stencil's own site-steps/s, the roofline of the dominant kernel
 measured with HIP events on the launch stream, and the FP64 CPU oracle timed
 on a bounded sample.
 
+The serving tier is measured beside it: 512 mixed requests through the
+continuous-batching server (saturation throughput batched and unbatched,
+p50/p99 latency under Poisson arrivals).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-serving]
        python bench.py --copy-calib   (a plain copy of one field, for counters)
 """
 import argparse
@@ -86,12 +91,87 @@ def copy_calib(steps):
                       "launches": steps}))
 
 
+def _submit(srv, r):
+    return srv.submit(dim=r["d"], N=r["N"], m=r["m"], k0=r["k0"], sigma=r["sigma"],
+                      center=r["center"], c_plus=r["c_plus"], c_minus=r["c_minus"], t=r["t"],
+                      dtype=r.get("dtype", "c64"))
+
+
+def _burst(srv, reqs):
+    """Submit everything while held, release, wait: makespan and results."""
+    srv.hold(True)
+    t0 = time.perf_counter()
+    tks = [_submit(srv, r) for r in reqs]
+    srv.hold(False)
+    res = [srv.wait(tk) for tk in tks]
+    return time.perf_counter() - t0, res
+
+
+def _pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(math.ceil(q * len(xs))) - 1)]
+
+
+def serving(qw, budget_gib=16):
+    """The mixed request stream (512 requests: 1D/2D/3D lattices, masses,
+    states and times drawn per request) through the continuous-batching
+    server: saturation throughput of a burst, the same burst unbatched
+    (one request per batch, one stream), and open-loop Poisson arrivals at
+    70% of the saturation rate for p50/p99 latency."""
+    from paper_1603_06442_amd import inputs
+    reqs = inputs.workload(3)["requests"]
+    budget = budget_gib << 30
+    srv = qw.Server(budget, max_batch=32, nstreams=4)
+    one = qw.Server(budget, max_batch=1, nstreams=1)
+    try:
+        _burst(srv, reqs)  # plans for every shape, pool warm
+        _burst(one, reqs)
+        st0 = srv.stats()
+        el, res = _burst(srv, reqs)
+        st = srv.stats()
+        nb = st["batches"] - st0["batches"]
+        el1, _ = _burst(one, reqs)
+        sat = len(reqs) / el
+        rate = 0.7 * sat
+        rng = inputs.rng_for(3)
+        gaps = rng.exponential(1.0 / rate, len(reqs))
+        tks = []
+        t0 = time.perf_counter()
+        due = 0.0
+        for r, gap in zip(reqs, gaps):
+            due += gap
+            while time.perf_counter() - t0 < due:
+                pass
+            tks.append(_submit(srv, r))
+        pres = [srv.wait(tk) for tk in tks]
+        lat = [1e3 * x["latency_s"] for x in pres]
+        bad = sum(1 for x in res + pres if x["status"] != qw.QW_OK)
+        drift = max(abs(x["obs"]["norm2"] - 1.0) for x in res)
+        return {
+            "requests": len(reqs), "budget_bytes": budget, "max_batch": 32, "streams": 4,
+            "saturation_requests_per_s": round(sat, 1),
+            "saturation_batches": nb,
+            "saturation_mean_batch": round(len(reqs) / max(1, nb), 2),
+            "unbatched_requests_per_s": round(len(reqs) / el1, 1),
+            "poisson_rate_per_s": round(rate, 1),
+            "p50_latency_ms": round(_pct(lat, 0.50), 3),
+            "p99_latency_ms": round(_pct(lat, 0.99), 3),
+            "mean_batch_poisson": round(sum(x["batch_size"] for x in pres) / len(pres), 2),
+            "peak_used_bytes": st["peak_used_bytes"], "failed": bad,
+            "max_norm_drift": drift,
+        }
+    finally:
+        srv.close()
+        one.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="print the evolution time of every schedule and exit")
@@ -249,6 +329,8 @@ def main():
         "norm_drift_c64": abs(plan.observables(y64, w["center"])["norm2"] - 1.0),
         "norm_drift_c128": abs(p128.observables(y128, w["center"])["norm2"] - 1.0)}
     del p128, x128, y128, diff
+    if not args.no_serving:
+        line["serving"] = serving(qw)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line))

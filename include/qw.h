@@ -158,6 +158,71 @@ qw_status qw_get_schedule(qw_plan_t plan, int* slab_planes, int* contig_elems,
  * fastest; *best_ms (nullable) receives its time per evolution. Waits. */
 qw_status qw_autotune(qw_plan_t plan, void* stream, double* best_ms);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of Fourier evolutions of particle states.
+ * A request describes one lattice (dim, N), the mass m, a Gaussian particle /
+ * antiparticle state (as in qw_prepare_state: k0, sigma, center, c_plus,
+ * c_minus), a time t and the precision. The server prepares the state,
+ * evolves it to t (Sec. 4) and returns the reductions of psi(t) about
+ * `center` (Sec. 5.2). Requests are admitted in arrival order while the
+ * device memory they need (one field, two for the 1D four-step) fits
+ * budget_bytes, grouped by (dim, N, dtype) into batches of at most max_batch
+ * instances (each with its own m, state and t), and run on nstreams streams;
+ * at most 2 * nstreams batches are on the device at once, and requests
+ * that arrive meanwhile gather into the next batches, admitted as batches
+ * finish and memory frees. A request's result does not depend on what it
+ * was batched with.
+ * ------------------------------------------------------------------------ */
+typedef struct qw_server_s* qw_server_t;
+
+typedef struct {
+  int dim;           /* 1, 2, 3 */
+  int64_t N[3];      /* dim entries used; powers of two as for qw_plan */
+  double m;          /* 0 <= m <= 1 */
+  qw_dtype dtype;
+  double k0[3];      /* Cartesian central wave-vector (dim entries) */
+  double sigma;      /* packet width in cells, > 0 */
+  double center[3];  /* packet centre and origin of the reductions */
+  double c_plus, c_minus;
+  int64_t t;         /* any sign */
+} qw_request;
+
+typedef struct {
+  int64_t ticket;
+  qw_status status;
+  int batch_size;          /* instances in the batch that served the request */
+  double queue_s;          /* submit -> launch of its batch (host clock) */
+  double latency_s;        /* submit -> completion signalled by the stream */
+  qw_obs obs;              /* reductions of psi(t) about center (no overlap) */
+  double sector_norm2[2];  /* squared norms of the two sector amplitudes before normalisation */
+} qw_result;
+
+typedef struct {
+  int64_t submitted, completed, batches, queued;
+  int64_t inflight_batches, max_inflight_batches;
+  int64_t used_bytes, peak_used_bytes;
+} qw_server_info;
+
+/* Start a server on the current device. budget_bytes >= 1 MiB, max_batch in
+ * [1, 4096], nstreams in [1, 16]. */
+qw_status qw_server_create(qw_server_t* out, size_t budget_bytes, int max_batch, int nstreams);
+/* Queue a request; never blocks on the device. QW_ERR_NOMEM if the request
+ * alone exceeds the budget; argument errors as for qw_plan / qw_prepare_state. */
+qw_status qw_server_submit(qw_server_t server, const qw_request* req, int64_t* ticket);
+/* *done = 1 and *out filled once the request has completed, else *done = 0.
+ * A result is handed out once (by poll or wait); the ticket is then unknown
+ * (QW_ERR_INVALID): of two callers waiting on one ticket, one gets the
+ * result and the other QW_ERR_INVALID. */
+qw_status qw_server_poll(qw_server_t server, int64_t ticket, qw_result* out, int* done);
+/* Block until the request has completed. */
+qw_status qw_server_wait(qw_server_t server, int64_t ticket, qw_result* out);
+/* hold != 0: queue requests but launch none (batches already on the device
+ * finish); hold = 0: resume, batching everything queued meanwhile. */
+qw_status qw_server_hold(qw_server_t server, int hold);
+qw_status qw_server_stats(qw_server_t server, qw_server_info* out);
+/* Finish every queued and running request, then release everything. */
+qw_status qw_server_destroy(qw_server_t server);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* qw_last_error(void);
 

@@ -20,16 +20,15 @@
 #include <new>
 #include <vector>
 
-#include "qw_internal.h"
+#include "plan.h"
 
 using namespace qw;
-typedef std::complex<double> zc;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-qw_status fail(qw_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace qw {
 qw_status fail(qw_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -39,14 +38,9 @@ qw_status fail(qw_status s, const char* fmt, ...) {
   g_last_error = buf;
   return s;
 }
+}  // namespace qw
 
-#define HIP_TRY(expr)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(e_ == hipErrorOutOfMemory ? QW_ERR_NOMEM : QW_ERR_DEVICE, "%s: %s (%s:%d)", \
-                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                         \
-  } while (0)
+namespace {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 int lg2(int64_t v) {
@@ -170,11 +164,6 @@ void dirac_symbol(int dim, const double q[3], double m, zc D[4][4]) {
 
 // --- transition matrices ----------------------------------------------------
 
-struct Table {
-  int dim, s;
-  // offsets in {-1,0,1}^d, index = sum (o_i + 1) 3^(d-1-i)
-  zc U[27][4][4];
-};
 
 int off_index(int dim, const int* o) {
   int idx = 0;
@@ -365,70 +354,7 @@ bool pack_coef(const Table& Tb, double m, StencilCoef<T>& C, std::string& why) {
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Plan
-// ---------------------------------------------------------------------------
-struct qw_plan_s {
-  int dim = 0, s = 0;
-  int64_t N[3] = {1, 1, 1};
-  int lg[3] = {0, 0, 0};
-  int64_t V = 0;
-  double m = 0.0, n = 1.0;
-  qw_dtype dtype = QW_C64;
-  bool dbl = false;
-  size_t elem = 8;        // bytes per complex entry
-  size_t field_bytes = 0;
-  int device = 0;
-
-  Table table;
-  StencilCoef<double> coef_d;
-  StencilCoef<float> coef_f;
-
-  // FFT schedule
-  int Nc = 1;
-  int shift[3] = {0, 0, 0};
-  bool fourstep = false;
-  int64_t fs_N1 = 1, fs_N2 = 1;
-
-  // device memory
-  void* d_tw = nullptr;     // exp(-2 pi i j / 4096), field precision
-  void* d_tw4 = nullptr;    // exp(-2 pi i j / N) for the 1D four-step, field precision
-  double* d_cs = nullptr;   // (cos, sin)(pi j / Nc), j < 2 Nc
-  float* d_csf = nullptr;   // the same, FP32
-  double* d_partials = nullptr;
-  double* d_result = nullptr;
-  double* h_result = nullptr;  // pinned
-  void* d_scratch = nullptr;
-  size_t scratch_bytes = 0;
-  InstParam* d_inst = nullptr;
-  InstParam* h_inst = nullptr;  // pinned
-  int inst_cap = 0;
-  double* d_omega = nullptr;    // omega(q) at the plan's mass, built on first use
-  bool omega_failed = false;
-
-  // Schedule of the 3D Fourier evolution (see qw_set_schedule / qw_autotune).
-  int slab = 0;  // n1 planes per slab of the middle passes (0 = whole field)
-  int ce = 8;    // elements per thread of the fused contiguous pass (4 or 8)
-  int cb = 256;  // target workgroup size of the fused contiguous pass
-  int gw = 1;    // pencil groups per workgroup of the fused pass (prefetch when > 1)
-  bool sparse3 = false;  // 3D transition matrices have the rank-one block pattern
-
-  ~qw_plan_s() {
-    if (d_tw) (void)hipFree(d_tw);
-    if (d_tw4) (void)hipFree(d_tw4);
-    if (d_cs) (void)hipFree(d_cs);
-    if (d_csf) (void)hipFree(d_csf);
-    if (d_partials) (void)hipFree(d_partials);
-    if (d_result) (void)hipFree(d_result);
-    if (h_result) (void)hipHostFree(h_result);
-    if (d_scratch) (void)hipFree(d_scratch);
-    if (d_inst) (void)hipFree(d_inst);
-    if (h_inst) (void)hipHostFree(h_inst);
-    if (d_omega) (void)hipFree(d_omega);
-  }
-};
-
-namespace {
+namespace qw {
 
 // Optional per-pass event recorder (measurement entry point only).
 struct PassTimer {
@@ -633,7 +559,147 @@ qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstP
   return QW_OK;
 }
 
-}  // namespace
+}  // namespace qw
+
+namespace qw {
+
+StateGeom state_geom(qw_plan_t p) {
+  StateGeom g;
+  memset(&g, 0, sizeof g);
+  g.dim = p->dim;
+  g.s = p->s;
+  g.V = p->V;
+  for (int i = 0; i < 3; ++i) {
+    g.N[i] = p->N[i];
+    g.lg[i] = p->lg[i];
+    g.shift[i] = p->shift[i];
+  }
+  g.Nc = p->Nc;
+  g.cs = p->d_cs;
+  return g;
+}
+
+ObsGeom obs_geom(qw_plan_t p) {
+  ObsGeom g;
+  memset(&g, 0, sizeof g);
+  g.dim = p->dim;
+  g.s = p->s;
+  g.V = p->V;
+  for (int i = 0; i < 3; ++i) {
+    g.N[i] = p->N[i];
+    g.lg[i] = p->lg[i];
+  }
+  return g;
+}
+
+void finish_obs(qw_plan_t p, const double* R, const double* origin, qw_obs* out) {
+  memset(out, 0, sizeof *out);
+  out->norm2 = R[0];
+  const double inv = R[0] > 0.0 ? 1.0 / R[0] : 0.0;
+  for (int i = 0; i < p->dim; ++i) out->mean[i] = origin[i] + R[1 + i] * inv;
+  static const int pr[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+  for (int k = 0; k < 6; ++k)
+    if (pr[k][0] < p->dim && pr[k][1] < p->dim) out->second[k] = R[4 + k] * inv;
+  if (p->dim == 1) {
+    out->mean_cart[0] = out->mean[0];
+  } else if (p->dim == 2) {
+    out->mean_cart[0] = out->mean[0] + out->mean[1];
+    out->mean_cart[1] = out->mean[0] - out->mean[1];
+  } else {
+    const double a = out->mean[0], b = out->mean[1], c = out->mean[2];
+    out->mean_cart[0] = a + b - c;
+    out->mean_cart[1] = a - b + c;
+    out->mean_cart[2] = a - b - c;
+  }
+  out->overlap_re = R[10];
+  out->overlap_im = R[11];
+  out->ref_norm2 = R[12];
+}
+
+StateInst make_state_inst(qw_plan_t p, double m, const double* k0, double sigma,
+                          const double* center, double c_plus, double c_minus) {
+  StateInst si;
+  memset(&si, 0, sizeof si);
+  si.m = m;
+  si.n = sqrt(1.0 - m * m);
+  si.sigma = sigma;
+  si.c_plus = c_plus;
+  si.c_minus = c_minus;
+  double kk[3] = {0, 0, 0}, q0[3];
+  for (int i = 0; i < p->dim; ++i) {
+    kk[i] = k0[i];
+    si.center[i] = center[i];
+  }
+  q_of_k(p->dim, kk, q0);
+  for (int i = 0; i < 3; ++i) si.q0[i] = q0[i];
+  // chi_s: normalised column of largest norm of P_s(q0) = (I + s M / sin(omega)) / 2.
+  zc M[4][4];
+  double cosw, sinw;
+  double kq0[3];
+  k_of_q(p->dim, q0, kq0);
+  dirac_M(p->dim, kq0, m, M, cosw, sinw);
+  const int s = p->s;
+  for (int sec = 0; sec < 2; ++sec) {
+    const double sg = sec == 0 ? 1.0 : -1.0;
+    zc P[4][4];
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) {
+        const zc mh = sinw >= 1e-12 ? M[a][b] / sinw : zc(0.0);
+        P[a][b] = 0.5 * ((a == b ? 1.0 : 0.0) + sg * mh);
+      }
+    // Column norms of a projector come in exact pairs (P_jj = P_kk): take the
+    // lowest index within a relative 1e-12 of the largest norm.
+    double nrm[4] = {0.0, 0.0, 0.0, 0.0}, top = 0.0;
+    for (int b = 0; b < s; ++b) {
+      for (int a = 0; a < s; ++a) nrm[b] += std::norm(P[a][b]);
+      nrm[b] = sqrt(nrm[b]);
+      top = fmax(top, nrm[b]);
+    }
+    int best = 0;
+    while (best < s - 1 && !(nrm[best] >= top * (1.0 - 1e-12))) ++best;
+    const double bn = nrm[best];
+    double (*chi)[2] = sec == 0 ? si.chi_p : si.chi_m;
+    for (int a = 0; a < s; ++a) {
+      chi[a][0] = P[a][best].real() / bn;
+      chi[a][1] = P[a][best].imag() / bn;
+    }
+  }
+  return si;
+}
+
+qw_status transform_impl(qw_plan_t p, int B, const void* in, void* out, int direction,
+                         void* scratch, hipStream_t st) {
+  const int64_t L = contig_len(p);
+  PassGeom g = pass_geom(p, L, B);
+  const int64_t planes = (int64_t)p->s * B;
+  if (direction > 0) {
+    if (has_strided(p)) {
+      qw_status r = strided_passes(p, +1, out, in, B, st);
+      if (r != QW_OK) return r;
+      HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, out, out, g, p->d_tw, st));
+    } else {
+      HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, out, in, g, p->d_tw, st));
+    }
+    if (p->fourstep) {
+      if (!scratch) return fail(QW_ERR_INVALID, "four-step transform needs scratch");
+      // row k1, column k2 holds q index k1 + N1 k2: transpose to natural order.
+      HIP_TRY(launch_transpose(p->dbl, scratch, out, planes, p->fs_N1, p->fs_N2, st));
+      HIP_TRY(hipMemcpyAsync(out, scratch, p->field_bytes * B, hipMemcpyDeviceToDevice, st));
+    }
+    return QW_OK;
+  }
+  const void* src = in;
+  if (p->fourstep) {
+    if (!scratch) return fail(QW_ERR_INVALID, "four-step transform needs scratch");
+    HIP_TRY(launch_transpose(p->dbl, scratch, in, planes, p->fs_N2, p->fs_N1, st));
+    src = scratch;
+  }
+  HIP_TRY(launch_fft_contig(p->dbl, MODE_INV, L, out, src, g, p->d_tw, st));
+  if (has_strided(p)) return strided_passes(p, -1, out, out, B, st);
+  return QW_OK;
+}
+
+}  // namespace qw
 
 extern "C" {
 
@@ -748,6 +814,8 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
       hipError_t e = hipMalloc(&p->d_partials, sizeof(double) * kObsFields * kObsBlocks);
       if (e == hipSuccess) e = hipMalloc(&p->d_result, sizeof(double) * 16);
       if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_result, sizeof(double) * 16, hipHostMallocDefault);
+      if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_stage, sizeof(StateInst), hipHostMallocDefault);
+      if (e == hipSuccess) e = hipMalloc((void**)&p->d_stage, sizeof(StateInst));
       // the host vectors above are released at scope end: wait for the uploads
       if (e == hipSuccess) e = hipStreamSynchronize(st);
       if (e != hipSuccess)
@@ -976,36 +1044,11 @@ qw_status qw_transform(qw_plan_t p, const void* in, void* out, int direction, vo
   if (r != QW_OK) return r;
   if (!in || !out) return fail(QW_ERR_INVALID, "field pointer is NULL");
   if (direction != 1 && direction != -1) return fail(QW_ERR_INVALID, "direction must be +1 or -1");
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t L = contig_len(p);
-  PassGeom g = pass_geom(p, L, 1);
   if (p->fourstep) {
     r = ensure_scratch(p, p->field_bytes);
     if (r != QW_OK) return r;
   }
-  if (direction > 0) {
-    if (has_strided(p)) {
-      r = strided_passes(p, +1, out, in, 1, st);
-      if (r != QW_OK) return r;
-      HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, out, out, g, p->d_tw, st));
-    } else {
-      HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, out, in, g, p->d_tw, st));
-    }
-    if (p->fourstep) {
-      // row k1, column k2 holds q index k1 + N1 k2: transpose to natural order.
-      HIP_TRY(launch_transpose(p->dbl, p->d_scratch, out, p->s, p->fs_N1, p->fs_N2, st));
-      HIP_TRY(hipMemcpyAsync(out, p->d_scratch, p->field_bytes, hipMemcpyDeviceToDevice, st));
-    }
-    return QW_OK;
-  }
-  const void* src = in;
-  if (p->fourstep) {
-    HIP_TRY(launch_transpose(p->dbl, p->d_scratch, in, p->s, p->fs_N2, p->fs_N1, st));
-    src = p->d_scratch;
-  }
-  HIP_TRY(launch_fft_contig(p->dbl, MODE_INV, L, out, src, g, p->d_tw, st));
-  if (has_strided(p)) return strided_passes(p, -1, out, out, 1, st);
-  return QW_OK;
+  return transform_impl(p, 1, in, out, direction, p->d_scratch, (hipStream_t)stream);
 }
 
 qw_status qw_observables(qw_plan_t p, const void* psi, const double* origin, const void* ref,
@@ -1014,45 +1057,17 @@ qw_status qw_observables(qw_plan_t p, const void* psi, const double* origin, con
   if (r != QW_OK) return r;
   if (!psi || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  ObsGeom g;
-  memset(&g, 0, sizeof g);
-  g.dim = p->dim;
-  g.s = p->s;
-  g.V = p->V;
-  for (int i = 0; i < 3; ++i) {
-    g.N[i] = p->N[i];
-    g.lg[i] = p->lg[i];
-    g.c[i] = i < p->dim ? origin[i] : 0.0;
-    if (i < p->dim && !isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+  ObsGeom g = obs_geom(p);
+  for (int i = 0; i < p->dim; ++i) {
+    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+    g.c[i] = origin[i];
   }
-  HIP_TRY(launch_observables(p->dbl, g, psi, ref, p->d_partials, p->d_result, st));
+  HIP_TRY(launch_observables(p->dbl, g, 1, psi, ref, nullptr, p->d_partials, p->d_result, st));
   HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const double* R = p->h_result;
-  memset(out, 0, sizeof *out);
-  out->norm2 = R[0];
-  const double inv = R[0] > 0.0 ? 1.0 / R[0] : 0.0;
-  for (int i = 0; i < p->dim; ++i) out->mean[i] = g.c[i] + R[1 + i] * inv;
-  static const int pr[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
-  for (int k = 0; k < 6; ++k)
-    if (pr[k][0] < p->dim && pr[k][1] < p->dim) out->second[k] = R[4 + k] * inv;
-  if (p->dim == 1) {
-    out->mean_cart[0] = out->mean[0];
-  } else if (p->dim == 2) {
-    out->mean_cart[0] = out->mean[0] + out->mean[1];
-    out->mean_cart[1] = out->mean[0] - out->mean[1];
-  } else {
-    const double a = out->mean[0], b = out->mean[1], c = out->mean[2];
-    out->mean_cart[0] = a + b - c;
-    out->mean_cart[1] = a - b + c;
-    out->mean_cart[2] = a - b - c;
-  }
-  if (ref) {
-    out->overlap_re = R[10];
-    out->overlap_im = R[11];
-    out->ref_norm2 = R[12];
-  }
+  finish_obs(p, p->h_result, origin, out);
+  if (!ref) out->overlap_re = out->overlap_im = out->ref_norm2 = 0.0;
   return QW_OK;
 }
 
@@ -1067,74 +1082,21 @@ qw_status qw_prepare_state(qw_plan_t p, void* psi, const double* k0, double sigm
   for (int i = 0; i < p->dim; ++i)
     if (!isfinite(k0[i]) || !isfinite(center[i])) return fail(QW_ERR_INVALID, "k0/center not finite");
   hipStream_t st = (hipStream_t)stream;
-  StateGeom g;
-  memset(&g, 0, sizeof g);
-  g.dim = p->dim;
-  g.s = p->s;
-  g.V = p->V;
-  for (int i = 0; i < 3; ++i) {
-    g.N[i] = p->N[i];
-    g.lg[i] = p->lg[i];
-    g.shift[i] = p->shift[i];
+  if (p->fourstep) {
+    r = ensure_scratch(p, p->field_bytes);
+    if (r != QW_OK) return r;
   }
-  g.m = p->m;
-  g.n = p->n;
-  g.sigma = sigma;
-  g.Nc = p->Nc;
-  g.cs = p->d_cs;
-  double kk[3] = {0, 0, 0}, q0[3];
-  for (int i = 0; i < p->dim; ++i) {
-    kk[i] = k0[i];
-    g.center[i] = center[i];
-  }
-  q_of_k(p->dim, kk, q0);
-  for (int i = 0; i < 3; ++i) g.q0[i] = q0[i];
-  // chi_s: normalised column of largest norm of P_s(q0) = (I + s M / sin(omega)) / 2.
-  zc M[4][4];
-  double cosw, sinw;
-  double kq0[3];
-  k_of_q(p->dim, q0, kq0);
-  dirac_M(p->dim, kq0, p->m, M, cosw, sinw);
-  const int s = p->s;
-  for (int sec = 0; sec < 2; ++sec) {
-    const double sg = sec == 0 ? 1.0 : -1.0;
-    zc P[4][4];
-    for (int a = 0; a < s; ++a)
-      for (int b = 0; b < s; ++b) {
-        const zc mh = sinw >= 1e-12 ? M[a][b] / sinw : zc(0.0);
-        P[a][b] = 0.5 * ((a == b ? 1.0 : 0.0) + sg * mh);
-      }
-    // Column norms of a projector come in exact pairs (P_jj = P_kk): take the
-    // lowest index within a relative 1e-12 of the largest norm.
-    double nrm[4] = {0.0, 0.0, 0.0, 0.0}, top = 0.0;
-    for (int b = 0; b < s; ++b) {
-      for (int a = 0; a < s; ++a) nrm[b] += std::norm(P[a][b]);
-      nrm[b] = sqrt(nrm[b]);
-      top = fmax(top, nrm[b]);
-    }
-    int best = 0;
-    while (best < s - 1 && !(nrm[best] >= top * (1.0 - 1e-12))) ++best;
-    const double bn = nrm[best];
-    double (*chi)[2] = sec == 0 ? g.chi_p : g.chi_m;
-    for (int a = 0; a < s; ++a) {
-      chi[a][0] = P[a][best].real() / bn;
-      chi[a][1] = P[a][best].imag() / bn;
-    }
-  }
-  HIP_TRY(launch_state_norms(g, p->d_partials, p->d_result, st));
+  *p->h_stage = make_state_inst(p, p->m, k0, sigma, center, c_plus, c_minus);
+  HIP_TRY(hipMemcpyAsync(p->d_stage, p->h_stage, sizeof(StateInst), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_state_prepare(p->dbl, state_geom(p), 1, p->d_stage, p->d_partials, p->d_result,
+                               psi, st));
   HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  r = transform_impl(p, 1, psi, psi, -1, p->d_scratch, st);
+  if (r != QW_OK) return r;
   HIP_TRY(hipStreamSynchronize(st));
   const double np = p->h_result[0], nm = p->h_result[1];
   if ((c_plus != 0.0 && !(np > 0.0)) || (c_minus != 0.0 && !(nm > 0.0)))
     return fail(QW_ERR_INVALID, "state has zero weight in a requested sector");
-  // Unnormalised inverse DFT multiplies the norm by V (Parseval): scale so |psi| = 1.
-  const double total = sqrt((double)p->V * (c_plus * c_plus + c_minus * c_minus));
-  g.coef_p = c_plus != 0.0 ? c_plus / sqrt(np) / total : 0.0;
-  g.coef_m = c_minus != 0.0 ? c_minus / sqrt(nm) / total : 0.0;
-  HIP_TRY(launch_state_fill(p->dbl, g, psi, st));
-  r = qw_transform(p, psi, psi, -1, stream);
-  if (r != QW_OK) return r;
-  HIP_TRY(hipStreamSynchronize(st));
   return QW_OK;
 }
 

@@ -95,6 +95,8 @@ hipError_t launch_transpose(bool dbl, void* out, const void* in, int64_t planes,
 hipError_t launch_step(bool dbl, const StencilGeom& g, void* out, const void* in,
                        const void* coef, hipStream_t st);
 
+// Reductions over B fields of one shape. Instance b's origin is
+// origins[3b..3b+2] if `origins` is given, else c[] (B = 1).
 struct ObsGeom {
   int dim;
   int s;
@@ -105,29 +107,35 @@ struct ObsGeom {
 };
 constexpr int kObsFields = 13;  // norm2, s1[3], s2[6], ov_re, ov_im, ref_norm2
 constexpr int kObsBlocks = 4096;
-hipError_t launch_observables(bool dbl, const ObsGeom& g, const void* psi, const void* ref,
-                              double* partials, double* result, hipStream_t st);
+// Workgroups per instance of the reduction (partials need B * this * 13 doubles).
+int64_t observables_blocks(const ObsGeom& g, int B);
+hipError_t launch_observables(bool dbl, const ObsGeom& g, int B, const void* psi, const void* ref,
+                              const double* origins, double* partials, double* result,
+                              hipStream_t st);
 
+// Particle states: shape, and the per-instance parameters (device array).
 struct StateGeom {
   int dim;
   int s;
   int64_t N[3];
   int lg[3];
   int64_t V;
-  double m, n;
-  double q0[3];
-  double center[3];
-  double sigma;
-  double chi_p[4][2];  // chi_+ (re, im)
-  double chi_m[4][2];  // chi_-
-  double coef_p, coef_m;  // c+/|a+|, c-/|a-| times the overall scale (fill pass)
   int Nc;
   int shift[3];
   const double* cs;
 };
-hipError_t launch_state_norms(const StateGeom& g, double* partials, double* result,
-                              hipStream_t st);
-hipError_t launch_state_fill(bool dbl, const StateGeom& g, void* out, hipStream_t st);
+struct StateInst {
+  double m, n, sigma, c_plus, c_minus;
+  double q0[3];
+  double center[3];
+  double chi_p[4][2];  // chi_+ (re, im)
+  double chi_m[4][2];  // chi_-
+};
+int64_t state_blocks(const StateGeom& g, int B);  // partials need B * this * 2 doubles
+// norms[2b], norms[2b+1]: squared norms of the two sector amplitudes of
+// instance b; the fill pass writes the normalised spectrum of every instance.
+hipError_t launch_state_prepare(bool dbl, const StateGeom& g, int B, const StateInst* inst,
+                                double* partials, double* norms, void* out, hipStream_t st);
 
 // Kernel-side helpers shared by the apply and the state preparation:
 // u_k and n~_k of the Weyl symbol at lattice frequency indices (j1, j2, j3),

@@ -27,18 +27,6 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NF], double* __
   }
 }
 
-template <int NF>
-__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partials, int nblk,
-                                                      double* __restrict__ result) {
-  double acc[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) acc[f] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 256)
-#pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] += partials[(int64_t)b * NF + f];
-  block_reduce_store<NF>(acc, result);
-}
-
 // Minimum image of n - c in [-N/2, N/2) for integer n, written with integer
 // arithmetic: c = ci + cf with ci = floor(c), cf in [0, 1); for cf = 0 the
 // image is ((n - ci + N/2) mod N) - N/2, otherwise
@@ -57,20 +45,26 @@ __device__ __forceinline__ double min_image(int64_t n, const AxisImage& a) {
 // Each thread takes UNR sites per round, all loads of a round issued before
 // any arithmetic; FP64 accumulation.
 template <typename T, int DIM, bool REF>
-__global__ __launch_bounds__(256) void k_observables(const cx<T>* __restrict__ psi,
-                                                     const cx<T>* __restrict__ ref, ObsGeom g,
-                                                     double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_observables(const cx<T>* __restrict__ psi_all,
+                                                     const cx<T>* __restrict__ ref_all, ObsGeom g,
+                                                     const double* __restrict__ origins,
+                                                     double* __restrict__ partials_all) {
   constexpr int S = DIM == 1 ? 2 : 4;
   constexpr int UNR = 4;
+  const int64_t inst = blockIdx.y;
+  const cx<T>* __restrict__ psi = psi_all + inst * S * g.V;
+  const cx<T>* __restrict__ ref = REF ? ref_all + inst * S * g.V : nullptr;
+  double* __restrict__ partials = partials_all + inst * (int64_t)gridDim.x * kObsFields;
   double acc[kObsFields];
 #pragma unroll
   for (int f = 0; f < kObsFields; ++f) acc[f] = 0.0;
   AxisImage ax[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const double fl = floor(g.c[i]);
+    const double ci = origins ? origins[3 * inst + i] : g.c[i];
+    const double fl = floor(ci);
     ax[i].ci = (int64_t)fl;
-    ax[i].cf = g.c[i] - fl;
+    ax[i].cf = ci - fl;
     ax[i].half = g.N[i] / 2;
     ax[i].mask = g.N[i] - 1;
   }
@@ -143,13 +137,38 @@ __global__ __launch_bounds__(256) void k_observables(const cx<T>* __restrict__ p
   block_reduce_store<kObsFields>(acc, partials + (int64_t)blockIdx.x * kObsFields);
 }
 
+// Per-instance final sums: block b adds the nblk partial vectors of instance b.
+template <int NF>
+__global__ __launch_bounds__(256) void k_reduce_final_b(const double* __restrict__ partials,
+                                                        int nblk, double* __restrict__ result) {
+  const int64_t b = blockIdx.x;
+  double acc[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = 0.0;
+  const double* p = partials + b * (int64_t)nblk * NF;
+  for (int k = threadIdx.x; k < nblk; k += 256)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] += p[(int64_t)k * NF + f];
+  block_reduce_store<NF>(acc, result + b * NF);
+}
+
+// The number of workgroups (and so the summation order) depends on the shape
+// only, never on the batch: an instance reduces identically alone or batched.
+int64_t observables_blocks(const ObsGeom& g, int B) {
+  (void)B;
+  int64_t nb = (g.V + 1023) / 1024;
+  if (nb > kObsBlocks) nb = kObsBlocks;
+  return nb < 1 ? 1 : nb;
+}
+
 template <typename T>
-static void launch_obs_t(const ObsGeom& g, const void* psi, const void* ref, double* partials,
-                         unsigned nb, hipStream_t st) {
+static void launch_obs_t(const ObsGeom& g, int B, const void* psi, const void* ref,
+                         const double* origins, double* partials, unsigned nb, hipStream_t st) {
   auto p = (const cx<T>*)psi;
   auto r = (const cx<T>*)ref;
+  const dim3 grid(nb, (unsigned)B);
 #define QW_OBS(D, R) \
-  hipLaunchKernelGGL((k_observables<T, D, R>), dim3(nb), dim3(256), 0, st, p, r, g, partials)
+  hipLaunchKernelGGL((k_observables<T, D, R>), grid, dim3(256), 0, st, p, r, g, origins, partials)
   if (g.dim == 1) {
     if (ref) QW_OBS(1, true); else QW_OBS(1, false);
   } else if (g.dim == 2) {
@@ -160,18 +179,18 @@ static void launch_obs_t(const ObsGeom& g, const void* psi, const void* ref, dou
 #undef QW_OBS
 }
 
-hipError_t launch_observables(bool dbl, const ObsGeom& g, const void* psi, const void* ref,
-                              double* partials, double* result, hipStream_t st) {
-  int64_t nb = (g.V + 1023) / 1024;
-  if (nb > kObsBlocks) nb = kObsBlocks;
+hipError_t launch_observables(bool dbl, const ObsGeom& g, int B, const void* psi, const void* ref,
+                              const double* origins, double* partials, double* result,
+                              hipStream_t st) {
+  const int64_t nb = observables_blocks(g, B);
   if (dbl)
-    launch_obs_t<double>(g, psi, ref, partials, (unsigned)nb, st);
+    launch_obs_t<double>(g, B, psi, ref, origins, partials, (unsigned)nb, st);
   else
-    launch_obs_t<float>(g, psi, ref, partials, (unsigned)nb, st);
+    launch_obs_t<float>(g, B, psi, ref, origins, partials, (unsigned)nb, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_final<kObsFields>, dim3(1), dim3(256), 0, st, partials, (int)nb,
-                     result);
+  hipLaunchKernelGGL(k_reduce_final_b<kObsFields>, dim3((unsigned)B), dim3(256), 0, st, partials,
+                     (int)nb, result);
   return hipGetLastError();
 }
 
@@ -180,10 +199,13 @@ hipError_t launch_observables(bool dbl, const ObsGeom& g, const void* psi, const
 //   a_s(q) = exp(-sigma^2 |dq|^2 / 2) e^{+i q.c} P_s(q) chi_s,
 //   P_s = (I + s M_q / sin(omega)) / 2  (I/2 where sin(omega) < 1e-12),
 // with M_q and sin(omega) as in the per-q evolution, dq_j = q_j - q'_j wrapped
-// to [-pi, pi).
+// to [-pi, pi). The squared norms of a_+ and a_- are reduced per instance,
+// then the fill pass writes c+ a+/|a+| + c- a-/|a-|, scaled so that the
+// unnormalised inverse DFT has unit norm (Parseval: |psi|^2 = V |hat psi|^2
+// and the two sectors are orthogonal at every q).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void state_amplitudes(const StateGeom& g, int64_t idx, double ap[4][2],
-                                                 double am[4][2]) {
+__device__ __forceinline__ void state_amplitudes(const StateGeom& g, const StateInst& si,
+                                                 int64_t idx, double ap[4][2], double am[4][2]) {
   int64_t j[3] = {0, 0, 0};
   int64_t rem = idx;
   for (int i = g.dim - 1; i >= 0; --i) {
@@ -194,12 +216,12 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, int64_t idx
   const double twopi = 2.0 * M_PI;
   for (int i = 0; i < g.dim; ++i) {
     const double q = twopi * (double)j[i] / (double)g.N[i];
-    double d = q - g.q0[i] + M_PI;
+    double d = q - si.q0[i] + M_PI;
     d = d - twopi * floor(d / twopi) - M_PI;
     e2 += d * d;
-    ph += q * g.center[i];
+    ph += q * si.center[i];
   }
-  const double amp = exp(-0.5 * g.sigma * g.sigma * e2);
+  const double amp = exp(-0.5 * si.sigma * si.sigma * e2);
   double sp, cp;
   sincos(ph, &sp, &cp);
   const double gr = amp * cp, gi = amp * sp;
@@ -207,7 +229,7 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, int64_t idx
   double u, n1, n2, n3;
   weyl_un(g.dim, g.cs, g.Nc, g.shift, j[0], j[1], j[2], u, n1, n2, n3);
   (void)u;
-  const double nn = g.n, m = g.m;
+  const double nn = si.n, m = si.m;
   const double sinw = sqrt(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
   const double inv = sinw >= 1e-12 ? 1.0 / sinw : 0.0;
   // Mh = M / sin(omega), applied to chi (complex) for both sectors.
@@ -221,8 +243,7 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, int64_t idx
       return;
     }
     const double a = nn * n3 * inv, b = nn * n1 * inv, e = nn * n2 * inv, gg = -m * inv;
-    // sigma.n~ = [[n3, n1 - i n2], [n1 + i n2, -n3]] scaled by n / sin(omega)
-    // upper: a c0 + (b - i e) c1 + gg c2 ; a c0.. with c complex
+    // upper: n sigma.n~ chi_u - m chi_l; lower: -m chi_u - n sigma.n~ chi_l, over sin(omega)
     const double* c0 = chi[0];
     const double* c1 = chi[1];
     const double* c2 = chi[2];
@@ -237,12 +258,12 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, int64_t idx
     out[3][1] = gg * c1[1] - (b * c2[1] + e * c2[0]) + a * c3[1];
   };
   double mp[4][2], mm[4][2];
-  apply_mh(g.chi_p, mp);
-  apply_mh(g.chi_m, mm);
+  apply_mh(si.chi_p, mp);
+  apply_mh(si.chi_m, mm);
   for (int c = 0; c < g.s; ++c) {
     // P_+ chi = (chi + Mh chi)/2, P_- chi = (chi - Mh chi)/2, times g(q).
-    const double pr = 0.5 * (g.chi_p[c][0] + mp[c][0]), pi = 0.5 * (g.chi_p[c][1] + mp[c][1]);
-    const double mr = 0.5 * (g.chi_m[c][0] - mm[c][0]), mi = 0.5 * (g.chi_m[c][1] - mm[c][1]);
+    const double pr = 0.5 * (si.chi_p[c][0] + mp[c][0]), pi = 0.5 * (si.chi_p[c][1] + mp[c][1]);
+    const double mr = 0.5 * (si.chi_m[c][0] - mm[c][0]), mi = 0.5 * (si.chi_m[c][1] - mm[c][1]);
     ap[c][0] = gr * pr - gi * pi;
     ap[c][1] = gr * pi + gi * pr;
     am[c][0] = gr * mr - gi * mi;
@@ -250,54 +271,72 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, int64_t idx
   }
 }
 
-__global__ __launch_bounds__(256) void k_state_norms(StateGeom g, double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_state_norms(StateGeom g, const StateInst* __restrict__ inst,
+                                                     double* __restrict__ partials) {
+  const int64_t b = blockIdx.y;
+  const StateInst si = inst[b];
   double acc[2] = {0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < g.V; idx += stride) {
     double ap[4][2], am[4][2];
-    state_amplitudes(g, idx, ap, am);
+    state_amplitudes(g, si, idx, ap, am);
     for (int c = 0; c < g.s; ++c) {
       acc[0] += ap[c][0] * ap[c][0] + ap[c][1] * ap[c][1];
       acc[1] += am[c][0] * am[c][0] + am[c][1] * am[c][1];
     }
   }
-  block_reduce_store<2>(acc, partials + (int64_t)blockIdx.x * 2);
+  block_reduce_store<2>(acc, partials + (b * gridDim.x + blockIdx.x) * 2);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_state_fill(StateGeom g, cx<T>* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_state_fill(StateGeom g, const StateInst* __restrict__ inst,
+                                                    const double* __restrict__ norms,
+                                                    cx<T>* __restrict__ out_all) {
+  const int64_t b = blockIdx.y;
+  const StateInst si = inst[b];
+  const double np = norms[2 * b], nm = norms[2 * b + 1];
+  const double total = sqrt((double)g.V * (si.c_plus * si.c_plus + si.c_minus * si.c_minus));
+  const double coef_p = (si.c_plus != 0.0 && np > 0.0) ? si.c_plus / sqrt(np) / total : 0.0;
+  const double coef_m = (si.c_minus != 0.0 && nm > 0.0) ? si.c_minus / sqrt(nm) / total : 0.0;
+  cx<T>* __restrict__ out = out_all + b * g.s * g.V;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < g.V; idx += stride) {
     double ap[4][2], am[4][2];
-    state_amplitudes(g, idx, ap, am);
+    state_amplitudes(g, si, idx, ap, am);
     for (int c = 0; c < g.s; ++c) {
-      const double re = g.coef_p * ap[c][0] + g.coef_m * am[c][0];
-      const double im = g.coef_p * ap[c][1] + g.coef_m * am[c][1];
+      const double re = coef_p * ap[c][0] + coef_m * am[c][0];
+      const double im = coef_p * ap[c][1] + coef_m * am[c][1];
       out[c * g.V + idx] = mk((T)re, (T)im);
     }
   }
 }
 
-hipError_t launch_state_norms(const StateGeom& g, double* partials, double* result,
-                              hipStream_t st) {
+int64_t state_blocks(const StateGeom& g, int B) {
+  (void)B;
   int64_t nb = (g.V + 255) / 256;
-  if (nb > kObsBlocks) nb = kObsBlocks;
-  hipLaunchKernelGGL(k_state_norms, dim3((unsigned)nb), dim3(256), 0, st, g, partials);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_final<2>, dim3(1), dim3(256), 0, st, partials, (int)nb, result);
-  return hipGetLastError();
+  if (nb > 1024) nb = 1024;
+  return nb < 1 ? 1 : nb;
 }
 
-hipError_t launch_state_fill(bool dbl, const StateGeom& g, void* out, hipStream_t st) {
-  int64_t nb = (g.V + 255) / 256;
-  if (nb > 65536) nb = 65536;
+hipError_t launch_state_prepare(bool dbl, const StateGeom& g, int B, const StateInst* inst,
+                                double* partials, double* norms, void* out, hipStream_t st) {
+  const int64_t nb = state_blocks(g, B);
+  hipLaunchKernelGGL(k_state_norms, dim3((unsigned)nb, (unsigned)B), dim3(256), 0, st, g, inst,
+                     partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final_b<2>, dim3((unsigned)B), dim3(256), 0, st, partials, (int)nb,
+                     norms);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t nf = (g.V + 255) / 256;
+  if (nf > 65536) nf = 65536;
   if (dbl)
-    hipLaunchKernelGGL(k_state_fill<double>, dim3((unsigned)nb), dim3(256), 0, st, g,
-                       (cx<double>*)out);
+    hipLaunchKernelGGL(k_state_fill<double>, dim3((unsigned)nf, (unsigned)B), dim3(256), 0, st, g,
+                       inst, norms, (cx<double>*)out);
   else
-    hipLaunchKernelGGL(k_state_fill<float>, dim3((unsigned)nb), dim3(256), 0, st, g,
-                       (cx<float>*)out);
+    hipLaunchKernelGGL(k_state_fill<float>, dim3((unsigned)nf, (unsigned)B), dim3(256), 0, st, g,
+                       inst, norms, (cx<float>*)out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,545 @@
+// Continuous-batching server for Fourier evolutions of particle states.
+//
+// Requests (dimension, lattice, mass, state, time, precision) are queued by
+// qw_server_submit. A worker thread admits them in arrival order while the
+// device memory they need fits the byte budget, groups admitted requests of
+// the same shape and precision into batches of up to max_batch, and runs
+// each batch on one of several streams: state preparation (Sec. 5.1,
+// Definition 1 and the Sec. 5.2 superposition), the Fourier evolution to each
+// request's own time with its own mass (Sec. 4), and the position / norm
+// reductions of Sec. 5.2 about the request's centre. Completion is signalled
+// from the stream itself (a host function after the result copy); memory is
+// returned to a pool and waiting requests are admitted at once, so requests
+// that arrive while others are on the device join as capacity frees up.
+// Every kernel treats the instances of a batch independently and the
+// reduction order depends only on the shape, so a request's result is the
+// same whether it ran alone or in a mix.
+#include <stdint.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "plan.h"
+
+using namespace qw;
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Key {
+  int dim;
+  int64_t N[3];
+  int dtype;
+  bool operator<(const Key& o) const {
+    return std::tie(dim, N[0], N[1], N[2], dtype) < std::tie(o.dim, o.N[0], o.N[1], o.N[2], o.dtype);
+  }
+};
+
+struct Pending {
+  int64_t ticket;
+  qw_request req;
+  double t_submit;
+  size_t footprint;
+  Key key;
+};
+
+// Pool of device / pinned blocks by power-of-two size class.
+struct Pool {
+  std::map<size_t, std::vector<void*>> dev_free, host_free;
+  std::vector<void*> dev_all, host_all;
+  static size_t cls(size_t b) {
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+  }
+  hipError_t get_dev(size_t b, void** out) {
+    const size_t c = cls(b);
+    auto& v = dev_free[c];
+    if (!v.empty()) {
+      *out = v.back();
+      v.pop_back();
+      return hipSuccess;
+    }
+    hipError_t e = hipMalloc(out, c);
+    if (e == hipSuccess) dev_all.push_back(*out);
+    return e;
+  }
+  hipError_t get_host(size_t b, void** out) {
+    const size_t c = cls(b);
+    auto& v = host_free[c];
+    if (!v.empty()) {
+      *out = v.back();
+      v.pop_back();
+      return hipSuccess;
+    }
+    hipError_t e = hipHostMalloc(out, c, hipHostMallocDefault);
+    if (e == hipSuccess) host_all.push_back(*out);
+    return e;
+  }
+  void put_dev(size_t b, void* p) { dev_free[cls(b)].push_back(p); }
+  void put_host(size_t b, void* p) { host_free[cls(b)].push_back(p); }
+  void release() {
+    for (void* p : dev_all) (void)hipFree(p);
+    for (void* p : host_all) (void)hipHostFree(p);
+    dev_all.clear();
+    host_all.clear();
+    dev_free.clear();
+    host_free.clear();
+  }
+};
+
+struct Batch;
+
+}  // namespace
+
+struct qw_server_s {
+  size_t budget = 0, used = 0, peak_used = 0;
+  int max_batch = 1;
+  int device = 0;
+  std::vector<hipStream_t> streams;
+  hipStream_t plan_stream = nullptr;  // plan set-up only
+  int next_stream = 0;
+  std::mutex mu;
+  std::condition_variable cv;       // worker wake-up
+  std::condition_variable cv_done;  // result waiters
+  std::deque<Pending> queue;
+  std::vector<Batch*> inflight;
+  std::vector<Batch*> finished;     // signalled by the stream, not yet retired
+  std::unordered_map<int64_t, qw_result> results;  // completed, not yet collected
+  std::unordered_set<int64_t> live;                // submitted, not yet collected
+  std::map<Key, qw_plan_t> plans;
+  Pool pool;
+  std::thread worker;
+  bool stop = false;
+  bool hold = false;      // admit nothing while set
+  int max_inflight = 2;   // batches on the device at once (per server)
+  int64_t next_ticket = 1;
+  int64_t submitted = 0, completed = 0, batches = 0, peak_inflight = 0;
+  std::string worker_error;
+};
+
+namespace {
+
+struct Batch {
+  qw_server_s* srv;
+  Key key;
+  qw_plan_t plan;
+  std::vector<Pending> reqs;
+  void* dmem = nullptr;
+  size_t dbytes = 0;
+  void* hmem = nullptr;
+  size_t hbytes = 0;
+  size_t footprint = 0;
+  hipStream_t st = nullptr;
+  double t_launch = 0.0, t_done = 0.0;
+  qw_status status = QW_OK;
+  // layout of hmem / dmem
+  size_t off_sinst, off_inst, off_orig, off_part, off_norm, off_res, off_field, off_scratch;
+  size_t h_sinst, h_inst, h_orig, h_res, h_norm;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t field_bytes_of(const qw_request& r) {
+  int64_t V = 1;
+  for (int i = 0; i < r.dim; ++i) V *= r.N[i];
+  const int s = r.dim == 1 ? 2 : 4;
+  return (size_t)V * s * (r.dtype == QW_C128 ? 16 : 8);
+}
+
+bool fourstep_of(const qw_request& r) { return r.dim == 1 && r.N[0] > 4096; }
+
+size_t request_footprint(const qw_request& r) {
+  const size_t fb = field_bytes_of(r);
+  return fb * (fourstep_of(r) ? 2 : 1) + 4096;
+}
+
+qw_status validate(const qw_request* r) {
+  if (!r) return fail(QW_ERR_INVALID, "request is NULL");
+  if (r->dim < 1 || r->dim > 3) return fail(QW_ERR_INVALID, "dim must be 1, 2 or 3");
+  if (r->dtype != QW_C64 && r->dtype != QW_C128) return fail(QW_ERR_INVALID, "unknown dtype");
+  const int64_t maxN = r->dim == 1 ? 65536 : (r->dim == 2 ? 1024 : 512);
+  for (int i = 0; i < r->dim; ++i) {
+    const int64_t n = r->N[i];
+    if (n < 2 || n > maxN || (n & (n - 1)))
+      return fail(QW_ERR_UNSUPPORTED, "N[%d] = %lld unsupported", i, (long long)n);
+    if (!isfinite(r->k0[i]) || !isfinite(r->center[i]))
+      return fail(QW_ERR_INVALID, "k0 / center not finite");
+  }
+  if (!(r->m >= 0.0 && r->m <= 1.0)) return fail(QW_ERR_INVALID, "m must lie in [0, 1]");
+  if (!(r->sigma > 0.0) || !isfinite(r->sigma)) return fail(QW_ERR_INVALID, "sigma must be > 0");
+  if (!isfinite(r->c_plus) || !isfinite(r->c_minus) || (r->c_plus == 0.0 && r->c_minus == 0.0))
+    return fail(QW_ERR_INVALID, "c_plus, c_minus must be finite and not both zero");
+  return QW_OK;
+}
+
+void on_stream_done(void* arg) {
+  Batch* b = (Batch*)arg;
+  qw_server_s* s = b->srv;
+  b->t_done = now_s();
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->finished.push_back(b);
+  s->cv.notify_all();
+}
+
+// Runs with the lock NOT held. Enqueues everything for one batch.
+qw_status launch_batch(qw_server_s* s, Batch* b) {
+  const int B = (int)b->reqs.size();
+  qw_plan_t p = b->plan;
+  const size_t fb = p->field_bytes;
+  const StateGeom sg = state_geom(p);
+  const ObsGeom og = obs_geom(p);
+  const int64_t nbs = state_blocks(sg, B), nbo = observables_blocks(og, B);
+  // device layout
+  size_t o = 0;
+  b->off_field = o;
+  o = align256(o + fb * B);
+  b->off_scratch = o;
+  if (p->fourstep) o = align256(o + fb * B);
+  b->off_sinst = o;
+  o = align256(o + sizeof(StateInst) * B);
+  b->off_inst = o;
+  o = align256(o + sizeof(InstParam) * B);
+  b->off_orig = o;
+  o = align256(o + sizeof(double) * 3 * B);
+  b->off_part = o;
+  o = align256(o + sizeof(double) * (size_t)B * std::max<int64_t>(nbs * 2, nbo * kObsFields));
+  b->off_norm = o;
+  o = align256(o + sizeof(double) * 2 * B);
+  b->off_res = o;
+  o = align256(o + sizeof(double) * kObsFields * B);
+  b->dbytes = o;
+  // host (pinned) layout
+  size_t h = 0;
+  b->h_sinst = h;
+  h = align256(h + sizeof(StateInst) * B);
+  b->h_inst = h;
+  h = align256(h + sizeof(InstParam) * B);
+  b->h_orig = h;
+  h = align256(h + sizeof(double) * 3 * B);
+  b->h_res = h;
+  h = align256(h + sizeof(double) * kObsFields * B);
+  b->h_norm = h;
+  h = align256(h + sizeof(double) * 2 * B);
+  b->hbytes = h;
+  HIP_TRY(s->pool.get_dev(b->dbytes, &b->dmem));
+  HIP_TRY(s->pool.get_host(b->hbytes, &b->hmem));
+  char* H = (char*)b->hmem;
+  char* D = (char*)b->dmem;
+  StateInst* hs = (StateInst*)(H + b->h_sinst);
+  InstParam* hi = (InstParam*)(H + b->h_inst);
+  double* ho = (double*)(H + b->h_orig);
+  for (int k = 0; k < B; ++k) {
+    const qw_request& r = b->reqs[k].req;
+    hs[k] = make_state_inst(p, r.m, r.k0, r.sigma, r.center, r.c_plus, r.c_minus);
+    hi[k].m = r.m;
+    hi[k].n = sqrt(1.0 - r.m * r.m);
+    hi[k].t = r.t;
+    for (int i = 0; i < 3; ++i) ho[3 * k + i] = i < r.dim ? r.center[i] : 0.0;
+  }
+  hipStream_t st = b->st;
+  // one upload of the three parameter arrays (contiguous in both layouts)
+  HIP_TRY(hipMemcpyAsync(D + b->off_sinst, H + b->h_sinst, b->h_res - b->h_sinst,
+                         hipMemcpyHostToDevice, st));
+  void* field = D + b->off_field;
+  void* scratch = p->fourstep ? (void*)(D + b->off_scratch) : nullptr;
+  double* part = (double*)(D + b->off_part);
+  HIP_TRY(launch_state_prepare(p->dbl, sg, B, (const StateInst*)(D + b->off_sinst), part,
+                               (double*)(D + b->off_norm), field, st));
+  qw_status r = transform_impl(p, B, field, field, -1, scratch, st);
+  if (r != QW_OK) return r;
+  InstParam dummy;
+  dummy.m = 0.0;
+  dummy.n = 1.0;
+  dummy.t = 0;
+  r = evolve_impl(p, B, field, field, (const InstParam*)(D + b->off_inst), dummy, st);
+  if (r != QW_OK) return r;
+  HIP_TRY(launch_observables(p->dbl, og, B, field, nullptr, (const double*)(D + b->off_orig), part,
+                             (double*)(D + b->off_res), st));
+  HIP_TRY(hipMemcpyAsync(H + b->h_res, D + b->off_res, sizeof(double) * kObsFields * B,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(H + b->h_norm, D + b->off_norm, sizeof(double) * 2 * B,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipLaunchHostFunc(st, on_stream_done, b));
+  return QW_OK;
+}
+
+void retire(qw_server_s* s, Batch* b) {  // lock held
+  const int B = (int)b->reqs.size();
+  const char* H = (const char*)b->hmem;
+  const double* R = (const double*)(H + b->h_res);
+  const double* NR = (const double*)(H + b->h_norm);
+  for (int k = 0; k < B; ++k) {
+    const Pending& pd = b->reqs[k];
+    qw_result res;
+    memset(&res, 0, sizeof res);
+    res.ticket = pd.ticket;
+    res.status = b->status;
+    res.batch_size = B;
+    res.queue_s = b->t_launch - pd.t_submit;
+    res.latency_s = b->t_done - pd.t_submit;
+    if (b->status == QW_OK) {
+      finish_obs(b->plan, R + (size_t)k * kObsFields, pd.req.center, &res.obs);
+      res.obs.overlap_re = res.obs.overlap_im = res.obs.ref_norm2 = 0.0;
+      res.sector_norm2[0] = NR[2 * k];
+      res.sector_norm2[1] = NR[2 * k + 1];
+      if ((pd.req.c_plus != 0.0 && !(NR[2 * k] > 0.0)) || (pd.req.c_minus != 0.0 && !(NR[2 * k + 1] > 0.0)))
+        res.status = QW_ERR_INVALID;
+    }
+    s->results[pd.ticket] = res;
+    ++s->completed;
+  }
+  if (b->dmem) s->pool.put_dev(b->dbytes, b->dmem);
+  if (b->hmem) s->pool.put_host(b->hbytes, b->hmem);
+  s->used -= b->footprint;
+  s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), b));
+  delete b;
+  s->cv_done.notify_all();
+}
+
+// Worker thread only, server lock NOT held: plan creation synchronises its
+// own stream, and a completion host function queued on a serving stream
+// takes the server lock, so no HIP call may be made while holding it.
+qw_plan_t make_plan(qw_server_s* s, const Key& k) {
+  qw_plan_t p = nullptr;
+  if (qw_plan(&p, k.dim, k.N, 0.0, (qw_dtype)k.dtype, s->plan_stream) != QW_OK) return nullptr;
+  return p;
+}
+
+void worker_main(qw_server_s* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    // retire batches whose stream has signalled
+    while (!s->finished.empty()) {
+      Batch* b = s->finished.back();
+      s->finished.pop_back();
+      retire(s, b);
+    }
+    if (s->stop && s->queue.empty() && s->inflight.empty()) break;
+    // admit in arrival order while the budget allows; group by shape
+    // A new batch opens only while fewer than max_inflight batches are on the
+    // device, so requests that arrive while it is busy gather into the next
+    // batches instead of going out one by one.
+    std::vector<Batch*> ready;
+    std::map<Key, Batch*> open;
+    while (!s->hold && !s->queue.empty()) {
+      Pending& pd = s->queue.front();
+      if (s->used + pd.footprint > s->budget) break;  // wait for memory (arrival order kept)
+      auto it = open.find(pd.key);
+      Batch* b;
+      if (it == open.end() || (int)it->second->reqs.size() >= s->max_batch) {
+        if ((int)(s->inflight.size() + ready.size()) >= s->max_inflight) break;
+        qw_plan_t p = nullptr;
+        auto pit = s->plans.find(pd.key);
+        if (pit != s->plans.end()) {
+          p = pit->second;
+        } else {
+          // Only this thread pops the queue, so pd stays at its front.
+          const Key key = pd.key;
+          lk.unlock();
+          p = make_plan(s, key);
+          lk.lock();
+          if (p) s->plans[key] = p;
+        }
+        if (!p) {
+          qw_result res;
+          memset(&res, 0, sizeof res);
+          res.ticket = pd.ticket;
+          res.status = QW_ERR_DEVICE;
+          s->results[pd.ticket] = res;
+          ++s->completed;
+          s->queue.pop_front();
+          s->cv_done.notify_all();
+          continue;
+        }
+        b = new Batch();
+        b->srv = s;
+        b->key = pd.key;
+        b->plan = p;
+        b->st = s->streams[s->next_stream];
+        s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
+        open[pd.key] = b;
+        ready.push_back(b);
+      } else {
+        b = it->second;
+      }
+      s->used += pd.footprint;
+      s->peak_used = std::max(s->peak_used, s->used);
+      b->footprint += pd.footprint;
+      b->reqs.push_back(pd);
+      s->queue.pop_front();
+    }
+    if (!ready.empty()) {
+      for (Batch* b : ready) s->inflight.push_back(b);
+      s->batches += (int64_t)ready.size();
+      s->peak_inflight = std::max<int64_t>(s->peak_inflight, (int64_t)s->inflight.size());
+      lk.unlock();
+      for (Batch* b : ready) {
+        b->t_launch = now_s();
+        b->status = launch_batch(s, b);
+        if (b->status != QW_OK) {
+          // the stream still runs whatever was enqueued; mark and signal when it drains
+          (void)hipStreamSynchronize(b->st);
+          on_stream_done(b);
+        }
+      }
+      lk.lock();
+      continue;
+    }
+    s->cv.wait(lk);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+qw_status qw_server_create(qw_server_t* out, size_t budget_bytes, int max_batch, int nstreams) {
+  if (!out) return fail(QW_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (budget_bytes < (1u << 20)) return fail(QW_ERR_INVALID, "budget must be at least 1 MiB");
+  if (max_batch < 1 || max_batch > 4096) return fail(QW_ERR_INVALID, "max_batch must lie in [1, 4096]");
+  if (nstreams < 1 || nstreams > 16) return fail(QW_ERR_INVALID, "nstreams must lie in [1, 16]");
+  qw_server_s* s = new (std::nothrow) qw_server_s();
+  if (!s) return fail(QW_ERR_NOMEM, "host allocation failed");
+  s->budget = budget_bytes;
+  s->max_batch = max_batch;
+  s->max_inflight = 2 * nstreams;
+  (void)hipGetDevice(&s->device);
+  for (int i = 0; i <= nstreams; ++i) {
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
+      delete s;
+      return fail(QW_ERR_DEVICE, "stream creation failed");
+    }
+    if (i == nstreams)
+      s->plan_stream = st;
+    else
+      s->streams.push_back(st);
+  }
+  s->worker = std::thread(worker_main, s);
+  *out = s;
+  return QW_OK;
+}
+
+qw_status qw_server_submit(qw_server_t s, const qw_request* req, int64_t* ticket) {
+  if (!s || !ticket) return fail(QW_ERR_INVALID, "NULL argument");
+  qw_status r = validate(req);
+  if (r != QW_OK) return r;
+  Pending pd;
+  pd.req = *req;
+  for (int i = req->dim; i < 3; ++i) {
+    pd.req.N[i] = 1;
+    pd.req.k0[i] = 0.0;
+    pd.req.center[i] = 0.0;
+  }
+  pd.footprint = request_footprint(pd.req);
+  if (pd.footprint > s->budget)
+    return fail(QW_ERR_NOMEM, "request needs %zu bytes, budget is %zu", pd.footprint, s->budget);
+  pd.key.dim = req->dim;
+  for (int i = 0; i < 3; ++i) pd.key.N[i] = pd.req.N[i];
+  pd.key.dtype = (int)req->dtype;
+  pd.t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(QW_ERR_INVALID, "server is shutting down");
+    pd.ticket = s->next_ticket++;
+    s->live.insert(pd.ticket);
+    ++s->submitted;
+    s->queue.push_back(pd);
+  }
+  s->cv.notify_all();
+  *ticket = pd.ticket;
+  return QW_OK;
+}
+
+qw_status qw_server_poll(qw_server_t s, int64_t ticket, qw_result* out, int* done) {
+  if (!s || !out || !done) return fail(QW_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!s->live.count(ticket)) return fail(QW_ERR_INVALID, "unknown or already collected ticket");
+  auto it = s->results.find(ticket);
+  if (it == s->results.end()) {
+    *done = 0;
+    return QW_OK;
+  }
+  *out = it->second;
+  *done = 1;
+  s->results.erase(it);
+  s->live.erase(ticket);
+  s->cv_done.notify_all();
+  return QW_OK;
+}
+
+qw_status qw_server_wait(qw_server_t s, int64_t ticket, qw_result* out) {
+  if (!s || !out) return fail(QW_ERR_INVALID, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (!s->live.count(ticket)) return fail(QW_ERR_INVALID, "unknown or already collected ticket");
+  s->cv_done.wait(lk, [&] { return s->results.count(ticket) > 0 || !s->live.count(ticket); });
+  if (!s->results.count(ticket)) return fail(QW_ERR_INVALID, "result collected by another caller");
+  *out = s->results[ticket];
+  s->results.erase(ticket);
+  s->live.erase(ticket);
+  s->cv_done.notify_all();
+  return QW_OK;
+}
+
+qw_status qw_server_hold(qw_server_t s, int hold) {
+  if (!s) return fail(QW_ERR_INVALID, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->hold = hold != 0;
+  }
+  s->cv.notify_all();
+  return QW_OK;
+}
+
+qw_status qw_server_stats(qw_server_t s, qw_server_info* out) {
+  if (!s || !out) return fail(QW_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->batches = s->batches;
+  out->queued = (int64_t)s->queue.size();
+  out->inflight_batches = (int64_t)s->inflight.size();
+  out->max_inflight_batches = s->peak_inflight;
+  out->used_bytes = (int64_t)s->used;
+  out->peak_used_bytes = (int64_t)s->peak_used;
+  return QW_OK;
+}
+
+qw_status qw_server_destroy(qw_server_t s) {
+  if (!s) return QW_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->hold = false;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  for (auto& kv : s->plans) qw_destroy(kv.second);
+  s->pool.release();
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  (void)hipStreamDestroy(s->plan_stream);
+  delete s;
+  return QW_OK;
+}
+
+}  // extern "C"

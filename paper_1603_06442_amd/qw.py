@@ -4,7 +4,8 @@ Every computation runs in the HIP library; PyTorch supplies device memory
 and the current stream. The names mirror the C ABI of include/qw.h:
 ``Plan`` wraps qw_plan / qw_destroy, and its methods call qw_step,
 qw_evolve_fft, qw_evolve_fft_batched, qw_transform, qw_observables and
-qw_prepare_state.
+qw_prepare_state. ``Server`` wraps the continuous-batching server
+(qw_server_create / submit / poll / wait / stats / destroy).
 
 Importing this module loads libqw.so and fails loudly if it is missing.
 """
@@ -21,7 +22,9 @@ QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_evolve_fft", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_prepare_state",
-           "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version")
+           "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
+           "qw_server_create", "qw_server_submit", "qw_server_poll", "qw_server_wait",
+           "qw_server_hold", "qw_server_stats", "qw_server_destroy")
 
 
 class QwError(RuntimeError):
@@ -35,6 +38,25 @@ class QwObs(ctypes.Structure):
                 ("second", ctypes.c_double * 6), ("mean_cart", ctypes.c_double * 3),
                 ("overlap_re", ctypes.c_double), ("overlap_im", ctypes.c_double),
                 ("ref_norm2", ctypes.c_double)]
+
+
+class QwRequest(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("N", ctypes.c_int64 * 3), ("m", ctypes.c_double),
+                ("dtype", ctypes.c_int), ("k0", ctypes.c_double * 3), ("sigma", ctypes.c_double),
+                ("center", ctypes.c_double * 3), ("c_plus", ctypes.c_double),
+                ("c_minus", ctypes.c_double), ("t", ctypes.c_int64)]
+
+
+class QwResult(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int), ("batch_size", ctypes.c_int),
+                ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double), ("obs", QwObs),
+                ("sector_norm2", ctypes.c_double * 2)]
+
+
+class QwServerInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted", "completed", "batches", "queued", "inflight_batches",
+        "max_inflight_batches", "used_bytes", "peak_used_bytes")]
 
 
 def _load():
@@ -58,6 +80,13 @@ def _load():
         "qw_get_schedule": [vp, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint),
                             ctypes.POINTER(cint)],
         "qw_autotune": [vp, vp, ctypes.POINTER(dbl)],
+        "qw_server_create": [ctypes.POINTER(vp), ctypes.c_size_t, cint, cint],
+        "qw_server_submit": [vp, ctypes.POINTER(QwRequest), ctypes.POINTER(i64)],
+        "qw_server_poll": [vp, i64, ctypes.POINTER(QwResult), ctypes.POINTER(cint)],
+        "qw_server_wait": [vp, i64, ctypes.POINTER(QwResult)],
+        "qw_server_hold": [vp, cint],
+        "qw_server_stats": [vp, ctypes.POINTER(QwServerInfo)],
+        "qw_server_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -229,3 +258,85 @@ class Plan:
 
 def version():
     return LIB.qw_version().decode()
+
+
+def _obs_dict(o, dim):
+    return {"norm2": o.norm2, "mean": list(o.mean)[:dim], "second": list(o.second),
+            "mean_cart": list(o.mean_cart)}
+
+
+class Server:
+    """Continuous-batching server (qw_server_*): requests are Gaussian
+    particle states evolved to their own time with their own mass; results
+    are the reductions of psi(t) about the request's centre."""
+
+    def __init__(self, budget_bytes, max_batch=16, nstreams=2):
+        self._h = ctypes.c_void_p()
+        _check(LIB.qw_server_create(ctypes.byref(self._h), int(budget_bytes), int(max_batch),
+                                    int(nstreams)))
+        self._dims = {}
+
+    def submit(self, dim, N, m, k0, sigma, center, c_plus, c_minus, t, dtype="c64"):
+        r = QwRequest()
+        r.dim = int(dim)
+        Ns = [int(N)] * r.dim if isinstance(N, int) else [int(x) for x in N]
+        if len(Ns) != r.dim:
+            raise ValueError("need %d lattice sizes" % r.dim)
+        for i in range(3):
+            r.N[i] = Ns[i] if i < r.dim else 1
+        r.m = float(m)
+        if dtype not in DTYPES:
+            raise ValueError("dtype must be 'c64' or 'c128'")
+        r.dtype = DTYPES[dtype][0]
+        k0 = [float(x) for x in k0]
+        center = [float(x) for x in center]
+        if len(k0) != r.dim or len(center) != r.dim:
+            raise ValueError("k0 and center need %d entries" % r.dim)
+        for i in range(r.dim):
+            r.k0[i] = k0[i]
+            r.center[i] = center[i]
+        r.sigma = float(sigma)
+        r.c_plus = float(c_plus)
+        r.c_minus = float(c_minus)
+        r.t = int(t)
+        tk = ctypes.c_int64()
+        _check(LIB.qw_server_submit(self._h, ctypes.byref(r), ctypes.byref(tk)))
+        self._dims[tk.value] = r.dim
+        return tk.value
+
+    def _convert(self, res):
+        dim = self._dims.get(res.ticket, 3)
+        return {"ticket": res.ticket, "status": res.status, "batch_size": res.batch_size,
+                "queue_s": res.queue_s, "latency_s": res.latency_s,
+                "obs": _obs_dict(res.obs, dim), "sector_norm2": list(res.sector_norm2)}
+
+    def poll(self, ticket):
+        res = QwResult()
+        done = ctypes.c_int()
+        _check(LIB.qw_server_poll(self._h, int(ticket), ctypes.byref(res), ctypes.byref(done)))
+        return self._convert(res) if done.value else None
+
+    def wait(self, ticket):
+        res = QwResult()
+        _check(LIB.qw_server_wait(self._h, int(ticket), ctypes.byref(res)))
+        return self._convert(res)
+
+    def hold(self, on=True):
+        """qw_server_hold: queue without launching (on) or resume (off)."""
+        _check(LIB.qw_server_hold(self._h, 1 if on else 0))
+
+    def stats(self):
+        info = QwServerInfo()
+        _check(LIB.qw_server_stats(self._h, ctypes.byref(info)))
+        return {n: getattr(info, n) for n, _ in QwServerInfo._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            LIB.qw_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,165 @@
+"""Serving tier through the C ABI (qw_server_*): results against the FP64
+oracle, bitwise independence of a request's result from what it was batched
+with, admission under the byte budget, and argument errors."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fourier, observables as ob, states, walk
+
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def qw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1603_06442_amd import qw as mod
+    return mod
+
+
+def req(d, N, m, k0, sigma, t, cp=1.0, cm=0.0, dtype="c64", center=None):
+    return dict(dim=d, N=N, m=m, k0=k0, sigma=sigma,
+                center=center if center is not None else [N // 2] * d,
+                c_plus=cp, c_minus=cm, t=t, dtype=dtype)
+
+
+def oracle_obs(r):
+    d, N = r["dim"], r["N"]
+    psi = states.particle_state(d, N, r["m"], r["k0"], r["sigma"], r["center"], r["c_plus"],
+                                r["c_minus"])
+    psit = fourier.evolve_fourier(psi, walk.stencil_table(d, r["m"]), r["t"])
+    return ob.observables(psit, r["center"])
+
+
+def run_all(server, reqs, hold=True):
+    if hold:
+        server.hold(True)
+    tickets = [server.submit(**r) for r in reqs]
+    if hold:
+        server.hold(False)
+    return [server.wait(tk) for tk in tickets]
+
+
+MIX = [
+    req(1, 1024, 0.1, [0.3], 10.0, 1000),
+    req(1, 8192, 0.05, [-0.2], 40.0, 12345, 0.6, 0.8),          # four-step length
+    req(2, 64, 0.2, [0.2, -0.1], 4.0, 77, 1 / math.sqrt(2), 1 / math.sqrt(2)),
+    req(3, 16, 0.3, [0.1, 0.1, 0.1], 2.5, -40),
+    req(3, 32, 0.1, [0.3, -0.2, 0.1], 3.0, 100000, 0.0, 1.0),
+    req(1, 1024, 0.0, [0.1], 20.0, 333),                         # massless
+    req(2, 64, 1.0, [0.0, 0.3], 6.0, 5),                         # m = 1: no hopping
+    req(3, 16, 0.05, [-0.3, 0.0, 0.2], 2.0, 999, 1 / math.sqrt(2), 1 / math.sqrt(2)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_server_results_match_oracle(qw, dtype):
+    reqs = [dict(r, dtype=dtype) for r in MIX]
+    srv = qw.Server(1 << 30, max_batch=4, nstreams=2)
+    try:
+        got = run_all(srv, reqs)
+    finally:
+        srv.close()
+    for r, g in zip(reqs, got):
+        assert g["status"] == qw.QW_OK
+        want = oracle_obs(r)
+        d = r["dim"]
+        rt = 2e-4 if dtype == "c64" else 1e-9
+        assert abs(g["obs"]["norm2"] - 1.0) < (5e-5 if dtype == "c64" else 1e-11)
+        assert np.allclose(g["obs"]["mean"], want["mean"][:d], rtol=0, atol=rt * r["N"]), r
+        assert np.allclose(g["obs"]["second"], want["second"], rtol=rt,
+                           atol=rt * r["N"] ** 2 * 1e-2), r
+        assert np.allclose(g["obs"]["mean_cart"], want["mean_cart"], rtol=0,
+                           atol=rt * r["N"] * 2), r
+
+
+def test_result_does_not_depend_on_the_batch_mix(qw):
+    rng = np.random.default_rng(1234)
+    reqs = []
+    for i in range(24):
+        d, N = [(3, 16), (3, 32), (1, 1024), (2, 64)][i % 4]
+        reqs.append(req(d, N, float(rng.uniform(0, 0.3)), list(rng.uniform(-0.3, 0.3, d)),
+                        float(rng.uniform(2.0, 4.0)), int(rng.integers(-5000, 5000)),
+                        dtype="c64" if i % 3 else "c128"))
+    alone_srv = qw.Server(1 << 30, max_batch=1, nstreams=1)
+    try:
+        alone = [run_all(alone_srv, [r], hold=False)[0] for r in reqs]
+    finally:
+        alone_srv.close()
+    mix_srv = qw.Server(1 << 30, max_batch=8, nstreams=3)
+    try:
+        mixed = run_all(mix_srv, reqs)
+        st = mix_srv.stats()
+    finally:
+        mix_srv.close()
+    assert max(m["batch_size"] for m in mixed) > 1
+    assert st["batches"] < len(reqs)
+    for a, m in zip(alone, mixed):
+        assert a["status"] == m["status"] == qw.QW_OK
+        assert a["batch_size"] == 1
+        assert a["obs"] == m["obs"]                    # bitwise
+        assert a["sector_norm2"] == m["sector_norm2"]
+
+
+def test_admission_respects_the_budget(qw):
+    # one 32^3 complex128 field is 2 MiB: a 3 MiB budget admits one at a time
+    srv = qw.Server(3 * MiB, max_batch=8, nstreams=2)
+    try:
+        reqs = [req(3, 32, 0.1, [0.1, 0.0, -0.1], 3.0, 10 * i + 1, dtype="c128") for i in range(6)]
+        got = run_all(srv, reqs)
+        st = srv.stats()
+        with pytest.raises(qw.QwError) as e:
+            srv.submit(**req(3, 64, 0.1, [0.1, 0.0, -0.1], 3.0, 5, dtype="c128"))
+        assert e.value.status == qw.QW_ERR_NOMEM
+    finally:
+        srv.close()
+    assert all(g["status"] == qw.QW_OK for g in got)
+    assert all(g["batch_size"] == 1 for g in got)
+    assert st["batches"] == 6 and st["completed"] == 6
+    assert 0 < st["peak_used_bytes"] <= 3 * MiB
+    assert st["used_bytes"] == 0 and st["queued"] == 0
+    # queued behind memory: later requests wait for earlier ones
+    lat = [g["latency_s"] for g in got]
+    assert lat[-1] >= lat[0]
+
+
+def test_requests_are_collected_once_and_bad_requests_rejected(qw):
+    srv = qw.Server(64 * MiB, max_batch=4, nstreams=1)
+    try:
+        tk = srv.submit(**req(1, 1024, 0.1, [0.3], 10.0, 100))
+        r = srv.wait(tk)
+        assert r["status"] == qw.QW_OK and r["ticket"] == tk
+        with pytest.raises(qw.QwError):
+            srv.wait(tk)
+        with pytest.raises(qw.QwError):
+            srv.poll(tk + 100)
+        bad = [
+            (dict(N=48), qw.QW_ERR_UNSUPPORTED),
+            (dict(sigma=0.0), qw.QW_ERR_INVALID),
+            (dict(c_plus=0.0, c_minus=0.0), qw.QW_ERR_INVALID),
+            (dict(m=1.5), qw.QW_ERR_INVALID),
+        ]
+        for change, status in bad:
+            r = dict(req(1, 1024, 0.1, [0.3], 10.0, 100), **change)
+            if "N" in change:
+                r["center"] = [24]
+            with pytest.raises(qw.QwError) as e:
+                srv.submit(**r)
+            assert e.value.status == status, change
+        # a poll loop sees the request complete
+        tk = srv.submit(**req(2, 64, 0.1, [0.1, 0.1], 5.0, 50))
+        res = None
+        for _ in range(100000):
+            res = srv.poll(tk)
+            if res is not None:
+                break
+        if res is None:
+            res = srv.wait(tk)
+        assert res["status"] == qw.QW_OK
+    finally:
+        srv.close()

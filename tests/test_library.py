@@ -75,3 +75,17 @@ def test_calls_reject_null_plan():
     assert qw.LIB.qw_step(None, ctypes.c_void_p(1), 1, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_evolve_fft(None, None, None, 1, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_destroy(None) == qw.QW_OK
+
+
+def test_server_rejects_bad_arguments_on_the_host():
+    import ctypes
+    from paper_1603_06442_amd import qw
+    h = ctypes.c_void_p()
+    for budget, mb, ns in [(1000, 4, 1), (1 << 30, 0, 1), (1 << 30, 4, 0), (1 << 30, 5000, 1),
+                           (1 << 30, 4, 17)]:
+        assert qw.LIB.qw_server_create(ctypes.byref(h), budget, mb, ns) == qw.QW_ERR_INVALID
+        assert h.value is None
+    tk = ctypes.c_int64()
+    assert qw.LIB.qw_server_submit(None, None, ctypes.byref(tk)) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_server_hold(None, 1) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_server_destroy(None) == qw.QW_OK
