@@ -9,7 +9,8 @@
 //   inverse FFT along the axis (sign -).
 // The forward transform leaves each thread holding the spectrum at the same
 // positions the inverse starts from, so the apply needs no data exchange.
-// MODE_FWD / MODE_INV do only the forward / inverse transform.
+// MODE_FWD / MODE_INV do only the forward / inverse transform; MODE_APPLY_INV
+// skips the forward transform (its input is already a spectrum).
 //
 // Per-q symbol (Sec. 3.1, 3.2): u, n~ of the Weyl walk at the Cartesian k of
 // the lattice frequency q (3D: k = ((q1+q2)/2, (q1+q3)/2, -(q2+q3)/2); 2D:
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
     const int64_t pen = g.pen0 + (gpc - b * g.ppi);
     const int64_t base = b * S * g.V + pen * L;
 
-    if constexpr (MODE != MODE_INV) {
+    if constexpr (MODE != MODE_INV && MODE != MODE_APPLY_INV) {
       if (DIM == 1 && g.fourstep) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -329,7 +330,8 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
           v[c][E - 1] = y[c];
         }
       }
-    } else if constexpr (MODE == MODE_EVOLVE || MODE == MODE_EVOLVE_TAB) {
+    } else if constexpr (MODE == MODE_EVOLVE || MODE == MODE_EVOLVE_TAB ||
+                         MODE == MODE_APPLY_INV) {
       const InstParam ip = g.inst ? g.inst[b] : g.single;
       // One wave-vector per iteration, deliberately not unrolled (an unrolled
       // loop lets the compiler hoist every element's table reads and keep
@@ -480,15 +482,22 @@ static hipError_t dispatch_dim(int64_t L, cx<T>* out, const cx<T>* in, const Pas
 template <typename T>
 static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in,
                                 const PassGeom& g, const cx<T>* tw, hipStream_t st, int E) {
-  // Four elements per thread only for the evolution modes of d = 2, 3 (the
-  // autotuner's alternative); everything else uses eight.
+  // Four elements per thread for the table evolution of d = 2, 3 when the
+  // autotuner picks it. The per-instance modes evaluate omega(q) in FP64 in
+  // the kernel and run out of registers with eight (scratch spills), so they
+  // take four wherever the team fits a workgroup (L <= 2048), except the
+  // complex64 line, which fits eight.
   const bool e4 = E == 4 && g.dim >= 2;
+  const bool e4i = L <= 2048 && (g.dim >= 2 || sizeof(T) == 8);
   switch (mode) {
     case MODE_EVOLVE:
-      return e4 ? dispatch_dim<T, MODE_EVOLVE, 4>(L, out, in, g, tw, st)
-                : dispatch_dim<T, MODE_EVOLVE, 8>(L, out, in, g, tw, st);
+      return e4i ? dispatch_dim<T, MODE_EVOLVE, 4>(L, out, in, g, tw, st)
+                 : dispatch_dim<T, MODE_EVOLVE, 8>(L, out, in, g, tw, st);
     case MODE_FWD: return dispatch_dim<T, MODE_FWD, 8>(L, out, in, g, tw, st);
     case MODE_INV: return dispatch_dim<T, MODE_INV, 8>(L, out, in, g, tw, st);
+    case MODE_APPLY_INV:
+      return e4i ? dispatch_dim<T, MODE_APPLY_INV, 4>(L, out, in, g, tw, st)
+                 : dispatch_dim<T, MODE_APPLY_INV, 8>(L, out, in, g, tw, st);
     case MODE_EVOLVE_TAB:
       return e4 ? dispatch_dim<T, MODE_EVOLVE_TAB, 4>(L, out, in, g, tw, st)
                 : dispatch_dim<T, MODE_EVOLVE_TAB, 8>(L, out, in, g, tw, st);

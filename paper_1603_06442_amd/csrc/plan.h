@@ -105,6 +105,10 @@ qw_status ensure_scratch(qw_plan_t p, size_t bytes);
 // (m, n, t), or nullptr to use `single` (B = 1, the plan's mass, omega table).
 qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstParam* dinst,
                       const InstParam& single, hipStream_t st);
+// psi_t = T^-1 [D_q^t a(q)] in place for B spectra in storage order, device
+// per-instance (m, n, t); QW_ERR_UNSUPPORTED for the 1D four-step.
+qw_status evolve_spectrum_impl(qw_plan_t p, int B, void* data, const InstParam* dinst,
+                               hipStream_t st);
 // Unnormalised DFT of B instances (direction +1 / -1); `scratch` holds B
 // fields for the 1D four-step transposes (unused otherwise; may be null then).
 qw_status transform_impl(qw_plan_t p, int B, const void* in, void* out, int direction,

@@ -559,6 +559,25 @@ qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstP
   return QW_OK;
 }
 
+// psi_t = T^-1 [D_q^t a(q)] for B spectra a already in storage order (a
+// state prepared in momentum space), in place: the fused pass applies the
+// per-instance symbol power and inverts the contiguous axis, then the
+// strided inverse passes. Not for the 1D four-step (transposed spectrum).
+qw_status evolve_spectrum_impl(qw_plan_t p, int B, void* data, const InstParam* dinst,
+                               hipStream_t st) {
+  if (p->fourstep) return fail(QW_ERR_UNSUPPORTED, "four-step spectrum layout");
+  const int64_t L = contig_len(p);
+  PassGeom g = pass_geom(p, L, B);
+  g.inst = dinst;
+  g.single.m = p->m;
+  g.single.n = p->n;
+  g.single.t = 0;
+  g.inv_scale = 1.0;  // the spectrum is that of the unnormalised inverse
+  HIP_TRY(launch_fft_contig(p->dbl, MODE_APPLY_INV, L, data, data, g, p->d_tw, st, 8));
+  if (has_strided(p)) return strided_passes(p, -1, data, data, B, st);
+  return QW_OK;
+}
+
 }  // namespace qw
 
 namespace qw {

@@ -45,7 +45,9 @@ struct PassGeom {
 
 // MODE_EVOLVE evaluates omega(q) per wave-vector (any per-instance mass);
 // MODE_EVOLVE_TAB reads it from the plan's FP64 table (the plan's mass).
-enum { MODE_EVOLVE = 0, MODE_FWD = 1, MODE_INV = 2, MODE_EVOLVE_TAB = 3 };
+// MODE_APPLY_INV starts from a spectrum already in storage order (a state
+// prepared in momentum space): per-instance apply, then the inverse only.
+enum { MODE_EVOLVE = 0, MODE_FWD = 1, MODE_INV = 2, MODE_EVOLVE_TAB = 3, MODE_APPLY_INV = 4 };
 
 // ---------------------------------------------------------------------------
 // Stencil coefficients, in the kernel's precision. Offsets per dimension:

@@ -260,13 +260,23 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
   double* part = (double*)(D + b->off_part);
   HIP_TRY(launch_state_prepare(p->dbl, sg, B, (const StateInst*)(D + b->off_sinst), part,
                                (double*)(D + b->off_norm), field, st));
-  qw_status r = transform_impl(p, B, field, field, -1, scratch, st);
-  if (r != QW_OK) return r;
-  InstParam dummy;
-  dummy.m = 0.0;
-  dummy.n = 1.0;
-  dummy.t = 0;
-  r = evolve_impl(p, B, field, field, (const InstParam*)(D + b->off_inst), dummy, st);
+  // The state is prepared as its spectrum: apply D_q^t there and invert once.
+  // The 1D four-step keeps its transposed spectrum internal, so it goes to
+  // position space and through the full evolution.
+  const InstParam* dinst = (const InstParam*)(D + b->off_inst);
+  qw_status r;
+  if (!p->fourstep) {
+    r = evolve_spectrum_impl(p, B, field, dinst, st);
+  } else {
+    r = transform_impl(p, B, field, field, -1, scratch, st);
+    if (r == QW_OK) {
+      InstParam unused;
+      unused.m = 0.0;
+      unused.n = 1.0;
+      unused.t = 0;
+      r = evolve_impl(p, B, field, field, dinst, unused, st);
+    }
+  }
   if (r != QW_OK) return r;
   HIP_TRY(launch_observables(p->dbl, og, B, field, nullptr, (const double*)(D + b->off_orig), part,
                              (double*)(D + b->off_res), st));
@@ -331,58 +341,61 @@ void worker_main(qw_server_s* s) {
       retire(s, b);
     }
     if (s->stop && s->queue.empty() && s->inflight.empty()) break;
-    // admit in arrival order while the budget allows; group by shape
-    // A new batch opens only while fewer than max_inflight batches are on the
-    // device, so requests that arrive while it is busy gather into the next
-    // batches instead of going out one by one.
+    // Batches are formed while fewer than max_inflight are on the device, so
+    // requests that arrive while it is busy gather into the next batches. The
+    // oldest queued request always opens the next batch (no starvation); the
+    // batch then takes the later queued requests of the same shape, in
+    // arrival order, while they fit the budget.
     std::vector<Batch*> ready;
-    std::map<Key, Batch*> open;
-    while (!s->hold && !s->queue.empty()) {
-      Pending& pd = s->queue.front();
-      if (s->used + pd.footprint > s->budget) break;  // wait for memory (arrival order kept)
-      auto it = open.find(pd.key);
-      Batch* b;
-      if (it == open.end() || (int)it->second->reqs.size() >= s->max_batch) {
-        if ((int)(s->inflight.size() + ready.size()) >= s->max_inflight) break;
-        qw_plan_t p = nullptr;
-        auto pit = s->plans.find(pd.key);
-        if (pit != s->plans.end()) {
-          p = pit->second;
-        } else {
-          // Only this thread pops the queue, so pd stays at its front.
-          const Key key = pd.key;
-          lk.unlock();
-          p = make_plan(s, key);
-          lk.lock();
-          if (p) s->plans[key] = p;
-        }
-        if (!p) {
-          qw_result res;
-          memset(&res, 0, sizeof res);
-          res.ticket = pd.ticket;
-          res.status = QW_ERR_DEVICE;
-          s->results[pd.ticket] = res;
-          ++s->completed;
-          s->queue.pop_front();
-          s->cv_done.notify_all();
-          continue;
-        }
-        b = new Batch();
-        b->srv = s;
-        b->key = pd.key;
-        b->plan = p;
-        b->st = s->streams[s->next_stream];
-        s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
-        open[pd.key] = b;
-        ready.push_back(b);
+    while (!s->hold && !s->queue.empty() &&
+           (int)(s->inflight.size() + ready.size()) < s->max_inflight) {
+      Pending& head = s->queue.front();
+      if (s->used + head.footprint > s->budget) break;  // wait for memory
+      const Key key = head.key;
+      qw_plan_t p = nullptr;
+      auto pit = s->plans.find(key);
+      if (pit != s->plans.end()) {
+        p = pit->second;
       } else {
-        b = it->second;
+        // Only this thread removes from the queue, so head stays in front.
+        lk.unlock();
+        p = make_plan(s, key);
+        lk.lock();
+        if (p) s->plans[key] = p;
       }
-      s->used += pd.footprint;
+      if (!p) {
+        Pending& pd = s->queue.front();
+        qw_result res;
+        memset(&res, 0, sizeof res);
+        res.ticket = pd.ticket;
+        res.status = QW_ERR_DEVICE;
+        s->results[pd.ticket] = res;
+        ++s->completed;
+        s->queue.pop_front();
+        s->cv_done.notify_all();
+        continue;
+      }
+      Batch* b = new Batch();
+      b->srv = s;
+      b->key = key;
+      b->plan = p;
+      b->st = s->streams[s->next_stream];
+      s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
+      for (auto it = s->queue.begin();
+           it != s->queue.end() && (int)b->reqs.size() < s->max_batch;) {
+        if (it->key.dim == key.dim && it->key.N[0] == key.N[0] && it->key.N[1] == key.N[1] &&
+            it->key.N[2] == key.N[2] && it->key.dtype == key.dtype &&
+            s->used + it->footprint <= s->budget) {
+          s->used += it->footprint;
+          b->footprint += it->footprint;
+          b->reqs.push_back(*it);
+          it = s->queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
       s->peak_used = std::max(s->peak_used, s->used);
-      b->footprint += pd.footprint;
-      b->reqs.push_back(pd);
-      s->queue.pop_front();
+      ready.push_back(b);
     }
     if (!ready.empty()) {
       for (Batch* b : ready) s->inflight.push_back(b);
