@@ -7,8 +7,8 @@ phase), m = 0.02, an equal-weight particle/antiparticle Gaussian state at
 k0 = (0.1, 0.1, 0.1) with width 20 cells, prepared on the GPU. One timed
 step is one pass over the whole hot path:
   * one Fourier jump psi_t = U^t psi_0 (t cycling through the 64 times
-    log-spaced in [1, 1e5]),
-  * the position/norm reduction of psi_t (the Zitterbewegung observable),
+    log-spaced in [1, 1e5]) with the position/norm reduction of psi_t (the
+    Zitterbewegung observable) taken inside its last inverse pass,
   * two position-space steps of a second field.
 `value` is steps per second, i.e. Fourier evolutions per second with the
 reduction and the two stencil steps included in each. The JSON line also
@@ -217,8 +217,7 @@ def main():
     field_bytes = psi0.numel() * psi0.element_size()
 
     def step(i):
-        plan.evolve_fft(psi0, times[i % len(times)], out=psit)
-        o = plan.observables(psit, w["center"])
+        o = plan.evolve_fft_observables(psi0, times[i % len(times)], w["center"], out=psit)
         plan.step(psis, 2)
         return o
 

@@ -117,6 +117,17 @@ qw_status qw_transform(qw_plan_t plan, const void* in, void* out, int direction,
 qw_status qw_observables(qw_plan_t plan, const void* psi, const double* origin, const void* ref,
                          qw_obs* out, void* stream);
 
+/* psi_t = U^t psi0 (as qw_evolve_fft) and the reductions of psi_t about
+ * origin (as qw_observables with ref = NULL; overlap fields zero), in one
+ * pass less: where the Fourier schedule ends with a strided inverse pass
+ * (d = 2, 3 and the 1D four-step) the reductions are taken inside it, so
+ * psi_t is not read back. psi_t: DEVICE field, may equal psi0, or NULL when
+ * only the reductions are wanted (psi_t is then not written; the plan's
+ * scratch field holds the intermediate passes). origin: dim HOST doubles;
+ * out: HOST. Waits for the result. */
+qw_status qw_evolve_fft_observables(qw_plan_t plan, const void* psi0, void* psi_t, int64_t t,
+                                    const double* origin, qw_obs* out, void* stream);
+
 /* Write a Gaussian particle/antiparticle state into psi (Sec. 5.1,
  * Definition 1; Sec. 5.2, superposition c+ psi+ + c- psi-):
  *   hat psi(q) = c+ a+(q)/|a+| + c- a-(q)/|a-|,

@@ -122,6 +122,155 @@ hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const vo
   return launch_fft_strided_slab(dbl, sign, L, out, in, 1, O, 0, 0, I, tw, st);
 }
 
+// Last inverse pass of an evolution with the Sec. 5.2 reductions fused: the
+// transformed values are reduced where they are produced (the field need
+// not be read again, nor written at all when only the reductions are
+// wanted). Whole fields: outer index o = b * s + component.
+template <typename T, int L, int E>
+__global__ __launch_bounds__(1024) void k_fft_strided_obs(cx<T>* __restrict__ out,
+                                                          const cx<T>* __restrict__ in, int64_t I,
+                                                          int lgP, int64_t nblk_i, int s,
+                                                          ObsFuse f,
+                                                          const cx<T>* __restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int TT = L / E;
+  const int P = 1 << lgP;
+  const int tid = threadIdx.x;
+  const int p = tid & (P - 1);
+  const int t = tid >> lgP;
+  const int64_t blk = blockIdx.x;
+  const int64_t o = blk / nblk_i;
+  const int64_t col = ((blk - o * nblk_i) << lgP) + p;
+  const int64_t base = o * (int64_t)L * I + col;
+  cx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = in[base + (int64_t)(t + TT * e) * I];
+  fft_team<T, L, E, -1>(v, lds + p, P, t, tw);
+  if (f.store) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) out[base + (int64_t)(t + TT * e) * I] = v[e];
+  }
+  const int64_t b = o / s;
+  double org[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) org[a] = f.origins ? f.origins[3 * b + a] : f.c[a];
+  const AxisImage a0 = axis_image(org[0], f.N[0]);
+  // Along the pass only the axis-0 displacement varies: accumulate the
+  // zeroth, first and second moments in it, the other axes are per column.
+  double S0 = 0.0, S1 = 0.0, S11 = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int64_t pos = t + TT * e;
+    const double w = min_image(f.dim == 1 ? pos * I + col : pos, a0);
+    const double x = (double)v[e].x, y = (double)v[e].y;
+    const double pr = x * x + y * y;
+    const double wp = w * pr;
+    S0 += pr;
+    S1 += wp;
+    S11 += w * wp;
+  }
+  double wb = 0.0, wc = 0.0;
+  if (f.dim == 2) {
+    wb = min_image(col, axis_image(org[1], f.N[1]));
+  } else if (f.dim == 3) {
+    wb = min_image(col >> f.lg[2], axis_image(org[1], f.N[1]));
+    wc = min_image(col & (f.N[2] - 1), axis_image(org[2], f.N[2]));
+  }
+  double acc[kObsFields] = {S0,      S1,      wb * S0, wc * S0,      S11, wb * wb * S0, wc * wc * S0,
+                            wb * S1, wc * S1, wb * wc * S0, 0.0, 0.0, 0.0};
+  block_reduce_store<kObsFields>(acc, f.partials + blk * kObsFields);
+}
+
+// Columns per workgroup of a strided pass (the same choice as run_strided).
+template <typename T, int L>
+static int strided_cols(int64_t I) {
+  constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
+  constexpr int E = L < Emax ? L : Emax;
+  constexpr int TT = L / E;
+  const int Pmin = sizeof(T) == 8 ? 8 : 16;
+  int P = 256 / TT;
+  if (P < Pmin) P = Pmin;
+  if (P > I) P = (int)I;
+  return P;
+}
+
+template <typename T, int L>
+static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int64_t I,
+                                  const ObsFuse& f, const cx<T>* tw, hipStream_t st) {
+  constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
+  constexpr int E = L < Emax ? L : Emax;
+  constexpr int TT = L / E;
+  const int P = strided_cols<T, L>(I);
+  if (TT * P > 1024 || (TT * P) % 64 != 0) return hipErrorInvalidValue;
+  const int lgP = ilog2(P);
+  const size_t lds = (size_t)P * L * sizeof(cx<T>);
+  auto kern = k_fft_strided_obs<T, L, E>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t nblk_i = I / P;
+  const int64_t nblk = (int64_t)s * B * nblk_i;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(TT * P), lds, st, out, in, I, lgP, nblk_i, s,
+                     f, tw);
+  return hipGetLastError();
+}
+
+template <typename T>
+static int64_t obs_blocks_t(int64_t L, int64_t I) {
+  int P = 0, TT = 0;
+  switch (L) {
+#define QW_CASE(LL)                                           \
+  case LL: {                                                  \
+    constexpr int Emax = sizeof(T) == 8 ? 8 : 16;             \
+    TT = LL / (LL < Emax ? LL : Emax);                        \
+    P = strided_cols<T, LL>(I);                               \
+    break;                                                    \
+  }
+    QW_CASE(2) QW_CASE(4) QW_CASE(8) QW_CASE(16) QW_CASE(32) QW_CASE(64) QW_CASE(128)
+    QW_CASE(256) QW_CASE(512) QW_CASE(1024)
+#undef QW_CASE
+    default: return 0;
+  }
+  if (TT * P > 1024 || (TT * P) % 64 != 0) return 0;
+  return I / P;
+}
+
+int64_t strided_obs_blocks(bool dbl, int64_t L, int64_t I) {
+  return dbl ? obs_blocks_t<double>(L, I) : obs_blocks_t<float>(L, I);
+}
+
+template <typename T>
+static hipError_t dispatch_strided_obs(int64_t L, cx<T>* out, const cx<T>* in, int s, int B,
+                                       int64_t I, const ObsFuse& f, const cx<T>* tw,
+                                       hipStream_t st) {
+  switch (L) {
+    case 2: return run_strided_obs<T, 2>(out, in, s, B, I, f, tw, st);
+    case 4: return run_strided_obs<T, 4>(out, in, s, B, I, f, tw, st);
+    case 8: return run_strided_obs<T, 8>(out, in, s, B, I, f, tw, st);
+    case 16: return run_strided_obs<T, 16>(out, in, s, B, I, f, tw, st);
+    case 32: return run_strided_obs<T, 32>(out, in, s, B, I, f, tw, st);
+    case 64: return run_strided_obs<T, 64>(out, in, s, B, I, f, tw, st);
+    case 128: return run_strided_obs<T, 128>(out, in, s, B, I, f, tw, st);
+    case 256: return run_strided_obs<T, 256>(out, in, s, B, I, f, tw, st);
+    case 512: return run_strided_obs<T, 512>(out, in, s, B, I, f, tw, st);
+    case 1024: return run_strided_obs<T, 1024>(out, in, s, B, I, f, tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fft_strided_obs(bool dbl, int64_t L, void* out, const void* in, int s, int B,
+                                  int64_t I, const ObsFuse& f, const void* tw, hipStream_t st) {
+  if (dbl)
+    return dispatch_strided_obs<double>(L, (cx<double>*)out, (const cx<double>*)in, s, B, I, f,
+                                        (const cx<double>*)tw, st);
+  return dispatch_strided_obs<float>(L, (cx<float>*)out, (const cx<float>*)in, s, B, I, f,
+                                     (const cx<float>*)tw, st);
+}
+
 // out[p][c][r] = in[p][r][c] for planes p of an R x C matrix (32 x 32 tiles).
 template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(cx<T>* __restrict__ out,

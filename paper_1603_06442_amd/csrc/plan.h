@@ -60,7 +60,8 @@ struct qw_plan_s {
   void* d_tw4 = nullptr;    // exp(-2 pi i j / N) for the 1D four-step, field precision
   double* d_cs = nullptr;   // (cos, sin)(pi j / Nc), j < 2 Nc
   float* d_csf = nullptr;   // the same, FP32
-  double* d_partials = nullptr;
+  double* d_partials = nullptr;  // partial sums of the reductions (partials_len doubles)
+  int64_t partials_len = 0;
   double* d_result = nullptr;
   double* h_result = nullptr;  // pinned
   void* d_scratch = nullptr;
@@ -103,12 +104,19 @@ qw_status check_plan(qw_plan_t p);
 qw_status ensure_scratch(qw_plan_t p, size_t bytes);
 // psi_out = U^t psi_in for B instances back to back; dinst: device per-instance
 // (m, n, t), or nullptr to use `single` (B = 1, the plan's mass, omega table).
+// With `fuse`, the last inverse pass also writes the reduction partials (and
+// writes the field only if fuse->store); an error if the schedule ends
+// without a strided pass (1D, N <= 4096).
 qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstParam* dinst,
-                      const InstParam& single, hipStream_t st);
+                      const InstParam& single, hipStream_t st, const ObsFuse* fuse = nullptr);
+// Column blocks per component of the fused last pass (0: no fusion possible).
+int64_t fused_obs_blocks(qw_plan_t p);
+ObsFuse make_fuse(qw_plan_t p, const double* origin, const double* origins, double* partials,
+                  bool store);
 // psi_t = T^-1 [D_q^t a(q)] in place for B spectra in storage order, device
 // per-instance (m, n, t); QW_ERR_UNSUPPORTED for the 1D four-step.
 qw_status evolve_spectrum_impl(qw_plan_t p, int B, void* data, const InstParam* dinst,
-                               hipStream_t st);
+                               hipStream_t st, const ObsFuse* fuse = nullptr);
 // Unnormalised DFT of B instances (direction +1 / -1); `scratch` holds B
 // fields for the 1D four-step transposes (unused otherwise; may be null then).
 qw_status transform_impl(qw_plan_t p, int B, const void* in, void* out, int direction,

@@ -446,9 +446,44 @@ PassGeom pass_geom(qw_plan_t p, int64_t L, int B) {
   return g;
 }
 
-// Forward (+) strided passes of the schedule: all axes but the contiguous one.
+// The last inverse pass of the schedule (axis 0; the 1D four-step's n1),
+// with the reductions fused when `fuse` is given.
+static qw_status last_pass(qw_plan_t p, int64_t L, void* out, const void* in, int B, int64_t I,
+                           hipStream_t st, const ObsFuse* fuse) {
+  if (fuse)
+    HIP_TRY(launch_fft_strided_obs(p->dbl, L, out, in, p->s, B, I, *fuse, p->d_tw, st));
+  else
+    HIP_TRY(launch_fft_strided(p->dbl, -1, L, out, in, (int64_t)p->s * B, I, p->d_tw, st));
+  mark();
+  return QW_OK;
+}
+
+int64_t fused_obs_blocks(qw_plan_t p) {
+  if (p->dim == 3) return strided_obs_blocks(p->dbl, p->N[0], p->N[1] * p->N[2]);
+  if (p->dim == 2) return strided_obs_blocks(p->dbl, p->N[0], p->N[1]);
+  if (p->fourstep) return strided_obs_blocks(p->dbl, p->fs_N1, p->fs_N2);
+  return 0;
+}
+
+ObsFuse make_fuse(qw_plan_t p, const double* origin, const double* origins, double* partials,
+                  bool store) {
+  ObsFuse f;
+  memset(&f, 0, sizeof f);
+  f.dim = p->dim;
+  for (int i = 0; i < 3; ++i) {
+    f.N[i] = p->N[i];
+    f.lg[i] = p->lg[i];
+    f.c[i] = (origin && i < p->dim) ? origin[i] : 0.0;
+  }
+  f.origins = origins;
+  f.partials = partials;
+  f.store = store ? 1 : 0;
+  return f;
+}
+
+// Strided passes of the schedule: all axes but the contiguous one.
 qw_status strided_passes(qw_plan_t p, int sign, void* out, const void* in, int B,
-                         hipStream_t st) {
+                         hipStream_t st, const ObsFuse* fuse) {
   const int s = p->s;
   if (p->dim == 3) {
     const int64_t N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
@@ -460,13 +495,14 @@ qw_status strided_passes(qw_plan_t p, int sign, void* out, const void* in, int B
     } else {
       HIP_TRY(launch_fft_strided(p->dbl, -1, N2, out, in, (int64_t)s * B * N1, N3, p->d_tw, st));
       mark();
-      HIP_TRY(launch_fft_strided(p->dbl, -1, N1, out, out, (int64_t)s * B, N2 * N3, p->d_tw, st));
-      mark();
+      return last_pass(p, N1, out, out, B, N2 * N3, st, fuse);
     }
   } else if (p->dim == 2) {
+    if (sign < 0) return last_pass(p, p->N[0], out, in, B, p->N[1], st, fuse);
     HIP_TRY(launch_fft_strided(p->dbl, sign, p->N[0], out, in, (int64_t)s * B, p->N[1], p->d_tw, st));
     mark();
   } else if (p->fourstep) {
+    if (sign < 0) return last_pass(p, p->fs_N1, out, in, B, p->fs_N2, st, fuse);
     HIP_TRY(launch_fft_strided(p->dbl, sign, p->fs_N1, out, in, (int64_t)s * B, p->fs_N2, p->d_tw, st));
     mark();
   } else if (out != in) {
@@ -505,7 +541,7 @@ const double* omega_table(qw_plan_t p, hipStream_t st) {
 }
 
 qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstParam* dinst,
-                      const InstParam& single, hipStream_t st) {
+                      const InstParam& single, hipStream_t st, const ObsFuse* fuse) {
   const int64_t L = contig_len(p);
   PassGeom g = pass_geom(p, L, B);
   g.single = single;
@@ -543,17 +579,16 @@ qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstP
     }
     g_mark_off = false;
     mark();
-    HIP_TRY(launch_fft_strided(p->dbl, -1, N1, out, out, nc, N2 * N3, p->d_tw, st));
-    mark();
-    return QW_OK;
+    return last_pass(p, N1, out, out, B, N2 * N3, st, fuse);
   }
   if (has_strided(p)) {
-    qw_status r = strided_passes(p, +1, out, in, B, st);
+    qw_status r = strided_passes(p, +1, out, in, B, st, nullptr);
     if (r != QW_OK) return r;
     HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, out, g, p->d_tw, st, p->ce));
     mark();
-    return strided_passes(p, -1, out, out, B, st);
+    return strided_passes(p, -1, out, out, B, st, fuse);
   }
+  if (fuse) return fail(QW_ERR_INVALID, "no strided pass to fuse the reductions into");
   HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, in, g, p->d_tw, st, p->ce));
   mark();
   return QW_OK;
@@ -564,7 +599,7 @@ qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstP
 // per-instance symbol power and inverts the contiguous axis, then the
 // strided inverse passes. Not for the 1D four-step (transposed spectrum).
 qw_status evolve_spectrum_impl(qw_plan_t p, int B, void* data, const InstParam* dinst,
-                               hipStream_t st) {
+                               hipStream_t st, const ObsFuse* fuse) {
   if (p->fourstep) return fail(QW_ERR_UNSUPPORTED, "four-step spectrum layout");
   const int64_t L = contig_len(p);
   PassGeom g = pass_geom(p, L, B);
@@ -574,7 +609,8 @@ qw_status evolve_spectrum_impl(qw_plan_t p, int B, void* data, const InstParam* 
   g.single.t = 0;
   g.inv_scale = 1.0;  // the spectrum is that of the unnormalised inverse
   HIP_TRY(launch_fft_contig(p->dbl, MODE_APPLY_INV, L, data, data, g, p->d_tw, st, 8));
-  if (has_strided(p)) return strided_passes(p, -1, data, data, B, st);
+  if (has_strided(p)) return strided_passes(p, -1, data, data, B, st, fuse);
+  if (fuse) return fail(QW_ERR_INVALID, "no strided pass to fuse the reductions into");
   return QW_OK;
 }
 
@@ -693,7 +729,7 @@ qw_status transform_impl(qw_plan_t p, int B, const void* in, void* out, int dire
   const int64_t planes = (int64_t)p->s * B;
   if (direction > 0) {
     if (has_strided(p)) {
-      qw_status r = strided_passes(p, +1, out, in, B, st);
+      qw_status r = strided_passes(p, +1, out, in, B, st, nullptr);
       if (r != QW_OK) return r;
       HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, out, out, g, p->d_tw, st));
     } else {
@@ -714,7 +750,7 @@ qw_status transform_impl(qw_plan_t p, int B, const void* in, void* out, int dire
     src = scratch;
   }
   HIP_TRY(launch_fft_contig(p->dbl, MODE_INV, L, out, src, g, p->d_tw, st));
-  if (has_strided(p)) return strided_passes(p, -1, out, out, B, st);
+  if (has_strided(p)) return strided_passes(p, -1, out, out, B, st, nullptr);
   return QW_OK;
 }
 
@@ -830,7 +866,9 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
     if (r == QW_OK) r = upload((void**)&p->d_cs, cs.data(), cs.size() * sizeof(double));
     if (r == QW_OK) r = upload((void**)&p->d_csf, csf.data(), csf.size() * sizeof(float));
     if (r == QW_OK) {
-      hipError_t e = hipMalloc(&p->d_partials, sizeof(double) * kObsFields * kObsBlocks);
+      const int64_t nfp = ((int64_t)p->s * fused_obs_blocks(p) + 64) * kObsFields;
+      p->partials_len = std::max<int64_t>((int64_t)kObsFields * kObsBlocks, nfp);
+      hipError_t e = hipMalloc(&p->d_partials, sizeof(double) * p->partials_len);
       if (e == hipSuccess) e = hipMalloc(&p->d_result, sizeof(double) * 16);
       if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_result, sizeof(double) * 16, hipHostMallocDefault);
       if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_stage, sizeof(StateInst), hipHostMallocDefault);
@@ -1068,6 +1106,47 @@ qw_status qw_transform(qw_plan_t p, const void* in, void* out, int direction, vo
     if (r != QW_OK) return r;
   }
   return transform_impl(p, 1, in, out, direction, p->d_scratch, (hipStream_t)stream);
+}
+
+qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, int64_t t,
+                                    const double* origin, qw_obs* out, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi0 || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
+  for (int i = 0; i < p->dim; ++i)
+    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+  hipStream_t st = (hipStream_t)stream;
+  void* dst = psi_t;
+  if (!dst) {  // intermediate passes need a field; the result is not kept
+    r = ensure_scratch(p, p->field_bytes);
+    if (r != QW_OK) return r;
+    dst = p->d_scratch;
+  }
+  InstParam ip;
+  ip.m = p->m;
+  ip.n = p->n;
+  ip.t = t;
+  const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
+  if (nb > 0) {
+    const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, psi_t != nullptr);
+    r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, &f);
+    if (r != QW_OK) return r;
+    HIP_TRY(launch_reduce_partials(1, nb, p->d_partials, p->d_partials + nb * kObsFields,
+                                   p->d_result, st));
+  } else {
+    r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, nullptr);
+    if (r != QW_OK) return r;
+    ObsGeom g = obs_geom(p);
+    for (int i = 0; i < p->dim; ++i) g.c[i] = origin[i];
+    HIP_TRY(launch_observables(p->dbl, g, 1, dst, nullptr, nullptr, p->d_partials, p->d_result,
+                               st));
+  }
+  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  finish_obs(p, p->h_result, origin, out);
+  out->overlap_re = out->overlap_im = out->ref_norm2 = 0.0;
+  return QW_OK;
 }
 
 qw_status qw_observables(qw_plan_t p, const void* psi, const double* origin, const void* ref,

@@ -115,6 +115,82 @@ hipError_t launch_observables(bool dbl, const ObsGeom& g, int B, const void* psi
                               const double* origins, double* partials, double* result,
                               hipStream_t st);
 
+// Minimum image of n - c in [-N/2, N/2) for integer n (N a power of two),
+// written with integer arithmetic: c = ci + cf with ci = floor(c), cf in
+// [0, 1); for cf = 0 the image is ((n - ci + N/2) mod N) - N/2, otherwise
+// ((n - ci + N/2 - 1) mod N) + 1 - cf - N/2.
+struct AxisImage {
+  int64_t ci;
+  double cf;
+  int64_t half, mask;
+};
+
+__device__ __forceinline__ AxisImage axis_image(double c, int64_t N) {
+  AxisImage a;
+  const double fl = floor(c);
+  a.ci = (int64_t)fl;
+  a.cf = c - fl;
+  a.half = N / 2;
+  a.mask = N - 1;
+  return a;
+}
+
+__device__ __forceinline__ double min_image(int64_t n, const AxisImage& a) {
+  if (a.cf == 0.0) return (double)(((n - a.ci + a.half) & a.mask) - a.half);
+  return (double)(((n - a.ci + a.half - 1) & a.mask) - a.half) + (1.0 - a.cf);
+}
+
+// Block sum of NF doubles per thread, for blockDim.x a multiple of 64 up to
+// 1024; thread f < NF writes field f to dst[f].
+template <int NF>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NF], double* __restrict__ dst) {
+  __shared__ double red[NF][16];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    double v = acc[f];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[f][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NF) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+    dst[threadIdx.x] = s;
+  }
+}
+
+// The Sec. 5.2 reductions fused into the last (inverse, strided) pass of an
+// evolution. The pass runs along axis 0 of the lattice (d = 2, 3: position
+// n_1 = index along the pass, the column index holds the other axes) or,
+// for the 1D four-step, along n1 of x = n1 * I + column. Every workgroup
+// writes one partial vector of kObsFields doubles (overlap fields zero).
+struct ObsFuse {
+  int dim;
+  int64_t N[3];
+  int lg[3];
+  double c[3];             // origin of instance 0 when origins is null
+  const double* origins;   // [B][3] or null
+  double* partials;        // [B][s * column blocks][kObsFields]
+  int store;               // write the transformed field too
+};
+// Column blocks per component of the fused pass (partials per instance are
+// s times this), or 0 if the pass cannot take the fused reduction (workgroup
+// not a multiple of 64 threads).
+int64_t strided_obs_blocks(bool dbl, int64_t L, int64_t I);
+// Inverse transform along L (stride I) of B instances of s components,
+// whole fields, with the reductions of `f`.
+hipError_t launch_fft_strided_obs(bool dbl, int64_t L, void* out, const void* in, int s, int B,
+                                  int64_t I, const ObsFuse& f, const void* tw, hipStream_t st);
+// Sums nb partial vectors of kObsFields doubles per instance into
+// result[B][kObsFields], through `mid` (B * 64 * kObsFields doubles), in a
+// fixed order.
+hipError_t launch_reduce_partials(int B, int64_t nb, const double* partials, double* mid,
+                                  double* result, hipStream_t st);
+
 // Particle states: shape, and the per-instance parameters (device array).
 struct StateGeom {
   int dim;

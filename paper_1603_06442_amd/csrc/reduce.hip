@@ -7,41 +7,6 @@
 
 namespace qw {
 
-template <int NF>
-__device__ __forceinline__ void block_reduce_store(double (&acc)[NF], double* __restrict__ dst) {
-  __shared__ double red[NF][256 / 64];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    double v = acc[f];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) red[f][wave] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < NF) {
-    double s = 0.0;
-    for (int w = 0; w < 4; ++w) s += red[threadIdx.x][w];
-    dst[threadIdx.x] = s;
-  }
-}
-
-// Minimum image of n - c in [-N/2, N/2) for integer n, written with integer
-// arithmetic: c = ci + cf with ci = floor(c), cf in [0, 1); for cf = 0 the
-// image is ((n - ci + N/2) mod N) - N/2, otherwise
-// ((n - ci + N/2 - 1) mod N) + 1 - cf - N/2.
-struct AxisImage {
-  int64_t ci;
-  double cf;
-  int64_t half, mask;
-};
-
-__device__ __forceinline__ double min_image(int64_t n, const AxisImage& a) {
-  if (a.cf == 0.0) return (double)(((n - a.ci + a.half) & a.mask) - a.half);
-  return (double)(((n - a.ci + a.half - 1) & a.mask) - a.half) + (1.0 - a.cf);
-}
-
 // Each thread takes UNR sites per round, all loads of a round issued before
 // any arithmetic; FP64 accumulation.
 template <typename T, int DIM, bool REF>
@@ -60,14 +25,7 @@ __global__ __launch_bounds__(256) void k_observables(const cx<T>* __restrict__ p
   for (int f = 0; f < kObsFields; ++f) acc[f] = 0.0;
   AxisImage ax[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const double ci = origins ? origins[3 * inst + i] : g.c[i];
-    const double fl = floor(ci);
-    ax[i].ci = (int64_t)fl;
-    ax[i].cf = ci - fl;
-    ax[i].half = g.N[i] / 2;
-    ax[i].mask = g.N[i] - 1;
-  }
+  for (int i = 0; i < 3; ++i) ax[i] = axis_image(origins ? origins[3 * inst + i] : g.c[i], g.N[i]);
   const int64_t V = g.V;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   auto site = [&](int64_t idx, const cx<T> (&a)[S], const cx<T> (&r)[S]) {
@@ -150,6 +108,40 @@ __global__ __launch_bounds__(256) void k_reduce_final_b(const double* __restrict
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] += p[(int64_t)k * NF + f];
   block_reduce_store<NF>(acc, result + b * NF);
+}
+
+// Chunked first stage: block (g, b) adds chunk g of instance b's partials.
+template <int NF>
+__global__ __launch_bounds__(256) void k_reduce_chunks(const double* __restrict__ partials,
+                                                       int64_t nblk, double* __restrict__ mid) {
+  const int64_t b = blockIdx.y;
+  const int64_t ng = gridDim.x;
+  const int64_t lo = nblk * blockIdx.x / ng, hi = nblk * (blockIdx.x + 1) / ng;
+  double acc[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = 0.0;
+  const double* p = partials + b * nblk * NF;
+  for (int64_t k = lo + threadIdx.x; k < hi; k += 256)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] += p[k * NF + f];
+  block_reduce_store<NF>(acc, mid + (b * ng + blockIdx.x) * NF);
+}
+
+hipError_t launch_reduce_partials(int B, int64_t nb, const double* partials, double* mid,
+                                  double* result, hipStream_t st) {
+  if (nb <= 1024) {
+    hipLaunchKernelGGL(k_reduce_final_b<kObsFields>, dim3((unsigned)B), dim3(256), 0, st,
+                       partials, (int)nb, result);
+    return hipGetLastError();
+  }
+  const int ng = 64;
+  hipLaunchKernelGGL(k_reduce_chunks<kObsFields>, dim3(ng, (unsigned)B), dim3(256), 0, st,
+                     partials, nb, mid);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final_b<kObsFields>, dim3((unsigned)B), dim3(256), 0, st, mid, ng,
+                     result);
+  return hipGetLastError();
 }
 
 // The number of workgroups (and so the summation order) depends on the shape

@@ -204,6 +204,7 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
   const StateGeom sg = state_geom(p);
   const ObsGeom og = obs_geom(p);
   const int64_t nbs = state_blocks(sg, B), nbo = observables_blocks(og, B);
+  const int64_t nbf = (int64_t)p->s * fused_obs_blocks(p);  // 0: separate reduction pass
   // device layout
   size_t o = 0;
   b->off_field = o;
@@ -217,7 +218,10 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
   b->off_orig = o;
   o = align256(o + sizeof(double) * 3 * B);
   b->off_part = o;
-  o = align256(o + sizeof(double) * (size_t)B * std::max<int64_t>(nbs * 2, nbo * kObsFields));
+  o = align256(o + sizeof(double) * (size_t)B *
+                       (std::max<int64_t>(std::max<int64_t>(nbs * 2, nbo * kObsFields),
+                                          nbf * kObsFields) +
+                        64 * kObsFields));
   b->off_norm = o;
   o = align256(o + sizeof(double) * 2 * B);
   b->off_res = o;
@@ -262,11 +266,17 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
                                (double*)(D + b->off_norm), field, st));
   // The state is prepared as its spectrum: apply D_q^t there and invert once.
   // The 1D four-step keeps its transposed spectrum internal, so it goes to
-  // position space and through the full evolution.
+  // position space and through the full evolution. Where the schedule ends
+  // with a strided pass, the reductions are fused into it and psi(t) is
+  // never written.
   const InstParam* dinst = (const InstParam*)(D + b->off_inst);
+  const double* origins = (const double*)(D + b->off_orig);
+  double* res = (double*)(D + b->off_res);
+  const ObsFuse fuse = make_fuse(p, nullptr, origins, part, false);
+  const ObsFuse* fz = nbf > 0 ? &fuse : nullptr;
   qw_status r;
   if (!p->fourstep) {
-    r = evolve_spectrum_impl(p, B, field, dinst, st);
+    r = evolve_spectrum_impl(p, B, field, dinst, st, fz);
   } else {
     r = transform_impl(p, B, field, field, -1, scratch, st);
     if (r == QW_OK) {
@@ -274,12 +284,14 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
       unused.m = 0.0;
       unused.n = 1.0;
       unused.t = 0;
-      r = evolve_impl(p, B, field, field, dinst, unused, st);
+      r = evolve_impl(p, B, field, field, dinst, unused, st, fz);
     }
   }
   if (r != QW_OK) return r;
-  HIP_TRY(launch_observables(p->dbl, og, B, field, nullptr, (const double*)(D + b->off_orig), part,
-                             (double*)(D + b->off_res), st));
+  if (fz)
+    HIP_TRY(launch_reduce_partials(B, nbf, part, part + (size_t)B * nbf * kObsFields, res, st));
+  else
+    HIP_TRY(launch_observables(p->dbl, og, B, field, nullptr, origins, part, res, st));
   HIP_TRY(hipMemcpyAsync(H + b->h_res, D + b->off_res, sizeof(double) * kObsFields * B,
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(H + b->h_norm, D + b->off_norm, sizeof(double) * 2 * B,

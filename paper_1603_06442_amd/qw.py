@@ -21,7 +21,8 @@ QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE = range(5
 QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_evolve_fft", "qw_evolve_fft_batched",
-           "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_prepare_state",
+           "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables",
+           "qw_prepare_state",
            "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
            "qw_server_create", "qw_server_submit", "qw_server_poll", "qw_server_wait",
            "qw_server_hold", "qw_server_stats", "qw_server_destroy")
@@ -75,6 +76,8 @@ def _load():
         "qw_evolve_fft_batched": [vp, cint, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), vp],
         "qw_transform": [vp, vp, vp, cint, vp],
         "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
+        "qw_evolve_fft_observables": [vp, vp, vp, i64, ctypes.POINTER(dbl),
+                                      ctypes.POINTER(QwObs), vp],
         "qw_prepare_state": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl, vp],
         "qw_set_schedule": [vp, cint, cint, cint, cint],
         "qw_get_schedule": [vp, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint),
@@ -226,6 +229,17 @@ class Plan:
         return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
                 "mean_cart": list(o.mean_cart),
                 "overlap": complex(o.overlap_re, o.overlap_im), "ref_norm2": o.ref_norm2}
+
+    def evolve_fft_observables(self, psi0, t, origin, out=None, stream=None):
+        """qw_evolve_fft_observables: psi_t = U^t psi0 into ``out`` (not kept
+        when out is None) and the reductions of psi_t about origin."""
+        o = QwObs()
+        outp = self._field(out, name="out") if out is not None else ctypes.c_void_p(0)
+        _check(LIB.qw_evolve_fft_observables(self._h, self._field(psi0, name="psi0"), outp,
+                                             int(t), _darr(origin, self.dim), ctypes.byref(o),
+                                             _stream(stream)))
+        return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
+                "mean_cart": list(o.mean_cart)}
 
     def set_schedule(self, slab_planes, contig_elems=8, contig_threads=256, contig_groups=1):
         """qw_set_schedule: slab size (n1 planes, 0 = whole field), the fused

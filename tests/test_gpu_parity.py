@@ -307,3 +307,45 @@ def test_fp32_path_vs_fp64_path_large_t(qw):
         a = to_np(p64.evolve_fft(to_dev(psi0, p64), t))
         b = to_np(p128.evolve_fft(to_dev(psi0, p128), t))
         assert ob.rel_l2(a, b) < 2e-5
+
+
+def _obs_close(a, b, dim, rt):
+    assert abs(a["norm2"] - b["norm2"]) <= rt * max(1.0, abs(b["norm2"]))
+    for x, y in zip(a["mean"][:dim], b["mean"][:dim]):
+        assert abs(x - y) <= rt * max(1.0, abs(y))
+    for x, y in zip(a["second"], b["second"]):
+        assert abs(x - y) <= rt * max(1.0, abs(y))
+    for x, y in zip(a["mean_cart"], b["mean_cart"]):
+        assert abs(x - y) <= rt * max(1.0, abs(y))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape,slab", [
+    (3, (16, 16, 16), 0), (3, (8, 16, 64), 0), (3, (32, 16, 64), 8), (2, (32, 64), 0),
+    (2, (256, 16), 0), (1, (8192,), 0), (1, (1024,), 0)])
+def test_evolve_fft_observables_fused(qw, d, shape, slab, dtype):
+    """The reductions taken inside the last inverse pass equal evolve_fft
+    followed by observables; the field it writes is evolve_fft's, bitwise."""
+    psi = rand_field(d, shape, 21)
+    plan = qw.Plan(d, list(shape), 0.15, dtype)
+    if slab:
+        plan.set_schedule(slab, 8, 256, 1)
+    x = to_dev(psi, plan)
+    t = 777
+    ref_t = plan.evolve_fft(x, t)
+    for origin in ([n // 2 for n in shape], [n / 3 + 0.37 for n in shape]):
+        want = plan.observables(ref_t, origin)
+        out = plan.empty()
+        got = plan.evolve_fft_observables(x, t, origin, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref_t)
+        _obs_close(got, want, d, 1e-12)
+        got2 = plan.evolve_fft_observables(x, t, origin)  # result not kept
+        assert got2 == got
+    # against the oracle
+    ref = fourier.evolve_fourier(psi, table(d, 0.15), t)
+    want = ob.observables(ref, [n // 2 for n in shape])
+    got = plan.evolve_fft_observables(x, t, [n // 2 for n in shape])
+    rt = 1e-4 if dtype == "c64" else 1e-10
+    _obs_close(got, {"norm2": want["norm2"], "mean": list(want["mean"]),
+                     "second": list(want["second"]), "mean_cart": list(want["mean_cart"])}, d, rt)

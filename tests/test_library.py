@@ -74,6 +74,8 @@ def test_calls_reject_null_plan():
     from paper_1603_06442_amd import qw
     assert qw.LIB.qw_step(None, ctypes.c_void_p(1), 1, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_evolve_fft(None, None, None, 1, None) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_evolve_fft_observables(None, None, None, 1, None, None, None) == \
+        qw.QW_ERR_INVALID
     assert qw.LIB.qw_destroy(None) == qw.QW_OK
 
 
