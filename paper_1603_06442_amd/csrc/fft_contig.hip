@@ -191,13 +191,14 @@ __device__ __forceinline__ void apply_q_f32(cx<float> (&y)[DIM == 1 ? 2 : 4], co
     n3 = g.csf[2 * jj + 1];
   }
   const float nn = (float)ip.n, m = (float)ip.m;
-  const float sinw = sqrtf(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
+  const float sinw2 = nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m;
   const float r = (float)reduced_phase(g.omega[qidx], ip.t);
   float S, C;
   __sincosf(r, &S, &C);
   const float sc = (float)g.inv_scale;
   const float c = C * sc;
-  const float st = sinw > 1e-30f ? S * sc / sinw : 0.0f;  // V^-1 sin(omega t) / sin(omega)
+  // V^-1 sin(omega t) / sin(omega), with the hardware reciprocal square root
+  const float st = sinw2 > 1e-30f ? S * sc * __frsqrt_rn(sinw2) : 0.0f;
   if constexpr (DIM == 1) {
     const float a = nn * n3 * st, gg = m * st;
     const cx<float> z0 = mk(a * y[0].x - gg * y[1].x, a * y[0].y - gg * y[1].y);
@@ -252,7 +253,7 @@ __device__ __forceinline__ void load_group(cx<T> (&dst)[S][E], const cx<T>* __re
   const int64_t gp = grp * P + p;
   const bool valid = gp < g.pencils;
   const int64_t gpc = valid ? gp : 0;
-  const int64_t b = gpc / g.ppi;
+  const int64_t b = g.lg_ppi >= 0 ? gpc >> g.lg_ppi : gpc / g.ppi;
   const int64_t pen = g.pen0 + (gpc - b * g.ppi);
   const int64_t base = b * S * g.V + pen * L;
   // Lanes past the last pencil read pencil 0 (in bounds) and never store:
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
     const int64_t gp = grp * P + p;
     const bool valid = gp < g.pencils;
     const int64_t gpc = valid ? gp : 0;
-    const int64_t b = gpc / g.ppi;
+    const int64_t b = g.lg_ppi >= 0 ? gpc >> g.lg_ppi : gpc / g.ppi;
     const int64_t pen = g.pen0 + (gpc - b * g.ppi);
     const int64_t base = b * S * g.V + pen * L;
 
@@ -313,7 +314,22 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
       }
       fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
     }
-    if constexpr (MODE == MODE_EVOLVE_TAB && sizeof(T) == 4) {
+    if constexpr (MODE == MODE_EVOLVE_TAB && sizeof(T) == 4 && E <= 4) {
+      // Four wave-vectors per thread: unrolled (independent chains, no
+      // register rotation).
+      const InstParam ip = g.single;
+      const PencilTrig pt = pencil_trig<DIM>(g, pen);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int z = t + TT * e;
+        cx<T> y[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) y[c] = v[c][e];
+        apply_q_f32<DIM>(y, g, ip, pt, pen, z, pen * L + z);
+#pragma unroll
+        for (int c = 0; c < S; ++c) v[c][e] = y[c];
+      }
+    } else if constexpr (MODE == MODE_EVOLVE_TAB && sizeof(T) == 4) {
       const InstParam ip = g.single;
       const PencilTrig pt = pencil_trig<DIM>(g, pen);
 #pragma unroll 1

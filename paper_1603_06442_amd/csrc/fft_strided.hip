@@ -46,16 +46,33 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
   for (int e = 0; e < E; ++e) out[base + (int64_t)(t + TT * e) * I] = v[e];
 }
 
+// Columns per workgroup of a strided pass: 256 bytes of each row (32
+// complex64 or 16 complex128 columns), at least 256 threads; then at most
+// 1024 threads, and at most 64 KB of LDS unless rows would drop below 128
+// bytes; at most the I columns there are. Measured on the 256^3 complex64
+// evolution: 16 columns (128-byte rows) 1.175 ms, 32 columns 1.131 ms,
+// 64 columns (128 KB of LDS, one workgroup per CU) 1.160 ms.
+template <typename T, int L>
+static int strided_cols(int64_t I) {
+  constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
+  constexpr int E = L < Emax ? L : Emax;
+  constexpr int TT = L / E;
+  constexpr int row128 = 128 / (int)sizeof(cx<T>);
+  int P = 2 * row128;
+  while (TT * P < 256) P <<= 1;
+  while (TT * P > 1024 && P > 1) P >>= 1;
+  while ((size_t)P * L * sizeof(cx<T>) > 65536 && P > row128) P >>= 1;
+  if (P > I) P = (int)I;
+  return P;
+}
+
 template <typename T, int L, int SIGN>
 static hipError_t run_strided(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
                               const OuterMap& om, const cx<T>* tw, hipStream_t st) {
   constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
   constexpr int E = L < Emax ? L : Emax;
   constexpr int TT = L / E;
-  const int Pmin = sizeof(T) == 8 ? 8 : 16;
-  int P = 256 / TT;
-  if (P < Pmin) P = Pmin;
-  if (P > I) P = (int)I;
+  int P = strided_cols<T, L>(I);
   if (TT * P > 1024) return hipErrorInvalidValue;
   const int lgP = ilog2(P);
   const size_t lds = (size_t)P * L * sizeof(cx<T>);
@@ -180,19 +197,6 @@ __global__ __launch_bounds__(1024) void k_fft_strided_obs(cx<T>* __restrict__ ou
   double acc[kObsFields] = {S0,      S1,      wb * S0, wc * S0,      S11, wb * wb * S0, wc * wc * S0,
                             wb * S1, wc * S1, wb * wc * S0, 0.0, 0.0, 0.0};
   block_reduce_store<kObsFields>(acc, f.partials + blk * kObsFields);
-}
-
-// Columns per workgroup of a strided pass (the same choice as run_strided).
-template <typename T, int L>
-static int strided_cols(int64_t I) {
-  constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
-  constexpr int E = L < Emax ? L : Emax;
-  constexpr int TT = L / E;
-  const int Pmin = sizeof(T) == 8 ? 8 : 16;
-  int P = 256 / TT;
-  if (P < Pmin) P = Pmin;
-  if (P > I) P = (int)I;
-  return P;
 }
 
 template <typename T, int L>

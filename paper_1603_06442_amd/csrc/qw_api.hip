@@ -417,6 +417,14 @@ qw_status check_plan(qw_plan_t p) {
   return QW_OK;
 }
 
+// log2 x for a power of two x > 0, else -1.
+static int lg_pow2(int64_t x) {
+  if (x <= 0 || (x & (x - 1))) return -1;
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
 PassGeom pass_geom(qw_plan_t p, int64_t L, int B) {
   PassGeom g;
   memset(&g, 0, sizeof g);
@@ -425,6 +433,7 @@ PassGeom pass_geom(qw_plan_t p, int64_t L, int B) {
   g.V = p->V;
   for (int i = 0; i < 3; ++i) g.N[i] = p->N[i];
   g.ppi = p->V / L;
+  g.lg_ppi = lg_pow2(g.ppi);
   g.pencils = g.ppi * B;
   g.pen0 = 0;
   g.block_threads = p->cb;
@@ -567,6 +576,7 @@ qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstP
         PassGeom gs = g;
         gs.pen0 = a * N2;
         gs.ppi = k * N2;
+        gs.lg_ppi = lg_pow2(gs.ppi);
         gs.pencils = gs.ppi * B;
         e = launch_fft_contig(p->dbl, mode, L, out, out, gs, p->d_tw, st, p->ce);
       }

@@ -26,6 +26,7 @@ struct PassGeom {
   int64_t N[3];      // lattice sizes
   int64_t pencils;   // pencils (of all s components) in this launch, over all instances
   int64_t ppi;       // pencils per instance in this launch
+  int lg_ppi;        // log2 ppi when ppi is a power of two, else -1
   int64_t pen0;      // first pencil of each instance in this launch (slabs)
   int block_threads; // target workgroup size of the contiguous pass (0 = 256)
   int groups_per_wg; // pencil groups per workgroup (loads one group ahead); 1 = none

@@ -8,10 +8,17 @@
 
 namespace qw {
 
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc + a b as four chained FMAs (the plain expression compiles to a
+// multiply, an FMA and an add per real part).
 template <typename T>
 __device__ __forceinline__ cx<T> fma_c(cx<T> acc, cx<T> a, cx<T> b) {
-  acc.x += a.x * b.x - a.y * b.y;
-  acc.y += a.x * b.y + a.y * b.x;
+  acc.x = fma_r(a.x, b.x, acc.x);
+  acc.x = fma_r(a.y, -b.y, acc.x);
+  acc.y = fma_r(a.x, b.y, acc.y);
+  acc.y = fma_r(a.y, b.x, acc.y);
   return acc;
 }
 
