@@ -277,8 +277,8 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
   const int t = tid & (TT - 1);
   const int p = tid / TT;
   const int P = blockDim.x / TT;
-  constexpr int LP = lds_len<true>(L);
-  cx<T>* my = lds + p * S * LP;
+  constexpr int LP = L;                 // component stride (swizzled slots)
+  cx<T>* my = lds + p * (S * L + TT);  // team region (see fft_team_multi)
   const int64_t ngroups = (g.pencils + P - 1) / P;
   const cx<T>* tw4 = (const cx<T>*)g.tw4;
   const int64_t N = g.N[0];
@@ -422,7 +422,7 @@ static hipError_t run_contig_k(cx<T>* out, const cx<T>* in, const PassGeom& g, c
   }
   const int threads = TT * P;
   if (threads > 512) return hipErrorInvalidValue;
-  const size_t lds = (size_t)P * (g.dim == 1 ? 2 : 4) * lds_len<true>(L) * sizeof(cx<T>);
+  const size_t lds = (size_t)P * ((g.dim == 1 ? 2 : 4) * L + TT) * sizeof(cx<T>);
   auto kern = k_fft_contig<T, L, E, DIM, MODE, PIPE>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,

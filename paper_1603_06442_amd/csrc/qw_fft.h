@@ -139,6 +139,19 @@ __host__ __device__ constexpr int lds_len(int L) {
   return PAD ? L + L / 16 : L;
 }
 
+// LDS slot of pencil position `pos` in the multi-component team transform
+// with E elements per thread: the low five bits (in 8- or 16-byte words)
+// are XORed with bits lg E .. lg E + 4. Every exchange of the transform
+// (stage writes base + r NS, reads t + (L/E) e) then touches 32 distinct
+// words per 32 lanes, i.e. all LDS banks once, and no padding is needed.
+// Bits 5 and up are unchanged and bits lg E .. 4 can be recovered from them,
+// so the map is a bijection on [0, L) for every power-of-two L.
+template <int E>
+__device__ __forceinline__ int lds_swz(int pos) {
+  constexpr int lg = E >= 16 ? 4 : (E >= 8 ? 3 : (E >= 4 ? 2 : (E >= 2 ? 1 : 0)));
+  return pos ^ ((pos >> lg) & 31);
+}
+
 // One Stockham stage (and, recursively, the rest). NS = product of the radices
 // already done. LDS addressing: element at pencil position `pos` lives at
 // lds[lds_slot<PAD>(pos) * ls] (the caller offsets lds to its pencil).
@@ -195,8 +208,11 @@ __device__ __forceinline__ void fft_team(cx<T> (&v)[E], cx<T>* lds, int ls, int 
 // The same transform applied to S pencils in lockstep (the spinor components
 // of one lattice row): twiddles and LDS slots are computed once per stage and
 // shared, and each exchange is one write/barrier/read/barrier for all S.
-// Component c of the team's pencil lives at lds + c * cstride.
-template <typename T, int L, int E, int SIGN, int NS, bool PAD, int S>
+// Component c of the team's pencil lives at lds + c * cstride (cstride >= L),
+// position pos at slot lds_swz<E>(pos). Teams of fewer than 32 threads share
+// a wave: their regions should be S * L + L / E elements apart, which puts
+// the teams of one wave on disjoint banks.
+template <typename T, int L, int E, int SIGN, int NS, int S>
 struct StagesMulti {
   static constexpr int REM = L / NS;
   static constexpr int R = REM >= E ? E : REM;
@@ -231,7 +247,7 @@ struct StagesMulti {
           for (int r = 0; r < R; ++r) v[c][b + r * NB] = a[r];
         } else {
 #pragma unroll
-          for (int r = 0; r < R; ++r) lds[c * cstride + lds_slot<PAD>(base + r * NS)] = a[r];
+          for (int r = 0; r < R; ++r) lds[c * cstride + lds_swz<E>(base + r * NS)] = a[r];
         }
       }
     }
@@ -240,18 +256,18 @@ struct StagesMulti {
 #pragma unroll
       for (int c = 0; c < S; ++c)
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[c][e] = lds[c * cstride + lds_slot<PAD>(t + TT * e)];
+        for (int e = 0; e < E; ++e) v[c][e] = lds[c * cstride + lds_swz<E>(t + TT * e)];
       __syncthreads();
-      StagesMulti<T, L, E, SIGN, NS * R, PAD, S>::run(v, lds, cstride, t, tw);
+      StagesMulti<T, L, E, SIGN, NS * R, S>::run(v, lds, cstride, t, tw);
     }
   }
 };
 
-template <typename T, int L, int E, int SIGN, int S, bool PAD = true>
+template <typename T, int L, int E, int SIGN, int S>
 __device__ __forceinline__ void fft_team_multi(cx<T> (&v)[S][E], cx<T>* lds, int cstride, int t,
                                                const cx<T>* __restrict__ tw) {
   static_assert((L & (L - 1)) == 0 && L >= 1 && L <= TWN, "length");
-  StagesMulti<T, L, E, SIGN, 1, PAD, S>::run(v, lds, cstride, t, tw);
+  StagesMulti<T, L, E, SIGN, 1, S>::run(v, lds, cstride, t, tw);
 }
 
 }  // namespace qw
