@@ -112,6 +112,43 @@ def _pct(xs, q):
     return xs[min(len(xs) - 1, int(math.ceil(q * len(xs))) - 1)]
 
 
+def stencil_line(qw):
+    """The 1D workload (N = 4096, two components, complex128, m = 0.1, 1000
+    steps): one field alone, and 1024 instances with masses drawn in
+    [0, 0.3] batched. Each field is 128 KB and is stepped on-chip."""
+    import torch
+    from paper_1603_06442_amd import inputs
+    w = inputs.workload(0)
+    N, steps, B = w["N"], w["steps"], 1024
+    plan = qw.Plan(1, N, w["m"], "c128")
+    x = plan.empty()
+    plan.prepare_state(x, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
+    xb = x.unsqueeze(0).repeat(B, 1, 1).contiguous()
+    rng = inputs.rng_for(0)
+    ms = [float(v) for v in rng.uniform(0.0, 0.3, B)]
+    plan.step(x.clone(), 10)
+    plan.step_batched(xb, ms, 10)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    y = x.clone()
+    e0.record(st)
+    plan.step(y, steps)
+    e1.record(st)
+    e1.synchronize()
+    one_ms = e0.elapsed_time(e1)
+    e0.record(st)
+    plan.step_batched(xb, ms, steps)
+    e1.record(st)
+    e1.synchronize()
+    b_ms = e0.elapsed_time(e1)
+    return {"workload": "1D N=4096 complex128 m=0.1, %d steps" % steps,
+            "single_ms": round(one_ms, 4),
+            "single_site_steps_per_s": round(N * steps / (one_ms * 1e-3), 1),
+            "batched_instances": B, "batched_ms": round(b_ms, 4),
+            "batched_site_steps_per_s": round(B * N * steps / (b_ms * 1e-3), 1)}
+
+
 def serving(qw, budget_gib=16):
     """The mixed request stream (512 requests: 1D/2D/3D lattices, masses,
     states and times drawn per request) through the continuous-batching
@@ -328,6 +365,7 @@ def main():
         "norm_drift_c64": abs(plan.observables(y64, w["center"])["norm2"] - 1.0),
         "norm_drift_c128": abs(p128.observables(y128, w["center"])["norm2"] - 1.0)}
     del p128, x128, y128, diff
+    line["stencil_1d"] = stencil_line(qw)
     if not args.no_serving:
         line["serving"] = serving(qw)
     if not args.no_cpu_baseline:

@@ -89,8 +89,20 @@ qw_status qw_destroy(qw_plan_t plan);
 
 /* nsteps >= 0 applications of the update rule psi(x,t+1) = sum_h U_h psi(x+h,t)
  * (Sec. 2, update rule and walk operator), in place on psi. The plan's
- * scratch holds the second buffer of the ping-pong. */
+ * scratch holds the second buffer of the ping-pong; a 1D field of at most
+ * 160 KB (N <= 8192) stays in on-chip memory for up to 4096 steps per launch
+ * instead. */
 qw_status qw_step(qw_plan_t plan, void* psi, int64_t nsteps, void* stream);
+
+/* The same for B (0..65535) fields of the plan's shape and precision back to
+ * back in psi (DEVICE), instance b with its own mass m[b] (HOST, 0 <= m[b]
+ * <= 1): its transition matrices are derived from the symbol exactly as
+ * qw_plan derives the plan's. An instance with the plan's mass gets the
+ * same result as qw_step, bit for bit. The plan's scratch grows to B fields
+ * (none for the on-chip 1D case). Waits for the previous call's parameter
+ * upload on `stream` before staging the masses. */
+qw_status qw_step_batched(qw_plan_t plan, int B, void* psi, const double* m, int64_t nsteps,
+                          void* stream);
 
 /* psi_t = U^t psi0 in one jump through the Fourier representation (Sec. 4):
  * forward DFT with the sign of Sec. 4, per wave-vector the closed form

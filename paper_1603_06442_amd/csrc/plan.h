@@ -69,6 +69,10 @@ struct qw_plan_s {
   qw::InstParam* d_inst = nullptr;
   qw::InstParam* h_inst = nullptr;  // pinned
   int inst_cap = 0;
+  void* d_coef = nullptr;            // the plan's StencilCoef (field precision), device
+  void* d_coefs = nullptr;           // per-instance StencilCoef of qw_step_batched
+  unsigned char* h_coefs = nullptr;  // pinned staging for d_coefs
+  int coefs_cap = 0;
   qw::StateInst* h_stage = nullptr;  // pinned staging of one state's parameters
   qw::StateInst* d_stage = nullptr;
   double* d_omega = nullptr;    // omega(q) at the plan's mass, built on first use
@@ -92,6 +96,9 @@ struct qw_plan_s {
     if (d_scratch) (void)hipFree(d_scratch);
     if (d_inst) (void)hipFree(d_inst);
     if (h_inst) (void)hipHostFree(h_inst);
+    if (d_coef) (void)hipFree(d_coef);
+    if (d_coefs) (void)hipFree(d_coefs);
+    if (h_coefs) (void)hipHostFree(h_coefs);
     if (d_omega) (void)hipFree(d_omega);
     if (h_stage) (void)hipHostFree(h_stage);
     if (d_stage) (void)hipFree(d_stage);
@@ -102,6 +109,7 @@ struct qw_plan_s {
 namespace qw {
 qw_status check_plan(qw_plan_t p);
 qw_status ensure_scratch(qw_plan_t p, size_t bytes);
+qw_status ensure_coefs(qw_plan_t p, int B);
 // psi_out = U^t psi_in for B instances back to back; dinst: device per-instance
 // (m, n, t), or nullptr to use `single` (B = 1, the plan's mass, omega table).
 // With `fuse`, the last inverse pass also writes the reduction partials (and

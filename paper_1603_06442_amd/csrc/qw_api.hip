@@ -288,6 +288,20 @@ const int kOff3h[8][3] = {{1, 0, 0},  {0, -1, 0}, {0, 0, -1}, {-1, -1, -1},
 
 // Fill the kernel coefficient struct; check that everything the kernel does
 // not read is zero (block-diagonal neighbours, mass coupling on site).
+// The rank-one pattern of the 3D neighbour blocks that k_step3d_ring<SPARSE>
+// relies on: for offsets 0..3 row 1 of `up` and column 0 of `lo` are zero,
+// for offsets 4..7 row 0 of `up` and column 1 of `lo`.
+static bool coef_sparse3(const StencilCoef<double>& C) {
+  for (int k = 0; k < 8; ++k) {
+    const int ur = k < 4 ? 1 : 0, lc = k < 4 ? 0 : 1;
+    for (int j = 0; j < 2; ++j) {
+      const cx<double> a = C.up[k][ur][j], b = C.lo[k][j][lc];
+      if (a.x != 0.0 || a.y != 0.0 || b.x != 0.0 || b.y != 0.0) return false;
+    }
+  }
+  return true;
+}
+
 template <typename T>
 bool pack_coef(const Table& Tb, double m, StencilCoef<T>& C, std::string& why) {
   memset(&C, 0, sizeof C);
@@ -398,6 +412,25 @@ qw_status ensure_inst(qw_plan_t p, int B) {
   HIP_TRY(hipMalloc(&p->d_inst, sizeof(InstParam) * cap));
   HIP_TRY(hipHostMalloc((void**)&p->h_inst, sizeof(InstParam) * cap, hipHostMallocDefault));
   p->inst_cap = cap;
+  return QW_OK;
+}
+
+qw_status ensure_coefs(qw_plan_t p, int B) {
+  if (p->coefs_cap >= B) return QW_OK;
+  if (p->d_coefs) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(p->d_coefs));
+    HIP_TRY(hipHostFree(p->h_coefs));
+    p->d_coefs = nullptr;
+    p->h_coefs = nullptr;
+    p->coefs_cap = 0;
+  }
+  int cap = 16;
+  while (cap < B) cap <<= 1;
+  const size_t one = sizeof(StencilCoef<double>);
+  HIP_TRY(hipMalloc(&p->d_coefs, one * cap));
+  HIP_TRY(hipHostMalloc((void**)&p->h_coefs, one * cap, hipHostMallocDefault));
+  p->coefs_cap = cap;
   return QW_OK;
 }
 
@@ -821,17 +854,7 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
   }
 
   // Rank-one pattern of the 3D neighbour blocks (lets the stencil skip zeros).
-  if (dim == 3) {
-    bool ok = true;
-    for (int k = 0; k < 8; ++k) {
-      const int ur = k < 4 ? 1 : 0, lc = k < 4 ? 0 : 1;
-      for (int j = 0; j < 2; ++j) {
-        const cx<double> a = p->coef_d.up[k][ur][j], b = p->coef_d.lo[k][j][lc];
-        if (a.x != 0.0 || a.y != 0.0 || b.x != 0.0 || b.y != 0.0) ok = false;
-      }
-    }
-    p->sparse3 = ok;
-  }
+  if (dim == 3) p->sparse3 = coef_sparse3(p->coef_d);
 
   // Fourier schedule.
   if (dim == 1 && N[0] > 4096) {
@@ -876,6 +899,12 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
     if (r == QW_OK) r = upload((void**)&p->d_cs, cs.data(), cs.size() * sizeof(double));
     if (r == QW_OK) r = upload((void**)&p->d_csf, csf.data(), csf.size() * sizeof(float));
     if (r == QW_OK) {
+      if (p->dbl)
+        r = upload(&p->d_coef, &p->coef_d, sizeof(p->coef_d));
+      else
+        r = upload(&p->d_coef, &p->coef_f, sizeof(p->coef_f));
+    }
+    if (r == QW_OK) {
       const int64_t nfp = ((int64_t)p->s * fused_obs_blocks(p) + 64) * kObsFields;
       p->partials_len = std::max<int64_t>((int64_t)kObsFields * kObsBlocks, nfp);
       hipError_t e = hipMalloc(&p->d_partials, sizeof(double) * p->partials_len);
@@ -907,15 +936,7 @@ qw_status qw_destroy(qw_plan_t p) {
   return QW_OK;
 }
 
-qw_status qw_step(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!psi) return fail(QW_ERR_INVALID, "psi is NULL");
-  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
-  if (nsteps == 0) return QW_OK;
-  hipStream_t st = (hipStream_t)stream;
-  r = ensure_scratch(p, p->field_bytes);
-  if (r != QW_OK) return r;
+static StencilGeom stencil_geom(qw_plan_t p) {
   StencilGeom g;
   g.dim = p->dim;
   for (int i = 0; i < 3; ++i) {
@@ -924,17 +945,85 @@ qw_status qw_step(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
   }
   g.V = p->V;
   g.sparse3 = p->sparse3 ? 1 : 0;
-  const void* coef = p->dbl ? (const void*)&p->coef_d : (const void*)&p->coef_f;
+  return g;
+}
+
+// nsteps steps of B fields in place with device coefficients `coefs`: the
+// LDS-resident kernel where a 1D field fits (at most 4096 steps per launch),
+// otherwise one launch per step, ping-ponging with the plan's scratch.
+static qw_status step_impl(qw_plan_t p, const StencilGeom& g, int B, void* psi,
+                           const void* coefs, int64_t nsteps, hipStream_t st) {
+  if (step1d_resident_ok(p->dbl, g)) {
+    for (int64_t done = 0; done < nsteps;) {
+      const int64_t k = std::min<int64_t>(4096, nsteps - done);
+      HIP_TRY(launch_step1d_resident(p->dbl, g, B, psi, coefs, k, st));
+      done += k;
+    }
+    return QW_OK;
+  }
+  const size_t bytes = p->field_bytes * (size_t)B;
+  qw_status r = ensure_scratch(p, bytes);
+  if (r != QW_OK) return r;
   void* a = psi;
   void* b = p->d_scratch;
   for (int64_t k = 0; k < nsteps; ++k) {
-    HIP_TRY(launch_step(p->dbl, g, b, a, coef, st));
+    HIP_TRY(launch_step(p->dbl, g, B, b, a, coefs, st));
     void* t = a;
     a = b;
     b = t;
   }
-  if (a != psi) HIP_TRY(hipMemcpyAsync(psi, a, p->field_bytes, hipMemcpyDeviceToDevice, st));
+  if (a != psi) HIP_TRY(hipMemcpyAsync(psi, a, bytes, hipMemcpyDeviceToDevice, st));
   return QW_OK;
+}
+
+qw_status qw_step(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi) return fail(QW_ERR_INVALID, "psi is NULL");
+  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+  if (nsteps == 0) return QW_OK;
+  return step_impl(p, stencil_geom(p), 1, psi, p->d_coef, nsteps, (hipStream_t)stream);
+}
+
+qw_status qw_step_batched(qw_plan_t p, int B, void* psi, const double* m, int64_t nsteps,
+                          void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (B < 0 || B > 65535) return fail(QW_ERR_INVALID, "B must lie in [0, 65535]");
+  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+  if (B == 0 || nsteps == 0) return QW_OK;
+  if (!psi || !m) return fail(QW_ERR_INVALID, "NULL argument");
+  for (int b = 0; b < B; ++b)
+    if (!(m[b] >= 0.0 && m[b] <= 1.0)) return fail(QW_ERR_INVALID, "m[%d] outside [0, 1]", b);
+  hipStream_t st = (hipStream_t)stream;
+  // Per-instance transition matrices, derived and packed exactly as the
+  // plan's own (an instance with the plan's mass gets the plan's numbers).
+  StencilGeom g = stencil_geom(p);
+  const size_t one = p->dbl ? sizeof(StencilCoef<double>) : sizeof(StencilCoef<float>);
+  r = ensure_coefs(p, B);
+  if (r != QW_OK) return r;
+  // The pinned staging area may still feed an earlier call's copy.
+  HIP_TRY(hipStreamSynchronize(st));
+  bool sparse = p->dim == 3;
+  for (int b = 0; b < B; ++b) {
+    Table T;
+    const double leak = derive_table(p->dim, m[b], T);
+    if (leak > 1e-14 || unitarity_defect(T) > 1e-13)
+      return fail(QW_ERR_DEVICE, "derived transition matrices fail checks for m[%d]", b);
+    StencilCoef<double> cd;
+    StencilCoef<float> cf;
+    std::string why;
+    if (!pack_coef<double>(T, m[b], cd, why) || !pack_coef<float>(T, m[b], cf, why))
+      return fail(QW_ERR_DEVICE, "transition matrices for m[%d]: %s", b, why.c_str());
+    if (sparse && !coef_sparse3(cd)) sparse = false;
+    if (p->dbl)
+      memcpy(p->h_coefs + one * b, &cd, one);
+    else
+      memcpy(p->h_coefs + one * b, &cf, one);
+  }
+  g.sparse3 = sparse ? 1 : 0;
+  HIP_TRY(hipMemcpyAsync(p->d_coefs, p->h_coefs, one * B, hipMemcpyHostToDevice, st));
+  return step_impl(p, g, B, psi, p->d_coefs, nsteps, st);
 }
 
 qw_status qw_evolve_fft(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, void* stream) {

@@ -95,8 +95,15 @@ hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const voi
 hipError_t launch_omega_table(const PassGeom& g, int64_t L, double* omega, hipStream_t st);
 hipError_t launch_transpose(bool dbl, void* out, const void* in, int64_t planes, int64_t R,
                             int64_t C, hipStream_t st);
-hipError_t launch_step(bool dbl, const StencilGeom& g, void* out, const void* in,
-                       const void* coef, hipStream_t st);
+// One step of B fields back to back; coefs: DEVICE array of B StencilCoef of
+// the field precision (instance b uses coefs[b]). B <= 65535.
+hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
+                       const void* coefs, hipStream_t st);
+// 1D lattices with 2 N b <= 160 KB and N <= 8192: nsteps steps of B fields in
+// place, each field held in LDS by one workgroup.
+bool step1d_resident_ok(bool dbl, const StencilGeom& g);
+hipError_t launch_step1d_resident(bool dbl, const StencilGeom& g, int B, void* psi,
+                                  const void* coefs, int64_t nsteps, hipStream_t st);
 
 // Reductions over B fields of one shape. Instance b's origin is
 // origins[3b..3b+2] if `origins` is given, else c[] (B = 1).

@@ -22,27 +22,95 @@ __device__ __forceinline__ cx<T> fma_c(cx<T> acc, cx<T> a, cx<T> b) {
   return acc;
 }
 
+// One 1D site: U_{+1} acts on psi(n+1) (r), U_{-1} on psi(n-1) (l), U_0 on
+// psi(n) (p). Shared by the streaming and the LDS-resident kernels, so both
+// give bitwise the same result.
 template <typename T>
-__global__ __launch_bounds__(256) void k_step1d(cx<T>* __restrict__ out, const cx<T>* __restrict__ in,
-                                               StencilGeom g, StencilCoef<T> C) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.V) return;
-  const int64_t msk = g.N[0] - 1;
-  const int64_t r = (n + 1) & msk, l = (n - 1) & msk;
-  const int64_t V = g.V;
-  const cx<T> p0 = in[n], p1 = in[V + n];
-  const cx<T> r0 = in[r], r1 = in[V + r];
-  const cx<T> l0 = in[l], l1 = in[V + l];
-  cx<T> a0 = mk((T)0, (T)0), a1 = a0;
-  // U_{+1} acts on psi(n+1), U_{-1} on psi(n-1), U_0 on psi(n).
+__device__ __forceinline__ void site1d(const StencilCoef<T>& C, cx<T> p0, cx<T> p1, cx<T> r0,
+                                       cx<T> r1, cx<T> l0, cx<T> l1, cx<T>& a0, cx<T>& a1) {
+  a0 = mk((T)0, (T)0);
+  a1 = a0;
   a0 = fma_c(a0, C.up[0][0][0], r0); a0 = fma_c(a0, C.up[0][0][1], r1);
   a1 = fma_c(a1, C.up[0][1][0], r0); a1 = fma_c(a1, C.up[0][1][1], r1);
   a0 = fma_c(a0, C.up[1][0][0], l0); a0 = fma_c(a0, C.up[1][0][1], l1);
   a1 = fma_c(a1, C.up[1][1][0], l0); a1 = fma_c(a1, C.up[1][1][1], l1);
   a0 = fma_c(a0, C.onsite[0][0], p0); a0 = fma_c(a0, C.onsite[0][1], p1);
   a1 = fma_c(a1, C.onsite[1][0], p0); a1 = fma_c(a1, C.onsite[1][1], p1);
+}
+
+// Instance blockIdx.y of a batch of fields back to back, with its own
+// coefficients coefs[blockIdx.y].
+template <typename T>
+__global__ __launch_bounds__(256) void k_step1d(cx<T>* __restrict__ out_all,
+                                               const cx<T>* __restrict__ in_all, StencilGeom g,
+                                               const StencilCoef<T>* __restrict__ coefs) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.V) return;
+  const int64_t V = g.V;
+  const cx<T>* __restrict__ in = in_all + (int64_t)blockIdx.y * 2 * V;
+  cx<T>* __restrict__ out = out_all + (int64_t)blockIdx.y * 2 * V;
+  const StencilCoef<T> C = coefs[blockIdx.y];
+  const int64_t msk = g.N[0] - 1;
+  const int64_t r = (n + 1) & msk, l = (n - 1) & msk;
+  cx<T> a0, a1;
+  site1d(C, in[n], in[V + n], in[r], in[V + r], in[l], in[V + l], a0, a1);
   out[n] = a0;
   out[V + n] = a1;
+}
+
+// 1D lattices whose field fits in LDS: one workgroup per instance keeps the
+// field in LDS for all `nsteps` steps (one global read and write in total).
+// Each thread updates sites tid, tid + blockDim, ...: new values are formed
+// in registers from the LDS copy, then written back after a barrier.
+constexpr int kResThreads = 1024;
+// Sites per thread: N <= 8192 (complex64) or 4096 (complex128), the sizes
+// whose two components fit in 160 KB of LDS.
+template <typename T>
+constexpr int res_max_sites() { return sizeof(T) == 4 ? 8 : 4; }
+
+template <typename T>
+__global__ __launch_bounds__(kResThreads) void k_step1d_resident(
+    cx<T>* __restrict__ psi_all, StencilGeom g, const StencilCoef<T>* __restrict__ coefs,
+    int64_t nsteps) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* f0 = reinterpret_cast<cx<T>*>(smem_raw);
+  const int N = (int)g.N[0];
+  cx<T>* f1 = f0 + N;
+  cx<T>* __restrict__ psi = psi_all + (int64_t)blockIdx.y * 2 * N;
+  const StencilCoef<T> C = coefs[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int msk = N - 1;
+  for (int n = tid; n < N; n += kResThreads) {
+    f0[n] = psi[n];
+    f1[n] = psi[N + n];
+  }
+  __syncthreads();
+  constexpr int MS = res_max_sites<T>();
+  for (int64_t k = 0; k < nsteps; ++k) {
+    cx<T> a0[MS], a1[MS];
+#pragma unroll
+    for (int j = 0; j < MS; ++j) {
+      const int n = tid + j * kResThreads;
+      if (n < N) {
+        const int r = (n + 1) & msk, l = (n - 1) & msk;
+        site1d(C, f0[n], f1[n], f0[r], f1[r], f0[l], f1[l], a0[j], a1[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < MS; ++j) {
+      const int n = tid + j * kResThreads;
+      if (n < N) {
+        f0[n] = a0[j];
+        f1[n] = a1[j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int n = tid; n < N; n += kResThreads) {
+    psi[n] = f0[n];
+    psi[N + n] = f1[n];
+  }
 }
 
 __device__ constexpr int kOff2[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
@@ -50,11 +118,15 @@ __device__ constexpr int kOff3[8][3] = {{1, 0, 0},  {0, -1, 0}, {0, 0, -1}, {-1,
                                         {-1, 0, 0}, {0, 1, 0},  {0, 0, 1},  {1, 1, 1}};
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_step_nd(cx<T>* __restrict__ out, const cx<T>* __restrict__ in,
-                                                StencilGeom g, StencilCoef<T> C) {
+__global__ __launch_bounds__(256) void k_step_nd(cx<T>* __restrict__ out_all,
+                                                const cx<T>* __restrict__ in_all, StencilGeom g,
+                                                const StencilCoef<T>* __restrict__ coefs) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.V) return;
   const int64_t V = g.V;
+  const cx<T>* __restrict__ in = in_all + (int64_t)blockIdx.y * 4 * V;
+  cx<T>* __restrict__ out = out_all + (int64_t)blockIdx.y * 4 * V;
+  const StencilCoef<T> C = coefs[blockIdx.y];
   int64_t n[3];
   const int64_t m[3] = {g.N[0] - 1, g.N[1] - 1, g.N[2] - 1};
   if constexpr (DIM == 3) {
@@ -180,12 +252,16 @@ __device__ __forceinline__ void store_plane(const PlaneRegs<T>& R, cx<T>* ring, 
 }
 
 template <typename T, int PF, bool SPARSE>
-__global__ __launch_bounds__(kStepThreads) void k_step3d_ring(cx<T>* __restrict__ out,
-                                                             const cx<T>* __restrict__ in,
-                                                             StencilGeom g, StencilCoef<T> C,
+__global__ __launch_bounds__(kStepThreads) void k_step3d_ring(cx<T>* __restrict__ out_all,
+                                                             const cx<T>* __restrict__ in_all,
+                                                             StencilGeom g,
+                                                             const StencilCoef<T>* __restrict__ coefs,
                                                              int chunk, int64_t tiles2,
                                                              int64_t tiles3, int64_t nchunks) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const cx<T>* __restrict__ in = in_all + (int64_t)blockIdx.y * 4 * g.V;
+  cx<T>* __restrict__ out = out_all + (int64_t)blockIdx.y * 4 * g.V;
+  const StencilCoef<T> C = coefs[blockIdx.y];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   constexpr int PL = 4 * kPlaneSites;  // elements per ring plane
   const int tid = threadIdx.x;
@@ -292,8 +368,8 @@ bool step3d_ring_ok(const StencilGeom& g) {
   return g.dim == 3 && g.N[1] >= kTN2 && g.N[2] >= kTN3 && g.N[0] >= 4;
 }
 
-hipError_t launch_step3d_ring(bool dbl, const StencilGeom& g, void* out, const void* in,
-                              const void* coef, hipStream_t st) {
+hipError_t launch_step3d_ring(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
+                              const void* coefs, hipStream_t st) {
   const int64_t tiles2 = g.N[1] / kTN2, tiles3 = g.N[2] / kTN3;
   // Chunks of 32 planes where that leaves at least ~2 workgroups per CU slot.
   int chunk = g.N[0] * tiles2 * tiles3 >= 32 * 1024 ? 32 : 16;
@@ -307,9 +383,9 @@ hipError_t launch_step3d_ring(bool dbl, const StencilGeom& g, void* out, const v
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kStepThreads), lds, st, (cx<double>*)out,
-                       (const cx<double>*)in, g, *(const StencilCoef<double>*)coef, chunk, tiles2,
-                       tiles3, nchunks);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk, (unsigned)B), dim3(kStepThreads), lds, st,
+                       (cx<double>*)out, (const cx<double>*)in, g,
+                       (const StencilCoef<double>*)coefs, chunk, tiles2, tiles3, nchunks);
   } else {
     const size_t lds = 3 * 4 * kPlaneSites * sizeof(cx<float>);
     auto kern = g.sparse3 ? k_step3d_ring<float, 2, true> : k_step3d_ring<float, 2, false>;
@@ -318,31 +394,64 @@ hipError_t launch_step3d_ring(bool dbl, const StencilGeom& g, void* out, const v
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kStepThreads), lds, st, (cx<float>*)out,
-                       (const cx<float>*)in, g, *(const StencilCoef<float>*)coef, chunk, tiles2,
-                       tiles3, nchunks);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk, (unsigned)B), dim3(kStepThreads), lds, st,
+                       (cx<float>*)out, (const cx<float>*)in, g, (const StencilCoef<float>*)coefs,
+                       chunk, tiles2, tiles3, nchunks);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step(bool dbl, const StencilGeom& g, void* out, const void* in,
-                       const void* coef, hipStream_t st) {
-  if (step3d_ring_ok(g)) return launch_step3d_ring(dbl, g, out, in, coef, st);
-  const unsigned nblk = (unsigned)((g.V + 255) / 256);
+hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
+                       const void* coefs, hipStream_t st) {
+  if (B < 1 || B > 65535) return hipErrorInvalidValue;
+  if (step3d_ring_ok(g)) return launch_step3d_ring(dbl, g, B, out, in, coefs, st);
+  const dim3 grid((unsigned)((g.V + 255) / 256), (unsigned)B);
   if (dbl) {
-    const StencilCoef<double>& C = *(const StencilCoef<double>*)coef;
+    auto C = (const StencilCoef<double>*)coefs;
     auto o = (cx<double>*)out;
     auto i = (const cx<double>*)in;
-    if (g.dim == 1) hipLaunchKernelGGL(k_step1d<double>, dim3(nblk), dim3(256), 0, st, o, i, g, C);
-    else if (g.dim == 2) hipLaunchKernelGGL((k_step_nd<double, 2>), dim3(nblk), dim3(256), 0, st, o, i, g, C);
-    else hipLaunchKernelGGL((k_step_nd<double, 3>), dim3(nblk), dim3(256), 0, st, o, i, g, C);
+    if (g.dim == 1) hipLaunchKernelGGL(k_step1d<double>, grid, dim3(256), 0, st, o, i, g, C);
+    else if (g.dim == 2) hipLaunchKernelGGL((k_step_nd<double, 2>), grid, dim3(256), 0, st, o, i, g, C);
+    else hipLaunchKernelGGL((k_step_nd<double, 3>), grid, dim3(256), 0, st, o, i, g, C);
   } else {
-    const StencilCoef<float>& C = *(const StencilCoef<float>*)coef;
+    auto C = (const StencilCoef<float>*)coefs;
     auto o = (cx<float>*)out;
     auto i = (const cx<float>*)in;
-    if (g.dim == 1) hipLaunchKernelGGL(k_step1d<float>, dim3(nblk), dim3(256), 0, st, o, i, g, C);
-    else if (g.dim == 2) hipLaunchKernelGGL((k_step_nd<float, 2>), dim3(nblk), dim3(256), 0, st, o, i, g, C);
-    else hipLaunchKernelGGL((k_step_nd<float, 3>), dim3(nblk), dim3(256), 0, st, o, i, g, C);
+    if (g.dim == 1) hipLaunchKernelGGL(k_step1d<float>, grid, dim3(256), 0, st, o, i, g, C);
+    else if (g.dim == 2) hipLaunchKernelGGL((k_step_nd<float, 2>), grid, dim3(256), 0, st, o, i, g, C);
+    else hipLaunchKernelGGL((k_step_nd<float, 3>), grid, dim3(256), 0, st, o, i, g, C);
+  }
+  return hipGetLastError();
+}
+
+bool step1d_resident_ok(bool dbl, const StencilGeom& g) {
+  const int ms = dbl ? res_max_sites<double>() : res_max_sites<float>();
+  return g.dim == 1 && g.N[0] <= (int64_t)kResThreads * ms &&
+         2 * g.N[0] * (dbl ? 16 : 8) <= 160 * 1024;
+}
+
+hipError_t launch_step1d_resident(bool dbl, const StencilGeom& g, int B, void* psi,
+                                  const void* coefs, int64_t nsteps, hipStream_t st) {
+  if (!step1d_resident_ok(dbl, g) || B < 1 || B > 65535) return hipErrorInvalidValue;
+  const size_t lds = 2 * (size_t)g.N[0] * (dbl ? 16 : 8);
+  if (dbl) {
+    auto kern = k_step1d_resident<double>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(1, (unsigned)B), dim3(kResThreads), lds, st, (cx<double>*)psi,
+                       g, (const StencilCoef<double>*)coefs, nsteps);
+  } else {
+    auto kern = k_step1d_resident<float>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(1, (unsigned)B), dim3(kResThreads), lds, st, (cx<float>*)psi, g,
+                       (const StencilCoef<float>*)coefs, nsteps);
   }
   return hipGetLastError();
 }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libqw.so")
 QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE = range(5)
 QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
-EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_evolve_fft", "qw_evolve_fft_batched",
+EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables",
            "qw_prepare_state",
            "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
@@ -70,6 +70,7 @@ def _load():
         "qw_plan": [ctypes.POINTER(vp), cint, ctypes.POINTER(i64), dbl, cint, vp],
         "qw_destroy": [vp],
         "qw_step": [vp, vp, i64, vp],
+        "qw_step_batched": [vp, cint, vp, ctypes.POINTER(dbl), i64, vp],
         "qw_evolve_fft": [vp, vp, vp, i64, vp],
         "qw_evolve_fft_timed": [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_float),
                                 ctypes.POINTER(cint)],
@@ -180,6 +181,14 @@ class Plan:
     def step(self, psi, nsteps, stream=None):
         """qw_step: nsteps position-space steps, in place."""
         _check(LIB.qw_step(self._h, self._field(psi, name="psi"), int(nsteps), _stream(stream)))
+        return psi
+
+    def step_batched(self, psi, m, nsteps, stream=None):
+        """qw_step_batched: nsteps steps of B = len(m) fields (shape (B,) +
+        self.shape, contiguous) in place, instance b with mass m[b]."""
+        B = len(m)
+        _check(LIB.qw_step_batched(self._h, B, self._field(psi, batch=B, name="psi"),
+                                   _darr(m, B), int(nsteps), _stream(stream)))
         return psi
 
     def evolve_fft(self, psi0, t, out=None, stream=None):
