@@ -9,6 +9,8 @@
 // LDS for the exchanges between radix stages. The column index is the
 // fastest-varying thread index, so LDS is addressed [pos][column]: the lanes
 // of a wave touch consecutive words.
+#include <algorithm>
+
 #include "qw_internal.h"
 
 namespace qw {
@@ -172,14 +174,15 @@ __global__ __launch_bounds__(1024) void k_fft_strided_obs(cx<T>* __restrict__ ou
   double org[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) org[a] = f.origins ? f.origins[3 * b + a] : f.c[a];
-  const AxisImage a0 = axis_image(org[0], f.N[0]);
-  // Along the pass only the axis-0 displacement varies: accumulate the
-  // zeroth, first and second moments in it, the other axes are per column.
+  const AxisImage32 a0 = axis_image32(axis_image(org[0], f.N[0]));
+  // (1) Over the thread's elements: only the axis-0 displacement varies
+  // along the pass, so three moments in it suffice (the other axes are
+  // fixed per column).
   double S0 = 0.0, S1 = 0.0, S11 = 0.0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int64_t pos = t + TT * e;
-    const double w = min_image(f.dim == 1 ? pos * I + col : pos, a0);
+    const int pos = t + TT * e;
+    const double w = min_image32(f.dim == 1 ? pos * (int)I + (int)col : pos, a0);
     const double x = (double)v[e].x, y = (double)v[e].y;
     const double pr = x * x + y * y;
     const double wp = w * pr;
@@ -187,16 +190,65 @@ __global__ __launch_bounds__(1024) void k_fft_strided_obs(cx<T>* __restrict__ ou
     S1 += wp;
     S11 += w * wp;
   }
-  double wb = 0.0, wc = 0.0;
-  if (f.dim == 2) {
-    wb = min_image(col, axis_image(org[1], f.N[1]));
-  } else if (f.dim == 3) {
-    wb = min_image(col >> f.lg[2], axis_image(org[1], f.N[1]));
-    wc = min_image(col & (f.N[2] - 1), axis_image(org[2], f.N[2]));
+  // (2) Over the TT threads of each column, through LDS (free once the
+  // transform is done; the launch sizes it for 3 doubles per thread).
+  const int nth = TT * P;
+  double* red = reinterpret_cast<double*>(smem_raw);
+  __syncthreads();
+  red[tid] = S0;
+  red[nth + tid] = S1;
+  red[2 * nth + tid] = S11;
+  __syncthreads();
+  double acc[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+  if (tid < P) {
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+    for (int r = 0; r < TT; ++r) {
+      const int i = r * P + tid;
+      c0 += red[i];
+      c1 += red[nth + i];
+      c2 += red[2 * nth + i];
+    }
+    const int64_t cc = col - p + tid;  // the column these sums belong to
+    double wb = 0.0, wc = 0.0;
+    if (f.dim == 2) {
+      wb = min_image(cc, axis_image(org[1], f.N[1]));
+    } else if (f.dim == 3) {
+      wb = min_image(cc >> f.lg[2], axis_image(org[1], f.N[1]));
+      wc = min_image(cc & (f.N[2] - 1), axis_image(org[2], f.N[2]));
+    }
+    acc[0] = c0;
+    acc[1] = c1;
+    acc[2] = wb * c0;
+    acc[3] = wc * c0;
+    acc[4] = c2;
+    acc[5] = wb * wb * c0;
+    acc[6] = wc * wc * c0;
+    acc[7] = wb * c1;
+    acc[8] = wc * c1;
+    acc[9] = wb * wc * c0;
   }
-  double acc[kObsFields] = {S0,      S1,      wb * S0, wc * S0,      S11, wb * wb * S0, wc * wc * S0,
-                            wb * S1, wc * S1, wb * wc * S0, 0.0, 0.0, 0.0};
-  block_reduce_store<kObsFields>(acc, f.partials + blk * kObsFields);
+  // (3) Over the columns: only the waves holding column sums shuffle.
+  __shared__ double red2[10][16];
+  const int lane = tid & 63, wave = tid >> 6;
+  const int nwc = (P + 63) >> 6;
+  if (wave < nwc) {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      double vv = acc[k];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) vv += __shfl_down(vv, off, 64);
+      if (lane == 0) red2[k][wave] = vv;
+    }
+  }
+  __syncthreads();
+  if (tid < kObsFields) {
+    double sum = 0.0;
+    if (tid < 10)
+      for (int w = 0; w < nwc; ++w) sum += red2[tid][w];
+    f.partials[blk * kObsFields + tid] = sum;
+  }
 }
 
 template <typename T, int L>
@@ -208,7 +260,8 @@ static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int
   const int P = strided_cols<T, L>(I);
   if (TT * P > 1024 || (TT * P) % 64 != 0) return hipErrorInvalidValue;
   const int lgP = ilog2(P);
-  const size_t lds = (size_t)P * L * sizeof(cx<T>);
+  // the transform's exchanges, then 3 doubles per thread for the reduction
+  const size_t lds = std::max((size_t)P * L * sizeof(cx<T>), (size_t)TT * P * 3 * sizeof(double));
   auto kern = k_fft_strided_obs<T, L, E>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,

@@ -148,6 +148,28 @@ __device__ __forceinline__ double min_image(int64_t n, const AxisImage& a) {
   return (double)(((n - a.ci + a.half - 1) & a.mask) - a.half) + (1.0 - a.cf);
 }
 
+// The same for 0 <= n < 2^30 in 32-bit arithmetic (the image depends on ci
+// only modulo N, and N <= 2^16 here), for per-element use in hot loops.
+struct AxisImage32 {
+  int ci, half, mask;
+  double cf1;  // 1 - cf, or 0 when cf = 0
+  int off;     // 0 when cf = 0, else 1
+};
+
+__device__ __forceinline__ AxisImage32 axis_image32(const AxisImage& a) {
+  AxisImage32 b;
+  b.ci = (int)(a.ci & a.mask);
+  b.half = (int)a.half;
+  b.mask = (int)a.mask;
+  b.off = a.cf == 0.0 ? 0 : 1;
+  b.cf1 = a.cf == 0.0 ? 0.0 : 1.0 - a.cf;
+  return b;
+}
+
+__device__ __forceinline__ double min_image32(int n, const AxisImage32& a) {
+  return (double)(((n - a.ci + a.half - a.off) & a.mask) - a.half) + a.cf1;
+}
+
 // Block sum of NF doubles per thread, for blockDim.x a multiple of 64 up to
 // 1024; thread f < NF writes field f to dst[f].
 template <int NF>
