@@ -1,0 +1,94 @@
+"""Parity at the full sizes of the timed workloads, in the launch
+configuration the benchmark uses (the autotuned Fourier schedule).
+
+256^3 complex64 (the headline workload): the GPU stencil and the GPU Fourier
+jump are compared with the FP64 oracle's position-space steps on the whole
+field (two steps: about 16 s of host time), the fused reductions with the
+oracle's reductions of that field, and the evolution is checked to be
+reversible at t = 1e5. 512^3 (the large workload): complex64 against
+complex128 at t = 1e6 and the Fourier jump against a stencil step, on the
+whole field."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import observables as ob, stepper, walk
+from paper_1603_06442_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1603_06442_amd import qw as mod
+    return mod
+
+
+def rel(a, b):
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def test_bcc256_c64_against_oracle_steps(qw):
+    w = inputs.workload(2)
+    plan = qw.Plan(3, w["N"], w["m"], "c64")
+    x = plan.empty()
+    plan.prepare_state(x, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
+    plan.autotune()
+    torch.cuda.synchronize()
+    psi0 = x.cpu().numpy().astype(np.complex128)
+    ref = stepper.evolve_steps(psi0, walk.stencil_table(3, w["m"]), 2)
+    # stencil
+    y = x.clone()
+    plan.step(y, 2)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.complex128)
+    assert ob.rel_l2(got, ref) < 2e-5
+    del got, y
+    # Fourier jump with the fused reductions
+    z = plan.empty()
+    o = plan.evolve_fft_observables(x, 2, w["center"], out=z)
+    torch.cuda.synchronize()
+    got = z.cpu().numpy().astype(np.complex128)
+    assert ob.rel_l2(got, ref) < 2e-5
+    want = ob.observables(ref, w["center"])
+    assert abs(o["norm2"] - want["norm2"]) < 1e-5
+    assert np.allclose(o["mean"], want["mean"], rtol=0, atol=1e-4)
+    assert np.allclose(o["mean_cart"], want["mean_cart"], rtol=0, atol=1e-4)
+    assert np.allclose(o["second"], want["second"], rtol=1e-4, atol=1e-3)
+
+
+def test_bcc256_c64_reversible_at_large_t(qw):
+    w = inputs.workload(2)
+    plan = qw.Plan(3, w["N"], w["m"], "c64")
+    x = plan.empty()
+    plan.prepare_state(x, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
+    plan.autotune()
+    t = 100000
+    y = plan.evolve_fft(x, t)
+    back = plan.evolve_fft(y, -t)
+    assert rel(back, x) < 2e-5
+    o = plan.evolve_fft_observables(x, t, w["center"])
+    assert abs(o["norm2"] - 1.0) < 2e-5
+
+
+def test_bcc512_c64_vs_c128_and_jump_vs_step(qw):
+    w = inputs.workload(4)
+    N = w["N"]
+    p64 = qw.Plan(3, N, w["m"], "c64")
+    p128 = qw.Plan(3, N, w["m"], "c128")
+    x128 = p128.empty()
+    p128.prepare_state(x128, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
+    x64 = x128.to(torch.complex64)
+    t = w["t"]
+    y128 = p128.evolve_fft(x128, t)
+    y64 = p64.evolve_fft(x64, t)
+    assert rel(y64.to(torch.complex128), y128) < 2e-5
+    assert abs(float(torch.linalg.vector_norm(y128)) ** 2 - 1.0) < 1e-9
+    del y128, y64
+    # one Fourier jump t = 1 against one stencil step (independent kernels)
+    s = x128.clone()
+    p128.step(s, 1)
+    j = p128.evolve_fft(x128, 1)
+    assert rel(j, s) < 1e-12
