@@ -23,9 +23,17 @@
  *   One field occupies s * V * (8 or 16) bytes and must be 16-byte aligned.
  *
  * Execution: every call is enqueued on `stream` (a hipStream_t; NULL is the
- * null stream) and returns without waiting, except qw_observables and
- * qw_prepare_state, which wait for their results. A plan may be used by one
- * stream at a time; distinct plans are independent.
+ * null stream) and returns without waiting, except qw_observables,
+ * qw_evolve_fft_observables and qw_prepare_state, which wait for their
+ * results, and the batched calls, which wait for `stream` before staging
+ * their per-instance parameters. A plan may be used by one stream at a
+ * time; distinct plans are independent.
+ *
+ * Graph capture: qw_step, qw_evolve_fft and qw_transform enqueue only
+ * kernels and device-to-device copies and never synchronise, so a caller may
+ * capture them into a HIP graph and replay it. Their first call on a plan
+ * may allocate (scratch, the omega table); make one call outside the
+ * capture first.
  *
  * Errors: every call returns a qw_status; nothing throws across the ABI.
  * qw_last_error() returns a message for the last failing call of the calling

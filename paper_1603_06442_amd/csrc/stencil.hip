@@ -4,6 +4,8 @@
 // The generic kernels use one thread per output site for all s components,
 // with neighbour reads served by L1/L2; large 3D lattices use the LDS-ring
 // kernel below.
+#include <algorithm>
+
 #include "qw_internal.h"
 
 namespace qw {
@@ -368,43 +370,39 @@ bool step3d_ring_ok(const StencilGeom& g) {
   return g.dim == 3 && g.N[1] >= kTN2 && g.N[2] >= kTN3 && g.N[0] >= 4;
 }
 
-hipError_t launch_step3d_ring(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
+// complex64 only: the complex128 ring kernel spills registers and ran slower
+// than one thread per site at every size measured (64^3: 72 vs 11 us,
+// 128^3: 115 vs 86 us per step).
+hipError_t launch_step3d_ring(const StencilGeom& g, int B, void* out, const void* in,
                               const void* coefs, hipStream_t st) {
   const int64_t tiles2 = g.N[1] / kTN2, tiles3 = g.N[2] / kTN3;
-  // Chunks of 32 planes where that leaves at least ~2 workgroups per CU slot.
-  int chunk = g.N[0] * tiles2 * tiles3 >= 32 * 1024 ? 32 : 16;
+  // Planes per workgroup: N2 N3 / 2048 within [2, 32], i.e. about 4 N1
+  // workgroups for cubic lattices. Measured best at 64^3 (2 planes: 8.0 us
+  // per step against 27.9 with 16), 128^3 (8: 28.9 against 32.7) and 256^3
+  // (32: 217 us).
+  const int64_t planeN = g.N[1] * g.N[2];
+  int chunk = (int)std::min<int64_t>(32, std::max<int64_t>(2, planeN / 2048));
   while (chunk > 2 && g.N[0] % chunk) chunk >>= 1;
   if (chunk > g.N[0]) chunk = (int)g.N[0];  // N1 >= 4 is a power of two: chunk >= 2 = PF
   const int64_t nchunks = g.N[0] / chunk;
   const int64_t nblk = tiles2 * tiles3 * nchunks;
-  if (dbl) {
-    const size_t lds = 3 * 4 * kPlaneSites * sizeof(cx<double>);
-    auto kern = g.sparse3 ? k_step3d_ring<double, 1, true> : k_step3d_ring<double, 1, false>;
+  const size_t lds = 3 * 4 * kPlaneSites * sizeof(cx<float>);
+  auto kern = g.sparse3 ? k_step3d_ring<float, 2, true> : k_step3d_ring<float, 2, false>;
+  if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk, (unsigned)B), dim3(kStepThreads), lds, st,
-                       (cx<double>*)out, (const cx<double>*)in, g,
-                       (const StencilCoef<double>*)coefs, chunk, tiles2, tiles3, nchunks);
-  } else {
-    const size_t lds = 3 * 4 * kPlaneSites * sizeof(cx<float>);
-    auto kern = g.sparse3 ? k_step3d_ring<float, 2, true> : k_step3d_ring<float, 2, false>;
-    if (lds > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk, (unsigned)B), dim3(kStepThreads), lds, st,
-                       (cx<float>*)out, (const cx<float>*)in, g, (const StencilCoef<float>*)coefs,
-                       chunk, tiles2, tiles3, nchunks);
   }
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk, (unsigned)B), dim3(kStepThreads), lds, st,
+                     (cx<float>*)out, (const cx<float>*)in, g, (const StencilCoef<float>*)coefs,
+                     chunk, tiles2, tiles3, nchunks);
   return hipGetLastError();
 }
 
 hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
                        const void* coefs, hipStream_t st) {
   if (B < 1 || B > 65535) return hipErrorInvalidValue;
-  if (step3d_ring_ok(g)) return launch_step3d_ring(dbl, g, B, out, in, coefs, st);
+  if (!dbl && step3d_ring_ok(g)) return launch_step3d_ring(g, B, out, in, coefs, st);
   const dim3 grid((unsigned)((g.V + 255) / 256), (unsigned)B);
   if (dbl) {
     auto C = (const StencilCoef<double>*)coefs;

@@ -78,8 +78,9 @@ def test_step_matches_oracle(qw, d, shape, m, dtype):
 @pytest.mark.parametrize("shape", [(8, 8, 64), (4, 16, 128), (32, 8, 64)])
 @pytest.mark.parametrize("m", [0.0, 0.3])
 def test_step_3d_plane_ring_matches_oracle(qw, shape, m, dtype):
-    """Lattices with N2 >= 8 and N3 >= 64 take the LDS plane-ring kernel
-    (tiles of 8 x 64, chunks along n1, periodic wrap in all three axes)."""
+    """complex64 lattices with N2 >= 8 and N3 >= 64 take the LDS plane-ring
+    kernel (tiles of 8 x 64, chunks along n1, periodic wrap in all three
+    axes); complex128 takes one thread per site."""
     psi0 = rand_field(3, shape, 31)
     plan = qw.Plan(3, list(shape), m, dtype)
     x = to_dev(psi0, plan)
@@ -395,3 +396,43 @@ def test_step_1d_on_chip_long_runs(qw, dtype):
     want = to_np(to_dev(psi0, p0))
     assert np.array_equal(got[0], np.roll(want[0], -nsteps))
     assert np.array_equal(got[1], np.roll(want[1], nsteps))
+
+
+@pytest.mark.parametrize("d,shape,dtype", [(3, (64, 64, 64), "c64"), (3, (16, 16, 16), "c128"),
+                                           (1, (8192,), "c64"), (2, (64, 32), "c64")])
+def test_capture_into_a_graph(qw, d, shape, dtype):
+    """qw_step and qw_evolve_fft, called once beforehand (so the plan has its
+    scratch and tables), can be captured into a HIP graph by the caller.
+    Each replay, with eager work and synchronisations between replays,
+    gives bitwise the eager result."""
+    plan = qw.Plan(d, list(shape), 0.07, dtype)
+    x0 = to_dev(rand_field(d, shape, 5), plan)
+    a = x0.clone()
+    b = plan.empty()
+    plan.step(a, 3)
+    plan.evolve_fft(a, 41, out=b)
+    torch.cuda.synchronize()
+    want_a, want_b = a.clone(), b.clone()
+    ga, gb = x0.clone(), plan.empty()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.step(ga.clone(), 3, stream=side)
+        plan.evolve_fft(ga, 41, out=gb, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        s = torch.cuda.current_stream()
+        plan.step(ga, 3, stream=s)
+        plan.evolve_fft(ga, 41, out=gb, stream=s)
+    for r in range(3):
+        ga.copy_(x0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ga, want_a), r
+        assert torch.equal(gb, want_b), r
+        e = x0.clone()  # eager work between replays
+        plan.step(e, 1)
+        torch.cuda.synchronize()
