@@ -116,9 +116,19 @@ qw_status qw_step_batched(qw_plan_t plan, int B, void* psi, const double* m, int
  * forward DFT with the sign of Sec. 4, per wave-vector the closed form
  * D_q^t = cos(omega t) I - i sin(omega t)/sin(omega) M_q (from
  * D_q = cos(omega) I - i M_q, Sec. 3.2 gamma-matrix form and interpolating
- * Hamiltonian), inverse DFT. Any int64 t; t < 0 gives U^{-|t|}. psi_t may
- * equal psi0 (in place); partial overlap is invalid. */
+ * Hamiltonian), inverse DFT. |t| <= 2^53 (else QW_ERR_UNSUPPORTED); t < 0
+ * gives U^{-|t|}. psi_t may equal psi0 (in place); partial overlap is
+ * invalid. */
 qw_status qw_evolve_fft(qw_plan_t plan, const void* psi0, void* psi_t, int64_t t, void* stream);
+
+/* The same for real t: the continuous-time evolution exp(-i H t) of Sec. 4
+ * that interpolates the walk (H the interpolating Hamiltonian of Sec. 3.2,
+ * eigenvalues +-omega(q) in [0, pi]); equal to qw_evolve_fft, bit for bit,
+ * at integer t. Where omega = pi (the band edge, reached only for m = 0)
+ * the two branches +-pi are averaged, giving cos(pi t) I there. t finite,
+ * |t| <= 2^53. */
+qw_status qw_evolve_fft_real(qw_plan_t plan, const void* psi0, void* psi_t, double t,
+                             void* stream);
 
 /* B independent instances of one plan shape, each with its own mass and time:
  * in and out hold B fields back to back (instance b at byte offset

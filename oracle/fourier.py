@@ -9,7 +9,9 @@ changes the result). With this sign a plane wave e^{-iq.n} v is the pure
 frequency q, and one step multiplies hat psi(q) by U_q = sum_h e^{-iq.h} U_h.
 
 U_q is summed directly from the transition-matrix table (not from any closed
-form), and U_q^t is formed by binary powering (U_q^dag for t < 0).
+form), and U_q^t is formed by binary powering (U_q^dag for t < 0); for real
+t (the continuous-time interpolation of Sec. 4, psi(t) with e^{-i H(k) t})
+by diagonalising U_q.
 """
 import numpy as np
 
@@ -63,4 +65,34 @@ def evolve_fourier(psi, table, t):
     """U^t psi by DFT, per-q binary powering of U_q, inverse DFT."""
     d = psi.ndim - 1
     Dt = matpow(symbol_grid(table, psi.shape[1:], d), t)
+    return idft(apply_symbol(Dt, dft(psi)))
+
+
+def matpow_real(D, t):
+    """D^t for real t and a stack of unitary D[..., s, s]: exp(-i t H) with
+    D = exp(-i H) and the spectrum of H in [-pi, pi] (the continuous-time
+    interpolation of Sec. 4, exact at integer t). D is diagonalised in an
+    orthonormal basis through the commuting Hermitian parts A = (D + D^dag)/2,
+    B = (D - D^dag)/2i: the eigenvectors of A + c B for a generic c are
+    eigenvectors of D. An eigenvalue -1 (phase pi, reached only at the band
+    edge when m = 0) has two one-sided limits e^{+-i pi t}; their average
+    cos(pi t) is taken."""
+    t = float(t)
+    Dh = np.conj(np.swapaxes(D, -1, -2))
+    A = (D + Dh) / 2
+    B = (D - Dh) / 2j
+    _, V = np.linalg.eigh(A + 0.7390851332151607 * B)
+    lam = np.einsum("...ji,...jk,...ki->...i", np.conj(V), D, V)
+    theta = np.angle(lam)
+    f = np.exp(1j * t * theta)
+    edge = np.abs(lam + 1.0) < 1e-12
+    f = np.where(edge, np.cos(np.pi * t), f)
+    return V @ (f[..., :, None] * np.conj(np.swapaxes(V, -1, -2)))
+
+
+def evolve_fourier_real(psi, table, t):
+    """U^t psi for real t: DFT, per-q exp(-i t H_q) by diagonalisation,
+    inverse DFT."""
+    d = psi.ndim - 1
+    Dt = matpow_real(symbol_grid(table, psi.shape[1:], d), t)
     return idft(apply_symbol(Dt, dft(psi)))

@@ -37,8 +37,8 @@ namespace qw {
 // p + pl (FMA remainder), then 2 pi is removed in two parts (Cody-Waite:
 // 2 pi = HI + LO with HI the double nearest 2 pi). For |k| < 2^20 the first
 // FMA is exact, so the reduced angle keeps the accuracy of omega itself.
-__device__ __forceinline__ double reduced_phase(double w, int64_t t) {
-  const double tt = (double)t;
+// t is any real (integer t are exact up to 2^53).
+__device__ __forceinline__ double reduced_phase(double w, double tt) {
   const double p = w * tt;
   const double pl = fma(w, tt, -p);
   const double k = rint(p * 0.15915494309189533577);

@@ -877,8 +877,14 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
     std::vector<double> cs((size_t)4 * Nc);
     for (int64_t j = 0; j < 2 * Nc; ++j) {
       const long double a = 3.14159265358979323846264338327950288L * (long double)j / (long double)Nc;
-      cs[(size_t)2 * j] = (double)cosl(a);
-      cs[(size_t)2 * j + 1] = (double)sinl(a);
+      double c = (double)cosl(a), sn = (double)sinl(a);
+      // exact zeros at multiples of pi/2 (the smallest other |value| is
+      // sin(pi / 65536) ~ 5e-5), so that n~ vanishes exactly at the band
+      // edge q = pi and sin(omega) = 0 there when m = 0
+      if (std::fabs(c) < 1e-15) c = 0.0;
+      if (std::fabs(sn) < 1e-15) sn = 0.0;
+      cs[(size_t)2 * j] = c;
+      cs[(size_t)2 * j + 1] = sn;
     }
     if (p->dbl) {
       auto tw = make_twiddles<double>(TWN);
@@ -1026,10 +1032,34 @@ qw_status qw_step_batched(qw_plan_t p, int B, void* psi, const double* m, int64_
   return step_impl(p, g, B, psi, p->d_coefs, nsteps, st);
 }
 
+// |t| <= 2^53: every such integer is a double, and the phase omega t is
+// reduced exactly (larger t would not be meaningful in FP64 anyway).
+static constexpr double kMaxT = 9007199254740992.0;
+
+static qw_status check_time(double t) {
+  if (!(fabs(t) <= kMaxT)) return fail(QW_ERR_UNSUPPORTED, "|t| must be finite and at most 2^53");
+  return QW_OK;
+}
+
 qw_status qw_evolve_fft(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, void* stream) {
   qw_status r = check_plan(p);
   if (r != QW_OK) return r;
   if (!psi0 || !psi_t) return fail(QW_ERR_INVALID, "field pointer is NULL");
+  r = check_time((double)t);
+  if (r != QW_OK) return r;
+  InstParam ip;
+  ip.m = p->m;
+  ip.n = p->n;
+  ip.t = (double)t;
+  return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
+}
+
+qw_status qw_evolve_fft_real(qw_plan_t p, const void* psi0, void* psi_t, double t, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi0 || !psi_t) return fail(QW_ERR_INVALID, "field pointer is NULL");
+  r = check_time(t);
+  if (r != QW_OK) return r;
   InstParam ip;
   ip.m = p->m;
   ip.n = p->n;
@@ -1151,7 +1181,9 @@ qw_status qw_evolve_fft_timed(qw_plan_t p, const void* psi0, void* psi_t, int64_
   InstParam ip;
   ip.m = p->m;
   ip.n = p->n;
-  ip.t = t;
+  r = check_time((double)t);
+  if (r != QW_OK) return r;
+  ip.t = (double)t;
   g_timer = &tm;
   r = evolve_impl(p, 1, psi0, psi_t, nullptr, ip, st);
   g_timer = nullptr;
@@ -1175,8 +1207,11 @@ qw_status qw_evolve_fft_batched(qw_plan_t p, int B, const void* in, void* out, c
   if (B < 0) return fail(QW_ERR_INVALID, "B must be >= 0");
   if (B == 0) return QW_OK;
   if (!in || !out || !m || !t) return fail(QW_ERR_INVALID, "NULL argument");
-  for (int b = 0; b < B; ++b)
+  for (int b = 0; b < B; ++b) {
     if (!(m[b] >= 0.0 && m[b] <= 1.0)) return fail(QW_ERR_INVALID, "m[%d] outside [0, 1]", b);
+    r = check_time((double)t[b]);
+    if (r != QW_OK) return r;
+  }
   hipStream_t st = (hipStream_t)stream;
   r = ensure_inst(p, B);
   if (r != QW_OK) return r;
@@ -1185,7 +1220,7 @@ qw_status qw_evolve_fft_batched(qw_plan_t p, int B, const void* in, void* out, c
   for (int b = 0; b < B; ++b) {
     p->h_inst[b].m = m[b];
     p->h_inst[b].n = sqrt(1.0 - m[b] * m[b]);
-    p->h_inst[b].t = t[b];
+    p->h_inst[b].t = (double)t[b];
   }
   HIP_TRY(hipMemcpyAsync(p->d_inst, p->h_inst, sizeof(InstParam) * B, hipMemcpyHostToDevice, st));
   InstParam ip;
@@ -1224,7 +1259,9 @@ qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, 
   InstParam ip;
   ip.m = p->m;
   ip.n = p->n;
-  ip.t = t;
+  r = check_time((double)t);
+  if (r != QW_OK) return r;
+  ip.t = (double)t;
   const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
   if (nb > 0) {
     const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, psi_t != nullptr);

@@ -16,7 +16,7 @@ namespace qw {
 // ---------------------------------------------------------------------------
 struct InstParam {  // per batch instance, device resident for batched calls
   double m, n;      // mass and n = sqrt(1 - m^2)
-  int64_t t;        // time
+  double t;         // time (integer for the walk itself, any real for the interpolation)
 };
 
 struct PassGeom {

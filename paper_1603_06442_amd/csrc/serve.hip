@@ -184,6 +184,8 @@ qw_status validate(const qw_request* r) {
   if (!(r->sigma > 0.0) || !isfinite(r->sigma)) return fail(QW_ERR_INVALID, "sigma must be > 0");
   if (!isfinite(r->c_plus) || !isfinite(r->c_minus) || (r->c_plus == 0.0 && r->c_minus == 0.0))
     return fail(QW_ERR_INVALID, "c_plus, c_minus must be finite and not both zero");
+  if (r->t > (int64_t(1) << 53) || r->t < -(int64_t(1) << 53))
+    return fail(QW_ERR_UNSUPPORTED, "|t| must be at most 2^53");
   return QW_OK;
 }
 
@@ -252,7 +254,7 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
     hs[k] = make_state_inst(p, r.m, r.k0, r.sigma, r.center, r.c_plus, r.c_minus);
     hi[k].m = r.m;
     hi[k].n = sqrt(1.0 - r.m * r.m);
-    hi[k].t = r.t;
+    hi[k].t = (double)r.t;
     for (int i = 0; i < 3; ++i) ho[3 * k + i] = i < r.dim ? r.center[i] : 0.0;
   }
   hipStream_t st = b->st;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libqw.so")
 QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE = range(5)
 QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
-EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_batched",
+EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables",
            "qw_prepare_state",
            "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
@@ -72,6 +72,7 @@ def _load():
         "qw_step": [vp, vp, i64, vp],
         "qw_step_batched": [vp, cint, vp, ctypes.POINTER(dbl), i64, vp],
         "qw_evolve_fft": [vp, vp, vp, i64, vp],
+        "qw_evolve_fft_real": [vp, vp, vp, dbl, vp],
         "qw_evolve_fft_timed": [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_float),
                                 ctypes.POINTER(cint)],
         "qw_evolve_fft_batched": [vp, cint, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), vp],
@@ -238,6 +239,14 @@ class Plan:
         return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
                 "mean_cart": list(o.mean_cart),
                 "overlap": complex(o.overlap_re, o.overlap_im), "ref_norm2": o.ref_norm2}
+
+    def evolve_fft_real(self, psi0, t, out=None, stream=None):
+        """qw_evolve_fft_real: the continuous-time evolution to real t."""
+        if out is None:
+            out = torch.empty_like(psi0)
+        _check(LIB.qw_evolve_fft_real(self._h, self._field(psi0, name="psi0"),
+                                      self._field(out, name="out"), float(t), _stream(stream)))
+        return out
 
     def evolve_fft_observables(self, psi0, t, origin, out=None, stream=None):
         """qw_evolve_fft_observables: psi_t = U^t psi0 into ``out`` (not kept

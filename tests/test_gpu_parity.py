@@ -436,3 +436,38 @@ def test_capture_into_a_graph(qw, d, shape, dtype):
         e = x0.clone()  # eager work between replays
         plan.step(e, 1)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", [(1, (256,)), (1, (8192,)), (2, (16, 32)), (3, (8, 16, 16))])
+def test_evolve_fft_real_t(qw, d, shape, dtype):
+    """Real t against the oracle's diagonalised exp(-i t H_q); integer t
+    through the real entry equals qw_evolve_fft bit for bit."""
+    m = 0.17
+    psi = rand_field(d, shape, 61)
+    plan = qw.Plan(d, list(shape), m, dtype)
+    x = to_dev(psi, plan)
+    for t in (0.5, -1.25, 2.75, 1000.37):
+        out = plan.evolve_fft_real(x, t)
+        ref = fourier.evolve_fourier_real(psi, table(d, m), t)
+        assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t), t
+    for t in (3, -7, 1000):
+        a = plan.evolve_fft_real(x, float(t))
+        b = plan.evolve_fft(x, t)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+    # half steps compose to a stencil step
+    h = plan.evolve_fft_real(plan.evolve_fft_real(x, 0.5), 0.5)
+    s = x.clone()
+    plan.step(s, 1)
+    assert ob.rel_l2(to_np(h), to_np(s)) < (2e-5 if dtype == "c64" else 1e-12)
+
+
+def test_evolve_fft_real_t_band_edge_convention(qw):
+    """m = 0: at omega = pi (q = pi on an even 1D lattice) the two branches
+    are averaged, as in the oracle."""
+    psi = rand_field(1, (64,), 62)
+    plan = qw.Plan(1, 64, 0.0, "c128")
+    out = plan.evolve_fft_real(to_dev(psi, plan), 0.5)
+    ref = fourier.evolve_fourier_real(psi, table(1, 0.0), 0.5)
+    assert ob.rel_l2(to_np(out), ref) < 1e-12

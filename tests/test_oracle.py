@@ -475,3 +475,67 @@ def test_zb_time_schedule():
     ts = inputs.zb_times()
     assert len(ts) == 64 and ts[0] == 1 and ts[-1] == 100000
     assert all(b > a for a, b in zip(ts, ts[1:]))
+
+
+# --- real t (the continuous-time interpolation of Sec. 4) ------------------
+
+def _rand(shape, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    return x / np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("d,shape", [(1, (16,)), (2, (4, 8)), (3, (4, 4, 8))])
+def test_real_t_at_integers_is_binary_powering(d, shape):
+    m = 0.23
+    tab = walk.stencil_table(d, m)
+    psi = _rand((walk.spinor_dim(d),) + shape, 900 + d)
+    for t in (0, 1, 5, -3):
+        a = fourier.evolve_fourier_real(psi, tab, float(t))
+        b = fourier.evolve_fourier(psi, tab, t)
+        assert np.linalg.norm(a - b) < 1e-12
+
+
+@pytest.mark.parametrize("d,shape", [(1, (16,)), (2, (4, 8)), (3, (4, 4, 8))])
+def test_real_t_fractional_steps_compose_to_a_stencil_step(d, shape):
+    """(U^{1/2})^2 and (U^{1/3})^3 equal one application of the update rule
+    (position-space stepping: independent of the Fourier code)."""
+    m = 0.31
+    tab = walk.stencil_table(d, m)
+    psi = _rand((walk.spinor_dim(d),) + shape, 910 + d)
+    one = stepper.step(psi, tab)
+    h = fourier.evolve_fourier_real(fourier.evolve_fourier_real(psi, tab, 0.5), tab, 0.5)
+    assert np.linalg.norm(h - one) < 1e-12
+    x = psi
+    for _ in range(3):
+        x = fourier.evolve_fourier_real(x, tab, 1.0 / 3.0)
+    assert np.linalg.norm(x - one) < 1e-12
+
+
+def test_real_t_group_property_and_norm():
+    d, shape, m = 3, (4, 8, 4), 0.11
+    tab = walk.stencil_table(d, m)
+    psi = _rand((4,) + shape, 920)
+    a = fourier.evolve_fourier_real(fourier.evolve_fourier_real(psi, tab, 0.3), tab, 1.45)
+    b = fourier.evolve_fourier_real(psi, tab, 1.75)
+    assert np.linalg.norm(a - b) < 1e-12
+    assert abs(np.linalg.norm(fourier.evolve_fourier_real(psi, tab, 7.61)) - 1.0) < 1e-13
+
+
+def test_real_t_matches_the_interpolating_hamiltonian_dispersion():
+    """A plane wave of sector s at q is multiplied by exp(-i s omega(q) t) for
+    real t, with omega the printed dispersion (1D: cos omega = n cos q)."""
+    N, m = 32, 0.2
+    n = math.sqrt(1 - m * m)
+    tab = walk.stencil_table(1, m)
+    j = 5
+    q = 2 * math.pi * j / N
+    D = walk.symbol_from_table(tab, np.array([[q]]))[0]
+    w, v = np.linalg.eig(D)
+    omega = math.acos(n * math.cos(q))
+    x = np.arange(N)
+    for k in range(2):
+        s = 1 if np.angle(w[k]) < 0 else -1
+        psi = np.exp(-1j * q * x)[None, :] * v[:, k][:, None]
+        out = fourier.evolve_fourier_real(psi, tab, 2.37)
+        assert np.allclose(out, np.exp(-1j * s * omega * 2.37) * psi, atol=1e-12)
