@@ -199,6 +199,27 @@ qw_status qw_get_schedule(qw_plan_t plan, int* slab_planes, int* contig_elems,
  * fastest; *best_ms (nullable) receives its time per evolution. Waits. */
 qw_status qw_autotune(qw_plan_t plan, void* stream, double* best_ms);
 
+/* Dispersive approximation of Proposition 1 (Sec. 5.1): the particle /
+ * antiparticle state of qw_prepare_state (same arguments) evolved to real t
+ * with omega(k) replaced by its Taylor polynomial of the given order about
+ * k0: each wave-vector of the + sector is multiplied by e^{-i t T(k - k0)},
+ * of the - sector by e^{+i t T(k - k0)} (k - k0 from the wrapped lattice
+ * difference, mapped to Cartesian k). order 0 (phase only), 1 (drift
+ * vector) or 2 (drift and diffusion tensor, the second-order dispersive
+ * equation); else QW_ERR_UNSUPPORTED. QW_ERR_INVALID if omega is not
+ * differentiable at k0 (sin omega = 0, only for m = 0). Writes psi (DEVICE);
+ * waits for the result. */
+qw_status qw_evolve_dispersive(qw_plan_t plan, void* psi, const double* k0, double sigma,
+                               const double* center, double c_plus, double c_minus, int order,
+                               double t, void* stream);
+
+/* Host only, no device needed: the Taylor coefficients of omega(k) =
+ * arccos(n u(k)) at the Cartesian k0 (dim entries) that
+ * qw_evolve_dispersive uses, coeffs[10] (HOST): omega(k0); d omega / dk_i
+ * (i = x, y, z); (1/2) d^2 omega / dk_i^2; d^2 omega / dk_x dk_y,
+ * dk_x dk_z, dk_y dk_z. Entries beyond dim and beyond order are zero. */
+qw_status qw_dispersion_taylor(int dim, double m, const double* k0, int order, double* coeffs);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of Fourier evolutions of particle states.
  * A request describes one lattice (dim, N), the mass m, a Gaussian particle /

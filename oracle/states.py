@@ -55,11 +55,11 @@ def _chi(P0):
     return P0[:, j] / norms[j]
 
 
-def particle_state(d, N, m, k0_cart, sigma, center, c_plus=1.0, c_minus=0.0):
-    """Gaussian particle/antiparticle state on the N^d torus, unit 2-norm.
-
-    Returns psi[c, n_1..n_d] (complex128).
-    """
+def particle_spectra(d, N, m, k0_cart, sigma, center, c_plus=1.0, c_minus=0.0):
+    """The two sector spectra c+ hat psi+(q) and c- hat psi-(q) of the
+    Gaussian particle/antiparticle state, component-first [s, q_1..q_d],
+    scaled so that their sum has the unit-norm position state as its
+    inverse DFT. A sector with a zero coefficient is all zeros."""
     table = walk.stencil_table(d, m)
     q = walk.lattice_q(N, d)
     q0 = walk.q_of_k(d, np.asarray(k0_cart, dtype=np.float64).reshape(d))
@@ -69,15 +69,27 @@ def particle_state(d, N, m, k0_cart, sigma, center, c_plus=1.0, c_minus=0.0):
     Dq = walk.symbol_from_table(table, q)
     Pp, Pm = sector_projectors(Dq)
     P0p, P0m = sector_projectors(walk.symbol_from_table(table, q0))
-    phat = 0.0
+    out = []
     for coef, P, P0 in ((c_plus, Pp, P0p), (c_minus, Pm, P0m)):
         if coef == 0:
+            out.append(np.zeros((Dq.shape[-1],) + tuple(g.shape), dtype=np.complex128))
             continue
         sec = g[..., None] * (P @ _chi(P0))            # [..., s]
         sec = sec / np.sqrt(np.sum(np.abs(sec) ** 2))
-        phat = phat + coef * sec
-    phat = np.moveaxis(np.asarray(phat), -1, 0)
-    psi = fourier.idft(phat)
+        out.append(np.moveaxis(coef * sec, -1, 0))
+    # the sectors are orthogonal at every q: |psi|^2 = |c+|^2 + |c-|^2 before
+    # the inverse DFT, whose norm is that over sqrt(V)
+    V = int(np.prod(g.shape))
+    scale = np.sqrt(V) / np.sqrt(abs(c_plus) ** 2 + abs(c_minus) ** 2)
+    return out[0] * scale, out[1] * scale
+
+
+def particle_state(d, N, m, k0_cart, sigma, center, c_plus=1.0, c_minus=0.0):
+    """Gaussian particle/antiparticle state on the N^d torus, unit 2-norm.
+    Returns psi[c, n_1..n_d] (complex128).
+    """
+    sp, sm = particle_spectra(d, N, m, k0_cart, sigma, center, c_plus, c_minus)
+    psi = fourier.idft(sp + sm)
     return psi / np.sqrt(np.sum(np.abs(psi) ** 2))
 
 

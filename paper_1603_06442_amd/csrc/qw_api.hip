@@ -718,6 +718,7 @@ StateInst make_state_inst(qw_plan_t p, double m, const double* k0, double sigma,
                           const double* center, double c_plus, double c_minus) {
   StateInst si;
   memset(&si, 0, sizeof si);
+  si.order = -1;
   si.m = m;
   si.n = sqrt(1.0 - m * m);
   si.sigma = sigma;
@@ -1305,33 +1306,128 @@ qw_status qw_observables(qw_plan_t p, const void* psi, const double* origin, con
   return QW_OK;
 }
 
-qw_status qw_prepare_state(qw_plan_t p, void* psi, const double* k0, double sigma,
-                           const double* center, double c_plus, double c_minus, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
+// Taylor coefficients of omega(k) = arccos(n u(k)) at k0 (Cartesian), with
+// u the identity component of the Weyl symbol (Sec. 3.1; cos omega = n u,
+// Sec. 3.2): 1D cos k, 2D cos kx cos ky, 3D cos kx cos ky cos kz +
+// sin kx sin ky sin kz. Derivatives by implicit differentiation of
+// cos omega = n u: sin(w) dw_i = -n du_i and
+// sin(w) dw_ij = -n du_ij - cos(w) dw_i dw_j.
+qw_status qw_dispersion_taylor(int dim, double m, const double* k0, int order, double* c) {
+  if (dim < 1 || dim > 3) return fail(QW_ERR_INVALID, "dim must be 1, 2 or 3");
+  if (!(m >= 0.0 && m <= 1.0)) return fail(QW_ERR_INVALID, "m must lie in [0, 1]");
+  if (order < 0 || order > 2) return fail(QW_ERR_UNSUPPORTED, "order must be 0, 1 or 2");
+  if (!k0 || !c) return fail(QW_ERR_INVALID, "NULL argument");
+  double k[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < dim; ++i) {
+    if (!isfinite(k0[i])) return fail(QW_ERR_INVALID, "k0 not finite");
+    k[i] = k0[i];
+  }
+  const double cx_ = cos(k[0]), sx = sin(k[0]), cy = cos(k[1]), sy = sin(k[1]), cz = cos(k[2]),
+               sz = sin(k[2]);
+  double u, du[3] = {0, 0, 0}, d2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (dim == 1) {
+    u = cx_;
+    du[0] = -sx;
+    d2[0][0] = -cx_;
+  } else if (dim == 2) {
+    u = cx_ * cy;
+    du[0] = -sx * cy;
+    du[1] = -cx_ * sy;
+    d2[0][0] = d2[1][1] = -cx_ * cy;
+    d2[0][1] = d2[1][0] = sx * sy;
+  } else {
+    u = cx_ * cy * cz + sx * sy * sz;
+    du[0] = -sx * cy * cz + cx_ * sy * sz;
+    du[1] = -cx_ * sy * cz + sx * cy * sz;
+    du[2] = -cx_ * cy * sz + sx * sy * cz;
+    d2[0][0] = d2[1][1] = d2[2][2] = -u;
+    d2[0][1] = d2[1][0] = sx * sy * cz + cx_ * cy * sz;
+    d2[0][2] = d2[2][0] = sx * cy * sz + cx_ * sy * cz;
+    d2[1][2] = d2[2][1] = cx_ * sy * sz + sx * cy * cz;
+  }
+  const double n = sqrt(1.0 - m * m);
+  const double cw = n * u;
+  const double sw = sqrt(fmax(0.0, 1.0 - cw * cw));
+  for (int i = 0; i < 10; ++i) c[i] = 0.0;
+  c[0] = atan2(sw, cw);
+  if (order >= 1) {
+    if (!(sw > 1e-12)) return fail(QW_ERR_INVALID, "omega is not differentiable at k0 (sin omega = 0)");
+    double dw[3];
+    for (int i = 0; i < 3; ++i) dw[i] = -n * du[i] / sw;
+    for (int i = 0; i < dim; ++i) c[1 + i] = dw[i];
+    if (order >= 2) {
+      auto dd = [&](int i, int j) { return (-n * d2[i][j] - cw * dw[i] * dw[j]) / sw; };
+      for (int i = 0; i < dim; ++i) c[4 + i] = 0.5 * dd(i, i);
+      if (dim >= 2) c[7] = dd(0, 1);
+      if (dim >= 3) {
+        c[8] = dd(0, 2);
+        c[9] = dd(1, 2);
+      }
+    }
+  }
+  return QW_OK;
+}
+
+static qw_status check_state_args(qw_plan_t p, void* psi, const double* k0, double sigma,
+                                  const double* center, double c_plus, double c_minus) {
   if (!psi || !k0 || !center) return fail(QW_ERR_INVALID, "NULL argument");
   if (!(sigma > 0.0) || !isfinite(sigma)) return fail(QW_ERR_INVALID, "sigma must be > 0");
   if (!isfinite(c_plus) || !isfinite(c_minus) || (c_plus == 0.0 && c_minus == 0.0))
     return fail(QW_ERR_INVALID, "c_plus, c_minus must be finite and not both zero");
   for (int i = 0; i < p->dim; ++i)
     if (!isfinite(k0[i]) || !isfinite(center[i])) return fail(QW_ERR_INVALID, "k0/center not finite");
-  hipStream_t st = (hipStream_t)stream;
+  return QW_OK;
+}
+
+// Spectrum of the state `si` (with its dispersive phases, if any) and the
+// inverse DFT into psi; waits for the sector norms.
+static qw_status prepare_impl(qw_plan_t p, void* psi, const StateInst& si, hipStream_t st) {
   if (p->fourstep) {
-    r = ensure_scratch(p, p->field_bytes);
+    qw_status r = ensure_scratch(p, p->field_bytes);
     if (r != QW_OK) return r;
   }
-  *p->h_stage = make_state_inst(p, p->m, k0, sigma, center, c_plus, c_minus);
+  // The pinned staging area may still feed an earlier call's copy.
+  HIP_TRY(hipStreamSynchronize(st));
+  *p->h_stage = si;
   HIP_TRY(hipMemcpyAsync(p->d_stage, p->h_stage, sizeof(StateInst), hipMemcpyHostToDevice, st));
   HIP_TRY(launch_state_prepare(p->dbl, state_geom(p), 1, p->d_stage, p->d_partials, p->d_result,
                                psi, st));
   HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
-  r = transform_impl(p, 1, psi, psi, -1, p->d_scratch, st);
+  qw_status r = transform_impl(p, 1, psi, psi, -1, p->d_scratch, st);
   if (r != QW_OK) return r;
   HIP_TRY(hipStreamSynchronize(st));
   const double np = p->h_result[0], nm = p->h_result[1];
-  if ((c_plus != 0.0 && !(np > 0.0)) || (c_minus != 0.0 && !(nm > 0.0)))
+  if ((si.c_plus != 0.0 && !(np > 0.0)) || (si.c_minus != 0.0 && !(nm > 0.0)))
     return fail(QW_ERR_INVALID, "state has zero weight in a requested sector");
   return QW_OK;
+}
+
+qw_status qw_prepare_state(qw_plan_t p, void* psi, const double* k0, double sigma,
+                           const double* center, double c_plus, double c_minus, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  r = check_state_args(p, psi, k0, sigma, center, c_plus, c_minus);
+  if (r != QW_OK) return r;
+  return prepare_impl(p, psi, make_state_inst(p, p->m, k0, sigma, center, c_plus, c_minus),
+                      (hipStream_t)stream);
+}
+
+qw_status qw_evolve_dispersive(qw_plan_t p, void* psi, const double* k0, double sigma,
+                               const double* center, double c_plus, double c_minus, int order,
+                               double t, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  r = check_state_args(p, psi, k0, sigma, center, c_plus, c_minus);
+  if (r != QW_OK) return r;
+  if (order < 0 || order > 2) return fail(QW_ERR_UNSUPPORTED, "order must be 0, 1 or 2");
+  r = check_time(t);
+  if (r != QW_OK) return r;
+  StateInst si = make_state_inst(p, p->m, k0, sigma, center, c_plus, c_minus);
+  r = qw_dispersion_taylor(p->dim, p->m, k0, order, si.tay);
+  if (r != QW_OK) return r;
+  si.order = order;
+  si.tdisp = t;
+  return prepare_impl(p, psi, si, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -238,6 +238,14 @@ struct StateInst {
   double center[3];
   double chi_p[4][2];  // chi_+ (re, im)
   double chi_m[4][2];  // chi_-
+  // Dispersive approximation (order >= 0): the + sector is multiplied by
+  // e^{-i tdisp T(dk)}, the - sector by e^{+i tdisp T(dk)}, with T the Taylor
+  // polynomial of omega about k0 in dk = k(q) - k0 (wrapped q):
+  // tay[0] + tay[1..3] . dk + tay[4..6] . dk^2 + tay[7] dk_x dk_y
+  // + tay[8] dk_x dk_z + tay[9] dk_y dk_z.
+  int order;  // -1: none
+  double tdisp;
+  double tay[10];
 };
 int64_t state_blocks(const StateGeom& g, int B);  // partials need B * this * 2 doubles
 // norms[2b], norms[2b+1]: squared norms of the two sector amplitudes of

@@ -196,6 +196,28 @@ hipError_t launch_observables(bool dbl, const ObsGeom& g, int B, const void* psi
 // unnormalised inverse DFT has unit norm (Parseval: |psi|^2 = V |hat psi|^2
 // and the two sectors are orthogonal at every q).
 // ---------------------------------------------------------------------------
+// Phase t T(dk) of the dispersive approximation at wrapped dq (lattice axes).
+__device__ __forceinline__ double dispersive_phase(int dim, const StateInst& si, const double* dq) {
+  double k[3] = {0.0, 0.0, 0.0};
+  if (dim == 1) {
+    k[0] = dq[0];
+  } else if (dim == 2) {
+    k[0] = 0.5 * (dq[0] + dq[1]);
+    k[1] = 0.5 * (dq[0] - dq[1]);
+  } else {
+    k[0] = 0.5 * (dq[0] + dq[1]);
+    k[1] = 0.5 * (dq[0] + dq[2]);
+    k[2] = -0.5 * (dq[1] + dq[2]);
+  }
+  const double* c = si.tay;
+  double T = c[0];
+  if (si.order >= 1) T += c[1] * k[0] + c[2] * k[1] + c[3] * k[2];
+  if (si.order >= 2)
+    T += c[4] * k[0] * k[0] + c[5] * k[1] * k[1] + c[6] * k[2] * k[2] + c[7] * k[0] * k[1] +
+         c[8] * k[0] * k[2] + c[9] * k[1] * k[2];
+  return si.tdisp * T;
+}
+
 __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const StateInst& si,
                                                  int64_t idx, double ap[4][2], double am[4][2]) {
   int64_t j[3] = {0, 0, 0};
@@ -205,11 +227,13 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const State
     rem >>= g.lg[i];
   }
   double e2 = 0.0, ph = 0.0;
+  double dq[3] = {0.0, 0.0, 0.0};
   const double twopi = 2.0 * M_PI;
   for (int i = 0; i < g.dim; ++i) {
     const double q = twopi * (double)j[i] / (double)g.N[i];
     double d = q - si.q0[i] + M_PI;
     d = d - twopi * floor(d / twopi) - M_PI;
+    dq[i] = d;
     e2 += d * d;
     ph += q * si.center[i];
   }
@@ -252,14 +276,24 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const State
   double mp[4][2], mm[4][2];
   apply_mh(si.chi_p, mp);
   apply_mh(si.chi_m, mm);
+  // Sector factors g(q) e^{-+i t T}: equal to g(q) unless dispersive.
+  double gpr = gr, gpi = gi, gmr = gr, gmi = gi;
+  if (si.order >= 0) {
+    double s1, c1;
+    sincos(dispersive_phase(g.dim, si, dq), &s1, &c1);
+    gpr = gr * c1 + gi * s1;  // g e^{-i theta}
+    gpi = gi * c1 - gr * s1;
+    gmr = gr * c1 - gi * s1;  // g e^{+i theta}
+    gmi = gi * c1 + gr * s1;
+  }
   for (int c = 0; c < g.s; ++c) {
     // P_+ chi = (chi + Mh chi)/2, P_- chi = (chi - Mh chi)/2, times g(q).
     const double pr = 0.5 * (si.chi_p[c][0] + mp[c][0]), pi = 0.5 * (si.chi_p[c][1] + mp[c][1]);
     const double mr = 0.5 * (si.chi_m[c][0] - mm[c][0]), mi = 0.5 * (si.chi_m[c][1] - mm[c][1]);
-    ap[c][0] = gr * pr - gi * pi;
-    ap[c][1] = gr * pi + gi * pr;
-    am[c][0] = gr * mr - gi * mi;
-    am[c][1] = gr * mi + gi * mr;
+    ap[c][0] = gpr * pr - gpi * pi;
+    ap[c][1] = gpr * pi + gpi * pr;
+    am[c][0] = gmr * mr - gmi * mi;
+    am[c][1] = gmr * mi + gmi * mr;
   }
 }
 

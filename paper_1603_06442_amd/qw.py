@@ -22,7 +22,7 @@ QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables",
-           "qw_prepare_state",
+           "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
            "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
            "qw_server_create", "qw_server_submit", "qw_server_poll", "qw_server_wait",
            "qw_server_hold", "qw_server_stats", "qw_server_destroy")
@@ -81,6 +81,9 @@ def _load():
         "qw_evolve_fft_observables": [vp, vp, vp, i64, ctypes.POINTER(dbl),
                                       ctypes.POINTER(QwObs), vp],
         "qw_prepare_state": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl, vp],
+        "qw_evolve_dispersive": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl,
+                                 cint, dbl, vp],
+        "qw_dispersion_taylor": [cint, dbl, ctypes.POINTER(dbl), cint, ctypes.POINTER(dbl)],
         "qw_set_schedule": [vp, cint, cint, cint, cint],
         "qw_get_schedule": [vp, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint),
                             ctypes.POINTER(cint)],
@@ -286,6 +289,21 @@ class Plan:
                                     float(sigma), _darr(center, self.dim), float(c_plus),
                                     float(c_minus), _stream(stream)))
         return psi
+
+    def evolve_dispersive(self, psi, k0, sigma, center, c_plus, c_minus, order, t, stream=None):
+        """qw_evolve_dispersive: the particle state evolved to real t with the
+        order-n Taylor polynomial of omega (Proposition 1)."""
+        _check(LIB.qw_evolve_dispersive(self._h, self._field(psi, name="psi"), _darr(k0, self.dim),
+                                        float(sigma), _darr(center, self.dim), float(c_plus),
+                                        float(c_minus), int(order), float(t), _stream(stream)))
+        return psi
+
+
+def dispersion_taylor(dim, m, k0, order):
+    """qw_dispersion_taylor: the 10 Taylor coefficients of omega at k0."""
+    out = (ctypes.c_double * 10)()
+    _check(LIB.qw_dispersion_taylor(int(dim), float(m), _darr(k0, int(dim)), int(order), out))
+    return list(out)
 
 
 def version():

@@ -91,3 +91,46 @@ def test_server_rejects_bad_arguments_on_the_host():
     assert qw.LIB.qw_server_submit(None, None, ctypes.byref(tk)) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_server_hold(None, 1) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_server_destroy(None) == qw.QW_OK
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_dispersion_taylor_matches_symbolic_derivatives(d):
+    """The library's analytic Taylor coefficients of omega (host code, no
+    GPU) against the oracle's symbolic differentiation."""
+    from oracle import dispersive
+    from paper_1603_06442_amd import qw
+    m = 0.07
+    k0 = [0.31, -0.22, 0.17][:d]
+    got = qw.dispersion_taylor(d, m, k0, 2)
+    want = dispersive.taylor_coefficients(d, m, k0, 2)
+    names = {(0,) * d: 0}
+    for i in range(d):
+        a = [0] * d
+        a[i] = 1
+        names[tuple(a)] = 1 + i
+        a[i] = 2
+        names[tuple(a)] = 4 + i
+    mixed = [(0, 1, 7), (0, 2, 8), (1, 2, 9)]
+    for i, j, slot in mixed:
+        if j < d:
+            a = [0] * d
+            a[i] = a[j] = 1
+            names[tuple(a)] = slot
+    for a, slot in names.items():
+        assert abs(got[slot] - want[a]) < 1e-13 * max(1.0, abs(want[a])), (a, got[slot], want[a])
+    for slot in range(10):
+        if slot not in names.values():
+            assert got[slot] == 0.0
+
+
+def test_dispersion_taylor_rejects_bad_arguments():
+    import ctypes
+    from paper_1603_06442_amd import qw
+    out = (ctypes.c_double * 10)()
+    k = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    assert qw.LIB.qw_dispersion_taylor(4, 0.1, k, 1, out) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_dispersion_taylor(1, 1.5, k, 1, out) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_dispersion_taylor(1, 0.1, k, 3, out) == qw.QW_ERR_UNSUPPORTED
+    # m = 0 at k0 = 0: sin omega = 0, omega not differentiable
+    assert qw.LIB.qw_dispersion_taylor(3, 0.0, k, 1, out) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_dispersion_taylor(3, 0.0, k, 0, out) == qw.QW_OK

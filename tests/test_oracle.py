@@ -539,3 +539,93 @@ def test_real_t_matches_the_interpolating_hamiltonian_dispersion():
         psi = np.exp(-1j * q * x)[None, :] * v[:, k][:, None]
         out = fourier.evolve_fourier_real(psi, tab, 2.37)
         assert np.allclose(out, np.exp(-1j * s * omega * 2.37) * psi, atol=1e-12)
+
+
+# --- Proposition 1: dispersive approximation ---------------------------------
+
+from oracle import dispersive  # noqa: E402
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_dispersion_u_is_the_printed_weyl_u(d):
+    import sympy as sp
+    rng = np.random.default_rng(930 + d)
+    k = sp.symbols("k0:%d" % d, real=True)
+    f = sp.lambdify(k, dispersive.u_expr(d, k), "numpy")
+    for _ in range(5):
+        kk = rng.uniform(-3, 3, d)
+        u, _ = walk.weyl_u_n(d, kk)
+        assert abs(f(*kk) - float(u)) < 1e-14
+
+
+@pytest.mark.parametrize("d,N", [(1, (64,)), (2, (16, 32)), (3, (8, 16, 8))])
+def test_dispersion_gradient_matches_the_table(d, N):
+    """First derivatives (symbolic) against grad_q omega from the transition
+    matrices (derivative of tr U_q), at a grid point, by the chain rule."""
+    m = 0.21
+    tab = walk.stencil_table(d, m)
+    omega, grad = ob.omega_and_grad(tab, N, d)
+    idx = tuple(n // 3 + 1 for n in N)
+    q0 = walk.lattice_q(N, d)[idx]
+    k0 = walk.k_of_q(d, q0)
+    der = dispersive.derivatives(d, m, k0, 1)
+    gk = np.array([der[tuple(int(i == j) for i in range(d))] for j in range(d)])
+    gq = np.linalg.inv(walk.generators(d)) @ gk
+    assert abs(der[(0,) * d] - omega[idx]) < 1e-13
+    assert np.allclose(gq, grad[idx], atol=1e-12)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_dispersion_second_derivatives_by_finite_differences(d):
+    m = 0.13
+    tab = walk.stencil_table(d, m)
+    k0 = np.array([0.31, -0.22, 0.17][:d])
+
+    def omega(k):
+        D = walk.symbol_from_table(tab, walk.q_of_k(d, k)[None, :])[0]
+        return math.acos(np.real(np.trace(D)) / D.shape[0])
+
+    der = dispersive.derivatives(d, m, k0, 2)
+    h = 1e-4
+    for i in range(d):
+        for j in range(d):
+            ei = np.eye(d)[i] * h
+            ej = np.eye(d)[j] * h
+            fd = (omega(k0 + ei + ej) - omega(k0 + ei - ej) - omega(k0 - ei + ej) +
+                  omega(k0 - ei - ej)) / (4 * h * h)
+            a = [0] * d
+            a[i] += 1
+            a[j] += 1
+            assert abs(der[tuple(a)] - fd) < 2e-6
+
+
+def test_dispersive_state_at_t0_is_the_particle_state():
+    d, N, m = 2, (32, 32), 0.2
+    args = (d, N, m, [0.2, -0.1], 4.0, [16, 16], 1 / math.sqrt(2), 1 / math.sqrt(2))
+    a = dispersive.evolve_dispersive(*args, 2, 0.0)
+    b = states.particle_state(*args)
+    assert np.linalg.norm(a - b) < 1e-13
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_dispersive_overlap_obeys_the_bound_of_proposition_1(order):
+    """1D workload parameters (m = 0.1, k' = 0.3, sigma = 40 cells): the
+    overlap of the order-n approximation with the exact evolution is at
+    least 1 - epsilon - gamma Sigma^{n+1} t, Sigma = 4 / sigma."""
+    d, N, m, k0, sigma, c = 1, (4096,), 0.1, [0.3], 40.0, [2048]
+    psi0 = states.particle_state(d, N, m, k0, sigma, c)
+    tab = walk.stencil_table(d, m)
+    box = 4.0 / sigma
+    for t in (10, 100, 1000):
+        exact = fourier.evolve_fourier(psi0, tab, t)
+        approx = dispersive.evolve_dispersive(d, N, m, k0, sigma, c, 1.0, 0.0, order, float(t))
+        fid = abs(np.vdot(approx, exact))
+        bound, eps, gamma = dispersive.overlap_bound(d, N, m, k0, sigma, c, order, t, box)
+        assert eps < 1e-6 and gamma > 0
+        assert fid >= bound, (t, fid, bound)
+    # and the approximation improves with the order at fixed t
+    t = 1000
+    exact = fourier.evolve_fourier(psi0, tab, t)
+    f1 = abs(np.vdot(dispersive.evolve_dispersive(d, N, m, k0, sigma, c, 1.0, 0.0, 1, t), exact))
+    f2 = abs(np.vdot(dispersive.evolve_dispersive(d, N, m, k0, sigma, c, 1.0, 0.0, 2, t), exact))
+    assert f2 > f1
