@@ -147,6 +147,20 @@ qw_status qw_transform(qw_plan_t plan, const void* in, void* out, int direction,
 qw_status qw_observables(qw_plan_t plan, const void* psi, const double* origin, const void* ref,
                          qw_obs* out, void* stream);
 
+/* Mean position without the interference of the two frequency sectors
+ * (the Newton-Wigner position of the closing remark of Sec. 5.2, taken
+ * gauge-free): psi is split into P_+ psi and P_- psi with the spectral
+ * projectors P_s = (I + s M_q / sin omega) / 2 of U_q, and the reductions of
+ * each part are taken about origin (as qw_observables). sectors[0], [1]
+ * (HOST) receive those of P_+ psi and P_- psi (norm2 = sector weight);
+ * nw[0..2] (HOST) the weighted mean in lattice coordinates and nw[3..5] in
+ * Cartesian coordinates. For a state of one sector this is the ordinary
+ * mean; under the evolution it moves by the drift alone (no
+ * Zitterbewegung). The plan's scratch grows to two fields. 1D lattices above
+ * 4096 sites: QW_ERR_UNSUPPORTED. Waits for the result. */
+qw_status qw_newton_wigner(qw_plan_t plan, const void* psi, const double* origin, qw_obs* sectors,
+                           double* nw, void* stream);
+
 /* psi_t = U^t psi0 (as qw_evolve_fft) and the reductions of psi_t about
  * origin (as qw_observables with ref = NULL; overlap fields zero), in one
  * pass less: where the Fourier schedule ends with a strided inverse pass

@@ -143,3 +143,24 @@ def mean_position_kspace(psi, table, center, times, parts=False):
     if parts:
         return mean, drift, np.array([xint(t) for t in times])
     return mean
+
+
+def newton_wigner(psi, table, center):
+    """Mean position without the interference of the two frequency sectors
+    (the Newton-Wigner position of the closing remark of Sec. 5.2, read
+    gauge-free): psi is split into its sector parts P+- psi (spectral
+    projectors of U_q applied to hat psi), each part's reductions are taken
+    about c as in ``observables``, and the means are combined with the
+    sector weights. Returns (mean[3], mean_cart[3], (obs_plus, obs_minus))."""
+    d = psi.ndim - 1
+    N = psi.shape[1:]
+    Pp, Pm = states.sector_projectors(walk.symbol_from_table(table, walk.lattice_q(N, d)))
+    phat = fourier.dft(psi)
+    parts = [observables(fourier.idft(fourier.apply_symbol(P, phat)), center) for P in (Pp, Pm)]
+    wsum = parts[0]["norm2"] + parts[1]["norm2"]
+    mean = (parts[0]["norm2"] * np.asarray(parts[0]["mean"]) +
+            parts[1]["norm2"] * np.asarray(parts[1]["mean"])) / wsum
+    H = walk.generators(d)
+    mean_cart = np.zeros(3)
+    mean_cart[:d] = H @ mean[:d]
+    return mean, mean_cart, parts

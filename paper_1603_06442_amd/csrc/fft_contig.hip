@@ -130,6 +130,44 @@ __device__ __forceinline__ void apply_q(cx<T> (&y)[DIM == 1 ? 2 : 4], const Pass
 }
 
 
+// hat psi(q) <- V^-1 P_s hat psi(q), P_s = (I + s M_q / sin(omega)) / 2: the
+// spectral projector on the sector of eigenvalue e^{-s i omega} (Sec. 3.2),
+// I/2 where sin(omega) < 1e-12 (as in the state preparation).
+template <typename T, int DIM>
+__device__ __forceinline__ void apply_proj(cx<T> (&y)[DIM == 1 ? 2 : 4], const PassGeom& g,
+                                           double sgn, int64_t j1, int64_t j2, int64_t j3) {
+  double u, n1, n2, n3;
+  weyl_un(DIM, g.cs, g.Nc, g.shift, j1, j2, j3, u, n1, n2, n3);
+  (void)u;
+  const double nn = g.single.n, m = g.single.m;
+  const double sinw = sqrt(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
+  const double isw = sinw >= 1e-12 ? 1.0 / sinw : 0.0;
+  const T h = (T)(0.5 * g.inv_scale);
+  const double kk = sgn * 0.5 * g.inv_scale * isw;
+  const T a = (T)(nn * n3 * kk), gg = (T)(m * kk);
+  if constexpr (DIM == 1) {
+    const cx<T> p0 = y[0], p1 = y[1];
+    y[0] = mk(h * p0.x + a * p0.x - gg * p1.x, h * p0.y + a * p0.y - gg * p1.y);
+    y[1] = mk(h * p1.x - gg * p0.x - a * p1.x, h * p1.y - gg * p0.y - a * p1.y);
+  } else {
+    const T b = (T)(nn * n1 * kk), e = (T)(nn * n2 * kk);
+    const cx<T> p0 = y[0], p1 = y[1], p2 = y[2], p3 = y[3];
+    // z = k M p with M = [[n sigma.n~, -m I], [-m I, -n sigma.n~]]
+    const cx<T> z0 = mk(a * p0.x + (b * p1.x + e * p1.y) - gg * p2.x,
+                        a * p0.y + (b * p1.y - e * p1.x) - gg * p2.y);
+    const cx<T> z1 = mk((b * p0.x - e * p0.y) - a * p1.x - gg * p3.x,
+                        (b * p0.y + e * p0.x) - a * p1.y - gg * p3.y);
+    const cx<T> z2 = mk(-gg * p0.x - a * p2.x - (b * p3.x + e * p3.y),
+                        -gg * p0.y - a * p2.y - (b * p3.y - e * p3.x));
+    const cx<T> z3 = mk(-gg * p1.x - (b * p2.x - e * p2.y) + a * p3.x,
+                        -gg * p1.y - (b * p2.y + e * p2.x) + a * p3.y);
+    y[0] = mk(h * p0.x + z0.x, h * p0.y + z0.y);
+    y[1] = mk(h * p1.x + z1.x, h * p1.y + z1.y);
+    y[2] = mk(h * p2.x + z2.x, h * p2.y + z2.y);
+    y[3] = mk(h * p3.x + z3.x, h * p3.y + z3.y);
+  }
+}
+
 // complex64 with the plan's omega table: omega and the phase reduction stay
 // FP64; n~, sin(omega) and M_q are FP32 (they only scale the result), read
 // from the FP32 (cos, sin)(pi j / Nc) table; the sine and cosine of the
@@ -303,7 +341,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
     const int64_t pen = g.pen0 + (gpc - b * g.ppi);
     const int64_t base = b * S * g.V + pen * L;
 
-    if constexpr (MODE != MODE_INV && MODE != MODE_APPLY_INV) {
+    if constexpr (MODE != MODE_INV && MODE != MODE_APPLY_INV && MODE != MODE_PROJ_INV) {
       if (DIM == 1 && g.fourstep) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -339,6 +377,24 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
 #pragma unroll
         for (int c = 0; c < S; ++c) y[c] = v[c][0];
         apply_q_f32<DIM>(y, g, ip, pt, pen, z, pen * L + z);
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+#pragma unroll
+          for (int k = 0; k + 1 < E; ++k) v[c][k] = v[c][k + 1];
+          v[c][E - 1] = y[c];
+        }
+      }
+    } else if constexpr (MODE == MODE_PROJ_INV) {
+      const double sgn = (b & 1) ? -1.0 : 1.0;
+#pragma unroll 1
+      for (int e = 0; e < E; ++e) {
+        const int64_t z = t + TT * e;
+        int64_t j1, j2, j3;
+        q_index<DIM>(g, pen, z, j1, j2, j3);
+        cx<T> y[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) y[c] = v[c][0];
+        apply_proj<T, DIM>(y, g, sgn, j1, j2, j3);
 #pragma unroll
         for (int c = 0; c < S; ++c) {
 #pragma unroll
@@ -514,6 +570,9 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
     case MODE_APPLY_INV:
       return e4i ? dispatch_dim<T, MODE_APPLY_INV, 4>(L, out, in, g, tw, st)
                  : dispatch_dim<T, MODE_APPLY_INV, 8>(L, out, in, g, tw, st);
+    case MODE_PROJ_INV:
+      return e4i ? dispatch_dim<T, MODE_PROJ_INV, 4>(L, out, in, g, tw, st)
+                 : dispatch_dim<T, MODE_PROJ_INV, 8>(L, out, in, g, tw, st);
     case MODE_EVOLVE_TAB:
       return e4 ? dispatch_dim<T, MODE_EVOLVE_TAB, 4>(L, out, in, g, tw, st)
                 : dispatch_dim<T, MODE_EVOLVE_TAB, 8>(L, out, in, g, tw, st);

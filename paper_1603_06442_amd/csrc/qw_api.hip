@@ -915,8 +915,8 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
       const int64_t nfp = ((int64_t)p->s * fused_obs_blocks(p) + 64) * kObsFields;
       p->partials_len = std::max<int64_t>((int64_t)kObsFields * kObsBlocks, nfp);
       hipError_t e = hipMalloc(&p->d_partials, sizeof(double) * p->partials_len);
-      if (e == hipSuccess) e = hipMalloc(&p->d_result, sizeof(double) * 16);
-      if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_result, sizeof(double) * 16, hipHostMallocDefault);
+      if (e == hipSuccess) e = hipMalloc(&p->d_result, sizeof(double) * 32);
+      if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_result, sizeof(double) * 32, hipHostMallocDefault);
       if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_stage, sizeof(StateInst), hipHostMallocDefault);
       if (e == hipSuccess) e = hipMalloc((void**)&p->d_stage, sizeof(StateInst));
       // the host vectors above are released at scope end: wait for the uploads
@@ -1283,6 +1283,65 @@ qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, 
   HIP_TRY(hipStreamSynchronize(st));
   finish_obs(p, p->h_result, origin, out);
   out->overlap_re = out->overlap_im = out->ref_norm2 = 0.0;
+  return QW_OK;
+}
+
+qw_status qw_newton_wigner(qw_plan_t p, const void* psi, const double* origin, qw_obs* sectors,
+                           double* nw, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi || !origin || !sectors || !nw) return fail(QW_ERR_INVALID, "NULL argument");
+  for (int i = 0; i < p->dim; ++i)
+    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+  if (p->fourstep)
+    return fail(QW_ERR_UNSUPPORTED, "1D lattices above 4096 sites keep a transposed spectrum");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
+  const size_t fb = p->field_bytes;
+  const size_t part_bytes =
+      sizeof(double) * kObsFields * (size_t)std::max<int64_t>(2 * nb + 2 * 64, 2 * kObsBlocks);
+  r = ensure_scratch(p, 2 * fb + part_bytes);
+  if (r != QW_OK) return r;
+  char* base = (char*)p->d_scratch;
+  void* f0 = base;
+  void* f1 = base + fb;
+  double* part = (double*)(base + 2 * fb);
+  // spectrum of psi, twice; sector projector and inverse of instance 0 (+)
+  // and 1 (-); reductions of both about the origin
+  r = transform_impl(p, 1, psi, f0, +1, nullptr, st);
+  if (r != QW_OK) return r;
+  HIP_TRY(hipMemcpyAsync(f1, f0, fb, hipMemcpyDeviceToDevice, st));
+  const int64_t L = contig_len(p);
+  PassGeom g = pass_geom(p, L, 2);
+  HIP_TRY(launch_fft_contig(p->dbl, MODE_PROJ_INV, L, f0, f0, g, p->d_tw, st, 8));
+  if (nb > 0) {
+    const ObsFuse f = make_fuse(p, origin, nullptr, part, false);
+    r = strided_passes(p, -1, f0, f0, 2, st, &f);
+    if (r != QW_OK) return r;
+    HIP_TRY(launch_reduce_partials(2, nb, part, part + 2 * nb * kObsFields, p->d_result, st));
+  } else {
+    if (has_strided(p)) {
+      r = strided_passes(p, -1, f0, f0, 2, st, nullptr);
+      if (r != QW_OK) return r;
+    }
+    ObsGeom og = obs_geom(p);
+    for (int i = 0; i < p->dim; ++i) og.c[i] = origin[i];
+    HIP_TRY(launch_observables(p->dbl, og, 2, f0, nullptr, nullptr, part, p->d_result, st));
+  }
+  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 2 * kObsFields,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int k = 0; k < 2; ++k) {
+    finish_obs(p, p->h_result + k * kObsFields, origin, &sectors[k]);
+    sectors[k].overlap_re = sectors[k].overlap_im = sectors[k].ref_norm2 = 0.0;
+  }
+  const double w0 = sectors[0].norm2, w1 = sectors[1].norm2, ws = w0 + w1;
+  for (int i = 0; i < 6; ++i) nw[i] = 0.0;
+  if (ws > 0.0)
+    for (int i = 0; i < 3; ++i) {
+      nw[i] = (w0 * sectors[0].mean[i] + w1 * sectors[1].mean[i]) / ws;
+      nw[3 + i] = (w0 * sectors[0].mean_cart[i] + w1 * sectors[1].mean_cart[i]) / ws;
+    }
   return QW_OK;
 }
 

@@ -48,7 +48,17 @@ struct PassGeom {
 // MODE_EVOLVE_TAB reads it from the plan's FP64 table (the plan's mass).
 // MODE_APPLY_INV starts from a spectrum already in storage order (a state
 // prepared in momentum space): per-instance apply, then the inverse only.
-enum { MODE_EVOLVE = 0, MODE_FWD = 1, MODE_INV = 2, MODE_EVOLVE_TAB = 3, MODE_APPLY_INV = 4 };
+// MODE_PROJ_INV also starts from a spectrum: instance b gets the sector
+// projector P_s = (I + s M_q / sin(omega)) / 2 with s = + for even b, - for
+// odd b (I/2 where sin(omega) < 1e-12), times 1/V, then the inverse.
+enum {
+  MODE_EVOLVE = 0,
+  MODE_FWD = 1,
+  MODE_INV = 2,
+  MODE_EVOLVE_TAB = 3,
+  MODE_APPLY_INV = 4,
+  MODE_PROJ_INV = 5
+};
 
 // ---------------------------------------------------------------------------
 // Stencil coefficients, in the kernel's precision. Offsets per dimension:

@@ -21,7 +21,7 @@ QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE = range(5
 QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
-           "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables",
+           "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables", "qw_newton_wigner",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
            "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
            "qw_server_create", "qw_server_submit", "qw_server_poll", "qw_server_wait",
@@ -78,6 +78,8 @@ def _load():
         "qw_evolve_fft_batched": [vp, cint, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), vp],
         "qw_transform": [vp, vp, vp, cint, vp],
         "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
+        "qw_newton_wigner": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(QwObs), ctypes.POINTER(dbl),
+                             vp],
         "qw_evolve_fft_observables": [vp, vp, vp, i64, ctypes.POINTER(dbl),
                                       ctypes.POINTER(QwObs), vp],
         "qw_prepare_state": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl, vp],
@@ -261,6 +263,16 @@ class Plan:
                                              _stream(stream)))
         return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
                 "mean_cart": list(o.mean_cart)}
+
+    def newton_wigner(self, psi, origin, stream=None):
+        """qw_newton_wigner: sector-projected mean position; returns
+        {"mean", "mean_cart", "sectors": [obs+, obs-]}."""
+        sec = (QwObs * 2)()
+        nw = (ctypes.c_double * 6)()
+        _check(LIB.qw_newton_wigner(self._h, self._field(psi, name="psi"), _darr(origin, self.dim),
+                                    sec, nw, _stream(stream)))
+        return {"mean": list(nw[0:3]), "mean_cart": list(nw[3:6]),
+                "sectors": [_obs_dict(sec[k], 3) for k in range(2)]}
 
     def set_schedule(self, slab_planes, contig_elems=8, contig_threads=256, contig_groups=1):
         """qw_set_schedule: slab size (n1 planes, 0 = whole field), the fused

@@ -513,3 +513,44 @@ def test_evolve_dispersive_overlap_bound_on_the_gpu(qw):
         assert fid >= bound, (t, fid, bound, eps, gamma)
         bounds.append(bound)
     assert bounds[0] > 0.9  # the bound is informative at these parameters
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", [(1, (1024,)), (2, (32, 64)), (3, (16, 16, 32)), (3, (32, 32, 32))])
+def test_newton_wigner_matches_oracle(qw, d, shape, dtype):
+    m = 0.15
+    plan = qw.Plan(d, list(shape), m, dtype)
+    c = [n / 2 for n in shape]
+    psi = rand_field(d, shape, 71)
+    for field in (psi, states.particle_state(d, shape, m, [0.2, 0.1, -0.1][:d], 3.0, c,
+                                             1 / math.sqrt(2), 1 / math.sqrt(2))):
+        got = plan.newton_wigner(to_dev(field, plan), c)
+        if dtype == "c64":
+            field = field.astype(np.complex64).astype(np.complex128)
+        mean, mean_cart, parts = ob.newton_wigner(field, table(d, m), c)
+        tol = 2e-5 if dtype == "c64" else 1e-10
+        assert np.allclose(got["mean"][:d], mean[:d], atol=tol * max(shape)), (got, mean)
+        assert np.allclose(got["mean_cart"][:d], mean_cart[:d], atol=tol * max(shape))
+        for k in range(2):
+            assert abs(got["sectors"][k]["norm2"] - parts[k]["norm2"]) < tol
+
+
+def test_newton_wigner_moves_with_the_drift_on_the_gpu(qw):
+    """Particle + antiparticle packet in 3D: the GPU's sector-projected mean
+    after t jumps equals its value at t = 0 plus the drift term, while the
+    ordinary mean jitters."""
+    d, N, m = 3, 32, 0.3
+    c = [16, 16, 16]
+    plan = qw.Plan(d, N, m, "c128")
+    x0 = plan.empty()
+    plan.prepare_state(x0, [0.2, 0.1, 0.0], 2.5, c, 1 / math.sqrt(2), 1 / math.sqrt(2))
+    psi0 = to_np(x0)
+    nw0 = np.array(plan.newton_wigner(x0, c)["mean"][:d])
+    jit = []
+    for t in (2, 5, 9):
+        xt = plan.evolve_fft(x0, t)
+        nw = np.array(plan.newton_wigner(xt, c)["mean"][:d])
+        want = nw0 + ob.drift_prediction(psi0, table(d, m), t)
+        assert np.allclose(nw, want, atol=1e-8), t
+        jit.append(abs(plan.observables(xt, c)["mean"][0] - nw[0]))
+    assert max(jit) > 1e-3

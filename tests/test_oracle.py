@@ -629,3 +629,35 @@ def test_dispersive_overlap_obeys_the_bound_of_proposition_1(order):
     f1 = abs(np.vdot(dispersive.evolve_dispersive(d, N, m, k0, sigma, c, 1.0, 0.0, 1, t), exact))
     f2 = abs(np.vdot(dispersive.evolve_dispersive(d, N, m, k0, sigma, c, 1.0, 0.0, 2, t), exact))
     assert f2 > f1
+
+
+# --- Newton-Wigner position (sector-projected, no interference term) ---------
+
+def test_newton_wigner_equals_the_mean_for_one_sector():
+    d, N, m = 2, (32, 32), 0.2
+    psi = states.particle_state(d, N, m, [0.2, -0.1], 4.0, [16, 16], 1.0, 0.0)
+    tab = walk.stencil_table(d, m)
+    nw, nwc, parts = ob.newton_wigner(psi, tab, [16, 16])
+    o = ob.observables(psi, [16, 16])
+    assert np.allclose(nw[:d], o["mean"][:d], atol=1e-12)
+    assert parts[1]["norm2"] < 1e-24
+
+
+def test_newton_wigner_moves_with_the_drift_only():
+    """Particle + antiparticle state (Zitterbewegung parameters, 1D line):
+    the ordinary mean oscillates, the sector-projected mean moves exactly by
+    the drift term -t sum grad omega (|psi+|^2 - |psi-|^2) (an independent
+    k-space formula), before the packet reaches the wrap."""
+    d, N, m = 1, (1024,), 0.15
+    tab = walk.stencil_table(d, m)
+    c = [512]
+    psi0 = states.particle_state(d, N, m, [0.2], 12.0, c, 1 / math.sqrt(2), 1 / math.sqrt(2))
+    nw0 = ob.newton_wigner(psi0, tab, c)[0][:d]
+    means = []
+    for t in (3, 7, 12, 40):
+        psi = fourier.evolve_fourier(psi0, tab, t)
+        nw = ob.newton_wigner(psi, tab, c)[0][:d]
+        want = nw0 + ob.drift_prediction(psi0, tab, t)
+        assert np.allclose(nw, want, atol=1e-9), t
+        means.append(ob.observables(psi, c)["mean"][0] - nw[0])
+    assert max(abs(x) for x in means) > 1e-3  # the ordinary mean jitters
