@@ -161,6 +161,20 @@ qw_status qw_observables(qw_plan_t plan, const void* psi, const double* origin, 
 qw_status qw_newton_wigner(qw_plan_t plan, const void* psi, const double* origin, qw_obs* sectors,
                            double* nw, void* stream);
 
+/* Probability marginals along the Cartesian axes (the projections shown
+ * for the localised state of Sec. 5.2): every site n adds |psi(n)|^2 to the
+ * bin X = (H w)_i of axis i, with w the minimum image of n - origin (origin:
+ * dim HOST integers, lattice coordinates) and H the generators of the
+ * lattice. On return xmin[i] and len[i] (HOST, dim each) give the bins of
+ * axis i, X = xmin[i] .. xmin[i] + len[i] - 1; out (HOST, out_len doubles)
+ * holds axis 0's len[0] values, then axis 1's, ... With out = NULL only the
+ * layout is returned (psi is not read). d = 2, 3 need the bins of all axes
+ * within 64 KB (N <= 1024 in 2D, 512 in 3D). Waits for the result; the
+ * summation order inside a workgroup is not fixed (results agree to
+ * rounding). */
+qw_status qw_marginals(qw_plan_t plan, const void* psi, const int64_t* origin, double* out,
+                       int64_t out_len, int64_t* xmin, int64_t* len, void* stream);
+
 /* psi_t = U^t psi0 (as qw_evolve_fft) and the reductions of psi_t about
  * origin (as qw_observables with ref = NULL; overlap fields zero), in one
  * pass less: where the Fourier schedule ends with a strided inverse pass

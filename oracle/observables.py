@@ -164,3 +164,23 @@ def newton_wigner(psi, table, center):
     mean_cart = np.zeros(3)
     mean_cart[:d] = H @ mean[:d]
     return mean, mean_cart, parts
+
+
+def marginals(psi, center):
+    """Probability marginals along the Cartesian axes (the projections of
+    the figures of Sec. 5.2): every site n contributes |psi(n)|^2 to bin
+    X_i = (H w)_i of axis i, w the minimum image of n - c (integer c).
+    Returns a list of d (xmin, values) pairs, values[b] at X_i = xmin + b."""
+    d = psi.ndim - 1
+    N = psi.shape[1:]
+    p = np.sum(np.abs(psi) ** 2, axis=0)
+    w = np.rint(min_image(N, d, center)).astype(np.int64)  # [d, N...]
+    H = walk.generators(d).astype(np.int64)
+    out = []
+    for i in range(d):
+        X = np.tensordot(H[i], w, axes=(0, 0))
+        lo = sum(-(N[j] // 2) if H[i, j] > 0 else -(N[j] // 2 - 1) for j in range(d) if H[i, j] != 0)
+        hi = sum(N[j] // 2 - 1 if H[i, j] > 0 else N[j] // 2 for j in range(d) if H[i, j] != 0)
+        vals = np.bincount((X - lo).ravel(), weights=p.ravel(), minlength=hi - lo + 1)
+        out.append((lo, vals))
+    return out

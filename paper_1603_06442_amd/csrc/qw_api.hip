@@ -1345,6 +1345,64 @@ qw_status qw_newton_wigner(qw_plan_t p, const void* psi, const double* origin, q
   return QW_OK;
 }
 
+qw_status qw_marginals(qw_plan_t p, const void* psi, const int64_t* origin, double* out,
+                       int64_t out_len, int64_t* xmin, int64_t* len, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!xmin || !len) return fail(QW_ERR_INVALID, "NULL argument");
+  // Cartesian components of the generators (columns h_j): x = sum_j w_j h_j.
+  static const int H1[3][3] = {{1, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  static const int H2[3][3] = {{1, 1, 0}, {1, -1, 0}, {0, 0, 0}};
+  static const int H3[3][3] = {{1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+  const int(*H)[3] = p->dim == 1 ? H1 : (p->dim == 2 ? H2 : H3);
+  MargGeom g;
+  memset(&g, 0, sizeof g);
+  g.dim = p->dim;
+  g.V = p->V;
+  g.s = p->s;
+  int total = 0;
+  for (int i = 0; i < p->dim; ++i) {
+    g.N[i] = p->N[i];
+    g.lg[i] = p->lg[i];
+    int lo = 0, hi = 0;
+    for (int j = 0; j < p->dim; ++j) {
+      g.H[i][j] = H[i][j];
+      const int half = (int)(p->N[j] / 2);
+      if (H[i][j] > 0) {
+        lo -= half;
+        hi += half - 1;
+      } else if (H[i][j] < 0) {
+        lo -= half - 1;
+        hi += half;
+      }
+    }
+    g.xmin[i] = lo;
+    g.off[i] = total;
+    xmin[i] = lo;
+    len[i] = hi - lo + 1;
+    total += hi - lo + 1;
+  }
+  g.total = total;
+  if (!out) return QW_OK;  // layout query
+  if (!psi || !origin) return fail(QW_ERR_INVALID, "NULL argument");
+  if (out_len < total) return fail(QW_ERR_INVALID, "out holds %lld values, %d needed",
+                                   (long long)out_len, total);
+  if (p->dim > 1 && (size_t)total * sizeof(double) > 64 * 1024)
+    return fail(QW_ERR_UNSUPPORTED, "marginal bins exceed 64 KB of LDS");
+  for (int i = 0; i < p->dim; ++i) g.c[i] = (int)(origin[i] & (p->N[i] - 1));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nb = p->dim == 1 ? 0 : marginal_blocks(g);
+  const size_t bytes = sizeof(double) * ((size_t)nb * total + total);
+  r = ensure_scratch(p, bytes);
+  if (r != QW_OK) return r;
+  double* part = (double*)p->d_scratch;
+  double* dout = part + (size_t)nb * total;
+  HIP_TRY(launch_marginals(p->dbl, g, psi, part, dout, st));
+  HIP_TRY(hipMemcpyAsync(out, dout, sizeof(double) * total, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return QW_OK;
+}
+
 qw_status qw_observables(qw_plan_t p, const void* psi, const double* origin, const void* ref,
                          qw_obs* out, void* stream) {
   qw_status r = check_plan(p);

@@ -231,6 +231,27 @@ hipError_t launch_fft_strided_obs(bool dbl, int64_t L, void* out, const void* in
 hipError_t launch_reduce_partials(int B, int64_t nb, const double* partials, double* mid,
                                   double* result, hipStream_t st);
 
+// Marginals along the Cartesian axes: site n adds |psi(n)|^2 to bin
+// off[i] + (H w)_i - xmin[i] of axis i, w the minimum image of n - c for the
+// integer origin c (taken modulo N).
+struct MargGeom {
+  int dim;
+  int64_t N[3];
+  int lg[3];
+  int64_t V;
+  int s;
+  int c[3];      // origin modulo N
+  int H[3][3];   // generators as rows of Cartesian components
+  int xmin[3];
+  int off[3];
+  int total;     // bins over all axes
+};
+// Workgroups of the marginal reduction (partials need this * total doubles).
+int64_t marginal_blocks(const MargGeom& g);
+// out_dev[total]: the marginals; partials: marginal_blocks * total doubles.
+hipError_t launch_marginals(bool dbl, const MargGeom& g, const void* psi, double* partials,
+                            double* out_dev, hipStream_t st);
+
 // Particle states: shape, and the per-instance parameters (device array).
 struct StateGeom {
   int dim;

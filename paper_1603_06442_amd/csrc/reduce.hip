@@ -187,6 +187,110 @@ hipError_t launch_observables(bool dbl, const ObsGeom& g, int B, const void* psi
 }
 
 // ---------------------------------------------------------------------------
+// Marginals. Each workgroup accumulates its sites into a histogram in LDS
+// (the order of the LDS atomic adds within a workgroup is not fixed, so
+// results agree to rounding between runs); the per-workgroup histograms are
+// then added bin by bin in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_marginals(const cx<T>* __restrict__ psi, MargGeom g,
+                                                   double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* hist = reinterpret_cast<double*>(smem_raw);
+  for (int i = threadIdx.x; i < g.total; i += blockDim.x) hist[i] = 0.0;
+  __syncthreads();
+  const int64_t V = g.V;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < V; idx += stride) {
+    double pr = 0.0;
+    for (int c = 0; c < g.s; ++c) {
+      const cx<T> a = psi[c * V + idx];
+      pr += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+    }
+    int w[3] = {0, 0, 0};
+    int64_t rem = idx;
+#pragma unroll
+    for (int j = DIM - 1; j >= 0; --j) {
+      const int n = (int)(rem & (g.N[j] - 1));
+      rem >>= g.lg[j];
+      const int half = (int)(g.N[j] / 2);
+      w[j] = ((n - g.c[j] + half) & (int)(g.N[j] - 1)) - half;
+    }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      int X = 0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) X += g.H[i][j] * w[j];
+      atomicAdd(&hist[g.off[i] + X - g.xmin[i]], pr);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < g.total; i += blockDim.x)
+    partials[(int64_t)blockIdx.x * g.total + i] = hist[i];
+}
+
+// 1D: every site is its own bin (no reduction).
+template <typename T>
+__global__ __launch_bounds__(256) void k_marginals1d(const cx<T>* __restrict__ psi, MargGeom g,
+                                                     double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.V) return;
+  const cx<T> a = psi[idx], b = psi[g.V + idx];
+  const double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y +
+                    (double)b.x * (double)b.x + (double)b.y * (double)b.y;
+  const int half = (int)(g.N[0] / 2);
+  const int w = (((int)idx - g.c[0] + half) & (int)(g.N[0] - 1)) - half;
+  out[w - g.xmin[0]] = pr;
+}
+
+__global__ __launch_bounds__(256) void k_marginals_final(const double* __restrict__ partials,
+                                                         int64_t nblk, int total,
+                                                         double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  double sum = 0.0;
+  for (int64_t b = 0; b < nblk; ++b) sum += partials[b * total + i];
+  out[i] = sum;
+}
+
+int64_t marginal_blocks(const MargGeom& g) {
+  int64_t nb = (g.V + 255) / 256;
+  if (nb > 512) nb = 512;
+  return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_marginals(bool dbl, const MargGeom& g, const void* psi, double* partials,
+                            double* out_dev, hipStream_t st) {
+  if (g.dim == 1) {
+    const unsigned nb = (unsigned)((g.V + 255) / 256);
+    if (dbl)
+      hipLaunchKernelGGL(k_marginals1d<double>, dim3(nb), dim3(256), 0, st,
+                         (const cx<double>*)psi, g, out_dev);
+    else
+      hipLaunchKernelGGL(k_marginals1d<float>, dim3(nb), dim3(256), 0, st, (const cx<float>*)psi,
+                         g, out_dev);
+    return hipGetLastError();
+  }
+  const size_t lds = sizeof(double) * (size_t)g.total;
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  const int64_t nb = marginal_blocks(g);
+#define QW_MARG(T, D)                                                                      \
+  hipLaunchKernelGGL((k_marginals<T, D>), dim3((unsigned)nb), dim3(256), lds, st,          \
+                     (const cx<T>*)psi, g, partials)
+  if (dbl) {
+    if (g.dim == 2) QW_MARG(double, 2); else QW_MARG(double, 3);
+  } else {
+    if (g.dim == 2) QW_MARG(float, 2); else QW_MARG(float, 3);
+  }
+#undef QW_MARG
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_marginals_final, dim3((unsigned)((g.total + 255) / 256)), dim3(256), 0, st,
+                     partials, nb, g.total, out_dev);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Particle states. For every q on the grid:
 //   a_s(q) = exp(-sigma^2 |dq|^2 / 2) e^{+i q.c} P_s(q) chi_s,
 //   P_s = (I + s M_q / sin(omega)) / 2  (I/2 where sin(omega) < 1e-12),

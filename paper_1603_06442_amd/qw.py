@@ -22,6 +22,7 @@ QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables", "qw_newton_wigner",
+           "qw_marginals",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
            "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
            "qw_server_create", "qw_server_submit", "qw_server_poll", "qw_server_wait",
@@ -80,6 +81,8 @@ def _load():
         "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
         "qw_newton_wigner": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(QwObs), ctypes.POINTER(dbl),
                              vp],
+        "qw_marginals": [vp, vp, ctypes.POINTER(i64), ctypes.POINTER(dbl), i64,
+                         ctypes.POINTER(i64), ctypes.POINTER(i64), vp],
         "qw_evolve_fft_observables": [vp, vp, vp, i64, ctypes.POINTER(dbl),
                                       ctypes.POINTER(QwObs), vp],
         "qw_prepare_state": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl, vp],
@@ -273,6 +276,22 @@ class Plan:
                                     sec, nw, _stream(stream)))
         return {"mean": list(nw[0:3]), "mean_cart": list(nw[3:6]),
                 "sectors": [_obs_dict(sec[k], 3) for k in range(2)]}
+
+    def marginals(self, psi, origin, stream=None):
+        """qw_marginals: [(xmin, values), ...] per Cartesian axis."""
+        xmin = (ctypes.c_int64 * 3)()
+        ln = (ctypes.c_int64 * 3)()
+        _check(LIB.qw_marginals(self._h, None, None, None, 0, xmin, ln, None))
+        total = sum(ln[i] for i in range(self.dim))
+        out = (ctypes.c_double * total)()
+        org = (ctypes.c_int64 * self.dim)(*[int(x) for x in origin])
+        _check(LIB.qw_marginals(self._h, self._field(psi, name="psi"), org, out, total, xmin, ln,
+                                _stream(stream)))
+        res, o = [], 0
+        for i in range(self.dim):
+            res.append((xmin[i], list(out[o:o + ln[i]])))
+            o += ln[i]
+        return res
 
     def set_schedule(self, slab_planes, contig_elems=8, contig_threads=256, contig_groups=1):
         """qw_set_schedule: slab size (n1 planes, 0 = whole field), the fused

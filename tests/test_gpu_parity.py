@@ -554,3 +554,34 @@ def test_newton_wigner_moves_with_the_drift_on_the_gpu(qw):
         assert np.allclose(nw, want, atol=1e-8), t
         jit.append(abs(plan.observables(xt, c)["mean"][0] - nw[0]))
     assert max(jit) > 1e-3
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape,c", [(1, (1024,), [300]), (2, (32, 64), [5, 60]),
+                                       (3, (16, 32, 8), [15, 0, 3]), (3, (64, 64, 64), [32, 32, 32])])
+def test_marginals_match_oracle(qw, d, shape, c, dtype):
+    plan = qw.Plan(d, list(shape), 0.1, dtype)
+    psi = rand_field(d, shape, 81)
+    got = plan.marginals(to_dev(psi, plan), c)
+    if dtype == "c64":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    want = ob.marginals(psi, c)
+    for (lo, vals), (wlo, wvals) in zip(got, want):
+        assert lo == wlo and len(vals) == len(wvals)
+        assert np.allclose(vals, wvals, rtol=1e-12, atol=1e-15)
+
+
+def test_marginals_of_the_localised_state_on_the_gpu(qw):
+    """Localised state after 28 steps (the 3D walk of the paper's projection
+    figure, m = 0.03): zero beyond |X| = 28, equal to the oracle's."""
+    d, N, m, t = 3, 64, 0.03, 28
+    plan = qw.Plan(d, N, m, "c128")
+    psi0 = states.localized_state(d, N, [32, 32, 32], [1, 0, 0, 0])
+    x = to_dev(psi0, plan)
+    plan.step(x, t)
+    got = plan.marginals(x, [32, 32, 32])
+    want = ob.marginals(stepper.evolve_steps(psi0, table(d, m), t), [32, 32, 32])
+    for (lo, vals), (_, wvals) in zip(got, want):
+        X = np.arange(lo, lo + len(vals))
+        assert np.all(np.asarray(vals)[np.abs(X) > t] == 0.0)
+        assert np.allclose(vals, wvals, rtol=1e-11, atol=1e-15)

@@ -5,6 +5,7 @@ the paper prints (tests/golden), a closed form, an invariant, a special case
 that reduces to a known operation, or brute force on a tiny torus. None of
 these tests touches the GPU.
 """
+import itertools
 import json
 import math
 import os
@@ -661,3 +662,40 @@ def test_newton_wigner_moves_with_the_drift_only():
         assert np.allclose(nw, want, atol=1e-9), t
         means.append(ob.observables(psi, c)["mean"][0] - nw[0])
     assert max(abs(x) for x in means) > 1e-3  # the ordinary mean jitters
+
+
+# --- marginals along the Cartesian axes ---------------------------------------
+
+@pytest.mark.parametrize("d,N", [(1, (16,)), (2, (8, 16)), (3, (4, 8, 8))])
+def test_marginals_by_brute_force(d, N):
+    rng = np.random.default_rng(940 + d)
+    psi = rng.standard_normal((walk.spinor_dim(d),) + N) + 1j * rng.standard_normal((walk.spinor_dim(d),) + N)
+    c = [n // 2 - 1 for n in N]
+    H = walk.generators(d)
+    got = ob.marginals(psi, c)
+    want = [dict() for _ in range(d)]
+    for n in itertools.product(*[range(x) for x in N]):
+        w = [((n[j] - c[j] + N[j] // 2) % N[j]) - N[j] // 2 for j in range(d)]
+        pr = float(np.sum(np.abs(psi[(slice(None),) + n]) ** 2))
+        for i in range(d):
+            X = int(round(sum(H[i, j] * w[j] for j in range(d))))
+            want[i][X] = want[i].get(X, 0.0) + pr
+    for i in range(d):
+        lo, vals = got[i]
+        for X, v in want[i].items():
+            assert abs(vals[X - lo] - v) < 1e-12
+        assert abs(np.sum(vals) - sum(want[i].values())) < 1e-12
+
+
+def test_marginals_of_a_localised_state_stay_in_the_light_cone():
+    """Perfectly localised state (3D, m = 0.03): after t steps every
+    Cartesian marginal vanishes beyond |X| = t, and its first moment is the
+    Cartesian mean position."""
+    d, N, m, t = 3, (16, 16, 16), 0.03, 5
+    psi = states.localized_state(d, 16, [8, 8, 8], [1, 0, 0, 0])
+    psi = stepper.evolve_steps(psi, walk.stencil_table(d, m), t)
+    o = ob.observables(psi, [8, 8, 8])
+    for i, (lo, vals) in enumerate(ob.marginals(psi, [8, 8, 8])):
+        X = np.arange(lo, lo + len(vals))
+        assert np.all(vals[np.abs(X) > t] < 1e-28)
+        assert abs(np.sum(X * vals) / np.sum(vals) - (o["mean_cart"][i] - (walk.generators(d) @ np.array([8, 8, 8]))[i])) < 1e-12
