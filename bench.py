@@ -383,6 +383,25 @@ def main():
     line["dispersive"] = {"order": 2, "t": tdisp, "ms_per_state": round(disp_ms, 4),
                           "overlap_with_exact": fid}
     del approx, exact
+
+    # The other widened operations on the same field (wall time per call,
+    # including the host wait of the calls that return values).
+    def wall(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return round(1e3 * (time.perf_counter() - t0) / reps, 4)
+
+    line["more_ops_ms"] = {
+        "evolve_fft_real_t_1000.5": wall(lambda: plan.evolve_fft_real(psi0, 1000.5, out=psit)),
+        "newton_wigner": wall(lambda: plan.newton_wigner(psi0, w["center"])),
+        "marginals": wall(lambda: plan.marginals(psi0, [int(x) for x in w["center"]])),
+        "evolve_fft_observables": wall(lambda: plan.evolve_fft_observables(
+            psi0, 1000, w["center"], out=psit)),
+    }
     line["stencil_1d"] = stencil_line(qw)
     if not args.no_serving:
         line["serving"] = serving(qw)
