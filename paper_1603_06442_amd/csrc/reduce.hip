@@ -322,18 +322,24 @@ __device__ __forceinline__ double dispersive_phase(int dim, const StateInst& si,
   return si.tdisp * T;
 }
 
+// DIM is a template parameter so that every loop over axes and components
+// unrolls and the per-site arrays stay in registers.
+template <int DIM>
 __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const StateInst& si,
                                                  int64_t idx, double ap[4][2], double am[4][2]) {
+  constexpr int S = DIM == 1 ? 2 : 4;
   int64_t j[3] = {0, 0, 0};
   int64_t rem = idx;
-  for (int i = g.dim - 1; i >= 0; --i) {
+#pragma unroll
+  for (int i = DIM - 1; i >= 0; --i) {
     j[i] = rem & (g.N[i] - 1);
     rem >>= g.lg[i];
   }
   double e2 = 0.0, ph = 0.0;
   double dq[3] = {0.0, 0.0, 0.0};
   const double twopi = 2.0 * M_PI;
-  for (int i = 0; i < g.dim; ++i) {
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
     const double q = twopi * (double)j[i] / (double)g.N[i];
     double d = q - si.q0[i] + M_PI;
     d = d - twopi * floor(d / twopi) - M_PI;
@@ -347,14 +353,14 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const State
   const double gr = amp * cp, gi = amp * sp;
 
   double u, n1, n2, n3;
-  weyl_un(g.dim, g.cs, g.Nc, g.shift, j[0], j[1], j[2], u, n1, n2, n3);
+  weyl_un(DIM, g.cs, g.Nc, g.shift, j[0], j[1], j[2], u, n1, n2, n3);
   (void)u;
   const double nn = si.n, m = si.m;
   const double sinw = sqrt(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
   const double inv = sinw >= 1e-12 ? 1.0 / sinw : 0.0;
   // Mh = M / sin(omega), applied to chi (complex) for both sectors.
   auto apply_mh = [&](const double chi[4][2], double out[4][2]) {
-    if (g.dim == 1) {
+    if constexpr (DIM == 1) {
       const double a = nn * n3 * inv, gg = -m * inv;
       out[0][0] = a * chi[0][0] + gg * chi[1][0];
       out[0][1] = a * chi[0][1] + gg * chi[1][1];
@@ -384,13 +390,14 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const State
   double gpr = gr, gpi = gi, gmr = gr, gmi = gi;
   if (si.order >= 0) {
     double s1, c1;
-    sincos(dispersive_phase(g.dim, si, dq), &s1, &c1);
+    sincos(dispersive_phase(DIM, si, dq), &s1, &c1);
     gpr = gr * c1 + gi * s1;  // g e^{-i theta}
     gpi = gi * c1 - gr * s1;
     gmr = gr * c1 - gi * s1;  // g e^{+i theta}
     gmi = gi * c1 + gr * s1;
   }
-  for (int c = 0; c < g.s; ++c) {
+#pragma unroll
+  for (int c = 0; c < S; ++c) {
     // P_+ chi = (chi + Mh chi)/2, P_- chi = (chi - Mh chi)/2, times g(q).
     const double pr = 0.5 * (si.chi_p[c][0] + mp[c][0]), pi = 0.5 * (si.chi_p[c][1] + mp[c][1]);
     const double mr = 0.5 * (si.chi_m[c][0] - mm[c][0]), mi = 0.5 * (si.chi_m[c][1] - mm[c][1]);
@@ -401,16 +408,19 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const State
   }
 }
 
+template <int DIM>
 __global__ __launch_bounds__(256) void k_state_norms(StateGeom g, const StateInst* __restrict__ inst,
                                                      double* __restrict__ partials) {
+  constexpr int S = DIM == 1 ? 2 : 4;
   const int64_t b = blockIdx.y;
-  const StateInst si = inst[b];
+  const StateInst& si = inst[b];
   double acc[2] = {0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < g.V; idx += stride) {
     double ap[4][2], am[4][2];
-    state_amplitudes(g, si, idx, ap, am);
-    for (int c = 0; c < g.s; ++c) {
+    state_amplitudes<DIM>(g, si, idx, ap, am);
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
       acc[0] += ap[c][0] * ap[c][0] + ap[c][1] * ap[c][1];
       acc[1] += am[c][0] * am[c][0] + am[c][1] * am[c][1];
     }
@@ -418,22 +428,24 @@ __global__ __launch_bounds__(256) void k_state_norms(StateGeom g, const StateIns
   block_reduce_store<2>(acc, partials + (b * gridDim.x + blockIdx.x) * 2);
 }
 
-template <typename T>
+template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_state_fill(StateGeom g, const StateInst* __restrict__ inst,
                                                     const double* __restrict__ norms,
                                                     cx<T>* __restrict__ out_all) {
+  constexpr int S = DIM == 1 ? 2 : 4;
   const int64_t b = blockIdx.y;
-  const StateInst si = inst[b];
+  const StateInst& si = inst[b];
   const double np = norms[2 * b], nm = norms[2 * b + 1];
   const double total = sqrt((double)g.V * (si.c_plus * si.c_plus + si.c_minus * si.c_minus));
   const double coef_p = (si.c_plus != 0.0 && np > 0.0) ? si.c_plus / sqrt(np) / total : 0.0;
   const double coef_m = (si.c_minus != 0.0 && nm > 0.0) ? si.c_minus / sqrt(nm) / total : 0.0;
-  cx<T>* __restrict__ out = out_all + b * g.s * g.V;
+  cx<T>* __restrict__ out = out_all + b * S * g.V;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < g.V; idx += stride) {
     double ap[4][2], am[4][2];
-    state_amplitudes(g, si, idx, ap, am);
-    for (int c = 0; c < g.s; ++c) {
+    state_amplitudes<DIM>(g, si, idx, ap, am);
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
       const double re = coef_p * ap[c][0] + coef_m * am[c][0];
       const double im = coef_p * ap[c][1] + coef_m * am[c][1];
       out[c * g.V + idx] = mk((T)re, (T)im);
@@ -451,8 +463,10 @@ int64_t state_blocks(const StateGeom& g, int B) {
 hipError_t launch_state_prepare(bool dbl, const StateGeom& g, int B, const StateInst* inst,
                                 double* partials, double* norms, void* out, hipStream_t st) {
   const int64_t nb = state_blocks(g, B);
-  hipLaunchKernelGGL(k_state_norms, dim3((unsigned)nb, (unsigned)B), dim3(256), 0, st, g, inst,
-                     partials);
+  const dim3 gn((unsigned)nb, (unsigned)B);
+  if (g.dim == 1) hipLaunchKernelGGL(k_state_norms<1>, gn, dim3(256), 0, st, g, inst, partials);
+  else if (g.dim == 2) hipLaunchKernelGGL(k_state_norms<2>, gn, dim3(256), 0, st, g, inst, partials);
+  else hipLaunchKernelGGL(k_state_norms<3>, gn, dim3(256), 0, st, g, inst, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_final_b<2>, dim3((unsigned)B), dim3(256), 0, st, partials, (int)nb,
@@ -461,12 +475,15 @@ hipError_t launch_state_prepare(bool dbl, const StateGeom& g, int B, const State
   if (e != hipSuccess) return e;
   int64_t nf = (g.V + 255) / 256;
   if (nf > 65536) nf = 65536;
-  if (dbl)
-    hipLaunchKernelGGL(k_state_fill<double>, dim3((unsigned)nf, (unsigned)B), dim3(256), 0, st, g,
-                       inst, norms, (cx<double>*)out);
-  else
-    hipLaunchKernelGGL(k_state_fill<float>, dim3((unsigned)nf, (unsigned)B), dim3(256), 0, st, g,
-                       inst, norms, (cx<float>*)out);
+  const dim3 gf((unsigned)nf, (unsigned)B);
+#define QW_FILL(T, D) \
+  hipLaunchKernelGGL((k_state_fill<T, D>), gf, dim3(256), 0, st, g, inst, norms, (cx<T>*)out)
+  if (dbl) {
+    if (g.dim == 1) QW_FILL(double, 1); else if (g.dim == 2) QW_FILL(double, 2); else QW_FILL(double, 3);
+  } else {
+    if (g.dim == 1) QW_FILL(float, 1); else if (g.dim == 2) QW_FILL(float, 2); else QW_FILL(float, 3);
+  }
+#undef QW_FILL
   return hipGetLastError();
 }
 
