@@ -54,6 +54,22 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
 // bytes; at most the I columns there are. Measured on the 256^3 complex64
 // evolution: 16 columns (128-byte rows) 1.175 ms, 32 columns 1.131 ms,
 // 64 columns (128 KB of LDS, one workgroup per CU) 1.160 ms.
+// Workgroup size of a strided pass with unlimited columns (the launch
+// bound of the fused kernel, so that the compiler may use the registers the
+// actual workgroups leave free).
+template <typename T, int L>
+constexpr int strided_max_threads() {
+  constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
+  constexpr int E = L < Emax ? L : Emax;
+  constexpr int TT = L / E;
+  constexpr int row128 = 128 / (int)sizeof(cx<T>);
+  int P = 2 * row128;
+  while (TT * P < 256) P <<= 1;
+  while (TT * P > 1024 && P > 1) P >>= 1;
+  while ((size_t)P * L * sizeof(cx<T>) > 65536 && P > row128) P >>= 1;
+  return TT * P;
+}
+
 template <typename T, int L>
 static int strided_cols(int64_t I) {
   constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
@@ -146,7 +162,7 @@ hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const vo
 // not be read again, nor written at all when only the reductions are
 // wanted). Whole fields: outer index o = b * s + component.
 template <typename T, int L, int E>
-__global__ __launch_bounds__(1024) void k_fft_strided_obs(cx<T>* __restrict__ out,
+__global__ __launch_bounds__((strided_max_threads<T, L>())) void k_fft_strided_obs(cx<T>* __restrict__ out,
                                                           const cx<T>* __restrict__ in, int64_t I,
                                                           int lgP, int64_t nblk_i, int s,
                                                           ObsFuse f,
@@ -278,6 +294,9 @@ static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int
 
 template <typename T>
 static int64_t obs_blocks_t(int64_t L, int64_t I) {
+  // Longer complex64 (1024) and complex128 (512, 1024) passes would spill
+  // registers with the reduction fused; those take a separate reduction.
+  if (L > (sizeof(T) == 4 ? 512 : 256)) return 0;
   int P = 0, TT = 0;
   switch (L) {
 #define QW_CASE(LL)                                           \

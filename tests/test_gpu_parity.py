@@ -325,7 +325,8 @@ def _obs_close(a, b, dim, rt):
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("d,shape,slab", [
     (3, (16, 16, 16), 0), (3, (8, 16, 64), 0), (3, (32, 16, 64), 8), (2, (32, 64), 0),
-    (2, (256, 16), 0), (1, (8192,), 0), (1, (1024,), 0)])
+    (2, (256, 16), 0), (1, (8192,), 0), (1, (1024,), 0),
+    (2, (1024, 16), 0), (3, (512, 4, 8), 0)])  # long first axes: reduction not fused
 def test_evolve_fft_observables_fused(qw, d, shape, slab, dtype):
     """The reductions taken inside the last inverse pass equal evolve_fft
     followed by observables; the field it writes is evolve_fft's, bitwise."""
