@@ -914,6 +914,7 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
     if (r == QW_OK) {
       const int64_t nfp = ((int64_t)p->s * fused_obs_blocks(p) + 64) * kObsFields;
       p->partials_len = std::max<int64_t>((int64_t)kObsFields * kObsBlocks, nfp);
+      p->partials_len = std::max<int64_t>(p->partials_len, state_scratch_doubles(state_geom(p), 1));
       hipError_t e = hipMalloc(&p->d_partials, sizeof(double) * p->partials_len);
       if (e == hipSuccess) e = hipMalloc(&p->d_result, sizeof(double) * 32);
       if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_result, sizeof(double) * 32, hipHostMallocDefault);
@@ -1507,6 +1508,8 @@ static qw_status prepare_impl(qw_plan_t p, void* psi, const StateInst& si, hipSt
   HIP_TRY(hipStreamSynchronize(st));
   *p->h_stage = si;
   HIP_TRY(hipMemcpyAsync(p->d_stage, p->h_stage, sizeof(StateInst), hipMemcpyHostToDevice, st));
+  if (state_scratch_doubles(state_geom(p), 1) > p->partials_len)
+    return fail(QW_ERR_DEVICE, "state preparation scratch exceeds the plan's partials");
   HIP_TRY(launch_state_prepare(p->dbl, state_geom(p), 1, p->d_stage, p->d_partials, p->d_result,
                                psi, st));
   HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 2, hipMemcpyDeviceToHost, st));

@@ -278,11 +278,14 @@ struct StateInst {
   double tdisp;
   double tay[10];
 };
-int64_t state_blocks(const StateGeom& g, int B);  // partials need B * this * 2 doubles
+int64_t state_blocks(const StateGeom& g, int B);
 // norms[2b], norms[2b+1]: squared norms of the two sector amplitudes of
 // instance b; the fill pass writes the normalised spectrum of every instance.
+// scratch: state_scratch_doubles(g, B) doubles (partial sums and the
+// per-axis Gaussian/carrier tables of every instance).
+int64_t state_scratch_doubles(const StateGeom& g, int B);
 hipError_t launch_state_prepare(bool dbl, const StateGeom& g, int B, const StateInst* inst,
-                                double* partials, double* norms, void* out, hipStream_t st);
+                                double* scratch, double* norms, void* out, hipStream_t st);
 
 // Kernel-side helpers shared by the apply and the state preparation:
 // u_k and n~_k of the Weyl symbol at lattice frequency indices (j1, j2, j3),

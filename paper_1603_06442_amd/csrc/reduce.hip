@@ -324,9 +324,43 @@ __device__ __forceinline__ double dispersive_phase(int dim, const StateInst& si,
 
 // DIM is a template parameter so that every loop over axes and components
 // unrolls and the per-site arrays stay in registers.
+// Wrapped q_i - q0_i of lattice index j on axis i.
+__device__ __forceinline__ double wrapped_dq(const StateGeom& g, const StateInst& si, int i,
+                                             int64_t j) {
+  const double twopi = 2.0 * M_PI;
+  const double q = twopi * (double)j / (double)g.N[i];
+  double d = q - si.q0[i] + M_PI;
+  return d - twopi * floor(d / twopi) - M_PI;
+}
+
+// The Gaussian and the carrier factorise over the lattice axes: per instance
+// a table of exp(-sigma^2 dq_i^2 / 2) e^{+i q_i c_i} for every axis i and
+// index j (axis i at offset N_0 + .. + N_{i-1}), complex FP64.
+__global__ __launch_bounds__(256) void k_state_table(StateGeom g, const StateInst* __restrict__ inst,
+                                                     double* __restrict__ tab_all, int nsum) {
+  const int64_t b = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsum) return;
+  const StateInst& si = inst[b];
+  int i = 0, j = t;
+  while (i < g.dim - 1 && j >= g.N[i]) {
+    j -= (int)g.N[i];
+    ++i;
+  }
+  const double d = wrapped_dq(g, si, i, j);
+  const double q = 2.0 * M_PI * (double)j / (double)g.N[i];
+  const double amp = exp(-0.5 * si.sigma * si.sigma * d * d);
+  double sp, cp;
+  sincos(q * si.center[i], &sp, &cp);
+  double* tab = tab_all + 2 * (b * nsum + t);
+  tab[0] = amp * cp;
+  tab[1] = amp * sp;
+}
+
 template <int DIM>
 __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const StateInst& si,
-                                                 int64_t idx, double ap[4][2], double am[4][2]) {
+                                                 const double* __restrict__ tab, int64_t idx,
+                                                 double ap[4][2], double am[4][2]) {
   constexpr int S = DIM == 1 ? 2 : 4;
   int64_t j[3] = {0, 0, 0};
   int64_t rem = idx;
@@ -335,22 +369,17 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const State
     j[i] = rem & (g.N[i] - 1);
     rem >>= g.lg[i];
   }
-  double e2 = 0.0, ph = 0.0;
-  double dq[3] = {0.0, 0.0, 0.0};
-  const double twopi = 2.0 * M_PI;
+  // g(q) = product of the per-axis factors
+  double gr = tab[2 * j[0]], gi = tab[2 * j[0] + 1];
+  int64_t off = g.N[0];
 #pragma unroll
-  for (int i = 0; i < DIM; ++i) {
-    const double q = twopi * (double)j[i] / (double)g.N[i];
-    double d = q - si.q0[i] + M_PI;
-    d = d - twopi * floor(d / twopi) - M_PI;
-    dq[i] = d;
-    e2 += d * d;
-    ph += q * si.center[i];
+  for (int i = 1; i < DIM; ++i) {
+    const double tr = tab[2 * (off + j[i])], ti = tab[2 * (off + j[i]) + 1];
+    const double r = gr * tr - gi * ti;
+    gi = gr * ti + gi * tr;
+    gr = r;
+    off += g.N[i];
   }
-  const double amp = exp(-0.5 * si.sigma * si.sigma * e2);
-  double sp, cp;
-  sincos(ph, &sp, &cp);
-  const double gr = amp * cp, gi = amp * sp;
 
   double u, n1, n2, n3;
   weyl_un(DIM, g.cs, g.Nc, g.shift, j[0], j[1], j[2], u, n1, n2, n3);
@@ -389,6 +418,9 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const State
   // Sector factors g(q) e^{-+i t T}: equal to g(q) unless dispersive.
   double gpr = gr, gpi = gi, gmr = gr, gmi = gi;
   if (si.order >= 0) {
+    double dq[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) dq[i] = wrapped_dq(g, si, i, j[i]);
     double s1, c1;
     sincos(dispersive_phase(DIM, si, dq), &s1, &c1);
     gpr = gr * c1 + gi * s1;  // g e^{-i theta}
@@ -410,15 +442,17 @@ __device__ __forceinline__ void state_amplitudes(const StateGeom& g, const State
 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_state_norms(StateGeom g, const StateInst* __restrict__ inst,
+                                                     const double* __restrict__ tab_all, int nsum,
                                                      double* __restrict__ partials) {
   constexpr int S = DIM == 1 ? 2 : 4;
   const int64_t b = blockIdx.y;
   const StateInst& si = inst[b];
+  const double* __restrict__ tab = tab_all + 2 * b * nsum;
   double acc[2] = {0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < g.V; idx += stride) {
     double ap[4][2], am[4][2];
-    state_amplitudes<DIM>(g, si, idx, ap, am);
+    state_amplitudes<DIM>(g, si, tab, idx, ap, am);
 #pragma unroll
     for (int c = 0; c < S; ++c) {
       acc[0] += ap[c][0] * ap[c][0] + ap[c][1] * ap[c][1];
@@ -430,11 +464,13 @@ __global__ __launch_bounds__(256) void k_state_norms(StateGeom g, const StateIns
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_state_fill(StateGeom g, const StateInst* __restrict__ inst,
+                                                    const double* __restrict__ tab_all, int nsum,
                                                     const double* __restrict__ norms,
                                                     cx<T>* __restrict__ out_all) {
   constexpr int S = DIM == 1 ? 2 : 4;
   const int64_t b = blockIdx.y;
   const StateInst& si = inst[b];
+  const double* __restrict__ tab = tab_all + 2 * b * nsum;
   const double np = norms[2 * b], nm = norms[2 * b + 1];
   const double total = sqrt((double)g.V * (si.c_plus * si.c_plus + si.c_minus * si.c_minus));
   const double coef_p = (si.c_plus != 0.0 && np > 0.0) ? si.c_plus / sqrt(np) / total : 0.0;
@@ -443,7 +479,7 @@ __global__ __launch_bounds__(256) void k_state_fill(StateGeom g, const StateInst
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < g.V; idx += stride) {
     double ap[4][2], am[4][2];
-    state_amplitudes<DIM>(g, si, idx, ap, am);
+    state_amplitudes<DIM>(g, si, tab, idx, ap, am);
 #pragma unroll
     for (int c = 0; c < S; ++c) {
       const double re = coef_p * ap[c][0] + coef_m * am[c][0];
@@ -460,14 +496,28 @@ int64_t state_blocks(const StateGeom& g, int B) {
   return nb < 1 ? 1 : nb;
 }
 
+int64_t state_scratch_doubles(const StateGeom& g, int B) {
+  int64_t nsum = 0;
+  for (int i = 0; i < g.dim; ++i) nsum += g.N[i];
+  return (int64_t)B * (2 * state_blocks(g, B) + 2 * nsum);
+}
+
 hipError_t launch_state_prepare(bool dbl, const StateGeom& g, int B, const StateInst* inst,
-                                double* partials, double* norms, void* out, hipStream_t st) {
+                                double* scratch, double* norms, void* out, hipStream_t st) {
   const int64_t nb = state_blocks(g, B);
-  const dim3 gn((unsigned)nb, (unsigned)B);
-  if (g.dim == 1) hipLaunchKernelGGL(k_state_norms<1>, gn, dim3(256), 0, st, g, inst, partials);
-  else if (g.dim == 2) hipLaunchKernelGGL(k_state_norms<2>, gn, dim3(256), 0, st, g, inst, partials);
-  else hipLaunchKernelGGL(k_state_norms<3>, gn, dim3(256), 0, st, g, inst, partials);
+  int nsum = 0;
+  for (int i = 0; i < g.dim; ++i) nsum += (int)g.N[i];
+  double* partials = scratch;
+  double* tab = scratch + (size_t)B * nb * 2;
+  hipLaunchKernelGGL(k_state_table, dim3((unsigned)((nsum + 255) / 256), (unsigned)B), dim3(256), 0,
+                     st, g, inst, tab, nsum);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 gn((unsigned)nb, (unsigned)B);
+  if (g.dim == 1) hipLaunchKernelGGL(k_state_norms<1>, gn, dim3(256), 0, st, g, inst, tab, nsum, partials);
+  else if (g.dim == 2) hipLaunchKernelGGL(k_state_norms<2>, gn, dim3(256), 0, st, g, inst, tab, nsum, partials);
+  else hipLaunchKernelGGL(k_state_norms<3>, gn, dim3(256), 0, st, g, inst, tab, nsum, partials);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_final_b<2>, dim3((unsigned)B), dim3(256), 0, st, partials, (int)nb,
                      norms);
@@ -477,7 +527,7 @@ hipError_t launch_state_prepare(bool dbl, const StateGeom& g, int B, const State
   if (nf > 65536) nf = 65536;
   const dim3 gf((unsigned)nf, (unsigned)B);
 #define QW_FILL(T, D) \
-  hipLaunchKernelGGL((k_state_fill<T, D>), gf, dim3(256), 0, st, g, inst, norms, (cx<T>*)out)
+  hipLaunchKernelGGL((k_state_fill<T, D>), gf, dim3(256), 0, st, g, inst, tab, nsum, norms, (cx<T>*)out)
   if (dbl) {
     if (g.dim == 1) QW_FILL(double, 1); else if (g.dim == 2) QW_FILL(double, 2); else QW_FILL(double, 3);
   } else {

@@ -205,7 +205,7 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
   const size_t fb = p->field_bytes;
   const StateGeom sg = state_geom(p);
   const ObsGeom og = obs_geom(p);
-  const int64_t nbs = state_blocks(sg, B), nbo = observables_blocks(og, B);
+  const int64_t nbo = observables_blocks(og, B);
   const int64_t nbf = (int64_t)p->s * fused_obs_blocks(p);  // 0: separate reduction pass
   // device layout
   size_t o = 0;
@@ -220,10 +220,9 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
   b->off_orig = o;
   o = align256(o + sizeof(double) * 3 * B);
   b->off_part = o;
-  o = align256(o + sizeof(double) * (size_t)B *
-                       (std::max<int64_t>(std::max<int64_t>(nbs * 2, nbo * kObsFields),
-                                          nbf * kObsFields) +
-                        64 * kObsFields));
+  o = align256(o + sizeof(double) * std::max<int64_t>(
+                       state_scratch_doubles(sg, B),
+                       (int64_t)B * (std::max<int64_t>(nbo, nbf) * kObsFields + 64 * kObsFields)));
   b->off_norm = o;
   o = align256(o + sizeof(double) * 2 * B);
   b->off_res = o;
