@@ -92,3 +92,43 @@ def test_bcc512_c64_vs_c128_and_jump_vs_step(qw):
     p128.step(s, 1)
     j = p128.evolve_fft(x128, 1)
     assert rel(j, s) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_max_1d_lattice_against_oracle(qw, dtype):
+    """The largest 1D lattice (N = 65536: four-step transform with the
+    reductions fused into its strided pass) at t = 1e5 against the oracle."""
+    from oracle import fourier, states
+    N, m = 65536, 0.1
+    psi = states.particle_state(1, N, m, [0.3], 200.0, [N // 2], 1 / np.sqrt(2), 1 / np.sqrt(2))
+    plan = qw.Plan(1, N, m, dtype)
+    x = torch.from_numpy(np.ascontiguousarray(psi)).to(plan.torch_dtype).cuda()
+    t = 100000
+    y = plan.empty()
+    o = plan.evolve_fft_observables(x, t, [N // 2], out=y)
+    torch.cuda.synchronize()
+    ref = fourier.evolve_fourier(psi, walk.stencil_table(1, m), t)
+    got = y.cpu().numpy().astype(np.complex128)
+    tol = 2e-5 if dtype == "c64" else 1e-10
+    assert ob.rel_l2(got, ref) < tol
+    want = ob.observables(ref, [N // 2])
+    assert abs(o["mean"][0] - want["mean"][0]) < tol * N
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_max_2d_lattice_against_oracle(qw, dtype):
+    """The largest 2D lattice (1024 x 1024; the first axis is too long for
+    the fused reduction): Fourier jump and three stencil steps against the
+    oracle."""
+    from oracle import fourier, states
+    N, m = 1024, 0.2
+    psi = states.particle_state(2, N, m, [0.2, -0.1], 30.0, [N // 2] * 2)
+    tab = walk.stencil_table(2, m)
+    plan = qw.Plan(2, N, m, dtype)
+    x = torch.from_numpy(np.ascontiguousarray(psi)).to(plan.torch_dtype).cuda()
+    tol = 2e-5 if dtype == "c64" else 1e-11
+    y = plan.evolve_fft(x, 1000)
+    assert ob.rel_l2(y.cpu().numpy().astype(np.complex128), fourier.evolve_fourier(psi, tab, 1000)) < tol
+    s = x.clone()
+    plan.step(s, 3)
+    assert ob.rel_l2(s.cpu().numpy().astype(np.complex128), stepper.evolve_steps(psi, tab, 3)) < tol
