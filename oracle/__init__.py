@@ -21,9 +21,13 @@ It is plain, slow and meant to be checked against the paper by eye:
 * ``observables`` -- norm, position expectation (Sec. 5.2), overlap/fidelity,
                      the drift law (Sec. 5.1) and the k-space Zitterbewegung
                      form of the mean position (Sec. 5.2).
+* ``cubic``       -- the cubic-supercell BCC representation of Sec. 4: the
+                     two sublattice arrays, the two-sublattice DFT
+                     (eq:bcc-dft, eq:bcc-idft) and the evolution through the
+                     Cartesian embedding.
 
 Every function names the passage of the paper it follows. Readings of
 passages that are ambiguous or garbled are listed in the repository's design
 notes and repeated at the function that takes them.
 """
-from . import walk, stepper, dense, fourier, states, observables  # noqa: F401
+from . import walk, stepper, dense, fourier, states, observables, cubic  # noqa: F401
