@@ -142,6 +142,40 @@ qw_status qw_evolve_fft_batched(qw_plan_t plan, int B, const void* in, void* out
  * unshifted index j_i in [0, N_i). out may equal in. */
 qw_status qw_transform(qw_plan_t plan, const void* in, void* out, int direction, void* stream);
 
+/* Cubic-supercell representation of the BCC lattice (Sec. 4, the paragraph
+ * on the BCC DFT, eq:bcc-dft and eq:bcc-idft). The BCC vertex set is
+ * G = 2Z^3 u (2Z^3 + t), t = (1,1,1) (the Cartesian sites whose coordinates
+ * share one parity; Cartesian x here is the x of the header above), taken
+ * periodic with period 2 N_i along Cartesian axis i. It is stored as the two
+ * sublattice arrays f0_n = f(2n) and f1_n = f(2n + t), n in
+ * [0,N1) x [0,N2) x [0,N3), where N1, N2, N3 are the sizes of a 3D plan
+ * (its mass and dtype apply; its primitive-cell torus is not used). Layout:
+ * f[(j * s + c) * V + lin(n)], sublattice j = 0, 1 first, then the spinor
+ * component c, then n as in the field layout above; 2 * s * V complex
+ * entries, 16-byte aligned, DEVICE memory owned by the caller. This torus
+ * holds 2 N1 N2 N3 sites and differs from the plan's primitive-cell torus
+ * of N1 N2 N3 sites; on a state far from both boundaries the two walks
+ * agree site by site.
+ *
+ * qw_bcc_transform: direction +1 writes (hat f0, hat f1) of eq:bcc-dft in
+ * the same layout, with F the rectangular DFT of each sublattice array with
+ * the sign of Sec. 4, normalised by 1/sqrt(V), unshifted (k_i in [0, N_i))
+ * and a_k = e^{i pi sum_i k_i / N_i}: hat f1_k is the spectrum at the
+ * Cartesian wave-vector kappa = (pi k_1/N_1, pi k_2/N_2, pi k_3/N_3) and
+ * hat f0_k the one at kappa + (pi, 0, 0). The transform is unitary;
+ * direction -1 applies eq:bcc-idft, its inverse. out may equal in. A plan of
+ * dim != 3 gives QW_ERR_UNSUPPORTED. */
+qw_status qw_bcc_transform(qw_plan_t plan, const void* in, void* out, int direction,
+                           void* stream);
+
+/* f_t = U^t f0 on the cubic-supercell torus: eq:bcc-dft, per k the closed
+ * form D^t of qw_evolve_fft at kappa applied to hat f1 and at kappa + (pi,0,0)
+ * applied to hat f0, eq:bcc-idft; one read and one write of the field per
+ * transform axis (the combine, the powers and the recombination are fused
+ * into the pass along n3). t real as in qw_evolve_fft_real (exact integer
+ * powers up to 2^53). f_t may equal f0. */
+qw_status qw_bcc_evolve_fft(qw_plan_t plan, const void* f0, void* f_t, double t, void* stream);
+
 /* Reductions of psi (see qw_obs). origin: dim HOST doubles. ref: NULL or a
  * DEVICE field of the same shape. out: HOST. Waits for the result. */
 qw_status qw_observables(qw_plan_t plan, const void* psi, const double* origin, const void* ref,

@@ -168,6 +168,122 @@ __device__ __forceinline__ void apply_proj(cx<T> (&y)[DIM == 1 ? 2 : 4], const P
   }
 }
 
+// p <- c p - i Z p for one 4-spinor with Z = [[A, -g I], [-g I, -A]] and
+// A = a sigma_z + b sigma_x + e sigma_y (the D^t of Sec. 3.2 with
+// c = cos(omega t), (a, b, e) = n n~ sin(omega t)/sin(omega), g = m
+// sin(omega t)/sin(omega), all already scaled).
+template <typename T>
+__device__ __forceinline__ void dirac_mix4(cx<T> (&p)[4], T c, T a, T b, T e, T gg) {
+  const cx<T> p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
+  const cx<T> z0 = mk(a * p0.x + (b * p1.x + e * p1.y) - gg * p2.x,
+                      a * p0.y + (b * p1.y - e * p1.x) - gg * p2.y);
+  const cx<T> z1 = mk((b * p0.x - e * p0.y) - a * p1.x - gg * p3.x,
+                      (b * p0.y + e * p0.x) - a * p1.y - gg * p3.y);
+  const cx<T> z2 = mk(-gg * p0.x - a * p2.x - (b * p3.x + e * p3.y),
+                      -gg * p0.y - a * p2.y - (b * p3.y - e * p3.x));
+  const cx<T> z3 = mk(-gg * p1.x - (b * p2.x - e * p2.y) + a * p3.x,
+                      -gg * p1.y - (b * p2.y + e * p2.x) + a * p3.y);
+  p[0] = mk(c * p0.x + z0.y, c * p0.y - z0.x);
+  p[1] = mk(c * p1.x + z1.y, c * p1.y - z1.x);
+  p[2] = mk(c * p2.x + z2.y, c * p2.y - z2.x);
+  p[3] = mk(c * p3.x + z3.y, c * p3.y - z3.x);
+}
+
+// Cubic-supercell BCC (Sec. 4, eq:bcc-dft / eq:bcc-idft) at the sublattice
+// frequency indices (j1, j2, j3). After the forward transforms (sign +,
+// unshifted) y[0..4) = F0(k), y[4..8) = F1(k), the rectangular spectra of the
+// even and odd sublattice, and with a_k = e^{i pi sum_i j_i / N_i}
+//   h1 = F0 + a_k F1   is the BCC spectrum at the Cartesian kappa = pi j / N,
+//   h0 = F0 - a_k F1   the one at kappa + pi e_x.
+// MODE_BCC applies D^t at kappa to h1 and at kappa + pi e_x to h0 and
+// recombines G0 = h0 + h1, G1 = conj(a_k) (h1 - h0) for the inverse
+// transforms; the two factors 1/sqrt(2) and the 1/V of the transform pair
+// are one factor g.inv_scale = 1/(2V). At kappa + pi e_x the Weyl u and n~
+// change sign and the mass term does not. MODE_BCC_FWD stores (h0, h1) and
+// MODE_BCC_INV recombines a stored (hat f0, hat f1); both scale by
+// g.inv_scale = 1/sqrt(2V). The trig values come from the plan's FP64
+// (cos, sin)(pi j / Nc) table: pi j_i / N_i is entry j_i << shift_i.
+template <typename T, int MODE>
+__device__ __forceinline__ void apply_bcc(cx<T> (&y)[8], const PassGeom& g, int64_t j1,
+                                          int64_t j2, int64_t j3) {
+  const int64_t mask = 2 * (int64_t)g.Nc - 1;
+  const int64_t a1 = (j1 << g.shift[0]) & mask;
+  const int64_t a2 = (j2 << g.shift[1]) & mask;
+  const int64_t a3 = (j3 << g.shift[2]) & mask;
+  const int64_t ia = (a1 + a2 + a3) & mask;
+  const T ar = (T)g.cs[2 * ia], ai = (T)g.cs[2 * ia + 1];
+  const T sc = (T)g.inv_scale;
+  if constexpr (MODE == MODE_BCC_INV) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const cx<T> h0 = y[c], h1 = y[4 + c];
+      const T dx = h1.x - h0.x, dy = h1.y - h0.y;
+      y[c] = mk((h0.x + h1.x) * sc, (h0.y + h1.y) * sc);
+      y[4 + c] = mk((ar * dx + ai * dy) * sc, (ar * dy - ai * dx) * sc);  // conj(a) d
+    }
+    return;
+  }
+  if constexpr (MODE == MODE_BCC_FWD) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const cx<T> f1 = y[4 + c];
+      const T px = ar * f1.x - ai * f1.y, py = ar * f1.y + ai * f1.x;  // a f1
+      const cx<T> f0 = y[c];
+      y[c] = mk((f0.x - px) * sc, (f0.y - py) * sc);      // h0
+      y[4 + c] = mk((f0.x + px) * sc, (f0.y + py) * sc);  // h1
+    }
+    return;
+  } else {
+    // The scalar coefficients first (FP64 omega and phase reduction), so the
+    // spinor values are combined only once they are needed.
+    const double cxd = g.cs[2 * a1], sxd = g.cs[2 * a1 + 1];
+    const double cyd = g.cs[2 * a2], syd = g.cs[2 * a2 + 1];
+    const double czd = g.cs[2 * a3], szd = g.cs[2 * a3 + 1];
+    const double u = cxd * cyd * czd + sxd * syd * szd;
+    const double n1 = sxd * cyd * czd - cxd * syd * szd;
+    const double n2 = cxd * syd * czd + sxd * cyd * szd;
+    const double n3 = cxd * cyd * szd - sxd * syd * czd;
+    const double nn = g.single.n, m = g.single.m;
+    const double sinw = sqrt(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
+    const double wA = atan2(sinw, nn * u);
+    // omega at kappa + pi e_x: atan2(sin, -cos) = pi - omega, with pi in two
+    // parts (the double nearest pi and its remainder).
+    const double wB = (3.141592653589793116 - wA) + 1.2246467991473532e-16;
+    const double rA = reduced_phase(wA, g.single.t);
+    const double rB = reduced_phase(wB, g.single.t);
+    T CA, SA, CB, SB, isw;
+    if constexpr (sizeof(T) == 4) {
+      sincosf((float)rA, &SA, &CA);
+      sincosf((float)rB, &SB, &CB);
+      const float swf = (float)sinw;
+      isw = swf > 1e-30f ? 1.0f / swf : 0.0f;
+    } else {
+      sincos(rA, &SA, &CA);
+      sincos(rB, &SB, &CB);
+      isw = sinw > 0.0 ? 1.0 / sinw : 0.0;
+    }
+    const T tn = (T)nn, tm = (T)m;
+    const T a = tn * (T)n3, b = tn * (T)n1, e = tn * (T)n2;
+    const T stA = SA * isw * sc, stB = SB * isw * sc;
+    cx<T> h0[4], h1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const cx<T> f1 = y[4 + c];
+      const T px = ar * f1.x - ai * f1.y, py = ar * f1.y + ai * f1.x;  // a f1
+      h1[c] = mk(y[c].x + px, y[c].y + py);
+      h0[c] = mk(y[c].x - px, y[c].y - py);
+    }
+    dirac_mix4<T>(h1, CA * sc, a * stA, b * stA, e * stA, tm * stA);
+    dirac_mix4<T>(h0, CB * sc, -a * stB, -b * stB, -e * stB, tm * stB);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const T dx = h1[c].x - h0[c].x, dy = h1[c].y - h0[c].y;
+      y[c] = mk(h0[c].x + h1[c].x, h0[c].y + h1[c].y);
+      y[4 + c] = mk(ar * dx + ai * dy, ar * dy - ai * dx);  // conj(a) (h1 - h0)
+    }
+  }
+}
+
 // complex64 with the plan's omega table: omega and the phase reduction stay
 // FP64; n~, sin(omega) and M_q are FP32 (they only scale the result), read
 // from the FP32 (cos, sin)(pi j / Nc) table; the sine and cosine of the
@@ -307,7 +423,7 @@ template <typename T, int L, int E, int DIM, int MODE, bool PIPE>
 __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
                                                     const cx<T>* __restrict__ in, PassGeom g,
                                                     const cx<T>* __restrict__ tw) {
-  constexpr int S = DIM == 1 ? 2 : 4;
+  constexpr int S = contig_components(DIM, MODE);
   constexpr int TT = L / E;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -341,7 +457,8 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
     const int64_t pen = g.pen0 + (gpc - b * g.ppi);
     const int64_t base = b * S * g.V + pen * L;
 
-    if constexpr (MODE != MODE_INV && MODE != MODE_APPLY_INV && MODE != MODE_PROJ_INV) {
+    if constexpr (MODE != MODE_INV && MODE != MODE_APPLY_INV && MODE != MODE_PROJ_INV &&
+                  MODE != MODE_BCC_INV) {
       if (DIM == 1 && g.fourstep) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -352,7 +469,25 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
       }
       fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
     }
-    if constexpr (MODE == MODE_EVOLVE_TAB && sizeof(T) == 4 && E <= 4) {
+    if constexpr (is_bcc_mode(MODE)) {
+      // One wave-vector per iteration with the register rotation below.
+#pragma unroll 1
+      for (int e = 0; e < E; ++e) {
+        const int64_t z = t + TT * e;
+        int64_t j1, j2, j3;
+        q_index<3>(g, pen, z, j1, j2, j3);
+        cx<T> y[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) y[c] = v[c][0];
+        apply_bcc<T, MODE>(y, g, j1, j2, j3);
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+#pragma unroll
+          for (int k = 0; k + 1 < E; ++k) v[c][k] = v[c][k + 1];
+          v[c][E - 1] = y[c];
+        }
+      }
+    } else if constexpr (MODE == MODE_EVOLVE_TAB && sizeof(T) == 4 && E <= 4) {
       // Four wave-vectors per thread: unrolled (independent chains, no
       // register rotation).
       const InstParam ip = g.single;
@@ -427,7 +562,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
         }
       }
     }
-    if constexpr (MODE != MODE_FWD) {
+    if constexpr (MODE != MODE_FWD && MODE != MODE_BCC_FWD) {
       fft_team_multi<T, L, E, -1, S>(v, my, LP, t, tw);
       if (DIM == 1 && g.fourstep) {
 #pragma unroll
@@ -478,7 +613,7 @@ static hipError_t run_contig_k(cx<T>* out, const cx<T>* in, const PassGeom& g, c
   }
   const int threads = TT * P;
   if (threads > 512) return hipErrorInvalidValue;
-  const size_t lds = (size_t)P * ((g.dim == 1 ? 2 : 4) * L + TT) * sizeof(cx<T>);
+  const size_t lds = (size_t)P * (contig_components(DIM, MODE) * L + TT) * sizeof(cx<T>);
   auto kern = k_fft_contig<T, L, E, DIM, MODE, PIPE>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -560,6 +695,9 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
   // take four wherever the team fits a workgroup (L <= 2048), except the
   // complex64 line, which fits eight.
   const bool e4 = E == 4 && g.dim >= 2;
+  // Four elements per thread for complex64, two for complex128 (whose 32
+  // values of eight components would not fit the register file).
+  constexpr int kBccE = sizeof(T) == 8 ? 2 : 4;
   const bool e4i = L <= 2048 && (g.dim >= 2 || sizeof(T) == 8);
   switch (mode) {
     case MODE_EVOLVE:
@@ -576,6 +714,16 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
     case MODE_EVOLVE_TAB:
       return e4 ? dispatch_dim<T, MODE_EVOLVE_TAB, 4>(L, out, in, g, tw, st)
                 : dispatch_dim<T, MODE_EVOLVE_TAB, 8>(L, out, in, g, tw, st);
+    // Cubic-supercell field: eight components per pencil, kBccE elements each.
+    case MODE_BCC:
+      if (g.dim != 3) return hipErrorInvalidValue;
+      return dispatch_contig<T, 3, MODE_BCC, kBccE>(L, out, in, g, tw, st);
+    case MODE_BCC_FWD:
+      if (g.dim != 3) return hipErrorInvalidValue;
+      return dispatch_contig<T, 3, MODE_BCC_FWD, kBccE>(L, out, in, g, tw, st);
+    case MODE_BCC_INV:
+      if (g.dim != 3) return hipErrorInvalidValue;
+      return dispatch_contig<T, 3, MODE_BCC_INV, kBccE>(L, out, in, g, tw, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1244,6 +1244,52 @@ qw_status qw_transform(qw_plan_t p, const void* in, void* out, int direction, vo
   return transform_impl(p, 1, in, out, direction, p->d_scratch, (hipStream_t)stream);
 }
 
+// Cubic-supercell field [2][s][N1 N2 N3] (Sec. 4, eq:bcc-dft / eq:bcc-idft):
+// the strided passes take it as two fields of s components, the pass along n3
+// as one pencil of 2s components (combine, per-k powers, recombination).
+static qw_status bcc_impl(qw_plan_t p, const void* in, void* out, int mode, double t,
+                          hipStream_t st) {
+  const int64_t L = p->N[2];
+  PassGeom g = pass_geom(p, L, 1);
+  g.single.t = t;
+  g.inv_scale = mode == MODE_BCC ? 0.5 / (double)p->V : 1.0 / sqrt(2.0 * (double)p->V);
+  if (mode == MODE_BCC_INV) {
+    HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, in, g, p->d_tw, st, 4));
+    mark();
+    return strided_passes(p, -1, out, out, 2, st, nullptr);
+  }
+  qw_status r = strided_passes(p, +1, out, in, 2, st, nullptr);
+  if (r != QW_OK) return r;
+  HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, out, g, p->d_tw, st, 4));
+  mark();
+  if (mode == MODE_BCC_FWD) return QW_OK;
+  return strided_passes(p, -1, out, out, 2, st, nullptr);
+}
+
+static qw_status check_bcc(qw_plan_t p, const void* in, const void* out) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (p->dim != 3) return fail(QW_ERR_UNSUPPORTED, "the cubic supercell needs a 3D plan");
+  if (!in || !out) return fail(QW_ERR_INVALID, "field pointer is NULL");
+  return QW_OK;
+}
+
+qw_status qw_bcc_transform(qw_plan_t p, const void* in, void* out, int direction, void* stream) {
+  qw_status r = check_bcc(p, in, out);
+  if (r != QW_OK) return r;
+  if (direction != 1 && direction != -1) return fail(QW_ERR_INVALID, "direction must be +1 or -1");
+  return bcc_impl(p, in, out, direction > 0 ? MODE_BCC_FWD : MODE_BCC_INV, 0.0,
+                  (hipStream_t)stream);
+}
+
+qw_status qw_bcc_evolve_fft(qw_plan_t p, const void* f0, void* f_t, double t, void* stream) {
+  qw_status r = check_bcc(p, f0, f_t);
+  if (r != QW_OK) return r;
+  r = check_time(t);
+  if (r != QW_OK) return r;
+  return bcc_impl(p, f0, f_t, MODE_BCC, t, (hipStream_t)stream);
+}
+
 qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, int64_t t,
                                     const double* origin, qw_obs* out, void* stream) {
   qw_status r = check_plan(p);

@@ -51,14 +51,33 @@ struct PassGeom {
 // MODE_PROJ_INV also starts from a spectrum: instance b gets the sector
 // projector P_s = (I + s M_q / sin(omega)) / 2 with s = + for even b, - for
 // odd b (I/2 where sin(omega) < 1e-12), times 1/V, then the inverse.
+// The MODE_BCC* modes work on the cubic-supercell BCC field (Sec. 4,
+// eq:bcc-dft / eq:bcc-idft) of a 3D plan whose N1 x N2 x N3 are the sizes of
+// the two sublattice arrays: one launch holds a single field of 2s = 8
+// components (the s components of the even sublattice, sites 2n, then those
+// of the odd sublattice, sites 2n + t). MODE_BCC: forward, the a_k combine,
+// D^t at kappa = pi k / N and at kappa + pi e_x, recombination, inverse.
+// MODE_BCC_FWD: forward and combine (the two-sublattice spectrum);
+// MODE_BCC_INV: recombination of a two-sublattice spectrum and inverse.
 enum {
   MODE_EVOLVE = 0,
   MODE_FWD = 1,
   MODE_INV = 2,
   MODE_EVOLVE_TAB = 3,
   MODE_APPLY_INV = 4,
-  MODE_PROJ_INV = 5
+  MODE_PROJ_INV = 5,
+  MODE_BCC = 6,
+  MODE_BCC_FWD = 7,
+  MODE_BCC_INV = 8
 };
+
+constexpr bool is_bcc_mode(int mode) {
+  return mode == MODE_BCC || mode == MODE_BCC_FWD || mode == MODE_BCC_INV;
+}
+// Components per pencil of the contiguous pass.
+constexpr int contig_components(int dim, int mode) {
+  return is_bcc_mode(mode) ? 8 : (dim == 1 ? 2 : 4);
+}
 
 // ---------------------------------------------------------------------------
 // Stencil coefficients, in the kernel's precision. Offsets per dimension:

@@ -22,7 +22,7 @@ QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables", "qw_newton_wigner",
-           "qw_marginals",
+           "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
            "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
            "qw_server_create", "qw_server_submit", "qw_server_poll", "qw_server_wait",
@@ -78,6 +78,8 @@ def _load():
                                 ctypes.POINTER(cint)],
         "qw_evolve_fft_batched": [vp, cint, vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), vp],
         "qw_transform": [vp, vp, vp, cint, vp],
+        "qw_bcc_transform": [vp, vp, vp, cint, vp],
+        "qw_bcc_evolve_fft": [vp, vp, vp, dbl, vp],
         "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
         "qw_newton_wigner": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(QwObs), ctypes.POINTER(dbl),
                              vp],
@@ -236,6 +238,24 @@ class Plan:
             out = torch.empty_like(x)
         _check(LIB.qw_transform(self._h, self._field(x, name="x"), self._field(out, name="out"),
                                 int(direction), _stream(stream)))
+        return out
+
+    # -- cubic-supercell BCC field (3D plans): shape (2, s, N1, N2, N3) --------
+    def bcc_transform(self, f, direction, out=None, stream=None):
+        """qw_bcc_transform: +1 = (hat f0, hat f1) of the two-sublattice DFT,
+        -1 = its inverse; f holds the two sublattice arrays back to back."""
+        if out is None:
+            out = torch.empty_like(f)
+        _check(LIB.qw_bcc_transform(self._h, self._field(f, 2, "f"), self._field(out, 2, "out"),
+                                    int(direction), _stream(stream)))
+        return out
+
+    def bcc_evolve_fft(self, f0, t, out=None, stream=None):
+        """qw_bcc_evolve_fft: U^t on the cubic-supercell torus (real t)."""
+        if out is None:
+            out = torch.empty_like(f0)
+        _check(LIB.qw_bcc_evolve_fft(self._h, self._field(f0, 2, "f0"),
+                                     self._field(out, 2, "out"), float(t), _stream(stream)))
         return out
 
     def observables(self, psi, origin, ref=None, stream=None):
