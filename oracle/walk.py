@@ -170,6 +170,28 @@ def stencil_table(d, m, L=4, tol=1e-13):
     return table
 
 
+def weyl_table(d, L=4, tol=1e-13):
+    """Transition matrices of the two-component Weyl walk (Sec. 3.1): the
+    inverse DFT over the L^d grid of W at the Cartesian k = H^{-T} q, exactly
+    as for the Dirac walk in ``stencil_table``. The 1D Weyl walk is
+    W = diag(e^{-ik}, e^{ik}) (the Dirac walk at m = 0)."""
+    grid = np.stack(np.meshgrid(*([np.arange(L)] * d), indexing="ij"), axis=-1)
+    q = 2.0 * np.pi * grid.reshape(-1, d) / L
+    if d == 1:
+        Wq = dirac_symbol(1, q, 0.0)
+    else:
+        Wq = weyl_symbol(d, k_of_q(d, q))
+    table = {}
+    for off in itertools.product((-1, 0, 1, 2), repeat=d):
+        phase = np.exp(1j * (q @ np.array(off, dtype=np.float64)))
+        U = np.tensordot(phase, Wq, axes=(0, 0)) / q.shape[0]
+        if np.abs(U).max() > tol:
+            if max(abs(o) for o in off) > 1:
+                raise AssertionError("symbol support wider than one cell at %r" % (off,))
+            table[off] = U.reshape(2, 2)
+    return table
+
+
 def symbol_from_table(table, q):
     """U(q) = sum_h e^{-iq.h} U_h by direct summation (Sec. 2.1)."""
     q = np.asarray(q, dtype=np.float64)

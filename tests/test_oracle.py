@@ -699,3 +699,53 @@ def test_marginals_of_a_localised_state_stay_in_the_light_cone():
         X = np.arange(lo, lo + len(vals))
         assert np.all(vals[np.abs(X) > t] < 1e-28)
         assert abs(np.sum(X * vals) / np.sum(vals) - (o["mean_cart"][i] - (walk.generators(d) @ np.array([8, 8, 8]))[i])) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Two-component Weyl walks (Sec. 3.1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_weyl_table_is_unitary_and_is_the_massless_dirac_block(d):
+    """The Weyl transition matrices satisfy the unitarity conditions of
+    Sec. 2 and are the upper-left blocks of the Dirac walk's at m = 0 (the
+    Dirac symbol of Sec. 3.2 is diag(W, W^dag) there)."""
+    wt = walk.weyl_table(d)
+    assert walk.unitarity_defect(wt) < 1e-14
+    dt = walk.stencil_table(d, 0.0)
+    if d == 1:
+        assert set(wt) == set(dt)
+        for h in wt:
+            assert np.abs(wt[h] - dt[h]).max() < 1e-15
+        return
+    assert set(wt) == set(dt)
+    for h in wt:
+        assert np.abs(wt[h] - dt[h][:2, :2]).max() < 1e-15
+        assert np.abs(dt[h][:2, 2:]).max() < 1e-15
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_weyl_symbol_from_table_has_the_printed_dispersion(d):
+    """Sum_h e^{-ik.h} W_h reproduces W_k off the grid, with eigenvalues
+    e^{-+i omega}, cos omega = u_k (Sec. 3.1)."""
+    rng = np.random.default_rng(12 + d)
+    k = rng.uniform(-np.pi, np.pi, size=(32, d))
+    W = walk.symbol_from_table(walk.weyl_table(d), walk.q_of_k(d, k))
+    assert np.abs(W - walk.weyl_symbol(d, k)).max() < 1e-14
+    u, _ = walk.weyl_u_n(d, k)
+    ev = np.linalg.eigvals(W)
+    w = np.arccos(np.clip(u, -1, 1))
+    got = np.sort(np.angle(ev), axis=-1)
+    assert np.abs(got - np.stack([-w, w], axis=-1)).max() < 1e-10
+
+
+@pytest.mark.parametrize("d,shape", [(2, (8, 16)), (3, (4, 8, 8))])
+def test_weyl_fourier_equals_stepping(d, shape):
+    tab = walk.weyl_table(d)
+    rng = np.random.default_rng(50 + d)
+    psi = rng.standard_normal((2,) + shape) + 1j * rng.standard_normal((2,) + shape)
+    psi /= np.linalg.norm(psi)
+    for t in (1, 4, -3):
+        a = fourier.evolve_fourier(psi, tab, t)
+        b = stepper.evolve_steps(psi, tab, t)
+        assert np.abs(a - b).max() < 1e-13
