@@ -92,6 +92,21 @@ typedef struct {
 qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype dtype,
                   void* stream);
 
+/* A plan for the two-component Weyl walk of Sec. 3.1 (W_k = u_k I -
+ * i sigma.n~_k; 2D on the square lattice, 3D on the BCC lattice, with the
+ * same primitive-cell coordinates, sizes and dtype rules as qw_plan). The
+ * field has s = 2 components (the layout above with s = 2). Its transition
+ * matrices are the upper blocks of the Dirac walk's at m = 0, whose symbol is
+ * diag(W_k, W_k^dag). qw_step, qw_evolve_fft, qw_evolve_fft_real (W_k^t =
+ * cos(omega t) I - i sin(omega t)/sin(omega) sigma.n~, cos(omega) = u_k; at
+ * omega = pi the average cos(pi t) I, as for the Dirac walk),
+ * qw_evolve_fft_timed, qw_evolve_fft_observables, qw_transform,
+ * qw_observables, qw_marginals and the schedule calls take such a plan; the
+ * batched calls, the particle-state calls, qw_newton_wigner and the
+ * cubic-supercell calls return QW_ERR_UNSUPPORTED. dim = 1 gives the Dirac
+ * plan at m = 0, which is the 1D Weyl walk diag(e^{-ik}, e^{ik}). */
+qw_status qw_plan_weyl(qw_plan_t* out, int dim, const int64_t* N, qw_dtype dtype, void* stream);
+
 /* Release a plan and everything it owns. Waits for the plan's work. NULL is a no-op. */
 qw_status qw_destroy(qw_plan_t plan);
 

@@ -168,6 +168,39 @@ __device__ __forceinline__ void apply_proj(cx<T> (&y)[DIM == 1 ? 2 : 4], const P
   }
 }
 
+// Two-component Weyl walk (Sec. 3.1): W_q = u I - i sigma.n~ with
+// cos(omega) = u, sin(omega) = |n~|, so
+//   W_q^t = cos(omega t) I - i sin(omega t)/sin(omega) sigma.n~,
+// the Dirac closed form with n = 1, m = 0 restricted to its upper block.
+// omega and its phase reduction are FP64; the rest in the field precision.
+template <typename T, int DIM>
+__device__ __forceinline__ void apply_weyl(cx<T> (&y)[2], const PassGeom& g, const InstParam& ip,
+                                           int64_t j1, int64_t j2, int64_t j3) {
+  double u, n1, n2, n3;
+  weyl_un(DIM, g.cs, g.Nc, g.shift, j1, j2, j3, u, n1, n2, n3);
+  const double sinw = sqrt(n1 * n1 + n2 * n2 + n3 * n3);
+  const double r = reduced_phase(atan2(sinw, u), ip.t);
+  T C, S, isw;
+  if constexpr (sizeof(T) == 4) {
+    sincosf((float)r, &S, &C);
+    const float swf = (float)sinw;
+    isw = swf > 1e-30f ? 1.0f / swf : 0.0f;
+  } else {
+    sincos(r, &S, &C);
+    isw = sinw > 0.0 ? 1.0 / sinw : 0.0;
+  }
+  const T sc = (T)g.inv_scale;
+  const T c = C * sc;
+  const T st = S * isw * sc;
+  const T a = (T)n3 * st, b = (T)n1 * st, e = (T)n2 * st;
+  const cx<T> p0 = y[0], p1 = y[1];
+  // z = st sigma.n~ p; out = c p - i z
+  const cx<T> z0 = mk(a * p0.x + (b * p1.x + e * p1.y), a * p0.y + (b * p1.y - e * p1.x));
+  const cx<T> z1 = mk((b * p0.x - e * p0.y) - a * p1.x, (b * p0.y + e * p0.x) - a * p1.y);
+  y[0] = mk(c * p0.x + z0.y, c * p0.y - z0.x);
+  y[1] = mk(c * p1.x + z1.y, c * p1.y - z1.x);
+}
+
 // p <- c p - i Z p for one 4-spinor with Z = [[A, -g I], [-g I, -A]] and
 // A = a sigma_z + b sigma_x + e sigma_y (the D^t of Sec. 3.2 with
 // c = cos(omega t), (a, b, e) = n n~ sin(omega t)/sin(omega), g = m
@@ -469,7 +502,25 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
       }
       fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
     }
-    if constexpr (is_bcc_mode(MODE)) {
+    if constexpr (MODE == MODE_WEYL) {
+      const InstParam ip = g.single;
+#pragma unroll 1
+      for (int e = 0; e < E; ++e) {
+        const int64_t z = t + TT * e;
+        int64_t j1, j2, j3;
+        q_index<DIM>(g, pen, z, j1, j2, j3);
+        cx<T> y[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) y[c] = v[c][0];
+        apply_weyl<T, DIM>(y, g, ip, j1, j2, j3);
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+#pragma unroll
+          for (int k = 0; k + 1 < E; ++k) v[c][k] = v[c][k + 1];
+          v[c][E - 1] = y[c];
+        }
+      }
+    } else if constexpr (is_bcc_mode(MODE)) {
       // One wave-vector per iteration with the register rotation below.
 #pragma unroll 1
       for (int e = 0; e < E; ++e) {
@@ -699,6 +750,18 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
   // values of eight components would not fit the register file).
   constexpr int kBccE = sizeof(T) == 8 ? 2 : 4;
   const bool e4i = L <= 2048 && (g.dim >= 2 || sizeof(T) == 8);
+  // Two-component fields of d = 2, 3 (Weyl walks): the transforms alone are
+  // the one-dimensional kernels (two components per pencil, no apply).
+  if (g.s == 2 && g.dim >= 2) {
+    switch (mode) {
+      case MODE_FWD: return dispatch_contig<T, 1, MODE_FWD, 8>(L, out, in, g, tw, st);
+      case MODE_INV: return dispatch_contig<T, 1, MODE_INV, 8>(L, out, in, g, tw, st);
+      case MODE_WEYL:
+        return g.dim == 2 ? dispatch_contig<T, 2, MODE_WEYL, 8>(L, out, in, g, tw, st)
+                          : dispatch_contig<T, 3, MODE_WEYL, 8>(L, out, in, g, tw, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (mode) {
     case MODE_EVOLVE:
       return e4i ? dispatch_dim<T, MODE_EVOLVE, 4>(L, out, in, g, tw, st)

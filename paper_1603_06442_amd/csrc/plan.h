@@ -53,6 +53,7 @@ struct qw_plan_s {
   int Nc = 1;
   int shift[3] = {0, 0, 0};
   bool fourstep = false;
+  bool weyl = false;  // two-component Weyl walk (d = 2, 3; s = 2, m = 0)
   int64_t fs_N1 = 1, fs_N2 = 1;
 
   // device memory
@@ -108,6 +109,7 @@ struct qw_plan_s {
 
 namespace qw {
 qw_status check_plan(qw_plan_t p);
+qw_status dirac_only(qw_plan_t p, const char* what);
 qw_status ensure_scratch(qw_plan_t p, size_t bytes);
 qw_status ensure_coefs(qw_plan_t p, int B);
 // psi_out = U^t psi_in for B instances back to back; dinst: device per-instance

@@ -450,6 +450,13 @@ qw_status check_plan(qw_plan_t p) {
   return QW_OK;
 }
 
+// Calls defined for the Dirac walk only (per-instance masses, particle states,
+// sector projectors, the cubic supercell) refuse a Weyl plan.
+qw_status dirac_only(qw_plan_t p, const char* what) {
+  if (p->weyl) return fail(QW_ERR_UNSUPPORTED, "%s is not defined for a Weyl plan", what);
+  return QW_OK;
+}
+
 // log2 x for a power of two x > 0, else -1.
 static int lg_pow2(int64_t x) {
   if (x <= 0 || (x & (x - 1))) return -1;
@@ -589,7 +596,9 @@ qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstP
   g.single = single;
   g.inst = dinst;
   int mode = MODE_EVOLVE;
-  if (!dinst && B == 1) {
+  if (p->weyl) {
+    mode = MODE_WEYL;
+  } else if (!dinst && B == 1) {
     g.omega = omega_table(p, st);
     if (g.omega) mode = MODE_EVOLVE_TAB;
   }
@@ -806,8 +815,21 @@ const char* qw_last_error(void) { return g_last_error.c_str(); }
 
 const char* qw_version(void) { return "qw-mi355x 0.1 (gfx950)"; }
 
+static qw_status plan_create(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype dtype,
+                             void* stream, bool weyl);
+
 qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype dtype,
                   void* stream) {
+  return plan_create(out, dim, N, m, dtype, stream, false);
+}
+
+qw_status qw_plan_weyl(qw_plan_t* out, int dim, const int64_t* N, qw_dtype dtype, void* stream) {
+  // d = 1: the Weyl walk diag(e^{-ik}, e^{ik}) is the Dirac walk at m = 0.
+  return plan_create(out, dim, N, 0.0, dtype, stream, dim >= 2);
+}
+
+static qw_status plan_create(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype dtype,
+                             void* stream, bool weyl) {
   if (!out) return fail(QW_ERR_INVALID, "out is NULL");
   *out = nullptr;
   if (dim < 1 || dim > 3) return fail(QW_ERR_INVALID, "dim must be 1, 2 or 3 (got %d)", dim);
@@ -824,7 +846,8 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
   qw_plan_t p = new (std::nothrow) qw_plan_s();
   if (!p) return fail(QW_ERR_NOMEM, "host allocation failed");
   p->dim = dim;
-  p->s = dim == 1 ? 2 : 4;
+  p->weyl = weyl;
+  p->s = (dim == 1 || weyl) ? 2 : 4;
   p->V = 1;
   for (int i = 0; i < dim; ++i) {
     p->N[i] = N[i];
@@ -953,6 +976,7 @@ static StencilGeom stencil_geom(qw_plan_t p) {
   }
   g.V = p->V;
   g.sparse3 = p->sparse3 ? 1 : 0;
+  g.weyl = p->weyl ? 1 : 0;
   return g;
 }
 
@@ -996,6 +1020,8 @@ qw_status qw_step(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
 qw_status qw_step_batched(qw_plan_t p, int B, void* psi, const double* m, int64_t nsteps,
                           void* stream) {
   qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  r = dirac_only(p, "qw_step_batched");
   if (r != QW_OK) return r;
   if (B < 0 || B > 65535) return fail(QW_ERR_INVALID, "B must lie in [0, 65535]");
   if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
@@ -1206,6 +1232,8 @@ qw_status qw_evolve_fft_batched(qw_plan_t p, int B, const void* in, void* out, c
                                 const int64_t* t, void* stream) {
   qw_status r = check_plan(p);
   if (r != QW_OK) return r;
+  r = dirac_only(p, "qw_evolve_fft_batched");
+  if (r != QW_OK) return r;
   if (B < 0) return fail(QW_ERR_INVALID, "B must be >= 0");
   if (B == 0) return QW_OK;
   if (!in || !out || !m || !t) return fail(QW_ERR_INVALID, "NULL argument");
@@ -1268,6 +1296,8 @@ static qw_status bcc_impl(qw_plan_t p, const void* in, void* out, int mode, doub
 
 static qw_status check_bcc(qw_plan_t p, const void* in, const void* out) {
   qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  r = dirac_only(p, "the cubic supercell");
   if (r != QW_OK) return r;
   if (p->dim != 3) return fail(QW_ERR_UNSUPPORTED, "the cubic supercell needs a 3D plan");
   if (!in || !out) return fail(QW_ERR_INVALID, "field pointer is NULL");
@@ -1336,6 +1366,8 @@ qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, 
 qw_status qw_newton_wigner(qw_plan_t p, const void* psi, const double* origin, qw_obs* sectors,
                            double* nw, void* stream) {
   qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  r = dirac_only(p, "qw_newton_wigner");
   if (r != QW_OK) return r;
   if (!psi || !origin || !sectors || !nw) return fail(QW_ERR_INVALID, "NULL argument");
   for (int i = 0; i < p->dim; ++i)
@@ -1534,6 +1566,7 @@ qw_status qw_dispersion_taylor(int dim, double m, const double* k0, int order, d
 
 static qw_status check_state_args(qw_plan_t p, void* psi, const double* k0, double sigma,
                                   const double* center, double c_plus, double c_minus) {
+  if (p->weyl) return fail(QW_ERR_UNSUPPORTED, "particle states are defined for the Dirac walk");
   if (!psi || !k0 || !center) return fail(QW_ERR_INVALID, "NULL argument");
   if (!(sigma > 0.0) || !isfinite(sigma)) return fail(QW_ERR_INVALID, "sigma must be > 0");
   if (!isfinite(c_plus) || !isfinite(c_minus) || (c_plus == 0.0 && c_minus == 0.0))

@@ -68,7 +68,8 @@ enum {
   MODE_PROJ_INV = 5,
   MODE_BCC = 6,
   MODE_BCC_FWD = 7,
-  MODE_BCC_INV = 8
+  MODE_BCC_INV = 8,
+  MODE_WEYL = 9  // two-component Weyl walk (d = 2, 3): W_q^t, omega per wave-vector
 };
 
 constexpr bool is_bcc_mode(int mode) {
@@ -76,7 +77,7 @@ constexpr bool is_bcc_mode(int mode) {
 }
 // Components per pencil of the contiguous pass.
 constexpr int contig_components(int dim, int mode) {
-  return is_bcc_mode(mode) ? 8 : (dim == 1 ? 2 : 4);
+  return is_bcc_mode(mode) ? 8 : ((dim == 1 || mode == MODE_WEYL) ? 2 : 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -107,6 +108,7 @@ struct StencilGeom {
   int lg[3];  // log2 N_i
   int64_t V;
   int sparse3;  // the 3D coefficients have the rank-one pattern above
+  int weyl;     // two-component Weyl walk (d = 2, 3): the `up` blocks only
 };
 
 // ---------------------------------------------------------------------------

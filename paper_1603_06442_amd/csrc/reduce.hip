@@ -9,12 +9,11 @@ namespace qw {
 
 // Each thread takes UNR sites per round, all loads of a round issued before
 // any arithmetic; FP64 accumulation.
-template <typename T, int DIM, bool REF>
+template <typename T, int DIM, bool REF, int S>
 __global__ __launch_bounds__(256) void k_observables(const cx<T>* __restrict__ psi_all,
                                                      const cx<T>* __restrict__ ref_all, ObsGeom g,
                                                      const double* __restrict__ origins,
                                                      double* __restrict__ partials_all) {
-  constexpr int S = DIM == 1 ? 2 : 4;
   constexpr int UNR = 4;
   const int64_t inst = blockIdx.y;
   const cx<T>* __restrict__ psi = psi_all + inst * S * g.V;
@@ -159,14 +158,17 @@ static void launch_obs_t(const ObsGeom& g, int B, const void* psi, const void* r
   auto p = (const cx<T>*)psi;
   auto r = (const cx<T>*)ref;
   const dim3 grid(nb, (unsigned)B);
-#define QW_OBS(D, R) \
-  hipLaunchKernelGGL((k_observables<T, D, R>), grid, dim3(256), 0, st, p, r, g, origins, partials)
+#define QW_OBS(D, R, S) \
+  hipLaunchKernelGGL((k_observables<T, D, R, S>), grid, dim3(256), 0, st, p, r, g, origins, partials)
+  // S = 2: the 1D Dirac walk and the two-component Weyl walks of d = 2, 3.
   if (g.dim == 1) {
-    if (ref) QW_OBS(1, true); else QW_OBS(1, false);
+    if (ref) QW_OBS(1, true, 2); else QW_OBS(1, false, 2);
   } else if (g.dim == 2) {
-    if (ref) QW_OBS(2, true); else QW_OBS(2, false);
+    if (g.s == 2) { if (ref) QW_OBS(2, true, 2); else QW_OBS(2, false, 2); }
+    else { if (ref) QW_OBS(2, true, 4); else QW_OBS(2, false, 4); }
   } else {
-    if (ref) QW_OBS(3, true); else QW_OBS(3, false);
+    if (g.s == 2) { if (ref) QW_OBS(3, true, 2); else QW_OBS(3, false, 2); }
+    else { if (ref) QW_OBS(3, true, 4); else QW_OBS(3, false, 4); }
   }
 #undef QW_OBS
 }

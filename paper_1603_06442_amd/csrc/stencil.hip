@@ -172,6 +172,53 @@ __global__ __launch_bounds__(256) void k_step_nd(cx<T>* __restrict__ out_all,
 }
 
 
+// Two-component Weyl walk of d = 2, 3 (Sec. 3.1): the same neighbour offsets
+// as the Dirac walk, with the Weyl transition matrices in `up` (the upper
+// blocks of the Dirac walk at m = 0) and no on-site term. One thread per
+// output site; each instance (blockIdx.y) is a field of 2 V entries.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_step_weyl(cx<T>* __restrict__ out_all,
+                                                  const cx<T>* __restrict__ in_all, StencilGeom g,
+                                                  const StencilCoef<T>* __restrict__ coefs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.V) return;
+  const int64_t V = g.V;
+  const cx<T>* __restrict__ in = in_all + (int64_t)blockIdx.y * 2 * V;
+  cx<T>* __restrict__ out = out_all + (int64_t)blockIdx.y * 2 * V;
+  const StencilCoef<T>& C = coefs[blockIdx.y];
+  int64_t n[3];
+  const int64_t m[3] = {g.N[0] - 1, g.N[1] - 1, g.N[2] - 1};
+  if constexpr (DIM == 3) {
+    n[2] = idx & m[2];
+    n[1] = (idx >> g.lg[2]) & m[1];
+    n[0] = idx >> (g.lg[2] + g.lg[1]);
+  } else {
+    n[1] = idx & m[1];
+    n[0] = idx >> g.lg[1];
+  }
+  constexpr int K = DIM == 3 ? 8 : 4;
+  cx<T> a0 = mk((T)0, (T)0), a1 = a0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    int64_t nb;
+    if constexpr (DIM == 3) {
+      const int64_t x = (n[0] + kOff3[k][0]) & m[0];
+      const int64_t y = (n[1] + kOff3[k][1]) & m[1];
+      const int64_t z = (n[2] + kOff3[k][2]) & m[2];
+      nb = (((x << g.lg[1]) | y) << g.lg[2]) | z;
+    } else {
+      const int64_t x = (n[0] + kOff2[k][0]) & m[0];
+      const int64_t y = (n[1] + kOff2[k][1]) & m[1];
+      nb = (x << g.lg[1]) | y;
+    }
+    const cx<T> q0 = in[nb], q1 = in[V + nb];
+    a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+    a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+  }
+  out[idx] = a0;
+  out[V + idx] = a1;
+}
+
 // ---------------------------------------------------------------------------
 // 3D step with an LDS ring of lattice planes. A workgroup owns a TN2 x TN3
 // tile of (n2, n3) and marches along n1 through a chunk of planes. Each input
@@ -402,8 +449,25 @@ hipError_t launch_step3d_ring(const StencilGeom& g, int B, void* out, const void
 hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
                        const void* coefs, hipStream_t st) {
   if (B < 1 || B > 65535) return hipErrorInvalidValue;
-  if (!dbl && step3d_ring_ok(g)) return launch_step3d_ring(g, B, out, in, coefs, st);
   const dim3 grid((unsigned)((g.V + 255) / 256), (unsigned)B);
+  if (g.weyl) {
+    if (g.dim < 2) return hipErrorInvalidValue;
+    if (dbl) {
+      auto C = (const StencilCoef<double>*)coefs;
+      auto o = (cx<double>*)out;
+      auto i = (const cx<double>*)in;
+      if (g.dim == 2) hipLaunchKernelGGL((k_step_weyl<double, 2>), grid, dim3(256), 0, st, o, i, g, C);
+      else hipLaunchKernelGGL((k_step_weyl<double, 3>), grid, dim3(256), 0, st, o, i, g, C);
+    } else {
+      auto C = (const StencilCoef<float>*)coefs;
+      auto o = (cx<float>*)out;
+      auto i = (const cx<float>*)in;
+      if (g.dim == 2) hipLaunchKernelGGL((k_step_weyl<float, 2>), grid, dim3(256), 0, st, o, i, g, C);
+      else hipLaunchKernelGGL((k_step_weyl<float, 3>), grid, dim3(256), 0, st, o, i, g, C);
+    }
+    return hipGetLastError();
+  }
+  if (!dbl && step3d_ring_ok(g)) return launch_step3d_ring(g, B, out, in, coefs, st);
   if (dbl) {
     auto C = (const StencilCoef<double>*)coefs;
     auto o = (cx<double>*)out;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libqw.so")
 QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE = range(5)
 QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
-EXPORTS = ("qw_plan", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
+EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables", "qw_newton_wigner",
            "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
@@ -69,6 +69,7 @@ def _load():
     vp, i64, dbl, cint = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     sig = {
         "qw_plan": [ctypes.POINTER(vp), cint, ctypes.POINTER(i64), dbl, cint, vp],
+        "qw_plan_weyl": [ctypes.POINTER(vp), cint, ctypes.POINTER(i64), cint, vp],
         "qw_destroy": [vp],
         "qw_step": [vp, vp, i64, vp],
         "qw_step_batched": [vp, cint, vp, ctypes.POINTER(dbl), i64, vp],
@@ -140,7 +141,10 @@ def _darr(vals, n):
 class Plan:
     """A lattice shape, mass and precision (qw_plan)."""
 
-    def __init__(self, dim, N, m, dtype="c64", stream=None):
+    def __init__(self, dim, N, m, dtype="c64", stream=None, weyl=False):
+        """weyl=True: the two-component Weyl walk (qw_plan_weyl; m must be 0)."""
+        if weyl and float(m) != 0.0:
+            raise ValueError("the Weyl walk is massless (m = 0)")
         if dtype not in DTYPES:
             raise ValueError("dtype must be 'c64' or 'c128'")
         self.dim = int(dim)
@@ -150,13 +154,18 @@ class Plan:
         self.N = tuple(Ns)
         self.m = float(m)
         self.dtype = dtype
-        self.s = 2 if self.dim == 1 else 4
+        self.weyl = bool(weyl)
+        self.s = 2 if (self.dim == 1 or self.weyl) else 4
         self.torch_dtype = DTYPES[dtype][1]
         self.shape = (self.s,) + self.N
         self._h = ctypes.c_void_p()
         arr = (ctypes.c_int64 * self.dim)(*Ns)
-        _check(LIB.qw_plan(ctypes.byref(self._h), self.dim, arr, self.m, DTYPES[dtype][0],
-                           _stream(stream)))
+        if self.weyl:
+            _check(LIB.qw_plan_weyl(ctypes.byref(self._h), self.dim, arr, DTYPES[dtype][0],
+                                    _stream(stream)))
+        else:
+            _check(LIB.qw_plan(ctypes.byref(self._h), self.dim, arr, self.m, DTYPES[dtype][0],
+                               _stream(stream)))
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -1,0 +1,189 @@
+"""GPU parity of the two-component Weyl walks of Sec. 3.1 (qw_plan_weyl)
+through the C ABI, against the oracle's Weyl transition matrices
+(walk.weyl_table): position-space steps, the Fourier jump for integer and
+real t, the transforms, the reductions, and the GPU Dirac walk at m = 0
+(whose upper block is the Weyl walk)."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fourier, observables as ob, stepper, walk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1603_06442_amd import qw as mod
+    return mod
+
+
+def to_dev(x, plan):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(plan.torch_dtype).cuda()
+
+
+def to_np(x):
+    torch.cuda.synchronize()
+    return x.cpu().numpy().astype(np.complex128)
+
+
+def tol_fft(dtype, t):
+    return 2e-5 if dtype == "c64" else max(1e-12, 1e-15 * abs(t))
+
+
+def tol_step(dtype, steps):
+    return max(2e-5, 4 * steps * 2.0 ** -24) if dtype == "c64" else 1e-12
+
+
+def rand2(shape, seed):
+    rng = np.random.default_rng(seed)
+    psi = rng.standard_normal((2,) + shape) + 1j * rng.standard_normal((2,) + shape)
+    return psi / np.linalg.norm(psi)
+
+
+SHAPES = [(2, (8, 16)), (2, (32, 32)), (2, (2, 2)), (3, (4, 8, 16)), (3, (16, 16, 16)),
+          (3, (2, 2, 2)), (3, (8, 4, 64))]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", SHAPES)
+def test_weyl_step_matches_oracle(qw, d, shape, dtype):
+    psi0 = rand2(shape, 3 + d)
+    plan = qw.Plan(d, list(shape), 0.0, dtype, weyl=True)
+    assert plan.shape == (2,) + shape
+    x = to_dev(psi0, plan)
+    tab = walk.weyl_table(d)
+    ref = psi0
+    done = 0
+    for k in (1, 6):
+        plan.step(x, k)
+        ref = stepper.evolve_steps(ref, tab, k)
+        done += k
+        assert ob.rel_l2(to_np(x), ref) < tol_step(dtype, done)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", SHAPES)
+@pytest.mark.parametrize("t", [0, 1, 5, -3, 1000, 100000])
+def test_weyl_evolve_fft_matches_oracle(qw, d, shape, t, dtype):
+    psi0 = rand2(shape, 20 + d)
+    plan = qw.Plan(d, list(shape), 0.0, dtype, weyl=True)
+    out = plan.evolve_fft(to_dev(psi0, plan), t)
+    ref = fourier.evolve_fourier(psi0, walk.weyl_table(d), t)
+    assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", [(2, (16, 8)), (3, (8, 8, 16))])
+@pytest.mark.parametrize("t", [2.5, -7.25, 1000.5])
+def test_weyl_real_t_matches_oracle(qw, d, shape, t, dtype):
+    """Real t: the principal-logarithm interpolation of Sec. 4 (at the band
+    edge omega = pi the average cos(pi t), as for the Dirac walk)."""
+    psi0 = rand2(shape, 30 + d)
+    plan = qw.Plan(d, list(shape), 0.0, dtype, weyl=True)
+    out = plan.evolve_fft_real(to_dev(psi0, plan), t)
+    ref = fourier.evolve_fourier_real(psi0, walk.weyl_table(d), t)
+    assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", SHAPES)
+def test_weyl_transform_matches_dft(qw, d, shape, dtype):
+    psi0 = rand2(shape, 40 + d)
+    plan = qw.Plan(d, list(shape), 0.0, dtype, weyl=True)
+    fw = plan.transform(to_dev(psi0, plan), +1)
+    tol = 1e-6 if dtype == "c64" else 1e-13
+    assert ob.rel_l2(to_np(fw), fourier.dft(psi0)) < tol
+    back = plan.transform(fw, -1)
+    assert ob.rel_l2(to_np(back) / np.prod(shape), psi0) < tol
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", [(2, (32, 16)), (3, (16, 8, 32))])
+def test_weyl_observables_and_marginals_match_oracle(qw, d, shape, dtype):
+    psi = rand2(shape, 50 + d)
+    refp = rand2(shape, 51 + d)
+    plan = qw.Plan(d, list(shape), 0.0, dtype, weyl=True)
+    c = [n / 3 + 0.37 for n in shape]
+    got = plan.observables(to_dev(psi, plan), c, ref=to_dev(refp, plan))
+    if dtype == "c64":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+        refp = refp.astype(np.complex64).astype(np.complex128)
+    want = ob.observables(psi, c, refp)
+    assert abs(got["norm2"] - want["norm2"]) < 1e-12
+    assert np.allclose(got["mean"][:d], want["mean"][:d], atol=1e-10)
+    assert np.allclose(got["second"], want["second"], atol=1e-9)
+    assert np.allclose(got["mean_cart"], want["mean_cart"], atol=1e-10)
+    assert abs(got["overlap"] - want["overlap"]) < 1e-12
+    ci = [n // 3 for n in shape]
+    gm = plan.marginals(to_dev(psi, plan), ci)
+    for (lo, vals), (wlo, wvals) in zip(gm, ob.marginals(psi, ci)):
+        assert lo == wlo and np.allclose(vals, wvals, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", [(2, (64, 32)), (3, (32, 16, 64))])
+def test_weyl_fused_observables_match_oracle(qw, d, shape, dtype):
+    psi0 = rand2(shape, 60 + d)
+    plan = qw.Plan(d, list(shape), 0.0, dtype, weyl=True)
+    t = 37
+    c = [n / 2 for n in shape]
+    out = torch.empty_like(to_dev(psi0, plan))
+    got = plan.evolve_fft_observables(to_dev(psi0, plan), t, c, out=out)
+    ref = fourier.evolve_fourier(psi0, walk.weyl_table(d), t)
+    assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
+    want = ob.observables(ref, c)
+    tol = 2e-5 if dtype == "c64" else 1e-10
+    assert abs(got["norm2"] - want["norm2"]) < tol
+    assert np.allclose(got["mean"][:d], want["mean"][:d], atol=tol * max(shape))
+
+
+@pytest.mark.parametrize("d,shape", [(2, (16, 32)), (3, (8, 16, 16))])
+def test_weyl_plan_is_the_upper_block_of_the_massless_dirac_plan(qw, d, shape):
+    """Two GPU paths: the Dirac walk at m = 0 on (psi, 0) keeps the lower
+    components at zero and its upper block equals the Weyl walk's result."""
+    psi0 = rand2(shape, 70 + d)
+    pw = qw.Plan(d, list(shape), 0.0, "c128", weyl=True)
+    pd = qw.Plan(d, list(shape), 0.0, "c128")
+    full = np.zeros((4,) + shape, dtype=np.complex128)
+    full[:2] = psi0
+    for t in (9, 1234):
+        a = to_np(pw.evolve_fft(to_dev(psi0, pw), t))
+        b = to_np(pd.evolve_fft(to_dev(full, pd), t))
+        assert np.abs(b[2:]).max() < 1e-13
+        assert np.abs(a - b[:2]).max() < 1e-12
+    xw = to_dev(psi0, pw)
+    xd = to_dev(full, pd)
+    pw.step(xw, 5)
+    pd.step(xd, 5)
+    assert np.abs(to_np(xw) - to_np(xd)[:2]).max() < 1e-13
+
+
+def test_weyl_1d_is_the_massless_dirac_walk(qw):
+    psi0 = rand2((64,), 80)
+    pw = qw.Plan(1, [64], 0.0, "c128", weyl=True)
+    assert pw.s == 2
+    got = to_np(pw.evolve_fft(to_dev(psi0, pw), 17))
+    assert ob.rel_l2(got, fourier.evolve_fourier(psi0, walk.weyl_table(1), 17)) < 1e-12
+
+
+def test_weyl_plan_rejects_dirac_only_calls(qw):
+    plan = qw.Plan(3, [8, 8, 8], 0.0, "c64", weyl=True)
+    x = plan.empty()
+    p = ctypes.c_void_p(x.data_ptr())
+    m = (ctypes.c_double * 1)(0.1)
+    t = (ctypes.c_int64 * 1)(3)
+    k = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    assert qw.LIB.qw_step_batched(plan._h, 1, p, m, 1, None) == qw.QW_ERR_UNSUPPORTED
+    assert qw.LIB.qw_evolve_fft_batched(plan._h, 1, p, p, m, t, None) == qw.QW_ERR_UNSUPPORTED
+    assert qw.LIB.qw_prepare_state(plan._h, p, k, 3.0, k, 1.0, 0.0, None) == qw.QW_ERR_UNSUPPORTED
+    assert qw.LIB.qw_bcc_evolve_fft(plan._h, p, p, 1.0, None) == qw.QW_ERR_UNSUPPORTED
+    sec = (qw.QwObs * 2)()
+    nw = (ctypes.c_double * 6)()
+    assert qw.LIB.qw_newton_wigner(plan._h, p, k, sec, nw, None) == qw.QW_ERR_UNSUPPORTED
+    with pytest.raises(ValueError):
+        qw.Plan(2, [8, 8], 0.3, "c64", weyl=True)
