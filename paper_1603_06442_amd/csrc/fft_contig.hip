@@ -238,7 +238,7 @@ __device__ __forceinline__ void dirac_mix4(cx<T> (&p)[4], T c, T a, T b, T e, T 
 // (cos, sin)(pi j / Nc) table: pi j_i / N_i is entry j_i << shift_i.
 template <typename T, int MODE>
 __device__ __forceinline__ void apply_bcc(cx<T> (&y)[8], const PassGeom& g, int64_t j1,
-                                          int64_t j2, int64_t j3) {
+                                          int64_t j2, int64_t j3, int64_t qidx) {
   const int64_t mask = 2 * (int64_t)g.Nc - 1;
   const int64_t a1 = (j1 << g.shift[0]) & mask;
   const int64_t a2 = (j2 << g.shift[1]) & mask;
@@ -266,6 +266,42 @@ __device__ __forceinline__ void apply_bcc(cx<T> (&y)[8], const PassGeom& g, int6
       y[4 + c] = mk((f0.x + px) * sc, (f0.y + py) * sc);  // h1
     }
     return;
+  } else if constexpr (MODE == MODE_BCC_TAB) {
+    // complex64 with the plan's table: omega(kappa) and the phase reductions
+    // FP64, n~ and sin(omega) FP32 from the FP32 trig table (they only scale
+    // the result).
+    const float cxf = g.csf[2 * a1], sxf = g.csf[2 * a1 + 1];
+    const float cyf = g.csf[2 * a2], syf = g.csf[2 * a2 + 1];
+    const float czf = g.csf[2 * a3], szf = g.csf[2 * a3 + 1];
+    const float n1 = sxf * cyf * czf - cxf * syf * szf;
+    const float n2 = cxf * syf * czf + sxf * cyf * szf;
+    const float n3 = cxf * cyf * szf - sxf * syf * czf;
+    const float tn = (float)g.single.n, tm = (float)g.single.m;
+    const float sinw = sqrtf(tn * tn * (n1 * n1 + n2 * n2 + n3 * n3) + tm * tm);
+    const double wA = g.omega[qidx];
+    const double wB = (3.141592653589793116 - wA) + 1.2246467991473532e-16;
+    float CA, SA, CB, SB;
+    sincosf((float)reduced_phase(wA, g.single.t), &SA, &CA);
+    sincosf((float)reduced_phase(wB, g.single.t), &SB, &CB);
+    const float isw = sinw > 1e-30f ? 1.0f / sinw : 0.0f;
+    const T a = (T)(tn * n3), b = (T)(tn * n1), e = (T)(tn * n2);
+    const T stA = (T)(SA * isw) * sc, stB = (T)(SB * isw) * sc;
+    cx<T> h0[4], h1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const cx<T> f1 = y[4 + c];
+      const T px = ar * f1.x - ai * f1.y, py = ar * f1.y + ai * f1.x;  // a f1
+      h1[c] = mk(y[c].x + px, y[c].y + py);
+      h0[c] = mk(y[c].x - px, y[c].y - py);
+    }
+    dirac_mix4<T>(h1, (T)CA * sc, a * stA, b * stA, e * stA, (T)tm * stA);
+    dirac_mix4<T>(h0, (T)CB * sc, -a * stB, -b * stB, -e * stB, (T)tm * stB);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const T dx = h1[c].x - h0[c].x, dy = h1[c].y - h0[c].y;
+      y[c] = mk(h0[c].x + h1[c].x, h0[c].y + h1[c].y);
+      y[4 + c] = mk(ar * dx + ai * dy, ar * dy - ai * dx);  // conj(a) (h1 - h0)
+    }
   } else {
     // The scalar coefficients first (FP64 omega and phase reduction), so the
     // spinor values are combined only once they are needed.
@@ -530,7 +566,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
         cx<T> y[S];
 #pragma unroll
         for (int c = 0; c < S; ++c) y[c] = v[c][0];
-        apply_bcc<T, MODE>(y, g, j1, j2, j3);
+        apply_bcc<T, MODE>(y, g, j1, j2, j3, pen * L + z);
 #pragma unroll
         for (int c = 0; c < S; ++c) {
 #pragma unroll
@@ -787,6 +823,12 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
     case MODE_BCC_INV:
       if (g.dim != 3) return hipErrorInvalidValue;
       return dispatch_contig<T, 3, MODE_BCC_INV, kBccE>(L, out, in, g, tw, st);
+    case MODE_BCC_TAB:
+      if constexpr (sizeof(T) == 4) {
+        if (g.dim != 3 || !g.omega) return hipErrorInvalidValue;
+        return dispatch_contig<T, 3, MODE_BCC_TAB, kBccE>(L, out, in, g, tw, st);
+      }
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -808,6 +850,37 @@ hipError_t launch_omega_table(const PassGeom& g, int64_t L, double* omega, hipSt
   if (g.dim == 1) hipLaunchKernelGGL(k_omega_table<1>, dim3(nblk), dim3(256), 0, st, g, L, omega);
   else if (g.dim == 2) hipLaunchKernelGGL(k_omega_table<2>, dim3(nblk), dim3(256), 0, st, g, L, omega);
   else hipLaunchKernelGGL(k_omega_table<3>, dim3(nblk), dim3(256), 0, st, g, L, omega);
+  return hipGetLastError();
+}
+
+// omega(kappa), kappa = pi j / N, for the cubic-supercell pass (the Weyl u
+// and n~ at the Cartesian kappa, from the FP64 trig table).
+__global__ __launch_bounds__(256) void k_omega_bcc_table(PassGeom g, int64_t L,
+                                                         double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.V) return;
+  const int64_t pen = idx / L, z = idx - pen * L;
+  int64_t j1, j2, j3;
+  q_index<3>(g, pen, z, j1, j2, j3);
+  const int64_t mask = 2 * (int64_t)g.Nc - 1;
+  const int64_t a1 = (j1 << g.shift[0]) & mask;
+  const int64_t a2 = (j2 << g.shift[1]) & mask;
+  const int64_t a3 = (j3 << g.shift[2]) & mask;
+  const double cx_ = g.cs[2 * a1], sx = g.cs[2 * a1 + 1];
+  const double cy = g.cs[2 * a2], sy = g.cs[2 * a2 + 1];
+  const double cz = g.cs[2 * a3], sz = g.cs[2 * a3 + 1];
+  const double u = cx_ * cy * cz + sx * sy * sz;
+  const double n1 = sx * cy * cz - cx_ * sy * sz;
+  const double n2 = cx_ * sy * cz + sx * cy * sz;
+  const double n3 = cx_ * cy * sz - sx * sy * cz;
+  const double nn = g.single.n, m = g.single.m;
+  out[idx] = atan2(sqrt(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m), nn * u);
+}
+
+hipError_t launch_omega_bcc_table(const PassGeom& g, int64_t L, double* omega, hipStream_t st) {
+  if (g.dim != 3) return hipErrorInvalidValue;
+  const unsigned nblk = (unsigned)((g.V + 255) / 256);
+  hipLaunchKernelGGL(k_omega_bcc_table, dim3(nblk), dim3(256), 0, st, g, L, omega);
   return hipGetLastError();
 }
 

@@ -78,6 +78,8 @@ struct qw_plan_s {
   qw::StateInst* d_stage = nullptr;
   double* d_omega = nullptr;    // omega(q) at the plan's mass, built on first use
   bool omega_failed = false;
+  double* d_omega_bcc = nullptr;  // omega(kappa) of the cubic supercell, built on first use
+  bool omega_bcc_failed = false;
 
   // Schedule of the 3D Fourier evolution (see qw_set_schedule / qw_autotune).
   int slab = 0;  // n1 planes per slab of the middle passes (0 = whole field)
@@ -101,6 +103,7 @@ struct qw_plan_s {
     if (d_coefs) (void)hipFree(d_coefs);
     if (h_coefs) (void)hipHostFree(h_coefs);
     if (d_omega) (void)hipFree(d_omega);
+    if (d_omega_bcc) (void)hipFree(d_omega_bcc);
     if (h_stage) (void)hipHostFree(h_stage);
     if (d_stage) (void)hipFree(d_stage);
   }

@@ -1275,12 +1275,35 @@ qw_status qw_transform(qw_plan_t p, const void* in, void* out, int direction, vo
 // Cubic-supercell field [2][s][N1 N2 N3] (Sec. 4, eq:bcc-dft / eq:bcc-idft):
 // the strided passes take it as two fields of s components, the pass along n3
 // as one pencil of 2s components (combine, per-k powers, recombination).
+// omega(kappa) of the cubic supercell at the plan's mass (V doubles), built
+// on first use; without it the pass evaluates omega per wave-vector.
+static const double* omega_bcc_table(qw_plan_t p, hipStream_t st) {
+  if (p->d_omega_bcc || p->omega_bcc_failed) return p->d_omega_bcc;
+  if (hipMalloc((void**)&p->d_omega_bcc, sizeof(double) * p->V) != hipSuccess) {
+    p->d_omega_bcc = nullptr;
+    p->omega_bcc_failed = true;
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  PassGeom g = pass_geom(p, p->N[2], 1);
+  if (launch_omega_bcc_table(g, p->N[2], p->d_omega_bcc, st) != hipSuccess) {
+    (void)hipFree(p->d_omega_bcc);
+    p->d_omega_bcc = nullptr;
+    p->omega_bcc_failed = true;
+  }
+  return p->d_omega_bcc;
+}
+
 static qw_status bcc_impl(qw_plan_t p, const void* in, void* out, int mode, double t,
                           hipStream_t st) {
   const int64_t L = p->N[2];
   PassGeom g = pass_geom(p, L, 1);
   g.single.t = t;
   g.inv_scale = mode == MODE_BCC ? 0.5 / (double)p->V : 1.0 / sqrt(2.0 * (double)p->V);
+  if (mode == MODE_BCC && !p->dbl) {
+    g.omega = omega_bcc_table(p, st);
+    if (g.omega) mode = MODE_BCC_TAB;
+  }
   if (mode == MODE_BCC_INV) {
     HIP_TRY(launch_fft_contig(p->dbl, mode, L, out, in, g, p->d_tw, st, 4));
     mark();

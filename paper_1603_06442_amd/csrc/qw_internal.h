@@ -69,11 +69,12 @@ enum {
   MODE_BCC = 6,
   MODE_BCC_FWD = 7,
   MODE_BCC_INV = 8,
-  MODE_WEYL = 9  // two-component Weyl walk (d = 2, 3): W_q^t, omega per wave-vector
+  MODE_WEYL = 9,  // two-component Weyl walk (d = 2, 3): W_q^t, omega per wave-vector
+  MODE_BCC_TAB = 10  // MODE_BCC, complex64, omega(kappa) from the plan's cubic-supercell table
 };
 
 constexpr bool is_bcc_mode(int mode) {
-  return mode == MODE_BCC || mode == MODE_BCC_FWD || mode == MODE_BCC_INV;
+  return mode == MODE_BCC || mode == MODE_BCC_FWD || mode == MODE_BCC_INV || mode == MODE_BCC_TAB;
 }
 // Components per pencil of the contiguous pass.
 constexpr int contig_components(int dim, int mode) {
@@ -124,6 +125,9 @@ hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, con
 hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const void* in,
                              const PassGeom& g, const void* tw, hipStream_t st, int E = 0);
 hipError_t launch_omega_table(const PassGeom& g, int64_t L, double* omega, hipStream_t st);
+// omega(kappa) of the cubic-supercell field at kappa = pi j / N (sublattice
+// frequency indices in storage order), at the plan's mass; V doubles.
+hipError_t launch_omega_bcc_table(const PassGeom& g, int64_t L, double* omega, hipStream_t st);
 hipError_t launch_transpose(bool dbl, void* out, const void* in, int64_t planes, int64_t R,
                             int64_t C, hipStream_t st);
 // One step of B fields back to back; coefs: DEVICE array of B StencilCoef of
