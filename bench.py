@@ -402,7 +402,8 @@ def main():
         "evolve_fft_observables": wall(lambda: plan.evolve_fft_observables(
             psi0, 1000, w["center"], out=psit)),
     }
-    line["cubic_supercell"] = cubic_line(qw, N, w["m"], wall)
+    line["cubic_supercell"] = cubic_line(qw, [N, N, N], w["m"], wall)
+    line["weyl"] = weyl_line(qw, [N, N, N], wall)
     line["stencil_1d"] = stencil_line(qw)
     if not args.no_serving:
         line["serving"] = serving(qw)
@@ -417,6 +418,7 @@ def cubic_line(qw, N, m, wall):
     period 2N), one Fourier jump (three passes of the two arrays as eight
     planes, the a_k combine, both frequencies and the recombination fused into
     the pass along n3) and the two-sublattice transform alone."""
+    import torch
     plan = qw.Plan(3, N, m, "c64")
     f = torch.randn((2, 4) + tuple(N), dtype=torch.complex64, device="cuda",
                     generator=torch.Generator(device="cuda").manual_seed(5))
@@ -430,6 +432,25 @@ def cubic_line(qw, N, m, wall):
            "transform_ms": wall(lambda: plan.bcc_transform(f, 1, out=g), reps=10),
            "norm_after": float(torch.linalg.vector_norm(plan.bcc_evolve_fft(f, 1000, out=g)))}
     del f, g, plan
+    return out
+
+
+def weyl_line(qw, N, wall):
+    """The two-component Weyl walk on the workload's lattice (complex64):
+    one Fourier jump and the time per position-space step."""
+    import torch
+    plan = qw.Plan(3, N, 0.0, "c64", weyl=True)
+    x = torch.randn((2,) + tuple(N), dtype=torch.complex64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(6))
+    x /= torch.linalg.vector_norm(x)
+    y = torch.empty_like(x)
+    V = N[0] * N[1] * N[2]
+    ev = wall(lambda: plan.evolve_fft(x, 1000, out=y), reps=10)
+    # two steps per call: an even count ends in the caller's buffer (no copy back)
+    st = round(wall(lambda: plan.step(y, 2), reps=10) / 2, 4)
+    out = {"lattice": list(N), "spinor": 2, "ms_per_evolution": ev, "ms_per_step": st,
+           "step_gbs": round(2 * 2 * 8 * V / (st * 1e-3) / 1e9, 1)}
+    del x, y, plan
     return out
 
 

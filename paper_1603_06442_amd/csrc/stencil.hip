@@ -115,6 +115,14 @@ __global__ __launch_bounds__(kResThreads) void k_step1d_resident(
   }
 }
 
+// Workgroup b runs on XCD b % 8 (each XCD has its own L2). With a grid that
+// divides into eight, XCD x gets the contiguous range of blocks
+// [x n/8, (x+1) n/8): the neighbour rows and planes a site reads then sit in
+// the same L2 instead of being fetched by several XCDs.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
+  return (n & 7) == 0 ? (b & 7) * (n >> 3) + (b >> 3) : b;
+}
+
 __device__ constexpr int kOff2[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
 __device__ constexpr int kOff3[8][3] = {{1, 0, 0},  {0, -1, 0}, {0, 0, -1}, {-1, -1, -1},
                                         {-1, 0, 0}, {0, 1, 0},  {0, 0, 1},  {1, 1, 1}};
@@ -123,7 +131,7 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_step_nd(cx<T>* __restrict__ out_all,
                                                 const cx<T>* __restrict__ in_all, StencilGeom g,
                                                 const StencilCoef<T>* __restrict__ coefs) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (idx >= g.V) return;
   const int64_t V = g.V;
   const cx<T>* __restrict__ in = in_all + (int64_t)blockIdx.y * 4 * V;
@@ -180,7 +188,7 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_step_weyl(cx<T>* __restrict__ out_all,
                                                   const cx<T>* __restrict__ in_all, StencilGeom g,
                                                   const StencilCoef<T>* __restrict__ coefs) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (idx >= g.V) return;
   const int64_t V = g.V;
   const cx<T>* __restrict__ in = in_all + (int64_t)blockIdx.y * 2 * V;

@@ -67,6 +67,19 @@ def test_weyl_step_matches_oracle(qw, d, shape, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("shape", [(8, 8, 64), (4, 16, 128), (32, 8, 64), (16, 32, 256)])
+def test_weyl_step_3d_larger_lattices_match_oracle(qw, shape, dtype):
+    """Larger and non-cubic 3D lattices (many workgroups per XCD range of the
+    one-thread-per-site kernel)."""
+    psi0 = rand2(shape, 90)
+    plan = qw.Plan(3, list(shape), 0.0, dtype, weyl=True)
+    x = to_dev(psi0, plan)
+    plan.step(x, 5)
+    ref = stepper.evolve_steps(psi0, walk.weyl_table(3), 5)
+    assert ob.rel_l2(to_np(x), ref) < tol_step(dtype, 5)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("d,shape", SHAPES)
 @pytest.mark.parametrize("t", [0, 1, 5, -3, 1000, 100000])
 def test_weyl_evolve_fft_matches_oracle(qw, d, shape, t, dtype):
