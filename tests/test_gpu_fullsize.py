@@ -7,7 +7,9 @@ field (two steps: about 16 s of host time), the fused reductions with the
 oracle's reductions of that field, and the evolution is checked to be
 reversible at t = 1e5. 512^3 (the large workload): complex64 against
 complex128 at t = 1e6 and the Fourier jump against a stencil step, on the
-whole field."""
+whole field. The Weyl walk on the 256^3 lattice and the cubic supercell of
+two 256^3 sublattice arrays: a localised state against the oracle on a small
+torus that holds the whole light cone."""
 import numpy as np
 import pytest
 import torch
@@ -132,3 +134,61 @@ def test_max_2d_lattice_against_oracle(qw, dtype):
     s = x.clone()
     plan.step(s, 3)
     assert ob.rel_l2(s.cpu().numpy().astype(np.complex128), stepper.evolve_steps(psi, tab, 3)) < tol
+
+
+def test_weyl256_c64_localised_state_against_oracle(qw):
+    """The Weyl walk on the 256^3 workload lattice (complex64), stencil and
+    Fourier jump: a state localised at the centre, after 12 steps, against
+    the oracle's steps on a 32^3 torus (the light cone fits); the rest of
+    the 256^3 field stays zero up to rounding."""
+    N, t, c = 256, 12, 128
+    zeta = np.array([0.8, 0.6j])
+    plan = qw.Plan(3, N, 0.0, "c64", weyl=True)
+    x = torch.zeros((2, N, N, N), dtype=torch.complex64, device="cuda")
+    x[:, c, c, c] = torch.from_numpy(zeta).to(torch.complex64)
+    y = plan.evolve_fft(x, t)
+    plan.step(x, t)
+    small = np.zeros((2, 32, 32, 32), dtype=np.complex128)
+    small[:, 0, 0, 0] = zeta
+    ref = stepper.evolve_steps(small, walk.weyl_table(3), t)
+    for field in (x, y):
+        torch.cuda.synchronize()
+        win = field[:, c - t:c + t + 1, c - t:c + t + 1, c - t:c + t + 1].cpu().numpy()
+        r = np.arange(-t, t + 1) % 32
+        want = ref[np.ix_([0, 1], r, r, r)]
+        assert ob.rel_l2(win.astype(np.complex128), want) < 2e-5
+        assert abs(float(torch.linalg.vector_norm(field)) - 1.0) < 2e-5
+
+
+def test_cubic256_c64_localised_state_against_oracle(qw):
+    """The cubic supercell at the timed size (two 256^3 sublattice arrays,
+    complex64): a state localised on the even sublattice, evolved by one
+    jump to t = 6, against the oracle's Cartesian steps on a 16^3 Cartesian
+    torus (the light cone fits); norm kept on the whole field."""
+    from oracle import cubic
+    N, t, m = 256, 6, 0.02
+    zeta = np.array([0.6, 0.2j, -0.5, 0.3 + 0.4j])
+    zeta = zeta / np.linalg.norm(zeta)
+    plan = qw.Plan(3, N, m, "c64")
+    f = torch.zeros((2, 4, N, N, N), dtype=torch.complex64, device="cuda")
+    f[0, :, 64, 64, 64] = torch.from_numpy(zeta).to(torch.complex64)
+    g = plan.bcc_evolve_fft(f, t)
+    fc = np.zeros((4, 16, 16, 16), dtype=np.complex128)
+    fc[:, 0, 0, 0] = zeta
+    ct = cubic.cartesian_table(m)
+    for _ in range(t):
+        fc = cubic.step_cartesian(fc, ct)
+    # Cartesian site x = 2*64 + w (|w_i| <= t) of the big torus: sublattice
+    # parity of w, index 64 + floor(w/2)
+    r = np.arange(-t, t + 1)
+    W = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    W = W[(W[:, 0] % 2 == W[:, 1] % 2) & (W[:, 1] % 2 == W[:, 2] % 2)]
+    sub = W[:, 0] % 2
+    mm = 64 + (W - sub[:, None]) // 2
+    dev = lambda a: torch.from_numpy(a).cuda()
+    got = g[dev(sub), :, dev(mm[:, 0]), dev(mm[:, 1]), dev(mm[:, 2])].T
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.complex128)
+    want = fc[:, W[:, 0] % 16, W[:, 1] % 16, W[:, 2] % 16]
+    assert ob.rel_l2(got, want) < 2e-5
+    assert abs(float(torch.linalg.vector_norm(g)) - 1.0) < 2e-5
