@@ -173,13 +173,15 @@ __device__ __forceinline__ void apply_proj(cx<T> (&y)[DIM == 1 ? 2 : 4], const P
 //   W_q^t = cos(omega t) I - i sin(omega t)/sin(omega) sigma.n~,
 // the Dirac closed form with n = 1, m = 0 restricted to its upper block.
 // omega and its phase reduction are FP64; the rest in the field precision.
-template <typename T, int DIM>
+// With TAB, omega comes from the plan's table (the Dirac table at n = 1,
+// m = 0 is the Weyl omega).
+template <typename T, int DIM, bool TAB>
 __device__ __forceinline__ void apply_weyl(cx<T> (&y)[2], const PassGeom& g, const InstParam& ip,
-                                           int64_t j1, int64_t j2, int64_t j3) {
+                                           int64_t j1, int64_t j2, int64_t j3, int64_t qidx) {
   double u, n1, n2, n3;
   weyl_un(DIM, g.cs, g.Nc, g.shift, j1, j2, j3, u, n1, n2, n3);
   const double sinw = sqrt(n1 * n1 + n2 * n2 + n3 * n3);
-  const double r = reduced_phase(atan2(sinw, u), ip.t);
+  const double r = reduced_phase(TAB ? g.omega[qidx] : atan2(sinw, u), ip.t);
   T C, S, isw;
   if constexpr (sizeof(T) == 4) {
     sincosf((float)r, &S, &C);
@@ -538,7 +540,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
       }
       fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
     }
-    if constexpr (MODE == MODE_WEYL) {
+    if constexpr (MODE == MODE_WEYL || MODE == MODE_WEYL_TAB) {
       const InstParam ip = g.single;
 #pragma unroll 1
       for (int e = 0; e < E; ++e) {
@@ -548,7 +550,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
         cx<T> y[S];
 #pragma unroll
         for (int c = 0; c < S; ++c) y[c] = v[c][0];
-        apply_weyl<T, DIM>(y, g, ip, j1, j2, j3);
+        apply_weyl<T, DIM, MODE == MODE_WEYL_TAB>(y, g, ip, j1, j2, j3, pen * L + z);
 #pragma unroll
         for (int c = 0; c < S; ++c) {
 #pragma unroll
@@ -795,6 +797,10 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
       case MODE_WEYL:
         return g.dim == 2 ? dispatch_contig<T, 2, MODE_WEYL, 8>(L, out, in, g, tw, st)
                           : dispatch_contig<T, 3, MODE_WEYL, 8>(L, out, in, g, tw, st);
+      case MODE_WEYL_TAB:
+        if (!g.omega) return hipErrorInvalidValue;
+        return g.dim == 2 ? dispatch_contig<T, 2, MODE_WEYL_TAB, 8>(L, out, in, g, tw, st)
+                          : dispatch_contig<T, 3, MODE_WEYL_TAB, 8>(L, out, in, g, tw, st);
       default: return hipErrorInvalidValue;
     }
   }

@@ -70,7 +70,8 @@ enum {
   MODE_BCC_FWD = 7,
   MODE_BCC_INV = 8,
   MODE_WEYL = 9,  // two-component Weyl walk (d = 2, 3): W_q^t, omega per wave-vector
-  MODE_BCC_TAB = 10  // MODE_BCC, complex64, omega(kappa) from the plan's cubic-supercell table
+  MODE_BCC_TAB = 10,  // MODE_BCC, complex64, omega(kappa) from the plan's cubic-supercell table
+  MODE_WEYL_TAB = 11  // MODE_WEYL with omega(q) from the plan's table
 };
 
 constexpr bool is_bcc_mode(int mode) {
@@ -78,7 +79,8 @@ constexpr bool is_bcc_mode(int mode) {
 }
 // Components per pencil of the contiguous pass.
 constexpr int contig_components(int dim, int mode) {
-  return is_bcc_mode(mode) ? 8 : ((dim == 1 || mode == MODE_WEYL) ? 2 : 4);
+  return is_bcc_mode(mode) ? 8
+                           : ((dim == 1 || mode == MODE_WEYL || mode == MODE_WEYL_TAB) ? 2 : 4);
 }
 
 // ---------------------------------------------------------------------------
