@@ -29,11 +29,11 @@
  * their per-instance parameters. A plan may be used by one stream at a
  * time; distinct plans are independent.
  *
- * Graph capture: qw_step, qw_evolve_fft and qw_transform enqueue only
- * kernels and device-to-device copies and never synchronise, so a caller may
- * capture them into a HIP graph and replay it. Their first call on a plan
- * may allocate (scratch, the omega table); make one call outside the
- * capture first.
+ * Graph capture: qw_step, qw_evolve_fft, qw_evolve_fft_real, qw_transform,
+ * qw_bcc_transform and qw_bcc_evolve_fft enqueue only kernels and
+ * device-to-device copies and never synchronise, so a caller may capture them
+ * into a HIP graph and replay it. Their first call on a plan may allocate
+ * (scratch, the omega tables); make one call outside the capture first.
  *
  * Errors: every call returns a qw_status; nothing throws across the ABI.
  * qw_last_error() returns a message for the last failing call of the calling

@@ -151,3 +151,42 @@ def test_bcc_rejects_other_dimensions(qw):
     q = ctypes.c_void_p(y.data_ptr())
     assert qw.LIB.qw_bcc_transform(plan3._h, q, q, 0, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_bcc_evolve_fft(plan3._h, q, q, float("inf"), None) == qw.QW_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_bcc_capture_into_a_graph(qw, dtype):
+    """qw_bcc_evolve_fft and qw_bcc_transform, called once beforehand (the
+    plan builds its omega table then), captured into a HIP graph: every
+    replay, with eager work and synchronisations between replays, gives
+    bitwise the eager result."""
+    N = (16, 8, 64)
+    plan = qw.Plan(3, list(N), 0.11, dtype)
+    f0 = to_dev(rand_sub(N, 13), plan)
+    a = plan.bcc_evolve_fft(f0, 29)
+    h = plan.bcc_transform(a, +1)
+    torch.cuda.synchronize()
+    want_a, want_h = a.clone(), h.clone()
+    ga, gh = torch.empty_like(f0), torch.empty_like(f0)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.bcc_evolve_fft(f0, 29, out=ga, stream=side)
+        plan.bcc_transform(ga, +1, out=gh, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        s = torch.cuda.current_stream()
+        plan.bcc_evolve_fft(f0, 29, out=ga, stream=s)
+        plan.bcc_transform(ga, +1, out=gh, stream=s)
+    for r in range(3):
+        ga.zero_()
+        gh.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ga, want_a), r
+        assert torch.equal(gh, want_h), r
+        e = plan.bcc_evolve_fft(f0, 3)  # eager work between replays
+        torch.cuda.synchronize()
+        del e

@@ -200,3 +200,41 @@ def test_weyl_plan_rejects_dirac_only_calls(qw):
     assert qw.LIB.qw_newton_wigner(plan._h, p, k, sec, nw, None) == qw.QW_ERR_UNSUPPORTED
     with pytest.raises(ValueError):
         qw.Plan(2, [8, 8], 0.3, "c64", weyl=True)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_weyl_capture_into_a_graph(qw, dtype):
+    """qw_step and qw_evolve_fft on a Weyl plan, called once beforehand,
+    captured into a HIP graph: every replay, with eager work and
+    synchronisations between replays, gives bitwise the eager result."""
+    shape = (8, 16, 64)
+    plan = qw.Plan(3, list(shape), 0.0, dtype, weyl=True)
+    x0 = to_dev(rand2(shape, 7), plan)
+    a = x0.clone()
+    plan.step(a, 3)
+    b = plan.evolve_fft(a, 41)
+    torch.cuda.synchronize()
+    want_a, want_b = a.clone(), b.clone()
+    ga, gb = x0.clone(), torch.empty_like(x0)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.step(ga.clone(), 3, stream=side)
+        plan.evolve_fft(ga, 41, out=gb, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        s = torch.cuda.current_stream()
+        plan.step(ga, 3, stream=s)
+        plan.evolve_fft(ga, 41, out=gb, stream=s)
+    for r in range(3):
+        ga.copy_(x0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ga, want_a), r
+        assert torch.equal(gb, want_b), r
+        e = x0.clone()
+        plan.step(e, 1)
+        torch.cuda.synchronize()
