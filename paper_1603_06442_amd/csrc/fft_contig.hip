@@ -269,25 +269,40 @@ __device__ __forceinline__ void apply_bcc(cx<T> (&y)[8], const PassGeom& g, int6
     }
     return;
   } else if constexpr (MODE == MODE_BCC_TAB) {
-    // complex64 with the plan's table: omega(kappa) and the phase reductions
-    // FP64, n~ and sin(omega) FP32 from the FP32 trig table (they only scale
-    // the result).
-    const float cxf = g.csf[2 * a1], sxf = g.csf[2 * a1 + 1];
-    const float cyf = g.csf[2 * a2], syf = g.csf[2 * a2 + 1];
-    const float czf = g.csf[2 * a3], szf = g.csf[2 * a3 + 1];
-    const float n1 = sxf * cyf * czf - cxf * syf * szf;
-    const float n2 = cxf * syf * czf + sxf * cyf * szf;
-    const float n3 = cxf * cyf * szf - sxf * syf * czf;
-    const float tn = (float)g.single.n, tm = (float)g.single.m;
-    const float sinw = sqrtf(tn * tn * (n1 * n1 + n2 * n2 + n3 * n3) + tm * tm);
+    // omega(kappa) from the plan's table, the phase reductions FP64; n~ and
+    // sin(omega) in the field precision from the trig table of that
+    // precision (they only scale the result).
+    T cxf, sxf, cyf, syf, czf, szf;
+    if constexpr (sizeof(T) == 4) {
+      cxf = g.csf[2 * a1]; sxf = g.csf[2 * a1 + 1];
+      cyf = g.csf[2 * a2]; syf = g.csf[2 * a2 + 1];
+      czf = g.csf[2 * a3]; szf = g.csf[2 * a3 + 1];
+    } else {
+      cxf = g.cs[2 * a1]; sxf = g.cs[2 * a1 + 1];
+      cyf = g.cs[2 * a2]; syf = g.cs[2 * a2 + 1];
+      czf = g.cs[2 * a3]; szf = g.cs[2 * a3 + 1];
+    }
+    const T n1 = sxf * cyf * czf - cxf * syf * szf;
+    const T n2 = cxf * syf * czf + sxf * cyf * szf;
+    const T n3 = cxf * cyf * szf - sxf * syf * czf;
+    const T tn = (T)g.single.n, tm = (T)g.single.m;
+    const T s2 = tn * tn * (n1 * n1 + n2 * n2 + n3 * n3) + tm * tm;
     const double wA = g.omega[qidx];
     const double wB = (3.141592653589793116 - wA) + 1.2246467991473532e-16;
-    float CA, SA, CB, SB;
-    sincosf((float)reduced_phase(wA, g.single.t), &SA, &CA);
-    sincosf((float)reduced_phase(wB, g.single.t), &SB, &CB);
-    const float isw = sinw > 1e-30f ? 1.0f / sinw : 0.0f;
-    const T a = (T)(tn * n3), b = (T)(tn * n1), e = (T)(tn * n2);
-    const T stA = (T)(SA * isw) * sc, stB = (T)(SB * isw) * sc;
+    T CA, SA, CB, SB, isw;
+    if constexpr (sizeof(T) == 4) {
+      sincosf((float)reduced_phase(wA, g.single.t), &SA, &CA);
+      sincosf((float)reduced_phase(wB, g.single.t), &SB, &CB);
+      const float sinw = sqrtf(s2);
+      isw = sinw > 1e-30f ? 1.0f / sinw : 0.0f;
+    } else {
+      sincos(reduced_phase(wA, g.single.t), &SA, &CA);
+      sincos(reduced_phase(wB, g.single.t), &SB, &CB);
+      const double sinw = sqrt(s2);
+      isw = sinw > 0.0 ? 1.0 / sinw : 0.0;
+    }
+    const T a = tn * n3, b = tn * n1, e = tn * n2;
+    const T stA = SA * isw * sc, stB = SB * isw * sc;
     cx<T> h0[4], h1[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -830,11 +845,8 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
       if (g.dim != 3) return hipErrorInvalidValue;
       return dispatch_contig<T, 3, MODE_BCC_INV, kBccE>(L, out, in, g, tw, st);
     case MODE_BCC_TAB:
-      if constexpr (sizeof(T) == 4) {
-        if (g.dim != 3 || !g.omega) return hipErrorInvalidValue;
-        return dispatch_contig<T, 3, MODE_BCC_TAB, kBccE>(L, out, in, g, tw, st);
-      }
-      return hipErrorInvalidValue;
+      if (g.dim != 3 || !g.omega) return hipErrorInvalidValue;
+      return dispatch_contig<T, 3, MODE_BCC_TAB, kBccE>(L, out, in, g, tw, st);
     default: return hipErrorInvalidValue;
   }
 }

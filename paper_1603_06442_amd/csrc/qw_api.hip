@@ -1305,7 +1305,7 @@ static qw_status bcc_impl(qw_plan_t p, const void* in, void* out, int mode, doub
   PassGeom g = pass_geom(p, L, 1);
   g.single.t = t;
   g.inv_scale = mode == MODE_BCC ? 0.5 / (double)p->V : 1.0 / sqrt(2.0 * (double)p->V);
-  if (mode == MODE_BCC && !p->dbl) {
+  if (mode == MODE_BCC) {
     g.omega = omega_bcc_table(p, st);
     if (g.omega) mode = MODE_BCC_TAB;
   }
