@@ -76,7 +76,18 @@ def cpu_baseline(w, budget_s=15.0):
             "sample": "%d oracle Fourier evolutions (numpy FFT + binary powering, complex128, "
                       "single thread) of the 64^3 sub-lattice at t from the 1..1e5 schedule in "
                       "%.1f s, scaled by (64/256)^3 to the 256^3 unit" % (done, el),
-            "host_threads_available": os.cpu_count()}
+            "host_threads_available": os.cpu_count(), "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def copy_calib(steps):
@@ -184,6 +195,20 @@ def serving(qw, budget_gib=16):
         lat = [1e3 * x["latency_s"] for x in pres]
         bad = sum(1 for x in res + pres if x["status"] != qw.QW_OK)
         drift = max(abs(x["obs"]["norm2"] - 1.0) for x in res)
+        # The same burst in complex128, one request per batch (the plain
+        # single-instance FP64 form), and under a 256 MiB budget that forces
+        # requests to queue for memory.
+        reqs128 = [dict(r, dtype="c128") for r in reqs]
+        _burst(one, reqs128)
+        el128, res128 = _burst(one, reqs128)
+        small = qw.Server(256 << 20, max_batch=32, nstreams=4)
+        try:
+            _burst(small, reqs)
+            els, ress = _burst(small, reqs)
+            sst = small.stats()
+        finally:
+            small.close()
+        bad += sum(1 for x in res128 + ress if x["status"] != qw.QW_OK)
         return {
             "requests": len(reqs), "budget_bytes": budget, "max_batch": 32, "streams": 4,
             "saturation_requests_per_s": round(sat, 1),
@@ -196,6 +221,10 @@ def serving(qw, budget_gib=16):
             "mean_batch_poisson": round(sum(x["batch_size"] for x in pres) / len(pres), 2),
             "peak_used_bytes": st["peak_used_bytes"], "failed": bad,
             "max_norm_drift": drift,
+            "unbatched_c128_requests_per_s": round(len(reqs) / el128, 1),
+            "small_budget": {"budget_bytes": 256 << 20,
+                             "requests_per_s": round(len(reqs) / els, 1),
+                             "peak_used_bytes": sst["peak_used_bytes"]},
         }
     finally:
         srv.close()
