@@ -428,6 +428,7 @@ def main():
         "evolve_fft_real_t_1000.5": wall(lambda: plan.evolve_fft_real(psi0, 1000.5, out=psit)),
         "newton_wigner": wall(lambda: plan.newton_wigner(psi0, w["center"])),
         "marginals": wall(lambda: plan.marginals(psi0, [int(x) for x in w["center"]])),
+        "kspace_drift": wall(lambda: plan.kspace_drift(psi0)),
         "evolve_fft_observables": wall(lambda: plan.evolve_fft_observables(
             psi0, 1000, w["center"], out=psit)),
     }

@@ -191,6 +191,27 @@ qw_status qw_bcc_transform(qw_plan_t plan, const void* in, void* out, int direct
  * powers up to 2^53). f_t may equal f0. */
 qw_status qw_bcc_evolve_fft(qw_plan_t plan, const void* f0, void* f_t, double t, void* stream);
 
+/* The drift law of Sec. 5.1 (drift vector; Sec. 5.2, the classical part of
+ * the mean position), from the spectrum of psi: each frequency sector moves
+ * along -grad_q omega, so the drift part of the mean position changes by
+ *   velocity = -sum_q grad_q omega(q) (|P+ hat psi(q)|^2 - |P- hat psi(q)|^2)
+ *              / sum_q |hat psi(q)|^2
+ * per step (primitive coordinates; the Zitterbewegung term is left out),
+ * with P+- = (I +- M_q / sin(omega)) / 2 the sector projectors and
+ * grad_q omega = -n grad_q u / sin(omega). Also the sector weights
+ * <psi|P+-|psi> (= ||P+- psi||^2) and ||psi||^2. Wave-vectors with
+ * sin(omega) < 1e-12 (only at m = 0), where the two sectors coincide, add
+ * nothing to the drift and split their weight evenly between the sectors.
+ * Uses the plan's scratch field; waits for the result. Weyl plans:
+ * M = sigma . n~. */
+typedef struct {
+  double velocity[3];      /* primitive coordinates, per step */
+  double velocity_cart[3]; /* sum_j velocity_j h_j */
+  double sector_norm2[2];  /* <psi|P+|psi>, <psi|P-|psi> */
+  double norm2;            /* ||psi||^2 */
+} qw_drift;
+qw_status qw_kspace_drift(qw_plan_t plan, const void* psi, qw_drift* out, void* stream);
+
 /* Reductions of psi (see qw_obs). origin: dim HOST doubles. ref: NULL or a
  * DEVICE field of the same shape. out: HOST. Waits for the result. */
 qw_status qw_observables(qw_plan_t plan, const void* psi, const double* origin, const void* ref,

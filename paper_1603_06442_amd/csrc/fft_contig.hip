@@ -463,23 +463,6 @@ __device__ __forceinline__ void apply_q_f32(cx<float> (&y)[DIM == 1 ? 2 : 4], co
   }
 }
 
-// Map (pencil, position) of the contiguous pass to lattice frequency indices.
-template <int DIM>
-__device__ __forceinline__ void q_index(const PassGeom& g, int64_t pen, int64_t z, int64_t& j1,
-                                        int64_t& j2, int64_t& j3) {
-  j2 = 0;
-  j3 = 0;
-  if constexpr (DIM == 3) {
-    j1 = pen >> g.lgN1;
-    j2 = pen & (g.N[1] - 1);
-    j3 = z;
-  } else if constexpr (DIM == 2) {
-    j1 = pen;
-    j2 = z;
-  } else {
-    j1 = g.fourstep ? pen + g.N1 * z : z;
-  }
-}
 
 // Pencil groups: group r holds the P pencils r*P .. r*P+P-1 of the launch.
 // A workgroup walks the groups blockIdx.x, blockIdx.x + gridDim.x, ... and

@@ -1510,6 +1510,50 @@ qw_status qw_marginals(qw_plan_t p, const void* psi, const int64_t* origin, doub
   return QW_OK;
 }
 
+qw_status qw_kspace_drift(qw_plan_t p, const void* psi, qw_drift* out, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi || !out) return fail(QW_ERR_INVALID, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  r = ensure_scratch(p, p->field_bytes);
+  if (r != QW_OK) return r;
+  // The spectrum in the storage order of the fused pass (the forward half of
+  // the evolution), in the plan's scratch field.
+  const int64_t L = contig_len(p);
+  PassGeom g = pass_geom(p, L, 1);
+  if (has_strided(p)) {
+    r = strided_passes(p, +1, p->d_scratch, psi, 1, st, nullptr);
+    if (r != QW_OK) return r;
+    HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, p->d_scratch, p->d_scratch, g, p->d_tw, st));
+  } else {
+    HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, p->d_scratch, psi, g, p->d_tw, st));
+  }
+  HIP_TRY(launch_kdrift(p->dbl, g, L, p->d_scratch, p->d_partials, p->d_result, st));
+  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double* R = p->h_result;
+  memset(out, 0, sizeof *out);
+  const double inv = R[0] > 0.0 ? 1.0 / R[0] : 0.0;
+  for (int i = 0; i < p->dim; ++i) out->velocity[i] = -R[2 + i] * inv;
+  const double* v = out->velocity;
+  if (p->dim == 1) {
+    out->velocity_cart[0] = v[0];
+  } else if (p->dim == 2) {
+    out->velocity_cart[0] = v[0] + v[1];
+    out->velocity_cart[1] = v[0] - v[1];
+  } else {
+    out->velocity_cart[0] = v[0] + v[1] - v[2];
+    out->velocity_cart[1] = v[0] - v[1] + v[2];
+    out->velocity_cart[2] = v[0] - v[1] - v[2];
+  }
+  // Parseval: |hat psi|^2 sums to V |psi|^2 with the unnormalised transform.
+  const double iv = 1.0 / (double)p->V;
+  out->norm2 = R[0] * iv;
+  out->sector_norm2[0] = 0.5 * (R[0] + R[1]) * iv;
+  out->sector_norm2[1] = 0.5 * (R[0] - R[1]) * iv;
+  return QW_OK;
+}
+
 qw_status qw_observables(qw_plan_t p, const void* psi, const double* origin, const void* ref,
                          qw_obs* out, void* stream) {
   qw_status r = check_plan(p);

@@ -156,6 +156,12 @@ constexpr int kObsFields = 13;  // norm2, s1[3], s2[6], ov_re, ov_im, ref_norm2
 constexpr int kObsBlocks = 4096;
 // Workgroups per instance of the reduction (partials need B * this * 13 doubles).
 int64_t observables_blocks(const ObsGeom& g, int B);
+// k-space drift sums over a spectrum in the storage order of the fused pass
+// (pencils of length L): result[0] = sum |hat psi|^2, result[1] =
+// sum (|P+ hat psi|^2 - |P- hat psi|^2), result[2..4] = sum grad_q omega times
+// the latter (FP64; at most 1024 workgroups, one-stage final sum).
+hipError_t launch_kdrift(bool dbl, const PassGeom& g, int64_t L, const void* spec,
+                         double* partials, double* result, hipStream_t st);
 hipError_t launch_observables(bool dbl, const ObsGeom& g, int B, const void* psi, const void* ref,
                               const double* origins, double* partials, double* result,
                               hipStream_t st);
@@ -355,6 +361,24 @@ __device__ __forceinline__ void weyl_un(int dim, const double* __restrict__ cs, 
   n1 = sx * cy * cz - cx_ * sy * sz;
   n2 = cx_ * sy * cz + sx * cy * sz;
   n3 = cx_ * cy * sz - sx * sy * cz;
+}
+
+// Map (pencil, position) of the contiguous pass to lattice frequency indices.
+template <int DIM>
+__device__ __forceinline__ void q_index(const PassGeom& g, int64_t pen, int64_t z, int64_t& j1,
+                                        int64_t& j2, int64_t& j3) {
+  j2 = 0;
+  j3 = 0;
+  if constexpr (DIM == 3) {
+    j1 = pen >> g.lgN1;
+    j2 = pen & (g.N[1] - 1);
+    j3 = z;
+  } else if constexpr (DIM == 2) {
+    j1 = pen;
+    j2 = z;
+  } else {
+    j1 = g.fourstep ? pen + g.N1 * z : z;
+  }
 }
 
 }  // namespace qw

@@ -143,6 +143,134 @@ hipError_t launch_reduce_partials(int B, int64_t nb, const double* partials, dou
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// k-space drift (Sec. 5.1, drift vector; Sec. 5.2, the classical part of the
+// mean position). On the spectrum in the storage order of the fused pass:
+//   w(q)     = |hat psi(q)|^2,
+//   wd(q)    = |P+ hat psi|^2 - |P- hat psi|^2 = Re(hat psi^dag M_q hat psi) / sin(omega)
+//              (P+- = (I +- M_q / sin(omega)) / 2; 0 where sin(omega) < 1e-12),
+//   grad(q)  = d omega / d q_j = -n (d u / d q_j) / sin(omega)   (cos(omega) = n u),
+// summed in FP64: fields 0: sum w, 1: sum wd, 2..4: sum grad_j wd.
+// u is differentiated through the Cartesian k(q) of the lattice (3D:
+// k = ((q1+q2)/2, (q1+q3)/2, -(q2+q3)/2); 2D: ((q1+q2)/2, (q1-q2)/2); 1D: k = q).
+template <int DIM>
+__device__ __forceinline__ void weyl_du(const PassGeom& g, int64_t j1, int64_t j2, int64_t j3,
+                                        double (&du)[3]) {
+  const int64_t twoNc = 2 * (int64_t)g.Nc;
+  const int64_t a1 = j1 << g.shift[0];
+  du[0] = du[1] = du[2] = 0.0;
+  if constexpr (DIM == 1) {
+    du[0] = -g.cs[2 * ((2 * a1) & (twoNc - 1)) + 1];
+  } else if constexpr (DIM == 2) {
+    const int64_t a2 = j2 << g.shift[1];
+    const int64_t jx = (a1 + a2) & (twoNc - 1), jy = (a1 - a2 + twoNc) & (twoNc - 1);
+    const double cx_ = g.cs[2 * jx], sx = g.cs[2 * jx + 1];
+    const double cy = g.cs[2 * jy], sy = g.cs[2 * jy + 1];
+    const double dx = -sx * cy, dy = -cx_ * sy;
+    du[0] = 0.5 * (dx + dy);
+    du[1] = 0.5 * (dx - dy);
+  } else {
+    const int64_t a2 = j2 << g.shift[1], a3 = j3 << g.shift[2];
+    const int64_t jx = (a1 + a2) & (twoNc - 1), jy = (a1 + a3) & (twoNc - 1),
+                  jz = (a2 + a3) & (twoNc - 1);
+    const double cx_ = g.cs[2 * jx], sx = g.cs[2 * jx + 1];
+    const double cy = g.cs[2 * jy], sy = g.cs[2 * jy + 1];
+    const double cz = g.cs[2 * jz], sz = -g.cs[2 * jz + 1];
+    const double dx = -sx * cy * cz + cx_ * sy * sz;
+    const double dy = -cx_ * sy * cz + sx * cy * sz;
+    const double dz = -cx_ * cy * sz + sx * sy * cz;
+    du[0] = 0.5 * (dx + dy);
+    du[1] = 0.5 * (dx - dz);
+    du[2] = 0.5 * (dy - dz);
+  }
+}
+
+// a^dag (sigma . n~) a for a two-spinor a.
+template <typename T>
+__device__ __forceinline__ double sigma_form(cx<T> a0, cx<T> a1, double n1, double n2, double n3) {
+  const double x0 = a0.x, y0 = a0.y, x1 = a1.x, y1 = a1.y;
+  const double re = x0 * x1 + y0 * y1, im = x0 * y1 - y0 * x1;  // conj(a0) a1
+  return 2.0 * (n1 * re + n2 * im) + n3 * (x0 * x0 + y0 * y0 - x1 * x1 - y1 * y1);
+}
+
+template <typename T, int DIM, int S>
+__global__ __launch_bounds__(256) void k_kdrift(const cx<T>* __restrict__ spec, PassGeom g,
+                                               int64_t L, double* __restrict__ partials) {
+  double acc[kObsFields];
+#pragma unroll
+  for (int f = 0; f < kObsFields; ++f) acc[f] = 0.0;
+  const int64_t V = g.V;
+  const double nn = g.single.n, m = g.single.m;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < V; idx += stride) {
+    const int64_t pen = idx / L, z = idx - pen * L;
+    int64_t j1, j2, j3;
+    q_index<DIM>(g, pen, z, j1, j2, j3);
+    double u, n1, n2, n3;
+    weyl_un(DIM, g.cs, g.Nc, g.shift, j1, j2, j3, u, n1, n2, n3);
+    cx<T> y[S];
+#pragma unroll
+    for (int c = 0; c < S; ++c) y[c] = spec[c * V + idx];
+    double w = 0.0;
+#pragma unroll
+    for (int c = 0; c < S; ++c) w += (double)y[c].x * y[c].x + (double)y[c].y * y[c].y;
+    double form;  // Re(hat psi^dag M hat psi)
+    if constexpr (S == 4) {
+      const double cross = (double)y[0].x * y[2].x + (double)y[0].y * y[2].y +
+                           (double)y[1].x * y[3].x + (double)y[1].y * y[3].y;
+      form = nn * (sigma_form<T>(y[0], y[1], n1, n2, n3) - sigma_form<T>(y[2], y[3], n1, n2, n3)) -
+             2.0 * m * cross;
+    } else if constexpr (DIM == 1) {
+      // M = n sin(q) sigma_z - m sigma_x
+      const double cross = (double)y[0].x * y[1].x + (double)y[0].y * y[1].y;
+      form = nn * n3 * ((double)y[0].x * y[0].x + (double)y[0].y * y[0].y -
+                        (double)y[1].x * y[1].x - (double)y[1].y * y[1].y) -
+             2.0 * m * cross;
+    } else {
+      form = sigma_form<T>(y[0], y[1], n1, n2, n3);  // Weyl walk: M = sigma . n~
+    }
+    const double sinw = sqrt(nn * nn * (n1 * n1 + n2 * n2 + n3 * n3) + m * m);
+    acc[0] += w;
+    if (sinw >= 1e-12) {
+      const double isw = 1.0 / sinw;
+      const double wd = form * isw;
+      double du[3];
+      weyl_du<DIM>(g, j1, j2, j3, du);
+      acc[1] += wd;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc[2 + j] += -nn * du[j] * isw * wd;
+    }
+  }
+  block_reduce_store<kObsFields>(acc, partials + (int64_t)blockIdx.x * kObsFields);
+}
+
+int64_t kdrift_blocks(int64_t V) {
+  int64_t nb = (V + 1023) / 1024;
+  if (nb > 1024) nb = 1024;
+  return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_kdrift(bool dbl, const PassGeom& g, int64_t L, const void* spec,
+                         double* partials, double* result, hipStream_t st) {
+  const int64_t nb = kdrift_blocks(g.V);
+  const dim3 grid((unsigned)nb);
+#define QW_KD(T, D, S) \
+  hipLaunchKernelGGL((k_kdrift<T, D, S>), grid, dim3(256), 0, st, (const cx<T>*)spec, g, L, partials)
+  if (dbl) {
+    if (g.dim == 1) QW_KD(double, 1, 2);
+    else if (g.dim == 2) { if (g.s == 2) QW_KD(double, 2, 2); else QW_KD(double, 2, 4); }
+    else { if (g.s == 2) QW_KD(double, 3, 2); else QW_KD(double, 3, 4); }
+  } else {
+    if (g.dim == 1) QW_KD(float, 1, 2);
+    else if (g.dim == 2) { if (g.s == 2) QW_KD(float, 2, 2); else QW_KD(float, 2, 4); }
+    else { if (g.s == 2) QW_KD(float, 3, 2); else QW_KD(float, 3, 4); }
+  }
+#undef QW_KD
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_partials(1, nb, partials, nullptr, result, st);  // nb <= 1024: one stage
+}
+
 // The number of workgroups (and so the summation order) depends on the shape
 // only, never on the batch: an instance reduces identically alone or batched.
 int64_t observables_blocks(const ObsGeom& g, int B) {

@@ -22,7 +22,7 @@ QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables", "qw_newton_wigner",
-           "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft",
+           "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft", "qw_kspace_drift",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
            "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
            "qw_server_create", "qw_server_submit", "qw_server_poll", "qw_server_wait",
@@ -33,6 +33,11 @@ class QwError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("qw status %d: %s" % (status, message))
         self.status = status
+
+
+class QwDrift(ctypes.Structure):
+    _fields_ = [("velocity", ctypes.c_double * 3), ("velocity_cart", ctypes.c_double * 3),
+                ("sector_norm2", ctypes.c_double * 2), ("norm2", ctypes.c_double)]
 
 
 class QwObs(ctypes.Structure):
@@ -81,6 +86,7 @@ def _load():
         "qw_transform": [vp, vp, vp, cint, vp],
         "qw_bcc_transform": [vp, vp, vp, cint, vp],
         "qw_bcc_evolve_fft": [vp, vp, vp, dbl, vp],
+        "qw_kspace_drift": [vp, vp, ctypes.POINTER(QwDrift), vp],
         "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
         "qw_newton_wigner": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(QwObs), ctypes.POINTER(dbl),
                              vp],
@@ -266,6 +272,15 @@ class Plan:
         _check(LIB.qw_bcc_evolve_fft(self._h, self._field(f0, 2, "f0"),
                                      self._field(out, 2, "out"), float(t), _stream(stream)))
         return out
+
+    def kspace_drift(self, psi, stream=None):
+        """qw_kspace_drift: drift velocity per step (primitive and Cartesian)
+        and the sector norms of psi."""
+        o = QwDrift()
+        _check(LIB.qw_kspace_drift(self._h, self._field(psi, name="psi"), ctypes.byref(o),
+                                   _stream(stream)))
+        return {"velocity": list(o.velocity)[:self.dim], "velocity_cart": list(o.velocity_cart),
+                "sector_norm2": list(o.sector_norm2), "norm2": o.norm2}
 
     def observables(self, psi, origin, ref=None, stream=None):
         """qw_observables: norm, positions about origin, overlap with ref."""

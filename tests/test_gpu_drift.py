@@ -1,0 +1,124 @@
+"""GPU parity of the k-space drift (Sec. 5.1 drift vector, Sec. 5.2 classical
+part of the mean position) through the C ABI: qw_kspace_drift against the
+oracle's drift sum (gradients of omega from the transition-matrix table, not
+from the closed form) and sector projectors, and against the GPU's own
+evolution of a one-sector packet."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fourier, observables as ob, states, walk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1603_06442_amd import qw as mod
+    return mod
+
+
+def to_dev(x, plan):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(plan.torch_dtype).cuda()
+
+
+def rand_field(s, shape, seed):
+    rng = np.random.default_rng(seed)
+    psi = rng.standard_normal((s,) + shape) + 1j * rng.standard_normal((s,) + shape)
+    return psi / np.linalg.norm(psi)
+
+
+def oracle_drift(psi, table):
+    d = psi.ndim - 1
+    N = psi.shape[1:]
+    v = ob.drift_prediction(psi, table, 1.0)
+    D = walk.symbol_from_table(table, walk.lattice_q(N, d))
+    Pp, Pm = states.sector_projectors(D)
+    ph = fourier.dft(psi)
+    V = float(np.prod(N))
+    sp = np.sum(sector_weight(Pp, ph)) / V
+    sm = np.sum(sector_weight(Pm, ph)) / V
+    return v, sp, sm
+
+
+def sector_weight(P, ph):
+    """<hat psi(q)| P |hat psi(q)> per wave-vector: |P hat psi|^2 where P is a
+    projector; where the sectors coincide (P = I/2) it splits |hat psi|^2
+    evenly."""
+    return np.real(np.sum(np.conj(ph) * fourier.apply_symbol(P, ph), axis=0))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", [(1, (64,)), (1, (8192,)), (2, (16, 32)), (3, (8, 16, 16)),
+                                     (3, (16, 16, 16))])
+@pytest.mark.parametrize("m", [0.1, 0.4])
+def test_kspace_drift_matches_oracle(qw, d, shape, m, dtype):
+    s = walk.spinor_dim(d)
+    psi = rand_field(s, shape, 11 + d)
+    plan = qw.Plan(d, list(shape), m, dtype)
+    got = plan.kspace_drift(to_dev(psi, plan))
+    if dtype == "c64":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    v, sp, sm = oracle_drift(psi, walk.stencil_table(d, m))
+    tol = 2e-5 if dtype == "c64" else 1e-11
+    assert np.allclose(got["velocity"], v, atol=tol, rtol=0)
+    assert abs(got["sector_norm2"][0] - sp) < tol and abs(got["sector_norm2"][1] - sm) < tol
+    assert abs(got["norm2"] - np.sum(np.abs(psi) ** 2)) < tol
+    H = walk.generators(d)
+    assert np.allclose(got["velocity_cart"][:d], H @ np.array(got["velocity"]), atol=1e-14)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("d,shape", [(2, (32, 16)), (3, (8, 8, 16))])
+def test_kspace_drift_of_the_weyl_walk(qw, d, shape, dtype):
+    """The massless walk has sin(omega) = 0 at q = 0 and at the band edge,
+    where omega has no gradient and the two sectors coincide: those
+    wave-vectors add nothing to the drift and split their weight evenly
+    between the sectors (the oracle's sum is formed here from its gradient
+    and projectors with them left out of the drift)."""
+    psi = rand_field(2, shape, 21 + d)
+    plan = qw.Plan(d, list(shape), 0.0, dtype, weyl=True)
+    got = plan.kspace_drift(to_dev(psi, plan))
+    if dtype == "c64":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    tab = walk.weyl_table(d)
+    D = walk.symbol_from_table(tab, walk.lattice_q(shape, d))
+    cosw = np.real(np.trace(D, axis1=-2, axis2=-1)) / 2
+    sinw = np.sqrt(np.sum(np.abs(1j * (D - cosw[..., None, None] * np.eye(2))[..., :, 0]) ** 2,
+                          axis=-1))
+    ok = sinw >= states.SINGULAR_SIN_OMEGA
+    with np.errstate(divide="ignore", invalid="ignore"):
+        _, grad = ob.omega_and_grad(tab, shape, d)
+    grad = np.where(ok[..., None], grad, 0.0)
+    Pp, Pm = states.sector_projectors(D)
+    ph = fourier.dft(psi)
+    wp = sector_weight(Pp, ph)
+    wm = sector_weight(Pm, ph)
+    tot = np.sum(np.abs(ph) ** 2)
+    v = -np.array([np.sum(grad[..., j] * (wp - wm)) for j in range(d)]) / tot
+    V = float(np.prod(shape))
+    tol = 2e-5 if dtype == "c64" else 1e-11
+    assert np.allclose(got["velocity"], v, atol=tol, rtol=0)
+    assert abs(got["sector_norm2"][0] - np.sum(wp) / V) < tol
+    assert abs(got["sector_norm2"][1] - np.sum(wm) / V) < tol
+
+
+@pytest.mark.parametrize("d,N", [(1, 512), (3, 64)])
+def test_one_sector_packet_moves_with_the_drift(qw, d, N):
+    """A particle state (one sector, Def. 1) moves by t times the drift
+    velocity (GPU evolution and GPU observables against qw_kspace_drift)."""
+    m, sigma = 0.3, (20.0 if d == 1 else 6.0)
+    k0 = [0.4] if d == 1 else [0.3, -0.2, 0.1]
+    c = [N / 2] * d
+    plan = qw.Plan(d, [N] * d, m, "c128")
+    x = plan.empty()
+    plan.prepare_state(x, k0, sigma, c, 1.0, 0.0)
+    dr = plan.kspace_drift(x)
+    assert abs(dr["sector_norm2"][0] - 1.0) < 1e-12 and dr["sector_norm2"][1] < 1e-12
+    t = 10
+    o0 = plan.observables(x, c)
+    o1 = plan.observables(plan.evolve_fft(x, t), c)
+    shift = np.array(o1["mean"][:d]) - np.array(o0["mean"][:d])
+    assert np.allclose(shift, t * np.array(dr["velocity"]), atol=2e-5 * t)
