@@ -122,3 +122,24 @@ def test_one_sector_packet_moves_with_the_drift(qw, d, N):
     o1 = plan.observables(plan.evolve_fft(x, t), c)
     shift = np.array(o1["mean"][:d]) - np.array(o0["mean"][:d])
     assert np.allclose(shift, t * np.array(dr["velocity"]), atol=2e-5 * t)
+
+
+def test_drift_of_the_1d_workload_matches_the_oracle(qw):
+    """The 1D workload (N = 4096, complex128, m = 0.1, k0 = 0.3, sigma = 40,
+    one sector): the GPU's drift over t = 1000 steps equals the oracle's drift
+    sum on the oracle's own particle state, and the GPU's stepped mean moves by
+    the same amount (the drift law of Sec. 5.1 is exact for one sector)."""
+    from paper_1603_06442_amd import inputs
+    w = inputs.workload(0)
+    T = walk.stencil_table(1, w["m"])
+    psi = states.particle_state(1, w["N"], w["m"], w["k0"], w["sigma"], w["center"])
+    want = ob.drift_prediction(psi, T, 1000)[0]
+    plan = qw.Plan(1, w["N"], w["m"], "c128")
+    x = plan.empty()
+    plan.prepare_state(x, w["k0"], w["sigma"], w["center"], 1.0, 0.0)
+    got = 1000 * plan.kspace_drift(x)["velocity"][0]
+    assert abs(got - want) < 1e-8
+    y = x.clone()
+    plan.step(y, 1000)
+    dx = plan.observables(y, w["center"])["mean"][0] - plan.observables(x, w["center"])["mean"][0]
+    assert abs(dx - got) < 1e-8
