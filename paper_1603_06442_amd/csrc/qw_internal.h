@@ -159,7 +159,8 @@ int64_t observables_blocks(const ObsGeom& g, int B);
 // k-space drift sums over a spectrum in the storage order of the fused pass
 // (pencils of length L): result[0] = sum |hat psi|^2, result[1] =
 // sum (|P+ hat psi|^2 - |P- hat psi|^2), result[2..4] = sum grad_q omega times
-// the latter (FP64; at most 1024 workgroups, one-stage final sum).
+// the latter (FP64; at most 2048 workgroups; partials needs (2048 + 64) *
+// kObsFields doubles). L is a power of two.
 hipError_t launch_kdrift(bool dbl, const PassGeom& g, int64_t L, const void* spec,
                          double* partials, double* result, hipStream_t st);
 hipError_t launch_observables(bool dbl, const ObsGeom& g, int B, const void* psi, const void* ref,

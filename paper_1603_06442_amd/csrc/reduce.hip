@@ -195,7 +195,7 @@ __device__ __forceinline__ double sigma_form(cx<T> a0, cx<T> a1, double n1, doub
 
 template <typename T, int DIM, int S>
 __global__ __launch_bounds__(256) void k_kdrift(const cx<T>* __restrict__ spec, PassGeom g,
-                                               int64_t L, double* __restrict__ partials) {
+                                               int lgL, double* __restrict__ partials) {
   double acc[kObsFields];
 #pragma unroll
   for (int f = 0; f < kObsFields; ++f) acc[f] = 0.0;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void k_kdrift(const cx<T>* __restrict__ spec, 
   const double nn = g.single.n, m = g.single.m;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < V; idx += stride) {
-    const int64_t pen = idx / L, z = idx - pen * L;
+    const int64_t pen = idx >> lgL, z = idx & ((int64_t(1) << lgL) - 1);
     int64_t j1, j2, j3;
     q_index<DIM>(g, pen, z, j1, j2, j3);
     double u, n1, n2, n3;
@@ -244,9 +244,11 @@ __global__ __launch_bounds__(256) void k_kdrift(const cx<T>* __restrict__ spec, 
   block_reduce_store<kObsFields>(acc, partials + (int64_t)blockIdx.x * kObsFields);
 }
 
+// At most 2048 workgroups: their partials and the 64 of the middle stage
+// fit the plan's partials buffer (at least 13 * 4096 doubles) at any shape.
 int64_t kdrift_blocks(int64_t V) {
   int64_t nb = (V + 1023) / 1024;
-  if (nb > 1024) nb = 1024;
+  if (nb > 2048) nb = 2048;
   return nb < 1 ? 1 : nb;
 }
 
@@ -254,8 +256,11 @@ hipError_t launch_kdrift(bool dbl, const PassGeom& g, int64_t L, const void* spe
                          double* partials, double* result, hipStream_t st) {
   const int64_t nb = kdrift_blocks(g.V);
   const dim3 grid((unsigned)nb);
+  int lgL = 0;
+  while ((int64_t(1) << lgL) < L) ++lgL;
+  if ((int64_t(1) << lgL) != L) return hipErrorInvalidValue;
 #define QW_KD(T, D, S) \
-  hipLaunchKernelGGL((k_kdrift<T, D, S>), grid, dim3(256), 0, st, (const cx<T>*)spec, g, L, partials)
+  hipLaunchKernelGGL((k_kdrift<T, D, S>), grid, dim3(256), 0, st, (const cx<T>*)spec, g, lgL, partials)
   if (dbl) {
     if (g.dim == 1) QW_KD(double, 1, 2);
     else if (g.dim == 2) { if (g.s == 2) QW_KD(double, 2, 2); else QW_KD(double, 2, 4); }
@@ -268,7 +273,7 @@ hipError_t launch_kdrift(bool dbl, const PassGeom& g, int64_t L, const void* spe
 #undef QW_KD
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_reduce_partials(1, nb, partials, nullptr, result, st);  // nb <= 1024: one stage
+  return launch_reduce_partials(1, nb, partials, partials + nb * kObsFields, result, st);
 }
 
 // The number of workgroups (and so the summation order) depends on the shape

@@ -143,3 +143,16 @@ def test_drift_of_the_1d_workload_matches_the_oracle(qw):
     plan.step(y, 1000)
     dx = plan.observables(y, w["center"])["mean"][0] - plan.observables(x, w["center"])["mean"][0]
     assert abs(dx - got) < 1e-8
+
+
+def test_kspace_drift_two_stage_sum_matches_oracle(qw):
+    """128^3 (more than 1024 workgroups: partial sums reduced in two
+    stages), complex128, against the oracle."""
+    shape = (128, 128, 128)
+    m = 0.25
+    psi = rand_field(4, shape, 31)
+    plan = qw.Plan(3, list(shape), m, "c128")
+    got = plan.kspace_drift(to_dev(psi, plan))
+    v, sp, sm = oracle_drift(psi, walk.stencil_table(3, m))
+    assert np.allclose(got["velocity"], v, atol=1e-11, rtol=0)
+    assert abs(got["sector_norm2"][0] - sp) < 1e-11 and abs(got["sector_norm2"][1] - sm) < 1e-11
