@@ -190,3 +190,24 @@ def test_bcc_capture_into_a_graph(qw, dtype):
         e = plan.bcc_evolve_fft(f0, 3)  # eager work between replays
         torch.cuda.synchronize()
         del e
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("threads", [64, 128, 256, 512])
+def test_bcc_evolve_under_every_schedule(qw, dtype, threads):
+    """The cubic-supercell passes follow the plan's workgroup size (the
+    autotuner picks 64, 128 or 256 threads, a caller may set 512; a team
+    wider than that runs one pencil per workgroup); the slab schedule of the
+    primitive path does not apply to them. Same results as the oracle under
+    each."""
+    N = (16, 8, 64)
+    m, t = 0.13, 77
+    f = rand_sub(N, 61)
+    plan = qw.Plan(3, list(N), m, dtype)
+    plan.set_schedule(4, 8, threads, 1)
+    out = plan.bcc_evolve_fft(to_dev(f, plan), t)
+    ref = cubic.evolve_cubic(f, m, t)
+    assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
+    plan.autotune()
+    out2 = plan.bcc_evolve_fft(to_dev(f, plan), t)
+    assert ob.rel_l2(to_np(out2), ref) < tol_fft(dtype, t)

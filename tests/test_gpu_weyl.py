@@ -238,3 +238,21 @@ def test_weyl_capture_into_a_graph(qw, dtype):
         e = x0.clone()
         plan.step(e, 1)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("slab,threads", [(0, 64), (4, 128), (2, 256)])
+def test_weyl_evolve_under_every_schedule(qw, dtype, slab, threads):
+    """Slab schedules and workgroup sizes (the autotuner's candidates) give
+    the oracle's result on a Weyl plan, and so does the autotuned one."""
+    shape = (16, 8, 64)
+    psi0 = rand2(shape, 95)
+    plan = qw.Plan(3, list(shape), 0.0, dtype, weyl=True)
+    plan.set_schedule(slab, 8, threads, 1)
+    t = 333
+    ref = fourier.evolve_fourier(psi0, walk.weyl_table(3), t)
+    out = plan.evolve_fft(to_dev(psi0, plan), t)
+    assert ob.rel_l2(to_np(out), ref) < tol_fft(dtype, t)
+    plan.autotune()
+    out2 = plan.evolve_fft(to_dev(psi0, plan), t)
+    assert ob.rel_l2(to_np(out2), ref) < tol_fft(dtype, t)
