@@ -447,7 +447,8 @@ def cubic_line(qw, N, m, wall):
     sublattice arrays of the workload's size (2 N^3 sites, Cartesian torus of
     period 2N), one Fourier jump (three passes of the two arrays as eight
     planes, the a_k combine, both frequencies and the recombination fused into
-    the pass along n3) and the two-sublattice transform alone."""
+    the pass along n3), the two-sublattice transform alone, and the time per
+    position-space step."""
     import torch
     plan = qw.Plan(3, N, m, "c64")
     f = torch.randn((2, 4) + tuple(N), dtype=torch.complex64, device="cuda",
@@ -460,6 +461,8 @@ def cubic_line(qw, N, m, wall):
            "ms_per_evolution": ev,
            "site_evolutions_per_s": round(sites / (ev * 1e-3), 1),
            "transform_ms": wall(lambda: plan.bcc_transform(f, 1, out=g), reps=10),
+           # two steps per call: an even count ends in the caller's buffer
+           "ms_per_step": round(wall(lambda: plan.bcc_step(g, 2), reps=10) / 2, 4),
            "norm_after": float(torch.linalg.vector_norm(plan.bcc_evolve_fft(f, 1000, out=g)))}
     del f, g, plan
     return out

@@ -30,7 +30,7 @@
  * time; distinct plans are independent.
  *
  * Graph capture: qw_step, qw_evolve_fft, qw_evolve_fft_real, qw_transform,
- * qw_bcc_transform and qw_bcc_evolve_fft enqueue only kernels and
+ * qw_bcc_step, qw_bcc_transform and qw_bcc_evolve_fft enqueue only kernels and
  * device-to-device copies and never synchronise, so a caller may capture them
  * into a HIP graph and replay it. Their first call on a plan may allocate
  * (scratch, the omega tables); make one call outside the capture first.
@@ -182,6 +182,13 @@ qw_status qw_transform(qw_plan_t plan, const void* in, void* out, int direction,
  * dim != 3 gives QW_ERR_UNSUPPORTED. */
 qw_status qw_bcc_transform(qw_plan_t plan, const void* in, void* out, int direction,
                            void* stream);
+
+/* nsteps steps of the update rule of Sec. 2 on the cubic-supercell field f
+ * (layout above), in place: psi(x) <- sum_h U_h psi(x + h) with the
+ * transition matrices at their Cartesian displacements, the eight
+ * neighbours (+-1, +-1, +-1) lying on the other sublattice and the mass term
+ * on the site itself. nsteps >= 0. Uses two fields of plan scratch. */
+qw_status qw_bcc_step(qw_plan_t plan, void* f, int64_t nsteps, void* stream);
 
 /* f_t = U^t f0 on the cubic-supercell torus: eq:bcc-dft, per k the closed
  * form D^t of qw_evolve_fft at kappa applied to hat f1 and at kappa + (pi,0,0)

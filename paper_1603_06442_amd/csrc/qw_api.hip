@@ -1340,6 +1340,27 @@ qw_status qw_bcc_transform(qw_plan_t p, const void* in, void* out, int direction
                   (hipStream_t)stream);
 }
 
+qw_status qw_bcc_step(qw_plan_t p, void* f, int64_t nsteps, void* stream) {
+  qw_status r = check_bcc(p, f, f);
+  if (r != QW_OK) return r;
+  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = 2 * p->field_bytes;
+  r = ensure_scratch(p, bytes);
+  if (r != QW_OK) return r;
+  const StencilGeom g = stencil_geom(p);
+  void* a = f;
+  void* b = p->d_scratch;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    HIP_TRY(launch_step_bcc(p->dbl, g, b, a, p->d_coef, st));
+    void* tmp = a;
+    a = b;
+    b = tmp;
+  }
+  if (a != f) HIP_TRY(hipMemcpyAsync(f, a, bytes, hipMemcpyDeviceToDevice, st));
+  return QW_OK;
+}
+
 qw_status qw_bcc_evolve_fft(qw_plan_t p, const void* f0, void* f_t, double t, void* stream) {
   qw_status r = check_bcc(p, f0, f_t);
   if (r != QW_OK) return r;

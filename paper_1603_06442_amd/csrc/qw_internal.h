@@ -136,6 +136,10 @@ hipError_t launch_transpose(bool dbl, void* out, const void* in, int64_t planes,
 // the field precision (instance b uses coefs[b]). B <= 65535.
 hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
                        const void* coefs, hipStream_t st);
+// One step of the cubic-supercell field (two sublattice arrays of 4 * V
+// entries each; out and in distinct).
+hipError_t launch_step_bcc(bool dbl, const StencilGeom& g, void* out, const void* in,
+                           const void* coefs, hipStream_t st);
 // 1D lattices with 2 N b <= 160 KB and N <= 8192: nsteps steps of B fields in
 // place, each field held in LDS by one workgroup.
 bool step1d_resident_ok(bool dbl, const StencilGeom& g);

@@ -227,6 +227,75 @@ __global__ __launch_bounds__(256) void k_step_weyl(cx<T>* __restrict__ out_all,
   out[V + idx] = a1;
 }
 
+// Cubic-supercell BCC field (Sec. 4): two sublattice arrays of N1 x N2 x N3
+// sites, f_j(m) at the Cartesian site x = 2m + j t, t = (1,1,1). One step of
+// the update rule of Sec. 2, psi(x) <- sum_k U_k psi(x + c_k) + mass term,
+// with c_k the Cartesian displacement H o_k of the k-th neighbour offset o_k
+// (kOff3; H has the generators h1 = (1,1,1), h2 = (1,-1,-1), h3 = (-1,1,-1)
+// as columns). Every c_k has entries +-1, so x + c_k lies on the other
+// sublattice: at m + (c_k - t)/2 from sublattice 0 and at m + (c_k + t)/2 from
+// sublattice 1 (periodic in m). The mass term couples the upper and lower
+// components of the site itself. One thread per output site of both arrays.
+__device__ constexpr int kCart3[8][3] = {{1, 1, 1},    {-1, 1, 1},  {1, -1, 1},  {-1, -1, 1},
+                                         {-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1}};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_step_bcc(cx<T>* __restrict__ out,
+                                                 const cx<T>* __restrict__ in, StencilGeom g,
+                                                 const StencilCoef<T>* __restrict__ coefs) {
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t V = g.V;
+  if (gid >= 2 * V) return;
+  const int j = gid >= V ? 1 : 0;
+  const int64_t site = gid - j * V;
+  const cx<T>* __restrict__ src = in + (int64_t)(1 - j) * 4 * V;  // the other sublattice
+  const cx<T>* __restrict__ own = in + (int64_t)j * 4 * V;
+  cx<T>* __restrict__ dst = out + (int64_t)j * 4 * V;
+  const StencilCoef<T>& C = coefs[0];
+  const int64_t m0 = g.N[0] - 1, m1 = g.N[1] - 1, m2 = g.N[2] - 1;
+  const int64_t n2 = site & m2;
+  const int64_t n1 = (site >> g.lg[2]) & m1;
+  const int64_t n0 = site >> (g.lg[2] + g.lg[1]);
+  const int sh = j == 0 ? -1 : 1;  // (c - t)/2 or (c + t)/2, c = +-1
+  cx<T> a0 = mk((T)0, (T)0), a1 = a0, a2 = a0, a3 = a0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int64_t x = (n0 + (kCart3[k][0] + sh) / 2) & m0;
+    const int64_t y = (n1 + (kCart3[k][1] + sh) / 2) & m1;
+    const int64_t z = (n2 + (kCart3[k][2] + sh) / 2) & m2;
+    const int64_t nb = (((x << g.lg[1]) | y) << g.lg[2]) | z;
+    const cx<T> q0 = src[nb], q1 = src[V + nb], q2 = src[2 * V + nb], q3 = src[3 * V + nb];
+    a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+    a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+    a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
+    a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
+  }
+  const cx<T> mass = C.onsite[0][0];
+  a0 = fma_c(a0, mass, own[2 * V + site]);
+  a1 = fma_c(a1, mass, own[3 * V + site]);
+  a2 = fma_c(a2, mass, own[site]);
+  a3 = fma_c(a3, mass, own[V + site]);
+  dst[site] = a0;
+  dst[V + site] = a1;
+  dst[2 * V + site] = a2;
+  dst[3 * V + site] = a3;
+}
+
+hipError_t launch_step_bcc(bool dbl, const StencilGeom& g, void* out, const void* in,
+                           const void* coefs, hipStream_t st) {
+  if (g.dim != 3 || g.weyl) return hipErrorInvalidValue;
+  const int64_t nblk = (2 * g.V + 255) / 256;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (dbl)
+    hipLaunchKernelGGL(k_step_bcc<double>, dim3((unsigned)nblk), dim3(256), 0, st,
+                       (cx<double>*)out, (const cx<double>*)in, g,
+                       (const StencilCoef<double>*)coefs);
+  else
+    hipLaunchKernelGGL(k_step_bcc<float>, dim3((unsigned)nblk), dim3(256), 0, st,
+                       (cx<float>*)out, (const cx<float>*)in, g, (const StencilCoef<float>*)coefs);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // 3D step with an LDS ring of lattice planes. A workgroup owns a TN2 x TN3
 // tile of (n2, n3) and marches along n1 through a chunk of planes. Each input

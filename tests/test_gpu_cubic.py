@@ -211,3 +211,38 @@ def test_bcc_evolve_under_every_schedule(qw, dtype, threads):
     plan.autotune()
     out2 = plan.bcc_evolve_fft(to_dev(f, plan), t)
     assert ob.rel_l2(to_np(out2), ref) < tol_fft(dtype, t)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("N", [(2, 2, 2), (4, 8, 16), (8, 4, 32)])
+@pytest.mark.parametrize("m", [0.0, 0.3, 1.0])
+def test_bcc_step_matches_oracle(qw, N, m, dtype):
+    """Position-space steps on the two sublattice arrays against the oracle's
+    Cartesian stepping of the embedded field (odd and even step counts)."""
+    f = rand_sub(N, 71 + sum(N))
+    plan = qw.Plan(3, list(N), m, dtype)
+    x = to_dev(f, plan)
+    ct = cubic.cartesian_table(m)
+    fc = cubic.embed(f)
+    done = 0
+    for k in (1, 4):
+        plan.bcc_step(x, k)
+        for _ in range(k):
+            fc = cubic.step_cartesian(fc, ct)
+        done += k
+        tol = max(2e-5, 4 * done * 2.0 ** -24) if dtype == "c64" else 1e-12
+        assert ob.rel_l2(to_np(x), cubic.split(fc)) < tol
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_bcc_jump_equals_steps_on_the_gpu(qw, dtype):
+    """Sec. 4's two routes on the cubic supercell agree on the GPU: t
+    position-space steps and one Fourier jump to t."""
+    N = (16, 8, 32)
+    f = rand_sub(N, 83)
+    plan = qw.Plan(3, list(N), 0.17, dtype)
+    x = to_dev(f, plan)
+    jump = plan.bcc_evolve_fft(x, 9)
+    plan.bcc_step(x, 9)
+    tol = 4e-5 if dtype == "c64" else 1e-12
+    assert ob.rel_l2(to_np(x), to_np(jump)) < tol
