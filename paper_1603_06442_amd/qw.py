@@ -69,7 +69,7 @@ class QwServerInfo(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libqw.so is not built (%s): run __graft_entry__.build() or "
+        raise ImportError("libqw.so is not built (%s): run "
                           "python -m paper_1603_06442_amd.build" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, dbl, cint = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
