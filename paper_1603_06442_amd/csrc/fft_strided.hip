@@ -17,9 +17,11 @@ namespace qw {
 
 // Outer index o of a launch covers `ocount` consecutive planes o0.. of each
 // of several components, components `ostride` elements apart (a slab of the
-// lattice); a whole-field launch has ocount = O, o0 = 0.
+// lattice); a whole-field launch has ocount = O, o0 = 0. nt: the results are
+// written with non-temporal stores.
 struct OuterMap {
   int64_t ocount, o0, ostride;
+  int nt;
 };
 
 template <typename T, int L, int E, int SIGN>
@@ -44,8 +46,13 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = in[base + (int64_t)(t + TT * e) * I];
   fft_team<T, L, E, SIGN>(v, lds + p, P, t, tw);
+  if (om.nt) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) out[base + (int64_t)(t + TT * e) * I] = v[e];
+    for (int e = 0; e < E; ++e) store_nt(&out[base + (int64_t)(t + TT * e) * I], v[e]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) out[base + (int64_t)(t + TT * e) * I] = v[e];
+  }
 }
 
 // Columns per workgroup of a strided pass: 256 bytes of each row (32
@@ -130,8 +137,8 @@ static hipError_t dispatch_strided(int64_t L, cx<T>* out, const cx<T>* in, int64
 
 hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, const void* in,
                                    int64_t ncomp, int64_t ocount, int64_t o0, int64_t ostride,
-                                   int64_t I, const void* tw, hipStream_t st) {
-  const OuterMap om{ocount, o0, ostride};
+                                   int64_t I, const void* tw, hipStream_t st, bool nt) {
+  const OuterMap om{ocount, o0, ostride, nt ? 1 : 0};
   const int64_t O = ncomp * ocount;
   if (dbl) {
     auto o = (cx<double>*)out;
@@ -148,13 +155,13 @@ hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, con
 }
 
 hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
-                              int64_t I, const void* tw, hipStream_t st) {
+                              int64_t I, const void* tw, hipStream_t st, bool nt) {
   if (L == 1) {
     if (out != in)
       return hipMemcpyAsync(out, in, (dbl ? 16 : 8) * O * I, hipMemcpyDeviceToDevice, st);
     return hipSuccess;
   }
-  return launch_fft_strided_slab(dbl, sign, L, out, in, 1, O, 0, 0, I, tw, st);
+  return launch_fft_strided_slab(dbl, sign, L, out, in, 1, O, 0, 0, I, tw, st, nt);
 }
 
 // Last inverse pass of an evolution with the Sec. 5.2 reductions fused: the

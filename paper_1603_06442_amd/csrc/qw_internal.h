@@ -117,12 +117,14 @@ struct StencilGeom {
 // ---------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).
 // ---------------------------------------------------------------------------
+// nt: write the results with non-temporal stores (for fields larger than
+// the last-level cache whose next reader gains nothing from cached lines).
 hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
-                              int64_t I, const void* tw, hipStream_t st);
+                              int64_t I, const void* tw, hipStream_t st, bool nt = false);
 // Planes o0 .. o0+ocount-1 of each of ncomp components (ostride elements apart).
 hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, const void* in,
                                    int64_t ncomp, int64_t ocount, int64_t o0, int64_t ostride,
-                                   int64_t I, const void* tw, hipStream_t st);
+                                   int64_t I, const void* tw, hipStream_t st, bool nt = false);
 // E: elements per thread of the contiguous pass (4 or 8; 0 = default 8).
 hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const void* in,
                              const PassGeom& g, const void* tw, hipStream_t st, int E = 0);
@@ -324,6 +326,16 @@ int64_t state_blocks(const StateGeom& g, int B);
 int64_t state_scratch_doubles(const StateGeom& g, int B);
 hipError_t launch_state_prepare(bool dbl, const StateGeom& g, int B, const StateInst* inst,
                                 double* scratch, double* norms, void* out, hipStream_t st);
+
+// Non-temporal store of one complex value (not kept in the caches).
+template <typename T>
+__device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
+}
 
 // Kernel-side helpers shared by the apply and the state preparation:
 // u_k and n~_k of the Weyl symbol at lattice frequency indices (j1, j2, j3),
