@@ -536,13 +536,11 @@ qw_status strided_passes(qw_plan_t p, int sign, void* out, const void* in, int B
   const int s = p->s;
   if (p->dim == 3) {
     const int64_t N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
-    // The n2 passes write with non-temporal stores when the field read and
-    // written exceeds the 256 MB last-level cache (256^3 complex64: 0.199 ->
-    // 0.185 ms and 0.197 -> 0.188 ms). The n1 forward pass keeps plain
-    // stores: the n2 pass after it reads the lines still cached (the same
-    // stores there cost 0.225 -> 0.243 ms); at 128^3, where the field fits,
-    // plain stores are faster for every pass.
-    const bool nt = 2 * p->field_bytes * (size_t)B > (size_t(256) << 20);
+    // The n2 passes write with non-temporal stores when the field reaches
+    // kNtBytes (256^3 complex64: 0.199 -> 0.191 ms and 0.197 -> 0.184 ms).
+    // The n1 forward pass keeps plain stores: the n2 pass after it reads the
+    // lines still cached (the same stores there cost 0.225 -> 0.243 ms).
+    const bool nt = p->field_bytes * (size_t)B >= kNtBytes;
     if (sign > 0) {
       HIP_TRY(launch_fft_strided(p->dbl, 1, N1, out, in, (int64_t)s * B, N2 * N3, p->d_tw, st));
       mark();
@@ -989,6 +987,7 @@ static StencilGeom stencil_geom(qw_plan_t p) {
   g.V = p->V;
   g.sparse3 = p->sparse3 ? 1 : 0;
   g.weyl = p->weyl ? 1 : 0;
+  g.nt = 0;
   return g;
 }
 

@@ -173,10 +173,17 @@ __global__ __launch_bounds__(256) void k_step_nd(cx<T>* __restrict__ out_all,
   a1 = fma_c(a1, mass, in[3 * V + idx]);
   a2 = fma_c(a2, mass, in[idx]);
   a3 = fma_c(a3, mass, in[V + idx]);
-  out[idx] = a0;
-  out[V + idx] = a1;
-  out[2 * V + idx] = a2;
-  out[3 * V + idx] = a3;
+  if (g.nt) {
+    store_nt(&out[idx], a0);
+    store_nt(&out[V + idx], a1);
+    store_nt(&out[2 * V + idx], a2);
+    store_nt(&out[3 * V + idx], a3);
+  } else {
+    out[idx] = a0;
+    out[V + idx] = a1;
+    out[2 * V + idx] = a2;
+    out[3 * V + idx] = a3;
+  }
 }
 
 
@@ -223,8 +230,13 @@ __global__ __launch_bounds__(256) void k_step_weyl(cx<T>* __restrict__ out_all,
     a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
     a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
   }
-  out[idx] = a0;
-  out[V + idx] = a1;
+  if (g.nt) {
+    store_nt(&out[idx], a0);
+    store_nt(&out[V + idx], a1);
+  } else {
+    out[idx] = a0;
+    out[V + idx] = a1;
+  }
 }
 
 // Cubic-supercell BCC field (Sec. 4): two sublattice arrays of N1 x N2 x N3
@@ -275,24 +287,33 @@ __global__ __launch_bounds__(256) void k_step_bcc(cx<T>* __restrict__ out,
   a1 = fma_c(a1, mass, own[3 * V + site]);
   a2 = fma_c(a2, mass, own[site]);
   a3 = fma_c(a3, mass, own[V + site]);
-  dst[site] = a0;
-  dst[V + site] = a1;
-  dst[2 * V + site] = a2;
-  dst[3 * V + site] = a3;
+  if (g.nt) {
+    store_nt(&dst[site], a0);
+    store_nt(&dst[V + site], a1);
+    store_nt(&dst[2 * V + site], a2);
+    store_nt(&dst[3 * V + site], a3);
+  } else {
+    dst[site] = a0;
+    dst[V + site] = a1;
+    dst[2 * V + site] = a2;
+    dst[3 * V + site] = a3;
+  }
 }
 
 hipError_t launch_step_bcc(bool dbl, const StencilGeom& g, void* out, const void* in,
                            const void* coefs, hipStream_t st) {
   if (g.dim != 3 || g.weyl) return hipErrorInvalidValue;
   const int64_t nblk = (2 * g.V + 255) / 256;
+  StencilGeom gn = g;
+  gn.nt = 2 * 4 * (size_t)g.V * (dbl ? 16 : 8) >= kNtBytes;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   if (dbl)
     hipLaunchKernelGGL(k_step_bcc<double>, dim3((unsigned)nblk), dim3(256), 0, st,
-                       (cx<double>*)out, (const cx<double>*)in, g,
+                       (cx<double>*)out, (const cx<double>*)in, gn,
                        (const StencilCoef<double>*)coefs);
   else
     hipLaunchKernelGGL(k_step_bcc<float>, dim3((unsigned)nblk), dim3(256), 0, st,
-                       (cx<float>*)out, (const cx<float>*)in, g, (const StencilCoef<float>*)coefs);
+                       (cx<float>*)out, (const cx<float>*)in, gn, (const StencilCoef<float>*)coefs);
   return hipGetLastError();
 }
 
@@ -377,11 +398,9 @@ __device__ __forceinline__ void store_plane(const PlaneRegs<T>& R, cx<T>* ring, 
   }
 }
 
-// NT: outputs are written with non-temporal stores (used when the input and
-// output fields together exceed the 256 MB last-level cache, where keeping
-// them cached gains nothing: 256^3 complex64 0.230 -> 0.222-0.225 ms per
-// step; for fields that fit, the next step's read would have hit the cache:
-// 128^3 0.030 -> 0.035 ms, so there they are plain stores).
+// NT: outputs are written with non-temporal stores (fields of at least
+// kNtBytes: 256^3 complex64 0.230 -> 0.214 ms per step; at 128^3 they would
+// cost 0.030 -> 0.035 ms, the next step's read hitting the cache).
 template <typename T, int PF, bool SPARSE, bool NT>
 __global__ __launch_bounds__(kStepThreads) void k_step3d_ring(cx<T>* __restrict__ out_all,
                                                              const cx<T>* __restrict__ in_all,
@@ -523,7 +542,7 @@ hipError_t launch_step3d_ring(const StencilGeom& g, int B, void* out, const void
   const int64_t nchunks = g.N[0] / chunk;
   const int64_t nblk = tiles2 * tiles3 * nchunks;
   const size_t lds = 3 * 4 * kPlaneSites * sizeof(cx<float>);
-  const bool nt = 2 * (size_t)B * 4 * (size_t)g.V * sizeof(cx<float>) > (size_t(256) << 20);
+  const bool nt = (size_t)B * 4 * (size_t)g.V * sizeof(cx<float>) >= kNtBytes;
   auto kern = g.sparse3 ? (nt ? k_step3d_ring<float, 2, true, true> : k_step3d_ring<float, 2, true, false>)
                         : (nt ? k_step3d_ring<float, 2, false, true> : k_step3d_ring<float, 2, false, false>);
   if (lds > 65536) {
@@ -541,20 +560,22 @@ hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const v
                        const void* coefs, hipStream_t st) {
   if (B < 1 || B > 65535) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((g.V + 255) / 256), (unsigned)B);
+  StencilGeom gn = g;
+  gn.nt = (size_t)B * (g.weyl ? 2 : (g.dim == 1 ? 2 : 4)) * (size_t)g.V * (dbl ? 16 : 8) >= kNtBytes;
   if (g.weyl) {
     if (g.dim < 2) return hipErrorInvalidValue;
     if (dbl) {
       auto C = (const StencilCoef<double>*)coefs;
       auto o = (cx<double>*)out;
       auto i = (const cx<double>*)in;
-      if (g.dim == 2) hipLaunchKernelGGL((k_step_weyl<double, 2>), grid, dim3(256), 0, st, o, i, g, C);
-      else hipLaunchKernelGGL((k_step_weyl<double, 3>), grid, dim3(256), 0, st, o, i, g, C);
+      if (g.dim == 2) hipLaunchKernelGGL((k_step_weyl<double, 2>), grid, dim3(256), 0, st, o, i, gn, C);
+      else hipLaunchKernelGGL((k_step_weyl<double, 3>), grid, dim3(256), 0, st, o, i, gn, C);
     } else {
       auto C = (const StencilCoef<float>*)coefs;
       auto o = (cx<float>*)out;
       auto i = (const cx<float>*)in;
-      if (g.dim == 2) hipLaunchKernelGGL((k_step_weyl<float, 2>), grid, dim3(256), 0, st, o, i, g, C);
-      else hipLaunchKernelGGL((k_step_weyl<float, 3>), grid, dim3(256), 0, st, o, i, g, C);
+      if (g.dim == 2) hipLaunchKernelGGL((k_step_weyl<float, 2>), grid, dim3(256), 0, st, o, i, gn, C);
+      else hipLaunchKernelGGL((k_step_weyl<float, 3>), grid, dim3(256), 0, st, o, i, gn, C);
     }
     return hipGetLastError();
   }
@@ -563,16 +584,16 @@ hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const v
     auto C = (const StencilCoef<double>*)coefs;
     auto o = (cx<double>*)out;
     auto i = (const cx<double>*)in;
-    if (g.dim == 1) hipLaunchKernelGGL(k_step1d<double>, grid, dim3(256), 0, st, o, i, g, C);
-    else if (g.dim == 2) hipLaunchKernelGGL((k_step_nd<double, 2>), grid, dim3(256), 0, st, o, i, g, C);
-    else hipLaunchKernelGGL((k_step_nd<double, 3>), grid, dim3(256), 0, st, o, i, g, C);
+    if (g.dim == 1) hipLaunchKernelGGL(k_step1d<double>, grid, dim3(256), 0, st, o, i, gn, C);
+    else if (g.dim == 2) hipLaunchKernelGGL((k_step_nd<double, 2>), grid, dim3(256), 0, st, o, i, gn, C);
+    else hipLaunchKernelGGL((k_step_nd<double, 3>), grid, dim3(256), 0, st, o, i, gn, C);
   } else {
     auto C = (const StencilCoef<float>*)coefs;
     auto o = (cx<float>*)out;
     auto i = (const cx<float>*)in;
-    if (g.dim == 1) hipLaunchKernelGGL(k_step1d<float>, grid, dim3(256), 0, st, o, i, g, C);
-    else if (g.dim == 2) hipLaunchKernelGGL((k_step_nd<float, 2>), grid, dim3(256), 0, st, o, i, g, C);
-    else hipLaunchKernelGGL((k_step_nd<float, 3>), grid, dim3(256), 0, st, o, i, g, C);
+    if (g.dim == 1) hipLaunchKernelGGL(k_step1d<float>, grid, dim3(256), 0, st, o, i, gn, C);
+    else if (g.dim == 2) hipLaunchKernelGGL((k_step_nd<float, 2>), grid, dim3(256), 0, st, o, i, gn, C);
+    else hipLaunchKernelGGL((k_step_nd<float, 3>), grid, dim3(256), 0, st, o, i, gn, C);
   }
   return hipGetLastError();
 }
