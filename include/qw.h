@@ -101,7 +101,8 @@ qw_status qw_plan(qw_plan_t* out, int dim, const int64_t* N, double m, qw_dtype 
  * cos(omega t) I - i sin(omega t)/sin(omega) sigma.n~, cos(omega) = u_k; at
  * omega = pi the average cos(pi t) I, as for the Dirac walk),
  * qw_evolve_fft_timed, qw_evolve_fft_observables, qw_transform,
- * qw_observables, qw_marginals and the schedule calls take such a plan; the
+ * qw_observables, qw_marginals, qw_kspace_drift and the schedule calls take
+ * such a plan; the
  * batched calls, the particle-state calls, qw_newton_wigner and the
  * cubic-supercell calls return QW_ERR_UNSUPPORTED. dim = 1 gives the Dirac
  * plan at m = 0, which is the 1D Weyl walk diag(e^{-ik}, e^{ik}). */
