@@ -40,7 +40,7 @@ def rand_sub(N, seed):
     return f / np.linalg.norm(f)
 
 
-SHAPES = [(2, 2, 2), (4, 8, 16), (16, 16, 16), (8, 4, 32), (2, 16, 4), (4, 4, 128)]
+SHAPES = [(2, 2, 2), (4, 8, 16), (16, 16, 16), (8, 4, 32), (2, 16, 4), (4, 4, 128), (2, 2, 512)]
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
@@ -61,7 +61,8 @@ def test_bcc_transform_matches_oracle(qw, N, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("N", [(2, 2, 2), (4, 4, 8), (8, 8, 8), (16, 8, 32), (4, 2, 64)])
+@pytest.mark.parametrize("N", [(2, 2, 2), (4, 4, 8), (8, 8, 8), (16, 8, 32), (4, 2, 64),
+                               (2, 2, 512)])
 @pytest.mark.parametrize("t", [0, 1, 5, -3, 1000, 100000])
 def test_bcc_evolve_matches_oracle(qw, N, t, dtype):
     m = 0.21

@@ -46,7 +46,7 @@ def rand2(shape, seed):
 
 
 SHAPES = [(2, (8, 16)), (2, (32, 32)), (2, (2, 2)), (3, (4, 8, 16)), (3, (16, 16, 16)),
-          (3, (2, 2, 2)), (3, (8, 4, 64))]
+          (3, (2, 2, 2)), (3, (8, 4, 64)), (2, (2, 1024)), (3, (2, 2, 512))]
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
