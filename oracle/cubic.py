@@ -172,3 +172,14 @@ def evolve_two_sublattice(f, m, t):
     h = bcc_dft(f)
     h = np.stack([fourier.apply_symbol(D0, h[0]), fourier.apply_symbol(D1, h[1])])
     return bcc_idft(h)
+
+
+def observables_cubic(f, center):
+    """Norm and Cartesian position moments of a cubic-supercell field about
+    the Cartesian point c (Sec. 5.2 position expectation, minimum image on the
+    torus of period 2 N_i): the plain reductions of the Cartesian embedding,
+    whose grid indices are the Cartesian coordinates. Returns norm2, mean[3]
+    (Cartesian) and second[6] (pairs 00, 11, 22, 01, 02, 12 about c)."""
+    from . import observables as ob
+    o = ob.observables(embed(f), center)
+    return {"norm2": o["norm2"], "mean": o["mean"], "second": o["second"]}

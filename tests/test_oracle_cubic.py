@@ -10,7 +10,7 @@ where neither torus wraps. No GPU.
 import numpy as np
 import pytest
 
-from oracle import cubic, stepper, walk
+from oracle import cubic, observables as ob, stepper, walk
 
 
 def _rand(shape, seed):
@@ -128,3 +128,51 @@ def test_cubic_and_primitive_tori_agree_inside_the_light_cone(m):
         mapped[(slice(None),) + tuple(x % 16)] = v
     assert np.abs(mapped - fc).max() < 1e-14
     assert abs(np.linalg.norm(fc) - 1.0) < 1e-13
+
+
+def test_cubic_observables_by_brute_force():
+    """Norm and moments summed site by site over both sublattices."""
+    N = (2, 4, 4)
+    f = _rand((2, 4) + N, 91)
+    c = np.array([1.3, 6.0, 2.5])
+    got = cubic.observables_cubic(f, c)
+    L = 2 * np.array(N)
+    tot, s1, s2 = 0.0, np.zeros(3), np.zeros((3, 3))
+    for j in (0, 1):
+        for m in np.ndindex(*N):
+            x = 2 * np.array(m) + j
+            w = np.mod(x - c + L / 2, L) - L / 2
+            p = float(np.sum(np.abs(f[(j, slice(None)) + m]) ** 2))
+            tot += p
+            s1 += w * p
+            s2 += np.outer(w, w) * p
+    assert abs(got["norm2"] - tot) < 1e-13
+    assert np.allclose(got["mean"], c + s1 / tot, atol=1e-12)
+    pairs = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+    assert np.allclose(got["second"], [s2[i, j] / tot for i, j in pairs], atol=1e-12)
+
+
+def test_cubic_observables_equal_the_primitive_torus_ones_inside_the_light_cone():
+    """A localised state stepped on both tori: the Cartesian mean and the
+    Cartesian second moments (H S H^T of the primitive ones) agree."""
+    t, Np, m = 3, 16, 0.3
+    zeta = np.array([0.6, 0.2j, -0.5, 0.3 + 0.4j])
+    zeta = zeta / np.linalg.norm(zeta)
+    prim = np.zeros((4, Np, Np, Np), dtype=np.complex128)
+    prim[:, 8, 8, 8] = zeta
+    prim = stepper.evolve_steps(prim, walk.stencil_table(3, m), t)
+    op = ob.observables(prim, [8, 8, 8])
+    fc = np.zeros((4, 16, 16, 16), dtype=np.complex128)
+    fc[:, 0, 0, 0] = zeta
+    ct = cubic.cartesian_table(m)
+    for _ in range(t):
+        fc = cubic.step_cartesian(fc, ct)
+    oc = cubic.observables_cubic(cubic.split(fc), [0.0, 0.0, 0.0])
+    H = walk.generators(3)
+    assert np.allclose(oc["mean"], H @ (op["mean"] - 8.0), atol=1e-12)
+    pairs = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+    S = np.zeros((3, 3))
+    for k, (i, j) in enumerate(pairs):
+        S[i, j] = S[j, i] = op["second"][k]
+    Sc = H @ S @ H.T
+    assert np.allclose(oc["second"], [Sc[i, j] for i, j in pairs], atol=1e-12)
