@@ -191,6 +191,16 @@ qw_status qw_bcc_transform(qw_plan_t plan, const void* in, void* out, int direct
  * on the site itself. nsteps >= 0. Uses two fields of plan scratch. */
 qw_status qw_bcc_step(qw_plan_t plan, void* f, int64_t nsteps, void* stream);
 
+/* Norm and position moments of the cubic-supercell field f (Sec. 5.2, the
+ * position expectation; FP64 accumulation): Cartesian minimum-image
+ * displacements w of every site x = 2n + j (1,1,1) about the Cartesian point
+ * origin (3 HOST doubles) on the torus of period 2 N_i, so that mean = origin
+ * + sum w |f|^2 / norm2 and second = sum w_i w_j |f|^2 / norm2 (pairs 00, 11,
+ * 22, 01, 02, 12), all Cartesian (mean_cart = mean; overlap fields 0). out:
+ * HOST. Waits for the result. */
+qw_status qw_bcc_observables(qw_plan_t plan, const void* f, const double* origin, qw_obs* out,
+                             void* stream);
+
 /* f_t = U^t f0 on the cubic-supercell torus: eq:bcc-dft, per k the closed
  * form D^t of qw_evolve_fft at kappa applied to hat f1 and at kappa + (pi,0,0)
  * applied to hat f0, eq:bcc-idft; one read and one write of the field per

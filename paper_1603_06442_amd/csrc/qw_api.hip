@@ -1367,6 +1367,33 @@ qw_status qw_bcc_step(qw_plan_t p, void* f, int64_t nsteps, void* stream) {
   return QW_OK;
 }
 
+qw_status qw_bcc_observables(qw_plan_t p, const void* f, const double* origin, qw_obs* out,
+                             void* stream) {
+  qw_status r = check_bcc(p, f, f);
+  if (r != QW_OK) return r;
+  if (!origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  ObsGeom g = obs_geom(p);
+  for (int i = 0; i < 3; ++i) {
+    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+    g.c[i] = origin[i];
+  }
+  HIP_TRY(launch_bcc_observables(p->dbl, g, f, p->d_partials, p->d_result, st));
+  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double* R = p->h_result;
+  memset(out, 0, sizeof *out);
+  out->norm2 = R[0];
+  const double inv = R[0] > 0.0 ? 1.0 / R[0] : 0.0;
+  for (int i = 0; i < 3; ++i) {
+    out->mean[i] = origin[i] + R[1 + i] * inv;
+    out->mean_cart[i] = out->mean[i];  // the coordinates are Cartesian
+  }
+  for (int k = 0; k < 6; ++k) out->second[k] = R[4 + k] * inv;
+  return QW_OK;
+}
+
 qw_status qw_bcc_evolve_fft(qw_plan_t p, const void* f0, void* f_t, double t, void* stream) {
   qw_status r = check_bcc(p, f0, f_t);
   if (r != QW_OK) return r;

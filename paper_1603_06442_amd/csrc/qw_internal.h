@@ -178,6 +178,10 @@ int64_t observables_blocks(const ObsGeom& g, int B);
 // kObsFields doubles). L is a power of two.
 hipError_t launch_kdrift(bool dbl, const PassGeom& g, int64_t L, const void* spec,
                          double* partials, double* result, hipStream_t st);
+// Norm and Cartesian moments of a cubic-supercell field about g.c (Cartesian,
+// torus of period 2 N_i); result in the field layout of the observables.
+hipError_t launch_bcc_observables(bool dbl, const ObsGeom& g, const void* f, double* partials,
+                                  double* result, hipStream_t st);
 hipError_t launch_observables(bool dbl, const ObsGeom& g, int B, const void* psi, const void* ref,
                               const double* origins, double* partials, double* result,
                               hipStream_t st);

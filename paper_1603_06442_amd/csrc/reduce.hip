@@ -276,6 +276,66 @@ hipError_t launch_kdrift(bool dbl, const PassGeom& g, int64_t L, const void* spe
   return launch_reduce_partials(1, nb, partials, partials + nb * kObsFields, result, st);
 }
 
+// Cubic-supercell field (two sublattice arrays of 4 V entries, the site of
+// index m in array j at the Cartesian x = 2m + j (1,1,1)): norm and Cartesian
+// position moments about the Cartesian point g.c on the torus of period
+// 2 N_i (Sec. 5.2, minimum image), in the field layout of k_observables.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bcc_obs(const cx<T>* __restrict__ f, ObsGeom g,
+                                                double* __restrict__ partials) {
+  double acc[kObsFields];
+#pragma unroll
+  for (int k = 0; k < kObsFields; ++k) acc[k] = 0.0;
+  AxisImage ax[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) ax[i] = axis_image(g.c[i], 2 * g.N[i]);
+  const int64_t V = g.V;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < 2 * V; gid += stride) {
+    const int64_t j = gid >= V ? 1 : 0;
+    const int64_t site = gid - j * V;
+    const cx<T>* __restrict__ p = f + j * 4 * V + site;
+    double w = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const cx<T> a = p[c * V];
+      w += (double)a.x * a.x + (double)a.y * a.y;
+    }
+    const int64_t m2 = site & (g.N[2] - 1);
+    const int64_t m1 = (site >> g.lg[2]) & (g.N[1] - 1);
+    const int64_t m0 = site >> (g.lg[2] + g.lg[1]);
+    const double w0 = min_image(2 * m0 + j, ax[0]);
+    const double w1 = min_image(2 * m1 + j, ax[1]);
+    const double w2 = min_image(2 * m2 + j, ax[2]);
+    acc[0] += w;
+    acc[1] += w0 * w;
+    acc[2] += w1 * w;
+    acc[3] += w2 * w;
+    acc[4] += w0 * w0 * w;
+    acc[5] += w1 * w1 * w;
+    acc[6] += w2 * w2 * w;
+    acc[7] += w0 * w1 * w;
+    acc[8] += w0 * w2 * w;
+    acc[9] += w1 * w2 * w;
+  }
+  block_reduce_store<kObsFields>(acc, partials + (int64_t)blockIdx.x * kObsFields);
+}
+
+hipError_t launch_bcc_observables(bool dbl, const ObsGeom& g, const void* f, double* partials,
+                                  double* result, hipStream_t st) {
+  int64_t nb = (2 * g.V + 1023) / 1024;
+  if (nb > 2048) nb = 2048;  // partials and the middle stage fit 13 * 4096 doubles
+  if (dbl)
+    hipLaunchKernelGGL(k_bcc_obs<double>, dim3((unsigned)nb), dim3(256), 0, st,
+                       (const cx<double>*)f, g, partials);
+  else
+    hipLaunchKernelGGL(k_bcc_obs<float>, dim3((unsigned)nb), dim3(256), 0, st,
+                       (const cx<float>*)f, g, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_partials(1, nb, partials, partials + nb * kObsFields, result, st);
+}
+
 // The number of workgroups (and so the summation order) depends on the shape
 // only, never on the batch: an instance reduces identically alone or batched.
 int64_t observables_blocks(const ObsGeom& g, int B) {

@@ -22,7 +22,7 @@ QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables", "qw_newton_wigner",
-           "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft", "qw_bcc_step",
+           "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft", "qw_bcc_step", "qw_bcc_observables",
            "qw_kspace_drift",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
            "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
@@ -88,6 +88,7 @@ def _load():
         "qw_bcc_transform": [vp, vp, vp, cint, vp],
         "qw_bcc_evolve_fft": [vp, vp, vp, dbl, vp],
         "qw_bcc_step": [vp, vp, i64, vp],
+        "qw_bcc_observables": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(QwObs), vp],
         "qw_kspace_drift": [vp, vp, ctypes.POINTER(QwDrift), vp],
         "qw_observables": [vp, vp, ctypes.POINTER(dbl), vp, ctypes.POINTER(QwObs), vp],
         "qw_newton_wigner": [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(QwObs), ctypes.POINTER(dbl),
@@ -271,6 +272,14 @@ class Plan:
         """qw_bcc_step: nsteps position-space steps on the cubic supercell, in place."""
         _check(LIB.qw_bcc_step(self._h, self._field(f, 2, "f"), int(nsteps), _stream(stream)))
         return f
+
+    def bcc_observables(self, f, origin, stream=None):
+        """qw_bcc_observables: norm, Cartesian mean and second moments of a
+        cubic-supercell field about a Cartesian origin."""
+        o = QwObs()
+        _check(LIB.qw_bcc_observables(self._h, self._field(f, 2, "f"), _darr(origin, 3),
+                                      ctypes.byref(o), _stream(stream)))
+        return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second)}
 
     def bcc_evolve_fft(self, f0, t, out=None, stream=None):
         """qw_bcc_evolve_fft: U^t on the cubic-supercell torus (real t)."""

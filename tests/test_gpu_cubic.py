@@ -247,3 +247,21 @@ def test_bcc_jump_equals_steps_on_the_gpu(qw, dtype):
     plan.bcc_step(x, 9)
     tol = 4e-5 if dtype == "c64" else 1e-12
     assert ob.rel_l2(to_np(x), to_np(jump)) < tol
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("N", [(2, 2, 2), (4, 8, 16), (8, 4, 32), (2, 2, 512)])
+@pytest.mark.parametrize("origin", [(0.0, 0.0, 0.0), (3.0, 5.5, 1.25)])
+def test_bcc_observables_match_oracle(qw, N, origin, dtype):
+    """Norm and Cartesian moments about a Cartesian origin (integer and not)
+    on the period-2N torus, against the oracle's reductions of the Cartesian
+    embedding."""
+    f = rand_sub(N, 101 + sum(N))
+    plan = qw.Plan(3, list(N), 0.2, dtype)
+    got = plan.bcc_observables(to_dev(f, plan), origin)
+    if dtype == "c64":
+        f = f.astype(np.complex64).astype(np.complex128)
+    want = cubic.observables_cubic(f, origin)
+    assert abs(got["norm2"] - want["norm2"]) < 1e-12
+    assert np.allclose(got["mean"], want["mean"], atol=1e-10)
+    assert np.allclose(got["second"], want["second"], atol=1e-9)

@@ -78,6 +78,7 @@ def test_calls_reject_null_plan():
         qw.QW_ERR_INVALID
     assert qw.LIB.qw_kspace_drift(None, None, None, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_bcc_step(None, None, 1, None) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_bcc_observables(None, None, None, None, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_bcc_transform(None, None, None, 1, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_bcc_evolve_fft(None, None, None, 1.0, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_destroy(None) == qw.QW_OK
