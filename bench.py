@@ -447,8 +447,8 @@ def cubic_line(qw, N, m, wall):
     sublattice arrays of the workload's size (2 N^3 sites, Cartesian torus of
     period 2N), one Fourier jump (three passes of the two arrays as eight
     planes, the a_k combine, both frequencies and the recombination fused into
-    the pass along n3), the two-sublattice transform alone, and the time per
-    position-space step."""
+    the pass along n3), the two-sublattice transform alone, the time per
+    position-space step and the Cartesian position moments."""
     import torch
     plan = qw.Plan(3, N, m, "c64")
     f = torch.randn((2, 4) + tuple(N), dtype=torch.complex64, device="cuda",
@@ -463,6 +463,7 @@ def cubic_line(qw, N, m, wall):
            "transform_ms": wall(lambda: plan.bcc_transform(f, 1, out=g), reps=10),
            # two steps per call: an even count ends in the caller's buffer
            "ms_per_step": round(wall(lambda: plan.bcc_step(g, 2), reps=10) / 2, 4),
+           "observables_ms": wall(lambda: plan.bcc_observables(f, [256.0, 256.0, 256.0]), reps=10),
            "norm_after": float(torch.linalg.vector_norm(plan.bcc_evolve_fft(f, 1000, out=g)))}
     del f, g, plan
     return out
