@@ -247,63 +247,131 @@ __global__ __launch_bounds__(256) void k_step_weyl(cx<T>* __restrict__ out_all,
 // as columns). Every c_k has entries +-1, so x + c_k lies on the other
 // sublattice: at m + (c_k - t)/2 from sublattice 0 and at m + (c_k + t)/2 from
 // sublattice 1 (periodic in m). The mass term couples the upper and lower
-// components of the site itself. One thread per output site of both arrays.
+// components of the site itself.
+//
+// The eight sites read for output m therefore form a 2 x 2 x 2 block of the
+// other sublattice, {m + s a : a in {0,1}^3} with s = -1 for sublattice 0 and
+// s = +1 for sublattice 1. A thread marches along axis 0 through a chunk of
+// kBccChunk outputs at fixed (m1, m2): the quad of sites in plane m0 + s (or
+// m0) read for one output is the quad in plane m0 (or m0 + s) of the next, so
+// it is kept in registers and each output loads one new quad (16 values) and
+// its own four components, instead of eight sites.
 __device__ constexpr int kCart3[8][3] = {{1, 1, 1},    {-1, 1, 1},  {1, -1, 1},  {-1, -1, 1},
                                          {-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {1, 1, -1}};
+constexpr int kLgBccChunk = 4;  // kBccChunk = 16 planes per thread
+constexpr int kLgBccStrip = 5;  // rows of axis 1 a workgroup range covers
 
+// The four sites (m0, m1 + s a1, m2 + s a2), a1, a2 in {0,1}, of the plane at
+// offset plane_off, all four components: P[2 a1 + a2][c].
+template <typename T, int SH>
+__device__ __forceinline__ void load_quad(cx<T> (&P)[4][4], const cx<T>* __restrict__ src,
+                                          int64_t V, int64_t plane_off, int64_t n1, int64_t n2,
+                                          int64_t m1, int64_t m2, int lg2) {
+  const int64_t r0 = plane_off + (n1 << lg2);
+  const int64_t r1 = plane_off + (((n1 + SH) & m1) << lg2);
+  const int64_t z1 = (n2 + SH) & m2;
+  const int64_t idx[4] = {r0 + n2, r0 + z1, r1 + n2, r1 + z1};
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) P[q][c] = src[c * V + idx[q]];
+}
+
+template <typename T, int SH>
+__device__ __forceinline__ void bcc_column(cx<T>* __restrict__ dst, const cx<T>* __restrict__ src,
+                                           const cx<T>* __restrict__ own, const StencilGeom& g,
+                                           const StencilCoef<T>& C, int64_t c0, int len,
+                                           int64_t n1, int64_t n2) {
+  const int64_t V = g.V;
+  const int64_t m0 = g.N[0] - 1, m1 = g.N[1] - 1, m2 = g.N[2] - 1;
+  const int lg12 = g.lg[1] + g.lg[2];
+  const int64_t col = (n1 << g.lg[2]) | n2;
+  // H: the quad of the plane loaded last; Q: the new one. For s = +1 plane
+  // m0 is H and m0 + 1 is Q; for s = -1 plane m0 - 1 is H and m0 is Q.
+  cx<T> H[4][4], Q[4][4];
+  load_quad<T, SH>(H, src, V, (SH > 0 ? c0 : ((c0 - 1) & m0)) << lg12, n1, n2, m1, m2, g.lg[2]);
+  const cx<T> mass = C.onsite[0][0];
+  for (int i = 0; i < len; ++i) {
+    const int64_t n0 = c0 + i;
+    load_quad<T, SH>(Q, src, V, (SH > 0 ? ((n0 + 1) & m0) : n0) << lg12, n1, n2, m1, m2, g.lg[2]);
+    const int64_t site = (n0 << lg12) | col;
+    const cx<T> o0 = own[site], o1 = own[V + site], o2 = own[2 * V + site],
+                o3 = own[3 * V + site];
+    cx<T> a0 = mk((T)0, (T)0), a1 = a0, a2 = a0, a3 = a0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      // a_i = 1 where the k-th displacement is s along axis i
+      const int b0 = (kCart3[k][0] * SH + 1) >> 1;
+      const int b1 = (kCart3[k][1] * SH + 1) >> 1;
+      const int b2 = (kCart3[k][2] * SH + 1) >> 1;
+      const bool fresh = (b0 == 1) == (SH > 0);
+      const int qi = 2 * b1 + b2;
+      const cx<T> q0 = fresh ? Q[qi][0] : H[qi][0], q1 = fresh ? Q[qi][1] : H[qi][1];
+      const cx<T> q2 = fresh ? Q[qi][2] : H[qi][2], q3 = fresh ? Q[qi][3] : H[qi][3];
+      a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+      a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+      a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
+      a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
+    }
+    a0 = fma_c(a0, mass, o2);
+    a1 = fma_c(a1, mass, o3);
+    a2 = fma_c(a2, mass, o0);
+    a3 = fma_c(a3, mass, o1);
+    if (g.nt) {
+      store_nt(&dst[site], a0);
+      store_nt(&dst[V + site], a1);
+      store_nt(&dst[2 * V + site], a2);
+      store_nt(&dst[3 * V + site], a3);
+    } else {
+      dst[site] = a0;
+      dst[V + site] = a1;
+      dst[2 * V + site] = a2;
+      dst[3 * V + site] = a3;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) H[q][c] = Q[q][c];
+  }
+}
+
+// Thread order (a bijection onto the columns of both arrays), fastest first:
+// m2, a row of a strip of 2^kLgBccStrip rows of axis 1, the sublattice, the
+// strip, the chunk of axis 0. Each XCD takes a contiguous range of it
+// (xcd_block): the workgroups resident on one XCD cover a few strips of both
+// arrays and march through the same planes together, so the rows and planes
+// they share are fetched from HBM about once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_step_bcc(cx<T>* __restrict__ out,
                                                  const cx<T>* __restrict__ in, StencilGeom g,
                                                  const StencilCoef<T>* __restrict__ coefs) {
-  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int lgL = g.lg[0] < kLgBccChunk ? g.lg[0] : kLgBccChunk;
+  const int lgR = g.lg[1] < kLgBccStrip ? g.lg[1] : kLgBccStrip;
   const int64_t V = g.V;
-  if (gid >= 2 * V) return;
-  const int j = gid >= V ? 1 : 0;
-  const int64_t site = gid - j * V;
-  const cx<T>* __restrict__ src = in + (int64_t)(1 - j) * 4 * V;  // the other sublattice
-  const cx<T>* __restrict__ own = in + (int64_t)j * 4 * V;
+  const int64_t w = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (w >= (2 * V) >> lgL) return;
+  const int64_t n2 = w & (g.N[2] - 1);
+  int64_t q = w >> g.lg[2];
+  const int64_t r = q & ((int64_t(1) << lgR) - 1);
+  q >>= lgR;
+  const int j = (int)(q & 1);
+  q >>= 1;
+  const int64_t n1 = ((q & ((int64_t(1) << (g.lg[1] - lgR)) - 1)) << lgR) | r;
+  const int64_t c0 = (q >> (g.lg[1] - lgR)) << lgL;
   cx<T>* __restrict__ dst = out + (int64_t)j * 4 * V;
-  const StencilCoef<T>& C = coefs[0];
-  const int64_t m0 = g.N[0] - 1, m1 = g.N[1] - 1, m2 = g.N[2] - 1;
-  const int64_t n2 = site & m2;
-  const int64_t n1 = (site >> g.lg[2]) & m1;
-  const int64_t n0 = site >> (g.lg[2] + g.lg[1]);
-  const int sh = j == 0 ? -1 : 1;  // (c - t)/2 or (c + t)/2, c = +-1
-  cx<T> a0 = mk((T)0, (T)0), a1 = a0, a2 = a0, a3 = a0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int64_t x = (n0 + (kCart3[k][0] + sh) / 2) & m0;
-    const int64_t y = (n1 + (kCart3[k][1] + sh) / 2) & m1;
-    const int64_t z = (n2 + (kCart3[k][2] + sh) / 2) & m2;
-    const int64_t nb = (((x << g.lg[1]) | y) << g.lg[2]) | z;
-    const cx<T> q0 = src[nb], q1 = src[V + nb], q2 = src[2 * V + nb], q3 = src[3 * V + nb];
-    a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
-    a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
-    a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
-    a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
-  }
-  const cx<T> mass = C.onsite[0][0];
-  a0 = fma_c(a0, mass, own[2 * V + site]);
-  a1 = fma_c(a1, mass, own[3 * V + site]);
-  a2 = fma_c(a2, mass, own[site]);
-  a3 = fma_c(a3, mass, own[V + site]);
-  if (g.nt) {
-    store_nt(&dst[site], a0);
-    store_nt(&dst[V + site], a1);
-    store_nt(&dst[2 * V + site], a2);
-    store_nt(&dst[3 * V + site], a3);
-  } else {
-    dst[site] = a0;
-    dst[V + site] = a1;
-    dst[2 * V + site] = a2;
-    dst[3 * V + site] = a3;
-  }
+  const cx<T>* __restrict__ own = in + (int64_t)j * 4 * V;
+  const cx<T>* __restrict__ src = in + (int64_t)(1 - j) * 4 * V;  // the other sublattice
+  if (j == 0)
+    bcc_column<T, -1>(dst, src, own, g, coefs[0], c0, 1 << lgL, n1, n2);
+  else
+    bcc_column<T, 1>(dst, src, own, g, coefs[0], c0, 1 << lgL, n1, n2);
 }
 
 hipError_t launch_step_bcc(bool dbl, const StencilGeom& g, void* out, const void* in,
                            const void* coefs, hipStream_t st) {
   if (g.dim != 3 || g.weyl) return hipErrorInvalidValue;
-  const int64_t nblk = (2 * g.V + 255) / 256;
+  const int lgL = g.lg[0] < kLgBccChunk ? g.lg[0] : kLgBccChunk;
+  const int64_t nblk = (((2 * g.V) >> lgL) + 255) / 256;
   StencilGeom gn = g;
   gn.nt = 2 * 4 * (size_t)g.V * (dbl ? 16 : 8) >= kNtBytes;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
