@@ -367,13 +367,223 @@ __global__ __launch_bounds__(256) void k_step_bcc(cx<T>* __restrict__ out,
     bcc_column<T, 1>(dst, src, own, g, coefs[0], c0, 1 << lgL, n1, n2);
 }
 
+// LDS-tiled form of the same step. A workgroup owns a kBtR x kBtC tile of
+// (m1, m2) and a chunk of planes of axis 0, and forms the outputs of both
+// sublattice arrays there: output m of sublattice 0 reads sublattice 1 at
+// m - a and output m of sublattice 1 reads sublattice 0 at m + a, a in
+// {0,1}^3. Per plane it stages the sublattice-1 tile with a one-site halo on
+// the low side of axes 1 and 2 and the sublattice-0 tile with one on the high
+// side, each in a ring of two planes (m0 - 1 and m0 of sublattice 1, m0 and
+// m0 + 1 of sublattice 0). Each input value is then fetched once per
+// workgroup (plus its share of halo), every read of the eight neighbours and
+// of the site's own components (the mass term) is served from LDS, and a
+// barrier per plane keeps the workgroup's waves on the same plane.
+constexpr int kBtR = 4, kBtC = 64;
+constexpr int kBtHC = kBtC + 1;
+constexpr int kBtSites = (kBtR + 1) * kBtHC;     // tile plus halo: 325
+constexpr int kBtHalo = kBtSites - kBtR * kBtC;  // 69
+constexpr int kBtThreads = kBtR * kBtC;          // one tile site per thread
+
+// Halo site k < kBtHalo of a staged plane as local (row, column): for
+// sublattice 1 (halo low) row 0 in full, then column 0 of rows 1..kBtR; for
+// sublattice 0 (halo high) row kBtR in full, then column kBtC of rows
+// 0..kBtR-1.
+__device__ __forceinline__ void bt_halo_site(int sub, int k, int& lr, int& lc) {
+  if (k < kBtHC) {
+    lr = sub ? 0 : kBtR;
+    lc = k;
+  } else {
+    lr = sub ? k - kBtHC + 1 : k - kBtHC;
+    lc = sub ? 0 : kBtC;
+  }
+}
+
+// Per-thread staging of the tiled cubic step: the thread's own tile site of
+// a sublattice-1 plane p1 and a sublattice-0 plane p0, and its halo site (of
+// plane p1 or p0), held in registers between the global loads and the LDS
+// writes.
+template <typename T>
+struct BtRegs {
+  cx<T> v1[4], v0[4], vh[4];
+};
+struct BtSite {
+  int64_t col, hcol;  // (m1, m2) offsets of the tile site and of the halo site
+  int lh, l1, l0;     // LDS offsets: halo site, tile site in the two staged layouts
+  int hsub;           // sublattice of the halo site
+  bool has_halo;
+};
+
+template <typename T>
+__device__ __forceinline__ void bt_fetch(BtRegs<T>& v, const cx<T>* __restrict__ f0,
+                                         const cx<T>* __restrict__ f1, int64_t V, int64_t m0,
+                                         int lg12, const BtSite& S, int64_t p1, int64_t p0) {
+  const int64_t s1 = ((p1 & m0) << lg12) | S.col, s0 = ((p0 & m0) << lg12) | S.col;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v.v1[q] = f1[q * V + s1];
+    v.v0[q] = f0[q * V + s0];
+  }
+  if (S.has_halo) {
+    const cx<T>* __restrict__ hsrc = S.hsub ? f1 : f0;
+    const int64_t sh = (((S.hsub ? p1 : p0) & m0) << lg12) | S.hcol;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v.vh[q] = hsrc[q * V + sh];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void bt_stage(const BtRegs<T>& v, cx<T>* lds, const BtSite& S,
+                                         int slot) {
+  cx<T>* s1 = lds + (2 + slot) * 4 * kBtSites;
+  cx<T>* s0 = lds + slot * 4 * kBtSites;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    s1[q * kBtSites + S.l1] = v.v1[q];
+    s0[q * kBtSites + S.l0] = v.v0[q];
+  }
+  if (S.has_halo) {
+    cx<T>* sh = S.hsub ? s1 : s0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh[q * kBtSites + S.lh] = v.vh[q];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBtThreads) void k_step_bcc_tile(cx<T>* __restrict__ out,
+                                                              const cx<T>* __restrict__ in,
+                                                              StencilGeom g,
+                                                              const StencilCoef<T>* __restrict__ coefs,
+                                                              int lgL) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);  // [sub][slot][comp][kBtSites]
+  const int64_t V = g.V;
+  const int64_t m0 = g.N[0] - 1, m1 = g.N[1] - 1, m2 = g.N[2] - 1;
+  const int lg12 = g.lg[1] + g.lg[2];
+  const int64_t tiles2 = g.N[2] / kBtC, tiles1 = g.N[1] / kBtR;
+  const int64_t w = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t b2 = (w % tiles2) * kBtC;
+  const int64_t b1 = ((w / tiles2) % tiles1) * kBtR;
+  const int64_t c0 = (w / (tiles2 * tiles1)) << lgL;
+  const int tid = threadIdx.x;
+  const int r = tid / kBtC, c = tid % kBtC;
+  const cx<T>* __restrict__ f0 = in;
+  const cx<T>* __restrict__ f1 = in + 4 * V;
+  // The halo site this thread stages, if any: sublattice 1 for tid < kBtHalo,
+  // sublattice 0 for kBtHalo <= tid < 2 kBtHalo.
+  const int hsub = tid < kBtHalo ? 1 : 0;
+  const bool has_halo = tid < 2 * kBtHalo;
+  int hr = 0, hc = 0;
+  if (has_halo) bt_halo_site(hsub, hsub ? tid : tid - kBtHalo, hr, hc);
+  const int64_t hcol = hsub ? ((((b1 - 1 + hr) & m1) << g.lg[2]) | ((b2 - 1 + hc) & m2))
+                            : ((((b1 + hr) & m1) << g.lg[2]) | ((b2 + hc) & m2));
+  const int64_t col = ((b1 + r) << g.lg[2]) | (b2 + c);
+  const BtSite S{col, hcol, hr * kBtHC + hc, (r + 1) * kBtHC + c + 1, r * kBtHC + c, hsub,
+                 has_halo};
+  BtRegs<T> v;
+  const StencilCoef<T>& C = coefs[0];
+  const cx<T> mass = C.onsite[0][0];
+  const int L = 1 << lgL;
+  cx<T>* __restrict__ d0 = out;
+  cx<T>* __restrict__ d1 = out + 4 * V;
+  bt_fetch(v, f0, f1, V, m0, lg12, S, c0 - 1, c0);  // the older planes of the first output plane
+  bt_stage(v, lds, S, 0);
+  bt_fetch(v, f0, f1, V, m0, lg12, S, c0, c0 + 1);
+  for (int i = 0; i < L; ++i) {
+    const int oslot = i & 1, nslot = oslot ^ 1;
+    __syncthreads();  // the previous plane's reads of slot nslot are done
+    bt_stage(v, lds, S, nslot);
+    __syncthreads();
+    const int64_t n0 = c0 + i;
+    if (i + 1 < L) bt_fetch(v, f0, f1, V, m0, lg12, S, n0 + 1, n0 + 2);
+    const cx<T>* o1 = lds + (2 + oslot) * 4 * kBtSites;  // sublattice 1, plane n0 - 1
+    const cx<T>* n1p = lds + (2 + nslot) * 4 * kBtSites; // sublattice 1, plane n0
+    const cx<T>* o0 = lds + oslot * 4 * kBtSites;        // sublattice 0, plane n0
+    const cx<T>* n0p = lds + nslot * 4 * kBtSites;       // sublattice 0, plane n0 + 1
+    const int64_t site = (n0 << lg12) | col;
+    // Sublattice 0: neighbours m - a on sublattice 1, own components at m.
+    {
+      cx<T> a0 = mk((T)0, (T)0), a1 = a0, a2 = a0, a3 = a0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e0 = (1 - kCart3[k][0]) >> 1, e1 = (1 - kCart3[k][1]) >> 1,
+                  e2 = (1 - kCart3[k][2]) >> 1;
+        const cx<T>* P = e0 ? o1 : n1p;
+        const int l = (r + 1 - e1) * kBtHC + (c + 1 - e2);
+        const cx<T> q0 = P[l], q1 = P[kBtSites + l], q2 = P[2 * kBtSites + l],
+                    q3 = P[3 * kBtSites + l];
+        a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+        a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+        a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
+        a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
+      }
+      const int l = r * kBtHC + c;
+      a0 = fma_c(a0, mass, o0[2 * kBtSites + l]);
+      a1 = fma_c(a1, mass, o0[3 * kBtSites + l]);
+      a2 = fma_c(a2, mass, o0[l]);
+      a3 = fma_c(a3, mass, o0[kBtSites + l]);
+      if (g.nt) {
+        store_nt(&d0[site], a0); store_nt(&d0[V + site], a1);
+        store_nt(&d0[2 * V + site], a2); store_nt(&d0[3 * V + site], a3);
+      } else {
+        d0[site] = a0; d0[V + site] = a1; d0[2 * V + site] = a2; d0[3 * V + site] = a3;
+      }
+    }
+    // Sublattice 1: neighbours m + a on sublattice 0, own components at m.
+    {
+      cx<T> a0 = mk((T)0, (T)0), a1 = a0, a2 = a0, a3 = a0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e0 = (1 + kCart3[k][0]) >> 1, e1 = (1 + kCart3[k][1]) >> 1,
+                  e2 = (1 + kCart3[k][2]) >> 1;
+        const cx<T>* P = e0 ? n0p : o0;
+        const int l = (r + e1) * kBtHC + (c + e2);
+        const cx<T> q0 = P[l], q1 = P[kBtSites + l], q2 = P[2 * kBtSites + l],
+                    q3 = P[3 * kBtSites + l];
+        a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+        a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+        a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
+        a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
+      }
+      const int l = (r + 1) * kBtHC + c + 1;
+      a0 = fma_c(a0, mass, n1p[2 * kBtSites + l]);
+      a1 = fma_c(a1, mass, n1p[3 * kBtSites + l]);
+      a2 = fma_c(a2, mass, n1p[l]);
+      a3 = fma_c(a3, mass, n1p[kBtSites + l]);
+      if (g.nt) {
+        store_nt(&d1[site], a0); store_nt(&d1[V + site], a1);
+        store_nt(&d1[2 * V + site], a2); store_nt(&d1[3 * V + site], a3);
+      } else {
+        d1[site] = a0; d1[V + site] = a1; d1[2 * V + site] = a2; d1[3 * V + site] = a3;
+      }
+    }
+  }
+}
+
 hipError_t launch_step_bcc(bool dbl, const StencilGeom& g, void* out, const void* in,
                            const void* coefs, hipStream_t st) {
   if (g.dim != 3 || g.weyl) return hipErrorInvalidValue;
-  const int lgL = g.lg[0] < kLgBccChunk ? g.lg[0] : kLgBccChunk;
-  const int64_t nblk = (((2 * g.V) >> lgL) + 255) / 256;
   StencilGeom gn = g;
   gn.nt = 2 * 4 * (size_t)g.V * (dbl ? 16 : 8) >= kNtBytes;
+  // complex64 lattices that hold a whole tile take the LDS-tiled kernel;
+  // complex128 takes the marching one, whose staging registers the compiler
+  // keeps out of scratch memory (the tiled kernel's it does not, at double).
+  if (!dbl && g.N[1] >= kBtR && g.N[2] >= kBtC) {
+    // Planes per workgroup: 16, halved (down to 2) until there are at least
+    // 2048 workgroups, and at most the length of axis 0.
+    const int64_t tiles = (g.N[1] / kBtR) * (g.N[2] / kBtC);
+    int lgL = 4;
+    while (lgL > 1 && (tiles * g.N[0]) >> lgL < 2048) --lgL;
+    if (lgL > g.lg[0]) lgL = g.lg[0];
+    const int64_t nblk = tiles * (g.N[0] >> lgL);
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t lds = 2 * 2 * 4 * kBtSites * sizeof(cx<float>);
+    hipLaunchKernelGGL(k_step_bcc_tile<float>, dim3((unsigned)nblk), dim3(kBtThreads), lds, st,
+                       (cx<float>*)out, (const cx<float>*)in, gn, (const StencilCoef<float>*)coefs,
+                       lgL);
+    return hipGetLastError();
+  }
+  const int lgL = g.lg[0] < kLgBccChunk ? g.lg[0] : kLgBccChunk;
+  const int64_t nblk = (((2 * g.V) >> lgL) + 255) / 256;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   if (dbl)
     hipLaunchKernelGGL(k_step_bcc<double>, dim3((unsigned)nblk), dim3(256), 0, st,

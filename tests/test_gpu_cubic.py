@@ -215,11 +215,15 @@ def test_bcc_evolve_under_every_schedule(qw, dtype, threads):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("N", [(2, 2, 2), (4, 8, 16), (8, 4, 32)])
+@pytest.mark.parametrize("N", [(2, 2, 2), (4, 8, 16), (8, 4, 32), (2, 4, 64), (4, 4, 64),
+                               (16, 4, 64), (8, 8, 128)])
 @pytest.mark.parametrize("m", [0.0, 0.3, 1.0])
 def test_bcc_step_matches_oracle(qw, N, m, dtype):
     """Position-space steps on the two sublattice arrays against the oracle's
-    Cartesian stepping of the embedded field (odd and even step counts)."""
+    Cartesian stepping of the embedded field (odd and even step counts). The
+    shapes with at least 4 x 64 sites per plane of axis 0 take the LDS-tiled
+    kernel at complex64 (one tile per plane at 2 x 4 x 64, so its halos wrap
+    onto the tile itself; several chunks of planes at 16 x 4 x 64)."""
     f = rand_sub(N, 71 + sum(N))
     plan = qw.Plan(3, list(N), m, dtype)
     x = to_dev(f, plan)
