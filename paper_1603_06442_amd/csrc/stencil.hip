@@ -239,6 +239,157 @@ __global__ __launch_bounds__(256) void k_step_weyl(cx<T>* __restrict__ out_all,
   }
 }
 
+// LDS-tiled 3D Weyl step (two components). A workgroup owns a kWtR x kWtC
+// tile of (n1, n2) and a chunk of planes of axis 0; each plane of the tile
+// with a one-site halo in n1 and n2 is read from global memory once into a
+// ring of three LDS planes (n0 - 1, n0, n0 + 1), from which all eight terms
+// of the output plane n0 are formed. Each thread owns four rows of a column
+// of the tile, so a plane's barrier covers four sites per thread.
+constexpr int kWtR = 16, kWtC = 64;
+constexpr int kWtHR = kWtR + 2, kWtHC = kWtC + 2;
+constexpr int kWtSites = kWtHR * kWtHC;          // tile plus halo: 1188
+constexpr int kWtHalo = kWtSites - kWtR * kWtC;  // 164
+constexpr int kWtThreads = 256;
+constexpr int kWtRowsPerThread = kWtR * kWtC / kWtThreads;  // 4
+constexpr int kWtRowStep = kWtThreads / kWtC;               // 4
+
+// Halo site k < kWtHalo as local (row, column): rows 0 and kWtHR - 1 in
+// full, then columns 0 and kWtHC - 1 of rows 1..kWtR.
+__device__ __forceinline__ void wt_halo_site(int k, int& lr, int& lc) {
+  if (k < 2 * kWtHC) {
+    lr = k < kWtHC ? 0 : kWtHR - 1;
+    lc = k < kWtHC ? k : k - kWtHC;
+  } else {
+    const int q = k - 2 * kWtHC;
+    lr = 1 + (q >> 1);
+    lc = (q & 1) ? kWtHC - 1 : 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWtThreads) void k_step_weyl_tile(cx<T>* __restrict__ out_all,
+                                                               const cx<T>* __restrict__ in_all,
+                                                               StencilGeom g,
+                                                               const StencilCoef<T>* __restrict__ coefs,
+                                                               int lgL) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);  // [slot 3][component 2][kWtSites]
+  const int64_t V = g.V;
+  const cx<T>* __restrict__ in = in_all + (int64_t)blockIdx.y * 2 * V;
+  cx<T>* __restrict__ out = out_all + (int64_t)blockIdx.y * 2 * V;
+  const StencilCoef<T>& C = coefs[blockIdx.y];
+  const int64_t m0 = g.N[0] - 1, m1 = g.N[1] - 1, m2 = g.N[2] - 1;
+  const int lg2 = g.lg[2], lg12 = g.lg[1] + g.lg[2];
+  const int64_t tiles2 = g.N[2] / kWtC, tiles1 = g.N[1] / kWtR;
+  const int64_t w = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t b2 = (w % tiles2) * kWtC;
+  const int64_t b1 = ((w / tiles2) % tiles1) * kWtR;
+  const int64_t c0 = (w / (tiles2 * tiles1)) << lgL;
+  const int tid = threadIdx.x;
+  const int r = tid / kWtC, c = tid % kWtC;
+  const bool has_halo = tid < kWtHalo;
+  int hr = 0, hc = 0;
+  if (has_halo) wt_halo_site(tid, hr, hc);
+  const int64_t hcol = (((b1 - 1 + hr) & m1) << lg2) | ((b2 - 1 + hc) & m2);
+  const int lh = hr * kWtHC + hc;
+  int64_t col[kWtRowsPerThread];
+#pragma unroll
+  for (int h = 0; h < kWtRowsPerThread; ++h) col[h] = ((b1 + r + h * kWtRowStep) << lg2) | (b2 + c);
+
+  cx<T> v[kWtRowsPerThread][2], vh0 = mk((T)0, (T)0), vh1 = vh0;
+  auto fetch = [&](int64_t p) {
+    const int64_t base = (p & m0) << lg12;
+#pragma unroll
+    for (int h = 0; h < kWtRowsPerThread; ++h) {
+      v[h][0] = in[base + col[h]];
+      v[h][1] = in[V + base + col[h]];
+    }
+    if (has_halo) {
+      vh0 = in[base + hcol];
+      vh1 = in[V + base + hcol];
+    }
+  };
+  auto stage = [&](int slot) {
+    cx<T>* P = lds + slot * 2 * kWtSites;
+#pragma unroll
+    for (int h = 0; h < kWtRowsPerThread; ++h) {
+      const int l = (r + h * kWtRowStep + 1) * kWtHC + c + 1;
+      P[l] = v[h][0];
+      P[kWtSites + l] = v[h][1];
+    }
+    if (has_halo) {
+      P[lh] = vh0;
+      P[kWtSites + lh] = vh1;
+    }
+  };
+
+  const int L = 1 << lgL;
+  fetch(c0 - 1);
+  stage(0);
+  fetch(c0);
+  stage(1);
+  fetch(c0 + 1);
+  int sm = 0, s0 = 1, sp = 2;  // ring slots of planes n0 - 1, n0, n0 + 1
+  for (int i = 0; i < L; ++i) {
+    const int64_t n0 = c0 + i;
+    __syncthreads();  // the previous plane's reads of slot sp are done
+    stage(sp);
+    __syncthreads();
+    if (i + 1 < L) fetch(n0 + 2);
+    const cx<T>* Pm = lds + sm * 2 * kWtSites;
+    const cx<T>* P0 = lds + s0 * 2 * kWtSites;
+    const cx<T>* Pp = lds + sp * 2 * kWtSites;
+    const int64_t plane = (n0 & m0) << lg12;
+#pragma unroll
+    for (int h = 0; h < kWtRowsPerThread; ++h) {
+      const int ls = (r + h * kWtRowStep + 1) * kWtHC + c + 1;
+      cx<T> a0 = mk((T)0, (T)0), a1 = a0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int o1 = kOff3[k][0], o2 = kOff3[k][1], o3 = kOff3[k][2];
+        const cx<T>* P = (o1 > 0 ? Pp : (o1 < 0 ? Pm : P0)) + ls + o2 * kWtHC + o3;
+        const cx<T> q0 = P[0], q1 = P[kWtSites];
+        a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+        a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+      }
+      const int64_t idx = plane | col[h];
+      if (g.nt) {
+        store_nt(&out[idx], a0);
+        store_nt(&out[V + idx], a1);
+      } else {
+        out[idx] = a0;
+        out[V + idx] = a1;
+      }
+    }
+    const int t = sm;
+    sm = s0;
+    s0 = sp;
+    sp = t;
+  }
+}
+
+bool step_weyl_tile_ok(const StencilGeom& g) {
+  return g.dim == 3 && g.weyl && g.N[1] >= kWtR && g.N[2] >= kWtC;
+}
+
+hipError_t launch_step_weyl_tile(const StencilGeom& g, int B, void* out, const void* in,
+                                 const void* coefs, hipStream_t st) {
+  // Planes per workgroup: 16, halved (down to 2) until there are at least
+  // 1024 workgroups per instance, and at most the length of axis 0 (at 256^3:
+  // 16 planes, 0.130 ms per step; 8 planes and 2048 workgroups, 0.133).
+  const int64_t tiles = (g.N[1] / kWtR) * (g.N[2] / kWtC);
+  int lgL = 4;
+  while (lgL > 1 && (tiles * g.N[0]) >> lgL < 1024) --lgL;
+  if (lgL > g.lg[0]) lgL = g.lg[0];
+  const int64_t nblk = tiles * (g.N[0] >> lgL);
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  const size_t lds = 3 * 2 * kWtSites * sizeof(cx<float>);
+  hipLaunchKernelGGL(k_step_weyl_tile<float>, dim3((unsigned)nblk, (unsigned)B),
+                     dim3(kWtThreads), lds, st, (cx<float>*)out, (const cx<float>*)in, g,
+                     (const StencilCoef<float>*)coefs, lgL);
+  return hipGetLastError();
+}
+
 // Cubic-supercell BCC field (Sec. 4): two sublattice arrays of N1 x N2 x N3
 // sites, f_j(m) at the Cartesian site x = 2m + j t, t = (1,1,1). One step of
 // the update rule of Sec. 2, psi(x) <- sum_k U_k psi(x + c_k) + mass term,
@@ -842,6 +993,7 @@ hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const v
   gn.nt = (size_t)B * (g.weyl ? 2 : (g.dim == 1 ? 2 : 4)) * (size_t)g.V * (dbl ? 16 : 8) >= kNtBytes;
   if (g.weyl) {
     if (g.dim < 2) return hipErrorInvalidValue;
+    if (!dbl && step_weyl_tile_ok(g)) return launch_step_weyl_tile(gn, B, out, in, coefs, st);
     if (dbl) {
       auto C = (const StencilCoef<double>*)coefs;
       auto o = (cx<double>*)out;

@@ -67,10 +67,14 @@ def test_weyl_step_matches_oracle(qw, d, shape, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("shape", [(8, 8, 64), (4, 16, 128), (32, 8, 64), (16, 32, 256)])
+@pytest.mark.parametrize("shape", [(8, 8, 64), (4, 16, 128), (32, 8, 64), (16, 32, 256),
+                                   (2, 16, 64), (32, 16, 64)])
 def test_weyl_step_3d_larger_lattices_match_oracle(qw, shape, dtype):
-    """Larger and non-cubic 3D lattices (many workgroups per XCD range of the
-    one-thread-per-site kernel)."""
+    """Larger and non-cubic 3D lattices: many workgroups per XCD range of the
+    one-thread-per-site kernel, and at complex64 with planes of at least
+    16 x 64 sites the LDS-tiled kernel (2 x 16 x 64: one tile per plane, its
+    halos wrapping onto the tile itself and all three ring planes drawn from
+    two; 32 x 16 x 64: several chunks of planes)."""
     psi0 = rand2(shape, 90)
     plan = qw.Plan(3, list(shape), 0.0, dtype, weyl=True)
     x = to_dev(psi0, plan)
