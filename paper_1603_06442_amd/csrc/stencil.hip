@@ -2,8 +2,10 @@
 //   psi(n, t+1) = sum_h U_h psi(n + h, t)   on the periodic N^d torus,
 // with the transition matrices U_h derived by the plan from the symbol.
 // The generic kernels use one thread per output site for all s components,
-// with neighbour reads served by L1/L2; large 3D lattices use the LDS-ring
-// kernel below.
+// with neighbour reads served by L1/L2. Large 3D lattices stage planes of a
+// tile in LDS instead: the plane-ring kernel (Dirac, complex64), the tile
+// kernel (Dirac, complex128 fields beyond the cache), the Weyl and the
+// cubic-supercell tile kernels (complex64).
 #include <algorithm>
 
 #include "qw_internal.h"
@@ -387,6 +389,157 @@ hipError_t launch_step_weyl_tile(const StencilGeom& g, int B, void* out, const v
   hipLaunchKernelGGL(k_step_weyl_tile<float>, dim3((unsigned)nblk, (unsigned)B),
                      dim3(kWtThreads), lds, st, (cx<float>*)out, (const cx<float>*)in, g,
                      (const StencilCoef<float>*)coefs, lgL);
+  return hipGetLastError();
+}
+
+// LDS-tiled 3D Dirac step for complex128 fields of at least kNtBytes (the
+// complex64 lattices take the plane-ring kernel below). A workgroup owns a kDtR x kDtC tile of (n1, n2)
+// and a chunk of planes of axis 0; each plane of the tile with a one-site
+// halo is read from global memory once into a ring of three LDS planes, from
+// which the eight neighbour terms and the mass term of the output plane are
+// formed, in the order of the one-thread-per-site kernel. One site per
+// thread: the ring of 3 x 4 components x 396 sites takes 76 KB, two
+// workgroups per CU.
+constexpr int kDtR = 4, kDtC = 64;
+constexpr int kDtHR = kDtR + 2, kDtHC = kDtC + 2;
+constexpr int kDtSites = kDtHR * kDtHC;          // 396
+constexpr int kDtHalo = kDtSites - kDtR * kDtC;  // 140
+constexpr int kDtThreads = kDtR * kDtC;
+
+// Halo site k < kDtHalo as local (row, column): rows 0 and kDtHR - 1 in
+// full, then columns 0 and kDtHC - 1 of rows 1..kDtR.
+__device__ __forceinline__ void dt_halo_site(int k, int& lr, int& lc) {
+  if (k < 2 * kDtHC) {
+    lr = k < kDtHC ? 0 : kDtHR - 1;
+    lc = k < kDtHC ? k : k - kDtHC;
+  } else {
+    const int q = k - 2 * kDtHC;
+    lr = 1 + (q >> 1);
+    lc = (q & 1) ? kDtHC - 1 : 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDtThreads) void k_step3d_tile(cx<T>* __restrict__ out_all,
+                                                            const cx<T>* __restrict__ in_all,
+                                                            StencilGeom g,
+                                                            const StencilCoef<T>* __restrict__ coefs,
+                                                            int lgL) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);  // [slot 3][component 4][kDtSites]
+  constexpr int PL = 4 * kDtSites;
+  const int64_t V = g.V;
+  const cx<T>* __restrict__ in = in_all + (int64_t)blockIdx.y * 4 * V;
+  cx<T>* __restrict__ out = out_all + (int64_t)blockIdx.y * 4 * V;
+  const StencilCoef<T>& C = coefs[blockIdx.y];
+  const int64_t m0 = g.N[0] - 1, m1 = g.N[1] - 1, m2 = g.N[2] - 1;
+  const int lg2 = g.lg[2], lg12 = g.lg[1] + g.lg[2];
+  const int64_t tiles2 = g.N[2] / kDtC, tiles1 = g.N[1] / kDtR;
+  const int64_t w = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t b2 = (w % tiles2) * kDtC;
+  const int64_t b1 = ((w / tiles2) % tiles1) * kDtR;
+  const int64_t c0 = (w / (tiles2 * tiles1)) << lgL;
+  const int tid = threadIdx.x;
+  const int r = tid / kDtC, c = tid % kDtC;
+  const bool has_halo = tid < kDtHalo;
+  int hr = 0, hc = 0;
+  if (has_halo) dt_halo_site(tid, hr, hc);
+  const int64_t hcol = (((b1 - 1 + hr) & m1) << lg2) | ((b2 - 1 + hc) & m2);
+  const int64_t col = ((b1 + r) << lg2) | (b2 + c);
+  const int lh = hr * kDtHC + hc;
+  const int ls = (r + 1) * kDtHC + c + 1;
+
+  cx<T> v0, v1, v2, v3, h0, h1, h2, h3;
+  h0 = h1 = h2 = h3 = mk((T)0, (T)0);
+  auto fetch = [&](int64_t p) __attribute__((always_inline)) {
+    const int64_t s = ((p & m0) << lg12) | col;
+    v0 = in[s]; v1 = in[V + s]; v2 = in[2 * V + s]; v3 = in[3 * V + s];
+    if (has_halo) {
+      const int64_t sh = ((p & m0) << lg12) | hcol;
+      h0 = in[sh]; h1 = in[V + sh]; h2 = in[2 * V + sh]; h3 = in[3 * V + sh];
+    }
+  };
+  auto stage = [&](int slot) __attribute__((always_inline)) {
+    cx<T>* P = lds + slot * PL;
+    P[ls] = v0; P[kDtSites + ls] = v1; P[2 * kDtSites + ls] = v2; P[3 * kDtSites + ls] = v3;
+    if (has_halo) {
+      P[lh] = h0; P[kDtSites + lh] = h1; P[2 * kDtSites + lh] = h2; P[3 * kDtSites + lh] = h3;
+    }
+  };
+
+  const int L = 1 << lgL;
+  fetch(c0 - 1);
+  stage(0);
+  fetch(c0);
+  stage(1);
+  fetch(c0 + 1);
+  int sm = 0, s0 = 1, sp = 2;  // ring slots of planes n0 - 1, n0, n0 + 1
+  const cx<T> mass = C.onsite[0][0];
+  for (int i = 0; i < L; ++i) {
+    const int64_t n0 = c0 + i;
+    __syncthreads();  // the previous plane's reads of slot sp are done
+    stage(sp);
+    __syncthreads();
+    if (i + 1 < L) fetch(n0 + 2);
+    const cx<T>* Pm = lds + sm * PL;
+    const cx<T>* P0 = lds + s0 * PL;
+    const cx<T>* Pp = lds + sp * PL;
+    cx<T> a0 = mk((T)0, (T)0), a1 = a0, a2 = a0, a3 = a0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int o1 = kOff3[k][0], o2 = kOff3[k][1], o3 = kOff3[k][2];
+      const cx<T>* P = (o1 > 0 ? Pp : (o1 < 0 ? Pm : P0)) + ls + o2 * kDtHC + o3;
+      const cx<T> q0 = P[0], q1 = P[kDtSites], q2 = P[2 * kDtSites], q3 = P[3 * kDtSites];
+      a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+      a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+      a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
+      a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
+    }
+    a0 = fma_c(a0, mass, P0[2 * kDtSites + ls]);
+    a1 = fma_c(a1, mass, P0[3 * kDtSites + ls]);
+    a2 = fma_c(a2, mass, P0[ls]);
+    a3 = fma_c(a3, mass, P0[kDtSites + ls]);
+    const int64_t idx = ((n0 & m0) << lg12) | col;
+    if (g.nt) {
+      store_nt(&out[idx], a0);
+      store_nt(&out[V + idx], a1);
+      store_nt(&out[2 * V + idx], a2);
+      store_nt(&out[3 * V + idx], a3);
+    } else {
+      out[idx] = a0;
+      out[V + idx] = a1;
+      out[2 * V + idx] = a2;
+      out[3 * V + idx] = a3;
+    }
+    const int t = sm;
+    sm = s0;
+    s0 = sp;
+    sp = t;
+  }
+}
+
+bool step3d_tile_ok(const StencilGeom& g) {
+  return g.dim == 3 && !g.weyl && g.N[1] >= kDtR && g.N[2] >= kDtC;
+}
+
+hipError_t launch_step3d_tile(const StencilGeom& g, int B, void* out, const void* in,
+                              const void* coefs, hipStream_t st) {
+  // Planes per workgroup: 16, halved (down to 2) until there are at least
+  // 2048 workgroups per instance, and at most the length of axis 0.
+  const int64_t tiles = (g.N[1] / kDtR) * (g.N[2] / kDtC);
+  int lgL = 4;
+  while (lgL > 1 && (tiles * g.N[0]) >> lgL < 2048) --lgL;
+  if (lgL > g.lg[0]) lgL = g.lg[0];
+  const int64_t nblk = tiles * (g.N[0] >> lgL);
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  const size_t lds = 3 * 4 * kDtSites * sizeof(cx<double>);
+  auto kern = k_step3d_tile<double>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk, (unsigned)B), dim3(kDtThreads), lds, st,
+                     (cx<double>*)out, (const cx<double>*)in, g, (const StencilCoef<double>*)coefs,
+                     lgL);
   return hipGetLastError();
 }
 
@@ -1010,6 +1163,11 @@ hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const v
     return hipGetLastError();
   }
   if (!dbl && step3d_ring_ok(g)) return launch_step3d_ring(g, B, out, in, coefs, st);
+  // complex128 fields beyond the last-level cache take the LDS tile kernel
+  // (256^3: 0.89 -> 0.68 ms per step); smaller ones, whose neighbour reads
+  // hit the cache, one thread per site (128^3: 0.070 ms against 0.112).
+  if (dbl && step3d_tile_ok(g) && (size_t)4 * (size_t)g.V * 16 >= kNtBytes)
+    return launch_step3d_tile(gn, B, out, in, coefs, st);
   if (dbl) {
     auto C = (const StencilCoef<double>*)coefs;
     auto o = (cx<double>*)out;

@@ -195,3 +195,18 @@ def test_cubic256_c64_localised_state_against_oracle(qw):
         got = got.cpu().numpy().astype(np.complex128)
         assert ob.rel_l2(got, want) < 2e-5
         assert abs(float(torch.linalg.vector_norm(field)) - 1.0) < 2e-5
+
+
+def test_c128_tiled_step_against_oracle(qw):
+    """complex128 fields of at least 256 MiB take the LDS tile kernel of the
+    3D step: 256 x 128 x 128 (exactly 256 MiB; 64 tiles of 4 x 64 per plane,
+    chunks of 8 planes), two steps against the oracle's stepping."""
+    shape, m = (256, 128, 128), 0.3
+    rng = np.random.default_rng(77)
+    psi = rng.standard_normal((4,) + shape) + 1j * rng.standard_normal((4,) + shape)
+    psi /= np.linalg.norm(psi)
+    plan = qw.Plan(3, list(shape), m, "c128")
+    x = torch.from_numpy(psi).cuda()
+    plan.step(x, 2)
+    ref = stepper.evolve_steps(psi, walk.stencil_table(3, m), 2)
+    assert ob.rel_l2(x.cpu().numpy(), ref) < 1e-12

@@ -78,9 +78,10 @@ def test_step_matches_oracle(qw, d, shape, m, dtype):
 @pytest.mark.parametrize("shape", [(8, 8, 64), (4, 16, 128), (32, 8, 64)])
 @pytest.mark.parametrize("m", [0.0, 0.3])
 def test_step_3d_plane_ring_matches_oracle(qw, shape, m, dtype):
-    """complex64 lattices with N2 >= 8 and N3 >= 64 take the LDS plane-ring
-    kernel (tiles of 8 x 64, chunks along n1, periodic wrap in all three
-    axes); complex128 takes one thread per site."""
+    """complex64 lattices with N1 >= 4, N2 >= 8 and N3 >= 64 take the LDS
+    plane-ring kernel (tiles of 8 x 64, chunks along n1, periodic wrap in all
+    three axes); complex128 takes one thread per site here (its LDS tile
+    kernel serves fields of at least 256 MiB: the full-size tests)."""
     psi0 = rand_field(3, shape, 31)
     plan = qw.Plan(3, list(shape), m, dtype)
     x = to_dev(psi0, plan)
