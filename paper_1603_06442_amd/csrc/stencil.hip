@@ -245,19 +245,23 @@ __global__ __launch_bounds__(256) void k_step_weyl(cx<T>* __restrict__ out_all,
 // tile of (n1, n2) and a chunk of planes of axis 0; each plane of the tile
 // with a one-site halo in n1 and n2 is read from global memory once into a
 // ring of three LDS planes (n0 - 1, n0, n0 + 1), from which all eight terms
-// of the output plane n0 are formed. Each thread owns four rows of a column
-// of the tile, so a plane's barrier covers four sites per thread.
-constexpr int kWtR = 16, kWtC = 64;
-constexpr int kWtHR = kWtR + 2, kWtHC = kWtC + 2;
-constexpr int kWtSites = kWtHR * kWtHC;          // tile plus halo: 1188
-constexpr int kWtHalo = kWtSites - kWtR * kWtC;  // 164
+// of the output plane n0 are formed. Each thread owns every fourth row of a
+// column of the tile, so a plane's barrier covers several sites per thread.
+// Tiles of kWtR rows: 16 at complex64 (four sites per thread, 57 KB of LDS),
+// 8 at complex128 (two, 63 KB), two workgroups per CU either way. At
+// complex128 the staged values take 80 B per lane of scratch memory.
+template <typename T>
+constexpr int wt_rows() { return sizeof(T) == 4 ? 16 : 8; }
+constexpr int kWtC = 64;
+constexpr int kWtHC = kWtC + 2;
 constexpr int kWtThreads = 256;
-constexpr int kWtRowsPerThread = kWtR * kWtC / kWtThreads;  // 4
-constexpr int kWtRowStep = kWtThreads / kWtC;               // 4
+constexpr int kWtRowStep = kWtThreads / kWtC;  // 4
 
-// Halo site k < kWtHalo as local (row, column): rows 0 and kWtHR - 1 in
-// full, then columns 0 and kWtHC - 1 of rows 1..kWtR.
+// Halo site k of a tile of R rows as local (row, column): rows 0 and R + 1
+// in full, then columns 0 and kWtHC - 1 of rows 1..R.
+template <int R>
 __device__ __forceinline__ void wt_halo_site(int k, int& lr, int& lc) {
+  constexpr int kWtHR = R + 2;
   if (k < 2 * kWtHC) {
     lr = k < kWtHC ? 0 : kWtHR - 1;
     lc = k < kWtHC ? k : k - kWtHC;
@@ -274,6 +278,10 @@ __global__ __launch_bounds__(kWtThreads) void k_step_weyl_tile(cx<T>* __restrict
                                                                StencilGeom g,
                                                                const StencilCoef<T>* __restrict__ coefs,
                                                                int lgL) {
+  constexpr int kWtR = wt_rows<T>();
+  constexpr int kWtSites = (kWtR + 2) * kWtHC;     // tile plus halo
+  constexpr int kWtHalo = kWtSites - kWtR * kWtC;
+  constexpr int kWtRowsPerThread = kWtR * kWtC / kWtThreads;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);  // [slot 3][component 2][kWtSites]
   const int64_t V = g.V;
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(kWtThreads) void k_step_weyl_tile(cx<T>* __restrict
   const int r = tid / kWtC, c = tid % kWtC;
   const bool has_halo = tid < kWtHalo;
   int hr = 0, hc = 0;
-  if (has_halo) wt_halo_site(tid, hr, hc);
+  if (has_halo) wt_halo_site<kWtR>(tid, hr, hc);
   const int64_t hcol = (((b1 - 1 + hr) & m1) << lg2) | ((b2 - 1 + hc) & m2);
   const int lh = hr * kWtHC + hc;
   int64_t col[kWtRowsPerThread];
@@ -370,27 +378,37 @@ __global__ __launch_bounds__(kWtThreads) void k_step_weyl_tile(cx<T>* __restrict
   }
 }
 
-bool step_weyl_tile_ok(const StencilGeom& g) {
-  return g.dim == 3 && g.weyl && g.N[1] >= kWtR && g.N[2] >= kWtC;
+bool step_weyl_tile_ok(const StencilGeom& g, bool dbl) {
+  return g.dim == 3 && g.weyl && g.N[1] >= (dbl ? wt_rows<double>() : wt_rows<float>()) &&
+         g.N[2] >= kWtC;
 }
 
-hipError_t launch_step_weyl_tile(const StencilGeom& g, int B, void* out, const void* in,
+hipError_t launch_step_weyl_tile(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
                                  const void* coefs, hipStream_t st) {
   // Planes per workgroup: 16, halved (down to 2) until there are at least
-  // 1024 workgroups per instance, and at most the length of axis 0 (at 256^3:
-  // 16 planes, 0.130 ms per step; 8 planes and 2048 workgroups, 0.133).
-  const int64_t tiles = (g.N[1] / kWtR) * (g.N[2] / kWtC);
+  // 1024 workgroups per instance, and at most the length of axis 0 (at 256^3
+  // complex64: 16 planes, 0.130 ms per step; 8 planes and 2048 workgroups,
+  // 0.133).
+  const int R = dbl ? wt_rows<double>() : wt_rows<float>();
+  const int64_t tiles = (g.N[1] / R) * (g.N[2] / kWtC);
   int lgL = 4;
   while (lgL > 1 && (tiles * g.N[0]) >> lgL < 1024) --lgL;
   if (lgL > g.lg[0]) lgL = g.lg[0];
   const int64_t nblk = tiles * (g.N[0] >> lgL);
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  const size_t lds = 3 * 2 * kWtSites * sizeof(cx<float>);
-  hipLaunchKernelGGL(k_step_weyl_tile<float>, dim3((unsigned)nblk, (unsigned)B),
-                     dim3(kWtThreads), lds, st, (cx<float>*)out, (const cx<float>*)in, g,
-                     (const StencilCoef<float>*)coefs, lgL);
+  const size_t lds = 3 * 2 * (size_t)(R + 2) * kWtHC * (dbl ? sizeof(cx<double>) : sizeof(cx<float>));
+  if (dbl) {
+    hipLaunchKernelGGL(k_step_weyl_tile<double>, dim3((unsigned)nblk, (unsigned)B),
+                       dim3(kWtThreads), lds, st, (cx<double>*)out, (const cx<double>*)in, g,
+                       (const StencilCoef<double>*)coefs, lgL);
+  } else {
+    hipLaunchKernelGGL(k_step_weyl_tile<float>, dim3((unsigned)nblk, (unsigned)B),
+                       dim3(kWtThreads), lds, st, (cx<float>*)out, (const cx<float>*)in, g,
+                       (const StencilCoef<float>*)coefs, lgL);
+  }
   return hipGetLastError();
 }
+
 
 // LDS-tiled 3D Dirac step for complex128 fields of at least kNtBytes (the
 // complex64 lattices take the plane-ring kernel below). A workgroup owns a kDtR x kDtC tile of (n1, n2)
@@ -1146,7 +1164,11 @@ hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const v
   gn.nt = (size_t)B * (g.weyl ? 2 : (g.dim == 1 ? 2 : 4)) * (size_t)g.V * (dbl ? 16 : 8) >= kNtBytes;
   if (g.weyl) {
     if (g.dim < 2) return hipErrorInvalidValue;
-    if (!dbl && step_weyl_tile_ok(g)) return launch_step_weyl_tile(gn, B, out, in, coefs, st);
+    // complex64 lattices that hold a tile, and complex128 fields beyond the
+    // last-level cache, take the LDS tile kernel (256^3 complex128: 0.351 ->
+    // 0.306 ms per step); smaller complex128 fields one thread per site.
+    if (step_weyl_tile_ok(g, dbl) && (!dbl || (size_t)B * 2 * (size_t)g.V * 16 >= kNtBytes))
+      return launch_step_weyl_tile(dbl, gn, B, out, in, coefs, st);
     if (dbl) {
       auto C = (const StencilCoef<double>*)coefs;
       auto o = (cx<double>*)out;

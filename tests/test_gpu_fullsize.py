@@ -210,3 +210,18 @@ def test_c128_tiled_step_against_oracle(qw):
     plan.step(x, 2)
     ref = stepper.evolve_steps(psi, walk.stencil_table(3, m), 2)
     assert ob.rel_l2(x.cpu().numpy(), ref) < 1e-12
+
+
+def test_c128_weyl_tiled_step_against_oracle(qw):
+    """complex128 Weyl fields of at least 256 MiB take the LDS tile kernel
+    (tiles of 8 x 64): 128 x 256 x 256 (exactly 256 MiB), two steps against
+    the oracle's stepping."""
+    shape = (128, 256, 256)
+    rng = np.random.default_rng(78)
+    psi = rng.standard_normal((2,) + shape) + 1j * rng.standard_normal((2,) + shape)
+    psi /= np.linalg.norm(psi)
+    plan = qw.Plan(3, list(shape), 0.0, "c128", weyl=True)
+    x = torch.from_numpy(psi).cuda()
+    plan.step(x, 2)
+    ref = stepper.evolve_steps(psi, walk.weyl_table(3), 2)
+    assert ob.rel_l2(x.cpu().numpy(), ref) < 1e-12

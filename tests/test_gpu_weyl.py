@@ -74,7 +74,9 @@ def test_weyl_step_3d_larger_lattices_match_oracle(qw, shape, dtype):
     one-thread-per-site kernel, and at complex64 with planes of at least
     16 x 64 sites the LDS-tiled kernel (2 x 16 x 64: one tile per plane, its
     halos wrapping onto the tile itself and all three ring planes drawn from
-    two; 32 x 16 x 64: several chunks of planes)."""
+    two; 32 x 16 x 64: several chunks of planes). complex128 fields this
+    small take one thread per site (the tile kernel serves those of at least
+    256 MiB: the full-size tests)."""
     psi0 = rand2(shape, 90)
     plan = qw.Plan(3, list(shape), 0.0, dtype, weyl=True)
     x = to_dev(psi0, plan)
