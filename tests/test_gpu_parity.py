@@ -401,12 +401,14 @@ def test_step_1d_on_chip_long_runs(qw, dtype):
 
 
 @pytest.mark.parametrize("d,shape,dtype", [(3, (64, 64, 64), "c64"), (3, (16, 16, 16), "c128"),
-                                           (1, (8192,), "c64"), (2, (64, 32), "c64")])
+                                           (1, (8192,), "c64"), (2, (64, 32), "c64"),
+                                           (3, (256, 128, 128), "c128")])
 def test_capture_into_a_graph(qw, d, shape, dtype):
     """qw_step and qw_evolve_fft, called once beforehand (so the plan has its
     scratch and tables), can be captured into a HIP graph by the caller.
     Each replay, with eager work and synchronisations between replays,
-    gives bitwise the eager result."""
+    gives bitwise the eager result. The 256 MiB complex128 field steps
+    through the LDS tile kernel, whose launch sets its LDS size attribute."""
     plan = qw.Plan(d, list(shape), 0.07, dtype)
     x0 = to_dev(rand_field(d, shape, 5), plan)
     a = x0.clone()
