@@ -156,38 +156,46 @@ def test_bcc_rejects_other_dimensions(qw):
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_bcc_capture_into_a_graph(qw, dtype):
-    """qw_bcc_evolve_fft and qw_bcc_transform, called once beforehand (the
-    plan builds its omega table then), captured into a HIP graph: every
-    replay, with eager work and synchronisations between replays, gives
-    bitwise the eager result."""
+    """qw_bcc_evolve_fft, qw_bcc_transform and qw_bcc_step, called once
+    beforehand (the plan builds its omega table and stepping scratch then),
+    captured into a HIP graph: every replay, with eager work and
+    synchronisations between replays, gives bitwise the eager result (the
+    steps run the LDS-tiled kernel at complex64, the marching one at
+    complex128)."""
     N = (16, 8, 64)
     plan = qw.Plan(3, list(N), 0.11, dtype)
     f0 = to_dev(rand_sub(N, 13), plan)
     a = plan.bcc_evolve_fft(f0, 29)
     h = plan.bcc_transform(a, +1)
+    st = f0.clone()
+    plan.bcc_step(st, 3)
     torch.cuda.synchronize()
-    want_a, want_h = a.clone(), h.clone()
-    ga, gh = torch.empty_like(f0), torch.empty_like(f0)
+    want_a, want_h, want_s = a.clone(), h.clone(), st.clone()
+    ga, gh, gs = torch.empty_like(f0), torch.empty_like(f0), f0.clone()
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         plan.bcc_evolve_fft(f0, 29, out=ga, stream=side)
         plan.bcc_transform(ga, +1, out=gh, stream=side)
+        plan.bcc_step(f0.clone(), 3, stream=side)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     with torch.cuda.graph(g):
         s = torch.cuda.current_stream()
         plan.bcc_evolve_fft(f0, 29, out=ga, stream=s)
         plan.bcc_transform(ga, +1, out=gh, stream=s)
+        plan.bcc_step(gs, 3, stream=s)
     for r in range(3):
         ga.zero_()
         gh.zero_()
+        gs.copy_(f0)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(ga, want_a), r
         assert torch.equal(gh, want_h), r
+        assert torch.equal(gs, want_s), r
         e = plan.bcc_evolve_fft(f0, 3)  # eager work between replays
         torch.cuda.synchronize()
         del e
