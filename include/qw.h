@@ -34,6 +34,10 @@
  * device-to-device copies and never synchronise, so a caller may capture them
  * into a HIP graph and replay it. Their first call on a plan may allocate
  * (scratch, the omega tables); make one call outside the capture first.
+ * A plan's scratch and parameter buffers only grow: a buffer replaced by a
+ * larger one (a later call on more fields, two fields, B instances) is kept
+ * until qw_destroy, so work enqueued before and graphs captured before stay
+ * valid, and growth never synchronises the device.
  *
  * Errors: every call returns a qw_status; nothing throws across the ABI.
  * qw_last_error() returns a message for the last failing call of the calling
@@ -343,8 +347,8 @@ qw_status qw_dispersion_taylor(int dim, double m, const double* k0, int order, d
  * c_minus), a time t and the precision. The server prepares the state,
  * evolves it to t (Sec. 4) and returns the reductions of psi(t) about
  * `center` (Sec. 5.2). Requests are admitted in arrival order while the
- * device memory they need (one field, two for the 1D four-step) fits
- * budget_bytes, grouped by (dim, N, dtype) into batches of at most max_batch
+ * device memory they need (one field, two for the 1D four-step, plus their
+ * parameters and partial sums) fits budget_bytes, grouped by (dim, N, dtype) into batches of at most max_batch
  * instances (each with its own m, state and t), and run on nstreams streams;
  * at most 2 * nstreams batches are on the device at once, and requests
  * that arrive meanwhile gather into the next batches, admitted as batches
@@ -375,10 +379,16 @@ typedef struct {
   double sector_norm2[2];  /* squared norms of the two sector amplitudes before normalisation */
 } qw_result;
 
+/* used_bytes: the footprints charged against the budget by the requests on
+ * the device (a request's footprint is the device layout of a batch holding
+ * it alone: field, transpose buffer, parameters, partial sums, results);
+ * laid_out_bytes: the device layouts of the batches on the device, never
+ * more than used_bytes. peak_*: the largest value so far. */
 typedef struct {
   int64_t submitted, completed, batches, queued;
   int64_t inflight_batches, max_inflight_batches;
   int64_t used_bytes, peak_used_bytes;
+  int64_t laid_out_bytes, peak_laid_out_bytes;
 } qw_server_info;
 
 /* Start a server on the current device. budget_bytes >= 1 MiB, max_batch in

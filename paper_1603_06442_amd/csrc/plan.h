@@ -6,6 +6,7 @@
 
 #include <complex>
 #include <string>
+#include <vector>
 
 #include "qw_internal.h"
 
@@ -88,7 +89,14 @@ struct qw_plan_s {
   int gw = 1;    // pencil groups per workgroup of the fused pass (prefetch when > 1)
   bool sparse3 = false;  // 3D transition matrices have the rank-one block pattern
 
+  // Buffers replaced by a larger one (scratch, per-instance parameters and
+  // matrices). Work enqueued earlier, or a graph captured earlier, may still
+  // read or write them, so they are released only with the plan.
+  std::vector<void*> retired_dev, retired_host;
+
   ~qw_plan_s() {
+    for (void* q : retired_dev) (void)hipFree(q);
+    for (void* q : retired_host) (void)hipHostFree(q);
     if (d_tw) (void)hipFree(d_tw);
     if (d_tw4) (void)hipFree(d_tw4);
     if (d_cs) (void)hipFree(d_cs);
@@ -122,8 +130,12 @@ qw_status ensure_coefs(qw_plan_t p, int B);
 // without a strided pass (1D, N <= 4096).
 qw_status evolve_impl(qw_plan_t p, int B, const void* in, void* out, const InstParam* dinst,
                       const InstParam& single, hipStream_t st, const ObsFuse* fuse = nullptr);
-// Column blocks per component of the fused last pass (0: no fusion possible).
+// 1D lattices longer than this use the four-step split N = N1 * kFourStepL.
+constexpr int64_t kFourStepL = 4096;
+// Column blocks per component of the fused last pass (0: no fusion possible),
+// for a plan and for a lattice shape without one.
 int64_t fused_obs_blocks(qw_plan_t p);
+int64_t fused_obs_blocks_of(int dim, const int64_t* N, bool dbl);
 ObsFuse make_fuse(qw_plan_t p, const double* origin, const double* origins, double* partials,
                   bool store);
 // psi_t = T^-1 [D_q^t a(q)] in place for B spectra in storage order, device

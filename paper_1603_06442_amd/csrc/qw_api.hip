@@ -384,52 +384,57 @@ inline void mark() {
     (void)hipEventRecord(g_timer->ev[g_timer->n++], g_timer->st);
 }
 
+// The plan's buffers only grow. A buffer that is replaced is kept (retired)
+// until qw_destroy, not freed: kernels enqueued before the growth, and graphs
+// a caller captured before it, still hold its address. Growth therefore
+// needs no device synchronisation and never stalls other streams.
 qw_status ensure_scratch(qw_plan_t p, size_t bytes) {
   if (p->scratch_bytes >= bytes) return QW_OK;
-  if (p->d_scratch) {
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipFree(p->d_scratch));
-    p->d_scratch = nullptr;
-    p->scratch_bytes = 0;
-  }
-  HIP_TRY(hipMalloc(&p->d_scratch, bytes));
+  void* q = nullptr;
+  HIP_TRY(hipMalloc(&q, bytes));
+  if (p->d_scratch) p->retired_dev.push_back(p->d_scratch);
+  p->d_scratch = q;
   p->scratch_bytes = bytes;
   return QW_OK;
 }
 
 qw_status ensure_inst(qw_plan_t p, int B) {
   if (p->inst_cap >= B) return QW_OK;
-  if (p->d_inst) {
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipFree(p->d_inst));
-    HIP_TRY(hipHostFree(p->h_inst));
-    p->d_inst = nullptr;
-    p->h_inst = nullptr;
-    p->inst_cap = 0;
-  }
   int cap = 64;
   while (cap < B) cap <<= 1;
-  HIP_TRY(hipMalloc(&p->d_inst, sizeof(InstParam) * cap));
-  HIP_TRY(hipHostMalloc((void**)&p->h_inst, sizeof(InstParam) * cap, hipHostMallocDefault));
+  InstParam* d = nullptr;
+  InstParam* h = nullptr;
+  HIP_TRY(hipMalloc(&d, sizeof(InstParam) * cap));
+  hipError_t e = hipHostMalloc((void**)&h, sizeof(InstParam) * cap, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    HIP_TRY(e);
+  }
+  if (p->d_inst) p->retired_dev.push_back(p->d_inst);
+  if (p->h_inst) p->retired_host.push_back(p->h_inst);
+  p->d_inst = d;
+  p->h_inst = h;
   p->inst_cap = cap;
   return QW_OK;
 }
 
 qw_status ensure_coefs(qw_plan_t p, int B) {
   if (p->coefs_cap >= B) return QW_OK;
-  if (p->d_coefs) {
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipFree(p->d_coefs));
-    HIP_TRY(hipHostFree(p->h_coefs));
-    p->d_coefs = nullptr;
-    p->h_coefs = nullptr;
-    p->coefs_cap = 0;
-  }
   int cap = 16;
   while (cap < B) cap <<= 1;
   const size_t one = sizeof(StencilCoef<double>);
-  HIP_TRY(hipMalloc(&p->d_coefs, one * cap));
-  HIP_TRY(hipHostMalloc((void**)&p->h_coefs, one * cap, hipHostMallocDefault));
+  void* d = nullptr;
+  unsigned char* h = nullptr;
+  HIP_TRY(hipMalloc(&d, one * cap));
+  hipError_t e = hipHostMalloc((void**)&h, one * cap, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    HIP_TRY(e);
+  }
+  if (p->d_coefs) p->retired_dev.push_back(p->d_coefs);
+  if (p->h_coefs) p->retired_host.push_back(p->h_coefs);
+  p->d_coefs = d;
+  p->h_coefs = h;
   p->coefs_cap = cap;
   return QW_OK;
 }
@@ -507,12 +512,14 @@ static qw_status last_pass(qw_plan_t p, int64_t L, void* out, const void* in, in
   return QW_OK;
 }
 
-int64_t fused_obs_blocks(qw_plan_t p) {
-  if (p->dim == 3) return strided_obs_blocks(p->dbl, p->N[0], p->N[1] * p->N[2]);
-  if (p->dim == 2) return strided_obs_blocks(p->dbl, p->N[0], p->N[1]);
-  if (p->fourstep) return strided_obs_blocks(p->dbl, p->fs_N1, p->fs_N2);
+int64_t fused_obs_blocks_of(int dim, const int64_t* N, bool dbl) {
+  if (dim == 3) return strided_obs_blocks(dbl, N[0], N[1] * N[2]);
+  if (dim == 2) return strided_obs_blocks(dbl, N[0], N[1]);
+  if (N[0] > kFourStepL) return strided_obs_blocks(dbl, N[0] / kFourStepL, kFourStepL);
   return 0;
 }
+
+int64_t fused_obs_blocks(qw_plan_t p) { return fused_obs_blocks_of(p->dim, p->N, p->dbl); }
 
 ObsFuse make_fuse(qw_plan_t p, const double* origin, const double* origins, double* partials,
                   bool store) {
@@ -891,10 +898,10 @@ static qw_status plan_create(qw_plan_t* out, int dim, const int64_t* N, double m
   if (dim == 3) p->sparse3 = coef_sparse3(p->coef_d);
 
   // Fourier schedule.
-  if (dim == 1 && N[0] > 4096) {
+  if (dim == 1 && N[0] > kFourStepL) {
     p->fourstep = true;
-    p->fs_N2 = 4096;
-    p->fs_N1 = N[0] / 4096;
+    p->fs_N2 = kFourStepL;
+    p->fs_N1 = N[0] / kFourStepL;
   }
   int64_t Nc = 1;
   for (int i = 0; i < dim; ++i) Nc = N[i] > Nc ? N[i] : Nc;
@@ -993,9 +1000,11 @@ static StencilGeom stencil_geom(qw_plan_t p) {
 
 // nsteps steps of B fields in place with device coefficients `coefs`: the
 // LDS-resident kernel where a 1D field fits (at most 4096 steps per launch),
-// otherwise one launch per step, ping-ponging with the plan's scratch.
+// otherwise one launch per step, ping-ponging with `buf` (B fields), or with
+// the plan's scratch when buf is null.
 static qw_status step_impl(qw_plan_t p, const StencilGeom& g, int B, void* psi,
-                           const void* coefs, int64_t nsteps, hipStream_t st) {
+                           const void* coefs, int64_t nsteps, hipStream_t st,
+                           void* buf = nullptr) {
   if (step1d_resident_ok(p->dbl, g)) {
     for (int64_t done = 0; done < nsteps;) {
       const int64_t k = std::min<int64_t>(4096, nsteps - done);
@@ -1005,10 +1014,13 @@ static qw_status step_impl(qw_plan_t p, const StencilGeom& g, int B, void* psi,
     return QW_OK;
   }
   const size_t bytes = p->field_bytes * (size_t)B;
-  qw_status r = ensure_scratch(p, bytes);
-  if (r != QW_OK) return r;
+  if (!buf) {
+    qw_status r = ensure_scratch(p, bytes);
+    if (r != QW_OK) return r;
+    buf = p->d_scratch;
+  }
   void* a = psi;
-  void* b = p->d_scratch;
+  void* b = buf;
   for (int64_t k = 0; k < nsteps; ++k) {
     HIP_TRY(launch_step(p->dbl, g, B, b, a, coefs, st));
     void* t = a;
@@ -1212,6 +1224,8 @@ qw_status qw_evolve_fft_timed(qw_plan_t p, const void* psi0, void* psi_t, int64_
   qw_status r = check_plan(p);
   if (r != QW_OK) return r;
   if (!psi0 || !psi_t || !pass_ms || !npass) return fail(QW_ERR_INVALID, "NULL argument");
+  r = check_time((double)t);
+  if (r != QW_OK) return r;
   hipStream_t st = (hipStream_t)stream;
   PassTimer tm;
   tm.st = st;
@@ -1220,8 +1234,6 @@ qw_status qw_evolve_fft_timed(qw_plan_t p, const void* psi0, void* psi_t, int64_
   InstParam ip;
   ip.m = p->m;
   ip.n = p->n;
-  r = check_time((double)t);
-  if (r != QW_OK) return r;
   ip.t = (double)t;
   g_timer = &tm;
   r = evolve_impl(p, 1, psi0, psi_t, nullptr, ip, st);
@@ -1350,6 +1362,7 @@ qw_status qw_bcc_step(qw_plan_t p, void* f, int64_t nsteps, void* stream) {
   qw_status r = check_bcc(p, f, f);
   if (r != QW_OK) return r;
   if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+  if (nsteps == 0) return QW_OK;
   hipStream_t st = (hipStream_t)stream;
   const size_t bytes = 2 * p->field_bytes;
   r = ensure_scratch(p, bytes);
@@ -1409,6 +1422,8 @@ qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, 
   if (!psi0 || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
   for (int i = 0; i < p->dim; ++i)
     if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+  r = check_time((double)t);
+  if (r != QW_OK) return r;
   hipStream_t st = (hipStream_t)stream;
   void* dst = psi_t;
   if (!dst) {  // intermediate passes need a field; the result is not kept
@@ -1419,8 +1434,6 @@ qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, 
   InstParam ip;
   ip.m = p->m;
   ip.n = p->n;
-  r = check_time((double)t);
-  if (r != QW_OK) return r;
   ip.t = (double)t;
   const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
   if (nb > 0) {

@@ -108,6 +108,7 @@ struct Batch;
 
 struct qw_server_s {
   size_t budget = 0, used = 0, peak_used = 0;
+  size_t laid_out = 0, peak_laid_out = 0;  // device bytes of the in-flight batches' layouts
   int max_batch = 1;
   int device = 0;
   std::vector<hipStream_t> streams;
@@ -134,39 +135,100 @@ struct qw_server_s {
 
 namespace {
 
+// Device and pinned-host layout of one batch of B requests of one shape:
+// the fields (and the four-step transpose buffer), the per-instance state,
+// apply and origin parameters, the partial sums of the state preparation and
+// the reductions, the sector norms and the results, each 256-byte aligned.
+// Every part is B times a per-instance size that does not depend on B, so a
+// batch's layout never exceeds the sum of its requests' own layouts (which is
+// what admission charges against the budget).
+struct Layout {
+  size_t off_field, off_scratch, off_sinst, off_inst, off_orig, off_part, off_norm, off_res;
+  size_t dbytes;
+  size_t h_sinst, h_inst, h_orig, h_res, h_norm;
+  size_t hbytes;
+  int64_t nbo, nbf;  // reduction blocks per instance: separate pass, fused pass (0: none)
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout batch_layout(const Key& k, int B) {
+  Layout L;
+  const bool dbl = k.dtype == QW_C128;
+  const int s = k.dim == 1 ? 2 : 4;
+  int64_t V = 1;
+  StateGeom sg;
+  memset(&sg, 0, sizeof sg);
+  ObsGeom og;
+  memset(&og, 0, sizeof og);
+  sg.dim = og.dim = k.dim;
+  sg.s = og.s = s;
+  for (int i = 0; i < 3; ++i) sg.N[i] = og.N[i] = i < k.dim ? k.N[i] : 1;
+  for (int i = 0; i < k.dim; ++i) V *= k.N[i];
+  sg.V = og.V = V;
+  const size_t fb = (size_t)V * s * (dbl ? 16 : 8);
+  const bool fourstep = k.dim == 1 && k.N[0] > kFourStepL;
+  L.nbo = observables_blocks(og, B);
+  L.nbf = (int64_t)s * fused_obs_blocks_of(k.dim, k.N, dbl);
+  size_t o = 0;
+  L.off_field = o;
+  o = align256(o + fb * B);
+  L.off_scratch = o;
+  if (fourstep) o = align256(o + fb * B);
+  L.off_sinst = o;
+  o = align256(o + sizeof(StateInst) * B);
+  L.off_inst = o;
+  o = align256(o + sizeof(InstParam) * B);
+  L.off_orig = o;
+  o = align256(o + sizeof(double) * 3 * B);
+  L.off_part = o;
+  o = align256(o + sizeof(double) * std::max<int64_t>(
+                       state_scratch_doubles(sg, B),
+                       (int64_t)B * (std::max<int64_t>(L.nbo, L.nbf) * kObsFields + 64 * kObsFields)));
+  L.off_norm = o;
+  o = align256(o + sizeof(double) * 2 * B);
+  L.off_res = o;
+  o = align256(o + sizeof(double) * kObsFields * B);
+  L.dbytes = o;
+  size_t h = 0;
+  L.h_sinst = h;
+  h = align256(h + sizeof(StateInst) * B);
+  L.h_inst = h;
+  h = align256(h + sizeof(InstParam) * B);
+  L.h_orig = h;
+  h = align256(h + sizeof(double) * 3 * B);
+  L.h_res = h;
+  h = align256(h + sizeof(double) * kObsFields * B);
+  L.h_norm = h;
+  h = align256(h + sizeof(double) * 2 * B);
+  L.hbytes = h;
+  return L;
+}
+
 struct Batch {
   qw_server_s* srv;
   Key key;
   qw_plan_t plan;
   std::vector<Pending> reqs;
+  Layout lay;
   void* dmem = nullptr;
-  size_t dbytes = 0;
   void* hmem = nullptr;
-  size_t hbytes = 0;
   size_t footprint = 0;
   hipStream_t st = nullptr;
   double t_launch = 0.0, t_done = 0.0;
   qw_status status = QW_OK;
-  // layout of hmem / dmem
-  size_t off_sinst, off_inst, off_orig, off_part, off_norm, off_res, off_field, off_scratch;
-  size_t h_sinst, h_inst, h_orig, h_res, h_norm;
 };
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-size_t field_bytes_of(const qw_request& r) {
-  int64_t V = 1;
-  for (int i = 0; i < r.dim; ++i) V *= r.N[i];
-  const int s = r.dim == 1 ? 2 : 4;
-  return (size_t)V * s * (r.dtype == QW_C128 ? 16 : 8);
+Key key_of(const qw_request& r) {
+  Key k;
+  k.dim = r.dim;
+  for (int i = 0; i < 3; ++i) k.N[i] = i < r.dim ? r.N[i] : 1;
+  k.dtype = (int)r.dtype;
+  return k;
 }
 
-bool fourstep_of(const qw_request& r) { return r.dim == 1 && r.N[0] > 4096; }
-
-size_t request_footprint(const qw_request& r) {
-  const size_t fb = field_bytes_of(r);
-  return fb * (fourstep_of(r) ? 2 : 1) + 4096;
-}
+// Device bytes a request is charged at admission: its own one-request layout.
+size_t request_footprint(const qw_request& r) { return batch_layout(key_of(r), 1).dbytes; }
 
 qw_status validate(const qw_request* r) {
   if (!r) return fail(QW_ERR_INVALID, "request is NULL");
@@ -202,52 +264,17 @@ void on_stream_done(void* arg) {
 qw_status launch_batch(qw_server_s* s, Batch* b) {
   const int B = (int)b->reqs.size();
   qw_plan_t p = b->plan;
-  const size_t fb = p->field_bytes;
   const StateGeom sg = state_geom(p);
   const ObsGeom og = obs_geom(p);
-  const int64_t nbo = observables_blocks(og, B);
-  const int64_t nbf = (int64_t)p->s * fused_obs_blocks(p);  // 0: separate reduction pass
-  // device layout
-  size_t o = 0;
-  b->off_field = o;
-  o = align256(o + fb * B);
-  b->off_scratch = o;
-  if (p->fourstep) o = align256(o + fb * B);
-  b->off_sinst = o;
-  o = align256(o + sizeof(StateInst) * B);
-  b->off_inst = o;
-  o = align256(o + sizeof(InstParam) * B);
-  b->off_orig = o;
-  o = align256(o + sizeof(double) * 3 * B);
-  b->off_part = o;
-  o = align256(o + sizeof(double) * std::max<int64_t>(
-                       state_scratch_doubles(sg, B),
-                       (int64_t)B * (std::max<int64_t>(nbo, nbf) * kObsFields + 64 * kObsFields)));
-  b->off_norm = o;
-  o = align256(o + sizeof(double) * 2 * B);
-  b->off_res = o;
-  o = align256(o + sizeof(double) * kObsFields * B);
-  b->dbytes = o;
-  // host (pinned) layout
-  size_t h = 0;
-  b->h_sinst = h;
-  h = align256(h + sizeof(StateInst) * B);
-  b->h_inst = h;
-  h = align256(h + sizeof(InstParam) * B);
-  b->h_orig = h;
-  h = align256(h + sizeof(double) * 3 * B);
-  b->h_res = h;
-  h = align256(h + sizeof(double) * kObsFields * B);
-  b->h_norm = h;
-  h = align256(h + sizeof(double) * 2 * B);
-  b->hbytes = h;
-  HIP_TRY(s->pool.get_dev(b->dbytes, &b->dmem));
-  HIP_TRY(s->pool.get_host(b->hbytes, &b->hmem));
+  const Layout& Ly = b->lay;
+  const int64_t nbf = Ly.nbf;  // 0: separate reduction pass
+  HIP_TRY(s->pool.get_dev(Ly.dbytes, &b->dmem));
+  HIP_TRY(s->pool.get_host(Ly.hbytes, &b->hmem));
   char* H = (char*)b->hmem;
   char* D = (char*)b->dmem;
-  StateInst* hs = (StateInst*)(H + b->h_sinst);
-  InstParam* hi = (InstParam*)(H + b->h_inst);
-  double* ho = (double*)(H + b->h_orig);
+  StateInst* hs = (StateInst*)(H + Ly.h_sinst);
+  InstParam* hi = (InstParam*)(H + Ly.h_inst);
+  double* ho = (double*)(H + Ly.h_orig);
   for (int k = 0; k < B; ++k) {
     const qw_request& r = b->reqs[k].req;
     hs[k] = make_state_inst(p, r.m, r.k0, r.sigma, r.center, r.c_plus, r.c_minus);
@@ -258,21 +285,21 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
   }
   hipStream_t st = b->st;
   // one upload of the three parameter arrays (contiguous in both layouts)
-  HIP_TRY(hipMemcpyAsync(D + b->off_sinst, H + b->h_sinst, b->h_res - b->h_sinst,
+  HIP_TRY(hipMemcpyAsync(D + Ly.off_sinst, H + Ly.h_sinst, Ly.h_res - Ly.h_sinst,
                          hipMemcpyHostToDevice, st));
-  void* field = D + b->off_field;
-  void* scratch = p->fourstep ? (void*)(D + b->off_scratch) : nullptr;
-  double* part = (double*)(D + b->off_part);
-  HIP_TRY(launch_state_prepare(p->dbl, sg, B, (const StateInst*)(D + b->off_sinst), part,
-                               (double*)(D + b->off_norm), field, st));
+  void* field = D + Ly.off_field;
+  void* scratch = p->fourstep ? (void*)(D + Ly.off_scratch) : nullptr;
+  double* part = (double*)(D + Ly.off_part);
+  HIP_TRY(launch_state_prepare(p->dbl, sg, B, (const StateInst*)(D + Ly.off_sinst), part,
+                               (double*)(D + Ly.off_norm), field, st));
   // The state is prepared as its spectrum: apply D_q^t there and invert once.
   // The 1D four-step keeps its transposed spectrum internal, so it goes to
   // position space and through the full evolution. Where the schedule ends
   // with a strided pass, the reductions are fused into it and psi(t) is
   // never written.
-  const InstParam* dinst = (const InstParam*)(D + b->off_inst);
-  const double* origins = (const double*)(D + b->off_orig);
-  double* res = (double*)(D + b->off_res);
+  const InstParam* dinst = (const InstParam*)(D + Ly.off_inst);
+  const double* origins = (const double*)(D + Ly.off_orig);
+  double* res = (double*)(D + Ly.off_res);
   const ObsFuse fuse = make_fuse(p, nullptr, origins, part, false);
   const ObsFuse* fz = nbf > 0 ? &fuse : nullptr;
   qw_status r;
@@ -293,9 +320,9 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
     HIP_TRY(launch_reduce_partials(B, nbf, part, part + (size_t)B * nbf * kObsFields, res, st));
   else
     HIP_TRY(launch_observables(p->dbl, og, B, field, nullptr, origins, part, res, st));
-  HIP_TRY(hipMemcpyAsync(H + b->h_res, D + b->off_res, sizeof(double) * kObsFields * B,
+  HIP_TRY(hipMemcpyAsync(H + Ly.h_res, D + Ly.off_res, sizeof(double) * kObsFields * B,
                          hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(H + b->h_norm, D + b->off_norm, sizeof(double) * 2 * B,
+  HIP_TRY(hipMemcpyAsync(H + Ly.h_norm, D + Ly.off_norm, sizeof(double) * 2 * B,
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipLaunchHostFunc(st, on_stream_done, b));
   return QW_OK;
@@ -304,8 +331,8 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
 void retire(qw_server_s* s, Batch* b) {  // lock held
   const int B = (int)b->reqs.size();
   const char* H = (const char*)b->hmem;
-  const double* R = (const double*)(H + b->h_res);
-  const double* NR = (const double*)(H + b->h_norm);
+  const double* R = (const double*)(H + b->lay.h_res);
+  const double* NR = (const double*)(H + b->lay.h_norm);
   for (int k = 0; k < B; ++k) {
     const Pending& pd = b->reqs[k];
     qw_result res;
@@ -326,9 +353,10 @@ void retire(qw_server_s* s, Batch* b) {  // lock held
     s->results[pd.ticket] = res;
     ++s->completed;
   }
-  if (b->dmem) s->pool.put_dev(b->dbytes, b->dmem);
-  if (b->hmem) s->pool.put_host(b->hbytes, b->hmem);
+  if (b->dmem) s->pool.put_dev(b->lay.dbytes, b->dmem);
+  if (b->hmem) s->pool.put_host(b->lay.hbytes, b->hmem);
   s->used -= b->footprint;
+  s->laid_out -= b->lay.dbytes;
   s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), b));
   delete b;
   s->cv_done.notify_all();
@@ -408,6 +436,9 @@ void worker_main(qw_server_s* s) {
         }
       }
       s->peak_used = std::max(s->peak_used, s->used);
+      b->lay = batch_layout(key, (int)b->reqs.size());
+      s->laid_out += b->lay.dbytes;
+      s->peak_laid_out = std::max(s->peak_laid_out, s->laid_out);
       ready.push_back(b);
     }
     if (!ready.empty()) {
@@ -479,9 +510,7 @@ qw_status qw_server_submit(qw_server_t s, const qw_request* req, int64_t* ticket
   pd.footprint = request_footprint(pd.req);
   if (pd.footprint > s->budget)
     return fail(QW_ERR_NOMEM, "request needs %zu bytes, budget is %zu", pd.footprint, s->budget);
-  pd.key.dim = req->dim;
-  for (int i = 0; i < 3; ++i) pd.key.N[i] = pd.req.N[i];
-  pd.key.dtype = (int)req->dtype;
+  pd.key = key_of(pd.req);
   pd.t_submit = now_s();
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -547,6 +576,8 @@ qw_status qw_server_stats(qw_server_t s, qw_server_info* out) {
   out->max_inflight_batches = s->peak_inflight;
   out->used_bytes = (int64_t)s->used;
   out->peak_used_bytes = (int64_t)s->peak_used;
+  out->laid_out_bytes = (int64_t)s->laid_out;
+  out->peak_laid_out_bytes = (int64_t)s->peak_laid_out;
   return QW_OK;
 }
 

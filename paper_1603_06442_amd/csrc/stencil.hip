@@ -1185,10 +1185,12 @@ hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const v
     return hipGetLastError();
   }
   if (!dbl && step3d_ring_ok(g)) return launch_step3d_ring(g, B, out, in, coefs, st);
-  // complex128 fields beyond the last-level cache take the LDS tile kernel
-  // (256^3: 0.89 -> 0.68 ms per step); smaller ones, whose neighbour reads
-  // hit the cache, one thread per site (128^3: 0.070 ms against 0.112).
-  if (dbl && step3d_tile_ok(g) && (size_t)4 * (size_t)g.V * 16 >= kNtBytes)
+  // complex128 steps whose fields (the whole batch: its instances are
+  // stepped together and share the cache) exceed the last-level cache take
+  // the LDS tile kernel (256^3: 0.89 -> 0.68 ms per step); smaller ones,
+  // whose neighbour reads hit the cache, one thread per site (128^3: 0.070 ms
+  // against 0.112). The Weyl walk uses the same rule.
+  if (dbl && step3d_tile_ok(g) && (size_t)B * 4 * (size_t)g.V * 16 >= kNtBytes)
     return launch_step3d_tile(gn, B, out, in, coefs, st);
   if (dbl) {
     auto C = (const StencilCoef<double>*)coefs;

@@ -64,7 +64,8 @@ class QwResult(ctypes.Structure):
 class QwServerInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "submitted", "completed", "batches", "queued", "inflight_batches",
-        "max_inflight_batches", "used_bytes", "peak_used_bytes")]
+        "max_inflight_batches", "used_bytes", "peak_used_bytes", "laid_out_bytes",
+        "peak_laid_out_bytes")]
 
 
 def _load():

@@ -75,6 +75,34 @@ def test_bcc256_c64_reversible_at_large_t(qw):
     assert abs(o["norm2"] - 1.0) < 2e-5
 
 
+def test_bcc128_jump_at_t_1e5_against_oracle(qw):
+    """The headline workload's state on the 128^3 torus (width scaled to 10
+    cells) jumped to the last time of its schedule, t = 1e5, in both
+    precisions, against the oracle's binary powering of the summed symbol
+    (about 15 s of host time), with the fused reductions."""
+    from oracle import fourier, states
+    w = inputs.workload(2)
+    N, t = 128, w["times"][-1]
+    c = [N // 2] * 3
+    psi0 = states.particle_state(3, N, w["m"], w["k0"], w["sigma"] * N / w["N"], c,
+                                 w["c_plus"], w["c_minus"])
+    ref = fourier.evolve_fourier(psi0, walk.stencil_table(3, w["m"]), t)
+    want = ob.observables(ref, c)
+    for dtype, tol in (("c64", 2e-5), ("c128", 1e-15 * t)):
+        plan = qw.Plan(3, N, w["m"], dtype)
+        plan.autotune()
+        x = torch.from_numpy(np.ascontiguousarray(psi0)).to(plan.torch_dtype).cuda()
+        y = plan.empty()
+        o = plan.evolve_fft_observables(x, t, c, out=y)
+        torch.cuda.synchronize()
+        e = ob.rel_l2(y.cpu().numpy().astype(np.complex128), ref)
+        print("128^3 %s at t = %d: rel-L2 %.3e" % (dtype, t, e))
+        assert e < tol
+        assert np.allclose(o["mean"], want["mean"], rtol=0, atol=N * tol)
+        assert abs(o["norm2"] - 1.0) < (1e-5 if dtype == "c64" else 1e-12)
+        del plan, x, y
+
+
 def test_bcc512_c64_vs_c128_and_jump_vs_step(qw):
     w = inputs.workload(4)
     N = w["N"]
@@ -195,6 +223,32 @@ def test_cubic256_c64_localised_state_against_oracle(qw):
         got = got.cpu().numpy().astype(np.complex128)
         assert ob.rel_l2(got, want) < 2e-5
         assert abs(float(torch.linalg.vector_norm(field)) - 1.0) < 2e-5
+
+
+def test_c128_tiled_step_batched_against_oracle(qw):
+    """complex128 batches whose fields together reach 256 MiB take the LDS
+    tile kernel (the rule counts the whole batch): two 128^3 fields with
+    their own masses, and 32 fields of 512 x 4 x 64, whose planes are one
+    tile high and wide so that the halo of every tile wraps onto itself.
+    Three steps (odd: the result is copied back from scratch)."""
+    rng = np.random.default_rng(91)
+    for shape, ms in (((128, 128, 128), [0.05, 0.4]),
+                      ((512, 4, 64), [0.0, 0.1, 0.3, 1.0] * 8)):
+        B = len(ms)
+        plan = qw.Plan(3, list(shape), 0.1, "c128")
+        assert B * 4 * int(np.prod(shape)) * 16 >= 256 << 20
+        psis = []
+        for b in range(B):
+            z = rng.standard_normal((4,) + shape) + 1j * rng.standard_normal((4,) + shape)
+            psis.append(z / np.linalg.norm(z))
+        x = torch.from_numpy(np.stack(psis)).cuda()
+        plan.step_batched(x, ms, 3)
+        torch.cuda.synchronize()
+        got = x.cpu().numpy()
+        del x
+        for b in sorted(set(range(B)) & {0, 1, 2, 3, B - 1}):
+            ref = stepper.evolve_steps(psis[b], walk.stencil_table(3, ms[b]), 3)
+            assert ob.rel_l2(got[b], ref) < 1e-12, (shape, b)
 
 
 def test_c128_tiled_step_against_oracle(qw):

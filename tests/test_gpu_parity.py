@@ -6,8 +6,10 @@ alignment):
 * complex128: 1e-12 for t <= 1e3 and 1e-15 t beyond (the phase omega t
   carries an absolute error ~ t * eps64);
 * complex64: 2e-5 for the Fourier jump (FP32 transforms, FP64 phase); the
-  FP32 stencil accumulates ~sqrt(steps) * 2^-24 per entry, bounded here by
-  max(2e-5, 4 sqrt(steps) 2^-24).
+  FP32 stencil's transition matrices are rounded to FP32, so each step is
+  off the unitary one by O(2^-24) and the error grows linearly in the number
+  of steps: max(2e-5, 4 steps 2^-24), which is 2e-5 up to 83 steps; the
+  128-step 64^3 workload is held to 2e-5 itself.
 """
 import math
 
@@ -246,11 +248,19 @@ def test_workload_bcc_64_c64(qw):
     plan = qw.Plan(3, w["N"], w["m"], "c64")
     x = to_dev(psi0, plan)
     plan.step(x, w["steps"])
-    assert ob.rel_l2(to_np(x), ref) < tol_step("c64", w["steps"])
+    e_step = ob.rel_l2(to_np(x), ref)
     y = plan.evolve_fft(to_dev(psi0, plan), w["t"])
-    assert ob.rel_l2(to_np(y), ref) < 2e-5
+    e_fft = ob.rel_l2(to_np(y), ref)
     o = plan.observables(y, w["center"])
+    os_ = plan.observables(x, w["center"])
+    print("64^3 complex64, t = %d: stencil rel-L2 %.3e (norm drift %.2e), "
+          "Fourier jump rel-L2 %.3e (norm drift %.2e)"
+          % (w["t"], e_step, abs(os_["norm2"] - 1.0), e_fft, abs(o["norm2"] - 1.0)))
+    # the FP32-path bound, for the 128 stencil steps as for the jump
+    assert e_step < 2e-5
+    assert e_fft < 2e-5
     assert abs(o["norm2"] - 1.0) < 1e-5
+    assert abs(os_["norm2"] - 1.0) < 1e-5
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
@@ -439,6 +449,40 @@ def test_capture_into_a_graph(qw, d, shape, dtype):
         assert torch.equal(gb, want_b), r
         e = x0.clone()  # eager work between replays
         plan.step(e, 1)
+        torch.cuda.synchronize()
+
+
+def test_captured_step_survives_scratch_growth(qw):
+    """A graph that captured qw_step (whose ping-pong buffer is the plan's
+    scratch) is replayed after qw_bcc_step (two fields of scratch) and
+    qw_step_batched (three) have grown that scratch: the plan keeps the
+    buffer the graph holds until it is destroyed, so every replay still
+    gives the eager result bitwise. A call refused for its time leaves the
+    scratch as it was."""
+    shape = (16, 16, 64)
+    plan = qw.Plan(3, list(shape), 0.2, "c64")
+    x0 = to_dev(rand_field(3, shape, 17), plan)
+    want = x0.clone()
+    plan.step(want, 3)
+    torch.cuda.synchronize()
+    ga = x0.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.step(ga, 3, stream=torch.cuda.current_stream())
+    f = torch.from_numpy(rand_field(3, shape, 18)[None].repeat(2, 0)).to(torch.complex64).cuda()
+    plan.bcc_step(f, 2)
+    xb = torch.stack([x0.clone() for _ in range(3)]).contiguous()
+    plan.step_batched(xb, [0.2, 0.1, 0.0], 1)
+    with pytest.raises(qw.QwError):
+        plan.evolve_fft_observables(x0, 1 << 60, [8, 8, 32])
+    torch.cuda.synchronize()
+    for r in range(3):
+        ga.copy_(x0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ga, want), r
+        plan.step(x0.clone(), 1)  # eager work between replays
         torch.cuda.synchronize()
 
 

@@ -99,6 +99,9 @@ def test_result_does_not_depend_on_the_batch_mix(qw):
         mix_srv.close()
     assert max(m["batch_size"] for m in mixed) > 1
     assert st["batches"] < len(reqs)
+    # a batch's device layout never exceeds the footprints charged for it
+    assert 0 < st["peak_laid_out_bytes"] <= st["peak_used_bytes"]
+    assert st["laid_out_bytes"] == 0 and st["used_bytes"] == 0
     for a, m in zip(alone, mixed):
         assert a["status"] == m["status"] == qw.QW_OK
         assert a["batch_size"] == 1
@@ -122,6 +125,7 @@ def test_admission_respects_the_budget(qw):
     assert all(g["batch_size"] == 1 for g in got)
     assert st["batches"] == 6 and st["completed"] == 6
     assert 0 < st["peak_used_bytes"] <= 3 * MiB
+    assert 0 < st["peak_laid_out_bytes"] <= st["peak_used_bytes"]
     assert st["used_bytes"] == 0 and st["queued"] == 0
     # queued behind memory: later requests wait for earlier ones
     lat = [g["latency_s"] for g in got]
