@@ -122,6 +122,21 @@ qw_status qw_destroy(qw_plan_t plan);
  * instead. */
 qw_status qw_step(qw_plan_t plan, void* psi, int64_t nsteps, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that must not call hipMalloc):
+ * qw_step with its ping-pong buffer in a fixed device array of
+ * QW_NOALLOC_SCRATCH_BYTES (64 MiB), which the library holds on every device
+ * it runs on until the process ends, instead of the plan's scratch. It
+ * allocates nothing, on its first call too, and gives qw_step's result bit
+ * for bit. The field (s * V * 8 or 16 bytes) must fit the array, else
+ * QW_ERR_UNSUPPORTED (3D up to 128^3 in complex64, 2D up to 1024^2; 1D
+ * fields that stay on chip use no buffer); the plan's device must be current
+ * (QW_ERR_INVALID). Every call on one device shares that device's array and
+ * leaves its last contents there: calls that overlap in time on one device
+ * (several streams or threads) race and must be serialised by the caller. */
+#define QW_NOALLOC_SCRATCH_BYTES (64u << 20)
+qw_status qw_step_noalloc(qw_plan_t plan, void* psi, int64_t nsteps, void* stream);
+
 /* The same for B (0..65535) fields of the plan's shape and precision back to
  * back in psi (DEVICE), instance b with its own mass m[b] (HOST, 0 <= m[b]
  * <= 1): its transition matrices are derived from the symbol exactly as

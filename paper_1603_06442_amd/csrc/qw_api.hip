@@ -1040,6 +1040,63 @@ qw_status qw_step(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
   return step_impl(p, stencil_geom(p), 1, psi, p->d_coef, nsteps, (hipStream_t)stream);
 }
 
+}  // extern "C"
+
+// The ping-pong buffer of qw_step_noalloc: a fixed array in device memory,
+// one per device (the runtime places it in every device's memory with the
+// library's code), kept until the process ends. Host code never uses its
+// name as an address: each device's address is looked up once, with that
+// device current, and kept in noalloc_ptr.
+static __device__ __align__(256) unsigned char scratch[QW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (null and a message on failure).
+void* noalloc_ptr(qw_status* err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *err = fail(QW_ERR_DEVICE, "hipGetDevice: %s (device %d)", hipGetErrorString(e), dev);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *err = fail(QW_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    g_noalloc_ptr[dev] = ptr;
+  }
+  return g_noalloc_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+qw_status qw_step_noalloc(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi) return fail(QW_ERR_INVALID, "psi is NULL");
+  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+  if (p->field_bytes > (size_t)QW_NOALLOC_SCRATCH_BYTES)
+    return fail(QW_ERR_UNSUPPORTED,
+                "qw_step_noalloc: the field has %zu bytes, the fixed buffer holds %zu",
+                p->field_bytes, (size_t)QW_NOALLOC_SCRATCH_BYTES);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(QW_ERR_INVALID, "qw_step_noalloc: the plan's device (%d) is not current (%d)",
+                p->device, dev);
+  if (nsteps == 0) return QW_OK;
+  void* buf = noalloc_ptr(&r);
+  if (!buf) return r;
+  return step_impl(p, stencil_geom(p), 1, psi, p->d_coef, nsteps, (hipStream_t)stream, buf);
+}
+
 qw_status qw_step_batched(qw_plan_t p, int B, void* psi, const double* m, int64_t nsteps,
                           void* stream) {
   qw_status r = check_plan(p);

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libqw.so")
 QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE = range(5)
 QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
-EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
+EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_noalloc",
+           "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables", "qw_newton_wigner",
            "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft", "qw_bcc_step", "qw_bcc_observables",
            "qw_kspace_drift",
@@ -80,6 +81,7 @@ def _load():
         "qw_destroy": [vp],
         "qw_step": [vp, vp, i64, vp],
         "qw_step_batched": [vp, cint, vp, ctypes.POINTER(dbl), i64, vp],
+        "qw_step_noalloc": [vp, vp, i64, vp],
         "qw_evolve_fft": [vp, vp, vp, i64, vp],
         "qw_evolve_fft_real": [vp, vp, vp, dbl, vp],
         "qw_evolve_fft_timed": [vp, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_float),
@@ -211,6 +213,13 @@ class Plan:
     def step(self, psi, nsteps, stream=None):
         """qw_step: nsteps position-space steps, in place."""
         _check(LIB.qw_step(self._h, self._field(psi, name="psi"), int(nsteps), _stream(stream)))
+        return psi
+
+    def step_noalloc(self, psi, nsteps, stream=None):
+        """qw_step_noalloc: qw_step with the library's fixed per-device
+        buffer (allocates nothing; fields up to 64 MiB)."""
+        _check(LIB.qw_step_noalloc(self._h, self._field(psi, name="psi"), int(nsteps),
+                                   _stream(stream)))
         return psi
 
     def step_batched(self, psi, m, nsteps, stream=None):
