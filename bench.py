@@ -52,12 +52,18 @@ def _source_hash(rel):
 
 
 def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle's Fourier evaluation (numpy DFT + per-q binary powering
-    of the symbol) on the 64^3 sub-lattice of the workload, timed on the host
-    and scaled by 64^3/256^3 to evolutions of the 256^3 lattice."""
+    """The FP64 oracle's Fourier evaluation as it stands (numpy DFT, per-q
+    binary powering of the symbol summed from the transition matrices,
+    inverse DFT; single-threaded numpy) on the workload's state on the 128^3
+    torus (width scaled by 128/256), at times from the 1..1e5 schedule,
+    timed on the host and scaled by (128/256)^3 to the 256^3 unit (the
+    powering, which dominates, is linear in the volume; the FFT's log factor
+    is left out). Beside it, as context: a forward + inverse FFT of the 256^3
+    four-component field in complex128 with scipy.fft on all host cores,
+    the least any host evaluation of one evolution must spend."""
     import numpy as np
     from oracle import fourier, states, walk
-    Ns = 64
+    Ns = 128
     table = walk.stencil_table(3, w["m"])
     psi = states.particle_state(3, Ns, w["m"], w["k0"], w["sigma"] * Ns / 256.0, [Ns // 2] * 3,
                                 w["c_plus"], w["c_minus"])
@@ -68,15 +74,32 @@ def cpu_baseline(w, budget_s=15.0):
         fourier.evolve_fourier(psi, table, times[(7 * done + 40) % len(times)])
         done += 1
         el = time.perf_counter() - t0
-        if el > budget_s or done >= 64:
+        if el > budget_s or done >= 16:
             break
-    rate64 = done / el
     scale = (Ns / 256.0) ** 3
-    return {"value": rate64 * scale, "unit": "evolutions/s", "cores": 1, "kind": "oracle",
-            "sample": "%d oracle Fourier evolutions (numpy FFT + binary powering, complex128, "
-                      "single thread) of the 64^3 sub-lattice at t from the 1..1e5 schedule in "
-                      "%.1f s, scaled by (64/256)^3 to the 256^3 unit" % (done, el),
-            "host_threads_available": os.cpu_count(), "cpu_model": _cpu_model()}
+    out = {"value": done / el * scale, "unit": "evolutions/s", "cores": 1, "kind": "oracle",
+           "sample": "%d oracle Fourier evolutions (numpy FFT + binary powering, complex128, "
+                     "single thread) of the workload's state on the 128^3 torus at t from the "
+                     "1..1e5 schedule in %.1f s, scaled by (128/256)^3 to the 256^3 unit"
+                     % (done, el),
+           "host_threads_available": os.cpu_count(), "cpu_model": _cpu_model()}
+    try:
+        import scipy.fft as sfft
+        nw = os.cpu_count() or 1
+        x = (np.random.default_rng(0).standard_normal((4, 256, 256, 256)) + 0j)
+        sfft.ifftn(x, axes=(1, 2, 3), workers=nw, overwrite_x=False)
+        t0 = time.perf_counter()
+        y = sfft.ifftn(x, axes=(1, 2, 3), workers=nw)
+        sfft.fftn(y, axes=(1, 2, 3), workers=nw, overwrite_x=True)
+        ft = time.perf_counter() - t0
+        out["context_fft_roundtrip_256_c128"] = {
+            "seconds": round(ft, 3), "workers": nw,
+            "what": "scipy.fft forward + inverse of the 4 x 256^3 complex128 field on all "
+                    "host cores (no apply): a lower bound for a host evolution"}
+        del x, y
+    except ImportError:
+        pass
+    return out
 
 
 def _cpu_model():
@@ -160,47 +183,82 @@ def stencil_line(qw):
             "batched_site_steps_per_s": round(B * N * steps / (b_ms * 1e-3), 1)}
 
 
+def _poisson(srv, reqs, gaps):
+    """Open-loop arrivals: request i is submitted at sum(gaps[:i+1]) seconds
+    (host clock); returns the results."""
+    tks = []
+    t0 = time.perf_counter()
+    due = 0.0
+    for r, gap in zip(reqs, gaps):
+        due += gap
+        while time.perf_counter() - t0 < due:
+            pass
+        tks.append(_submit(srv, r))
+    return [srv.wait(tk) for tk in tks]
+
+
+def _lat(res):
+    lat = [1e3 * x["latency_s"] for x in res]
+    return {"p50_latency_ms": round(_pct(lat, 0.50), 3), "p99_latency_ms": round(_pct(lat, 0.99), 3),
+            "mean_batch": round(sum(x["batch_size"] for x in res) / len(res), 2)}
+
+
 def serving(qw, budget_gib=16):
     """The mixed request stream (512 requests: 1D/2D/3D lattices, masses,
     states and times drawn per request) through the continuous-batching
-    server: saturation throughput of a burst, the same burst unbatched
-    (one request per batch, one stream), and open-loop Poisson arrivals at
-    70% of the saturation rate for p50/p99 latency."""
+    server, in three forms: batched complex64 with the batch chains replayed
+    from captured HIP graphs (the serving form), the same without graphs,
+    and the plain single-instance complex128 form (one request per batch, one
+    stream, no graphs). Each form: saturation throughput of a burst of the
+    512 requests (after a warm-up burst that builds and tunes the plans and
+    captures the graphs), then open-loop Poisson arrivals at 70% of the
+    serving form's saturation rate, the same arrival times for every form,
+    for p50/p99 latency (submit to completion signalled by the stream); the
+    plain form also at 70% of its own saturation rate. Last, the serving form
+    under a 256 MiB budget, which makes requests wait for memory."""
     from paper_1603_06442_amd import inputs
     reqs = inputs.workload(3)["requests"]
+    reqs128 = [dict(r, dtype="c128") for r in reqs]
     budget = budget_gib << 30
-    srv = qw.Server(budget, max_batch=32, nstreams=4)
-    one = qw.Server(budget, max_batch=1, nstreams=1)
+    forms = {"batched_c64_graphs": (reqs, 32, 4, True),
+             "batched_c64_direct": (reqs, 32, 4, False),
+             "single_c128_plain": (reqs128, 1, 1, False)}
+    out = {"requests": len(reqs), "budget_bytes": budget}
+    servers = {}
+    bad = 0
+    drift = 0.0
     try:
-        _burst(srv, reqs)  # plans for every shape, pool warm
-        _burst(one, reqs)
-        st0 = srv.stats()
-        el, res = _burst(srv, reqs)
-        st = srv.stats()
-        nb = st["batches"] - st0["batches"]
-        el1, _ = _burst(one, reqs)
-        sat = len(reqs) / el
-        rate = 0.7 * sat
-        rng = inputs.rng_for(3)
-        gaps = rng.exponential(1.0 / rate, len(reqs))
-        tks = []
-        t0 = time.perf_counter()
-        due = 0.0
-        for r, gap in zip(reqs, gaps):
-            due += gap
-            while time.perf_counter() - t0 < due:
-                pass
-            tks.append(_submit(srv, r))
-        pres = [srv.wait(tk) for tk in tks]
-        lat = [1e3 * x["latency_s"] for x in pres]
-        bad = sum(1 for x in res + pres if x["status"] != qw.QW_OK)
-        drift = max(abs(x["obs"]["norm2"] - 1.0) for x in res)
-        # The same burst in complex128, one request per batch (the plain
-        # single-instance FP64 form), and under a 256 MiB budget that forces
-        # requests to queue for memory.
-        reqs128 = [dict(r, dtype="c128") for r in reqs]
-        _burst(one, reqs128)
-        el128, res128 = _burst(one, reqs128)
+        sat = {}
+        for name, (rq, mb, ns, gr) in forms.items():
+            srv = qw.Server(budget, max_batch=mb, nstreams=ns, graphs=gr)
+            servers[name] = srv
+            _burst(srv, rq)  # plans, tuning, graphs
+            st0 = srv.stats()
+            el, res = _burst(srv, rq)
+            st = srv.stats()
+            nb = st["batches"] - st0["batches"]
+            sat[name] = len(rq) / el
+            bad += sum(1 for x in res if x["status"] != qw.QW_OK)
+            drift = max(drift, max(abs(x["obs"]["norm2"] - 1.0) for x in res))
+            out[name] = {"max_batch": mb, "streams": ns, "graphs": gr,
+                         "saturation_requests_per_s": round(sat[name], 1),
+                         "saturation_batches": nb,
+                         "saturation_mean_batch": round(len(rq) / max(1, nb), 2),
+                         "graph_launches": st["graph_launches"] - st0["graph_launches"],
+                         "graphs_captured": st["graphs_captured"],
+                         "peak_used_bytes": st["peak_used_bytes"]}
+        rate = 0.7 * sat["batched_c64_graphs"]
+        gaps = inputs.rng_for(3).exponential(1.0 / rate, len(reqs))
+        out["poisson_rate_per_s"] = round(rate, 1)
+        for name, (rq, mb, ns, gr) in forms.items():
+            res = _poisson(servers[name], rq, gaps)
+            bad += sum(1 for x in res if x["status"] != qw.QW_OK)
+            out[name]["poisson"] = _lat(res)
+        own = 0.7 * sat["single_c128_plain"]
+        gaps128 = inputs.rng_for(3).exponential(1.0 / own, len(reqs))
+        res = _poisson(servers["single_c128_plain"], reqs128, gaps128)
+        bad += sum(1 for x in res if x["status"] != qw.QW_OK)
+        out["single_c128_plain"]["poisson_own_rate"] = dict(_lat(res), rate_per_s=round(own, 1))
         small = qw.Server(256 << 20, max_batch=32, nstreams=4)
         try:
             _burst(small, reqs)
@@ -208,27 +266,21 @@ def serving(qw, budget_gib=16):
             sst = small.stats()
         finally:
             small.close()
-        bad += sum(1 for x in res128 + ress if x["status"] != qw.QW_OK)
-        return {
-            "requests": len(reqs), "budget_bytes": budget, "max_batch": 32, "streams": 4,
-            "saturation_requests_per_s": round(sat, 1),
-            "saturation_batches": nb,
-            "saturation_mean_batch": round(len(reqs) / max(1, nb), 2),
-            "unbatched_requests_per_s": round(len(reqs) / el1, 1),
-            "poisson_rate_per_s": round(rate, 1),
-            "p50_latency_ms": round(_pct(lat, 0.50), 3),
-            "p99_latency_ms": round(_pct(lat, 0.99), 3),
-            "mean_batch_poisson": round(sum(x["batch_size"] for x in pres) / len(pres), 2),
-            "peak_used_bytes": st["peak_used_bytes"], "failed": bad,
-            "max_norm_drift": drift,
-            "unbatched_c128_requests_per_s": round(len(reqs) / el128, 1),
-            "small_budget": {"budget_bytes": 256 << 20,
-                             "requests_per_s": round(len(reqs) / els, 1),
-                             "peak_used_bytes": sst["peak_used_bytes"]},
-        }
+        bad += sum(1 for x in ress if x["status"] != qw.QW_OK)
+        out["small_budget"] = {"budget_bytes": 256 << 20,
+                               "requests_per_s": round(len(reqs) / els, 1),
+                               "peak_used_bytes": sst["peak_used_bytes"],
+                               "slot_bytes": sst["slot_bytes"]}
+        out["failed"] = bad
+        out["max_norm_drift"] = drift
+        # the serving form's figures at the top level of the section
+        out["p50_latency_ms"] = out["batched_c64_graphs"]["poisson"]["p50_latency_ms"]
+        out["p99_latency_ms"] = out["batched_c64_graphs"]["poisson"]["p99_latency_ms"]
+        out["saturation_requests_per_s"] = out["batched_c64_graphs"]["saturation_requests_per_s"]
+        return out
     finally:
-        srv.close()
-        one.close()
+        for srv in servers.values():
+            srv.close()
 
 
 def main():
@@ -239,8 +291,6 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
-    ap.add_argument("--sweep", action="store_true",
-                    help="print the evolution time of every schedule and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -260,22 +310,6 @@ def main():
     plan.prepare_state(psi0, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
     psit = plan.empty()
     psis = psi0.clone()
-    if args.sweep:
-        out = {}
-        for slab in (0, 64):
-            for ce in (4, 8):
-                for cb in (64, 128, 256):
-                    for gw in ((1, 4) if ce == 4 else (1,)):
-                        plan.set_schedule(slab, ce, cb, gw)
-                        plan.evolve_fft(psi0, 1000, out=psit)
-                        tot = 0.0
-                        for r in range(5):
-                            _, ms = plan.evolve_fft_timed(psi0, 1000 + r, out=psit)
-                            tot += sum(ms)
-                        out["slab%d_e%d_b%d_g%d" % (slab, ce, cb, gw)] = [round(tot / 5, 4)] + [
-                            round(x, 4) for x in ms]
-        print(json.dumps({"sweep_ms_per_evolution": out}))
-        return
     tuned_ms = plan.autotune()
     schedule = plan.schedule()
     times = w["times"]
@@ -317,12 +351,23 @@ def main():
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(reps):
+
+    def stencil_pair_ms():
+        """Time of plan.step(psis, 2) on the launch stream (HIP events)."""
         plan.step(psis, 2)
-    e1.record(st)
-    e1.synchronize()
-    stencil_ms = e0.elapsed_time(e1) / (2 * reps)
+        e0.record(st)
+        for _ in range(reps):
+            plan.step(psis, 2)
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # The two steps of a timed step, one launch each (the default); the
+    # two-step kernel (psi read and written once per pair) beside it.
+    single_ms = stencil_pair_ms() / 2
+    qw.set_step_kernel(True)
+    pair_ms = stencil_pair_ms()
+    qw.set_step_kernel(False)
     e0.record(st)
     for _ in range(reps):
         plan.observables(psit, w["center"])
@@ -332,13 +377,15 @@ def main():
     evo_ms = sum(pass_ms)
 
     # Dominant kernel of a step: the one with the largest time per step among
-    # single kernels (the slab group is several kernels and is not a candidate).
-    cands = [("k_step3d_ring (stencil step)", stencil_ms, 2)]
+    # single kernels (the slab group is several kernels and is not a
+    # candidate). Algorithmic bytes per launch: 2 s b per site-step, i.e. one
+    # read and one write of the field per Fourier pass and per stencil step
+    # (two per launch of the two-step kernel).
+    cands = [("k_step3d_ring (stencil step)", single_ms, 2, 2 * field_bytes)]
     for n, v, k in zip(names, pass_ms, launches):
         if k == 1:
-            cands.append((n, v, 1))
-    dom_name, dom_ms, dom_launches = max(cands, key=lambda c: c[1] * c[2])
-    alg_bytes = 2 * field_bytes  # read the field once, write it once, per launch
+            cands.append((n, v, 1, 2 * field_bytes))
+    dom_name, dom_ms, dom_launches, alg_bytes = max(cands, key=lambda c: c[1] * c[2])
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -351,12 +398,11 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": dom_name, "kernel_ms": round(dom_ms, 4), "launches_per_step": dom_launches,
                 "algorithmic_bytes_per_launch": alg_bytes}
-    stencil_gbs = 2 * field_bytes / (stencil_ms * 1e-3) / 1e9
 
     line = {
         "metric": "lattice site-steps/s and FFT evolutions/s at 256^3 4-spinor; p99 request latency",
         "value": round(1e3 / ms_per_step, 3),
-        "unit": "evolutions/s",
+        "unit": "hot-path steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -364,16 +410,21 @@ def main():
         "config": {"workload": "bcc256_zb: 3D Dirac walk, 256^3 BCC primitive-cell torus, "
                                "4-spinor complex64, m=0.02, particle+antiparticle Gaussian "
                                "k0=(0.1,0.1,0.1) sigma=20, t over 64 log-spaced times in [1,1e5]",
-                   "step": "1 Fourier jump + 1 position/norm reduction + 2 stencil steps",
+                   "step": "one hot-path step = 1 Fourier jump psi_t = U^t psi_0 with the "
+                           "<x>/norm reduction fused into its last pass + 2 stencil steps of a "
+                           "second field; value = such steps per second (wall clock)",
                    "lattice": [N, N, N], "spinor": 4, "global_batch": 1},
         "fft_evolutions_per_s_kernels": round(1e3 / evo_ms, 2),
         "schedule": {"slab_planes": schedule[0], "contig_elems": schedule[1],
                      "contig_threads": schedule[2], "contig_groups": schedule[3],
                      "autotune_ms_per_evolution": round(tuned_ms, 4)},
         "fft_pass_ms": {n: round(v, 4) for n, v in zip(names, pass_ms)},
-        "stencil_site_steps_per_s": round(V / (stencil_ms * 1e-3), 1),
-        "stencil_ms_per_step": round(stencil_ms, 4),
-        "stencil_gbs": round(stencil_gbs, 1),
+        "stencil_site_steps_per_s": round(V / (single_ms * 1e-3), 1),
+        "stencil_ms_per_step": round(single_ms, 4),
+        "stencil_gbs": round(2 * field_bytes / (single_ms * 1e-3) / 1e9, 1),
+        "stencil_two_step_kernel": {"ms_per_launch": round(pair_ms, 4),
+                                    "site_steps_per_s": round(2 * V / (pair_ms * 1e-3), 1),
+                                    "used": False},
         "observables_ms": round(obs_ms, 4),
         "roofline": roofline,
         "last_obs": {"norm2": obs["norm2"], "mean_cart": obs["mean_cart"]},
@@ -382,15 +433,19 @@ def main():
     # phase) against the complex128 GPU path on the same state, at the
     # largest time of the schedule; norm drift of both.
     p128 = qw.Plan(3, N, w["m"], "c128")
+    p128.autotune()
     x128 = p128.empty()
     p128.prepare_state(x128, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
     tmax = times[-1]
     y128 = p128.evolve_fft(x128, tmax)
     y64 = plan.evolve_fft(psi0, tmax, out=psit)
+    _, ms128 = p128.evolve_fft_timed(x128, tmax, out=y128)
     diff = (y64.to(torch.complex128) - y128)
     rel = float(torch.linalg.vector_norm(diff) / torch.linalg.vector_norm(y128))
     line["accuracy"] = {
         "t": tmax, "c64_vs_c128_rel_l2": rel,
+        "c128_ms_per_evolution": round(sum(ms128), 4),
+        "c128_fused_pass_ms": round(ms128[2], 4) if len(ms128) == 5 else None,
         "norm_drift_c64": abs(plan.observables(y64, w["center"])["norm2"] - 1.0),
         "norm_drift_c128": abs(p128.observables(y128, w["center"])["norm2"] - 1.0)}
     del p128, x128, y128, diff
@@ -432,6 +487,7 @@ def main():
         "evolve_fft_observables": wall(lambda: plan.evolve_fft_observables(
             psi0, 1000, w["center"], out=psit)),
     }
+    line["workload_512"] = workload512_line(qw)
     line["cubic_supercell"] = cubic_line(qw, [N, N, N], w["m"], wall)
     line["weyl"] = weyl_line(qw, [N, N, N], wall)
     line["stencil_1d"] = stencil_line(qw)
@@ -440,6 +496,52 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line))
+
+
+def workload512_line(qw):
+    """The 512^3 workload (m = 0.1, particle state of width 40 cells about
+    the centre, k0 from its seed, t = 1e6): one Fourier jump in complex64
+    (FP32 transforms, FP64 phase; 4.3 GB per field) and one in complex128
+    (8.6 GB) of the same state, with the time of each (HIP events), the
+    complex64 result's relative L2 distance and infidelity 1 - |<psi64|psi128>|
+    against the complex128 one, and both norm drifts."""
+    import torch
+    from paper_1603_06442_amd import inputs
+    w = inputs.workload(4)
+    N, t = w["N"], w["t"]
+    out = {"lattice": [N, N, N], "t": t, "m": w["m"], "sigma": w["sigma"]}
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    res = {}
+    for dtype in ("c64", "c128"):
+        plan = qw.Plan(3, N, w["m"], dtype)
+        plan.autotune()
+        x = plan.empty()
+        plan.prepare_state(x, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
+        y = plan.empty()
+        plan.evolve_fft(x, t, out=y)
+        e0.record(st)
+        for _ in range(3):
+            plan.evolve_fft(x, t, out=y)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        drift = abs(plan.observables(y, w["center"])["norm2"] - 1.0)
+        out[dtype] = {"ms_per_evolution": round(ms, 4), "norm_drift": drift,
+                      "field_bytes": y.numel() * y.element_size()}
+        res[dtype] = (plan, y)
+        del x
+    p128, y128 = res["c128"]
+    y64 = res["c64"][1].to(torch.complex128)
+    rel = float(torch.linalg.vector_norm(y64 - y128) / torch.linalg.vector_norm(y128))
+    o = p128.observables(y64, w["center"], ref=y128)
+    fid = abs(o["overlap"]) / math.sqrt(o["norm2"] * o["ref_norm2"])
+    out["c64_vs_c128_rel_l2"] = rel
+    out["c64_infidelity"] = 1.0 - fid
+    del res, p128, y128, y64
+    torch.cuda.empty_cache()
+    return out
 
 
 def cubic_line(qw, N, m, wall):

@@ -315,6 +315,16 @@ qw_status qw_prepare_state(qw_plan_t plan, void* psi, const double* k0, double s
 qw_status qw_evolve_fft_timed(qw_plan_t plan, const void* psi0, void* psi_t, int64_t t,
                               void* stream, float* pass_ms, int* npass);
 
+/* Measurement and tuning of the position-space step (process-wide; not
+ * thread-safe against concurrent steps). two_step = 1 runs pairs of steps of
+ * the 3D Dirac walk in complex64 (planes of at least 16 x 32 sites, or
+ * 8 x 64 with tile_shape 1) as one launch that reads and writes the field
+ * once per pair (temporal blocking); 0 (the default) runs every step as its
+ * own launch, which measured faster. Both give the same bits. tile_shape: 0 = 16 x 32 output tiles, 1 = 8 x 64;
+ * chunk: planes of axis 0 per workgroup (0 = chosen from the lattice, else a
+ * power of two in [2, 256]). */
+qw_status qw_set_step_kernel(int two_step, int tile_shape, int chunk);
+
 /* Schedule of the Fourier evolution. slab_planes = 0 runs the n2 and fused
  * n3 passes over the whole field; slab_planes = k runs the n2 forward, fused
  * n3 and n2 inverse passes on slabs of k planes of n1 in turn, so that a slab
@@ -404,11 +414,27 @@ typedef struct {
   int64_t inflight_batches, max_inflight_batches;
   int64_t used_bytes, peak_used_bytes;
   int64_t laid_out_bytes, peak_laid_out_bytes;
+  int64_t graphs_captured;  /* batch chains captured into graphs */
+  int64_t graph_launches;   /* batches run by replaying a captured graph */
+  int64_t slot_bytes;       /* device bytes held by the captured graphs' buffers */
 } qw_server_info;
 
 /* Start a server on the current device. budget_bytes >= 1 MiB, max_batch in
  * [1, 4096], nstreams in [1, 16]. */
 qw_status qw_server_create(qw_server_t* out, size_t budget_bytes, int max_batch, int nstreams);
+/* Options, before the first submit. use_graphs (default 1): the chain of
+ * copies and kernels of a batch is captured into a HIP graph once per
+ * (shape, precision, batch size), against buffers kept with the graph, and
+ * later batches of that shape and size replay it in one launch with their
+ * own parameters (per-instance mass, state, time and centre live in device
+ * memory the graph reads); the chain of a (shape, precision, batch size)
+ * runs directly until it has been seen twice, and its second direct run
+ * records the capture beside it. At most max_graphs graphs are kept (least
+ * recently used dropped first; default 256), and their buffers at most the
+ * budget; replays give bit for bit the results of the direct chain.
+ * autotune (default 1): each shape's schedule is timed once, on a plan of
+ * its own whose scratch is released afterwards. */
+qw_status qw_server_configure(qw_server_t server, int use_graphs, int autotune, int max_graphs);
 /* Queue a request; never blocks on the device. QW_ERR_NOMEM if the request
  * alone exceeds the budget; argument errors as for qw_plan / qw_prepare_state. */
 qw_status qw_server_submit(qw_server_t server, const qw_request* req, int64_t* ticket);

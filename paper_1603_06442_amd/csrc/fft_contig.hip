@@ -506,17 +506,24 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
   const cx<T>* tw4 = (const cx<T>*)g.tw4;
   const int64_t N = g.N[0];
 
+  // With PIPE the next group's loads are issued into nx before the current
+  // group is transformed; without it each workgroup loads its group straight
+  // into v (nx would otherwise stay live through the whole transform).
   cx<T> nx[S][E];
   int64_t grp = blockIdx.x;
-  if (grp < ngroups) load_group<T, S, E, L>(nx, in, g, grp, P, p, t);
+  if constexpr (PIPE) {
+    if (grp < ngroups) load_group<T, S, E, L>(nx, in, g, grp, P, p, t);
+  }
   for (; grp < ngroups; grp += gridDim.x) {
     cx<T> v[S][E];
-#pragma unroll
-    for (int c = 0; c < S; ++c)
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[c][e] = nx[c][e];
     if constexpr (PIPE) {
+#pragma unroll
+      for (int c = 0; c < S; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[c][e] = nx[c][e];
       if (grp + gridDim.x < ngroups) load_group<T, S, E, L>(nx, in, g, grp + gridDim.x, P, p, t);
+    } else {
+      load_group<T, S, E, L>(v, in, g, grp, P, p, t);
     }
 
     const int64_t gp = grp * P + p;

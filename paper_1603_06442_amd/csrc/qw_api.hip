@@ -877,6 +877,9 @@ static qw_status plan_create(qw_plan_t* out, int dim, const int64_t* N, double m
   p->dbl = dtype == QW_C128;
   p->elem = p->dbl ? 16 : 8;
   p->field_bytes = (size_t)p->s * p->V * p->elem;
+  // Fused pass: four elements per thread for complex128 fields of d = 2, 3
+  // (eight spill registers there), eight otherwise until tuned.
+  if (p->dbl && dim >= 2) p->ce = 4;
   hipStream_t st = (hipStream_t)stream;
   (void)hipGetDevice(&p->device);
 
@@ -998,6 +1001,12 @@ static StencilGeom stencil_geom(qw_plan_t p) {
   return g;
 }
 
+// Pairs of steps in one launch of the two-step kernel only when switched on
+// (qw_set_step_kernel): measured slower than one launch per step at 256^3
+// (0.56 against 0.48 ms per pair), its rings of 128 KB of LDS leave one
+// workgroup of 8 waves per CU.
+static bool g_step2_off = true;
+
 // nsteps steps of B fields in place with device coefficients `coefs`: the
 // LDS-resident kernel where a 1D field fits (at most 4096 steps per launch),
 // otherwise one launch per step, ping-ponging with `buf` (B fields), or with
@@ -1021,8 +1030,17 @@ static qw_status step_impl(qw_plan_t p, const StencilGeom& g, int B, void* psi,
   }
   void* a = psi;
   void* b = buf;
-  for (int64_t k = 0; k < nsteps; ++k) {
-    HIP_TRY(launch_step(p->dbl, g, B, b, a, coefs, st));
+  // Pairs of steps in one launch where the two-step kernel applies (it reads
+  // and writes the field once per pair), a last odd step alone.
+  const bool two = step2_ok(p->dbl, g) && !g_step2_off;
+  for (int64_t k = 0; k < nsteps;) {
+    if (two && nsteps - k >= 2) {
+      HIP_TRY(launch_step2(p->dbl, g, B, b, a, coefs, st));
+      k += 2;
+    } else {
+      HIP_TRY(launch_step(p->dbl, g, B, b, a, coefs, st));
+      k += 1;
+    }
     void* t = a;
     a = b;
     b = t;
@@ -1175,6 +1193,16 @@ qw_status qw_evolve_fft_real(qw_plan_t p, const void* psi0, void* psi_t, double 
   return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
 }
 
+qw_status qw_set_step_kernel(int two_step, int tile_shape, int chunk) {
+  if (two_step != 0 && two_step != 1) return fail(QW_ERR_INVALID, "two_step must be 0 or 1");
+  if (tile_shape != 0 && tile_shape != 1) return fail(QW_ERR_INVALID, "tile_shape must be 0 or 1");
+  if (chunk != 0 && (chunk < 2 || chunk > 256 || (chunk & (chunk - 1))))
+    return fail(QW_ERR_INVALID, "chunk must be 0 or a power of two in [2, 256]");
+  g_step2_off = two_step == 0;
+  set_step2_config(tile_shape, chunk);
+  return QW_OK;
+}
+
 qw_status qw_set_schedule(qw_plan_t p, int slab_planes, int contig_elems, int contig_threads,
                           int contig_groups) {
   qw_status r = check_plan(p);
@@ -1225,7 +1253,10 @@ qw_status qw_autotune(qw_plan_t p, void* stream, double* best_ms) {
       }
     }
   }
+  // complex128 with eight elements per thread spills registers in the
+  // lockstep transform of four components (d = 2, 3): four only.
   const int ces[2] = {8, 4};
+  const bool only4 = p->dbl && p->dim >= 2;
   const int cbs[3] = {64, 128, 256};
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -1242,6 +1273,7 @@ qw_status qw_autotune(qw_plan_t p, void* stream, double* best_ms) {
       for (int cb : cbs)
         for (int gw : gws) {
       if (ce == 4 && p->dim < 2) continue;
+      if (ce == 8 && only4) continue;
       if (gw > 1 && !(p->dim == 3 && ce == 4)) continue;
       p->slab = sl;
       p->ce = ce;

@@ -205,6 +205,23 @@ __device__ __forceinline__ void fft_team(cx<T> (&v)[E], cx<T>* lds, int ls, int 
   Stages<T, L, E, SIGN, 1, PAD>::run(v, lds, ls, t, tw);
 }
 
+// Orders a team's LDS writes before its reads of what other lanes wrote, and
+// those reads before the next writes. A team of at most 64 threads lies in
+// one wavefront, whose LDS operations complete in order, so a wavefront-level
+// fence and barrier suffice and the other wavefronts of the workgroup run on
+// (a workgroup-wide barrier would stall them at every exchange); larger
+// teams take the workgroup barrier.
+template <int TT>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (TT <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // The same transform applied to S pencils in lockstep (the spinor components
 // of one lattice row): twiddles and LDS slots are computed once per stage and
 // shared, and each exchange is one write/barrier/read/barrier for all S.
@@ -252,12 +269,12 @@ struct StagesMulti {
       }
     }
     if constexpr (!LAST) {
-      __syncthreads();
+      team_sync<TT>();
 #pragma unroll
       for (int c = 0; c < S; ++c)
 #pragma unroll
         for (int e = 0; e < E; ++e) v[c][e] = lds[c * cstride + lds_swz<E>(t + TT * e)];
-      __syncthreads();
+      team_sync<TT>();
       StagesMulti<T, L, E, SIGN, NS * R, S>::run(v, lds, cstride, t, tw);
     }
   }

@@ -147,6 +147,14 @@ hipError_t launch_transpose(bool dbl, void* out, const void* in, int64_t planes,
 // the field precision (instance b uses coefs[b]). B <= 65535.
 hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
                        const void* coefs, hipStream_t st);
+// Two steps of B fields in one launch (3D Dirac walk, complex64, planes of at
+// least 16 x 32 sites): psi(t+2) into out from psi(t) in in (distinct).
+bool step2_ok(bool dbl, const StencilGeom& g);
+hipError_t launch_step2(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
+                        const void* coefs, hipStream_t st);
+// Measurement: tile shape (0: 16 x 32, 1: 8 x 64) and planes per workgroup
+// (0: chosen from the lattice) of the two-step kernel.
+void set_step2_config(int shape, int chunk);
 // One step of the cubic-supercell field (two sublattice arrays of 4 * V
 // entries each; out and in distinct).
 hipError_t launch_step_bcc(bool dbl, const StencilGeom& g, void* out, const void* in,

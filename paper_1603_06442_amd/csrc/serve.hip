@@ -104,6 +104,26 @@ struct Pool {
 
 struct Batch;
 
+// A captured batch chain: the device and pinned-host buffers of one batch of
+// B requests of one shape, and an instantiated HIP graph of everything that
+// batch enqueues (parameter upload, state preparation, evolution with the
+// fused reductions, result copies), recorded against those buffers. A batch
+// of the same shape and size that finds an idle slot writes its parameters
+// into the slot's pinned buffer and replays the graph: one launch instead of
+// the chain's copies and kernels.
+struct GraphSlot {
+  int dim;
+  int64_t N[3];
+  int dtype;
+  int B;
+  void* dmem = nullptr;
+  void* hmem = nullptr;
+  size_t dbytes = 0, hbytes = 0;
+  hipGraphExec_t exec = nullptr;  // null if the capture failed: the chain runs eagerly
+  bool busy = false;
+  uint64_t last_use = 0;
+};
+
 }  // namespace
 
 struct qw_server_s {
@@ -131,6 +151,19 @@ struct qw_server_s {
   int64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, batches = 0, peak_inflight = 0;
   std::string worker_error;
+  // Graph replay of batches (see GraphSlot): slots are touched by the
+  // worker thread only.
+  bool use_graphs = true;
+  bool autotune = true;
+  int max_slots = 256;
+  // Direct runs so far of each (shape, precision, batch size): a chain is
+  // captured on its second direct run, so batch sizes seen once cost no
+  // capture.
+  std::map<std::tuple<int, int64_t, int64_t, int64_t, int, int>, int> chain_runs;
+  std::vector<GraphSlot*> slots;
+  size_t slot_bytes = 0;  // device bytes held by the slots
+  uint64_t slot_clock = 0;
+  int64_t graphs_captured = 0, graph_launches = 0;
 };
 
 namespace {
@@ -215,6 +248,8 @@ struct Batch {
   void* hmem = nullptr;
   size_t footprint = 0;
   hipStream_t st = nullptr;
+  GraphSlot* slot = nullptr;  // buffers of a graph slot (else of the pool)
+  bool replayed = false;
   double t_launch = 0.0, t_done = 0.0;
   qw_status status = QW_OK;
 };
@@ -260,18 +295,11 @@ void on_stream_done(void* arg) {
   s->cv.notify_all();
 }
 
-// Runs with the lock NOT held. Enqueues everything for one batch.
-qw_status launch_batch(qw_server_s* s, Batch* b) {
+// Per-instance parameters of a batch into its pinned buffer H.
+void fill_params(Batch* b, char* H) {
   const int B = (int)b->reqs.size();
   qw_plan_t p = b->plan;
-  const StateGeom sg = state_geom(p);
-  const ObsGeom og = obs_geom(p);
   const Layout& Ly = b->lay;
-  const int64_t nbf = Ly.nbf;  // 0: separate reduction pass
-  HIP_TRY(s->pool.get_dev(Ly.dbytes, &b->dmem));
-  HIP_TRY(s->pool.get_host(Ly.hbytes, &b->hmem));
-  char* H = (char*)b->hmem;
-  char* D = (char*)b->dmem;
   StateInst* hs = (StateInst*)(H + Ly.h_sinst);
   InstParam* hi = (InstParam*)(H + Ly.h_inst);
   double* ho = (double*)(H + Ly.h_orig);
@@ -283,7 +311,19 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
     hi[k].t = (double)r.t;
     for (int i = 0; i < 3; ++i) ho[3 * k + i] = i < r.dim ? r.center[i] : 0.0;
   }
-  hipStream_t st = b->st;
+}
+
+// Everything one batch enqueues on st, against device buffer D and pinned
+// buffer H (already holding the parameters): one upload of the parameters,
+// the state preparation, the evolution with the reductions, the result
+// copies. Only copies and kernels: the same chain can be captured.
+qw_status enqueue_chain(Batch* b, char* D, char* H, hipStream_t st) {
+  const int B = (int)b->reqs.size();
+  qw_plan_t p = b->plan;
+  const StateGeom sg = state_geom(p);
+  const ObsGeom og = obs_geom(p);
+  const Layout& Ly = b->lay;
+  const int64_t nbf = Ly.nbf;  // 0: separate reduction pass
   // one upload of the three parameter arrays (contiguous in both layouts)
   HIP_TRY(hipMemcpyAsync(D + Ly.off_sinst, H + Ly.h_sinst, Ly.h_res - Ly.h_sinst,
                          hipMemcpyHostToDevice, st));
@@ -324,13 +364,129 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(H + Ly.h_norm, D + Ly.off_norm, sizeof(double) * 2 * B,
                          hipMemcpyDeviceToHost, st));
+  return QW_OK;
+}
+
+bool slot_matches(const GraphSlot* g, const Batch* b) {
+  return g->dim == b->key.dim && g->N[0] == b->key.N[0] && g->N[1] == b->key.N[1] &&
+         g->N[2] == b->key.N[2] && g->dtype == b->key.dtype && g->B == (int)b->reqs.size();
+}
+
+void drop_slot(qw_server_s* s, GraphSlot* g) {  // worker thread, slot idle
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  s->pool.put_dev(g->dbytes, g->dmem);
+  s->pool.put_host(g->hbytes, g->hmem);
+  s->slot_bytes -= g->dbytes;
+  s->slots.erase(std::find(s->slots.begin(), s->slots.end(), g));
+  delete g;
+}
+
+// A new slot for batch b (its buffers from the pool), after evicting the
+// least recently used idle slots while there are max_slots slots or the
+// slots hold more than the budget. Null if none can be made.
+GraphSlot* new_slot(qw_server_s* s, Batch* b) {
+  for (;;) {
+    const bool full = (int)s->slots.size() >= s->max_slots ||
+                      s->slot_bytes + b->lay.dbytes > s->budget;
+    if (!full) break;
+    GraphSlot* lru = nullptr;
+    for (GraphSlot* g : s->slots)
+      if (!g->busy && (!lru || g->last_use < lru->last_use)) lru = g;
+    if (!lru) return nullptr;
+    drop_slot(s, lru);
+  }
+  GraphSlot* g = new GraphSlot();
+  g->dim = b->key.dim;
+  for (int i = 0; i < 3; ++i) g->N[i] = b->key.N[i];
+  g->dtype = b->key.dtype;
+  g->B = (int)b->reqs.size();
+  g->dbytes = b->lay.dbytes;
+  g->hbytes = b->lay.hbytes;
+  if (s->pool.get_dev(g->dbytes, &g->dmem) != hipSuccess) {
+    delete g;
+    return nullptr;
+  }
+  if (s->pool.get_host(g->hbytes, &g->hmem) != hipSuccess) {
+    s->pool.put_dev(g->dbytes, g->dmem);
+    delete g;
+    return nullptr;
+  }
+  s->slots.push_back(g);
+  s->slot_bytes += g->dbytes;
+  return g;
+}
+
+// Runs with the lock NOT held, on the worker thread. With graphs, a batch
+// replays the graph of an idle slot of its shape and size; otherwise it
+// takes a new slot, runs the chain eagerly on its buffers and captures the
+// chain into the slot's graph (recorded on the set-up stream, not run) for
+// the batches after it. Without graphs (or without a slot) the buffers come
+// from the pool and the chain runs eagerly.
+qw_status launch_batch(qw_server_s* s, Batch* b) {
+  hipStream_t st = b->st;
+  GraphSlot* g = nullptr;
+  if (s->use_graphs) {
+    for (GraphSlot* c : s->slots)
+      if (!c->busy && c->exec && slot_matches(c, b)) {
+        g = c;
+        break;
+      }
+    if (g) {
+      g->busy = true;
+      g->last_use = ++s->slot_clock;
+      b->slot = g;
+      b->replayed = true;
+      fill_params(b, (char*)g->hmem);
+      HIP_TRY(hipGraphLaunch(g->exec, st));
+      ++s->graph_launches;
+      HIP_TRY(hipLaunchHostFunc(st, on_stream_done, b));
+      return QW_OK;
+    }
+    const auto ck = std::make_tuple(b->key.dim, b->key.N[0], b->key.N[1], b->key.N[2],
+                                    b->key.dtype, (int)b->reqs.size());
+    if (++s->chain_runs[ck] >= 2) g = new_slot(s, b);
+  }
+  char* D;
+  char* H;
+  if (g) {
+    g->busy = true;
+    g->last_use = ++s->slot_clock;
+    b->slot = g;
+    D = (char*)g->dmem;
+    H = (char*)g->hmem;
+  } else {
+    HIP_TRY(s->pool.get_dev(b->lay.dbytes, &b->dmem));
+    HIP_TRY(s->pool.get_host(b->lay.hbytes, &b->hmem));
+    D = (char*)b->dmem;
+    H = (char*)b->hmem;
+  }
+  fill_params(b, H);
+  qw_status r = enqueue_chain(b, D, H, st);
+  if (r != QW_OK) return r;
   HIP_TRY(hipLaunchHostFunc(st, on_stream_done, b));
+  if (g) {
+    // Capture the same chain against the slot's buffers for later batches.
+    hipStream_t cs = s->plan_stream;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const qw_status rc = enqueue_chain(b, D, H, cs);
+      const hipError_t e = hipStreamEndCapture(cs, &graph);
+      if (rc == QW_OK && e == hipSuccess && graph) {
+        if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+          g->exec = nullptr;
+        else
+          ++s->graphs_captured;
+      }
+      if (graph) (void)hipGraphDestroy(graph);
+    }
+    (void)hipGetLastError();
+  }
   return QW_OK;
 }
 
 void retire(qw_server_s* s, Batch* b) {  // lock held
   const int B = (int)b->reqs.size();
-  const char* H = (const char*)b->hmem;
+  const char* H = (const char*)(b->slot ? b->slot->hmem : b->hmem);
   const double* R = (const double*)(H + b->lay.h_res);
   const double* NR = (const double*)(H + b->lay.h_norm);
   for (int k = 0; k < B; ++k) {
@@ -353,6 +509,7 @@ void retire(qw_server_s* s, Batch* b) {  // lock held
     s->results[pd.ticket] = res;
     ++s->completed;
   }
+  if (b->slot) b->slot->busy = false;
   if (b->dmem) s->pool.put_dev(b->lay.dbytes, b->dmem);
   if (b->hmem) s->pool.put_host(b->lay.hbytes, b->hmem);
   s->used -= b->footprint;
@@ -365,9 +522,23 @@ void retire(qw_server_s* s, Batch* b) {  // lock held
 // Worker thread only, server lock NOT held: plan creation synchronises its
 // own stream, and a completion host function queued on a serving stream
 // takes the server lock, so no HIP call may be made while holding it.
+// With autotuning, the schedule (workgroup size and pencil groups of the
+// pass along the contiguous axis) is timed once per shape on a second plan of
+// that shape, whose scratch field is released with it, and copied over.
 qw_plan_t make_plan(qw_server_s* s, const Key& k) {
   qw_plan_t p = nullptr;
   if (qw_plan(&p, k.dim, k.N, 0.0, (qw_dtype)k.dtype, s->plan_stream) != QW_OK) return nullptr;
+  if (s->autotune) {
+    qw_plan_t tp = nullptr;
+    if (qw_plan(&tp, k.dim, k.N, 0.0, (qw_dtype)k.dtype, s->plan_stream) == QW_OK) {
+      int sl, ce, cb, gw;
+      if (qw_autotune(tp, s->plan_stream, nullptr) == QW_OK &&
+          qw_get_schedule(tp, &sl, &ce, &cb, &gw) == QW_OK)
+        (void)qw_set_schedule(p, sl, ce, cb, gw);
+      (void)hipStreamSynchronize(s->plan_stream);
+      delete tp;  // its work is done; qw_destroy would wait for the whole device
+    }
+  }
   return p;
 }
 
@@ -496,6 +667,17 @@ qw_status qw_server_create(qw_server_t* out, size_t budget_bytes, int max_batch,
   return QW_OK;
 }
 
+qw_status qw_server_configure(qw_server_t s, int use_graphs, int autotune, int max_graphs) {
+  if (!s) return fail(QW_ERR_INVALID, "server is NULL");
+  if (max_graphs < 1 || max_graphs > 4096) return fail(QW_ERR_INVALID, "max_graphs must lie in [1, 4096]");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->submitted > 0) return fail(QW_ERR_INVALID, "configure before the first submit");
+  s->use_graphs = use_graphs != 0;
+  s->autotune = autotune != 0;
+  s->max_slots = max_graphs;
+  return QW_OK;
+}
+
 qw_status qw_server_submit(qw_server_t s, const qw_request* req, int64_t* ticket) {
   if (!s || !ticket) return fail(QW_ERR_INVALID, "NULL argument");
   qw_status r = validate(req);
@@ -578,6 +760,9 @@ qw_status qw_server_stats(qw_server_t s, qw_server_info* out) {
   out->peak_used_bytes = (int64_t)s->peak_used;
   out->laid_out_bytes = (int64_t)s->laid_out;
   out->peak_laid_out_bytes = (int64_t)s->peak_laid_out;
+  out->graphs_captured = s->graphs_captured;
+  out->graph_launches = s->graph_launches;
+  out->slot_bytes = (int64_t)s->slot_bytes;
   return QW_OK;
 }
 
@@ -591,6 +776,11 @@ qw_status qw_server_destroy(qw_server_t s) {
   s->cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  for (GraphSlot* g : s->slots) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    delete g;  // buffers belong to the pool, released below
+  }
+  s->slots.clear();
   for (auto& kv : s->plans) qw_destroy(kv.second);
   s->pool.release();
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);

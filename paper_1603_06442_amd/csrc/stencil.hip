@@ -998,6 +998,51 @@ __device__ __forceinline__ void store_plane(const PlaneRegs<T>& R, cx<T>* ring, 
   }
 }
 
+// The eight neighbour terms and the mass term of one output site of the 3D
+// Dirac step, read from planes n1-1 (Pm), n1 (P0) and n1+1 (Pp) of a tile
+// staged in LDS with rows of W sites and components CS sites apart. Shared
+// by the one-step and the two-step plane-ring kernels, so that both form
+// every site with the same operations in the same order (same bits).
+template <typename T, bool SPARSE, int W, int CS>
+__device__ __forceinline__ void site3d_lds(const cx<T>* Pm, const cx<T>* P0, const cx<T>* Pp,
+                                           int site, const StencilCoef<T>& C, cx<T>& a0,
+                                           cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  a0 = mk((T)0, (T)0);
+  a1 = a0;
+  a2 = a0;
+  a3 = a0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int o1 = kOff3[k][0], o2 = kOff3[k][1], o3 = kOff3[k][2];
+    const cx<T>* P = (o1 > 0 ? Pp : (o1 < 0 ? Pm : P0)) + site + o2 * W + o3;
+    const cx<T> q0 = P[0], q1 = P[CS];
+    if constexpr (SPARSE) {
+      // rank-one blocks: offsets 0..3 feed output 0 and read component 3,
+      // offsets 4..7 feed output 1 and read component 2
+      if (k < 4) {
+        const cx<T> q3 = P[3 * CS];
+        a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+        a2 = fma_c(a2, C.lo[k][0][1], q3); a3 = fma_c(a3, C.lo[k][1][1], q3);
+      } else {
+        const cx<T> q2 = P[2 * CS];
+        a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+        a2 = fma_c(a2, C.lo[k][0][0], q2); a3 = fma_c(a3, C.lo[k][1][0], q2);
+      }
+    } else {
+      const cx<T> q2 = P[2 * CS], q3 = P[3 * CS];
+      a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
+      a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
+      a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
+      a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
+    }
+  }
+  const cx<T> mass = C.onsite[0][0];
+  a0 = fma_c(a0, mass, P0[site + 2 * CS]);
+  a1 = fma_c(a1, mass, P0[site + 3 * CS]);
+  a2 = fma_c(a2, mass, P0[site]);
+  a3 = fma_c(a3, mass, P0[site + CS]);
+}
+
 // NT: outputs are written with non-temporal stores (fields of at least
 // kNtBytes: 256^3 complex64 0.230 -> 0.214 ms per step; at 128^3 they would
 // cost 0.030 -> 0.035 ms, the next step's read hitting the cache).
@@ -1063,38 +1108,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step3d_ring(cx<T>* __restrict_
     for (int h = 0; h < 2; ++h) {
       const int i2 = 1 + r0 + h * (kTN2 / 2), i3 = 1 + c3;
       const int site = i2 * kH3 + i3;
-      constexpr int CS = kH2 * kH3;  // component stride in a ring plane
-      cx<T> a0 = mk((T)0, (T)0), a1 = a0, a2 = a0, a3 = a0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int o1 = kOff3[k][0], o2 = kOff3[k][1], o3 = kOff3[k][2];
-        const cx<T>* P = (o1 > 0 ? Pp : (o1 < 0 ? Pm : P0)) + site + o2 * kH3 + o3;
-        const cx<T> q0 = P[0], q1 = P[CS];
-        if constexpr (SPARSE) {
-          // rank-one blocks: offsets 0..3 feed output 0 and read component 3,
-          // offsets 4..7 feed output 1 and read component 2
-          if (k < 4) {
-            const cx<T> q3 = P[3 * CS];
-            a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
-            a2 = fma_c(a2, C.lo[k][0][1], q3); a3 = fma_c(a3, C.lo[k][1][1], q3);
-          } else {
-            const cx<T> q2 = P[2 * CS];
-            a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
-            a2 = fma_c(a2, C.lo[k][0][0], q2); a3 = fma_c(a3, C.lo[k][1][0], q2);
-          }
-        } else {
-          const cx<T> q2 = P[2 * CS], q3 = P[3 * CS];
-          a0 = fma_c(a0, C.up[k][0][0], q0); a0 = fma_c(a0, C.up[k][0][1], q1);
-          a1 = fma_c(a1, C.up[k][1][0], q0); a1 = fma_c(a1, C.up[k][1][1], q1);
-          a2 = fma_c(a2, C.lo[k][0][0], q2); a2 = fma_c(a2, C.lo[k][0][1], q3);
-          a3 = fma_c(a3, C.lo[k][1][0], q2); a3 = fma_c(a3, C.lo[k][1][1], q3);
-        }
-      }
-      const cx<T> mass = C.onsite[0][0];
-      a0 = fma_c(a0, mass, P0[site + 2 * CS]);
-      a1 = fma_c(a1, mass, P0[site + 3 * CS]);
-      a2 = fma_c(a2, mass, P0[site]);
-      a3 = fma_c(a3, mass, P0[site + CS]);
+      cx<T> a0, a1, a2, a3;
+      site3d_lds<T, SPARSE, kH3, kH2 * kH3>(Pm, P0, Pp, site, C, a0, a1, a2, a3);
       const int64_t n2 = b2 + r0 + h * (kTN2 / 2), n3 = b3 + c3;
       const int64_t idx = n0 * planeN + (n2 << lg3) + n3;
       if constexpr (NT) {
@@ -1154,6 +1169,262 @@ hipError_t launch_step3d_ring(const StencilGeom& g, int B, void* out, const void
                      (cx<float>*)out, (const cx<float>*)in, g, (const StencilCoef<float>*)coefs,
                      chunk, tiles2, tiles3, nchunks);
   return hipGetLastError();
+}
+
+// Two steps per launch (temporal blocking of the update rule of Sec. 2):
+// psi(t+2) from psi(t) with one read and one write of the field. A
+// workgroup owns a TN2 x TN3 tile of (n2, n3) outputs and a chunk of planes
+// of axis 0, and keeps two rings of three LDS planes: psi(t) on the tile with
+// a two-site halo, and psi(t+1) on the tile with a one-site halo. Per output
+// plane n1 it stages psi(t) plane n1+2 (loaded PF planes ahead into
+// registers), forms psi(t+1) plane n1+1 on its haloed region from the first
+// ring, and psi(t+2) plane n1 on the tile from the second. psi(t+1) on the
+// halo is formed by every tile that borders it (the price of reading psi once
+// for two steps), and each site is formed by site3d_lds, as in the one-step
+// kernel, so that one launch gives the same bits as two one-step launches.
+// One output site per thread; the first step's halo sites go to the first
+// threads, one more site each.
+template <int TN2, int TN3>
+struct Ring2 {
+  static constexpr int A2 = TN2 + 4, A3 = TN3 + 4, AS = A2 * A3;  // psi(t) region
+  static constexpr int B2 = TN2 + 2, B3 = TN3 + 2, BS = B2 * B3;  // psi(t+1) region
+  static constexpr int NT = TN2 * TN3;                            // threads
+  static constexpr int BH = BS - NT;                              // halo of the psi(t+1) region
+  static constexpr int AX = AS - NT;                              // second psi(t) site per thread
+  static constexpr size_t lds_bytes(size_t elem) { return 3 * 4 * (size_t)(AS + BS) * elem; }
+};
+
+// Halo site k < BH of the psi(t+1) region as (row, column): rows 0 and
+// B2 - 1 in full, then columns 0 and B3 - 1 of the rows between.
+template <int B2, int B3>
+__device__ __forceinline__ void ring2_halo(int k, int& r, int& c) {
+  if (k < 2 * B3) {
+    r = k < B3 ? 0 : B2 - 1;
+    c = k < B3 ? k : k - B3;
+  } else {
+    const int q = k - 2 * B3;
+    r = 1 + (q >> 1);
+    c = (q & 1) ? B3 - 1 : 0;
+  }
+}
+
+template <typename T, int TN2, int TN3, int PF, bool SPARSE, bool NT>
+__global__ __launch_bounds__(TN2 * TN3) void k_step3d_ring2(cx<T>* __restrict__ out_all,
+                                                           const cx<T>* __restrict__ in_all,
+                                                           StencilGeom g,
+                                                           const StencilCoef<T>* __restrict__ coefs,
+                                                           int chunk, int64_t tiles2,
+                                                           int64_t tiles3) {
+  using G = Ring2<TN2, TN3>;
+  static_assert(G::AX > 0 && G::AX <= G::NT && G::BH > 0 && G::BH <= G::NT, "tile shape");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* ringA = reinterpret_cast<cx<T>*>(smem_raw);  // [slot 3][component 4][AS]
+  cx<T>* ringB = ringA + 3 * 4 * G::AS;                // [slot 3][component 4][BS]
+  constexpr int PA = 4 * G::AS, PB = 4 * G::BS;
+  const int64_t V = g.V;
+  const cx<T>* __restrict__ in = in_all + (int64_t)blockIdx.y * 4 * V;
+  cx<T>* __restrict__ out = out_all + (int64_t)blockIdx.y * 4 * V;
+  const StencilCoef<T> C = coefs[blockIdx.y];
+  const int tid = threadIdx.x;
+  // XCD-aware numbering: each XCD steps a contiguous range of (chunk, tile).
+  const int64_t w = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t t3 = w % tiles3;
+  const int64_t t2 = (w / tiles3) % tiles2;
+  const int64_t ch = w / (tiles3 * tiles2);
+  const int64_t b2 = t2 * TN2, b3 = t3 * TN3;
+  const int64_t m1 = g.N[0] - 1, m2 = g.N[1] - 1, m3 = g.N[2] - 1;
+  const int lg3 = g.lg[2];
+  const int64_t planeN = g.N[1] * g.N[2];
+  const int64_t a = ch * chunk;
+
+  // psi(t) sites this thread loads: region sites tid and NT + tid (the
+  // latter for tid < AX). Threads without a second site load the first one
+  // twice (in bounds, never staged): unconditional loads keep the wait
+  // counts exact.
+  const bool twoA = tid < G::AX;
+  int sA[2];
+  int64_t offA[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int sidx = (h == 0 || twoA) ? tid + h * G::NT : tid;
+    const int r = sidx / G::A3, c = sidx % G::A3;
+    sA[h] = sidx;
+    offA[h] = (((b2 - 2 + r) & m2) << lg3) | ((b3 - 2 + c) & m3);
+  }
+  cx<T> ld[PF][2][4];
+  auto fetch = [&](cx<T> (&dst)[2][4], int64_t p) __attribute__((always_inline)) {
+    const int64_t po = (p & m1) * planeN;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dst[h][c] = in[c * V + po + offA[h]];
+  };
+  auto stage = [&](const cx<T> (&src)[2][4], int slot) __attribute__((always_inline)) {
+    cx<T>* P = ringA + slot * PA;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) P[c * G::AS + sA[0]] = src[0][c];
+    if (twoA) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) P[c * G::AS + sA[1]] = src[1][c];
+    }
+  };
+  // psi(t+1) sites this thread forms: the tile site of the thread, and for
+  // tid < BH one halo site. Index in region B and of the same site in A.
+  const bool twoB = tid < G::BH;
+  int sB[2], sBA[2];
+  {
+    const int r = tid / TN3 + 1, c = tid % TN3 + 1;
+    sB[0] = r * G::B3 + c;
+    sBA[0] = (r + 1) * G::A3 + (c + 1);
+    int hr = 0, hc = 0;
+    ring2_halo<G::B2, G::B3>(twoB ? tid : 0, hr, hc);
+    sB[1] = hr * G::B3 + hc;
+    sBA[1] = (hr + 1) * G::A3 + (hc + 1);
+  }
+  auto first = [&](int sm, int s0, int sp, int slotB) __attribute__((always_inline)) {
+    const cx<T>* Pm = ringA + sm * PA;
+    const cx<T>* P0 = ringA + s0 * PA;
+    const cx<T>* Pp = ringA + sp * PA;
+    cx<T>* Q = ringB + slotB * PB;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 0 || twoB) {
+        cx<T> a0, a1, a2, a3;
+        site3d_lds<T, SPARSE, G::A3, G::AS>(Pm, P0, Pp, sBA[h], C, a0, a1, a2, a3);
+        Q[sB[h]] = a0;
+        Q[G::BS + sB[h]] = a1;
+        Q[2 * G::BS + sB[h]] = a2;
+        Q[3 * G::BS + sB[h]] = a3;
+      }
+    }
+  };
+  const int64_t offO = ((b2 + tid / TN3) << lg3) | (b3 + tid % TN3);
+  auto second = [&](int sm, int s0, int sp, int64_t p) __attribute__((always_inline)) {
+    cx<T> a0, a1, a2, a3;
+    site3d_lds<T, SPARSE, G::B3, G::BS>(ringB + sm * PB, ringB + s0 * PB, ringB + sp * PB, sB[0],
+                                        C, a0, a1, a2, a3);
+    const int64_t idx = (p & m1) * planeN + offO;
+    if constexpr (NT) {
+      store_nt(&out[idx], a0);
+      store_nt(&out[V + idx], a1);
+      store_nt(&out[2 * V + idx], a2);
+      store_nt(&out[3 * V + idx], a3);
+    } else {
+      out[idx] = a0;
+      out[V + idx] = a1;
+      out[2 * V + idx] = a2;
+      out[3 * V + idx] = a3;
+    }
+  };
+
+  // Ring slots: psi(t) plane p in slot (p - a + 2) mod 3, psi(t+1) plane p in
+  // slot (p - a + 1) mod 3. Prologue: psi(t+1) planes a-1 and a.
+  fetch(ld[0], a - 2);
+  stage(ld[0], 0);
+  fetch(ld[0], a - 1);
+  stage(ld[0], 1);
+  fetch(ld[0], a);
+  stage(ld[0], 2);
+  fetch(ld[0], a + 1);
+  __syncthreads();
+  first(0, 1, 2, 0);  // psi(t+1) plane a - 1
+  __syncthreads();
+  stage(ld[0], 0);  // psi(t) plane a + 1 replaces plane a - 2
+#pragma unroll
+  for (int u = 0; u < PF; ++u) fetch(ld[u], a + 2 + u);
+  __syncthreads();
+  first(1, 2, 0, 1);  // psi(t+1) plane a
+  __syncthreads();
+
+  // Output plane p = a + i: stage psi(t) plane p+2 (register set i mod PF,
+  // refilled with plane p+2+PF), psi(t+1) plane p+1, psi(t+2) plane p. The
+  // barrier after the psi(t+1) plane also orders the next stage after this
+  // plane's reads of ring A; the barrier after the stage orders the psi(t+1)
+  // writes after the previous plane's reads of ring B.
+  int a0s = 2, a1s = 0, a2s = 1;  // ring A slots of psi(t) planes p, p+1, p+2
+  int bm = 0, b0 = 1, bp = 2;     // ring B slots of psi(t+1) planes p-1, p, p+1
+  auto plane = [&](int64_t p, int u, bool refill) __attribute__((always_inline)) {
+    stage(ld[u], a2s);
+    if (refill) fetch(ld[u], p + 2 + PF);
+    __syncthreads();
+    first(a0s, a1s, a2s, bp);
+    __syncthreads();
+    second(bm, b0, bp, p);
+    const int ta = a0s;
+    a0s = a1s;
+    a1s = a2s;
+    a2s = ta;
+    const int tb = bm;
+    bm = b0;
+    b0 = bp;
+    bp = tb;
+  };
+  // chunk is a multiple of PF: all but the last PF planes refill their set.
+  for (int64_t p = a; p < a + chunk - PF; p += PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) plane(p + u, u, true);
+  }
+#pragma unroll
+  for (int u = 0; u < PF; ++u) plane(a + chunk - PF + u, u, false);
+}
+
+bool step3d_ring2_ok(const StencilGeom& g) {
+  return g.dim == 3 && !g.weyl && g.N[1] >= 16 && g.N[2] >= 32 && g.N[0] >= 2;
+}
+
+// Tile shape of the two-step kernel (16 x 32: 612 first-step sites per 512
+// outputs; 8 x 64: 660).
+static int g_ring2_shape = 0;  // 0: 16 x 32, 1: 8 x 64
+static int g_ring2_chunk = 0;  // planes per workgroup; 0: from the lattice
+
+template <int TN2, int TN3, int PF>
+static hipError_t launch_ring2_t(const StencilGeom& g, int B, void* out, const void* in,
+                                 const void* coefs, hipStream_t st) {
+  using G = Ring2<TN2, TN3>;
+  if (g.N[1] < TN2 || g.N[2] < TN3) return hipErrorInvalidValue;
+  const int64_t tiles2 = g.N[1] / TN2, tiles3 = g.N[2] / TN3;
+  // Planes per workgroup: 32, fewer while there would be under 2 workgroups
+  // per CU (256 CUs) per instance, at least PF, at most N1.
+  int chunk = 32;
+  if (g_ring2_chunk > 0) {
+    chunk = g_ring2_chunk;
+  } else {
+    while (chunk > 2 * PF && tiles2 * tiles3 * (g.N[0] / chunk) < 512) chunk >>= 1;
+  }
+  if (chunk > g.N[0]) chunk = (int)g.N[0];
+  if (chunk < PF || chunk % PF || g.N[0] % chunk) return hipErrorInvalidValue;
+  const int64_t nblk = tiles2 * tiles3 * (g.N[0] / chunk);
+  if (nblk > 0x7fffffffLL || B < 1 || B > 65535) return hipErrorInvalidValue;
+  const size_t lds = G::lds_bytes(sizeof(cx<float>));
+  const bool nt = (size_t)B * 4 * (size_t)g.V * sizeof(cx<float>) >= kNtBytes;
+  auto kern = g.sparse3 ? (nt ? k_step3d_ring2<float, TN2, TN3, PF, true, true>
+                              : k_step3d_ring2<float, TN2, TN3, PF, true, false>)
+                        : (nt ? k_step3d_ring2<float, TN2, TN3, PF, false, true>
+                              : k_step3d_ring2<float, TN2, TN3, PF, false, false>);
+  hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk, (unsigned)B), dim3(G::NT), lds, st,
+                     (cx<float>*)out, (const cx<float>*)in, g, (const StencilCoef<float>*)coefs,
+                     chunk, tiles2, tiles3);
+  return hipGetLastError();
+}
+
+bool step2_ok(bool dbl, const StencilGeom& g) {
+  if (dbl || !step3d_ring2_ok(g)) return false;
+  return g_ring2_shape == 0 ? (g.N[1] >= 16 && g.N[2] >= 32) : (g.N[1] >= 8 && g.N[2] >= 64);
+}
+
+hipError_t launch_step2(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
+                        const void* coefs, hipStream_t st) {
+  if (!step2_ok(dbl, g)) return hipErrorInvalidValue;
+  if (g_ring2_shape == 0) return launch_ring2_t<16, 32, 2>(g, B, out, in, coefs, st);
+  return launch_ring2_t<8, 64, 2>(g, B, out, in, coefs, st);
+}
+
+void set_step2_config(int shape, int chunk) {
+  g_ring2_shape = shape;
+  g_ring2_chunk = chunk;
 }
 
 hipError_t launch_step(bool dbl, const StencilGeom& g, int B, void* out, const void* in,

@@ -26,8 +26,9 @@ EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_noalloc"
            "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft", "qw_bcc_step", "qw_bcc_observables",
            "qw_kspace_drift",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
-           "qw_set_schedule", "qw_get_schedule", "qw_autotune", "qw_last_error", "qw_version",
-           "qw_server_create", "qw_server_submit", "qw_server_poll", "qw_server_wait",
+           "qw_set_schedule", "qw_get_schedule", "qw_set_step_kernel", "qw_autotune",
+           "qw_last_error", "qw_version",
+           "qw_server_create", "qw_server_configure", "qw_server_submit", "qw_server_poll", "qw_server_wait",
            "qw_server_hold", "qw_server_stats", "qw_server_destroy")
 
 
@@ -66,7 +67,7 @@ class QwServerInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "submitted", "completed", "batches", "queued", "inflight_batches",
         "max_inflight_batches", "used_bytes", "peak_used_bytes", "laid_out_bytes",
-        "peak_laid_out_bytes")]
+        "peak_laid_out_bytes", "graphs_captured", "graph_launches", "slot_bytes")]
 
 
 def _load():
@@ -105,10 +106,12 @@ def _load():
                                  cint, dbl, vp],
         "qw_dispersion_taylor": [cint, dbl, ctypes.POINTER(dbl), cint, ctypes.POINTER(dbl)],
         "qw_set_schedule": [vp, cint, cint, cint, cint],
+        "qw_set_step_kernel": [cint, cint, cint],
         "qw_get_schedule": [vp, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint),
                             ctypes.POINTER(cint)],
         "qw_autotune": [vp, vp, ctypes.POINTER(dbl)],
         "qw_server_create": [ctypes.POINTER(vp), ctypes.c_size_t, cint, cint],
+        "qw_server_configure": [vp, cint, cint, cint],
         "qw_server_submit": [vp, ctypes.POINTER(QwRequest), ctypes.POINTER(i64)],
         "qw_server_poll": [vp, i64, ctypes.POINTER(QwResult), ctypes.POINTER(cint)],
         "qw_server_wait": [vp, i64, ctypes.POINTER(QwResult)],
@@ -407,6 +410,13 @@ def dispersion_taylor(dim, m, k0, order):
     return list(out)
 
 
+def set_step_kernel(two_step=False, tile_shape=0, chunk=0):
+    """qw_set_step_kernel (measurement): pairs of 3D complex64 steps in one
+    launch (two_step) or one launch per step (the default); tile shape
+    0 = 16 x 32, 1 = 8 x 64; planes per workgroup (0 = automatic)."""
+    _check(LIB.qw_set_step_kernel(1 if two_step else 0, int(tile_shape), int(chunk)))
+
+
 def version():
     return LIB.qw_version().decode()
 
@@ -421,10 +431,18 @@ class Server:
     particle states evolved to their own time with their own mass; results
     are the reductions of psi(t) about the request's centre."""
 
-    def __init__(self, budget_bytes, max_batch=16, nstreams=2):
+    def __init__(self, budget_bytes, max_batch=16, nstreams=2, graphs=True, autotune=True,
+                 max_graphs=256):
         self._h = ctypes.c_void_p()
         _check(LIB.qw_server_create(ctypes.byref(self._h), int(budget_bytes), int(max_batch),
                                     int(nstreams)))
+        try:
+            _check(LIB.qw_server_configure(self._h, 1 if graphs else 0, 1 if autotune else 0,
+                                           int(max_graphs)))
+        except QwError:
+            LIB.qw_server_destroy(self._h)
+            self._h = None
+            raise
         self._dims = {}
 
     def submit(self, dim, N, m, k0, sigma, center, c_plus, c_minus, t, dtype="c64"):

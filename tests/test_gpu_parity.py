@@ -76,6 +76,64 @@ def test_step_matches_oracle(qw, d, shape, m, dtype):
     assert ob.rel_l2(to_np(x), ref) < tol_step(dtype, 7)
 
 
+@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("shape", [(2, 16, 64), (4, 16, 32), (16, 16, 64), (8, 32, 128),
+                                   (64, 16, 32), (4, 8, 64)])
+@pytest.mark.parametrize("m", [0.0, 0.3, 1.0])
+def test_two_step_kernel_matches_oracle_and_single_steps(qw, shape, m, tile):
+    """Pairs of complex64 3D steps run as one launch (both rings in LDS):
+    against the oracle over 2 and 5 steps (a pair, two pairs and a single
+    step), and bitwise equal to the same steps one launch each. Shapes whose
+    planes are one tile (16 x 32, or 8 x 64) so that every halo wraps onto
+    the tile itself, N1 = 2 (the whole axis in one chunk), several tiles and
+    chunks; both tile shapes."""
+    if (tile == 1 and (shape[1] < 8 or shape[2] < 64) or
+            tile == 0 and (shape[1] < 16 or shape[2] < 32)):
+        pytest.skip("plane smaller than the tile")
+    psi0 = rand_field(3, shape, 33)
+    plan = qw.Plan(3, list(shape), m, "c64")
+    try:
+        qw.set_step_kernel(True, tile)
+        for n in (2, 5):
+            x = to_dev(psi0, plan)
+            plan.step(x, n)
+            ref = stepper.evolve_steps(psi0, table(3, m), n)
+            assert ob.rel_l2(to_np(x), ref) < tol_step("c64", n), n
+            qw.set_step_kernel(False)
+            y = to_dev(psi0, plan)
+            plan.step(y, n)
+            torch.cuda.synchronize()
+            assert torch.equal(x, y), n
+            qw.set_step_kernel(True, tile)
+    finally:
+        qw.set_step_kernel(False, 0, 0)
+
+
+def test_two_step_kernel_batched_and_chunks(qw):
+    """Batched pairs of steps with per-instance masses, and every number of
+    planes per workgroup, against one launch per step (bitwise) and the
+    oracle."""
+    shape = (32, 16, 64)
+    ms = [0.0, 0.05, 0.3]
+    psis = [rand_field(3, shape, 60 + b) for b in range(3)]
+    plan = qw.Plan(3, list(shape), 0.1, "c64")
+    try:
+        qw.set_step_kernel(False)
+        want = torch.stack([to_dev(p, plan) for p in psis]).contiguous()
+        plan.step_batched(want, ms, 4)
+        for chunk in (2, 4, 8, 16, 32):
+            qw.set_step_kernel(True, 0, chunk)
+            x = torch.stack([to_dev(p, plan) for p in psis]).contiguous()
+            plan.step_batched(x, ms, 4)
+            torch.cuda.synchronize()
+            assert torch.equal(x, want), chunk
+    finally:
+        qw.set_step_kernel(False, 0, 0)
+    for b in range(3):
+        ref = stepper.evolve_steps(psis[b], table(3, ms[b]), 4)
+        assert ob.rel_l2(to_np(want[b]), ref) < tol_step("c64", 4)
+
+
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("shape", [(8, 8, 64), (4, 16, 128), (32, 8, 64)])
 @pytest.mark.parametrize("m", [0.0, 0.3])

@@ -167,3 +167,70 @@ def test_requests_are_collected_once_and_bad_requests_rejected(qw):
         assert res["status"] == qw.QW_OK
     finally:
         srv.close()
+
+
+def _mixed_requests(n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        d, N = [(3, 16), (3, 32), (1, 1024), (2, 64), (1, 8192)][i % 5]
+        reqs.append(req(d, N, float(rng.uniform(0, 0.3)), list(rng.uniform(-0.3, 0.3, d)),
+                        float(rng.uniform(2.0, 4.0)), int(rng.integers(-5000, 5000)),
+                        dtype="c64" if i % 3 else "c128"))
+    return reqs
+
+
+def test_graph_replays_equal_the_direct_chain(qw):
+    """With graphs, a (shape, precision, size) runs its chain directly until
+    its second run, which captures it; later batches replay the capture with
+    their own parameters. One request per batch, so every later request of a
+    shape is a replay: 30 requests over five shapes (the 1D four-step among
+    them) in both precisions, one at a time with eager GPU work and a
+    synchronisation between them, then all at once on two streams. Every
+    result is bitwise that of a server without graphs."""
+    reqs = _mixed_requests(30, 4321)
+    eager = qw.Server(1 << 30, max_batch=1, nstreams=1, graphs=False)
+    try:
+        want = [run_all(eager, [r], hold=False)[0] for r in reqs]
+        st_e = eager.stats()
+    finally:
+        eager.close()
+    assert st_e["graphs_captured"] == 0 and st_e["graph_launches"] == 0
+    srv = qw.Server(1 << 30, max_batch=1, nstreams=2, graphs=True)
+    try:
+        one = []
+        for r in reqs:
+            one.append(run_all(srv, [r], hold=False)[0])
+            x = torch.randn(4096, device="cuda")
+            (x * 2.0).sum().item()
+            torch.cuda.synchronize()
+        burst = run_all(srv, reqs)
+        st = srv.stats()
+    finally:
+        srv.close()
+    shapes = {(r["dim"], r["N"], r["dtype"]) for r in reqs}
+    # one at a time: each shape runs directly twice (capturing on the
+    # second run), then replays; in the burst the first request of each shape
+    # finds its graph idle (others may capture a second graph while it is busy)
+    assert st["graphs_captured"] >= len(shapes)
+    assert st["graph_launches"] >= len(reqs) - len(shapes)
+    for w, a, b in zip(want, one, burst):
+        assert w["status"] == a["status"] == b["status"] == qw.QW_OK
+        assert a["obs"] == w["obs"] and b["obs"] == w["obs"]  # bitwise
+        assert a["sector_norm2"] == w["sector_norm2"] == b["sector_norm2"]
+
+
+def test_graph_slots_stay_within_their_limits(qw):
+    """At most max_graphs captured graphs are kept, the least recently used
+    dropped first, and their buffers stay within the budget."""
+    reqs = _mixed_requests(40, 99)
+    srv = qw.Server(64 * MiB, max_batch=1, nstreams=1, graphs=True, max_graphs=2)
+    try:
+        got = [run_all(srv, [r], hold=False)[0] for r in reqs]
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert all(g["status"] == qw.QW_OK for g in got)
+    assert 0 < st["slot_bytes"] <= 64 * MiB
+    # ten (shape, precision) pairs in turn through two graphs: each recaptured
+    assert st["graphs_captured"] >= 10
