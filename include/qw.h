@@ -417,6 +417,7 @@ typedef struct {
   int64_t graphs_captured;  /* batch chains captured into graphs */
   int64_t graph_launches;   /* batches run by replaying a captured graph */
   int64_t slot_bytes;       /* device bytes held by the captured graphs' buffers */
+  int64_t launch_host_ns;   /* host time the server spent enqueuing batches */
 } qw_server_info;
 
 /* Start a server on the current device. budget_bytes >= 1 MiB, max_batch in

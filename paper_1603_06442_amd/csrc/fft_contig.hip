@@ -506,6 +506,14 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
   const cx<T>* tw4 = (const cx<T>*)g.tw4;
   const int64_t N = g.N[0];
 
+  // complex64 transforms of four elements per thread (at most 16 twiddles
+  // per thread) keep their twiddles in registers for every pencil group and
+  // both directions.
+  constexpr int TWC = team_twiddle_count<L, E>();
+  constexpr bool kTwCache = sizeof(T) == 4 && E == 4 && TWC > 0 && TWC <= 16;
+  cx<T> twc[kTwCache ? TWC : 1];
+  if constexpr (kTwCache) load_team_twiddles<T, L, E>(twc, t, tw);
+
   // With PIPE the next group's loads are issued into nx before the current
   // group is transformed; without it each workgroup loads its group straight
   // into v (nx would otherwise stay live through the whole transform).
@@ -543,7 +551,10 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
           for (int c = 0; c < S; ++c) v[c][e] = cmulc(v[c][e], w);  // times e^{+2 pi i n2 k1 / N}
         }
       }
-      fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
+      if constexpr (kTwCache)
+        fft_team_multi_c<T, L, E, 1, S>(v, my, LP, t, twc);
+      else
+        fft_team_multi<T, L, E, 1, S>(v, my, LP, t, tw);
     }
     if constexpr (MODE == MODE_WEYL || MODE == MODE_WEYL_TAB) {
       const InstParam ip = g.single;
@@ -657,7 +668,10 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
       }
     }
     if constexpr (MODE != MODE_FWD && MODE != MODE_BCC_FWD) {
-      fft_team_multi<T, L, E, -1, S>(v, my, LP, t, tw);
+      if constexpr (kTwCache)
+        fft_team_multi_c<T, L, E, -1, S>(v, my, LP, t, twc);
+      else
+        fft_team_multi<T, L, E, -1, S>(v, my, LP, t, tw);
       if (DIM == 1 && g.fourstep) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -683,10 +697,10 @@ static hipError_t run_contig_k(cx<T>* out, const cx<T>* in, const PassGeom& g, c
 template <typename T, int L, int DIM, int MODE, int EE>
 static hipError_t run_contig(cx<T>* out, const cx<T>* in, const PassGeom& g, const cx<T>* tw,
                              hipStream_t st) {
-  // The prefetching variant is built for the 3D evolution with four elements
-  // per thread only (the autotuner's candidate); elsewhere one group per
-  // workgroup.
-  constexpr bool kPipe = DIM == 3 && EE == 4 && MODE == MODE_EVOLVE_TAB;
+  // The prefetching variant is built for the complex64 3D evolution with
+  // four elements per thread only (the autotuner's candidate; in complex128
+  // it spills registers); elsewhere one group per workgroup.
+  constexpr bool kPipe = DIM == 3 && EE == 4 && MODE == MODE_EVOLVE_TAB && sizeof(T) == 4;
   if constexpr (kPipe) {
     if (g.groups_per_wg > 1) return run_contig_k<T, L, DIM, MODE, EE, true>(out, in, g, tw, st);
   }
@@ -813,8 +827,14 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
     case MODE_EVOLVE:
       return e4i ? dispatch_dim<T, MODE_EVOLVE, 4>(L, out, in, g, tw, st)
                  : dispatch_dim<T, MODE_EVOLVE, 8>(L, out, in, g, tw, st);
-    case MODE_FWD: return dispatch_dim<T, MODE_FWD, 8>(L, out, in, g, tw, st);
-    case MODE_INV: return dispatch_dim<T, MODE_INV, 8>(L, out, in, g, tw, st);
+    // complex128 transforms alone take four elements per thread wherever
+    // the team fits a workgroup (eight spill registers at L = 512).
+    case MODE_FWD:
+      return (sizeof(T) == 8 && e4i) ? dispatch_dim<T, MODE_FWD, 4>(L, out, in, g, tw, st)
+                                     : dispatch_dim<T, MODE_FWD, 8>(L, out, in, g, tw, st);
+    case MODE_INV:
+      return (sizeof(T) == 8 && e4i) ? dispatch_dim<T, MODE_INV, 4>(L, out, in, g, tw, st)
+                                     : dispatch_dim<T, MODE_INV, 8>(L, out, in, g, tw, st);
     case MODE_APPLY_INV:
       return e4i ? dispatch_dim<T, MODE_APPLY_INV, 4>(L, out, in, g, tw, st)
                  : dispatch_dim<T, MODE_APPLY_INV, 8>(L, out, in, g, tw, st);

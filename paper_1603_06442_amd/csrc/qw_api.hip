@@ -1265,7 +1265,9 @@ qw_status qw_autotune(qw_plan_t p, void* stream, double* best_ms) {
   ip.m = p->m;
   ip.n = p->n;
   ip.t = 12345;
-  const int gws[2] = {1, 4};
+  // 16 groups per workgroup: about one round of resident workgroups per CU
+  // at 256^3, each walking its groups with the loads one ahead.
+  const int gws[3] = {1, 4, 16};
   double best = 1e30;
   int bs = 0, bc = 8, bb = 256, bg = 1;
   for (int sl : slabs)

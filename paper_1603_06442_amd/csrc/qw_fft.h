@@ -287,4 +287,112 @@ __device__ __forceinline__ void fft_team_multi(cx<T> (&v)[S][E], cx<T>* lds, int
   StagesMulti<T, L, E, SIGN, 1, S>::run(v, lds, cstride, t, tw);
 }
 
+// Twiddles of a team transform held in registers. The twiddles a thread
+// applies depend only on its position t in the team and on the stage, not
+// on the pencil or on the direction (the inverse takes their conjugates), so
+// a thread that transforms many pencils, forward and back, loads them once.
+// Entries: for every stage after the first, NB groups of R - 1 table
+// values, in the order the stages consume them.
+template <int L, int E>
+__host__ __device__ constexpr int team_twiddle_count() {
+  int n = 0;
+  for (int NS = 1; NS < L;) {
+    const int REM = L / NS;
+    const int R = REM >= E ? E : REM;
+    if (NS > 1) n += (E / R) * (R - 1);
+    NS *= R;
+  }
+  return n;
+}
+
+template <typename T, int L, int E, int NS, int OFF>
+__device__ __forceinline__ void load_team_twiddles_from(cx<T>* w, int t,
+                                                        const cx<T>* __restrict__ tw) {
+  if constexpr (NS < L) {
+    constexpr int REM = L / NS;
+    constexpr int R = REM >= E ? E : REM;
+    constexpr int NB = E / R;
+    constexpr int TT = L / E;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int k = (t + b * TT) & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[OFF + b * (R - 1) + r - 1] = tw[r * k * (TWN / (NS * R))];
+      }
+      load_team_twiddles_from<T, L, E, NS * R, OFF + NB * (R - 1)>(w, t, tw);
+    } else {
+      load_team_twiddles_from<T, L, E, NS * R, OFF>(w, t, tw);
+    }
+  }
+}
+
+template <typename T, int L, int E>
+__device__ __forceinline__ void load_team_twiddles(cx<T>* w, int t, const cx<T>* __restrict__ tw) {
+  load_team_twiddles_from<T, L, E, 1, 0>(w, t, tw);
+}
+
+// StagesMulti with the twiddles from a register cache (load_team_twiddles).
+template <typename T, int L, int E, int SIGN, int NS, int S, int OFF>
+struct StagesMultiC {
+  static constexpr int REM = L / NS;
+  static constexpr int R = REM >= E ? E : REM;
+  static constexpr bool LAST = (NS * R == L);
+  static constexpr int TT = L / E;
+  static constexpr int NB = E / R;
+
+  __device__ __forceinline__ static void run(cx<T> (&v)[S][E], cx<T>* lds, int cstride, int t,
+                                             const cx<T>* wc) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = t + b * TT;
+      const int k = j & (NS - 1);
+      cx<T> w[R];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cx<T> x = wc[OFF + b * (R - 1) + r - 1];
+          w[r] = SIGN > 0 ? mk(x.x, -x.y) : x;
+        }
+      }
+      const int base = (j / NS) * (NS * R) + k;
+#pragma unroll
+      for (int c = 0; c < S; ++c) {
+        cx<T> a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = v[c][b + r * NB];
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) a[r] = cmul(a[r], w[r]);
+        }
+        dft_reg<R, SIGN>(a);
+        if constexpr (LAST) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[c][b + r * NB] = a[r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) lds[c * cstride + lds_swz<E>(base + r * NS)] = a[r];
+        }
+      }
+    }
+    if constexpr (!LAST) {
+      team_sync<TT>();
+#pragma unroll
+      for (int c = 0; c < S; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[c][e] = lds[c * cstride + lds_swz<E>(t + TT * e)];
+      team_sync<TT>();
+      StagesMultiC<T, L, E, SIGN, NS * R, S, (NS > 1 ? OFF + NB * (R - 1) : OFF)>::run(
+          v, lds, cstride, t, wc);
+    }
+  }
+};
+
+template <typename T, int L, int E, int SIGN, int S>
+__device__ __forceinline__ void fft_team_multi_c(cx<T> (&v)[S][E], cx<T>* lds, int cstride, int t,
+                                                 const cx<T>* wc) {
+  static_assert((L & (L - 1)) == 0 && L >= 1 && L <= TWN, "length");
+  StagesMultiC<T, L, E, SIGN, 1, S, 0>::run(v, lds, cstride, t, wc);
+}
+
 }  // namespace qw

@@ -119,9 +119,11 @@ struct GraphSlot {
   void* dmem = nullptr;
   void* hmem = nullptr;
   size_t dbytes = 0, hbytes = 0;
-  hipGraphExec_t exec = nullptr;  // null if the capture failed: the chain runs eagerly
+  hipGraphExec_t exec = nullptr;  // null until captured (or if the capture failed)
   bool busy = false;
   uint64_t last_use = 0;
+  qw_plan_t plan = nullptr;       // for the deferred capture
+  bool capture_failed = false;    // not tried again; the chain runs directly
 };
 
 }  // namespace
@@ -164,6 +166,11 @@ struct qw_server_s {
   size_t slot_bytes = 0;  // device bytes held by the slots
   uint64_t slot_clock = 0;
   int64_t graphs_captured = 0, graph_launches = 0;
+  int64_t launch_host_ns = 0;  // host time spent enqueuing batches (worker thread)
+  // Slots whose chain is still to be captured: the worker records the
+  // captures when it has no batch to form, so that a capture never delays
+  // the requests waiting in the queue.
+  std::vector<GraphSlot*> to_capture;
 };
 
 namespace {
@@ -317,12 +324,9 @@ void fill_params(Batch* b, char* H) {
 // buffer H (already holding the parameters): one upload of the parameters,
 // the state preparation, the evolution with the reductions, the result
 // copies. Only copies and kernels: the same chain can be captured.
-qw_status enqueue_chain(Batch* b, char* D, char* H, hipStream_t st) {
-  const int B = (int)b->reqs.size();
-  qw_plan_t p = b->plan;
+qw_status enqueue_chain(qw_plan_t p, int B, const Layout& Ly, char* D, char* H, hipStream_t st) {
   const StateGeom sg = state_geom(p);
   const ObsGeom og = obs_geom(p);
-  const Layout& Ly = b->lay;
   const int64_t nbf = Ly.nbf;  // 0: separate reduction pass
   // one upload of the three parameter arrays (contiguous in both layouts)
   HIP_TRY(hipMemcpyAsync(D + Ly.off_sinst, H + Ly.h_sinst, Ly.h_res - Ly.h_sinst,
@@ -373,6 +377,8 @@ bool slot_matches(const GraphSlot* g, const Batch* b) {
 }
 
 void drop_slot(qw_server_s* s, GraphSlot* g) {  // worker thread, slot idle
+  auto pc = std::find(s->to_capture.begin(), s->to_capture.end(), g);
+  if (pc != s->to_capture.end()) s->to_capture.erase(pc);
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   s->pool.put_dev(g->dbytes, g->dmem);
   s->pool.put_host(g->hbytes, g->hmem);
@@ -400,6 +406,7 @@ GraphSlot* new_slot(qw_server_s* s, Batch* b) {
   for (int i = 0; i < 3; ++i) g->N[i] = b->key.N[i];
   g->dtype = b->key.dtype;
   g->B = (int)b->reqs.size();
+  g->plan = b->plan;
   g->dbytes = b->lay.dbytes;
   g->hbytes = b->lay.hbytes;
   if (s->pool.get_dev(g->dbytes, &g->dmem) != hipSuccess) {
@@ -426,10 +433,14 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
   hipStream_t st = b->st;
   GraphSlot* g = nullptr;
   if (s->use_graphs) {
+    GraphSlot* uncaptured = nullptr;  // an idle slot whose capture is pending
     for (GraphSlot* c : s->slots)
-      if (!c->busy && c->exec && slot_matches(c, b)) {
-        g = c;
-        break;
+      if (!c->busy && slot_matches(c, b)) {
+        if (c->exec) {
+          g = c;
+          break;
+        }
+        uncaptured = c;
       }
     if (g) {
       g->busy = true;
@@ -444,7 +455,7 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
     }
     const auto ck = std::make_tuple(b->key.dim, b->key.N[0], b->key.N[1], b->key.N[2],
                                     b->key.dtype, (int)b->reqs.size());
-    if (++s->chain_runs[ck] >= 2) g = new_slot(s, b);
+    if (++s->chain_runs[ck] >= 2) g = uncaptured ? uncaptured : new_slot(s, b);
   }
   char* D;
   char* H;
@@ -461,27 +472,37 @@ qw_status launch_batch(qw_server_s* s, Batch* b) {
     H = (char*)b->hmem;
   }
   fill_params(b, H);
-  qw_status r = enqueue_chain(b, D, H, st);
+  qw_status r = enqueue_chain(b->plan, (int)b->reqs.size(), b->lay, D, H, st);
   if (r != QW_OK) return r;
   HIP_TRY(hipLaunchHostFunc(st, on_stream_done, b));
-  if (g) {
-    // Capture the same chain against the slot's buffers for later batches.
-    hipStream_t cs = s->plan_stream;
-    hipGraph_t graph = nullptr;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-      const qw_status rc = enqueue_chain(b, D, H, cs);
-      const hipError_t e = hipStreamEndCapture(cs, &graph);
-      if (rc == QW_OK && e == hipSuccess && graph) {
-        if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
-          g->exec = nullptr;
-        else
-          ++s->graphs_captured;
-      }
-      if (graph) (void)hipGraphDestroy(graph);
-    }
-    (void)hipGetLastError();
-  }
+  // captured when the worker is idle (once per slot)
+  if (g && !g->capture_failed &&
+      std::find(s->to_capture.begin(), s->to_capture.end(), g) == s->to_capture.end())
+    s->to_capture.push_back(g);
   return QW_OK;
+}
+
+// Records the chain of slot g against its buffers (on the set-up stream,
+// which runs nothing while capturing) and instantiates it. Worker thread,
+// lock not held.
+void capture_slot(qw_server_s* s, GraphSlot* g) {
+  const Key k{g->dim, {g->N[0], g->N[1], g->N[2]}, g->dtype};
+  const Layout Ly = batch_layout(k, g->B);
+  hipStream_t cs = s->plan_stream;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    const qw_status rc = enqueue_chain(g->plan, g->B, Ly, (char*)g->dmem, (char*)g->hmem, cs);
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc == QW_OK && e == hipSuccess && graph &&
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+      g->exec = exec;
+      ++s->graphs_captured;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  if (!g->exec) g->capture_failed = true;
+  (void)hipGetLastError();
 }
 
 void retire(qw_server_s* s, Batch* b) {  // lock held
@@ -620,12 +641,22 @@ void worker_main(qw_server_s* s) {
       for (Batch* b : ready) {
         b->t_launch = now_s();
         b->status = launch_batch(s, b);
+        s->launch_host_ns += (int64_t)((now_s() - b->t_launch) * 1e9);
         if (b->status != QW_OK) {
           // the stream still runs whatever was enqueued; mark and signal when it drains
           (void)hipStreamSynchronize(b->st);
           on_stream_done(b);
         }
       }
+      lk.lock();
+      continue;
+    }
+    if (!s->to_capture.empty() && s->finished.empty()) {
+      // nothing to form now: record one deferred capture
+      GraphSlot* g = s->to_capture.back();
+      s->to_capture.pop_back();
+      lk.unlock();
+      capture_slot(s, g);
       lk.lock();
       continue;
     }
@@ -763,6 +794,7 @@ qw_status qw_server_stats(qw_server_t s, qw_server_info* out) {
   out->graphs_captured = s->graphs_captured;
   out->graph_launches = s->graph_launches;
   out->slot_bytes = (int64_t)s->slot_bytes;
+  out->launch_host_ns = s->launch_host_ns;
   return QW_OK;
 }
 

@@ -67,7 +67,8 @@ class QwServerInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "submitted", "completed", "batches", "queued", "inflight_batches",
         "max_inflight_batches", "used_bytes", "peak_used_bytes", "laid_out_bytes",
-        "peak_laid_out_bytes", "graphs_captured", "graph_launches", "slot_bytes")]
+        "peak_laid_out_bytes", "graphs_captured", "graph_launches", "slot_bytes",
+        "launch_host_ns")]
 
 
 def _load():
