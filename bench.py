@@ -21,13 +21,17 @@ continuous-batching server (saturation throughput batched and unbatched,
 p50/p99 latency under Poisson arrivals).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-serving]
-       python bench.py --copy-calib   (a plain copy of one field, for counters)
+                       [--no-serving] [--record RUNS.jsonl]
+       python bench.py --copy-calib     (a plain copy of one field, for counters)
+       python bench.py --counter-pass   (the hot kernels only, for counters)
+--record (or QW_RUN_RECORD) appends the JSON line, with host, device, library
+version and time, to a JSONL file: one record per run.
 """
 import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -123,6 +127,32 @@ def copy_calib(steps):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calib_bytes_read": 8 * n, "copy_calib_bytes_written": 8 * n,
                       "launches": steps}))
+
+
+def counter_pass():
+    """A short run of the hot kernels for hardware-counter passes: three
+    Fourier jumps of the 256^3 workload with the fused reduction at the
+    five-pass schedule (no slab grouping, so every pass is one whole-field
+    launch), two single stencil steps and one two-step launch."""
+    import torch
+    from paper_1603_06442_amd import inputs, qw
+    w = inputs.workload(2)
+    plan = qw.Plan(3, w["N"], w["m"], "c64")
+    plan.set_schedule(0, 4, 128, 4)
+    x = plan.empty()
+    plan.prepare_state(x, w["k0"], w["sigma"], w["center"], w["c_plus"], w["c_minus"])
+    y = plan.empty()
+    for i in range(3):
+        plan.evolve_fft_observables(x, 1000 + i, w["center"], out=y)
+        print("jump", i, flush=True)
+    plan.step(y, 2)
+    qw.set_step_kernel(True)
+    try:
+        plan.step(y, 2)
+    finally:
+        qw.set_step_kernel(False)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_pass": "done"}))
 
 
 def _submit(srv, r):
@@ -304,6 +334,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--record", default=os.environ.get("QW_RUN_RECORD"),
+                    help="append the JSON line with host/device/time to this JSONL file")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="short run of the hot kernels only, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -312,6 +346,9 @@ def main():
     import torch
     if args.copy_calib:
         copy_calib(max(1, args.steps))
+        return
+    if args.counter_pass:
+        counter_pass()
         return
     from paper_1603_06442_amd import inputs, qw
 
@@ -509,6 +546,14 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line))
+    if args.record:
+        # one JSON record per run, appended: the line plus where and when it ran
+        rec = dict(line)
+        rec["record"] = {"unix_time": round(time.time(), 1), "host": platform.node(),
+                         "device": torch.cuda.get_device_name(0),
+                         "library": qw.version(), "argv": sys.argv[1:]}
+        with open(args.record, "a") as f:
+            f.write(json.dumps(rec) + "\n")
 
 
 def workload512_line(qw):

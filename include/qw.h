@@ -43,6 +43,13 @@
  * qw_last_error() returns a message for the last failing call of the calling
  * thread. Arguments are validated before any work is enqueued, so a call
  * that returns QW_ERR_INVALID or QW_ERR_UNSUPPORTED has changed nothing.
+ *
+ * Tracing and debugging: each plan-level entry point runs inside a roctx
+ * range named after it (rocprofv3 --marker-trace shows them). With the
+ * environment variable QW_DEBUG set (to anything but 0; read on every call)
+ * an entry point that enqueued work waits for its stream and reports a
+ * failed kernel as QW_ERR_DEVICE naming itself, except while the stream is
+ * being captured into a graph.
  */
 #ifndef QW_H
 #define QW_H
@@ -60,7 +67,8 @@ typedef enum {
   QW_ERR_INVALID = 1,      /* bad argument (null pointer, m outside [0,1], ...) */
   QW_ERR_UNSUPPORTED = 2,  /* valid but not provided (N not a power of two, too large) */
   QW_ERR_NOMEM = 3,        /* device or host allocation failed */
-  QW_ERR_DEVICE = 4        /* a HIP call or kernel launch failed */
+  QW_ERR_DEVICE = 4,       /* a HIP call or kernel launch failed */
+  QW_ERR_CANCELLED = 5     /* serving: the request was cancelled before it ran */
 } qw_status;
 
 typedef enum { QW_C64 = 0, QW_C128 = 1 } qw_dtype;
@@ -341,7 +349,14 @@ qw_status qw_get_schedule(qw_plan_t plan, int* slab_planes, int* contig_elems,
                           int* contig_threads, int* contig_groups);
 
 /* Time the candidate schedules on the plan's scratch field and keep the
- * fastest; *best_ms (nullable) receives its time per evolution. Waits. */
+ * fastest; *best_ms (nullable) receives its time per evolution. Waits.
+ * With the environment variable QW_TUNE_CACHE naming a text file, a schedule
+ * found there for the same (device architecture, walk, d, N, precision) is
+ * taken without timing (*best_ms = the time recorded with it; the last such
+ * line wins, malformed lines are ignored), and a newly timed one is appended
+ * as one line "qw-tune-v1 <arch> <dirac|weyl> d<d> <N1>x<N2>x<N3> <c64|c128>
+ * <slab> <elems> <threads> <groups> <ms>". Processes that share the file may
+ * append concurrently; each line is written by one fprintf. */
 qw_status qw_autotune(qw_plan_t plan, void* stream, double* best_ms);
 
 /* Dispersive approximation of Proposition 1 (Sec. 5.1): the particle /
@@ -418,9 +433,13 @@ typedef struct {
   int64_t graph_launches;   /* batches run by replaying a captured graph */
   int64_t slot_bytes;       /* device bytes held by the captured graphs' buffers */
   int64_t launch_host_ns;   /* host time the server spent enqueuing batches */
+  int64_t budget_bytes;     /* the budget in force (after resolving 0) */
+  int64_t cancelled;        /* requests cancelled while queued */
 } qw_server_info;
 
-/* Start a server on the current device. budget_bytes >= 1 MiB, max_batch in
+/* Start a server on the current device. budget_bytes >= 1 MiB, or 0 for
+ * the environment variable QW_HBM_BUDGET (bytes, optional K/M/G suffix) or,
+ * without it, half of the device memory free at creation; max_batch in
  * [1, 4096], nstreams in [1, 16]. */
 qw_status qw_server_create(qw_server_t* out, size_t budget_bytes, int max_batch, int nstreams);
 /* Options, before the first submit. use_graphs (default 1): the chain of
@@ -446,6 +465,15 @@ qw_status qw_server_submit(qw_server_t server, const qw_request* req, int64_t* t
 qw_status qw_server_poll(qw_server_t server, int64_t ticket, qw_result* out, int* done);
 /* Block until the request has completed. */
 qw_status qw_server_wait(qw_server_t server, int64_t ticket, qw_result* out);
+/* Cancel a request that is still queued (not yet in a batch): its result,
+ * with status QW_ERR_CANCELLED, is then collected by poll or wait as usual.
+ * *cancelled = 1 if it was cancelled, 0 if it is already on the device or
+ * done (it then completes normally). QW_ERR_INVALID for an unknown ticket. */
+qw_status qw_server_cancel(qw_server_t server, int64_t ticket, int* cancelled);
+/* qw_server_wait for at most timeout_s seconds: *done = 1 and *out filled if
+ * the request completed in time, else *done = 0 and it stays pending. */
+qw_status qw_server_wait_for(qw_server_t server, int64_t ticket, double timeout_s,
+                             qw_result* out, int* done);
 /* hold != 0: queue requests but launch none (batches already on the device
  * finish); hold = 0: resume, batching everything queued meanwhile. */
 qw_status qw_server_hold(qw_server_t server, int hold);

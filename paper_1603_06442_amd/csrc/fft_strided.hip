@@ -24,6 +24,16 @@ struct OuterMap {
   int nt;
 };
 
+// Workgroup b runs on XCD b % 8 (each XCD has its own L2 and translation
+// caches). For complex128 the work is numbered so that each XCD takes a
+// contiguous eighth of it (for an n1 pass, a contiguous range of columns of
+// every row it reads): 256^3 evolution 2.28 -> 2.23 ms, its n2 passes 0.42 ->
+// 0.38 ms. For complex64 the natural order is kept: there the same numbering
+// made the n1 forward pass 0.221 -> 0.252 ms and the evolution 1.05 -> 1.09 ms.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t n, bool on) {
+  return (on && (n & 7) == 0) ? (b & 7) * (n >> 3) + (b >> 3) : b;
+}
+
 template <typename T, int L, int E, int SIGN>
 __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
                                                       const cx<T>* __restrict__ in, int64_t I,
@@ -36,7 +46,7 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
   const int tid = threadIdx.x;
   const int p = tid & (P - 1);
   const int t = tid >> lgP;
-  const int64_t blk = blockIdx.x;
+  const int64_t blk = xcd_order(blockIdx.x, gridDim.x, sizeof(T) == 8);
   const int64_t o = blk / nblk_i;
   const int64_t i0 = (blk - o * nblk_i) << lgP;
   const int64_t comp = o / om.ocount;
@@ -181,7 +191,7 @@ __global__ __launch_bounds__((strided_max_threads<T, L>())) void k_fft_strided_o
   const int tid = threadIdx.x;
   const int p = tid & (P - 1);
   const int t = tid >> lgP;
-  const int64_t blk = blockIdx.x;
+  const int64_t blk = xcd_order(blockIdx.x, gridDim.x, sizeof(T) == 8);
   const int64_t o = blk / nblk_i;
   const int64_t col = ((blk - o * nblk_i) << lgP) + p;
   const int64_t base = o * (int64_t)L * I + col;

@@ -20,6 +20,8 @@
 #include <new>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "plan.h"
 
 using namespace qw;
@@ -826,6 +828,36 @@ qw_status transform_impl(qw_plan_t p, int B, const void* in, void* out, int dire
 
 }  // namespace qw
 
+namespace {
+
+// QW_DEBUG set (to anything but "0"): every entry point waits for its
+// stream and reports a failed kernel as its own error (for debugging; slow).
+// Read on every call, so that a process can switch it while it runs.
+bool debug_mode() {
+  const char* v = getenv("QW_DEBUG");
+  return v && *v && strcmp(v, "0") != 0;
+}
+
+// Runs one entry point inside a named roctx range (visible to rocprofv3
+// --marker-trace), and in debug mode synchronises its stream afterwards.
+template <typename F>
+qw_status traced(const char* name, void* stream, F&& body) {
+  roctxRangePush(name);
+  qw_status r = body();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (r == QW_OK && debug_mode() &&
+      hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess &&
+      cs == hipStreamCaptureStatusNone) {  // a capturing stream cannot be synchronised
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) r = fail(QW_ERR_DEVICE, "%s: %s (QW_DEBUG)", name, hipGetErrorString(e));
+  }
+  roctxRangePop();
+  return r;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* qw_last_error(void) { return g_last_error.c_str(); }
@@ -1050,12 +1082,14 @@ static qw_status step_impl(qw_plan_t p, const StencilGeom& g, int B, void* psi,
 }
 
 qw_status qw_step(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!psi) return fail(QW_ERR_INVALID, "psi is NULL");
-  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
-  if (nsteps == 0) return QW_OK;
-  return step_impl(p, stencil_geom(p), 1, psi, p->d_coef, nsteps, (hipStream_t)stream);
+  return traced("qw_step", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    if (!psi) return fail(QW_ERR_INVALID, "psi is NULL");
+    if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+    if (nsteps == 0) return QW_OK;
+    return step_impl(p, stencil_geom(p), 1, psi, p->d_coef, nsteps, (hipStream_t)stream);
+  });
 }
 
 }  // extern "C"
@@ -1097,65 +1131,69 @@ void* noalloc_ptr(qw_status* err) {
 extern "C" {
 
 qw_status qw_step_noalloc(qw_plan_t p, void* psi, int64_t nsteps, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!psi) return fail(QW_ERR_INVALID, "psi is NULL");
-  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
-  if (p->field_bytes > (size_t)QW_NOALLOC_SCRATCH_BYTES)
-    return fail(QW_ERR_UNSUPPORTED,
-                "qw_step_noalloc: the field has %zu bytes, the fixed buffer holds %zu",
-                p->field_bytes, (size_t)QW_NOALLOC_SCRATCH_BYTES);
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
-    return fail(QW_ERR_INVALID, "qw_step_noalloc: the plan's device (%d) is not current (%d)",
-                p->device, dev);
-  if (nsteps == 0) return QW_OK;
-  void* buf = noalloc_ptr(&r);
-  if (!buf) return r;
-  return step_impl(p, stencil_geom(p), 1, psi, p->d_coef, nsteps, (hipStream_t)stream, buf);
+  return traced("qw_step_noalloc", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    if (!psi) return fail(QW_ERR_INVALID, "psi is NULL");
+    if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+    if (p->field_bytes > (size_t)QW_NOALLOC_SCRATCH_BYTES)
+      return fail(QW_ERR_UNSUPPORTED,
+                  "qw_step_noalloc: the field has %zu bytes, the fixed buffer holds %zu",
+                  p->field_bytes, (size_t)QW_NOALLOC_SCRATCH_BYTES);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+      return fail(QW_ERR_INVALID, "qw_step_noalloc: the plan's device (%d) is not current (%d)",
+                  p->device, dev);
+    if (nsteps == 0) return QW_OK;
+    void* buf = noalloc_ptr(&r);
+    if (!buf) return r;
+    return step_impl(p, stencil_geom(p), 1, psi, p->d_coef, nsteps, (hipStream_t)stream, buf);
+  });
 }
 
 qw_status qw_step_batched(qw_plan_t p, int B, void* psi, const double* m, int64_t nsteps,
                           void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  r = dirac_only(p, "qw_step_batched");
-  if (r != QW_OK) return r;
-  if (B < 0 || B > 65535) return fail(QW_ERR_INVALID, "B must lie in [0, 65535]");
-  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
-  if (B == 0 || nsteps == 0) return QW_OK;
-  if (!psi || !m) return fail(QW_ERR_INVALID, "NULL argument");
-  for (int b = 0; b < B; ++b)
-    if (!(m[b] >= 0.0 && m[b] <= 1.0)) return fail(QW_ERR_INVALID, "m[%d] outside [0, 1]", b);
-  hipStream_t st = (hipStream_t)stream;
-  // Per-instance transition matrices, derived and packed exactly as the
-  // plan's own (an instance with the plan's mass gets the plan's numbers).
-  StencilGeom g = stencil_geom(p);
-  const size_t one = p->dbl ? sizeof(StencilCoef<double>) : sizeof(StencilCoef<float>);
-  r = ensure_coefs(p, B);
-  if (r != QW_OK) return r;
-  // The pinned staging area may still feed an earlier call's copy.
-  HIP_TRY(hipStreamSynchronize(st));
-  bool sparse = p->dim == 3;
-  for (int b = 0; b < B; ++b) {
-    Table T;
-    const double leak = derive_table(p->dim, m[b], T);
-    if (leak > 1e-14 || unitarity_defect(T) > 1e-13)
-      return fail(QW_ERR_DEVICE, "derived transition matrices fail checks for m[%d]", b);
-    StencilCoef<double> cd;
-    StencilCoef<float> cf;
-    std::string why;
-    if (!pack_coef<double>(T, m[b], cd, why) || !pack_coef<float>(T, m[b], cf, why))
-      return fail(QW_ERR_DEVICE, "transition matrices for m[%d]: %s", b, why.c_str());
-    if (sparse && !coef_sparse3(cd)) sparse = false;
-    if (p->dbl)
-      memcpy(p->h_coefs + one * b, &cd, one);
-    else
-      memcpy(p->h_coefs + one * b, &cf, one);
-  }
-  g.sparse3 = sparse ? 1 : 0;
-  HIP_TRY(hipMemcpyAsync(p->d_coefs, p->h_coefs, one * B, hipMemcpyHostToDevice, st));
-  return step_impl(p, g, B, psi, p->d_coefs, nsteps, st);
+  return traced("qw_step_batched", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    r = dirac_only(p, "qw_step_batched");
+    if (r != QW_OK) return r;
+    if (B < 0 || B > 65535) return fail(QW_ERR_INVALID, "B must lie in [0, 65535]");
+    if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+    if (B == 0 || nsteps == 0) return QW_OK;
+    if (!psi || !m) return fail(QW_ERR_INVALID, "NULL argument");
+    for (int b = 0; b < B; ++b)
+      if (!(m[b] >= 0.0 && m[b] <= 1.0)) return fail(QW_ERR_INVALID, "m[%d] outside [0, 1]", b);
+    hipStream_t st = (hipStream_t)stream;
+    // Per-instance transition matrices, derived and packed exactly as the
+    // plan's own (an instance with the plan's mass gets the plan's numbers).
+    StencilGeom g = stencil_geom(p);
+    const size_t one = p->dbl ? sizeof(StencilCoef<double>) : sizeof(StencilCoef<float>);
+    r = ensure_coefs(p, B);
+    if (r != QW_OK) return r;
+    // The pinned staging area may still feed an earlier call's copy.
+    HIP_TRY(hipStreamSynchronize(st));
+    bool sparse = p->dim == 3;
+    for (int b = 0; b < B; ++b) {
+      Table T;
+      const double leak = derive_table(p->dim, m[b], T);
+      if (leak > 1e-14 || unitarity_defect(T) > 1e-13)
+        return fail(QW_ERR_DEVICE, "derived transition matrices fail checks for m[%d]", b);
+      StencilCoef<double> cd;
+      StencilCoef<float> cf;
+      std::string why;
+      if (!pack_coef<double>(T, m[b], cd, why) || !pack_coef<float>(T, m[b], cf, why))
+        return fail(QW_ERR_DEVICE, "transition matrices for m[%d]: %s", b, why.c_str());
+      if (sparse && !coef_sparse3(cd)) sparse = false;
+      if (p->dbl)
+        memcpy(p->h_coefs + one * b, &cd, one);
+      else
+        memcpy(p->h_coefs + one * b, &cf, one);
+    }
+    g.sparse3 = sparse ? 1 : 0;
+    HIP_TRY(hipMemcpyAsync(p->d_coefs, p->h_coefs, one * B, hipMemcpyHostToDevice, st));
+    return step_impl(p, g, B, psi, p->d_coefs, nsteps, st);
+  });
 }
 
 // |t| <= 2^53: every such integer is a double, and the phase omega t is
@@ -1168,29 +1206,33 @@ static qw_status check_time(double t) {
 }
 
 qw_status qw_evolve_fft(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!psi0 || !psi_t) return fail(QW_ERR_INVALID, "field pointer is NULL");
-  r = check_time((double)t);
-  if (r != QW_OK) return r;
-  InstParam ip;
-  ip.m = p->m;
-  ip.n = p->n;
-  ip.t = (double)t;
-  return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
+  return traced("qw_evolve_fft", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    if (!psi0 || !psi_t) return fail(QW_ERR_INVALID, "field pointer is NULL");
+    r = check_time((double)t);
+    if (r != QW_OK) return r;
+    InstParam ip;
+    ip.m = p->m;
+    ip.n = p->n;
+    ip.t = (double)t;
+    return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
+  });
 }
 
 qw_status qw_evolve_fft_real(qw_plan_t p, const void* psi0, void* psi_t, double t, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!psi0 || !psi_t) return fail(QW_ERR_INVALID, "field pointer is NULL");
-  r = check_time(t);
-  if (r != QW_OK) return r;
-  InstParam ip;
-  ip.m = p->m;
-  ip.n = p->n;
-  ip.t = t;
-  return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
+  return traced("qw_evolve_fft_real", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    if (!psi0 || !psi_t) return fail(QW_ERR_INVALID, "field pointer is NULL");
+    r = check_time(t);
+    if (r != QW_OK) return r;
+    InstParam ip;
+    ip.m = p->m;
+    ip.n = p->n;
+    ip.t = t;
+    return evolve_impl(p, 1, psi0, psi_t, nullptr, ip, (hipStream_t)stream);
+  });
 }
 
 qw_status qw_set_step_kernel(int two_step, int tile_shape, int chunk) {
@@ -1235,155 +1277,209 @@ qw_status qw_get_schedule(qw_plan_t p, int* slab_planes, int* contig_elems, int*
 }
 
 qw_status qw_autotune(qw_plan_t p, void* stream, double* best_ms) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  hipStream_t st = (hipStream_t)stream;
-  r = ensure_scratch(p, p->field_bytes);
-  if (r != QW_OK) return r;
-  HIP_TRY(hipMemsetAsync(p->d_scratch, 0, p->field_bytes, st));
-  std::vector<int> slabs = {0};
-  if (p->dim == 3) {
-    const size_t plane = p->field_bytes / (size_t)p->N[0];
-    for (size_t target : {size_t(16) << 20, size_t(32) << 20, size_t(64) << 20, size_t(128) << 20}) {
-      int64_t k = (int64_t)(target / plane);
-      if (k >= 1 && k < p->N[0]) {
-        int64_t kk = 1;
-        while (kk * 2 <= k) kk *= 2;
-        if (std::find(slabs.begin(), slabs.end(), (int)kk) == slabs.end()) slabs.push_back((int)kk);
+  return traced("qw_autotune", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    // QW_TUNE_CACHE names a text file of earlier results, one line per
+    // (device architecture, walk, dimension, lattice, precision): a cached
+    // schedule is taken without timing; a new one is appended.
+    const char* cache_path = getenv("QW_TUNE_CACHE");
+    char key[256] = {0};
+    if (cache_path && *cache_path) {
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) prop.gcnArchName[0] = 0;
+      snprintf(key, sizeof key, "qw-tune-v1 %s %s d%d %lldx%lldx%lld %s", prop.gcnArchName,
+               p->weyl ? "weyl" : "dirac", p->dim, (long long)p->N[0], (long long)p->N[1],
+               (long long)p->N[2], p->dbl ? "c128" : "c64");
+      for (char* c = key; *c; ++c)
+        if (*c == ':' || *c == '\n') *c = '_';  // keep the key one token per field
+      if (FILE* f = fopen(cache_path, "r")) {
+        char line[512];
+        int fs = -1, fc = 0, fb = 0, fg = 0;
+        double fms = 0.0;
+        const size_t kl = strlen(key);
+        while (fgets(line, sizeof line, f)) {
+          int a, b, c, d;
+          double ms;
+          // the last well-formed entry wins; anything else is skipped
+          if (strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
+              sscanf(line + kl, " %d %d %d %d %lf", &a, &b, &c, &d, &ms) == 5 && a >= 0 &&
+              (b == 4 || b == 8) && (c == 64 || c == 128 || c == 256 || c == 512) && d >= 1 &&
+              d <= 64 && ms >= 0.0) {
+            fs = a; fc = b; fb = c; fg = d; fms = ms;
+          }
+        }
+        fclose(f);
+        if (fs >= 0) {
+          p->slab = p->dim == 3 ? fs : 0;
+          p->ce = fc;
+          p->cb = fb;
+          p->gw = fg;
+          if (best_ms) *best_ms = fms;
+          return QW_OK;
+        }
       }
     }
-  }
-  // complex128 with eight elements per thread spills registers in the
-  // lockstep transform of four components (d = 2, 3): four only.
-  const int ces[2] = {8, 4};
-  const bool only4 = p->dbl && p->dim >= 2;
-  const int cbs[3] = {64, 128, 256};
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  InstParam ip;
-  ip.m = p->m;
-  ip.n = p->n;
-  ip.t = 12345;
-  // 16 groups per workgroup: about one round of resident workgroups per CU
-  // at 256^3, each walking its groups with the loads one ahead.
-  const int gws[3] = {1, 4, 16};
-  double best = 1e30;
-  int bs = 0, bc = 8, bb = 256, bg = 1;
-  for (int sl : slabs)
-    for (int ce : ces)
-      for (int cb : cbs)
-        for (int gw : gws) {
-      if (ce == 4 && p->dim < 2) continue;
-      if (ce == 8 && only4) continue;
-      if (gw > 1 && !(p->dim == 3 && ce == 4)) continue;
-      p->slab = sl;
-      p->ce = ce;
-      p->cb = cb;
-      p->gw = gw;
-      r = evolve_impl(p, 1, p->d_scratch, p->d_scratch, nullptr, ip, st);  // warm-up
-      if (r != QW_OK) break;
-      (void)hipEventRecord(e0, st);
-      const int reps = 3;
-      for (int k = 0; k < reps && r == QW_OK; ++k)
-        r = evolve_impl(p, 1, p->d_scratch, p->d_scratch, nullptr, ip, st);
-      (void)hipEventRecord(e1, st);
-      (void)hipEventSynchronize(e1);
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (r == QW_OK && ms / reps < best) {
-        best = ms / reps;
-        bs = sl;
-        bc = ce;
-        bb = cb;
-        bg = gw;
-      }
+    r = ensure_scratch(p, p->field_bytes);
+    if (r != QW_OK) return r;
+    HIP_TRY(hipMemsetAsync(p->d_scratch, 0, p->field_bytes, st));
+    std::vector<int> slabs = {0};
+    if (p->dim == 3) {
+      const size_t plane = p->field_bytes / (size_t)p->N[0];
+      for (size_t target : {size_t(16) << 20, size_t(32) << 20, size_t(64) << 20, size_t(128) << 20}) {
+        int64_t k = (int64_t)(target / plane);
+        if (k >= 1 && k < p->N[0]) {
+          int64_t kk = 1;
+          while (kk * 2 <= k) kk *= 2;
+          if (std::find(slabs.begin(), slabs.end(), (int)kk) == slabs.end()) slabs.push_back((int)kk);
         }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  p->slab = bs;
-  p->ce = bc;
-  p->cb = bb;
-  p->gw = bg;
-  if (r != QW_OK) return r;
-  if (best_ms) *best_ms = best;
-  return QW_OK;
+      }
+    }
+    // complex128 with eight elements per thread spills registers in the
+    // lockstep transform of four components (d = 2, 3): four only.
+    const int ces[2] = {8, 4};
+    const bool only4 = p->dbl && p->dim >= 2;
+    const int cbs[3] = {64, 128, 256};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    InstParam ip;
+    ip.m = p->m;
+    ip.n = p->n;
+    ip.t = 12345;
+    // 16 groups per workgroup: about one round of resident workgroups per CU
+    // at 256^3, each walking its groups with the loads one ahead.
+    const int gws[3] = {1, 4, 16};
+    double best = 1e30;
+    int bs = 0, bc = 8, bb = 256, bg = 1;
+    for (int sl : slabs)
+      for (int ce : ces)
+        for (int cb : cbs)
+          for (int gw : gws) {
+        if (ce == 4 && p->dim < 2) continue;
+        if (ce == 8 && only4) continue;
+        if (gw > 1 && !(p->dim == 3 && ce == 4)) continue;
+        p->slab = sl;
+        p->ce = ce;
+        p->cb = cb;
+        p->gw = gw;
+        r = evolve_impl(p, 1, p->d_scratch, p->d_scratch, nullptr, ip, st);  // warm-up
+        if (r != QW_OK) break;
+        (void)hipEventRecord(e0, st);
+        const int reps = 3;
+        for (int k = 0; k < reps && r == QW_OK; ++k)
+          r = evolve_impl(p, 1, p->d_scratch, p->d_scratch, nullptr, ip, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (r == QW_OK && ms / reps < best) {
+          best = ms / reps;
+          bs = sl;
+          bc = ce;
+          bb = cb;
+          bg = gw;
+        }
+          }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->slab = bs;
+    p->ce = bc;
+    p->cb = bb;
+    p->gw = bg;
+    if (r != QW_OK) return r;
+    if (best_ms) *best_ms = best;
+    if (key[0]) {
+      if (FILE* f = fopen(cache_path, "a")) {
+        fprintf(f, "%s %d %d %d %d %.6f\n", key, bs, bc, bb, bg, best);
+        fclose(f);
+      }
+    }
+    return QW_OK;
+  });
 }
 
 qw_status qw_evolve_fft_timed(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, void* stream,
                               float* pass_ms, int* npass) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!psi0 || !psi_t || !pass_ms || !npass) return fail(QW_ERR_INVALID, "NULL argument");
-  r = check_time((double)t);
-  if (r != QW_OK) return r;
-  hipStream_t st = (hipStream_t)stream;
-  PassTimer tm;
-  tm.st = st;
-  for (int i = 0; i < 9; ++i) HIP_TRY(hipEventCreate(&tm.ev[i]));
-  HIP_TRY(hipEventRecord(tm.ev[tm.n++], st));
-  InstParam ip;
-  ip.m = p->m;
-  ip.n = p->n;
-  ip.t = (double)t;
-  g_timer = &tm;
-  r = evolve_impl(p, 1, psi0, psi_t, nullptr, ip, st);
-  g_timer = nullptr;
-  hipError_t e = hipEventSynchronize(tm.ev[tm.n - 1]);
-  *npass = tm.n - 1;
-  for (int i = 0; i + 1 < tm.n && i < 8; ++i) {
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, tm.ev[i], tm.ev[i + 1]);
-    pass_ms[i] = ms;
-  }
-  for (int i = 0; i < 9; ++i) (void)hipEventDestroy(tm.ev[i]);
-  if (r != QW_OK) return r;
-  if (e != hipSuccess) return fail(QW_ERR_DEVICE, "event timing: %s", hipGetErrorString(e));
-  return QW_OK;
+  return traced("qw_evolve_fft_timed", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    if (!psi0 || !psi_t || !pass_ms || !npass) return fail(QW_ERR_INVALID, "NULL argument");
+    r = check_time((double)t);
+    if (r != QW_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    PassTimer tm;
+    tm.st = st;
+    for (int i = 0; i < 9; ++i) HIP_TRY(hipEventCreate(&tm.ev[i]));
+    HIP_TRY(hipEventRecord(tm.ev[tm.n++], st));
+    InstParam ip;
+    ip.m = p->m;
+    ip.n = p->n;
+    ip.t = (double)t;
+    g_timer = &tm;
+    r = evolve_impl(p, 1, psi0, psi_t, nullptr, ip, st);
+    g_timer = nullptr;
+    hipError_t e = hipEventSynchronize(tm.ev[tm.n - 1]);
+    *npass = tm.n - 1;
+    for (int i = 0; i + 1 < tm.n && i < 8; ++i) {
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, tm.ev[i], tm.ev[i + 1]);
+      pass_ms[i] = ms;
+    }
+    for (int i = 0; i < 9; ++i) (void)hipEventDestroy(tm.ev[i]);
+    if (r != QW_OK) return r;
+    if (e != hipSuccess) return fail(QW_ERR_DEVICE, "event timing: %s", hipGetErrorString(e));
+    return QW_OK;
+  });
 }
 
 qw_status qw_evolve_fft_batched(qw_plan_t p, int B, const void* in, void* out, const double* m,
                                 const int64_t* t, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  r = dirac_only(p, "qw_evolve_fft_batched");
-  if (r != QW_OK) return r;
-  if (B < 0) return fail(QW_ERR_INVALID, "B must be >= 0");
-  if (B == 0) return QW_OK;
-  if (!in || !out || !m || !t) return fail(QW_ERR_INVALID, "NULL argument");
-  for (int b = 0; b < B; ++b) {
-    if (!(m[b] >= 0.0 && m[b] <= 1.0)) return fail(QW_ERR_INVALID, "m[%d] outside [0, 1]", b);
-    r = check_time((double)t[b]);
+  return traced("qw_evolve_fft_batched", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
     if (r != QW_OK) return r;
-  }
-  hipStream_t st = (hipStream_t)stream;
-  r = ensure_inst(p, B);
-  if (r != QW_OK) return r;
-  // The pinned staging area may still feed an earlier batched call's copy.
-  HIP_TRY(hipStreamSynchronize(st));
-  for (int b = 0; b < B; ++b) {
-    p->h_inst[b].m = m[b];
-    p->h_inst[b].n = sqrt(1.0 - m[b] * m[b]);
-    p->h_inst[b].t = (double)t[b];
-  }
-  HIP_TRY(hipMemcpyAsync(p->d_inst, p->h_inst, sizeof(InstParam) * B, hipMemcpyHostToDevice, st));
-  InstParam ip;
-  ip.m = p->m;
-  ip.n = p->n;
-  ip.t = 0;
-  return evolve_impl(p, B, in, out, p->d_inst, ip, st);
+    r = dirac_only(p, "qw_evolve_fft_batched");
+    if (r != QW_OK) return r;
+    if (B < 0) return fail(QW_ERR_INVALID, "B must be >= 0");
+    if (B == 0) return QW_OK;
+    if (!in || !out || !m || !t) return fail(QW_ERR_INVALID, "NULL argument");
+    for (int b = 0; b < B; ++b) {
+      if (!(m[b] >= 0.0 && m[b] <= 1.0)) return fail(QW_ERR_INVALID, "m[%d] outside [0, 1]", b);
+      r = check_time((double)t[b]);
+      if (r != QW_OK) return r;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    r = ensure_inst(p, B);
+    if (r != QW_OK) return r;
+    // The pinned staging area may still feed an earlier batched call's copy.
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b) {
+      p->h_inst[b].m = m[b];
+      p->h_inst[b].n = sqrt(1.0 - m[b] * m[b]);
+      p->h_inst[b].t = (double)t[b];
+    }
+    HIP_TRY(hipMemcpyAsync(p->d_inst, p->h_inst, sizeof(InstParam) * B, hipMemcpyHostToDevice, st));
+    InstParam ip;
+    ip.m = p->m;
+    ip.n = p->n;
+    ip.t = 0;
+    return evolve_impl(p, B, in, out, p->d_inst, ip, st);
+  });
 }
 
 qw_status qw_transform(qw_plan_t p, const void* in, void* out, int direction, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!in || !out) return fail(QW_ERR_INVALID, "field pointer is NULL");
-  if (direction != 1 && direction != -1) return fail(QW_ERR_INVALID, "direction must be +1 or -1");
-  if (p->fourstep) {
-    r = ensure_scratch(p, p->field_bytes);
+  return traced("qw_transform", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
     if (r != QW_OK) return r;
-  }
-  return transform_impl(p, 1, in, out, direction, p->d_scratch, (hipStream_t)stream);
+    if (!in || !out) return fail(QW_ERR_INVALID, "field pointer is NULL");
+    if (direction != 1 && direction != -1) return fail(QW_ERR_INVALID, "direction must be +1 or -1");
+    if (p->fourstep) {
+      r = ensure_scratch(p, p->field_bytes);
+      if (r != QW_OK) return r;
+    }
+    return transform_impl(p, 1, in, out, direction, p->d_scratch, (hipStream_t)stream);
+  });
 }
 
 // Cubic-supercell field [2][s][N1 N2 N3] (Sec. 4, eq:bcc-dft / eq:bcc-idft):
@@ -1442,294 +1538,312 @@ static qw_status check_bcc(qw_plan_t p, const void* in, const void* out) {
 }
 
 qw_status qw_bcc_transform(qw_plan_t p, const void* in, void* out, int direction, void* stream) {
-  qw_status r = check_bcc(p, in, out);
-  if (r != QW_OK) return r;
-  if (direction != 1 && direction != -1) return fail(QW_ERR_INVALID, "direction must be +1 or -1");
-  return bcc_impl(p, in, out, direction > 0 ? MODE_BCC_FWD : MODE_BCC_INV, 0.0,
-                  (hipStream_t)stream);
+  return traced("qw_bcc_transform", stream, [&]() -> qw_status {
+    qw_status r = check_bcc(p, in, out);
+    if (r != QW_OK) return r;
+    if (direction != 1 && direction != -1) return fail(QW_ERR_INVALID, "direction must be +1 or -1");
+    return bcc_impl(p, in, out, direction > 0 ? MODE_BCC_FWD : MODE_BCC_INV, 0.0,
+                    (hipStream_t)stream);
+  });
 }
 
 qw_status qw_bcc_step(qw_plan_t p, void* f, int64_t nsteps, void* stream) {
-  qw_status r = check_bcc(p, f, f);
-  if (r != QW_OK) return r;
-  if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
-  if (nsteps == 0) return QW_OK;
-  hipStream_t st = (hipStream_t)stream;
-  const size_t bytes = 2 * p->field_bytes;
-  r = ensure_scratch(p, bytes);
-  if (r != QW_OK) return r;
-  const StencilGeom g = stencil_geom(p);
-  void* a = f;
-  void* b = p->d_scratch;
-  for (int64_t k = 0; k < nsteps; ++k) {
-    HIP_TRY(launch_step_bcc(p->dbl, g, b, a, p->d_coef, st));
-    void* tmp = a;
-    a = b;
-    b = tmp;
-  }
-  if (a != f) HIP_TRY(hipMemcpyAsync(f, a, bytes, hipMemcpyDeviceToDevice, st));
-  return QW_OK;
+  return traced("qw_bcc_step", stream, [&]() -> qw_status {
+    qw_status r = check_bcc(p, f, f);
+    if (r != QW_OK) return r;
+    if (nsteps < 0) return fail(QW_ERR_INVALID, "nsteps must be >= 0");
+    if (nsteps == 0) return QW_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = 2 * p->field_bytes;
+    r = ensure_scratch(p, bytes);
+    if (r != QW_OK) return r;
+    const StencilGeom g = stencil_geom(p);
+    void* a = f;
+    void* b = p->d_scratch;
+    for (int64_t k = 0; k < nsteps; ++k) {
+      HIP_TRY(launch_step_bcc(p->dbl, g, b, a, p->d_coef, st));
+      void* tmp = a;
+      a = b;
+      b = tmp;
+    }
+    if (a != f) HIP_TRY(hipMemcpyAsync(f, a, bytes, hipMemcpyDeviceToDevice, st));
+    return QW_OK;
+  });
 }
 
 qw_status qw_bcc_observables(qw_plan_t p, const void* f, const double* origin, qw_obs* out,
                              void* stream) {
-  qw_status r = check_bcc(p, f, f);
-  if (r != QW_OK) return r;
-  if (!origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
-  hipStream_t st = (hipStream_t)stream;
-  ObsGeom g = obs_geom(p);
-  for (int i = 0; i < 3; ++i) {
-    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
-    g.c[i] = origin[i];
-  }
-  HIP_TRY(launch_bcc_observables(p->dbl, g, f, p->d_partials, p->d_result, st));
-  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
-                         hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  const double* R = p->h_result;
-  memset(out, 0, sizeof *out);
-  out->norm2 = R[0];
-  const double inv = R[0] > 0.0 ? 1.0 / R[0] : 0.0;
-  for (int i = 0; i < 3; ++i) {
-    out->mean[i] = origin[i] + R[1 + i] * inv;
-    out->mean_cart[i] = out->mean[i];  // the coordinates are Cartesian
-  }
-  for (int k = 0; k < 6; ++k) out->second[k] = R[4 + k] * inv;
-  return QW_OK;
+  return traced("qw_bcc_observables", stream, [&]() -> qw_status {
+    qw_status r = check_bcc(p, f, f);
+    if (r != QW_OK) return r;
+    if (!origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    ObsGeom g = obs_geom(p);
+    for (int i = 0; i < 3; ++i) {
+      if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+      g.c[i] = origin[i];
+    }
+    HIP_TRY(launch_bcc_observables(p->dbl, g, f, p->d_partials, p->d_result, st));
+    HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double* R = p->h_result;
+    memset(out, 0, sizeof *out);
+    out->norm2 = R[0];
+    const double inv = R[0] > 0.0 ? 1.0 / R[0] : 0.0;
+    for (int i = 0; i < 3; ++i) {
+      out->mean[i] = origin[i] + R[1 + i] * inv;
+      out->mean_cart[i] = out->mean[i];  // the coordinates are Cartesian
+    }
+    for (int k = 0; k < 6; ++k) out->second[k] = R[4 + k] * inv;
+    return QW_OK;
+  });
 }
 
 qw_status qw_bcc_evolve_fft(qw_plan_t p, const void* f0, void* f_t, double t, void* stream) {
-  qw_status r = check_bcc(p, f0, f_t);
-  if (r != QW_OK) return r;
-  r = check_time(t);
-  if (r != QW_OK) return r;
-  return bcc_impl(p, f0, f_t, MODE_BCC, t, (hipStream_t)stream);
+  return traced("qw_bcc_evolve_fft", stream, [&]() -> qw_status {
+    qw_status r = check_bcc(p, f0, f_t);
+    if (r != QW_OK) return r;
+    r = check_time(t);
+    if (r != QW_OK) return r;
+    return bcc_impl(p, f0, f_t, MODE_BCC, t, (hipStream_t)stream);
+  });
 }
 
 qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, int64_t t,
                                     const double* origin, qw_obs* out, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!psi0 || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
-  for (int i = 0; i < p->dim; ++i)
-    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
-  r = check_time((double)t);
-  if (r != QW_OK) return r;
-  hipStream_t st = (hipStream_t)stream;
-  void* dst = psi_t;
-  if (!dst) {  // intermediate passes need a field; the result is not kept
-    r = ensure_scratch(p, p->field_bytes);
+  return traced("qw_evolve_fft_observables", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
     if (r != QW_OK) return r;
-    dst = p->d_scratch;
-  }
-  InstParam ip;
-  ip.m = p->m;
-  ip.n = p->n;
-  ip.t = (double)t;
-  const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
-  if (nb > 0) {
-    const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, psi_t != nullptr);
-    r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, &f);
+    if (!psi0 || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
+    for (int i = 0; i < p->dim; ++i)
+      if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+    r = check_time((double)t);
     if (r != QW_OK) return r;
-    HIP_TRY(launch_reduce_partials(1, nb, p->d_partials, p->d_partials + nb * kObsFields,
-                                   p->d_result, st));
-  } else {
-    r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, nullptr);
-    if (r != QW_OK) return r;
-    ObsGeom g = obs_geom(p);
-    for (int i = 0; i < p->dim; ++i) g.c[i] = origin[i];
-    HIP_TRY(launch_observables(p->dbl, g, 1, dst, nullptr, nullptr, p->d_partials, p->d_result,
-                               st));
-  }
-  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
-                         hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  finish_obs(p, p->h_result, origin, out);
-  out->overlap_re = out->overlap_im = out->ref_norm2 = 0.0;
-  return QW_OK;
+    hipStream_t st = (hipStream_t)stream;
+    void* dst = psi_t;
+    if (!dst) {  // intermediate passes need a field; the result is not kept
+      r = ensure_scratch(p, p->field_bytes);
+      if (r != QW_OK) return r;
+      dst = p->d_scratch;
+    }
+    InstParam ip;
+    ip.m = p->m;
+    ip.n = p->n;
+    ip.t = (double)t;
+    const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
+    if (nb > 0) {
+      const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, psi_t != nullptr);
+      r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, &f);
+      if (r != QW_OK) return r;
+      HIP_TRY(launch_reduce_partials(1, nb, p->d_partials, p->d_partials + nb * kObsFields,
+                                     p->d_result, st));
+    } else {
+      r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, nullptr);
+      if (r != QW_OK) return r;
+      ObsGeom g = obs_geom(p);
+      for (int i = 0; i < p->dim; ++i) g.c[i] = origin[i];
+      HIP_TRY(launch_observables(p->dbl, g, 1, dst, nullptr, nullptr, p->d_partials, p->d_result,
+                                 st));
+    }
+    HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    finish_obs(p, p->h_result, origin, out);
+    out->overlap_re = out->overlap_im = out->ref_norm2 = 0.0;
+    return QW_OK;
+  });
 }
 
 qw_status qw_newton_wigner(qw_plan_t p, const void* psi, const double* origin, qw_obs* sectors,
                            double* nw, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  r = dirac_only(p, "qw_newton_wigner");
-  if (r != QW_OK) return r;
-  if (!psi || !origin || !sectors || !nw) return fail(QW_ERR_INVALID, "NULL argument");
-  for (int i = 0; i < p->dim; ++i)
-    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
-  if (p->fourstep)
-    return fail(QW_ERR_UNSUPPORTED, "1D lattices above 4096 sites keep a transposed spectrum");
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
-  const size_t fb = p->field_bytes;
-  const size_t part_bytes =
-      sizeof(double) * kObsFields * (size_t)std::max<int64_t>(2 * nb + 2 * 64, 2 * kObsBlocks);
-  r = ensure_scratch(p, 2 * fb + part_bytes);
-  if (r != QW_OK) return r;
-  char* base = (char*)p->d_scratch;
-  void* f0 = base;
-  void* f1 = base + fb;
-  double* part = (double*)(base + 2 * fb);
-  // spectrum of psi, twice; sector projector and inverse of instance 0 (+)
-  // and 1 (-); reductions of both about the origin
-  r = transform_impl(p, 1, psi, f0, +1, nullptr, st);
-  if (r != QW_OK) return r;
-  HIP_TRY(hipMemcpyAsync(f1, f0, fb, hipMemcpyDeviceToDevice, st));
-  const int64_t L = contig_len(p);
-  PassGeom g = pass_geom(p, L, 2);
-  HIP_TRY(launch_fft_contig(p->dbl, MODE_PROJ_INV, L, f0, f0, g, p->d_tw, st, 8));
-  if (nb > 0) {
-    const ObsFuse f = make_fuse(p, origin, nullptr, part, false);
-    r = strided_passes(p, -1, f0, f0, 2, st, &f);
+  return traced("qw_newton_wigner", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
     if (r != QW_OK) return r;
-    HIP_TRY(launch_reduce_partials(2, nb, part, part + 2 * nb * kObsFields, p->d_result, st));
-  } else {
-    if (has_strided(p)) {
-      r = strided_passes(p, -1, f0, f0, 2, st, nullptr);
+    r = dirac_only(p, "qw_newton_wigner");
+    if (r != QW_OK) return r;
+    if (!psi || !origin || !sectors || !nw) return fail(QW_ERR_INVALID, "NULL argument");
+    for (int i = 0; i < p->dim; ++i)
+      if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+    if (p->fourstep)
+      return fail(QW_ERR_UNSUPPORTED, "1D lattices above 4096 sites keep a transposed spectrum");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
+    const size_t fb = p->field_bytes;
+    const size_t part_bytes =
+        sizeof(double) * kObsFields * (size_t)std::max<int64_t>(2 * nb + 2 * 64, 2 * kObsBlocks);
+    r = ensure_scratch(p, 2 * fb + part_bytes);
+    if (r != QW_OK) return r;
+    char* base = (char*)p->d_scratch;
+    void* f0 = base;
+    void* f1 = base + fb;
+    double* part = (double*)(base + 2 * fb);
+    // spectrum of psi, twice; sector projector and inverse of instance 0 (+)
+    // and 1 (-); reductions of both about the origin
+    r = transform_impl(p, 1, psi, f0, +1, nullptr, st);
+    if (r != QW_OK) return r;
+    HIP_TRY(hipMemcpyAsync(f1, f0, fb, hipMemcpyDeviceToDevice, st));
+    const int64_t L = contig_len(p);
+    PassGeom g = pass_geom(p, L, 2);
+    HIP_TRY(launch_fft_contig(p->dbl, MODE_PROJ_INV, L, f0, f0, g, p->d_tw, st, 8));
+    if (nb > 0) {
+      const ObsFuse f = make_fuse(p, origin, nullptr, part, false);
+      r = strided_passes(p, -1, f0, f0, 2, st, &f);
       if (r != QW_OK) return r;
+      HIP_TRY(launch_reduce_partials(2, nb, part, part + 2 * nb * kObsFields, p->d_result, st));
+    } else {
+      if (has_strided(p)) {
+        r = strided_passes(p, -1, f0, f0, 2, st, nullptr);
+        if (r != QW_OK) return r;
+      }
+      ObsGeom og = obs_geom(p);
+      for (int i = 0; i < p->dim; ++i) og.c[i] = origin[i];
+      HIP_TRY(launch_observables(p->dbl, og, 2, f0, nullptr, nullptr, part, p->d_result, st));
     }
-    ObsGeom og = obs_geom(p);
-    for (int i = 0; i < p->dim; ++i) og.c[i] = origin[i];
-    HIP_TRY(launch_observables(p->dbl, og, 2, f0, nullptr, nullptr, part, p->d_result, st));
-  }
-  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 2 * kObsFields,
-                         hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  for (int k = 0; k < 2; ++k) {
-    finish_obs(p, p->h_result + k * kObsFields, origin, &sectors[k]);
-    sectors[k].overlap_re = sectors[k].overlap_im = sectors[k].ref_norm2 = 0.0;
-  }
-  const double w0 = sectors[0].norm2, w1 = sectors[1].norm2, ws = w0 + w1;
-  for (int i = 0; i < 6; ++i) nw[i] = 0.0;
-  if (ws > 0.0)
-    for (int i = 0; i < 3; ++i) {
-      nw[i] = (w0 * sectors[0].mean[i] + w1 * sectors[1].mean[i]) / ws;
-      nw[3 + i] = (w0 * sectors[0].mean_cart[i] + w1 * sectors[1].mean_cart[i]) / ws;
+    HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 2 * kObsFields,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int k = 0; k < 2; ++k) {
+      finish_obs(p, p->h_result + k * kObsFields, origin, &sectors[k]);
+      sectors[k].overlap_re = sectors[k].overlap_im = sectors[k].ref_norm2 = 0.0;
     }
-  return QW_OK;
+    const double w0 = sectors[0].norm2, w1 = sectors[1].norm2, ws = w0 + w1;
+    for (int i = 0; i < 6; ++i) nw[i] = 0.0;
+    if (ws > 0.0)
+      for (int i = 0; i < 3; ++i) {
+        nw[i] = (w0 * sectors[0].mean[i] + w1 * sectors[1].mean[i]) / ws;
+        nw[3 + i] = (w0 * sectors[0].mean_cart[i] + w1 * sectors[1].mean_cart[i]) / ws;
+      }
+    return QW_OK;
+  });
 }
 
 qw_status qw_marginals(qw_plan_t p, const void* psi, const int64_t* origin, double* out,
                        int64_t out_len, int64_t* xmin, int64_t* len, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!xmin || !len) return fail(QW_ERR_INVALID, "NULL argument");
-  // Cartesian components of the generators (columns h_j): x = sum_j w_j h_j.
-  static const int H1[3][3] = {{1, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  static const int H2[3][3] = {{1, 1, 0}, {1, -1, 0}, {0, 0, 0}};
-  static const int H3[3][3] = {{1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
-  const int(*H)[3] = p->dim == 1 ? H1 : (p->dim == 2 ? H2 : H3);
-  MargGeom g;
-  memset(&g, 0, sizeof g);
-  g.dim = p->dim;
-  g.V = p->V;
-  g.s = p->s;
-  int total = 0;
-  for (int i = 0; i < p->dim; ++i) {
-    g.N[i] = p->N[i];
-    g.lg[i] = p->lg[i];
-    int lo = 0, hi = 0;
-    for (int j = 0; j < p->dim; ++j) {
-      g.H[i][j] = H[i][j];
-      const int half = (int)(p->N[j] / 2);
-      if (H[i][j] > 0) {
-        lo -= half;
-        hi += half - 1;
-      } else if (H[i][j] < 0) {
-        lo -= half - 1;
-        hi += half;
+  return traced("qw_marginals", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    if (!xmin || !len) return fail(QW_ERR_INVALID, "NULL argument");
+    // Cartesian components of the generators (columns h_j): x = sum_j w_j h_j.
+    static const int H1[3][3] = {{1, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    static const int H2[3][3] = {{1, 1, 0}, {1, -1, 0}, {0, 0, 0}};
+    static const int H3[3][3] = {{1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+    const int(*H)[3] = p->dim == 1 ? H1 : (p->dim == 2 ? H2 : H3);
+    MargGeom g;
+    memset(&g, 0, sizeof g);
+    g.dim = p->dim;
+    g.V = p->V;
+    g.s = p->s;
+    int total = 0;
+    for (int i = 0; i < p->dim; ++i) {
+      g.N[i] = p->N[i];
+      g.lg[i] = p->lg[i];
+      int lo = 0, hi = 0;
+      for (int j = 0; j < p->dim; ++j) {
+        g.H[i][j] = H[i][j];
+        const int half = (int)(p->N[j] / 2);
+        if (H[i][j] > 0) {
+          lo -= half;
+          hi += half - 1;
+        } else if (H[i][j] < 0) {
+          lo -= half - 1;
+          hi += half;
+        }
       }
+      g.xmin[i] = lo;
+      g.off[i] = total;
+      xmin[i] = lo;
+      len[i] = hi - lo + 1;
+      total += hi - lo + 1;
     }
-    g.xmin[i] = lo;
-    g.off[i] = total;
-    xmin[i] = lo;
-    len[i] = hi - lo + 1;
-    total += hi - lo + 1;
-  }
-  g.total = total;
-  if (!out) return QW_OK;  // layout query
-  if (!psi || !origin) return fail(QW_ERR_INVALID, "NULL argument");
-  if (out_len < total) return fail(QW_ERR_INVALID, "out holds %lld values, %d needed",
-                                   (long long)out_len, total);
-  if (p->dim > 1 && (size_t)total * sizeof(double) > 64 * 1024)
-    return fail(QW_ERR_UNSUPPORTED, "marginal bins exceed 64 KB of LDS");
-  for (int i = 0; i < p->dim; ++i) g.c[i] = (int)(origin[i] & (p->N[i] - 1));
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t nb = p->dim == 1 ? 0 : marginal_blocks(g);
-  const size_t bytes = sizeof(double) * ((size_t)nb * total + total);
-  r = ensure_scratch(p, bytes);
-  if (r != QW_OK) return r;
-  double* part = (double*)p->d_scratch;
-  double* dout = part + (size_t)nb * total;
-  HIP_TRY(launch_marginals(p->dbl, g, psi, part, dout, st));
-  HIP_TRY(hipMemcpyAsync(out, dout, sizeof(double) * total, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  return QW_OK;
+    g.total = total;
+    if (!out) return QW_OK;  // layout query
+    if (!psi || !origin) return fail(QW_ERR_INVALID, "NULL argument");
+    if (out_len < total) return fail(QW_ERR_INVALID, "out holds %lld values, %d needed",
+                                     (long long)out_len, total);
+    if (p->dim > 1 && (size_t)total * sizeof(double) > 64 * 1024)
+      return fail(QW_ERR_UNSUPPORTED, "marginal bins exceed 64 KB of LDS");
+    for (int i = 0; i < p->dim; ++i) g.c[i] = (int)(origin[i] & (p->N[i] - 1));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nb = p->dim == 1 ? 0 : marginal_blocks(g);
+    const size_t bytes = sizeof(double) * ((size_t)nb * total + total);
+    r = ensure_scratch(p, bytes);
+    if (r != QW_OK) return r;
+    double* part = (double*)p->d_scratch;
+    double* dout = part + (size_t)nb * total;
+    HIP_TRY(launch_marginals(p->dbl, g, psi, part, dout, st));
+    HIP_TRY(hipMemcpyAsync(out, dout, sizeof(double) * total, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return QW_OK;
+  });
 }
 
 qw_status qw_kspace_drift(qw_plan_t p, const void* psi, qw_drift* out, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!psi || !out) return fail(QW_ERR_INVALID, "NULL argument");
-  hipStream_t st = (hipStream_t)stream;
-  r = ensure_scratch(p, p->field_bytes);
-  if (r != QW_OK) return r;
-  // The spectrum in the storage order of the fused pass (the forward half of
-  // the evolution), in the plan's scratch field.
-  const int64_t L = contig_len(p);
-  PassGeom g = pass_geom(p, L, 1);
-  if (has_strided(p)) {
-    r = strided_passes(p, +1, p->d_scratch, psi, 1, st, nullptr);
+  return traced("qw_kspace_drift", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
     if (r != QW_OK) return r;
-    HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, p->d_scratch, p->d_scratch, g, p->d_tw, st));
-  } else {
-    HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, p->d_scratch, psi, g, p->d_tw, st));
-  }
-  HIP_TRY(launch_kdrift(p->dbl, g, L, p->d_scratch, p->d_partials, p->d_result, st));
-  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  const double* R = p->h_result;
-  memset(out, 0, sizeof *out);
-  const double inv = R[0] > 0.0 ? 1.0 / R[0] : 0.0;
-  for (int i = 0; i < p->dim; ++i) out->velocity[i] = -R[2 + i] * inv;
-  const double* v = out->velocity;
-  if (p->dim == 1) {
-    out->velocity_cart[0] = v[0];
-  } else if (p->dim == 2) {
-    out->velocity_cart[0] = v[0] + v[1];
-    out->velocity_cart[1] = v[0] - v[1];
-  } else {
-    out->velocity_cart[0] = v[0] + v[1] - v[2];
-    out->velocity_cart[1] = v[0] - v[1] + v[2];
-    out->velocity_cart[2] = v[0] - v[1] - v[2];
-  }
-  // Parseval: |hat psi|^2 sums to V |psi|^2 with the unnormalised transform.
-  const double iv = 1.0 / (double)p->V;
-  out->norm2 = R[0] * iv;
-  out->sector_norm2[0] = 0.5 * (R[0] + R[1]) * iv;
-  out->sector_norm2[1] = 0.5 * (R[0] - R[1]) * iv;
-  return QW_OK;
+    if (!psi || !out) return fail(QW_ERR_INVALID, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    r = ensure_scratch(p, p->field_bytes);
+    if (r != QW_OK) return r;
+    // The spectrum in the storage order of the fused pass (the forward half of
+    // the evolution), in the plan's scratch field.
+    const int64_t L = contig_len(p);
+    PassGeom g = pass_geom(p, L, 1);
+    if (has_strided(p)) {
+      r = strided_passes(p, +1, p->d_scratch, psi, 1, st, nullptr);
+      if (r != QW_OK) return r;
+      HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, p->d_scratch, p->d_scratch, g, p->d_tw, st));
+    } else {
+      HIP_TRY(launch_fft_contig(p->dbl, MODE_FWD, L, p->d_scratch, psi, g, p->d_tw, st));
+    }
+    HIP_TRY(launch_kdrift(p->dbl, g, L, p->d_scratch, p->d_partials, p->d_result, st));
+    HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double* R = p->h_result;
+    memset(out, 0, sizeof *out);
+    const double inv = R[0] > 0.0 ? 1.0 / R[0] : 0.0;
+    for (int i = 0; i < p->dim; ++i) out->velocity[i] = -R[2 + i] * inv;
+    const double* v = out->velocity;
+    if (p->dim == 1) {
+      out->velocity_cart[0] = v[0];
+    } else if (p->dim == 2) {
+      out->velocity_cart[0] = v[0] + v[1];
+      out->velocity_cart[1] = v[0] - v[1];
+    } else {
+      out->velocity_cart[0] = v[0] + v[1] - v[2];
+      out->velocity_cart[1] = v[0] - v[1] + v[2];
+      out->velocity_cart[2] = v[0] - v[1] - v[2];
+    }
+    // Parseval: |hat psi|^2 sums to V |psi|^2 with the unnormalised transform.
+    const double iv = 1.0 / (double)p->V;
+    out->norm2 = R[0] * iv;
+    out->sector_norm2[0] = 0.5 * (R[0] + R[1]) * iv;
+    out->sector_norm2[1] = 0.5 * (R[0] - R[1]) * iv;
+    return QW_OK;
+  });
 }
 
 qw_status qw_observables(qw_plan_t p, const void* psi, const double* origin, const void* ref,
                          qw_obs* out, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  if (!psi || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
-  hipStream_t st = (hipStream_t)stream;
-  ObsGeom g = obs_geom(p);
-  for (int i = 0; i < p->dim; ++i) {
-    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
-    g.c[i] = origin[i];
-  }
-  HIP_TRY(launch_observables(p->dbl, g, 1, psi, ref, nullptr, p->d_partials, p->d_result, st));
-  HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
-                         hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  finish_obs(p, p->h_result, origin, out);
-  if (!ref) out->overlap_re = out->overlap_im = out->ref_norm2 = 0.0;
-  return QW_OK;
+  return traced("qw_observables", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    if (!psi || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    ObsGeom g = obs_geom(p);
+    for (int i = 0; i < p->dim; ++i) {
+      if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+      g.c[i] = origin[i];
+    }
+    HIP_TRY(launch_observables(p->dbl, g, 1, psi, ref, nullptr, p->d_partials, p->d_result, st));
+    HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    finish_obs(p, p->h_result, origin, out);
+    if (!ref) out->overlap_re = out->overlap_im = out->ref_norm2 = 0.0;
+    return QW_OK;
+  });
 }
 
 // Taylor coefficients of omega(k) = arccos(n u(k)) at k0 (Cartesian), with
@@ -1833,30 +1947,34 @@ static qw_status prepare_impl(qw_plan_t p, void* psi, const StateInst& si, hipSt
 
 qw_status qw_prepare_state(qw_plan_t p, void* psi, const double* k0, double sigma,
                            const double* center, double c_plus, double c_minus, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  r = check_state_args(p, psi, k0, sigma, center, c_plus, c_minus);
-  if (r != QW_OK) return r;
-  return prepare_impl(p, psi, make_state_inst(p, p->m, k0, sigma, center, c_plus, c_minus),
-                      (hipStream_t)stream);
+  return traced("qw_prepare_state", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    r = check_state_args(p, psi, k0, sigma, center, c_plus, c_minus);
+    if (r != QW_OK) return r;
+    return prepare_impl(p, psi, make_state_inst(p, p->m, k0, sigma, center, c_plus, c_minus),
+                        (hipStream_t)stream);
+  });
 }
 
 qw_status qw_evolve_dispersive(qw_plan_t p, void* psi, const double* k0, double sigma,
                                const double* center, double c_plus, double c_minus, int order,
                                double t, void* stream) {
-  qw_status r = check_plan(p);
-  if (r != QW_OK) return r;
-  r = check_state_args(p, psi, k0, sigma, center, c_plus, c_minus);
-  if (r != QW_OK) return r;
-  if (order < 0 || order > 2) return fail(QW_ERR_UNSUPPORTED, "order must be 0, 1 or 2");
-  r = check_time(t);
-  if (r != QW_OK) return r;
-  StateInst si = make_state_inst(p, p->m, k0, sigma, center, c_plus, c_minus);
-  r = qw_dispersion_taylor(p->dim, p->m, k0, order, si.tay);
-  if (r != QW_OK) return r;
-  si.order = order;
-  si.tdisp = t;
-  return prepare_impl(p, psi, si, (hipStream_t)stream);
+  return traced("qw_evolve_dispersive", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    r = check_state_args(p, psi, k0, sigma, center, c_plus, c_minus);
+    if (r != QW_OK) return r;
+    if (order < 0 || order > 2) return fail(QW_ERR_UNSUPPORTED, "order must be 0, 1 or 2");
+    r = check_time(t);
+    if (r != QW_OK) return r;
+    StateInst si = make_state_inst(p, p->m, k0, sigma, center, c_plus, c_minus);
+    r = qw_dispersion_taylor(p->dim, p->m, k0, order, si.tay);
+    if (r != QW_OK) return r;
+    si.order = order;
+    si.tdisp = t;
+    return prepare_impl(p, psi, si, (hipStream_t)stream);
+  });
 }
 
 }  // extern "C"

@@ -130,6 +130,7 @@ struct GraphSlot {
 
 struct qw_server_s {
   size_t budget = 0, used = 0, peak_used = 0;
+  int64_t cancelled = 0;
   size_t laid_out = 0, peak_laid_out = 0;  // device bytes of the in-flight batches' layouts
   int max_batch = 1;
   int device = 0;
@@ -668,9 +669,32 @@ void worker_main(qw_server_s* s) {
 
 extern "C" {
 
+// QW_HBM_BUDGET: bytes, with an optional K, M or G suffix (powers of 1024).
+static size_t env_budget() {
+  const char* v = getenv("QW_HBM_BUDGET");
+  if (!v || !*v) return 0;
+  char* end = nullptr;
+  const double x = strtod(v, &end);
+  if (!(x > 0.0)) return 0;
+  double mul = 1.0;
+  if (end && (*end == 'K' || *end == 'k')) mul = 1024.0;
+  if (end && (*end == 'M' || *end == 'm')) mul = 1024.0 * 1024.0;
+  if (end && (*end == 'G' || *end == 'g')) mul = 1024.0 * 1024.0 * 1024.0;
+  return (size_t)(x * mul);
+}
+
 qw_status qw_server_create(qw_server_t* out, size_t budget_bytes, int max_batch, int nstreams) {
   if (!out) return fail(QW_ERR_INVALID, "out is NULL");
   *out = nullptr;
+  if (budget_bytes == 0) {
+    budget_bytes = env_budget();
+    if (budget_bytes == 0) {
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
+        return fail(QW_ERR_DEVICE, "hipMemGetInfo failed (pass a budget)");
+      budget_bytes = free_b / 2;
+    }
+  }
   if (budget_bytes < (1u << 20)) return fail(QW_ERR_INVALID, "budget must be at least 1 MiB");
   if (max_batch < 1 || max_batch > 4096) return fail(QW_ERR_INVALID, "max_batch must lie in [1, 4096]");
   if (nstreams < 1 || nstreams > 16) return fail(QW_ERR_INVALID, "nstreams must lie in [1, 16]");
@@ -768,6 +792,50 @@ qw_status qw_server_wait(qw_server_t s, int64_t ticket, qw_result* out) {
   return QW_OK;
 }
 
+qw_status qw_server_cancel(qw_server_t s, int64_t ticket, int* cancelled) {
+  if (!s || !cancelled) return fail(QW_ERR_INVALID, "NULL argument");
+  *cancelled = 0;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!s->live.count(ticket)) return fail(QW_ERR_INVALID, "unknown or already collected ticket");
+  for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+    if (it->ticket != ticket) continue;
+    qw_result res;
+    memset(&res, 0, sizeof res);
+    res.ticket = ticket;
+    res.status = QW_ERR_CANCELLED;
+    res.queue_s = res.latency_s = now_s() - it->t_submit;
+    s->results[ticket] = res;
+    ++s->completed;
+    ++s->cancelled;
+    s->queue.erase(it);
+    *cancelled = 1;
+    s->cv_done.notify_all();
+    s->cv.notify_all();
+    break;
+  }
+  return QW_OK;
+}
+
+qw_status qw_server_wait_for(qw_server_t s, int64_t ticket, double timeout_s, qw_result* out,
+                             int* done) {
+  if (!s || !out || !done) return fail(QW_ERR_INVALID, "NULL argument");
+  if (!(timeout_s >= 0.0)) return fail(QW_ERR_INVALID, "timeout must be >= 0");
+  *done = 0;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (!s->live.count(ticket)) return fail(QW_ERR_INVALID, "unknown or already collected ticket");
+  const bool ready = s->cv_done.wait_for(
+      lk, std::chrono::duration<double>(timeout_s),
+      [&] { return s->results.count(ticket) > 0 || !s->live.count(ticket); });
+  if (!ready) return QW_OK;  // timed out: the request stays live
+  if (!s->results.count(ticket)) return fail(QW_ERR_INVALID, "result collected by another caller");
+  *out = s->results[ticket];
+  s->results.erase(ticket);
+  s->live.erase(ticket);
+  *done = 1;
+  s->cv_done.notify_all();
+  return QW_OK;
+}
+
 qw_status qw_server_hold(qw_server_t s, int hold) {
   if (!s) return fail(QW_ERR_INVALID, "server is NULL");
   {
@@ -795,6 +863,8 @@ qw_status qw_server_stats(qw_server_t s, qw_server_info* out) {
   out->graph_launches = s->graph_launches;
   out->slot_bytes = (int64_t)s->slot_bytes;
   out->launch_host_ns = s->launch_host_ns;
+  out->budget_bytes = (int64_t)s->budget;
+  out->cancelled = s->cancelled;
   return QW_OK;
 }
 

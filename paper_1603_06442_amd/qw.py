@@ -17,7 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqw.so")
 
-QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE = range(5)
+QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE, QW_ERR_CANCELLED = range(6)
 QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_noalloc",
@@ -29,6 +29,7 @@ EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_noalloc"
            "qw_set_schedule", "qw_get_schedule", "qw_set_step_kernel", "qw_autotune",
            "qw_last_error", "qw_version",
            "qw_server_create", "qw_server_configure", "qw_server_submit", "qw_server_poll", "qw_server_wait",
+           "qw_server_cancel", "qw_server_wait_for",
            "qw_server_hold", "qw_server_stats", "qw_server_destroy")
 
 
@@ -68,7 +69,7 @@ class QwServerInfo(ctypes.Structure):
         "submitted", "completed", "batches", "queued", "inflight_batches",
         "max_inflight_batches", "used_bytes", "peak_used_bytes", "laid_out_bytes",
         "peak_laid_out_bytes", "graphs_captured", "graph_launches", "slot_bytes",
-        "launch_host_ns")]
+        "launch_host_ns", "budget_bytes", "cancelled")]
 
 
 def _load():
@@ -116,6 +117,8 @@ def _load():
         "qw_server_submit": [vp, ctypes.POINTER(QwRequest), ctypes.POINTER(i64)],
         "qw_server_poll": [vp, i64, ctypes.POINTER(QwResult), ctypes.POINTER(cint)],
         "qw_server_wait": [vp, i64, ctypes.POINTER(QwResult)],
+        "qw_server_cancel": [vp, i64, ctypes.POINTER(cint)],
+        "qw_server_wait_for": [vp, i64, dbl, ctypes.POINTER(QwResult), ctypes.POINTER(cint)],
         "qw_server_hold": [vp, cint],
         "qw_server_stats": [vp, ctypes.POINTER(QwServerInfo)],
         "qw_server_destroy": [vp],
@@ -430,9 +433,10 @@ def _obs_dict(o, dim):
 class Server:
     """Continuous-batching server (qw_server_*): requests are Gaussian
     particle states evolved to their own time with their own mass; results
-    are the reductions of psi(t) about the request's centre."""
+    are the reductions of psi(t) about the request's centre. budget_bytes = 0
+    takes QW_HBM_BUDGET, else half of the free device memory."""
 
-    def __init__(self, budget_bytes, max_batch=16, nstreams=2, graphs=True, autotune=True,
+    def __init__(self, budget_bytes=0, max_batch=16, nstreams=2, graphs=True, autotune=True,
                  max_graphs=256):
         self._h = ctypes.c_void_p()
         _check(LIB.qw_server_create(ctypes.byref(self._h), int(budget_bytes), int(max_batch),
@@ -490,6 +494,22 @@ class Server:
         res = QwResult()
         _check(LIB.qw_server_wait(self._h, int(ticket), ctypes.byref(res)))
         return self._convert(res)
+
+    def wait_for(self, ticket, timeout_s):
+        """qw_server_wait_for: the result, or None if the request has not
+        completed within timeout_s seconds (it then stays pending)."""
+        res = QwResult()
+        done = ctypes.c_int()
+        _check(LIB.qw_server_wait_for(self._h, int(ticket), float(timeout_s), ctypes.byref(res),
+                                      ctypes.byref(done)))
+        return self._convert(res) if done.value else None
+
+    def cancel(self, ticket):
+        """qw_server_cancel: True if the request was still queued and is now
+        cancelled (its result carries status QW_ERR_CANCELLED)."""
+        c = ctypes.c_int()
+        _check(LIB.qw_server_cancel(self._h, int(ticket), ctypes.byref(c)))
+        return bool(c.value)
 
     def hold(self, on=True):
         """qw_server_hold: queue without launching (on) or resume (off)."""

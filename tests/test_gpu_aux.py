@@ -1,0 +1,195 @@
+"""Run-time machinery around the kernels, through the C ABI: the persisted
+schedule cache of qw_autotune (QW_TUNE_CACHE), the debug mode that waits
+after every entry point (QW_DEBUG), run-to-run determinism of the hot
+path, and the serving calls for cancellation, timed waits and the default
+byte budget (QW_HBM_BUDGET)."""
+import os
+import time
+
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1603_06442_amd import qw as mod
+    return mod
+
+
+class _env:
+    """Set one environment variable for the duration of a with-block."""
+
+    def __init__(self, name, value):
+        self.name, self.value = name, value
+
+    def __enter__(self):
+        self.old = os.environ.get(self.name)
+        os.environ[self.name] = self.value
+
+    def __exit__(self, *exc):
+        if self.old is None:
+            del os.environ[self.name]
+        else:
+            os.environ[self.name] = self.old
+
+
+def _state(plan, k0=(0.1, 0.1, 0.1), sigma=4.0):
+    n = plan.N if isinstance(plan.N, int) else plan.N[0]
+    x = plan.empty()
+    plan.prepare_state(x, list(k0)[:plan.dim], sigma, [n // 2] * plan.dim, 0.6, 0.8)
+    return x
+
+
+def _cache_lines(path):
+    with open(path) as f:
+        return [ln.split() for ln in f if ln.startswith("qw-tune-v1")]
+
+
+def test_tune_cache_round_trip(qw, tmp_path):
+    """A timed schedule is appended once; a later plan of the same shape
+    takes it without timing; a line added by hand for that key wins; a
+    malformed line is ignored; a plan of another shape gets a line of its own."""
+    path = str(tmp_path / "tune.txt")
+    with _env("QW_TUNE_CACHE", path):
+        p = qw.Plan(3, 64, 0.1, "c64")
+        ms = p.autotune()
+        first = p.schedule()
+        lines = _cache_lines(path)
+        assert len(lines) == 1
+        key = lines[0][:6]
+        assert key[2:] == ["dirac", "d3", "64x64x64", "c64"]
+        assert tuple(int(v) for v in lines[0][6:10]) == first
+        assert abs(float(lines[0][10]) - ms) < 1e-5
+
+        q = qw.Plan(3, 64, 0.3, "c64")
+        q.set_schedule(0, 8, 64, 1)
+        assert abs(q.autotune() - ms) < 1e-5      # the recorded time: not re-timed
+        assert q.schedule() == first
+        assert len(_cache_lines(path)) == 1
+
+        with open(path, "a") as f:
+            f.write(" ".join(key) + " 0 4 128 4 0.5\n")
+            f.write(" ".join(key) + " 0 4 100 4 0.25\n")   # 100 threads not allowed: ignored
+            f.write("garbage line\n")
+        q.set_schedule(0, 8, 64, 1)
+        assert q.autotune() == pytest.approx(0.5)
+        assert q.schedule() == (0, 4, 128, 4)
+
+        r = qw.Plan(3, 32, 0.1, "c128")
+        r.autotune()
+        lines = _cache_lines(path)
+        assert len(lines) == 4
+        assert lines[-1][2:6] == ["dirac", "d3", "32x32x32", "c128"]
+
+        # the schedule taken from the file computes what the timed one does
+        x = _state(q)
+        a = q.evolve_fft(x, 1000)
+        q.set_schedule(*first)
+        b = q.evolve_fft(x, 1000)
+        assert (a - b).abs().max().item() < 2e-5
+
+
+def test_debug_mode_runs_the_hot_path(qw):
+    """With QW_DEBUG set every entry point waits for its stream and checks
+    for a failed kernel; the results are those of the normal mode."""
+    p = qw.Plan(3, 32, 0.2, "c64")
+    x = _state(p)
+    a = p.evolve_fft(x, 77)
+    s = x.clone()
+    p.step(s, 3)
+    with _env("QW_DEBUG", "1"):
+        b = p.evolve_fft(x, 77)
+        s2 = x.clone()
+        p.step(s2, 3)
+        o = p.evolve_fft_observables(x, 77, [16, 16, 16])
+    assert torch.equal(a, b)
+    assert torch.equal(s, s2)
+    assert abs(o["norm2"] - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_hot_path_is_deterministic(qw, dtype):
+    """Two runs of the Fourier jump with its fused reduction and of the
+    stencil step give the same bits (no atomics or order-dependent sums)."""
+    p = qw.Plan(3, 64, 0.02, dtype)
+    x = _state(p)
+    outs = [p.evolve_fft_observables(x, 12345, [32, 32, 32]) for _ in range(2)]
+    assert outs[0] == outs[1]
+    y = [p.evolve_fft(x, 999) for _ in range(2)]
+    assert torch.equal(y[0], y[1])
+    s = [x.clone() for _ in range(2)]
+    for f in s:
+        p.step(f, 5)
+    assert torch.equal(s[0], s[1])
+    o = [p.observables(f, [32, 32, 32]) for f in s]
+    assert o[0] == o[1]
+
+
+def _req(t):
+    return dict(dim=3, N=16, m=0.2, k0=[0.1, 0.0, 0.2], sigma=2.5, center=[8, 8, 8],
+                c_plus=1.0, c_minus=0.0, t=t)
+
+
+def test_server_cancel_and_timed_wait(qw):
+    """A queued request is cancelled (its result carries QW_ERR_CANCELLED);
+    one already done is not; a timed wait returns None while the server is
+    held and the result once it ran; a collected ticket is unknown."""
+    srv = qw.Server(64 << 20, max_batch=4, nstreams=1)
+    try:
+        srv.hold(True)
+        tk = [srv.submit(**_req(t)) for t in (10, 20, 30)]
+        assert srv.wait_for(tk[0], 0.05) is None        # held: still queued
+        assert srv.cancel(tk[1]) is True
+        assert srv.cancel(tk[1]) is False               # already finished (cancelled)
+        st = srv.stats()
+        assert st["cancelled"] == 1 and st["queued"] == 2
+        srv.hold(False)
+        r0 = srv.wait_for(tk[0], 60.0)
+        assert r0 is not None and r0["status"] == qw.QW_OK
+        assert abs(r0["obs"]["norm2"] - 1.0) < 5e-5
+        r1 = srv.wait(tk[1])
+        assert r1["status"] == qw.QW_ERR_CANCELLED and r1["batch_size"] == 0
+        for _ in range(600):                            # completed, not collected
+            if srv.stats()["completed"] == 3:
+                break
+            time.sleep(0.1)
+        assert srv.stats()["completed"] == 3
+        assert srv.cancel(tk[2]) is False               # ran: not cancelled
+        with pytest.raises(qw.QwError):
+            srv.wait_for(tk[2], -1.0)
+        assert srv.wait(tk[2])["status"] == qw.QW_OK
+        with pytest.raises(qw.QwError):
+            srv.cancel(tk[0])                           # collected
+        with pytest.raises(qw.QwError):
+            srv.wait_for(tk[0], 0.0)
+    finally:
+        srv.close()
+
+
+def test_server_default_budget(qw):
+    """budget 0: QW_HBM_BUDGET when set (with a K/M/G suffix), else half of
+    the free device memory."""
+    with _env("QW_HBM_BUDGET", "96M"):
+        srv = qw.Server(0, max_batch=2, nstreams=1)
+        try:
+            assert srv.stats()["budget_bytes"] == 96 << 20
+            r = srv.wait(srv.submit(**_req(5)))
+            assert r["status"] == qw.QW_OK
+        finally:
+            srv.close()
+    old = os.environ.pop("QW_HBM_BUDGET", None)
+    try:
+        free, _ = torch.cuda.mem_get_info()
+        srv = qw.Server(0, max_batch=2, nstreams=1)
+        try:
+            b = srv.stats()["budget_bytes"]
+            assert 0.3 * free <= b <= 0.6 * free
+        finally:
+            srv.close()
+    finally:
+        if old is not None:
+            os.environ["QW_HBM_BUDGET"] = old
