@@ -71,7 +71,14 @@ typedef enum {
   QW_ERR_CANCELLED = 5     /* serving: the request was cancelled before it ran */
 } qw_status;
 
-typedef enum { QW_C64 = 0, QW_C128 = 1 } qw_dtype;
+/* The last two enumerators give the type the range of int, so that any value
+ * a caller passes is representable and rejected, not undefined behaviour. */
+typedef enum {
+  QW_C64 = 0,
+  QW_C128 = 1,
+  QW_DTYPE_INT_MIN_ = -0x7fffffff - 1,
+  QW_DTYPE_INT_MAX_ = 0x7fffffff
+} qw_dtype;
 
 /* Reductions of one field (Sec. 5.2: position operator X and <psi|X|psi>;
  * Sec. 5.1: the overlap <phi|psi>). Positions are taken about a caller origin

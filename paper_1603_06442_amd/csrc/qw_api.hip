@@ -1204,13 +1204,19 @@ static qw_status check_time(double t) {
   if (!(fabs(t) <= kMaxT)) return fail(QW_ERR_UNSUPPORTED, "|t| must be finite and at most 2^53");
   return QW_OK;
 }
+// Integer times are compared as integers: 2^53 + 1 would round to 2^53.
+static qw_status check_time(int64_t t) {
+  constexpr int64_t kMaxI = int64_t(1) << 53;
+  if (t > kMaxI || t < -kMaxI) return fail(QW_ERR_UNSUPPORTED, "|t| must be at most 2^53");
+  return QW_OK;
+}
 
 qw_status qw_evolve_fft(qw_plan_t p, const void* psi0, void* psi_t, int64_t t, void* stream) {
   return traced("qw_evolve_fft", stream, [&]() -> qw_status {
     qw_status r = check_plan(p);
     if (r != QW_OK) return r;
     if (!psi0 || !psi_t) return fail(QW_ERR_INVALID, "field pointer is NULL");
-    r = check_time((double)t);
+    r = check_time(t);
     if (r != QW_OK) return r;
     InstParam ip;
     ip.m = p->m;
@@ -1406,7 +1412,7 @@ qw_status qw_evolve_fft_timed(qw_plan_t p, const void* psi0, void* psi_t, int64_
     qw_status r = check_plan(p);
     if (r != QW_OK) return r;
     if (!psi0 || !psi_t || !pass_ms || !npass) return fail(QW_ERR_INVALID, "NULL argument");
-    r = check_time((double)t);
+    r = check_time(t);
     if (r != QW_OK) return r;
     hipStream_t st = (hipStream_t)stream;
     PassTimer tm;
@@ -1446,7 +1452,7 @@ qw_status qw_evolve_fft_batched(qw_plan_t p, int B, const void* in, void* out, c
     if (!in || !out || !m || !t) return fail(QW_ERR_INVALID, "NULL argument");
     for (int b = 0; b < B; ++b) {
       if (!(m[b] >= 0.0 && m[b] <= 1.0)) return fail(QW_ERR_INVALID, "m[%d] outside [0, 1]", b);
-      r = check_time((double)t[b]);
+      r = check_time(t[b]);
       if (r != QW_OK) return r;
     }
     hipStream_t st = (hipStream_t)stream;
@@ -1618,7 +1624,7 @@ qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, 
     if (!psi0 || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
     for (int i = 0; i < p->dim; ++i)
       if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
-    r = check_time((double)t);
+    r = check_time(t);
     if (r != QW_OK) return r;
     hipStream_t st = (hipStream_t)stream;
     void* dst = psi_t;
