@@ -498,6 +498,25 @@ def main():
         "c128_fused_pass_ms": round(ms128[2], 4) if len(ms128) == 5 else None,
         "norm_drift_c64": abs(plan.observables(y64, w["center"])["norm2"] - 1.0),
         "norm_drift_c128": abs(p128.observables(y128, w["center"])["norm2"] - 1.0)}
+    # The whole <x>(t) series of the workload in one call (the spectrum of
+    # psi0 taken once, three passes per time), in both precisions, against
+    # the per-time fused jumps at a few times.
+    line["zb_series"] = {}
+    for name, pl, xs in (("c64", plan, psi0), ("c128", p128, x128)):
+        pl.evolve_fft_series(xs, times[:4], w["center"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ser = pl.evolve_fft_series(xs, times, w["center"])
+        el = time.perf_counter() - t0
+        dev = 0.0
+        for i in (0, len(times) // 2, len(times) - 1):
+            o = pl.evolve_fft_observables(xs, times[i], w["center"])
+            dev = max(dev, max(abs(a - b) for a, b in zip(ser[i]["mean"], o["mean"])))
+        line["zb_series"][name] = {
+            "times": len(times), "ms_per_series": round(1e3 * el, 3),
+            "ms_per_time": round(1e3 * el / len(times), 4),
+            "evolutions_per_s": round(len(times) / el, 1),
+            "max_mean_dev_vs_fused_jump": dev}
     del p128, x128, y128, diff
     # Proposition 1 beside the exact jump: the order-2 dispersive state at
     # t = 100 (one state preparation with the phases and one inverse

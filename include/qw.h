@@ -308,6 +308,21 @@ qw_status qw_marginals(qw_plan_t plan, const void* psi, const int64_t* origin, d
 qw_status qw_evolve_fft_observables(qw_plan_t plan, const void* psi0, void* psi_t, int64_t t,
                                     const double* origin, qw_obs* out, void* stream);
 
+/* The reductions of psi(t_i) = U^{t_i} psi0 about origin (as
+ * qw_evolve_fft_observables) for n times t[0..n) (HOST int64, |t_i| <= 2^53,
+ * any order), out[0..n) (HOST). The series of the position expectation of
+ * Sec. 5.2 in one call: the spectrum of psi0 is computed once (Sec. 4: it
+ * does not depend on t), and each time costs the per-wave-vector power
+ * with the inverse transform, its reductions taken in the last pass, with
+ * no wait between times (d = 2, 3 Dirac plans: three field passes per time
+ * instead of five; Weyl plans and 1D lattices run a full jump per time).
+ * psi0 is not modified; the plan's scratch grows to two fields. The results
+ * agree with qw_evolve_fft_observables at each t to rounding (the forward
+ * transform is taken by a separate pass). 1 <= n <= 2^24. Waits once, at
+ * the end. */
+qw_status qw_evolve_fft_series(qw_plan_t plan, const void* psi0, int64_t n, const int64_t* t,
+                               const double* origin, qw_obs* out, void* stream);
+
 /* Write a Gaussian particle/antiparticle state into psi (Sec. 5.1,
  * Definition 1; Sec. 5.2, superposition c+ psi+ + c- psi-):
  *   hat psi(q) = c+ a+(q)/|a+| + c- a-(q)/|a-|,

@@ -494,6 +494,8 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
                                                     const cx<T>* __restrict__ tw) {
   constexpr int S = contig_components(DIM, MODE);
   constexpr int TT = L / E;
+  // omega(q) from the plan's table, one instance (the time in g.single)
+  constexpr bool kTabApply = MODE == MODE_EVOLVE_TAB || MODE == MODE_APPLY_INV_TAB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x;
@@ -541,8 +543,8 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
     const int64_t pen = g.pen0 + (gpc - b * g.ppi);
     const int64_t base = b * S * g.V + pen * L;
 
-    if constexpr (MODE != MODE_INV && MODE != MODE_APPLY_INV && MODE != MODE_PROJ_INV &&
-                  MODE != MODE_BCC_INV) {
+    if constexpr (MODE != MODE_INV && MODE != MODE_APPLY_INV && MODE != MODE_APPLY_INV_TAB &&
+                  MODE != MODE_PROJ_INV && MODE != MODE_BCC_INV) {
       if (DIM == 1 && g.fourstep) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -592,7 +594,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
           v[c][E - 1] = y[c];
         }
       }
-    } else if constexpr (MODE == MODE_EVOLVE_TAB && sizeof(T) == 4 && E <= 4) {
+    } else if constexpr (kTabApply && sizeof(T) == 4 && E <= 4) {
       // Four wave-vectors per thread: unrolled (independent chains, no
       // register rotation).
       const InstParam ip = g.single;
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
 #pragma unroll
         for (int c = 0; c < S; ++c) v[c][e] = y[c];
       }
-    } else if constexpr (MODE == MODE_EVOLVE_TAB && sizeof(T) == 4) {
+    } else if constexpr (kTabApply && sizeof(T) == 4) {
       const InstParam ip = g.single;
       const PencilTrig pt = pencil_trig<DIM>(g, pen);
 #pragma unroll 1
@@ -642,8 +644,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
           v[c][E - 1] = y[c];
         }
       }
-    } else if constexpr (MODE == MODE_EVOLVE || MODE == MODE_EVOLVE_TAB ||
-                         MODE == MODE_APPLY_INV) {
+    } else if constexpr (MODE == MODE_EVOLVE || MODE == MODE_APPLY_INV || kTabApply) {
       const InstParam ip = g.inst ? g.inst[b] : g.single;
       // One wave-vector per iteration, deliberately not unrolled (an unrolled
       // loop lets the compiler hoist every element's table reads and keep
@@ -658,7 +659,7 @@ __global__ __launch_bounds__(512) void k_fft_contig(cx<T>* __restrict__ out,
         cx<T> y[S];
 #pragma unroll
         for (int c = 0; c < S; ++c) y[c] = v[c][0];
-        apply_q<T, DIM, MODE == MODE_EVOLVE_TAB>(y, g, ip, j1, j2, j3, pen * L + z);
+        apply_q<T, DIM, kTabApply>(y, g, ip, j1, j2, j3, pen * L + z);
 #pragma unroll
         for (int c = 0; c < S; ++c) {
 #pragma unroll
@@ -844,6 +845,10 @@ static hipError_t dispatch_mode(int mode, int64_t L, cx<T>* out, const cx<T>* in
     case MODE_EVOLVE_TAB:
       return e4 ? dispatch_dim<T, MODE_EVOLVE_TAB, 4>(L, out, in, g, tw, st)
                 : dispatch_dim<T, MODE_EVOLVE_TAB, 8>(L, out, in, g, tw, st);
+    case MODE_APPLY_INV_TAB:
+      if (!g.omega || g.inst) return hipErrorInvalidValue;
+      return e4 ? dispatch_dim<T, MODE_APPLY_INV_TAB, 4>(L, out, in, g, tw, st)
+                : dispatch_dim<T, MODE_APPLY_INV_TAB, 8>(L, out, in, g, tw, st);
     // Cubic-supercell field: eight components per pencil, kBccE elements each.
     case MODE_BCC:
       if (g.dim != 3) return hipErrorInvalidValue;

@@ -66,6 +66,11 @@ struct qw_plan_s {
   int64_t partials_len = 0;
   double* d_result = nullptr;
   double* h_result = nullptr;  // pinned
+  // Results of a time series (qw_evolve_fft_series): kObsFields doubles per
+  // time, on the device and pinned; they only grow.
+  double* d_series = nullptr;
+  double* h_series = nullptr;
+  int64_t series_cap = 0;
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
   qw::InstParam* d_inst = nullptr;
@@ -104,6 +109,8 @@ struct qw_plan_s {
     if (d_partials) (void)hipFree(d_partials);
     if (d_result) (void)hipFree(d_result);
     if (h_result) (void)hipHostFree(h_result);
+    if (d_series) (void)hipFree(d_series);
+    if (h_series) (void)hipHostFree(h_series);
     if (d_scratch) (void)hipFree(d_scratch);
     if (d_inst) (void)hipFree(d_inst);
     if (h_inst) (void)hipHostFree(h_inst);

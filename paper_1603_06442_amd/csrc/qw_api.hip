@@ -1661,6 +1661,103 @@ qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, 
   });
 }
 
+// Result slots of a time series: grow to n times (replaced buffers are kept
+// until qw_destroy, like the plan's other buffers).
+static qw_status ensure_series(qw_plan_t p, int64_t n) {
+  if (p->series_cap >= n) return QW_OK;
+  int64_t cap = 64;
+  while (cap < n) cap <<= 1;
+  const size_t bytes = sizeof(double) * kObsFields * (size_t)cap;
+  double* d = nullptr;
+  double* h = nullptr;
+  HIP_TRY(hipMalloc((void**)&d, bytes));
+  hipError_t e = hipHostMalloc((void**)&h, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    HIP_TRY(e);
+  }
+  if (p->d_series) p->retired_dev.push_back(p->d_series);
+  if (p->h_series) p->retired_host.push_back(p->h_series);
+  p->d_series = d;
+  p->h_series = h;
+  p->series_cap = cap;
+  return QW_OK;
+}
+
+qw_status qw_evolve_fft_series(qw_plan_t p, const void* psi0, int64_t n, const int64_t* t,
+                               const double* origin, qw_obs* out, void* stream) {
+  return traced("qw_evolve_fft_series", stream, [&]() -> qw_status {
+    qw_status r = check_plan(p);
+    if (r != QW_OK) return r;
+    if (!psi0 || !t || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
+    if (n < 1 || n > (int64_t(1) << 24)) return fail(QW_ERR_INVALID, "n must lie in [1, 2^24]");
+    for (int i = 0; i < p->dim; ++i)
+      if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+    for (int64_t i = 0; i < n; ++i) {
+      r = check_time(t[i]);
+      if (r != QW_OK) return r;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    r = ensure_series(p, n);
+    if (r != QW_OK) return r;
+    const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
+    // The spectrum of psi0 once, then per time the apply with the inverse
+    // transform; that needs the natural-order spectrum and a strided pass
+    // to take the reductions in (d = 2, 3), else each time is a full jump.
+    const bool spectral = !p->weyl && !p->fourstep && nb > 0;
+    r = ensure_scratch(p, (spectral ? 2 : 1) * p->field_bytes);
+    if (r != QW_OK) return r;
+    char* spec = (char*)p->d_scratch;
+    void* work = spectral ? (void*)(spec + p->field_bytes) : p->d_scratch;
+    const int64_t L = contig_len(p);
+    const double* omega = nullptr;
+    if (spectral) {
+      r = transform_impl(p, 1, psi0, spec, +1, nullptr, st);
+      if (r != QW_OK) return r;
+      omega = omega_table(p, st);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      InstParam ip;
+      ip.m = p->m;
+      ip.n = p->n;
+      ip.t = (double)t[i];
+      double* res = p->d_series + (size_t)kObsFields * i;
+      if (spectral) {
+        PassGeom g = pass_geom(p, L, 1);
+        g.single = ip;
+        g.omega = omega;
+        const int mode = omega ? MODE_APPLY_INV_TAB : MODE_APPLY_INV;
+        HIP_TRY(launch_fft_contig(p->dbl, mode, L, work, spec, g, p->d_tw, st, p->ce));
+        const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, false);
+        r = strided_passes(p, -1, work, work, 1, st, &f);
+        if (r != QW_OK) return r;
+        HIP_TRY(launch_reduce_partials(1, nb, p->d_partials, p->d_partials + nb * kObsFields,
+                                       res, st));
+      } else if (nb > 0) {
+        const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, false);
+        r = evolve_impl(p, 1, psi0, work, nullptr, ip, st, &f);
+        if (r != QW_OK) return r;
+        HIP_TRY(launch_reduce_partials(1, nb, p->d_partials, p->d_partials + nb * kObsFields,
+                                       res, st));
+      } else {
+        r = evolve_impl(p, 1, psi0, work, nullptr, ip, st, nullptr);
+        if (r != QW_OK) return r;
+        ObsGeom og = obs_geom(p);
+        for (int a = 0; a < p->dim; ++a) og.c[a] = origin[a];
+        HIP_TRY(launch_observables(p->dbl, og, 1, work, nullptr, nullptr, p->d_partials, res, st));
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(p->h_series, p->d_series, sizeof(double) * kObsFields * (size_t)n,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) {
+      finish_obs(p, p->h_series + (size_t)kObsFields * i, origin, &out[i]);
+      out[i].overlap_re = out[i].overlap_im = out[i].ref_norm2 = 0.0;
+    }
+    return QW_OK;
+  });
+}
+
 qw_status qw_newton_wigner(qw_plan_t p, const void* psi, const double* origin, qw_obs* sectors,
                            double* nw, void* stream) {
   return traced("qw_newton_wigner", stream, [&]() -> qw_status {

@@ -71,7 +71,8 @@ enum {
   MODE_BCC_INV = 8,
   MODE_WEYL = 9,  // two-component Weyl walk (d = 2, 3): W_q^t, omega per wave-vector
   MODE_BCC_TAB = 10,  // MODE_BCC with omega(kappa) from the plan's cubic-supercell table
-  MODE_WEYL_TAB = 11  // MODE_WEYL with omega(q) from the plan's table
+  MODE_WEYL_TAB = 11,  // MODE_WEYL with omega(q) from the plan's table
+  MODE_APPLY_INV_TAB = 12  // MODE_APPLY_INV, one instance, omega(q) from the plan's table
 };
 
 constexpr bool is_bcc_mode(int mode) {

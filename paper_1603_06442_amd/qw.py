@@ -22,7 +22,8 @@ QW_C64, QW_C128 = 0, 1
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_noalloc",
            "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
-           "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables", "qw_newton_wigner",
+           "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables",
+           "qw_evolve_fft_series", "qw_newton_wigner",
            "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft", "qw_bcc_step", "qw_bcc_observables",
            "qw_kspace_drift",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
@@ -118,6 +119,8 @@ def _load():
         "qw_server_poll": [vp, i64, ctypes.POINTER(QwResult), ctypes.POINTER(cint)],
         "qw_server_wait": [vp, i64, ctypes.POINTER(QwResult)],
         "qw_server_cancel": [vp, i64, ctypes.POINTER(cint)],
+        "qw_evolve_fft_series": [vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(dbl),
+                                 ctypes.POINTER(QwObs), vp],
         "qw_server_wait_for": [vp, i64, dbl, ctypes.POINTER(QwResult), ctypes.POINTER(cint)],
         "qw_server_hold": [vp, cint],
         "qw_server_stats": [vp, ctypes.POINTER(QwServerInfo)],
@@ -343,6 +346,21 @@ class Plan:
                                              _stream(stream)))
         return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
                 "mean_cart": list(o.mean_cart)}
+
+    def evolve_fft_series(self, psi0, times, origin, stream=None):
+        """qw_evolve_fft_series: the reductions of U^t psi0 about origin for
+        every t in times (one call, one wait); a list of dicts as
+        evolve_fft_observables returns."""
+        times = [int(x) for x in times]
+        n = len(times)
+        if n < 1:
+            raise ValueError("need at least one time")
+        tarr = (ctypes.c_int64 * n)(*times)
+        outs = (QwObs * n)()
+        _check(LIB.qw_evolve_fft_series(self._h, self._field(psi0, name="psi0"), n, tarr,
+                                        _darr(origin, self.dim), outs, _stream(stream)))
+        return [{"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
+                 "mean_cart": list(o.mean_cart)} for o in outs]
 
     def newton_wigner(self, psi, origin, stream=None):
         """qw_newton_wigner: sector-projected mean position; returns

@@ -184,6 +184,11 @@ static void device_run() {
       EXPECT_STATUS(qw_evolve_fft_observables(p, x, nullptr, 1000, ctr, &o2, st), QW_OK);
       EXPECT(near(o1.norm2, 1.0, tol) && near(o1.mean[0], o2.mean[0], 1e-9));
       EXPECT_STATUS(qw_evolve_fft_real(p, x, z, 10.5, st), QW_OK);
+      int64_t ts[3] = {1000, -3, 1000};
+      qw_obs so[3];
+      EXPECT_STATUS(qw_evolve_fft_series(p, x, 3, ts, ctr, so, st), QW_OK);
+      EXPECT(near(so[0].norm2, 1.0, tol) && near(so[0].mean[0], o1.mean[0], 1e-3) &&
+             so[0].mean[0] == so[2].mean[0]);
       EXPECT_STATUS(qw_step(p, y, 3, st), QW_OK);
       EXPECT_STATUS(qw_step_noalloc(p, y, 2, st), QW_OK);
       EXPECT_STATUS(qw_transform(p, y, z, 1, st), QW_OK);
