@@ -347,10 +347,11 @@ qw_status qw_evolve_fft_timed(qw_plan_t plan, const void* psi0, void* psi_t, int
 
 /* Measurement and tuning of the position-space step (process-wide; not
  * thread-safe against concurrent steps). two_step = 1 runs pairs of steps of
- * the 3D Dirac walk in complex64 (planes of at least 16 x 32 sites, or
- * 8 x 64 with tile_shape 1) as one launch that reads and writes the field
- * once per pair (temporal blocking); 0 (the default) runs every step as its
- * own launch, which measured faster. Both give the same bits. tile_shape: 0 = 16 x 32 output tiles, 1 = 8 x 64;
+ * the 3D Dirac walk in complex64 (planes that hold one output tile) as one
+ * launch that reads and writes the field once per pair (temporal blocking);
+ * 0 (the default) runs every step as its own launch, which measured faster.
+ * Both give the same bits. tile_shape: 0 = 16 x 32 output tiles, 1 = 8 x 64,
+ * 2 = 16 x 16, 3 = 8 x 32;
  * chunk: planes of axis 0 per workgroup (0 = chosen from the lattice, else a
  * power of two in [2, 256]). */
 qw_status qw_set_step_kernel(int two_step, int tile_shape, int chunk);

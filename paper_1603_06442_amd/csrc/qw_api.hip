@@ -1243,7 +1243,7 @@ qw_status qw_evolve_fft_real(qw_plan_t p, const void* psi0, void* psi_t, double 
 
 qw_status qw_set_step_kernel(int two_step, int tile_shape, int chunk) {
   if (two_step != 0 && two_step != 1) return fail(QW_ERR_INVALID, "two_step must be 0 or 1");
-  if (tile_shape != 0 && tile_shape != 1) return fail(QW_ERR_INVALID, "tile_shape must be 0 or 1");
+  if (tile_shape < 0 || tile_shape > 3) return fail(QW_ERR_INVALID, "tile_shape must lie in [0, 3]");
   if (chunk != 0 && (chunk < 2 || chunk > 256 || (chunk & (chunk - 1))))
     return fail(QW_ERR_INVALID, "chunk must be 0 or a power of two in [2, 256]");
   g_step2_off = two_step == 0;

@@ -1369,12 +1369,13 @@ __global__ __launch_bounds__(TN2 * TN3) void k_step3d_ring2(cx<T>* __restrict__ 
 }
 
 bool step3d_ring2_ok(const StencilGeom& g) {
-  return g.dim == 3 && !g.weyl && g.N[1] >= 16 && g.N[2] >= 32 && g.N[0] >= 2;
+  return g.dim == 3 && !g.weyl && g.N[1] >= 8 && g.N[2] >= 16 && g.N[0] >= 2;
 }
 
 // Tile shape of the two-step kernel (16 x 32: 612 first-step sites per 512
-// outputs; 8 x 64: 660).
-static int g_ring2_shape = 0;  // 0: 16 x 32, 1: 8 x 64
+// outputs, 128 KB of LDS; 8 x 64: 660, 141 KB; 16 x 16: 324 per 256, 70 KB;
+// 8 x 32: 340 per 256, 74 KB — the last two fit two workgroups per CU).
+static int g_ring2_shape = 0;  // 0: 16 x 32, 1: 8 x 64, 2: 16 x 16, 3: 8 x 32
 static int g_ring2_chunk = 0;  // planes per workgroup; 0: from the lattice
 
 template <int TN2, int TN3, int PF>
@@ -1412,14 +1413,23 @@ static hipError_t launch_ring2_t(const StencilGeom& g, int B, void* out, const v
 
 bool step2_ok(bool dbl, const StencilGeom& g) {
   if (dbl || !step3d_ring2_ok(g)) return false;
-  return g_ring2_shape == 0 ? (g.N[1] >= 16 && g.N[2] >= 32) : (g.N[1] >= 8 && g.N[2] >= 64);
+  switch (g_ring2_shape) {
+    case 0: return g.N[1] >= 16 && g.N[2] >= 32;
+    case 1: return g.N[1] >= 8 && g.N[2] >= 64;
+    case 2: return g.N[1] >= 16 && g.N[2] >= 16;
+    default: return g.N[1] >= 8 && g.N[2] >= 32;
+  }
 }
 
 hipError_t launch_step2(bool dbl, const StencilGeom& g, int B, void* out, const void* in,
                         const void* coefs, hipStream_t st) {
   if (!step2_ok(dbl, g)) return hipErrorInvalidValue;
-  if (g_ring2_shape == 0) return launch_ring2_t<16, 32, 2>(g, B, out, in, coefs, st);
-  return launch_ring2_t<8, 64, 2>(g, B, out, in, coefs, st);
+  switch (g_ring2_shape) {
+    case 0: return launch_ring2_t<16, 32, 2>(g, B, out, in, coefs, st);
+    case 1: return launch_ring2_t<8, 64, 2>(g, B, out, in, coefs, st);
+    case 2: return launch_ring2_t<16, 16, 2>(g, B, out, in, coefs, st);
+    default: return launch_ring2_t<8, 32, 2>(g, B, out, in, coefs, st);
+  }
 }
 
 void set_step2_config(int shape, int chunk) {

@@ -435,7 +435,8 @@ def dispersion_taylor(dim, m, k0, order):
 def set_step_kernel(two_step=False, tile_shape=0, chunk=0):
     """qw_set_step_kernel (measurement): pairs of 3D complex64 steps in one
     launch (two_step) or one launch per step (the default); tile shape
-    0 = 16 x 32, 1 = 8 x 64; planes per workgroup (0 = automatic)."""
+    0 = 16 x 32, 1 = 8 x 64, 2 = 16 x 16, 3 = 8 x 32; planes per workgroup
+    (0 = automatic)."""
     _check(LIB.qw_set_step_kernel(1 if two_step else 0, int(tile_shape), int(chunk)))
 
 

@@ -76,9 +76,12 @@ def test_step_matches_oracle(qw, d, shape, m, dtype):
     assert ob.rel_l2(to_np(x), ref) < tol_step(dtype, 7)
 
 
-@pytest.mark.parametrize("tile", [0, 1])
+TWO_STEP_TILES = {0: (16, 32), 1: (8, 64), 2: (16, 16), 3: (8, 32)}
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
 @pytest.mark.parametrize("shape", [(2, 16, 64), (4, 16, 32), (16, 16, 64), (8, 32, 128),
-                                   (64, 16, 32), (4, 8, 64)])
+                                   (64, 16, 32), (4, 8, 64), (4, 16, 16), (2, 8, 32)])
 @pytest.mark.parametrize("m", [0.0, 0.3, 1.0])
 def test_two_step_kernel_matches_oracle_and_single_steps(qw, shape, m, tile):
     """Pairs of complex64 3D steps run as one launch (both rings in LDS):
@@ -86,9 +89,9 @@ def test_two_step_kernel_matches_oracle_and_single_steps(qw, shape, m, tile):
     step), and bitwise equal to the same steps one launch each. Shapes whose
     planes are one tile (16 x 32, or 8 x 64) so that every halo wraps onto
     the tile itself, N1 = 2 (the whole axis in one chunk), several tiles and
-    chunks; both tile shapes."""
-    if (tile == 1 and (shape[1] < 8 or shape[2] < 64) or
-            tile == 0 and (shape[1] < 16 or shape[2] < 32)):
+    chunks; every tile shape."""
+    t2, t3 = TWO_STEP_TILES[tile]
+    if shape[1] < t2 or shape[2] < t3:
         pytest.skip("plane smaller than the tile")
     psi0 = rand_field(3, shape, 33)
     plan = qw.Plan(3, list(shape), m, "c64")
@@ -121,12 +124,13 @@ def test_two_step_kernel_batched_and_chunks(qw):
         qw.set_step_kernel(False)
         want = torch.stack([to_dev(p, plan) for p in psis]).contiguous()
         plan.step_batched(want, ms, 4)
-        for chunk in (2, 4, 8, 16, 32):
-            qw.set_step_kernel(True, 0, chunk)
-            x = torch.stack([to_dev(p, plan) for p in psis]).contiguous()
-            plan.step_batched(x, ms, 4)
-            torch.cuda.synchronize()
-            assert torch.equal(x, want), chunk
+        for tile in (0, 2):
+            for chunk in (2, 4, 8, 16, 32):
+                qw.set_step_kernel(True, tile, chunk)
+                x = torch.stack([to_dev(p, plan) for p in psis]).contiguous()
+                plan.step_batched(x, ms, 4)
+                torch.cuda.synchronize()
+                assert torch.equal(x, want), (tile, chunk)
     finally:
         qw.set_step_kernel(False, 0, 0)
     for b in range(3):
