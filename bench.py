@@ -87,6 +87,22 @@ def cpu_baseline(w, budget_s=15.0):
                      "1..1e5 schedule in %.1f s, scaled by (128/256)^3 to the 256^3 unit"
                      % (done, el),
            "host_threads_available": os.cpu_count(), "cpu_model": _cpu_model()}
+    # The oracle's position-space stepping (np.roll over the transition
+    # matrices, complex128, one thread) on the 64^3 torus, as context for
+    # the stencil's site-steps/s.
+    from oracle import stepper
+    from paper_1603_06442_amd.inputs import random_field
+    f64 = random_field(np.random.default_rng(3), 3, 64, 4)
+    t0 = time.perf_counter()
+    nst = 0
+    while nst < 64 and time.perf_counter() - t0 < 3.0:
+        f64 = stepper.evolve_steps(f64, table, 2)
+        nst += 2
+    el = time.perf_counter() - t0
+    out["context_stencil_oracle_64"] = {
+        "site_steps_per_s": round(nst * 64 ** 3 / el, 1), "steps": nst, "seconds": round(el, 3),
+        "cores": 1, "what": "oracle stepping (np.roll over the transition matrices, complex128, "
+                            "single thread) on the 64^3 torus"}
     try:
         import scipy.fft as sfft
         nw = os.cpu_count() or 1
