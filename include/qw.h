@@ -318,7 +318,7 @@ qw_status qw_evolve_fft_observables(qw_plan_t plan, const void* psi0, void* psi_
  * instead of five; Weyl plans and 1D lattices run a full jump per time).
  * psi0 is not modified; the plan's scratch grows to two fields. The results
  * agree with qw_evolve_fft_observables at each t to rounding (the forward
- * transform is taken by a separate pass). 1 <= n <= 2^24. Waits once, at
+ * transform is taken by a separate pass). 1 <= n <= 2^20. Waits once, at
  * the end. */
 qw_status qw_evolve_fft_series(qw_plan_t plan, const void* psi0, int64_t n, const int64_t* t,
                                const double* origin, qw_obs* out, void* stream);
@@ -493,8 +493,9 @@ qw_status qw_server_wait(qw_server_t server, int64_t ticket, qw_result* out);
  * *cancelled = 1 if it was cancelled, 0 if it is already on the device or
  * done (it then completes normally). QW_ERR_INVALID for an unknown ticket. */
 qw_status qw_server_cancel(qw_server_t server, int64_t ticket, int* cancelled);
-/* qw_server_wait for at most timeout_s seconds: *done = 1 and *out filled if
- * the request completed in time, else *done = 0 and it stays pending. */
+/* qw_server_wait for at most timeout_s seconds (>= 0; 1e9 or more waits
+ * without limit): *done = 1 and *out filled if the request completed in
+ * time, else *done = 0 and it stays pending. */
 qw_status qw_server_wait_for(qw_server_t server, int64_t ticket, double timeout_s,
                              qw_result* out, int* done);
 /* hold != 0: queue requests but launch none (batches already on the device

@@ -1690,7 +1690,7 @@ qw_status qw_evolve_fft_series(qw_plan_t p, const void* psi0, int64_t n, const i
     qw_status r = check_plan(p);
     if (r != QW_OK) return r;
     if (!psi0 || !t || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
-    if (n < 1 || n > (int64_t(1) << 24)) return fail(QW_ERR_INVALID, "n must lie in [1, 2^24]");
+    if (n < 1 || n > (int64_t(1) << 20)) return fail(QW_ERR_INVALID, "n must lie in [1, 2^20]");
     for (int i = 0; i < p->dim; ++i)
       if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
     for (int64_t i = 0; i < n; ++i) {

@@ -823,9 +823,14 @@ qw_status qw_server_wait_for(qw_server_t s, int64_t ticket, double timeout_s, qw
   *done = 0;
   std::unique_lock<std::mutex> lk(s->mu);
   if (!s->live.count(ticket)) return fail(QW_ERR_INVALID, "unknown or already collected ticket");
-  const bool ready = s->cv_done.wait_for(
-      lk, std::chrono::duration<double>(timeout_s),
-      [&] { return s->results.count(ticket) > 0 || !s->live.count(ticket); });
+  auto finished = [&] { return s->results.count(ticket) > 0 || !s->live.count(ticket); };
+  bool ready;
+  if (timeout_s >= 1e9) {  // beyond what a clock duration can hold: no limit
+    s->cv_done.wait(lk, finished);
+    ready = true;
+  } else {
+    ready = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), finished);
+  }
   if (!ready) return QW_OK;  // timed out: the request stays live
   if (!s->results.count(ticket)) return fail(QW_ERR_INVALID, "result collected by another caller");
   *out = s->results[ticket];

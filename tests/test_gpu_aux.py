@@ -148,7 +148,7 @@ def test_server_cancel_and_timed_wait(qw):
         st = srv.stats()
         assert st["cancelled"] == 1 and st["queued"] == 2
         srv.hold(False)
-        r0 = srv.wait_for(tk[0], 60.0)
+        r0 = srv.wait_for(tk[0], 1e300)  # no limit
         assert r0 is not None and r0["status"] == qw.QW_OK
         assert abs(r0["obs"]["norm2"] - 1.0) < 5e-5
         r1 = srv.wait(tk[1])
