@@ -18,15 +18,13 @@ DRIVER = os.path.join(SAN_DIR, "sanitize_driver")
 SUPP = os.path.join(ROOT, "tests", "native", "lsan.supp")
 
 
-def _run(mode, timeout):
+def _run(mode, timeout, cwd):
     if not os.path.exists(DRIVER):
         pytest.skip("sanitizer build not present (run __graft_entry__.build())")
     env = dict(os.environ)
     env["ASAN_OPTIONS"] = "halt_on_error=1:detect_leaks=1:abort_on_error=0:exitcode=23"
     env["LSAN_OPTIONS"] = "suppressions=%s:print_suppressions=0" % SUPP
     env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1:exitcode=24"
-    cwd = os.path.join(ROOT, "gpurun_out") if mode == "device" else SAN_DIR
-    os.makedirs(cwd, exist_ok=True)
     print("running", DRIVER, mode, flush=True)
     p = subprocess.run([DRIVER, mode], env=env, cwd=cwd, capture_output=True, text=True,
                        timeout=timeout)
@@ -38,12 +36,13 @@ def _run(mode, timeout):
     assert out.rstrip().endswith("OK") or "\nOK\n" in out
 
 
-def test_host_paths_under_sanitizers():
+def test_host_paths_under_sanitizers(tmp_path):
     """No device needed: argument validation of every entry point and the
     error paths of plan and server creation."""
-    _run("host", timeout=120)
+    _run("host", 120, str(tmp_path))
 
 
 @pytest.mark.gpu
-def test_device_run_under_host_sanitizers():
-    _run("device", timeout=300)
+def test_device_run_under_host_sanitizers(tmp_path):
+    # the driver writes its schedule cache file into its working directory
+    _run("device", 300, str(tmp_path))
