@@ -10,6 +10,7 @@
 // fastest-varying thread index, so LDS is addressed [pos][column]: the lanes
 // of a wave touch consecutive words.
 #include <algorithm>
+#include <atomic>
 
 #include "qw_internal.h"
 
@@ -63,6 +64,217 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
 #pragma unroll
     for (int e = 0; e < E; ++e) out[base + (int64_t)(t + TT * e) * I] = v[e];
   }
+}
+
+// Length-256 complex64 passes with their loads staged through LDS by the
+// global-to-LDS loads of gfx950 (16 bytes per lane), double-buffered: a
+// workgroup of 512 threads takes kStagedTiles tiles of 32 columns (256-byte
+// rows) in turn, and the next tile's loads are in flight while the current
+// one is transformed and stored, without holding registers. The tiles and
+// their arithmetic are those of the register kernel at this length (E = 16,
+// 32 columns), so both give the same bits.
+//
+// Each wave stages exactly the rows its own threads read: thread (p, t) of
+// the team holds rows t + 16 e, and slot (t >> 1) * 32 + 2 e + (t & 1) of
+// the buffer holds row t + 16 e, so a wave waits for its own loads only.
+// Tiles per workgroup, measured on the n1 inverse pass at 256^3 (8192
+// tiles): 8 tiles 0.197 ms (1024 workgroups, four per CU in turn), 4 tiles
+// 0.207, 2 tiles 0.219, 1 tile 0.243, against 0.213 for the register
+// kernel; 6 and 12 (workgroup counts not a multiple of the 256 CUs) 0.227
+// and 0.217. Launches of fewer than kStagedMinTiles tiles (four workgroups
+// of eight tiles per CU) keep the register kernel.
+constexpr int kStagedCols = 32;
+constexpr int kStagedTiles = 8;
+constexpr int64_t kStagedMinTiles = 8192;
+
+// Workgroup barrier that orders LDS accesses only: this wave's LDS
+// operations complete, then all waves meet. Unlike __syncthreads it does not
+// wait for the vector memory counter, so loads into LDS issued earlier stay
+// in flight.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// This wave's vector memory operations (its loads into LDS among them)
+// complete. Written out: the compiler does not count loads into LDS issued
+// in an earlier iteration of a loop as outstanding at their use.
+__device__ __forceinline__ void vm_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// One tile (256 rows of 32 columns from `tile`, row stride I) into buf.
+__device__ __forceinline__ void stage_tile256(cx<float>* __restrict__ buf,
+                                              const cx<float>* __restrict__ in, int64_t tile,
+                                              int64_t I, int tid) {
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+  const int64_t col = 2 * (l & 15);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    // one instruction: four 256-byte rows, slots 4j .. 4j+3 of this wave
+    const int q = 4 * j + (l >> 4);
+    const int64_t r = 2 * w + (q & 1) + 16 * (q >> 1);
+    __builtin_amdgcn_global_load_lds(in + tile + r * I + col,
+                                     buf + (w * 32 + 4 * j) * kStagedCols, 16, 0, 0);
+  }
+}
+
+typedef float qw_f2 __attribute__((ext_vector_type(2)));
+typedef float qw_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ qw_f2 f2(cx<float> z) { return qw_f2{z.x, z.y}; }
+
+// The 256-point transform of the thread's column as two radix-16 Stockham
+// stages (those of fft_team at E = 16) with the stage twiddles in registers
+// (they depend on the thread's place only), so no global load is issued
+// while a tile's loads are in flight. X: this thread's column of the tile
+// buffer. The exchange's LDS accesses are written out with their waits:
+// compiled ones would also wait for the next tile's loads into the other
+// buffer, which the compiler cannot tell apart from X.
+template <int SIGN>
+__device__ __forceinline__ void fft256_regs(cx<float> (&v)[16], cx<float>* __restrict__ X, int t,
+                                            const cx<float> (&w)[16]) {
+  typedef __attribute__((address_space(3))) cx<float>* lds_ptr;
+  dft_reg<16, SIGN>(v);
+  // X[(16 t + r) * kStagedCols] = v[r]: byte offset 4096 t + 256 r, i.e.
+  // 32 r in the 8-byte units of ds_write2_b64 (r < 8; then from + 2048)
+  const unsigned aw = (unsigned)(size_t)(lds_ptr)(X + 16 * t * kStagedCols);
+  asm volatile(
+      "ds_write2_b64 %0, %2, %3 offset0:0 offset1:32\n\t"
+      "ds_write2_b64 %0, %4, %5 offset0:64 offset1:96\n\t"
+      "ds_write2_b64 %0, %6, %7 offset0:128 offset1:160\n\t"
+      "ds_write2_b64 %0, %8, %9 offset0:192 offset1:224\n\t"
+      "ds_write2_b64 %1, %10, %11 offset0:0 offset1:32\n\t"
+      "ds_write2_b64 %1, %12, %13 offset0:64 offset1:96\n\t"
+      "ds_write2_b64 %1, %14, %15 offset0:128 offset1:160\n\t"
+      "ds_write2_b64 %1, %16, %17 offset0:192 offset1:224\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "s_barrier" ::"v"(aw),
+      "v"(aw + 2048u), "v"(f2(v[0])), "v"(f2(v[1])), "v"(f2(v[2])), "v"(f2(v[3])), "v"(f2(v[4])),
+      "v"(f2(v[5])), "v"(f2(v[6])), "v"(f2(v[7])), "v"(f2(v[8])), "v"(f2(v[9])), "v"(f2(v[10])),
+      "v"(f2(v[11])), "v"(f2(v[12])), "v"(f2(v[13])), "v"(f2(v[14])), "v"(f2(v[15]))
+      : "memory");
+  // v[e] = X[(t + 16 e) * kStagedCols]: byte offset 4096 e, i.e. 8 e in the
+  // 512-byte units of ds_read2st64_b64, two elements per instruction
+  const unsigned a = (unsigned)(size_t)(lds_ptr)(X + t * kStagedCols);
+  qw_f4 q0, q1, q2, q3, q4, q5, q6, q7;
+  asm volatile(
+      "ds_read2st64_b64 %0, %8 offset0:0 offset1:8\n\t"
+      "ds_read2st64_b64 %1, %8 offset0:16 offset1:24\n\t"
+      "ds_read2st64_b64 %2, %8 offset0:32 offset1:40\n\t"
+      "ds_read2st64_b64 %3, %8 offset0:48 offset1:56\n\t"
+      "ds_read2st64_b64 %4, %8 offset0:64 offset1:72\n\t"
+      "ds_read2st64_b64 %5, %8 offset0:80 offset1:88\n\t"
+      "ds_read2st64_b64 %6, %8 offset0:96 offset1:104\n\t"
+      "ds_read2st64_b64 %7, %8 offset0:112 offset1:120\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(q0), "=&v"(q1), "=&v"(q2), "=&v"(q3), "=&v"(q4), "=&v"(q5), "=&v"(q6), "=&v"(q7)
+      : "v"(a)
+      : "memory");
+  const qw_f4 q[8] = {q0, q1, q2, q3, q4, q5, q6, q7};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    v[2 * i] = mk(q[i].x, q[i].y);
+    v[2 * i + 1] = mk(q[i].z, q[i].w);
+  }
+  lds_barrier();
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
+  dft_reg<16, SIGN>(v);
+}
+
+// The tile loop of the staged kernels: tiles blockIdx.x * kStagedTiles + k
+// of the nblk (nblk_i per outer index), each transformed and handed to
+// epi(v, tile, first element of the tile) with the thread's 16 values,
+// rows t + 16 e of column p. buf: 2 * 256 * kStagedCols elements of LDS.
+template <int SIGN, typename Epi>
+__device__ __forceinline__ void staged256_loop(cx<float>* __restrict__ buf,
+                                               const cx<float>* __restrict__ in, int64_t I,
+                                               int64_t nblk_i, int64_t nblk, const OuterMap& om,
+                                               const cx<float>* __restrict__ tw, Epi epi) {
+  const int tid = threadIdx.x;
+  const int p = tid & (kStagedCols - 1), t = tid >> 5;
+  cx<float> w[16];
+  w[0] = mk(1.0f, 0.0f);
+#pragma unroll
+  for (int r = 1; r < 16; ++r) w[r] = twiddle<SIGN>(tw, r * t * (TWN / 256));
+  auto tile_base = [&](int64_t blk) -> int64_t {
+    const int64_t o = blk / nblk_i;
+    const int64_t i0 = (blk - o * nblk_i) * kStagedCols;
+    const int64_t comp = o / om.ocount;
+    const int64_t plane = om.o0 + (o - comp * om.ocount);
+    return comp * om.ostride + plane * 256 * I + i0;
+  };
+  const int64_t first = (int64_t)blockIdx.x * kStagedTiles;
+  if (first >= nblk) return;
+  const int n = nblk - first < kStagedTiles ? (int)(nblk - first) : kStagedTiles;
+  int64_t cur = tile_base(first);
+  stage_tile256(buf, in, cur, I, tid);
+  const int s0 = (t >> 1) * 32 + (t & 1);
+  for (int k = 0; k < n; ++k) {
+    cx<float>* X = buf + (k & 1) * (256 * kStagedCols);
+    cx<float>* Y = buf + ((k + 1) & 1) * (256 * kStagedCols);
+    vm_drain();
+    cx<float> v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = X[(s0 + 2 * e) * kStagedCols + p];
+    // every wave has its rows before the exchange writes X, and the last
+    // reads of Y (the previous tile's exchange and epilogue) are done
+    lds_barrier();
+    int64_t nxt = 0;
+    if (k + 1 < n) {
+      nxt = tile_base(first + k + 1);
+      stage_tile256(Y, in, nxt, I, tid);
+    }
+    fft256_regs<SIGN>(v, X + p, t, w);
+    epi(v, first + k, cur);
+    cur = nxt;
+  }
+}
+
+// NT: non-temporal stores (a template parameter: as a branch inside the
+// loop the two store forms were merged into plain stores).
+template <int SIGN, bool NT>
+__global__ __launch_bounds__(512) void k_fft_strided_staged(cx<float>* __restrict__ out,
+                                                            const cx<float>* __restrict__ in,
+                                                            int64_t I, int64_t nblk_i,
+                                                            int64_t nblk, OuterMap om,
+                                                            const cx<float>* __restrict__ tw) {
+  __shared__ __align__(16) cx<float> buf[2 * 256 * kStagedCols];
+  const int p = threadIdx.x & (kStagedCols - 1), t = threadIdx.x >> 5;
+  staged256_loop<SIGN>(buf, in, I, nblk_i, nblk, om, tw,
+                             [&](const cx<float>(&v)[16], int64_t, int64_t base) {
+                               const int64_t b = base + p;
+#pragma unroll
+                               for (int e = 0; e < 16; ++e) {
+                                 if constexpr (NT)
+                                   store_nt(&out[b + (int64_t)(t + 16 * e) * I], v[e]);
+                                 else
+                                   out[b + (int64_t)(t + 16 * e) * I] = v[e];
+                               }
+                             });
+}
+
+// The staged kernels take a pass when they apply: complex64, length 256,
+// whole 32-column tiles, inverse direction (the forward passes measured no
+// faster staged: 0.227 and 0.190 ms against 0.229 and 0.191 at 256^3, where
+// the inverse ones went 0.187 -> 0.174 ms and 0.213 -> 0.197 ms) and at
+// least kStagedMinTiles tiles; unless switched off (qw_set_fft_kernel).
+static std::atomic<bool> g_staged{true};
+
+void set_fft_staged(bool on) { g_staged.store(on, std::memory_order_relaxed); }
+
+static bool use_staged(bool dbl, int sign, int64_t L, int64_t O, int64_t I) {
+  return g_staged.load(std::memory_order_relaxed) && !dbl && sign < 0 && L == 256 &&
+         I % kStagedCols == 0 && O * (I / kStagedCols) >= kStagedMinTiles;
+}
+
+static hipError_t run_staged(cx<float>* out, const cx<float>* in, int64_t O, int64_t I,
+                             const OuterMap& om, const cx<float>* tw, hipStream_t st) {
+  const int64_t nblk_i = I / kStagedCols;
+  const int64_t nblk = O * nblk_i;
+  const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
+  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
+  auto kern = om.nt ? k_fft_strided_staged<-1, true> : k_fft_strided_staged<-1, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
+  return hipGetLastError();
 }
 
 // Columns per workgroup of a strided pass: 256 bytes of each row (32
@@ -150,6 +362,8 @@ hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, con
                                    int64_t I, const void* tw, hipStream_t st, bool nt) {
   const OuterMap om{ocount, o0, ostride, nt ? 1 : 0};
   const int64_t O = ncomp * ocount;
+  if (use_staged(dbl, sign, L, O, I))
+    return run_staged((cx<float>*)out, (const cx<float>*)in, O, I, om, (const cx<float>*)tw, st);
   if (dbl) {
     auto o = (cx<double>*)out;
     auto i = (const cx<double>*)in;
@@ -178,6 +392,87 @@ hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const vo
 // transformed values are reduced where they are produced (the field need
 // not be read again, nor written at all when only the reductions are
 // wanted). Whole fields: outer index o = b * s + component.
+//
+// The arithmetic of the reductions of one tile of P columns, shared by the
+// register and the staged kernel so that both give the same partials:
+// (1) over the thread's E values (rows t + TT e of column col): only the
+// axis-0 displacement varies along the pass, so three moments in it
+// suffice (the other axes are fixed per column);
+template <typename T, int L, int E>
+__device__ __forceinline__ void obs_thread_moments(const cx<T> (&v)[E], int t, int64_t I,
+                                                   int64_t col, int dim, const AxisImage32& a0,
+                                                   double& S0, double& S1, double& S11) {
+  constexpr int TT = L / E;
+  S0 = 0.0;
+  S1 = 0.0;
+  S11 = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int pos = t + TT * e;
+    const double w = min_image32(dim == 1 ? pos * (int)I + (int)col : pos, a0);
+    const double x = (double)v[e].x, y = (double)v[e].y;
+    const double pr = x * x + y * y;
+    const double wp = w * pr;
+    S0 += pr;
+    S1 += wp;
+    S11 += w * wp;
+  }
+}
+
+// (2) the ten moment fields of column cc from its sums c0, c1, c2 over the
+// pass (the other axes' displacements wb, wc fixed per column);
+__device__ __forceinline__ void obs_column_disp(int64_t cc, const double (&org)[3],
+                                                const ObsFuse& f, double& wb, double& wc) {
+  wb = 0.0;
+  wc = 0.0;
+  if (f.dim == 2) {
+    wb = min_image(cc, axis_image(org[1], f.N[1]));
+  } else if (f.dim == 3) {
+    wb = min_image(cc >> f.lg[2], axis_image(org[1], f.N[1]));
+    wc = min_image(cc & (f.N[2] - 1), axis_image(org[2], f.N[2]));
+  }
+}
+
+__device__ __forceinline__ double obs_field(int k, double c0, double c1, double c2, double wb,
+                                            double wc) {
+  switch (k) {
+    case 0: return c0;
+    case 1: return c1;
+    case 2: return wb * c0;
+    case 3: return wc * c0;
+    case 4: return c2;
+    case 5: return wb * wb * c0;
+    case 6: return wc * wc * c0;
+    case 7: return wb * c1;
+    case 8: return wc * c1;
+    default: return wb * wc * c0;
+  }
+}
+
+__device__ __forceinline__ void obs_column_fields(double c0, double c1, double c2, int64_t cc,
+                                                  const double (&org)[3], const ObsFuse& f,
+                                                  double (&acc)[10]) {
+  double wb, wc;
+  obs_column_disp(cc, org, f, wb, wc);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) acc[k] = obs_field(k, c0, c1, c2, wb, wc);
+}
+
+// (3) over the columns: a shuffle sum over the 64 lanes of a wave (lane 0
+// takes the result); wave_sum32 the same steps after the first, for waves
+// whose lanes 32..63 hold zeros (that step then adds 0.0).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum32(double v) {
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
 template <typename T, int L, int E>
 __global__ __launch_bounds__((strided_max_threads<T, L>())) void k_fft_strided_obs(cx<T>* __restrict__ out,
                                                           const cx<T>* __restrict__ in, int64_t I,
@@ -207,23 +502,10 @@ __global__ __launch_bounds__((strided_max_threads<T, L>())) void k_fft_strided_o
   double org[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) org[a] = f.origins ? f.origins[3 * b + a] : f.c[a];
-  const AxisImage32 a0 = axis_image32(axis_image(org[0], f.N[0]));
-  // (1) Over the thread's elements: only the axis-0 displacement varies
-  // along the pass, so three moments in it suffice (the other axes are
-  // fixed per column).
-  double S0 = 0.0, S1 = 0.0, S11 = 0.0;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int pos = t + TT * e;
-    const double w = min_image32(f.dim == 1 ? pos * (int)I + (int)col : pos, a0);
-    const double x = (double)v[e].x, y = (double)v[e].y;
-    const double pr = x * x + y * y;
-    const double wp = w * pr;
-    S0 += pr;
-    S1 += wp;
-    S11 += w * wp;
-  }
-  // (2) Over the TT threads of each column, through LDS (free once the
+  double S0, S1, S11;
+  obs_thread_moments<T, L, E>(v, t, I, col, f.dim, axis_image32(axis_image(org[0], f.N[0])), S0,
+                              S1, S11);
+  // Over the TT threads of each column, through LDS (free once the
   // transform is done; the launch sizes it for 3 doubles per thread).
   const int nth = TT * P;
   double* red = reinterpret_cast<double*>(smem_raw);
@@ -243,35 +525,16 @@ __global__ __launch_bounds__((strided_max_threads<T, L>())) void k_fft_strided_o
       c1 += red[nth + i];
       c2 += red[2 * nth + i];
     }
-    const int64_t cc = col - p + tid;  // the column these sums belong to
-    double wb = 0.0, wc = 0.0;
-    if (f.dim == 2) {
-      wb = min_image(cc, axis_image(org[1], f.N[1]));
-    } else if (f.dim == 3) {
-      wb = min_image(cc >> f.lg[2], axis_image(org[1], f.N[1]));
-      wc = min_image(cc & (f.N[2] - 1), axis_image(org[2], f.N[2]));
-    }
-    acc[0] = c0;
-    acc[1] = c1;
-    acc[2] = wb * c0;
-    acc[3] = wc * c0;
-    acc[4] = c2;
-    acc[5] = wb * wb * c0;
-    acc[6] = wc * wc * c0;
-    acc[7] = wb * c1;
-    acc[8] = wc * c1;
-    acc[9] = wb * wc * c0;
+    obs_column_fields(c0, c1, c2, col - p + tid, org, f, acc);
   }
-  // (3) Over the columns: only the waves holding column sums shuffle.
+  // Only the waves holding column sums shuffle.
   __shared__ double red2[10][16];
   const int lane = tid & 63, wave = tid >> 6;
   const int nwc = (P + 63) >> 6;
   if (wave < nwc) {
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
-      double vv = acc[k];
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) vv += __shfl_down(vv, off, 64);
+      const double vv = wave_sum(acc[k]);
       if (lane == 0) red2[k][wave] = vv;
     }
   }
@@ -284,6 +547,113 @@ __global__ __launch_bounds__((strided_max_threads<T, L>())) void k_fft_strided_o
   }
 }
 
+// The same pass staged through LDS (see k_fft_strided_staged), for calls
+// with one origin (f.origins null): the same tiles and arithmetic, so the
+// same field and partial vectors. Its LDS accesses inside the tile loop are
+// written out with their waits (compiled ones would also wait for the next
+// tile's loads in flight), and the reduction area is LDS of its own, which
+// the loop's barriers order against the previous tile's readers. The 32
+// columns are one wave's: its lane 0 writes the tile's partial vector.
+typedef double qw_d2 __attribute__((ext_vector_type(2)));
+
+// c = sum over r = 0..15 (in that order) of the doubles at byte offsets
+// 256 r from LDS address a.
+__device__ __forceinline__ double lds_column_sum(unsigned a) {
+  qw_d2 y0, y1, y2, y3, y4, y5, y6, y7;
+  asm volatile(
+      "ds_read2_b64 %0, %8 offset0:0 offset1:32\n\t"
+      "ds_read2_b64 %1, %8 offset0:64 offset1:96\n\t"
+      "ds_read2_b64 %2, %8 offset0:128 offset1:160\n\t"
+      "ds_read2_b64 %3, %8 offset0:192 offset1:224\n\t"
+      "ds_read2_b64 %4, %9 offset0:0 offset1:32\n\t"
+      "ds_read2_b64 %5, %9 offset0:64 offset1:96\n\t"
+      "ds_read2_b64 %6, %9 offset0:128 offset1:160\n\t"
+      "ds_read2_b64 %7, %9 offset0:192 offset1:224\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(y0), "=&v"(y1), "=&v"(y2), "=&v"(y3), "=&v"(y4), "=&v"(y5), "=&v"(y6), "=&v"(y7)
+      : "v"(a), "v"(a + 2048u)
+      : "memory");
+  const qw_d2 y[8] = {y0, y1, y2, y3, y4, y5, y6, y7};
+  double c = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    c += y[i].x;
+    c += y[i].y;
+  }
+  return c;
+}
+
+__global__ __launch_bounds__(512) void k_fft_strided_obs_staged(cx<float>* __restrict__ out,
+                                                                const cx<float>* __restrict__ in,
+                                                                int64_t I, int64_t nblk_i,
+                                                                int64_t nblk, ObsFuse f,
+                                                                const cx<float>* __restrict__ tw) {
+  __shared__ __align__(16) cx<float> buf[2 * 256 * kStagedCols];
+  __shared__ __align__(16) double red[3 * 512];
+  const int tid = threadIdx.x;
+  const int p = tid & (kStagedCols - 1), t = tid >> 5;
+  const OuterMap om{nblk / nblk_i, 0, 0, 0};
+  const AxisImage32 a0 = axis_image32(axis_image(f.c[0], f.N[0]));
+  const double org[3] = {f.c[0], f.c[1], f.c[2]};
+  typedef __attribute__((address_space(3))) double* lds_dptr;
+  const unsigned ra = (unsigned)(size_t)(lds_dptr)(red + tid);
+  const unsigned rl = (unsigned)(size_t)(lds_dptr)(red + (tid & 63));  // column lane
+  staged256_loop<-1>(buf, in, I, nblk_i, nblk, om, tw,
+                     [&](const cx<float>(&v)[16], int64_t blk, int64_t base) {
+                       if (f.store) {
+#pragma unroll
+                         for (int e = 0; e < 16; ++e)
+                           out[base + p + (int64_t)(t + 16 * e) * I] = v[e];
+                       }
+                       const int64_t o = blk / nblk_i;
+                       const int64_t col = base - o * 256 * I + p;
+                       double S0, S1, S11;
+                       obs_thread_moments<float, 256, 16>(v, t, I, col, f.dim, a0, S0, S1, S11);
+                       // red[tid], red[512 + tid], red[1024 + tid]; then all
+                       // threads' moments are there
+                       asm volatile(
+                           "ds_write_b64 %0, %1\n\t"
+                           "ds_write_b64 %0, %2 offset:4096\n\t"
+                           "ds_write_b64 %0, %3 offset:8192\n\t"
+                           "s_waitcnt lgkmcnt(0)\n\t"
+                           "s_barrier" ::"v"(ra),
+                           "v"(S0), "v"(S1), "v"(S11)
+                           : "memory");
+                       // Fields over the waves, by the column sum they take:
+                       // c0: {0, 2}, {3, 5}, {6, 9}; c1: {1}, {7}, {8}; c2: {4};
+                       // the last wave writes the zero fields. Lanes 0..31 hold
+                       // the columns, lanes 32..63 zeros: the first step of the
+                       // shuffle sum (adding lane i + 32) is v + 0.0.
+                       const int wave = tid >> 6, lane = tid & 63;
+                       if (wave < 7) {
+                         const int m = wave < 3 ? 0 : (wave < 6 ? 1 : 2);
+                         // (the wave's two fields as nibbles of one constant;
+                         // 15: none)
+                         const int k0 = (0x04871630 >> (4 * wave)) & 15;
+                         const int k1r = (0x0FFFF952 >> (4 * wave)) & 15;
+                         const int k1 = k1r == 15 ? -1 : k1r;
+                         double v0 = 0.0, v1 = 0.0;
+                         if (lane < kStagedCols) {
+                           const double c = lds_column_sum(rl + 4096u * m);
+                           double wb, wc;
+                           obs_column_disp(col - p + lane, org, f, wb, wc);
+                           v0 = obs_field(k0, c, c, c, wb, wc);
+                           if (k1 >= 0) v1 = obs_field(k1, c, c, c, wb, wc);
+                         }
+                         v0 = wave_sum32(v0 + 0.0);
+                         if (k1 >= 0) v1 = wave_sum32(v1 + 0.0);
+                         if (lane == 0) {
+                           double* dst = f.partials + blk * kObsFields;
+                           dst[k0] = 0.0 + v0;
+                           if (k1 >= 0) dst[k1] = 0.0 + v1;
+                         }
+                       } else if (lane == 0) {
+                         double* dst = f.partials + blk * kObsFields;
+                         for (int k = 10; k < kObsFields; ++k) dst[k] = 0.0;
+                       }
+                     });
+}
+
 template <typename T, int L>
 static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int64_t I,
                                   const ObsFuse& f, const cx<T>* tw, hipStream_t st) {
@@ -293,6 +663,19 @@ static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int
   const int P = strided_cols<T, L>(I);
   if (TT * P > 1024 || (TT * P) % 64 != 0) return hipErrorInvalidValue;
   const int lgP = ilog2(P);
+  const int64_t nblk_i = I / P;
+  const int64_t nblk = (int64_t)s * B * nblk_i;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  if constexpr (sizeof(T) == 4 && L == 256) {
+    if (!f.origins && use_staged(false, -1, L, (int64_t)s * B, I)) {
+      static_assert(TT * kStagedCols == 512, "staged tiles are the register kernel's");
+      const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
+      hipLaunchKernelGGL(k_fft_strided_obs_staged, dim3((unsigned)ng), dim3(512), 0, st,
+                         (cx<float>*)out, (const cx<float>*)in, I, nblk_i, nblk, f,
+                         (const cx<float>*)tw);
+      return hipGetLastError();
+    }
+  }
   // the transform's exchanges, then 3 doubles per thread for the reduction
   const size_t lds = std::max((size_t)P * L * sizeof(cx<T>), (size_t)TT * P * 3 * sizeof(double));
   auto kern = k_fft_strided_obs<T, L, E>;
@@ -301,9 +684,6 @@ static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const int64_t nblk_i = I / P;
-  const int64_t nblk = (int64_t)s * B * nblk_i;
-  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(TT * P), lds, st, out, in, I, lgP, nblk_i, s,
                      f, tw);
   return hipGetLastError();

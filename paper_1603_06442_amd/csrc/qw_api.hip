@@ -1251,6 +1251,12 @@ qw_status qw_set_step_kernel(int two_step, int tile_shape, int chunk) {
   return QW_OK;
 }
 
+qw_status qw_set_fft_kernel(int staged) {
+  if (staged != 0 && staged != 1) return fail(QW_ERR_INVALID, "staged must be 0 or 1");
+  set_fft_staged(staged == 1);
+  return QW_OK;
+}
+
 qw_status qw_set_schedule(qw_plan_t p, int slab_planes, int contig_elems, int contig_threads,
                           int contig_groups) {
   qw_status r = check_plan(p);

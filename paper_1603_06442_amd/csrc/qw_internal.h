@@ -131,6 +131,9 @@ constexpr size_t kNtBytes = size_t(256) << 20;
 // the last-level cache whose next reader gains nothing from cached lines).
 hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
                               int64_t I, const void* tw, hipStream_t st, bool nt = false);
+// Length-256 complex64 inverse passes of large fields staged through LDS
+// (on by default; the same bits either way).
+void set_fft_staged(bool on);
 // Planes o0 .. o0+ocount-1 of each of ncomp components (ostride elements apart).
 hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, const void* in,
                                    int64_t ncomp, int64_t ocount, int64_t o0, int64_t ostride,

@@ -27,7 +27,8 @@ EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_noalloc"
            "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft", "qw_bcc_step", "qw_bcc_observables",
            "qw_kspace_drift",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
-           "qw_set_schedule", "qw_get_schedule", "qw_set_step_kernel", "qw_autotune",
+           "qw_set_schedule", "qw_get_schedule", "qw_set_step_kernel", "qw_set_fft_kernel",
+           "qw_autotune",
            "qw_last_error", "qw_version",
            "qw_server_create", "qw_server_configure", "qw_server_submit", "qw_server_poll", "qw_server_wait",
            "qw_server_cancel", "qw_server_wait_for",
@@ -110,6 +111,7 @@ def _load():
         "qw_dispersion_taylor": [cint, dbl, ctypes.POINTER(dbl), cint, ctypes.POINTER(dbl)],
         "qw_set_schedule": [vp, cint, cint, cint, cint],
         "qw_set_step_kernel": [cint, cint, cint],
+        "qw_set_fft_kernel": [cint],
         "qw_get_schedule": [vp, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint),
                             ctypes.POINTER(cint)],
         "qw_autotune": [vp, vp, ctypes.POINTER(dbl)],
@@ -438,6 +440,13 @@ def set_step_kernel(two_step=False, tile_shape=0, chunk=0):
     0 = 16 x 32, 1 = 8 x 64, 2 = 16 x 16, 3 = 8 x 32; planes per workgroup
     (0 = automatic)."""
     _check(LIB.qw_set_step_kernel(1 if two_step else 0, int(tile_shape), int(chunk)))
+
+
+def set_fft_kernel(staged=True):
+    """qw_set_fft_kernel (measurement): length-256 complex64 inverse passes
+    of large fields staged through LDS (the default) or with their loads in
+    registers; the same bits either way."""
+    _check(LIB.qw_set_fft_kernel(1 if staged else 0))
 
 
 def version():

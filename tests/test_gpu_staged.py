@@ -1,0 +1,103 @@
+"""Strided FFT passes staged through LDS (global-to-LDS loads, double
+buffered) against the register kernels they replace, bit for bit.
+
+The staged kernels take the length-256 complex64 inverse passes of fields of
+at least 8192 tiles of 32 columns (a 256^3 field of four components); with
+qw_set_fft_kernel(0) every pass keeps its loads in registers. Both run the
+same tiles through the same arithmetic, so every result must have the same
+bits: the field of a jump (Sec. 4: the Fourier evaluation of U^t), the
+reductions fused into its last pass (Sec. 5.2), the inverse transform, the
+time series, a batched jump whose instances together cross the size
+threshold, and the slab schedule (its n1 pass staged, its slab passes not)."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1603_06442_amd import qw as mod
+    yield mod
+    mod.set_fft_kernel(True)
+
+
+def _field(plan, seed, B=1):
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    shape = plan.empty().shape
+    x = torch.randn((B,) + tuple(shape) if B > 1 else shape, dtype=torch.complex64,
+                    generator=g, device="cuda")
+    return x / torch.linalg.vector_norm(x)
+
+
+def _both(qw, fn):
+    """fn() with the staged kernels (the default), then with register kernels."""
+    try:
+        qw.set_fft_kernel(True)
+        a = fn()
+        torch.cuda.synchronize()
+        qw.set_fft_kernel(False)
+        b = fn()
+        torch.cuda.synchronize()
+    finally:
+        qw.set_fft_kernel(True)
+    return a, b
+
+
+def test_full_size_jump_and_reductions(qw):
+    n = 256
+    plan = qw.Plan(3, n, 0.1, "c64")
+    x = _field(plan, 5)
+    origin = [n / 2 - 0.5, n / 3, 17.25]
+    print("256^3 complex64: jump, fused reductions, inverse transform, series", flush=True)
+    a, b = _both(qw, lambda: plan.evolve_fft(x, 777))
+    assert torch.equal(a, b)
+    del a, b
+    out = [plan.empty(), plan.empty()]
+    k = iter(range(2))
+
+    def fused():
+        i = next(k)
+        return plan.evolve_fft_observables(x, -12345, origin, out=out[i])
+    oa, ob = _both(qw, fused)
+    assert oa == ob
+    assert torch.equal(out[0], out[1])
+    want = plan.observables(out[0], origin)
+    assert abs(oa["norm2"] - want["norm2"]) < 1e-12
+    assert np.abs(np.array(oa["mean"]) - np.array(want["mean"])).max() < 1e-9
+    del out
+    na, nb = _both(qw, lambda: plan.evolve_fft_observables(x, 99, origin))  # no field written
+    assert na == nb
+    ta, tb = _both(qw, lambda: plan.transform(x, -1))
+    assert torch.equal(ta, tb)
+    del ta, tb
+    sa, sb = _both(qw, lambda: plan.evolve_fft_series(x, [1, 64, 4096, 100000], origin))
+    assert sa == sb
+
+
+def test_batched_instances_cross_the_threshold(qw):
+    """256 x 128 x 256: one instance is 4096 tiles (register kernel), two
+    are 8192 (staged); per-instance masses and times."""
+    plan = qw.Plan(3, [256, 128, 256], 0.2, "c64")
+    x = _field(plan, 9, B=2)
+    print("batched 2 x 256x128x256 complex64", flush=True)
+    a, b = _both(qw, lambda: plan.evolve_fft_batched(x, [0.2, 0.05], [333, -70]))
+    assert torch.equal(a, b)
+
+
+def test_slab_schedule(qw):
+    plan = qw.Plan(3, 256, 0.3, "c64")
+    plan.set_schedule(32, 8, 256, 1)
+    x = _field(plan, 13)
+    print("256^3 complex64, slab schedule", flush=True)
+    a, b = _both(qw, lambda: plan.evolve_fft(x, 4242))
+    assert torch.equal(a, b)
+
+
+def test_switch_arguments(qw):
+    assert qw.LIB.qw_set_fft_kernel(2) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_set_fft_kernel(-1) == qw.QW_ERR_INVALID
+    assert qw.LIB.qw_set_fft_kernel(1) == qw.QW_OK
