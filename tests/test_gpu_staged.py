@@ -88,6 +88,22 @@ def test_batched_instances_cross_the_threshold(qw):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("weyl,shape", [(True, [256, 512, 256]), (False, [256, 512, 128])])
+def test_other_shapes(qw, weyl, shape):
+    """The n1 inverse pass over 4096-column rows (Weyl, two components) and
+    2048-column rows of a non-cubic lattice (the n2 passes have length 512
+    there and keep the register kernel): field and fused reductions."""
+    plan = qw.Plan(3, shape, 0.0 if weyl else 0.15, "c64", weyl=weyl)
+    x = _field(plan, 17)
+    origin = [shape[0] / 2 + 0.25, shape[1] / 3, shape[2] - 5.5]
+    print("staged n1 pass: %s %s" % ("Weyl" if weyl else "Dirac", shape), flush=True)
+    a, b = _both(qw, lambda: plan.evolve_fft(x, 2024))
+    assert torch.equal(a, b)
+    del a, b
+    oa, ob = _both(qw, lambda: plan.evolve_fft_observables(x, -31, origin))
+    assert oa == ob
+
+
 def test_slab_schedule(qw):
     plan = qw.Plan(3, 256, 0.3, "c64")
     plan.set_schedule(32, 8, 256, 1)
