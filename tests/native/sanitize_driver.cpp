@@ -91,6 +91,8 @@ static void host_checks() {
                 QW_ERR_INVALID);
   EXPECT_STATUS(qw_set_step_kernel(2, 0, 0), QW_ERR_INVALID);
   EXPECT_STATUS(qw_set_step_kernel(0, 0, 0), QW_OK);
+  EXPECT_STATUS(qw_set_fft_kernel(2), QW_ERR_INVALID);
+  EXPECT_STATUS(qw_set_fft_kernel(1), QW_OK);
 
   // Host-only arithmetic: the Taylor coefficients of omega (Prop. 1).
   for (int dim = 1; dim <= 3; ++dim)
