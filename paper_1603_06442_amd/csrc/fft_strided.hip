@@ -252,28 +252,214 @@ __global__ __launch_bounds__(512) void k_fft_strided_staged(cx<float>* __restric
                              });
 }
 
-// The staged kernels take a pass when they apply: complex64, length 256,
-// whole 32-column tiles, inverse direction (the forward passes measured no
-// faster staged: 0.227 and 0.190 ms against 0.229 and 0.191 at 256^3, where
-// the inverse ones went 0.187 -> 0.174 ms and 0.213 -> 0.197 ms) and at
-// least kStagedMinTiles tiles; unless switched off (qw_set_fft_kernel).
+// The complex128 form: tiles of 16 columns (256-byte rows) and the register
+// kernel's transform at this length, E = 8 (radix 8, 8, 4). Thread (p, t),
+// p < 16, t < 32, holds rows t + 32 e; wave w holds t = 4w .. 4w+3, and slot
+// (t >> 2) * 32 + 4 e + (t & 3) of the buffer holds row t + 32 e.
+constexpr int kStagedColsD = 16;
+
+__device__ __forceinline__ void stage_tile256_c128(cx<double>* __restrict__ buf,
+                                                   const cx<double>* __restrict__ in,
+                                                   int64_t tile, int64_t I, int tid) {
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    // one instruction: four 256-byte rows, slots 4j .. 4j+3 of this wave
+    const int64_t r = 4 * w + (l >> 4) + 32 * j;
+    __builtin_amdgcn_global_load_lds(in + tile + r * I + (l & 15),
+                                     buf + (w * 32 + 4 * j) * kStagedColsD, 16, 0, 0);
+  }
+}
+
+typedef double qw_d2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ qw_d2 d2(cx<double> z) { return qw_d2{z.x, z.y}; }
+
+// Eight 16-byte values to LDS bytes a + OFF * k (k = 0..7), then the
+// workgroup barrier.
+template <int OFF>
+__device__ __forceinline__ void lds_write8_b128(unsigned a, const cx<double> (&y)[8]) {
+  asm volatile(
+      "ds_write_b128 %0, %1\n\t"
+      "ds_write_b128 %0, %2 offset:%c9\n\t"
+      "ds_write_b128 %0, %3 offset:%c10\n\t"
+      "ds_write_b128 %0, %4 offset:%c11\n\t"
+      "ds_write_b128 %0, %5 offset:%c12\n\t"
+      "ds_write_b128 %0, %6 offset:%c13\n\t"
+      "ds_write_b128 %0, %7 offset:%c14\n\t"
+      "ds_write_b128 %0, %8 offset:%c15\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "s_barrier" ::"v"(a),
+      "v"(d2(y[0])), "v"(d2(y[1])), "v"(d2(y[2])), "v"(d2(y[3])), "v"(d2(y[4])), "v"(d2(y[5])),
+      "v"(d2(y[6])), "v"(d2(y[7])), "i"(OFF), "i"(2 * OFF), "i"(3 * OFF), "i"(4 * OFF),
+      "i"(5 * OFF), "i"(6 * OFF), "i"(7 * OFF)
+      : "memory");
+}
+
+// y[k] = the 16-byte value at LDS bytes a + 8192 k (k = 0..7), then the
+// workgroup barrier.
+__device__ __forceinline__ void lds_read8_b128(unsigned a, cx<double> (&y)[8]) {
+  qw_d2 q0, q1, q2, q3, q4, q5, q6, q7;
+  asm volatile(
+      "ds_read_b128 %0, %8\n\t"
+      "ds_read_b128 %1, %8 offset:8192\n\t"
+      "ds_read_b128 %2, %8 offset:16384\n\t"
+      "ds_read_b128 %3, %8 offset:24576\n\t"
+      "ds_read_b128 %4, %8 offset:32768\n\t"
+      "ds_read_b128 %5, %8 offset:40960\n\t"
+      "ds_read_b128 %6, %8 offset:49152\n\t"
+      "ds_read_b128 %7, %8 offset:57344\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "s_barrier"
+      : "=&v"(q0), "=&v"(q1), "=&v"(q2), "=&v"(q3), "=&v"(q4), "=&v"(q5), "=&v"(q6), "=&v"(q7)
+      : "v"(a)
+      : "memory");
+  const qw_d2 q[8] = {q0, q1, q2, q3, q4, q5, q6, q7};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) y[k] = mk(q[k].x, q[k].y);
+}
+
+// Twiddles of thread t for the last two stages: w2[r] (stage 2, k = t & 7,
+// r = 1..7) and w3[b][r] (stage 3, k = t + 32 b, r = 1..3).
+template <int SIGN>
+struct Tw256D {
+  cx<double> w2[8], w3[2][4];
+  __device__ __forceinline__ void load(const cx<double>* __restrict__ tw, int t) {
+#pragma unroll
+    for (int r = 1; r < 8; ++r) w2[r] = twiddle<SIGN>(tw, r * (t & 7) * (TWN / 64));
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 1; r < 4; ++r) w3[b][r] = twiddle<SIGN>(tw, r * ((t + 32 * b) & 63) * (TWN / 256));
+  }
+};
+
+// The register kernel's three Stockham stages at L = 256, E = 8, with the
+// twiddles from registers and the exchanges written out. X: byte address
+// in LDS of this thread's column (element (pos, p) at X + 256 pos).
+template <int SIGN>
+__device__ __forceinline__ void fft256_c128(cx<double> (&v)[8], unsigned X, int t,
+                                            const Tw256D<SIGN>& W) {
+  // stage 1 (radix 8, no twiddles): positions 8t + r
+  dft_reg<8, SIGN>(v);
+  lds_write8_b128<256>(X + 2048u * t, v);
+  lds_read8_b128(X + 256u * t, v);
+  // stage 2 (radix 8): positions (t >> 3) 64 + (t & 7) + 8 r
+#pragma unroll
+  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], W.w2[r]);
+  dft_reg<8, SIGN>(v);
+  lds_write8_b128<2048>(X + 256u * ((t >> 3) * 64 + (t & 7)), v);
+  lds_read8_b128(X + 256u * t, v);
+  // stage 3 (radix 4, two butterflies per thread): in place in v
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    cx<double> a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = v[b + 2 * r];
+#pragma unroll
+    for (int r = 1; r < 4; ++r) a[r] = cmul(a[r], W.w3[b][r]);
+    dft_reg<4, SIGN>(a);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[b + 2 * r] = a[r];
+  }
+}
+
+template <int SIGN, bool NT>
+__global__ __launch_bounds__(512) void k_fft_strided_staged_c128(cx<double>* __restrict__ out,
+                                                                 const cx<double>* __restrict__ in,
+                                                                 int64_t I, int64_t nblk_i,
+                                                                 int64_t nblk, OuterMap om,
+                                                                 const cx<double>* __restrict__ tw) {
+  __shared__ __align__(16) cx<double> buf[2 * 256 * kStagedColsD];
+  const int tid = threadIdx.x;
+  const int p = tid & (kStagedColsD - 1), t = tid >> 4;
+  Tw256D<SIGN> W;
+  W.load(tw, t);
+  auto tile_base = [&](int64_t blk) -> int64_t {
+    const int64_t o = blk / nblk_i;
+    const int64_t i0 = (blk - o * nblk_i) * kStagedColsD;
+    const int64_t comp = o / om.ocount;
+    const int64_t plane = om.o0 + (o - comp * om.ocount);
+    return comp * om.ostride + plane * 256 * I + i0;
+  };
+  // in XCD order, as the register kernel at complex128 (without it the
+  // staged n1 inverse pass measured no faster than the register one)
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x, true);
+  const int64_t first = wg * kStagedTiles;
+  if (first >= nblk) return;
+  const int n = nblk - first < kStagedTiles ? (int)(nblk - first) : kStagedTiles;
+  int64_t cur = tile_base(first);
+  stage_tile256_c128(buf, in, cur, I, tid);
+  typedef __attribute__((address_space(3))) cx<double>* lds_ptr;
+  const int s0 = (t >> 2) * 32 + (t & 3);
+  for (int k = 0; k < n; ++k) {
+    cx<double>* X = buf + (k & 1) * (256 * kStagedColsD);
+    cx<double>* Y = buf + ((k + 1) & 1) * (256 * kStagedColsD);
+    vm_drain();
+    cx<double> v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = X[(s0 + 4 * e) * kStagedColsD + p];
+    // every wave has its rows before the exchange writes X, and the last
+    // reads of Y (the previous tile's exchange) are done
+    lds_barrier();
+    int64_t nxt = 0;
+    if (k + 1 < n) {
+      nxt = tile_base(first + k + 1);
+      stage_tile256_c128(Y, in, nxt, I, tid);
+    }
+    fft256_c128<SIGN>(v, (unsigned)(size_t)(lds_ptr)(X + p), t, W);
+    const int64_t b = cur + p;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if constexpr (NT)
+        store_nt(&out[b + (int64_t)(t + 32 * e) * I], v[e]);
+      else
+        out[b + (int64_t)(t + 32 * e) * I] = v[e];
+    }
+    cur = nxt;
+  }
+}
+
+// The staged kernels take a pass when they apply, unless switched off
+// (qw_set_fft_kernel): length 256, whole tiles, at least kStagedMinTiles
+// of them, and
+// * complex64: the inverse direction. The forward passes measured slower
+//   staged (0.246 and 0.210 ms against 0.226 and 0.190 at 256^3; in XCD
+//   order 0.240 and 0.183, but the fused pass after them then took 0.245
+//   against 0.238 ms), where the inverse ones went 0.187 -> 0.174 ms and
+//   0.213 -> 0.197 ms (in XCD order 0.190 and 0.195).
+// * complex128: rows at least 4096 elements (64 KB) apart, both
+//   directions: at 256^3 the n1 passes 0.490 -> 0.451 ms and 0.456 ->
+//   0.418 ms, where the n2 passes (4 KB apart) measured slower (0.382 ->
+//   0.394 and 0.384 -> 0.392 ms); the jump 2.26 -> 2.19 ms.
 static std::atomic<bool> g_staged{true};
 
 void set_fft_staged(bool on) { g_staged.store(on, std::memory_order_relaxed); }
 
 static bool use_staged(bool dbl, int sign, int64_t L, int64_t O, int64_t I) {
-  return g_staged.load(std::memory_order_relaxed) && !dbl && sign < 0 && L == 256 &&
-         I % kStagedCols == 0 && O * (I / kStagedCols) >= kStagedMinTiles;
+  if (!g_staged.load(std::memory_order_relaxed) || L != 256) return false;
+  const int cols = dbl ? kStagedColsD : kStagedCols;
+  if (I % cols != 0 || O * (I / cols) < kStagedMinTiles) return false;
+  return dbl ? I >= 4096 : sign < 0;
 }
 
-static hipError_t run_staged(cx<float>* out, const cx<float>* in, int64_t O, int64_t I,
-                             const OuterMap& om, const cx<float>* tw, hipStream_t st) {
-  const int64_t nblk_i = I / kStagedCols;
+template <typename T>
+static hipError_t run_staged(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
+                             const OuterMap& om, const cx<T>* tw, hipStream_t st, int sign) {
+  constexpr int cols = sizeof(T) == 8 ? kStagedColsD : kStagedCols;
+  const int64_t nblk_i = I / cols;
   const int64_t nblk = O * nblk_i;
   const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
   if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
-  auto kern = om.nt ? k_fft_strided_staged<-1, true> : k_fft_strided_staged<-1, false>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
+  if constexpr (sizeof(T) == 8) {
+    auto kern = sign > 0 ? (om.nt ? k_fft_strided_staged_c128<1, true> : k_fft_strided_staged_c128<1, false>)
+                         : (om.nt ? k_fft_strided_staged_c128<-1, true> : k_fft_strided_staged_c128<-1, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
+  } else {
+    if (sign > 0) return hipErrorInvalidValue;  // not instantiated: see use_staged
+    auto kern = om.nt ? k_fft_strided_staged<-1, true> : k_fft_strided_staged<-1, false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
+  }
   return hipGetLastError();
 }
 
@@ -363,7 +549,10 @@ hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, con
   const OuterMap om{ocount, o0, ostride, nt ? 1 : 0};
   const int64_t O = ncomp * ocount;
   if (use_staged(dbl, sign, L, O, I))
-    return run_staged((cx<float>*)out, (const cx<float>*)in, O, I, om, (const cx<float>*)tw, st);
+    return dbl ? run_staged<double>((cx<double>*)out, (const cx<double>*)in, O, I, om,
+                                    (const cx<double>*)tw, st, sign)
+               : run_staged<float>((cx<float>*)out, (const cx<float>*)in, O, I, om,
+                                   (const cx<float>*)tw, st, sign);
   if (dbl) {
     auto o = (cx<double>*)out;
     auto i = (const cx<double>*)in;

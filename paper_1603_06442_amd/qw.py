@@ -443,9 +443,9 @@ def set_step_kernel(two_step=False, tile_shape=0, chunk=0):
 
 
 def set_fft_kernel(staged=True):
-    """qw_set_fft_kernel (measurement): length-256 complex64 inverse passes
-    of large fields staged through LDS (the default) or with their loads in
-    registers; the same bits either way."""
+    """qw_set_fft_kernel (measurement): length-256 strided passes of large
+    fields (complex64 inverse, complex128 n1-like) staged through LDS (the
+    default) or with their loads in registers; the same bits either way."""
     _check(LIB.qw_set_fft_kernel(1 if staged else 0))
 
 

@@ -1,14 +1,16 @@
 """Strided FFT passes staged through LDS (global-to-LDS loads, double
 buffered) against the register kernels they replace, bit for bit.
 
-The staged kernels take the length-256 complex64 inverse passes of fields of
-at least 8192 tiles of 32 columns (a 256^3 field of four components); with
+The staged kernels take the length-256 passes of at least 8192 tiles: at
+complex64 the inverse ones (32-column tiles; a 256^3 field of four
+components), at complex128 those whose rows are at least 4096 elements apart,
+both directions (16-column tiles; the n1 passes at 256^3); with
 qw_set_fft_kernel(0) every pass keeps its loads in registers. Both run the
 same tiles through the same arithmetic, so every result must have the same
 bits: the field of a jump (Sec. 4: the Fourier evaluation of U^t), the
-reductions fused into its last pass (Sec. 5.2), the inverse transform, the
-time series, a batched jump whose instances together cross the size
-threshold, and the slab schedule (its n1 pass staged, its slab passes not)."""
+reductions fused into its last pass (Sec. 5.2), the transforms, the time
+series, a batched jump whose instances together cross the size threshold,
+and the slab schedule (its n1 pass staged, its slab passes not)."""
 import numpy as np
 import pytest
 import torch
@@ -28,7 +30,7 @@ def qw():
 def _field(plan, seed, B=1):
     g = torch.Generator(device="cuda").manual_seed(seed)
     shape = plan.empty().shape
-    x = torch.randn((B,) + tuple(shape) if B > 1 else shape, dtype=torch.complex64,
+    x = torch.randn((B,) + tuple(shape) if B > 1 else shape, dtype=plan.torch_dtype,
                     generator=g, device="cuda")
     return x / torch.linalg.vector_norm(x)
 
@@ -102,6 +104,34 @@ def test_other_shapes(qw, weyl, shape):
     del a, b
     oa, ob = _both(qw, lambda: plan.evolve_fft_observables(x, -31, origin))
     assert oa == ob
+
+
+def test_complex128_n1_passes(qw):
+    """256^3 complex128: the n1 passes of both directions staged."""
+    n = 256
+    plan = qw.Plan(3, n, 0.1, "c128")
+    x = _field(plan, 23)
+    origin = [n / 2 + 0.5, 100.0, 31.75]
+    print("256^3 complex128: jump, transforms, fused reductions", flush=True)
+    a, b = _both(qw, lambda: plan.evolve_fft(x, 4321))
+    assert torch.equal(a, b)
+    del a, b
+    for d in (1, -1):
+        ta, tb = _both(qw, lambda: plan.transform(x, d))
+        assert torch.equal(ta, tb), d
+        del ta, tb
+    oa, ob = _both(qw, lambda: plan.evolve_fft_observables(x, 777, origin))
+    assert oa == ob
+    ra, rb = _both(qw, lambda: plan.evolve_fft_real(x, 0.5))
+    assert torch.equal(ra, rb)
+
+
+def test_complex128_batched(qw):
+    plan = qw.Plan(3, [256, 128, 256], 0.2, "c128")
+    x = _field(plan, 29, B=2)
+    print("batched 2 x 256x128x256 complex128", flush=True)
+    a, b = _both(qw, lambda: plan.evolve_fft_batched(x, [0.2, 0.05], [333, -70]))
+    assert torch.equal(a, b)
 
 
 def test_slab_schedule(qw):
