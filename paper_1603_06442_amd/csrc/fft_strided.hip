@@ -364,13 +364,15 @@ __device__ __forceinline__ void fft256_c128(cx<double> (&v)[8], unsigned X, int 
   }
 }
 
-template <int SIGN, bool NT>
-__global__ __launch_bounds__(512) void k_fft_strided_staged_c128(cx<double>* __restrict__ out,
-                                                                 const cx<double>* __restrict__ in,
-                                                                 int64_t I, int64_t nblk_i,
-                                                                 int64_t nblk, OuterMap om,
-                                                                 const cx<double>* __restrict__ tw) {
-  __shared__ __align__(16) cx<double> buf[2 * 256 * kStagedColsD];
+// The tile loop of the complex128 staged kernels (as staged256_loop):
+// epi(v, tile, first element of the tile) with the thread's 8 values, rows
+// t + 32 e of column p.
+template <int SIGN, typename Epi>
+__device__ __forceinline__ void staged256_loop_c128(cx<double>* __restrict__ buf,
+                                                    const cx<double>* __restrict__ in, int64_t I,
+                                                    int64_t nblk_i, int64_t nblk,
+                                                    const OuterMap& om,
+                                                    const cx<double>* __restrict__ tw, Epi epi) {
   const int tid = threadIdx.x;
   const int p = tid & (kStagedColsD - 1), t = tid >> 4;
   Tw256D<SIGN> W;
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(512) void k_fft_strided_staged_c128(cx<double>* __r
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = X[(s0 + 4 * e) * kStagedColsD + p];
     // every wave has its rows before the exchange writes X, and the last
-    // reads of Y (the previous tile's exchange) are done
+    // reads of Y (the previous tile's exchange and epilogue) are done
     lds_barrier();
     int64_t nxt = 0;
     if (k + 1 < n) {
@@ -408,16 +410,30 @@ __global__ __launch_bounds__(512) void k_fft_strided_staged_c128(cx<double>* __r
       stage_tile256_c128(Y, in, nxt, I, tid);
     }
     fft256_c128<SIGN>(v, (unsigned)(size_t)(lds_ptr)(X + p), t, W);
-    const int64_t b = cur + p;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if constexpr (NT)
-        store_nt(&out[b + (int64_t)(t + 32 * e) * I], v[e]);
-      else
-        out[b + (int64_t)(t + 32 * e) * I] = v[e];
-    }
+    epi(v, first + k, cur);
     cur = nxt;
   }
+}
+
+template <int SIGN, bool NT>
+__global__ __launch_bounds__(512) void k_fft_strided_staged_c128(cx<double>* __restrict__ out,
+                                                                 const cx<double>* __restrict__ in,
+                                                                 int64_t I, int64_t nblk_i,
+                                                                 int64_t nblk, OuterMap om,
+                                                                 const cx<double>* __restrict__ tw) {
+  __shared__ __align__(16) cx<double> buf[2 * 256 * kStagedColsD];
+  const int p = threadIdx.x & (kStagedColsD - 1), t = threadIdx.x >> 4;
+  staged256_loop_c128<SIGN>(buf, in, I, nblk_i, nblk, om, tw,
+                            [&](const cx<double>(&v)[8], int64_t, int64_t base) {
+                              const int64_t b = base + p;
+#pragma unroll
+                              for (int e = 0; e < 8; ++e) {
+                                if constexpr (NT)
+                                  store_nt(&out[b + (int64_t)(t + 32 * e) * I], v[e]);
+                                else
+                                  out[b + (int64_t)(t + 32 * e) * I] = v[e];
+                              }
+                            });
 }
 
 // The staged kernels take a pass when they apply, unless switched off
@@ -843,6 +859,107 @@ __global__ __launch_bounds__(512) void k_fft_strided_obs_staged(cx<float>* __res
                      });
 }
 
+// The complex128 form (16-column tiles; see k_fft_strided_staged_c128):
+// the register kernel's 16 columns sit in lanes 0..15 of a wave, lanes
+// 16..63 hold zeros, so the first two steps of the shuffle sum add 0.0.
+// c = sum over r = 0..31 (in that order) of the doubles at byte offsets
+// 128 r from LDS address a.
+__device__ __forceinline__ double lds_column_sum32(unsigned a) {
+  double c = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    qw_d2 y0, y1, y2, y3, y4, y5, y6, y7;
+    asm volatile(
+        "ds_read2_b64 %0, %8 offset0:0 offset1:16\n\t"
+        "ds_read2_b64 %1, %8 offset0:32 offset1:48\n\t"
+        "ds_read2_b64 %2, %8 offset0:64 offset1:80\n\t"
+        "ds_read2_b64 %3, %8 offset0:96 offset1:112\n\t"
+        "ds_read2_b64 %4, %8 offset0:128 offset1:144\n\t"
+        "ds_read2_b64 %5, %8 offset0:160 offset1:176\n\t"
+        "ds_read2_b64 %6, %8 offset0:192 offset1:208\n\t"
+        "ds_read2_b64 %7, %8 offset0:224 offset1:240\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(y0), "=&v"(y1), "=&v"(y2), "=&v"(y3), "=&v"(y4), "=&v"(y5), "=&v"(y6), "=&v"(y7)
+        : "v"(a + 2048u * h)
+        : "memory");
+    const qw_d2 y[8] = {y0, y1, y2, y3, y4, y5, y6, y7};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      c += y[i].x;
+      c += y[i].y;
+    }
+  }
+  return c;
+}
+
+__device__ __forceinline__ double wave_sum16(double v) {
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(512) void k_fft_strided_obs_staged_c128(
+    cx<double>* __restrict__ out, const cx<double>* __restrict__ in, int64_t I, int64_t nblk_i,
+    int64_t nblk, ObsFuse f, const cx<double>* __restrict__ tw) {
+  __shared__ __align__(16) cx<double> buf[2 * 256 * kStagedColsD];
+  __shared__ __align__(16) double red[3 * 512];
+  const int tid = threadIdx.x;
+  const int p = tid & (kStagedColsD - 1), t = tid >> 4;
+  const OuterMap om{nblk / nblk_i, 0, 0, 0};
+  const AxisImage32 a0 = axis_image32(axis_image(f.c[0], f.N[0]));
+  const double org[3] = {f.c[0], f.c[1], f.c[2]};
+  typedef __attribute__((address_space(3))) double* lds_dptr;
+  const unsigned ra = (unsigned)(size_t)(lds_dptr)(red + tid);
+  const unsigned rl = (unsigned)(size_t)(lds_dptr)(red + (tid & 63));  // column lane
+  staged256_loop_c128<-1>(buf, in, I, nblk_i, nblk, om, tw,
+                          [&](const cx<double>(&v)[8], int64_t blk, int64_t base) {
+                            if (f.store) {
+#pragma unroll
+                              for (int e = 0; e < 8; ++e)
+                                out[base + p + (int64_t)(t + 32 * e) * I] = v[e];
+                            }
+                            const int64_t o = blk / nblk_i;
+                            const int64_t col = base - o * 256 * I + p;
+                            double S0, S1, S11;
+                            obs_thread_moments<double, 256, 8>(v, t, I, col, f.dim, a0, S0, S1,
+                                                               S11);
+                            asm volatile(
+                                "ds_write_b64 %0, %1\n\t"
+                                "ds_write_b64 %0, %2 offset:4096\n\t"
+                                "ds_write_b64 %0, %3 offset:8192\n\t"
+                                "s_waitcnt lgkmcnt(0)\n\t"
+                                "s_barrier" ::"v"(ra),
+                                "v"(S0), "v"(S1), "v"(S11)
+                                : "memory");
+                            // fields over the waves as in k_fft_strided_obs_staged
+                            const int wave = tid >> 6, lane = tid & 63;
+                            if (wave < 7) {
+                              const int m = wave < 3 ? 0 : (wave < 6 ? 1 : 2);
+                              const int k0 = (0x04871630 >> (4 * wave)) & 15;
+                              const int k1r = (0x0FFFF952 >> (4 * wave)) & 15;
+                              const int k1 = k1r == 15 ? -1 : k1r;
+                              double v0 = 0.0, v1 = 0.0;
+                              if (lane < kStagedColsD) {
+                                const double c = lds_column_sum32(rl + 4096u * m);
+                                double wb, wc;
+                                obs_column_disp(col - p + lane, org, f, wb, wc);
+                                v0 = obs_field(k0, c, c, c, wb, wc);
+                                if (k1 >= 0) v1 = obs_field(k1, c, c, c, wb, wc);
+                              }
+                              v0 = wave_sum16((v0 + 0.0) + 0.0);
+                              if (k1 >= 0) v1 = wave_sum16((v1 + 0.0) + 0.0);
+                              if (lane == 0) {
+                                double* dst = f.partials + blk * kObsFields;
+                                dst[k0] = 0.0 + v0;
+                                if (k1 >= 0) dst[k1] = 0.0 + v1;
+                              }
+                            } else if (lane == 0) {
+                              double* dst = f.partials + blk * kObsFields;
+                              for (int k = 10; k < kObsFields; ++k) dst[k] = 0.0;
+                            }
+                          });
+}
+
 template <typename T, int L>
 static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int64_t I,
                                   const ObsFuse& f, const cx<T>* tw, hipStream_t st) {
@@ -855,13 +972,17 @@ static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int
   const int64_t nblk_i = I / P;
   const int64_t nblk = (int64_t)s * B * nblk_i;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  if constexpr (sizeof(T) == 4 && L == 256) {
-    if (!f.origins && use_staged(false, -1, L, (int64_t)s * B, I)) {
-      static_assert(TT * kStagedCols == 512, "staged tiles are the register kernel's");
+  if constexpr (L == 256) {
+    if (!f.origins && use_staged(sizeof(T) == 8, -1, L, (int64_t)s * B, I)) {
+      static_assert(TT * (sizeof(T) == 8 ? kStagedColsD : kStagedCols) == 512,
+                    "staged tiles are the register kernel's");
       const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
-      hipLaunchKernelGGL(k_fft_strided_obs_staged, dim3((unsigned)ng), dim3(512), 0, st,
-                         (cx<float>*)out, (const cx<float>*)in, I, nblk_i, nblk, f,
-                         (const cx<float>*)tw);
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL(k_fft_strided_obs_staged_c128, dim3((unsigned)ng), dim3(512), 0, st,
+                           out, in, I, nblk_i, nblk, f, tw);
+      else
+        hipLaunchKernelGGL(k_fft_strided_obs_staged, dim3((unsigned)ng), dim3(512), 0, st, out,
+                           in, I, nblk_i, nblk, f, tw);
       return hipGetLastError();
     }
   }
