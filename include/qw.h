@@ -357,14 +357,15 @@ qw_status qw_evolve_fft_timed(qw_plan_t plan, const void* psi0, void* psi_t, int
 qw_status qw_set_step_kernel(int two_step, int tile_shape, int chunk);
 
 /* Measurement of the strided FFT passes (process-wide). staged = 1 (the
- * default): passes of length 256 over at least 8192 tiles stage their loads
- * through LDS with the global-to-LDS loads of gfx950, double-buffered, eight
- * tiles per workgroup: at complex64 the inverse passes (tiles of 32 columns;
- * a 256^3 field of 4 components), at complex128 the passes of either
- * direction whose rows lie at least 4096 elements apart (tiles of 16
- * columns; the n1 passes of a 256^3 field); staged = 0: every pass keeps
- * its loads in registers. Both give the same bits (the same tiles and
- * arithmetic). */
+ * default): passes over at least 8192 tiles stage their loads through LDS
+ * with the global-to-LDS loads of gfx950, double-buffered, eight tiles per
+ * workgroup: complex64 inverse passes of length 256 (tiles of 32 columns; a
+ * 256^3 field of 4 components), complex64 passes of length 512 of either
+ * direction (tiles of 16 columns; a 512^3 field), complex128 passes of
+ * length 256 of either direction whose rows lie at least 4096 elements
+ * apart (tiles of 16 columns; the n1 passes of a 256^3 field); staged = 0:
+ * every pass keeps its loads in registers. Both give the same bits (the
+ * same tiles and arithmetic). */
 qw_status qw_set_fft_kernel(int staged);
 
 /* Schedule of the Fourier evolution. slab_planes = 0 runs the n2 and fused

@@ -66,13 +66,13 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
   }
 }
 
-// Length-256 complex64 passes with their loads staged through LDS by the
-// global-to-LDS loads of gfx950 (16 bytes per lane), double-buffered: a
-// workgroup of 512 threads takes kStagedTiles tiles of 32 columns (256-byte
-// rows) in turn, and the next tile's loads are in flight while the current
-// one is transformed and stored, without holding registers. The tiles and
-// their arithmetic are those of the register kernel at this length (E = 16,
-// 32 columns), so both give the same bits.
+// Strided passes with their loads staged through LDS by the global-to-LDS
+// loads of gfx950 (16 bytes per lane), double-buffered: a workgroup of 512
+// threads takes kStagedTiles tiles in turn, and the next tile's loads are in
+// flight while the current one is transformed and stored, without holding
+// registers. The tiles and their arithmetic are those of the register
+// kernel at the same length and precision, so both give the same bits.
+// First length 256 at complex64: tiles of 32 columns (256-byte rows), E = 16.
 //
 // Each wave stages exactly the rows its own threads read: thread (p, t) of
 // the team holds rows t + 16 e, and slot (t >> 1) * 32 + 2 e + (t & 1) of
@@ -250,6 +250,175 @@ __global__ __launch_bounds__(512) void k_fft_strided_staged(cx<float>* __restric
                                    out[b + (int64_t)(t + 16 * e) * I] = v[e];
                                }
                              });
+}
+
+// y[e] = the 8-byte value at LDS bytes a + 4096 e (e = 0..15), then the
+// workgroup barrier.
+__device__ __forceinline__ void lds_read16_st64(unsigned a, cx<float> (&y)[16]) {
+  qw_f4 q0, q1, q2, q3, q4, q5, q6, q7;
+  asm volatile(
+      "ds_read2st64_b64 %0, %8 offset0:0 offset1:8\n\t"
+      "ds_read2st64_b64 %1, %8 offset0:16 offset1:24\n\t"
+      "ds_read2st64_b64 %2, %8 offset0:32 offset1:40\n\t"
+      "ds_read2st64_b64 %3, %8 offset0:48 offset1:56\n\t"
+      "ds_read2st64_b64 %4, %8 offset0:64 offset1:72\n\t"
+      "ds_read2st64_b64 %5, %8 offset0:80 offset1:88\n\t"
+      "ds_read2st64_b64 %6, %8 offset0:96 offset1:104\n\t"
+      "ds_read2st64_b64 %7, %8 offset0:112 offset1:120\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "s_barrier"
+      : "=&v"(q0), "=&v"(q1), "=&v"(q2), "=&v"(q3), "=&v"(q4), "=&v"(q5), "=&v"(q6), "=&v"(q7)
+      : "v"(a)
+      : "memory");
+  const qw_f4 q[8] = {q0, q1, q2, q3, q4, q5, q6, q7};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    y[2 * i] = mk(q[i].x, q[i].y);
+    y[2 * i + 1] = mk(q[i].z, q[i].w);
+  }
+}
+
+// Length-512 complex64: tiles of 16 columns (128-byte rows) and the
+// register kernel's transform at this length, E = 16 (radix 16, 16, 2).
+// Thread (p, t), p < 16, t < 32, holds rows t + 32 e; wave w holds
+// t = 4w .. 4w+3, and slot (t >> 2) * 64 + 4 e + (t & 3) of the buffer holds
+// row t + 32 e.
+constexpr int kStaged512Cols = 16;
+
+__device__ __forceinline__ void stage_tile512(cx<float>* __restrict__ buf,
+                                              const cx<float>* __restrict__ in, int64_t tile,
+                                              int64_t I, int tid) {
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+  const int64_t col = 2 * (l & 7);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    // one instruction: eight 128-byte rows, slots 8j .. 8j+7 of this wave
+    const int q = 8 * j + (l >> 3);
+    const int64_t r = 4 * w + (q & 3) + 32 * (q >> 2);
+    __builtin_amdgcn_global_load_lds(in + tile + r * I + col,
+                                     buf + (w * 64 + 8 * j) * kStaged512Cols, 16, 0, 0);
+  }
+}
+
+// Twiddles of thread t for the last two stages: w2[r] (stage 2, k = t & 15,
+// r = 1..15) and w3[b] (stage 3, k = t + 32 b).
+template <int SIGN>
+struct Tw512F {
+  cx<float> w2[16], w3[8];
+  __device__ __forceinline__ void load(const cx<float>* __restrict__ tw, int t) {
+#pragma unroll
+    for (int r = 1; r < 16; ++r) w2[r] = twiddle<SIGN>(tw, r * (t & 15) * (TWN / 256));
+#pragma unroll
+    for (int b = 0; b < 8; ++b) w3[b] = twiddle<SIGN>(tw, (t + 32 * b) * (TWN / 512));
+  }
+};
+
+// The register kernel's three Stockham stages at L = 512, E = 16, with the
+// twiddles from registers and the exchanges written out. X: byte address
+// in LDS of this thread's column (element (pos, p) at X + 128 pos).
+template <int SIGN>
+__device__ __forceinline__ void fft512_regs(cx<float> (&v)[16], unsigned X, int t,
+                                            const Tw512F<SIGN>& W) {
+  // stage 1 (radix 16, no twiddles): positions 16 t + r, bytes 2048 t + 128 r
+  dft_reg<16, SIGN>(v);
+  asm volatile(
+      "ds_write2_b64 %0, %1, %2 offset0:0 offset1:16\n\t"
+      "ds_write2_b64 %0, %3, %4 offset0:32 offset1:48\n\t"
+      "ds_write2_b64 %0, %5, %6 offset0:64 offset1:80\n\t"
+      "ds_write2_b64 %0, %7, %8 offset0:96 offset1:112\n\t"
+      "ds_write2_b64 %0, %9, %10 offset0:128 offset1:144\n\t"
+      "ds_write2_b64 %0, %11, %12 offset0:160 offset1:176\n\t"
+      "ds_write2_b64 %0, %13, %14 offset0:192 offset1:208\n\t"
+      "ds_write2_b64 %0, %15, %16 offset0:224 offset1:240\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "s_barrier" ::"v"(X + 2048u * t),
+      "v"(f2(v[0])), "v"(f2(v[1])), "v"(f2(v[2])), "v"(f2(v[3])), "v"(f2(v[4])), "v"(f2(v[5])),
+      "v"(f2(v[6])), "v"(f2(v[7])), "v"(f2(v[8])), "v"(f2(v[9])), "v"(f2(v[10])), "v"(f2(v[11])),
+      "v"(f2(v[12])), "v"(f2(v[13])), "v"(f2(v[14])), "v"(f2(v[15]))
+      : "memory");
+  lds_read16_st64(X + 128u * t, v);
+  // stage 2 (radix 16): positions (t >> 4) 256 + (t & 15) + 16 r, bytes
+  // 128 ((t >> 4) 256 + (t & 15)) + 2048 r
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], W.w2[r]);
+  dft_reg<16, SIGN>(v);
+  asm volatile(
+      "ds_write2st64_b64 %0, %1, %2 offset0:0 offset1:4\n\t"
+      "ds_write2st64_b64 %0, %3, %4 offset0:8 offset1:12\n\t"
+      "ds_write2st64_b64 %0, %5, %6 offset0:16 offset1:20\n\t"
+      "ds_write2st64_b64 %0, %7, %8 offset0:24 offset1:28\n\t"
+      "ds_write2st64_b64 %0, %9, %10 offset0:32 offset1:36\n\t"
+      "ds_write2st64_b64 %0, %11, %12 offset0:40 offset1:44\n\t"
+      "ds_write2st64_b64 %0, %13, %14 offset0:48 offset1:52\n\t"
+      "ds_write2st64_b64 %0, %15, %16 offset0:56 offset1:60\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "s_barrier" ::"v"(X + 128u * ((t >> 4) * 256 + (t & 15))),
+      "v"(f2(v[0])), "v"(f2(v[1])), "v"(f2(v[2])), "v"(f2(v[3])), "v"(f2(v[4])), "v"(f2(v[5])),
+      "v"(f2(v[6])), "v"(f2(v[7])), "v"(f2(v[8])), "v"(f2(v[9])), "v"(f2(v[10])), "v"(f2(v[11])),
+      "v"(f2(v[12])), "v"(f2(v[13])), "v"(f2(v[14])), "v"(f2(v[15]))
+      : "memory");
+  lds_read16_st64(X + 128u * t, v);
+  // stage 3 (radix 2, eight butterflies per thread): in place in v
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    cx<float> a[2] = {v[b], cmul(v[b + 8], W.w3[b])};
+    dft_reg<2, SIGN>(a);
+    v[b] = a[0];
+    v[b + 8] = a[1];
+  }
+}
+
+template <int SIGN, bool NT>
+__global__ __launch_bounds__(512) void k_fft_strided_staged512(cx<float>* __restrict__ out,
+                                                               const cx<float>* __restrict__ in,
+                                                               int64_t I, int64_t nblk_i,
+                                                               int64_t nblk, OuterMap om,
+                                                               const cx<float>* __restrict__ tw) {
+  __shared__ __align__(16) cx<float> buf[2 * 512 * kStaged512Cols];
+  const int tid = threadIdx.x;
+  const int p = tid & (kStaged512Cols - 1), t = tid >> 4;
+  Tw512F<SIGN> W;
+  W.load(tw, t);
+  auto tile_base = [&](int64_t blk) -> int64_t {
+    const int64_t o = blk / nblk_i;
+    const int64_t i0 = (blk - o * nblk_i) * kStaged512Cols;
+    const int64_t comp = o / om.ocount;
+    const int64_t plane = om.o0 + (o - comp * om.ocount);
+    return comp * om.ostride + plane * 512 * I + i0;
+  };
+  const int64_t first = (int64_t)blockIdx.x * kStagedTiles;
+  if (first >= nblk) return;
+  const int n = nblk - first < kStagedTiles ? (int)(nblk - first) : kStagedTiles;
+  int64_t cur = tile_base(first);
+  stage_tile512(buf, in, cur, I, tid);
+  typedef __attribute__((address_space(3))) cx<float>* lds_ptr;
+  const int s0 = (t >> 2) * 64 + (t & 3);
+  for (int k = 0; k < n; ++k) {
+    cx<float>* X = buf + (k & 1) * (512 * kStaged512Cols);
+    cx<float>* Y = buf + ((k + 1) & 1) * (512 * kStaged512Cols);
+    vm_drain();
+    cx<float> v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = X[(s0 + 4 * e) * kStaged512Cols + p];
+    // every wave has its rows before the exchange writes X, and the last
+    // reads of Y (the previous tile's exchange) are done
+    lds_barrier();
+    int64_t nxt = 0;
+    if (k + 1 < n) {
+      nxt = tile_base(first + k + 1);
+      stage_tile512(Y, in, nxt, I, tid);
+    }
+    fft512_regs<SIGN>(v, (unsigned)(size_t)(lds_ptr)(X + p), t, W);
+    const int64_t b = cur + p;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      if constexpr (NT)
+        store_nt(&out[b + (int64_t)(t + 32 * e) * I], v[e]);
+      else
+        out[b + (int64_t)(t + 32 * e) * I] = v[e];
+    }
+    cur = nxt;
+  }
 }
 
 // The complex128 form: tiles of 16 columns (256-byte rows) and the register
@@ -437,8 +606,12 @@ __global__ __launch_bounds__(512) void k_fft_strided_staged_c128(cx<double>* __r
 }
 
 // The staged kernels take a pass when they apply, unless switched off
-// (qw_set_fft_kernel): length 256, whole tiles, at least kStagedMinTiles
-// of them, and
+// (qw_set_fft_kernel): whole tiles, at least kStagedMinTiles of them, and
+// * length 512, complex64: both directions. At 512^3 the n1 forward pass
+//   2.82 -> 2.17 ms, n2 forward 1.77 -> 1.63, n2 inverse 1.83 -> 1.61, n1
+//   inverse 2.37 -> 2.08 (the jump 10.8 -> 9.5 ms); in XCD order slightly
+//   slower (9.66 ms).
+// Length 256:
 // * complex64: the inverse direction. The forward passes measured slower
 //   staged (0.246 and 0.210 ms against 0.226 and 0.190 at 256^3; in XCD
 //   order 0.240 and 0.183, but the fused pass after them then took 0.245
@@ -451,6 +624,24 @@ __global__ __launch_bounds__(512) void k_fft_strided_staged_c128(cx<double>* __r
 static std::atomic<bool> g_staged{true};
 
 void set_fft_staged(bool on) { g_staged.store(on, std::memory_order_relaxed); }
+
+static bool use_staged512(bool dbl, int64_t L, int64_t O, int64_t I) {
+  return g_staged.load(std::memory_order_relaxed) && L == 512 && !dbl &&
+         I % kStaged512Cols == 0 && O * (I / kStaged512Cols) >= kStagedMinTiles;
+}
+
+static hipError_t run_staged512(cx<float>* out, const cx<float>* in, int64_t O, int64_t I,
+                                const OuterMap& om, const cx<float>* tw, hipStream_t st,
+                                int sign) {
+  const int64_t nblk_i = I / kStaged512Cols;
+  const int64_t nblk = O * nblk_i;
+  const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
+  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
+  auto kern = sign > 0 ? (om.nt ? k_fft_strided_staged512<1, true> : k_fft_strided_staged512<1, false>)
+                       : (om.nt ? k_fft_strided_staged512<-1, true> : k_fft_strided_staged512<-1, false>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
+  return hipGetLastError();
+}
 
 static bool use_staged(bool dbl, int sign, int64_t L, int64_t O, int64_t I) {
   if (!g_staged.load(std::memory_order_relaxed) || L != 256) return false;
@@ -564,6 +755,9 @@ hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, con
                                    int64_t I, const void* tw, hipStream_t st, bool nt) {
   const OuterMap om{ocount, o0, ostride, nt ? 1 : 0};
   const int64_t O = ncomp * ocount;
+  if (use_staged512(dbl, L, O, I))
+    return run_staged512((cx<float>*)out, (const cx<float>*)in, O, I, om, (const cx<float>*)tw,
+                         st, sign);
   if (use_staged(dbl, sign, L, O, I))
     return dbl ? run_staged<double>((cx<double>*)out, (const cx<double>*)in, O, I, om,
                                     (const cx<double>*)tw, st, sign)
@@ -603,10 +797,13 @@ hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const vo
 // (1) over the thread's E values (rows t + TT e of column col): only the
 // axis-0 displacement varies along the pass, so three moments in it
 // suffice (the other axes are fixed per column);
+// Every operation is rounded on its own (no contraction into FMAs), so
+// that the register and the staged kernels give the same sums.
 template <typename T, int L, int E>
 __device__ __forceinline__ void obs_thread_moments(const cx<T> (&v)[E], int t, int64_t I,
                                                    int64_t col, int dim, const AxisImage32& a0,
                                                    double& S0, double& S1, double& S11) {
+#pragma clang fp contract(off)
   constexpr int TT = L / E;
   S0 = 0.0;
   S1 = 0.0;

@@ -36,14 +36,18 @@ template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.x + b.x, a.y + b.y); }
 template <typename T>
 __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+// Complex products written as one multiply and one FMA per part, so that
+// their rounding does not depend on how the compiler contracts them in a
+// given kernel: every kernel that runs the same transform steps then gives
+// the same bits.
 template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return mk(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 // a * conj(b)
 template <typename T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
-  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+  return mk(fma(a.x, b.x, a.y * b.y), fma(a.y, b.x, -(a.x * b.y)));
 }
 template <typename T>
 __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
@@ -76,7 +80,7 @@ __device__ __forceinline__ cx<T> rot16(cx<T> d, int idx) {
   if (idx == 12) return SIGN > 0 ? mk(d.y, -d.x) : mk(-d.y, d.x);
   const T c = (T)kCos16[idx];
   const T s = (T)(SIGN * kCos16[(idx + 12) & 15]);
-  return mk(d.x * c - d.y * s, d.x * s + d.y * c);
+  return mk(fma(d.x, c, -(d.y * s)), fma(d.x, s, d.y * c));
 }
 
 __host__ __device__ constexpr int bitrev(int i, int bits) {

@@ -443,9 +443,10 @@ def set_step_kernel(two_step=False, tile_shape=0, chunk=0):
 
 
 def set_fft_kernel(staged=True):
-    """qw_set_fft_kernel (measurement): length-256 strided passes of large
-    fields (complex64 inverse, complex128 n1-like) staged through LDS (the
-    default) or with their loads in registers; the same bits either way."""
+    """qw_set_fft_kernel (measurement): strided passes of large fields
+    (complex64 length-256 inverse and length-512, complex128 length-256 with
+    far-apart rows) staged through LDS (the default) or with their loads in
+    registers; the same bits either way."""
     _check(LIB.qw_set_fft_kernel(1 if staged else 0))
 
 

@@ -1,10 +1,11 @@
 """Strided FFT passes staged through LDS (global-to-LDS loads, double
 buffered) against the register kernels they replace, bit for bit.
 
-The staged kernels take the length-256 passes of at least 8192 tiles: at
-complex64 the inverse ones (32-column tiles; a 256^3 field of four
-components), at complex128 those whose rows are at least 4096 elements apart,
-both directions (16-column tiles; the n1 passes at 256^3); with
+The staged kernels take the passes of at least 8192 tiles: at complex64 the
+length-256 inverse ones (32-column tiles; a 256^3 field of four components)
+and the length-512 ones of both directions (16-column tiles), at complex128
+the length-256 ones whose rows are at least 4096 elements apart, both
+directions (16-column tiles; the n1 passes at 256^3); with
 qw_set_fft_kernel(0) every pass keeps its loads in registers. Both run the
 same tiles through the same arithmetic, so every result must have the same
 bits: the field of a jump (Sec. 4: the Fourier evaluation of U^t), the
@@ -131,6 +132,21 @@ def test_complex128_batched(qw):
     x = _field(plan, 29, B=2)
     print("batched 2 x 256x128x256 complex128", flush=True)
     a, b = _both(qw, lambda: plan.evolve_fft_batched(x, [0.2, 0.05], [333, -70]))
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("shape", [[512, 128, 256], [256, 512, 128]])
+def test_length_512_passes(qw, shape):
+    """complex64 passes of length 512 (the n1 pass over 32768-column rows,
+    then the n2 pass over 128-column rows), both directions."""
+    plan = qw.Plan(3, shape, 0.1, "c64")
+    x = _field(plan, 31)
+    print("length-512 passes: %s" % shape, flush=True)
+    for d in (1, -1):
+        ta, tb = _both(qw, lambda: plan.transform(x, d))
+        assert torch.equal(ta, tb), d
+        del ta, tb
+    a, b = _both(qw, lambda: plan.evolve_fft(x, -999))
     assert torch.equal(a, b)
 
 
