@@ -362,8 +362,9 @@ qw_status qw_set_step_kernel(int two_step, int tile_shape, int chunk);
  * workgroup: complex64 inverse passes of length 256 (tiles of 32 columns; a
  * 256^3 field of 4 components), complex64 passes of length 512 of either
  * direction (tiles of 16 columns; a 512^3 field), complex128 passes of
- * length 256 of either direction whose rows lie at least 4096 elements
- * apart (tiles of 16 columns; the n1 passes of a 256^3 field); staged = 0:
+ * length 256 and 512 of either direction whose rows lie at least 4096
+ * elements apart (tiles of 16 and 8 columns; the n1 passes of 256^3 and
+ * 512^3 fields); staged = 0:
  * every pass keeps its loads in registers. Both give the same bits (the
  * same tiles and arithmetic). */
 qw_status qw_set_fft_kernel(int staged);

@@ -605,12 +605,120 @@ __global__ __launch_bounds__(512) void k_fft_strided_staged_c128(cx<double>* __r
                             });
 }
 
+// Length 512 at complex128: tiles of 8 columns (128-byte rows) and the
+// register kernel's transform there, E = 8 (radix 8, 8, 8). Thread (p, t),
+// p < 8, t < 64, holds rows t + 64 e; wave w holds t = 8w .. 8w+7, and slot
+// (t >> 3) * 64 + 8 e + (t & 7) of the buffer holds row t + 64 e.
+constexpr int kStaged512ColsD = 8;
+
+__device__ __forceinline__ void stage_tile512_c128(cx<double>* __restrict__ buf,
+                                                   const cx<double>* __restrict__ in,
+                                                   int64_t tile, int64_t I, int tid) {
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    // one instruction: eight 128-byte rows, slots 8j .. 8j+7 of this wave
+    const int64_t r = 8 * w + (l >> 3) + 64 * j;
+    __builtin_amdgcn_global_load_lds(in + tile + r * I + (l & 7),
+                                     buf + (w * 64 + 8 * j) * kStaged512ColsD, 16, 0, 0);
+  }
+}
+
+// y[k] = the 16-byte value at LDS bytes a + 8192 k (k = 0..7), then the
+// workgroup barrier (lds_read8_b128); and the twiddles of thread t for the
+// last two stages: w2[r] (stage 2, k = t & 7) and w3[r] (stage 3, k = t).
+template <int SIGN>
+struct Tw512D {
+  cx<double> w2[8], w3[8];
+  __device__ __forceinline__ void load(const cx<double>* __restrict__ tw, int t) {
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+      w2[r] = twiddle<SIGN>(tw, r * (t & 7) * (TWN / 64));
+      w3[r] = twiddle<SIGN>(tw, r * t * (TWN / 512));
+    }
+  }
+};
+
+// The register kernel's three Stockham stages at L = 512, E = 8. X: byte
+// address in LDS of this thread's column (element (pos, p) at X + 128 pos).
+template <int SIGN>
+__device__ __forceinline__ void fft512_c128(cx<double> (&v)[8], unsigned X, int t,
+                                            const Tw512D<SIGN>& W) {
+  // stage 1 (radix 8, no twiddles): positions 8t + r
+  dft_reg<8, SIGN>(v);
+  lds_write8_b128<128>(X + 1024u * t, v);
+  lds_read8_b128(X + 128u * t, v);
+  // stage 2 (radix 8): positions (t >> 3) 64 + (t & 7) + 8 r
+#pragma unroll
+  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], W.w2[r]);
+  dft_reg<8, SIGN>(v);
+  lds_write8_b128<1024>(X + 128u * ((t >> 3) * 64 + (t & 7)), v);
+  lds_read8_b128(X + 128u * t, v);
+  // stage 3 (radix 8, the last): in place in v
+#pragma unroll
+  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], W.w3[r]);
+  dft_reg<8, SIGN>(v);
+}
+
+template <int SIGN, bool NT>
+__global__ __launch_bounds__(512) void k_fft_strided_staged512_c128(
+    cx<double>* __restrict__ out, const cx<double>* __restrict__ in, int64_t I, int64_t nblk_i,
+    int64_t nblk, OuterMap om, const cx<double>* __restrict__ tw) {
+  __shared__ __align__(16) cx<double> buf[2 * 512 * kStaged512ColsD];
+  const int tid = threadIdx.x;
+  const int p = tid & (kStaged512ColsD - 1), t = tid >> 3;
+  Tw512D<SIGN> W;
+  W.load(tw, t);
+  auto tile_base = [&](int64_t blk) -> int64_t {
+    const int64_t o = blk / nblk_i;
+    const int64_t i0 = (blk - o * nblk_i) * kStaged512ColsD;
+    const int64_t comp = o / om.ocount;
+    const int64_t plane = om.o0 + (o - comp * om.ocount);
+    return comp * om.ostride + plane * 512 * I + i0;
+  };
+  const int64_t first = (int64_t)blockIdx.x * kStagedTiles;
+  if (first >= nblk) return;
+  const int n = nblk - first < kStagedTiles ? (int)(nblk - first) : kStagedTiles;
+  int64_t cur = tile_base(first);
+  stage_tile512_c128(buf, in, cur, I, tid);
+  typedef __attribute__((address_space(3))) cx<double>* lds_ptr;
+  const int s0 = (t >> 3) * 64 + (t & 7);
+  for (int k = 0; k < n; ++k) {
+    cx<double>* X = buf + (k & 1) * (512 * kStaged512ColsD);
+    cx<double>* Y = buf + ((k + 1) & 1) * (512 * kStaged512ColsD);
+    vm_drain();
+    cx<double> v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = X[(s0 + 8 * e) * kStaged512ColsD + p];
+    lds_barrier();
+    int64_t nxt = 0;
+    if (k + 1 < n) {
+      nxt = tile_base(first + k + 1);
+      stage_tile512_c128(Y, in, nxt, I, tid);
+    }
+    fft512_c128<SIGN>(v, (unsigned)(size_t)(lds_ptr)(X + p), t, W);
+    const int64_t b = cur + p;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if constexpr (NT)
+        store_nt(&out[b + (int64_t)(t + 64 * e) * I], v[e]);
+      else
+        out[b + (int64_t)(t + 64 * e) * I] = v[e];
+    }
+    cur = nxt;
+  }
+}
+
 // The staged kernels take a pass when they apply, unless switched off
 // (qw_set_fft_kernel): whole tiles, at least kStagedMinTiles of them, and
 // * length 512, complex64: both directions. At 512^3 the n1 forward pass
 //   2.82 -> 2.17 ms, n2 forward 1.77 -> 1.63, n2 inverse 1.83 -> 1.61, n1
 //   inverse 2.37 -> 2.08 (the jump 10.8 -> 9.5 ms); in XCD order slightly
 //   slower (9.66 ms).
+// * length 512, complex128: rows at least 4096 elements apart, both
+//   directions: at 512^3 the n1 passes 4.83 -> 4.32 ms and 4.64 -> 4.32 ms,
+//   where the n2 passes (8 KB apart) measured slower (3.05 -> 3.37 ms); in
+//   XCD order the n1 passes 4.44 and 4.42 ms.
 // Length 256:
 // * complex64: the inverse direction. The forward passes measured slower
 //   staged (0.246 and 0.210 ms against 0.226 and 0.190 at 256^3; in XCD
@@ -626,8 +734,23 @@ static std::atomic<bool> g_staged{true};
 void set_fft_staged(bool on) { g_staged.store(on, std::memory_order_relaxed); }
 
 static bool use_staged512(bool dbl, int64_t L, int64_t O, int64_t I) {
-  return g_staged.load(std::memory_order_relaxed) && L == 512 && !dbl &&
-         I % kStaged512Cols == 0 && O * (I / kStaged512Cols) >= kStagedMinTiles;
+  if (!g_staged.load(std::memory_order_relaxed) || L != 512) return false;
+  const int cols = dbl ? kStaged512ColsD : kStaged512Cols;
+  if (I % cols != 0 || O * (I / cols) < kStagedMinTiles) return false;
+  return !dbl || I >= 4096;
+}
+
+static hipError_t run_staged512_c128(cx<double>* out, const cx<double>* in, int64_t O, int64_t I,
+                                     const OuterMap& om, const cx<double>* tw, hipStream_t st,
+                                     int sign) {
+  const int64_t nblk_i = I / kStaged512ColsD;
+  const int64_t nblk = O * nblk_i;
+  const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
+  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
+  auto kern = sign > 0 ? (om.nt ? k_fft_strided_staged512_c128<1, true> : k_fft_strided_staged512_c128<1, false>)
+                       : (om.nt ? k_fft_strided_staged512_c128<-1, true> : k_fft_strided_staged512_c128<-1, false>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
+  return hipGetLastError();
 }
 
 static hipError_t run_staged512(cx<float>* out, const cx<float>* in, int64_t O, int64_t I,
@@ -756,8 +879,10 @@ hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, con
   const OuterMap om{ocount, o0, ostride, nt ? 1 : 0};
   const int64_t O = ncomp * ocount;
   if (use_staged512(dbl, L, O, I))
-    return run_staged512((cx<float>*)out, (const cx<float>*)in, O, I, om, (const cx<float>*)tw,
-                         st, sign);
+    return dbl ? run_staged512_c128((cx<double>*)out, (const cx<double>*)in, O, I, om,
+                                    (const cx<double>*)tw, st, sign)
+               : run_staged512((cx<float>*)out, (const cx<float>*)in, O, I, om,
+                               (const cx<float>*)tw, st, sign);
   if (use_staged(dbl, sign, L, O, I))
     return dbl ? run_staged<double>((cx<double>*)out, (const cx<double>*)in, O, I, om,
                                     (const cx<double>*)tw, st, sign)

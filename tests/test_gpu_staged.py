@@ -4,8 +4,9 @@ buffered) against the register kernels they replace, bit for bit.
 The staged kernels take the passes of at least 8192 tiles: at complex64 the
 length-256 inverse ones (32-column tiles; a 256^3 field of four components)
 and the length-512 ones of both directions (16-column tiles), at complex128
-the length-256 ones whose rows are at least 4096 elements apart, both
-directions (16-column tiles; the n1 passes at 256^3); with
+the length-256 and -512 ones whose rows are at least 4096 elements apart,
+both directions (16- and 8-column tiles; the n1 passes at 256^3 and 512^3);
+with
 qw_set_fft_kernel(0) every pass keeps its loads in registers. Both run the
 same tiles through the same arithmetic, so every result must have the same
 bits: the field of a jump (Sec. 4: the Fourier evaluation of U^t), the
@@ -147,6 +148,20 @@ def test_length_512_passes(qw, shape):
         assert torch.equal(ta, tb), d
         del ta, tb
     a, b = _both(qw, lambda: plan.evolve_fft(x, -999))
+    assert torch.equal(a, b)
+
+
+def test_complex128_length_512(qw):
+    """512 x 128 x 128 complex128: the n1 pass (length 512, 16384-column rows)
+    staged, both directions."""
+    plan = qw.Plan(3, [512, 128, 128], 0.25, "c128")
+    x = _field(plan, 37)
+    print("complex128 length-512 n1 pass", flush=True)
+    for d in (1, -1):
+        ta, tb = _both(qw, lambda: plan.transform(x, d))
+        assert torch.equal(ta, tb), d
+        del ta, tb
+    a, b = _both(qw, lambda: plan.evolve_fft(x, 12))
     assert torch.equal(a, b)
 
 
