@@ -71,19 +71,21 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
 // threads takes kStagedTiles tiles in turn, and the next tile's loads are in
 // flight while the current one is transformed and stored, without holding
 // registers. The tiles and their arithmetic are those of the register
-// kernel at the same length and precision, so both give the same bits.
-// First length 256 at complex64: tiles of 32 columns (256-byte rows), E = 16.
+// kernel at the same length and precision (COLS columns per tile, E
+// elements per thread: thread (p, t), p < COLS, holds rows t + TT e of
+// column p, TT = L / E), so both give the same bits.
 //
-// Each wave stages exactly the rows its own threads read: thread (p, t) of
-// the team holds rows t + 16 e, and slot (t >> 1) * 32 + 2 e + (t & 1) of
-// the buffer holds row t + 16 e, so a wave waits for its own loads only.
-// Tiles per workgroup, measured on the n1 inverse pass at 256^3 (8192
-// tiles): 8 tiles 0.197 ms (1024 workgroups, four per CU in turn), 4 tiles
-// 0.207, 2 tiles 0.219, 1 tile 0.243, against 0.213 for the register
+// Each wave stages exactly the rows its own threads read: a wave holds
+// TPW = 64 / COLS values of t and RPW = TPW E rows, and slot
+// (t / TPW) RPW + TPW e + t % TPW of the buffer holds row t + TT e, so a
+// wave waits for its own loads only.
+//
+// Tiles per workgroup, measured on the n1 inverse pass at 256^3 complex64
+// (8192 tiles): 8 tiles 0.197 ms (1024 workgroups, four per CU in turn), 4
+// tiles 0.207, 2 tiles 0.219, 1 tile 0.243, against 0.213 for the register
 // kernel; 6 and 12 (workgroup counts not a multiple of the 256 CUs) 0.227
 // and 0.217. Launches of fewer than kStagedMinTiles tiles (four workgroups
 // of eight tiles per CU) keep the register kernel.
-constexpr int kStagedCols = 32;
 constexpr int kStagedTiles = 8;
 constexpr int64_t kStagedMinTiles = 8192;
 
@@ -100,157 +102,24 @@ __device__ __forceinline__ void lds_barrier() {
 // in an earlier iteration of a loop as outstanding at their use.
 __device__ __forceinline__ void vm_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// One tile (256 rows of 32 columns from `tile`, row stride I) into buf.
-__device__ __forceinline__ void stage_tile256(cx<float>* __restrict__ buf,
-                                              const cx<float>* __restrict__ in, int64_t tile,
-                                              int64_t I, int tid) {
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
-  const int64_t col = 2 * (l & 15);
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    // one instruction: four 256-byte rows, slots 4j .. 4j+3 of this wave
-    const int q = 4 * j + (l >> 4);
-    const int64_t r = 2 * w + (q & 1) + 16 * (q >> 1);
-    __builtin_amdgcn_global_load_lds(in + tile + r * I + col,
-                                     buf + (w * 32 + 4 * j) * kStagedCols, 16, 0, 0);
-  }
-}
-
 typedef float qw_f2 __attribute__((ext_vector_type(2)));
 typedef float qw_f4 __attribute__((ext_vector_type(4)));
+typedef double qw_d2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ qw_f2 f2(cx<float> z) { return qw_f2{z.x, z.y}; }
+__device__ __forceinline__ qw_d2 d2(cx<double> z) { return qw_d2{z.x, z.y}; }
 
-// The 256-point transform of the thread's column as two radix-16 Stockham
-// stages (those of fft_team at E = 16) with the stage twiddles in registers
-// (they depend on the thread's place only), so no global load is issued
-// while a tile's loads are in flight. X: this thread's column of the tile
-// buffer. The exchange's LDS accesses are written out with their waits:
-// compiled ones would also wait for the next tile's loads into the other
-// buffer, which the compiler cannot tell apart from X.
-template <int SIGN>
-__device__ __forceinline__ void fft256_regs(cx<float> (&v)[16], cx<float>* __restrict__ X, int t,
-                                            const cx<float> (&w)[16]) {
-  typedef __attribute__((address_space(3))) cx<float>* lds_ptr;
-  dft_reg<16, SIGN>(v);
-  // X[(16 t + r) * kStagedCols] = v[r]: byte offset 4096 t + 256 r, i.e.
-  // 32 r in the 8-byte units of ds_write2_b64 (r < 8; then from + 2048)
-  const unsigned aw = (unsigned)(size_t)(lds_ptr)(X + 16 * t * kStagedCols);
-  asm volatile(
-      "ds_write2_b64 %0, %2, %3 offset0:0 offset1:32\n\t"
-      "ds_write2_b64 %0, %4, %5 offset0:64 offset1:96\n\t"
-      "ds_write2_b64 %0, %6, %7 offset0:128 offset1:160\n\t"
-      "ds_write2_b64 %0, %8, %9 offset0:192 offset1:224\n\t"
-      "ds_write2_b64 %1, %10, %11 offset0:0 offset1:32\n\t"
-      "ds_write2_b64 %1, %12, %13 offset0:64 offset1:96\n\t"
-      "ds_write2_b64 %1, %14, %15 offset0:128 offset1:160\n\t"
-      "ds_write2_b64 %1, %16, %17 offset0:192 offset1:224\n\t"
-      "s_waitcnt lgkmcnt(0)\n\t"
-      "s_barrier" ::"v"(aw),
-      "v"(aw + 2048u), "v"(f2(v[0])), "v"(f2(v[1])), "v"(f2(v[2])), "v"(f2(v[3])), "v"(f2(v[4])),
-      "v"(f2(v[5])), "v"(f2(v[6])), "v"(f2(v[7])), "v"(f2(v[8])), "v"(f2(v[9])), "v"(f2(v[10])),
-      "v"(f2(v[11])), "v"(f2(v[12])), "v"(f2(v[13])), "v"(f2(v[14])), "v"(f2(v[15]))
-      : "memory");
-  // v[e] = X[(t + 16 e) * kStagedCols]: byte offset 4096 e, i.e. 8 e in the
-  // 512-byte units of ds_read2st64_b64, two elements per instruction
-  const unsigned a = (unsigned)(size_t)(lds_ptr)(X + t * kStagedCols);
-  qw_f4 q0, q1, q2, q3, q4, q5, q6, q7;
-  asm volatile(
-      "ds_read2st64_b64 %0, %8 offset0:0 offset1:8\n\t"
-      "ds_read2st64_b64 %1, %8 offset0:16 offset1:24\n\t"
-      "ds_read2st64_b64 %2, %8 offset0:32 offset1:40\n\t"
-      "ds_read2st64_b64 %3, %8 offset0:48 offset1:56\n\t"
-      "ds_read2st64_b64 %4, %8 offset0:64 offset1:72\n\t"
-      "ds_read2st64_b64 %5, %8 offset0:80 offset1:88\n\t"
-      "ds_read2st64_b64 %6, %8 offset0:96 offset1:104\n\t"
-      "ds_read2st64_b64 %7, %8 offset0:112 offset1:120\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(q0), "=&v"(q1), "=&v"(q2), "=&v"(q3), "=&v"(q4), "=&v"(q5), "=&v"(q6), "=&v"(q7)
-      : "v"(a)
-      : "memory");
-  const qw_f4 q[8] = {q0, q1, q2, q3, q4, q5, q6, q7};
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    v[2 * i] = mk(q[i].x, q[i].y);
-    v[2 * i + 1] = mk(q[i].z, q[i].w);
-  }
-  lds_barrier();
-#pragma unroll
-  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
-  dft_reg<16, SIGN>(v);
+template <typename T>
+__device__ __forceinline__ unsigned lds_addr(const T* p) {
+  typedef __attribute__((address_space(3))) const T* lds_ptr;
+  return (unsigned)(size_t)(lds_ptr)p;
 }
 
-// The tile loop of the staged kernels: tiles blockIdx.x * kStagedTiles + k
-// of the nblk (nblk_i per outer index), each transformed and handed to
-// epi(v, tile, first element of the tile) with the thread's 16 values,
-// rows t + 16 e of column p. buf: 2 * 256 * kStagedCols elements of LDS.
-template <int SIGN, typename Epi>
-__device__ __forceinline__ void staged256_loop(cx<float>* __restrict__ buf,
-                                               const cx<float>* __restrict__ in, int64_t I,
-                                               int64_t nblk_i, int64_t nblk, const OuterMap& om,
-                                               const cx<float>* __restrict__ tw, Epi epi) {
-  const int tid = threadIdx.x;
-  const int p = tid & (kStagedCols - 1), t = tid >> 5;
-  cx<float> w[16];
-  w[0] = mk(1.0f, 0.0f);
-#pragma unroll
-  for (int r = 1; r < 16; ++r) w[r] = twiddle<SIGN>(tw, r * t * (TWN / 256));
-  auto tile_base = [&](int64_t blk) -> int64_t {
-    const int64_t o = blk / nblk_i;
-    const int64_t i0 = (blk - o * nblk_i) * kStagedCols;
-    const int64_t comp = o / om.ocount;
-    const int64_t plane = om.o0 + (o - comp * om.ocount);
-    return comp * om.ostride + plane * 256 * I + i0;
-  };
-  const int64_t first = (int64_t)blockIdx.x * kStagedTiles;
-  if (first >= nblk) return;
-  const int n = nblk - first < kStagedTiles ? (int)(nblk - first) : kStagedTiles;
-  int64_t cur = tile_base(first);
-  stage_tile256(buf, in, cur, I, tid);
-  const int s0 = (t >> 1) * 32 + (t & 1);
-  for (int k = 0; k < n; ++k) {
-    cx<float>* X = buf + (k & 1) * (256 * kStagedCols);
-    cx<float>* Y = buf + ((k + 1) & 1) * (256 * kStagedCols);
-    vm_drain();
-    cx<float> v[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = X[(s0 + 2 * e) * kStagedCols + p];
-    // every wave has its rows before the exchange writes X, and the last
-    // reads of Y (the previous tile's exchange and epilogue) are done
-    lds_barrier();
-    int64_t nxt = 0;
-    if (k + 1 < n) {
-      nxt = tile_base(first + k + 1);
-      stage_tile256(Y, in, nxt, I, tid);
-    }
-    fft256_regs<SIGN>(v, X + p, t, w);
-    epi(v, first + k, cur);
-    cur = nxt;
-  }
-}
-
-// NT: non-temporal stores (a template parameter: as a branch inside the
-// loop the two store forms were merged into plain stores).
-template <int SIGN, bool NT>
-__global__ __launch_bounds__(512) void k_fft_strided_staged(cx<float>* __restrict__ out,
-                                                            const cx<float>* __restrict__ in,
-                                                            int64_t I, int64_t nblk_i,
-                                                            int64_t nblk, OuterMap om,
-                                                            const cx<float>* __restrict__ tw) {
-  __shared__ __align__(16) cx<float> buf[2 * 256 * kStagedCols];
-  const int p = threadIdx.x & (kStagedCols - 1), t = threadIdx.x >> 5;
-  staged256_loop<SIGN>(buf, in, I, nblk_i, nblk, om, tw,
-                             [&](const cx<float>(&v)[16], int64_t, int64_t base) {
-                               const int64_t b = base + p;
-#pragma unroll
-                               for (int e = 0; e < 16; ++e) {
-                                 if constexpr (NT)
-                                   store_nt(&out[b + (int64_t)(t + 16 * e) * I], v[e]);
-                                 else
-                                   out[b + (int64_t)(t + 16 * e) * I] = v[e];
-                               }
-                             });
-}
+// The exchanges of the staged transforms are written out with their waits
+// (compiled LDS accesses would also wait for the next tile's loads into the
+// other buffer, which the compiler cannot tell apart from the one being
+// transformed), and their twiddles sit in registers (any global load issued
+// after the next tile's loads would wait for them too).
 
 // y[e] = the 8-byte value at LDS bytes a + 4096 e (e = 0..15), then the
 // workgroup barrier.
@@ -278,49 +147,9 @@ __device__ __forceinline__ void lds_read16_st64(unsigned a, cx<float> (&y)[16]) 
   }
 }
 
-// Length-512 complex64: tiles of 16 columns (128-byte rows) and the
-// register kernel's transform at this length, E = 16 (radix 16, 16, 2).
-// Thread (p, t), p < 16, t < 32, holds rows t + 32 e; wave w holds
-// t = 4w .. 4w+3, and slot (t >> 2) * 64 + 4 e + (t & 3) of the buffer holds
-// row t + 32 e.
-constexpr int kStaged512Cols = 16;
-
-__device__ __forceinline__ void stage_tile512(cx<float>* __restrict__ buf,
-                                              const cx<float>* __restrict__ in, int64_t tile,
-                                              int64_t I, int tid) {
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
-  const int64_t col = 2 * (l & 7);
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    // one instruction: eight 128-byte rows, slots 8j .. 8j+7 of this wave
-    const int q = 8 * j + (l >> 3);
-    const int64_t r = 4 * w + (q & 3) + 32 * (q >> 2);
-    __builtin_amdgcn_global_load_lds(in + tile + r * I + col,
-                                     buf + (w * 64 + 8 * j) * kStaged512Cols, 16, 0, 0);
-  }
-}
-
-// Twiddles of thread t for the last two stages: w2[r] (stage 2, k = t & 15,
-// r = 1..15) and w3[b] (stage 3, k = t + 32 b).
-template <int SIGN>
-struct Tw512F {
-  cx<float> w2[16], w3[8];
-  __device__ __forceinline__ void load(const cx<float>* __restrict__ tw, int t) {
-#pragma unroll
-    for (int r = 1; r < 16; ++r) w2[r] = twiddle<SIGN>(tw, r * (t & 15) * (TWN / 256));
-#pragma unroll
-    for (int b = 0; b < 8; ++b) w3[b] = twiddle<SIGN>(tw, (t + 32 * b) * (TWN / 512));
-  }
-};
-
-// The register kernel's three Stockham stages at L = 512, E = 16, with the
-// twiddles from registers and the exchanges written out. X: byte address
-// in LDS of this thread's column (element (pos, p) at X + 128 pos).
-template <int SIGN>
-__device__ __forceinline__ void fft512_regs(cx<float> (&v)[16], unsigned X, int t,
-                                            const Tw512F<SIGN>& W) {
-  // stage 1 (radix 16, no twiddles): positions 16 t + r, bytes 2048 t + 128 r
-  dft_reg<16, SIGN>(v);
+// The 8-byte values y[r] to LDS bytes a + 128 r (r = 0..15), in the 8-byte
+// units of ds_write2_b64, then the workgroup barrier.
+__device__ __forceinline__ void lds_write16_b64_s128(unsigned a, const cx<float> (&y)[16]) {
   asm volatile(
       "ds_write2_b64 %0, %1, %2 offset0:0 offset1:16\n\t"
       "ds_write2_b64 %0, %3, %4 offset0:32 offset1:48\n\t"
@@ -331,17 +160,35 @@ __device__ __forceinline__ void fft512_regs(cx<float> (&v)[16], unsigned X, int 
       "ds_write2_b64 %0, %13, %14 offset0:192 offset1:208\n\t"
       "ds_write2_b64 %0, %15, %16 offset0:224 offset1:240\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
-      "s_barrier" ::"v"(X + 2048u * t),
-      "v"(f2(v[0])), "v"(f2(v[1])), "v"(f2(v[2])), "v"(f2(v[3])), "v"(f2(v[4])), "v"(f2(v[5])),
-      "v"(f2(v[6])), "v"(f2(v[7])), "v"(f2(v[8])), "v"(f2(v[9])), "v"(f2(v[10])), "v"(f2(v[11])),
-      "v"(f2(v[12])), "v"(f2(v[13])), "v"(f2(v[14])), "v"(f2(v[15]))
+      "s_barrier" ::"v"(a),
+      "v"(f2(y[0])), "v"(f2(y[1])), "v"(f2(y[2])), "v"(f2(y[3])), "v"(f2(y[4])), "v"(f2(y[5])),
+      "v"(f2(y[6])), "v"(f2(y[7])), "v"(f2(y[8])), "v"(f2(y[9])), "v"(f2(y[10])), "v"(f2(y[11])),
+      "v"(f2(y[12])), "v"(f2(y[13])), "v"(f2(y[14])), "v"(f2(y[15]))
       : "memory");
-  lds_read16_st64(X + 128u * t, v);
-  // stage 2 (radix 16): positions (t >> 4) 256 + (t & 15) + 16 r, bytes
-  // 128 ((t >> 4) 256 + (t & 15)) + 2048 r
-#pragma unroll
-  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], W.w2[r]);
-  dft_reg<16, SIGN>(v);
+}
+
+// The same at a + 256 r (r < 8) and a + 2048 + 256 (r - 8).
+__device__ __forceinline__ void lds_write16_b64_s256(unsigned a, const cx<float> (&y)[16]) {
+  asm volatile(
+      "ds_write2_b64 %0, %2, %3 offset0:0 offset1:32\n\t"
+      "ds_write2_b64 %0, %4, %5 offset0:64 offset1:96\n\t"
+      "ds_write2_b64 %0, %6, %7 offset0:128 offset1:160\n\t"
+      "ds_write2_b64 %0, %8, %9 offset0:192 offset1:224\n\t"
+      "ds_write2_b64 %1, %10, %11 offset0:0 offset1:32\n\t"
+      "ds_write2_b64 %1, %12, %13 offset0:64 offset1:96\n\t"
+      "ds_write2_b64 %1, %14, %15 offset0:128 offset1:160\n\t"
+      "ds_write2_b64 %1, %16, %17 offset0:192 offset1:224\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "s_barrier" ::"v"(a),
+      "v"(a + 2048u), "v"(f2(y[0])), "v"(f2(y[1])), "v"(f2(y[2])), "v"(f2(y[3])), "v"(f2(y[4])),
+      "v"(f2(y[5])), "v"(f2(y[6])), "v"(f2(y[7])), "v"(f2(y[8])), "v"(f2(y[9])), "v"(f2(y[10])),
+      "v"(f2(y[11])), "v"(f2(y[12])), "v"(f2(y[13])), "v"(f2(y[14])), "v"(f2(y[15]))
+      : "memory");
+}
+
+// The same at a + 2048 r (r = 0..15), in the 512-byte units of
+// ds_write2st64_b64.
+__device__ __forceinline__ void lds_write16_st64_s2048(unsigned a, const cx<float> (&y)[16]) {
   asm volatile(
       "ds_write2st64_b64 %0, %1, %2 offset0:0 offset1:4\n\t"
       "ds_write2st64_b64 %0, %3, %4 offset0:8 offset1:12\n\t"
@@ -352,99 +199,14 @@ __device__ __forceinline__ void fft512_regs(cx<float> (&v)[16], unsigned X, int 
       "ds_write2st64_b64 %0, %13, %14 offset0:48 offset1:52\n\t"
       "ds_write2st64_b64 %0, %15, %16 offset0:56 offset1:60\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
-      "s_barrier" ::"v"(X + 128u * ((t >> 4) * 256 + (t & 15))),
-      "v"(f2(v[0])), "v"(f2(v[1])), "v"(f2(v[2])), "v"(f2(v[3])), "v"(f2(v[4])), "v"(f2(v[5])),
-      "v"(f2(v[6])), "v"(f2(v[7])), "v"(f2(v[8])), "v"(f2(v[9])), "v"(f2(v[10])), "v"(f2(v[11])),
-      "v"(f2(v[12])), "v"(f2(v[13])), "v"(f2(v[14])), "v"(f2(v[15]))
+      "s_barrier" ::"v"(a),
+      "v"(f2(y[0])), "v"(f2(y[1])), "v"(f2(y[2])), "v"(f2(y[3])), "v"(f2(y[4])), "v"(f2(y[5])),
+      "v"(f2(y[6])), "v"(f2(y[7])), "v"(f2(y[8])), "v"(f2(y[9])), "v"(f2(y[10])), "v"(f2(y[11])),
+      "v"(f2(y[12])), "v"(f2(y[13])), "v"(f2(y[14])), "v"(f2(y[15]))
       : "memory");
-  lds_read16_st64(X + 128u * t, v);
-  // stage 3 (radix 2, eight butterflies per thread): in place in v
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    cx<float> a[2] = {v[b], cmul(v[b + 8], W.w3[b])};
-    dft_reg<2, SIGN>(a);
-    v[b] = a[0];
-    v[b + 8] = a[1];
-  }
 }
 
-template <int SIGN, bool NT>
-__global__ __launch_bounds__(512) void k_fft_strided_staged512(cx<float>* __restrict__ out,
-                                                               const cx<float>* __restrict__ in,
-                                                               int64_t I, int64_t nblk_i,
-                                                               int64_t nblk, OuterMap om,
-                                                               const cx<float>* __restrict__ tw) {
-  __shared__ __align__(16) cx<float> buf[2 * 512 * kStaged512Cols];
-  const int tid = threadIdx.x;
-  const int p = tid & (kStaged512Cols - 1), t = tid >> 4;
-  Tw512F<SIGN> W;
-  W.load(tw, t);
-  auto tile_base = [&](int64_t blk) -> int64_t {
-    const int64_t o = blk / nblk_i;
-    const int64_t i0 = (blk - o * nblk_i) * kStaged512Cols;
-    const int64_t comp = o / om.ocount;
-    const int64_t plane = om.o0 + (o - comp * om.ocount);
-    return comp * om.ostride + plane * 512 * I + i0;
-  };
-  const int64_t first = (int64_t)blockIdx.x * kStagedTiles;
-  if (first >= nblk) return;
-  const int n = nblk - first < kStagedTiles ? (int)(nblk - first) : kStagedTiles;
-  int64_t cur = tile_base(first);
-  stage_tile512(buf, in, cur, I, tid);
-  typedef __attribute__((address_space(3))) cx<float>* lds_ptr;
-  const int s0 = (t >> 2) * 64 + (t & 3);
-  for (int k = 0; k < n; ++k) {
-    cx<float>* X = buf + (k & 1) * (512 * kStaged512Cols);
-    cx<float>* Y = buf + ((k + 1) & 1) * (512 * kStaged512Cols);
-    vm_drain();
-    cx<float> v[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = X[(s0 + 4 * e) * kStaged512Cols + p];
-    // every wave has its rows before the exchange writes X, and the last
-    // reads of Y (the previous tile's exchange) are done
-    lds_barrier();
-    int64_t nxt = 0;
-    if (k + 1 < n) {
-      nxt = tile_base(first + k + 1);
-      stage_tile512(Y, in, nxt, I, tid);
-    }
-    fft512_regs<SIGN>(v, (unsigned)(size_t)(lds_ptr)(X + p), t, W);
-    const int64_t b = cur + p;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      if constexpr (NT)
-        store_nt(&out[b + (int64_t)(t + 32 * e) * I], v[e]);
-      else
-        out[b + (int64_t)(t + 32 * e) * I] = v[e];
-    }
-    cur = nxt;
-  }
-}
-
-// The complex128 form: tiles of 16 columns (256-byte rows) and the register
-// kernel's transform at this length, E = 8 (radix 8, 8, 4). Thread (p, t),
-// p < 16, t < 32, holds rows t + 32 e; wave w holds t = 4w .. 4w+3, and slot
-// (t >> 2) * 32 + 4 e + (t & 3) of the buffer holds row t + 32 e.
-constexpr int kStagedColsD = 16;
-
-__device__ __forceinline__ void stage_tile256_c128(cx<double>* __restrict__ buf,
-                                                   const cx<double>* __restrict__ in,
-                                                   int64_t tile, int64_t I, int tid) {
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    // one instruction: four 256-byte rows, slots 4j .. 4j+3 of this wave
-    const int64_t r = 4 * w + (l >> 4) + 32 * j;
-    __builtin_amdgcn_global_load_lds(in + tile + r * I + (l & 15),
-                                     buf + (w * 32 + 4 * j) * kStagedColsD, 16, 0, 0);
-  }
-}
-
-typedef double qw_d2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ qw_d2 d2(cx<double> z) { return qw_d2{z.x, z.y}; }
-
-// Eight 16-byte values to LDS bytes a + OFF * k (k = 0..7), then the
+// Eight 16-byte values to LDS bytes a + OFF k (k = 0..7), then the
 // workgroup barrier.
 template <int OFF>
 __device__ __forceinline__ void lds_write8_b128(unsigned a, const cx<double> (&y)[8]) {
@@ -488,309 +250,306 @@ __device__ __forceinline__ void lds_read8_b128(unsigned a, cx<double> (&y)[8]) {
   for (int k = 0; k < 8; ++k) y[k] = mk(q[k].x, q[k].y);
 }
 
-// Twiddles of thread t for the last two stages: w2[r] (stage 2, k = t & 7,
-// r = 1..7) and w3[b][r] (stage 3, k = t + 32 b, r = 1..3).
-template <int SIGN>
-struct Tw256D {
-  cx<double> w2[8], w3[2][4];
-  __device__ __forceinline__ void load(const cx<double>* __restrict__ tw, int t) {
+// The staged shapes: each gives COLS and E (the register kernel's), whether
+// its workgroups go in XCD order (as the register kernel's at complex128,
+// where the staged n1 inverse pass gained nothing without it at 256^3 and
+// lost at 512^3 with it), its twiddles and its transform. fft(v, X, t, W):
+// the register kernel's Stockham stages for thread t's values v, with the
+// element at (position pos, this thread's column) at LDS bytes
+// X + pos * COLS * sizeof(cx<T>).
+template <typename T, int L>
+struct Staged;
+
+// Length 256, complex64: radix 16, 16.
+template <>
+struct Staged<float, 256> {
+  static constexpr int COLS = 32, E = 16;
+  static constexpr bool XCD = false;
+  template <int SIGN>
+  struct Tw {
+    cx<float> w[16];
+    __device__ __forceinline__ void load(const cx<float>* __restrict__ tw, int t) {
 #pragma unroll
-    for (int r = 1; r < 8; ++r) w2[r] = twiddle<SIGN>(tw, r * (t & 7) * (TWN / 64));
+      for (int r = 1; r < 16; ++r) w[r] = twiddle<SIGN>(tw, r * t * (TWN / 256));
+    }
+  };
+  template <int SIGN>
+  __device__ __forceinline__ static void fft(cx<float> (&v)[16], unsigned X, int t,
+                                             const Tw<SIGN>& W) {
+    dft_reg<16, SIGN>(v);
+    lds_write16_b64_s256(X + 4096u * t, v);  // positions 16 t + r
+    lds_read16_st64(X + 256u * t, v);        // positions t + 16 e
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 1; r < 4; ++r) w3[b][r] = twiddle<SIGN>(tw, r * ((t + 32 * b) & 63) * (TWN / 256));
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], W.w[r]);
+    dft_reg<16, SIGN>(v);
   }
 };
 
-// The register kernel's three Stockham stages at L = 256, E = 8, with the
-// twiddles from registers and the exchanges written out. X: byte address
-// in LDS of this thread's column (element (pos, p) at X + 256 pos).
-template <int SIGN>
-__device__ __forceinline__ void fft256_c128(cx<double> (&v)[8], unsigned X, int t,
-                                            const Tw256D<SIGN>& W) {
-  // stage 1 (radix 8, no twiddles): positions 8t + r
-  dft_reg<8, SIGN>(v);
-  lds_write8_b128<256>(X + 2048u * t, v);
-  lds_read8_b128(X + 256u * t, v);
-  // stage 2 (radix 8): positions (t >> 3) 64 + (t & 7) + 8 r
+// Length 512, complex64: radix 16, 16, 2.
+template <>
+struct Staged<float, 512> {
+  static constexpr int COLS = 16, E = 16;
+  static constexpr bool XCD = false;
+  template <int SIGN>
+  struct Tw {
+    cx<float> w2[16], w3[8];  // stage 2 (k = t & 15), stage 3 (k = t + 32 b)
+    __device__ __forceinline__ void load(const cx<float>* __restrict__ tw, int t) {
 #pragma unroll
-  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], W.w2[r]);
-  dft_reg<8, SIGN>(v);
-  lds_write8_b128<2048>(X + 256u * ((t >> 3) * 64 + (t & 7)), v);
-  lds_read8_b128(X + 256u * t, v);
-  // stage 3 (radix 4, two butterflies per thread): in place in v
+      for (int r = 1; r < 16; ++r) w2[r] = twiddle<SIGN>(tw, r * (t & 15) * (TWN / 256));
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    cx<double> a[4];
+      for (int b = 0; b < 8; ++b) w3[b] = twiddle<SIGN>(tw, (t + 32 * b) * (TWN / 512));
+    }
+  };
+  template <int SIGN>
+  __device__ __forceinline__ static void fft(cx<float> (&v)[16], unsigned X, int t,
+                                             const Tw<SIGN>& W) {
+    dft_reg<16, SIGN>(v);
+    lds_write16_b64_s128(X + 2048u * t, v);  // positions 16 t + r
+    lds_read16_st64(X + 128u * t, v);        // positions t + 32 e
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a[r] = v[b + 2 * r];
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], W.w2[r]);
+    dft_reg<16, SIGN>(v);
+    // positions (t >> 4) 256 + (t & 15) + 16 r
+    lds_write16_st64_s2048(X + 128u * ((t >> 4) * 256 + (t & 15)), v);
+    lds_read16_st64(X + 128u * t, v);
 #pragma unroll
-    for (int r = 1; r < 4; ++r) a[r] = cmul(a[r], W.w3[b][r]);
-    dft_reg<4, SIGN>(a);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[b + 2 * r] = a[r];
+    for (int b = 0; b < 8; ++b) {
+      cx<float> a[2] = {v[b], cmul(v[b + 8], W.w3[b])};
+      dft_reg<2, SIGN>(a);
+      v[b] = a[0];
+      v[b + 8] = a[1];
+    }
   }
-}
+};
 
-// The tile loop of the complex128 staged kernels (as staged256_loop):
-// epi(v, tile, first element of the tile) with the thread's 8 values, rows
-// t + 32 e of column p.
-template <int SIGN, typename Epi>
-__device__ __forceinline__ void staged256_loop_c128(cx<double>* __restrict__ buf,
-                                                    const cx<double>* __restrict__ in, int64_t I,
-                                                    int64_t nblk_i, int64_t nblk,
-                                                    const OuterMap& om,
-                                                    const cx<double>* __restrict__ tw, Epi epi) {
+// Length 256, complex128: radix 8, 8, 4.
+template <>
+struct Staged<double, 256> {
+  static constexpr int COLS = 16, E = 8;
+  static constexpr bool XCD = true;
+  template <int SIGN>
+  struct Tw {
+    cx<double> w2[8], w3[2][4];  // stage 2 (k = t & 7), stage 3 (k = t + 32 b)
+    __device__ __forceinline__ void load(const cx<double>* __restrict__ tw, int t) {
+#pragma unroll
+      for (int r = 1; r < 8; ++r) w2[r] = twiddle<SIGN>(tw, r * (t & 7) * (TWN / 64));
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 1; r < 4; ++r)
+          w3[b][r] = twiddle<SIGN>(tw, r * ((t + 32 * b) & 63) * (TWN / 256));
+    }
+  };
+  template <int SIGN>
+  __device__ __forceinline__ static void fft(cx<double> (&v)[8], unsigned X, int t,
+                                             const Tw<SIGN>& W) {
+    dft_reg<8, SIGN>(v);
+    lds_write8_b128<256>(X + 2048u * t, v);  // positions 8 t + r
+    lds_read8_b128(X + 256u * t, v);         // positions t + 32 e
+#pragma unroll
+    for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], W.w2[r]);
+    dft_reg<8, SIGN>(v);
+    // positions (t >> 3) 64 + (t & 7) + 8 r
+    lds_write8_b128<2048>(X + 256u * ((t >> 3) * 64 + (t & 7)), v);
+    lds_read8_b128(X + 256u * t, v);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cx<double> a[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = v[b + 2 * r];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) a[r] = cmul(a[r], W.w3[b][r]);
+      dft_reg<4, SIGN>(a);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[b + 2 * r] = a[r];
+    }
+  }
+};
+
+// Length 512, complex128: radix 8, 8, 8.
+template <>
+struct Staged<double, 512> {
+  static constexpr int COLS = 8, E = 8;
+  static constexpr bool XCD = false;
+  template <int SIGN>
+  struct Tw {
+    cx<double> w2[8], w3[8];  // stage 2 (k = t & 7), stage 3 (k = t)
+    __device__ __forceinline__ void load(const cx<double>* __restrict__ tw, int t) {
+#pragma unroll
+      for (int r = 1; r < 8; ++r) {
+        w2[r] = twiddle<SIGN>(tw, r * (t & 7) * (TWN / 64));
+        w3[r] = twiddle<SIGN>(tw, r * t * (TWN / 512));
+      }
+    }
+  };
+  template <int SIGN>
+  __device__ __forceinline__ static void fft(cx<double> (&v)[8], unsigned X, int t,
+                                             const Tw<SIGN>& W) {
+    dft_reg<8, SIGN>(v);
+    lds_write8_b128<128>(X + 1024u * t, v);  // positions 8 t + r
+    lds_read8_b128(X + 128u * t, v);         // positions t + 64 e
+#pragma unroll
+    for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], W.w2[r]);
+    dft_reg<8, SIGN>(v);
+    // positions (t >> 3) 64 + (t & 7) + 8 r
+    lds_write8_b128<1024>(X + 128u * ((t >> 3) * 64 + (t & 7)), v);
+    lds_read8_b128(X + 128u * t, v);
+#pragma unroll
+    for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], W.w3[r]);
+    dft_reg<8, SIGN>(v);
+  }
+};
+
+// One tile (L rows of COLS columns from `tile`, row stride I) into buf:
+// each instruction loads RPI whole rows, slots RPI j .. RPI j + RPI - 1 of
+// this wave.
+template <typename T, int L>
+struct StagedTile {
+  __device__ __forceinline__ static void load(cx<T>* __restrict__ buf,
+                                              const cx<T>* __restrict__ in, int64_t tile,
+                                              int64_t I, int tid) {
+    using S = Staged<T, L>;
+    constexpr int TT = L / S::E, TPW = 64 / S::COLS, RPW = TPW * S::E;
+    constexpr int EPL = 16 / (int)sizeof(cx<T>);  // elements per lane
+    constexpr int LPR = S::COLS / EPL;             // lanes per row
+    constexpr int RPI = 64 / LPR;                  // rows per instruction
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+#pragma unroll
+    for (int j = 0; j < RPW / RPI; ++j) {
+      const int q = RPI * j + l / LPR;
+      const int64_t r = TPW * w + q % TPW + TT * (q / TPW);
+      __builtin_amdgcn_global_load_lds(in + tile + r * I + EPL * (l % LPR),
+                                       buf + (w * RPW + RPI * j) * S::COLS, 16, 0, 0);
+    }
+  }
+};
+
+// The tile loop: tiles blockIdx.x * kStagedTiles + k (workgroups in XCD
+// order where the shape says so) of the nblk (nblk_i per outer index), each
+// transformed and handed to epi(v, tile, first element of the tile) with the
+// thread's E values, rows t + TT e of column p. buf: 2 L COLS elements of
+// LDS.
+template <typename T, int L, int SIGN, typename Epi>
+__device__ __forceinline__ void staged_loop(cx<T>* __restrict__ buf,
+                                            const cx<T>* __restrict__ in, int64_t I,
+                                            int64_t nblk_i, int64_t nblk, const OuterMap& om,
+                                            const cx<T>* __restrict__ tw, Epi epi) {
+  using S = Staged<T, L>;
+  constexpr int COLS = S::COLS, E = S::E, TPW = 64 / COLS, RPW = TPW * E;
   const int tid = threadIdx.x;
-  const int p = tid & (kStagedColsD - 1), t = tid >> 4;
-  Tw256D<SIGN> W;
+  const int p = tid % COLS, t = tid / COLS;
+  typename S::template Tw<SIGN> W;
   W.load(tw, t);
   auto tile_base = [&](int64_t blk) -> int64_t {
     const int64_t o = blk / nblk_i;
-    const int64_t i0 = (blk - o * nblk_i) * kStagedColsD;
+    const int64_t i0 = (blk - o * nblk_i) * COLS;
     const int64_t comp = o / om.ocount;
     const int64_t plane = om.o0 + (o - comp * om.ocount);
-    return comp * om.ostride + plane * 256 * I + i0;
+    return comp * om.ostride + plane * L * I + i0;
   };
-  // in XCD order, as the register kernel at complex128 (without it the
-  // staged n1 inverse pass measured no faster than the register one)
-  const int64_t wg = xcd_order(blockIdx.x, gridDim.x, true);
-  const int64_t first = wg * kStagedTiles;
+  const int64_t first = xcd_order(blockIdx.x, gridDim.x, S::XCD) * kStagedTiles;
   if (first >= nblk) return;
   const int n = nblk - first < kStagedTiles ? (int)(nblk - first) : kStagedTiles;
   int64_t cur = tile_base(first);
-  stage_tile256_c128(buf, in, cur, I, tid);
-  typedef __attribute__((address_space(3))) cx<double>* lds_ptr;
-  const int s0 = (t >> 2) * 32 + (t & 3);
+  StagedTile<T, L>::load(buf, in, cur, I, tid);
+  const int s0 = (t / TPW) * RPW + t % TPW;
   for (int k = 0; k < n; ++k) {
-    cx<double>* X = buf + (k & 1) * (256 * kStagedColsD);
-    cx<double>* Y = buf + ((k + 1) & 1) * (256 * kStagedColsD);
+    cx<T>* X = buf + (k & 1) * (L * COLS);
+    cx<T>* Y = buf + ((k + 1) & 1) * (L * COLS);
     vm_drain();
-    cx<double> v[8];
+    cx<T> v[E];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = X[(s0 + 4 * e) * kStagedColsD + p];
+    for (int e = 0; e < E; ++e) v[e] = X[(s0 + TPW * e) * COLS + p];
     // every wave has its rows before the exchange writes X, and the last
     // reads of Y (the previous tile's exchange and epilogue) are done
     lds_barrier();
     int64_t nxt = 0;
     if (k + 1 < n) {
       nxt = tile_base(first + k + 1);
-      stage_tile256_c128(Y, in, nxt, I, tid);
+      StagedTile<T, L>::load(Y, in, nxt, I, tid);
     }
-    fft256_c128<SIGN>(v, (unsigned)(size_t)(lds_ptr)(X + p), t, W);
+    S::template fft<SIGN>(v, lds_addr(X + p), t, W);
     epi(v, first + k, cur);
     cur = nxt;
   }
 }
 
-template <int SIGN, bool NT>
-__global__ __launch_bounds__(512) void k_fft_strided_staged_c128(cx<double>* __restrict__ out,
-                                                                 const cx<double>* __restrict__ in,
-                                                                 int64_t I, int64_t nblk_i,
-                                                                 int64_t nblk, OuterMap om,
-                                                                 const cx<double>* __restrict__ tw) {
-  __shared__ __align__(16) cx<double> buf[2 * 256 * kStagedColsD];
-  const int p = threadIdx.x & (kStagedColsD - 1), t = threadIdx.x >> 4;
-  staged256_loop_c128<SIGN>(buf, in, I, nblk_i, nblk, om, tw,
-                            [&](const cx<double>(&v)[8], int64_t, int64_t base) {
-                              const int64_t b = base + p;
+// NT: non-temporal stores (a template parameter: as a branch inside the
+// loop the two store forms were merged into plain stores).
+template <typename T, int L, int SIGN, bool NT>
+__global__ __launch_bounds__(512) void k_fft_strided_staged(cx<T>* __restrict__ out,
+                                                            const cx<T>* __restrict__ in,
+                                                            int64_t I, int64_t nblk_i,
+                                                            int64_t nblk, OuterMap om,
+                                                            const cx<T>* __restrict__ tw) {
+  using S = Staged<T, L>;
+  constexpr int COLS = S::COLS, E = S::E, TT = L / E;
+  __shared__ __align__(16) cx<T> buf[2 * L * COLS];
+  const int p = threadIdx.x % COLS, t = threadIdx.x / COLS;
+  staged_loop<T, L, SIGN>(buf, in, I, nblk_i, nblk, om, tw,
+                          [&](const cx<T>(&v)[E], int64_t, int64_t base) {
+                            const int64_t b = base + p;
 #pragma unroll
-                              for (int e = 0; e < 8; ++e) {
-                                if constexpr (NT)
-                                  store_nt(&out[b + (int64_t)(t + 32 * e) * I], v[e]);
-                                else
-                                  out[b + (int64_t)(t + 32 * e) * I] = v[e];
-                              }
-                            });
-}
-
-// Length 512 at complex128: tiles of 8 columns (128-byte rows) and the
-// register kernel's transform there, E = 8 (radix 8, 8, 8). Thread (p, t),
-// p < 8, t < 64, holds rows t + 64 e; wave w holds t = 8w .. 8w+7, and slot
-// (t >> 3) * 64 + 8 e + (t & 7) of the buffer holds row t + 64 e.
-constexpr int kStaged512ColsD = 8;
-
-__device__ __forceinline__ void stage_tile512_c128(cx<double>* __restrict__ buf,
-                                                   const cx<double>* __restrict__ in,
-                                                   int64_t tile, int64_t I, int tid) {
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    // one instruction: eight 128-byte rows, slots 8j .. 8j+7 of this wave
-    const int64_t r = 8 * w + (l >> 3) + 64 * j;
-    __builtin_amdgcn_global_load_lds(in + tile + r * I + (l & 7),
-                                     buf + (w * 64 + 8 * j) * kStaged512ColsD, 16, 0, 0);
-  }
-}
-
-// y[k] = the 16-byte value at LDS bytes a + 8192 k (k = 0..7), then the
-// workgroup barrier (lds_read8_b128); and the twiddles of thread t for the
-// last two stages: w2[r] (stage 2, k = t & 7) and w3[r] (stage 3, k = t).
-template <int SIGN>
-struct Tw512D {
-  cx<double> w2[8], w3[8];
-  __device__ __forceinline__ void load(const cx<double>* __restrict__ tw, int t) {
-#pragma unroll
-    for (int r = 1; r < 8; ++r) {
-      w2[r] = twiddle<SIGN>(tw, r * (t & 7) * (TWN / 64));
-      w3[r] = twiddle<SIGN>(tw, r * t * (TWN / 512));
-    }
-  }
-};
-
-// The register kernel's three Stockham stages at L = 512, E = 8. X: byte
-// address in LDS of this thread's column (element (pos, p) at X + 128 pos).
-template <int SIGN>
-__device__ __forceinline__ void fft512_c128(cx<double> (&v)[8], unsigned X, int t,
-                                            const Tw512D<SIGN>& W) {
-  // stage 1 (radix 8, no twiddles): positions 8t + r
-  dft_reg<8, SIGN>(v);
-  lds_write8_b128<128>(X + 1024u * t, v);
-  lds_read8_b128(X + 128u * t, v);
-  // stage 2 (radix 8): positions (t >> 3) 64 + (t & 7) + 8 r
-#pragma unroll
-  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], W.w2[r]);
-  dft_reg<8, SIGN>(v);
-  lds_write8_b128<1024>(X + 128u * ((t >> 3) * 64 + (t & 7)), v);
-  lds_read8_b128(X + 128u * t, v);
-  // stage 3 (radix 8, the last): in place in v
-#pragma unroll
-  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], W.w3[r]);
-  dft_reg<8, SIGN>(v);
-}
-
-template <int SIGN, bool NT>
-__global__ __launch_bounds__(512) void k_fft_strided_staged512_c128(
-    cx<double>* __restrict__ out, const cx<double>* __restrict__ in, int64_t I, int64_t nblk_i,
-    int64_t nblk, OuterMap om, const cx<double>* __restrict__ tw) {
-  __shared__ __align__(16) cx<double> buf[2 * 512 * kStaged512ColsD];
-  const int tid = threadIdx.x;
-  const int p = tid & (kStaged512ColsD - 1), t = tid >> 3;
-  Tw512D<SIGN> W;
-  W.load(tw, t);
-  auto tile_base = [&](int64_t blk) -> int64_t {
-    const int64_t o = blk / nblk_i;
-    const int64_t i0 = (blk - o * nblk_i) * kStaged512ColsD;
-    const int64_t comp = o / om.ocount;
-    const int64_t plane = om.o0 + (o - comp * om.ocount);
-    return comp * om.ostride + plane * 512 * I + i0;
-  };
-  const int64_t first = (int64_t)blockIdx.x * kStagedTiles;
-  if (first >= nblk) return;
-  const int n = nblk - first < kStagedTiles ? (int)(nblk - first) : kStagedTiles;
-  int64_t cur = tile_base(first);
-  stage_tile512_c128(buf, in, cur, I, tid);
-  typedef __attribute__((address_space(3))) cx<double>* lds_ptr;
-  const int s0 = (t >> 3) * 64 + (t & 7);
-  for (int k = 0; k < n; ++k) {
-    cx<double>* X = buf + (k & 1) * (512 * kStaged512ColsD);
-    cx<double>* Y = buf + ((k + 1) & 1) * (512 * kStaged512ColsD);
-    vm_drain();
-    cx<double> v[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = X[(s0 + 8 * e) * kStaged512ColsD + p];
-    lds_barrier();
-    int64_t nxt = 0;
-    if (k + 1 < n) {
-      nxt = tile_base(first + k + 1);
-      stage_tile512_c128(Y, in, nxt, I, tid);
-    }
-    fft512_c128<SIGN>(v, (unsigned)(size_t)(lds_ptr)(X + p), t, W);
-    const int64_t b = cur + p;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if constexpr (NT)
-        store_nt(&out[b + (int64_t)(t + 64 * e) * I], v[e]);
-      else
-        out[b + (int64_t)(t + 64 * e) * I] = v[e];
-    }
-    cur = nxt;
-  }
+                            for (int e = 0; e < E; ++e) {
+                              if constexpr (NT)
+                                store_nt(&out[b + (int64_t)(t + TT * e) * I], v[e]);
+                              else
+                                out[b + (int64_t)(t + TT * e) * I] = v[e];
+                            }
+                          });
 }
 
 // The staged kernels take a pass when they apply, unless switched off
-// (qw_set_fft_kernel): whole tiles, at least kStagedMinTiles of them, and
-// * length 512, complex64: both directions. At 512^3 the n1 forward pass
+// (qw_set_fft_kernel): lengths 256 and 512, whole tiles, at least
+// kStagedMinTiles of them, and
+// * complex64, length 256: the inverse direction. The forward passes
+//   measured slower staged (0.246 and 0.210 ms against 0.226 and 0.190 at
+//   256^3; in XCD order 0.240 and 0.183, but the fused pass after them then
+//   took 0.245 against 0.238 ms), where the inverse ones went 0.187 -> 0.174
+//   ms and 0.213 -> 0.197 ms (in XCD order 0.190 and 0.195).
+// * complex64, length 512: both directions. At 512^3 the n1 forward pass
 //   2.82 -> 2.17 ms, n2 forward 1.77 -> 1.63, n2 inverse 1.83 -> 1.61, n1
 //   inverse 2.37 -> 2.08 (the jump 10.8 -> 9.5 ms); in XCD order slightly
 //   slower (9.66 ms).
-// * length 512, complex128: rows at least 4096 elements apart, both
-//   directions: at 512^3 the n1 passes 4.83 -> 4.32 ms and 4.64 -> 4.32 ms,
-//   where the n2 passes (8 KB apart) measured slower (3.05 -> 3.37 ms); in
-//   XCD order the n1 passes 4.44 and 4.42 ms.
-// Length 256:
-// * complex64: the inverse direction. The forward passes measured slower
-//   staged (0.246 and 0.210 ms against 0.226 and 0.190 at 256^3; in XCD
-//   order 0.240 and 0.183, but the fused pass after them then took 0.245
-//   against 0.238 ms), where the inverse ones went 0.187 -> 0.174 ms and
-//   0.213 -> 0.197 ms (in XCD order 0.190 and 0.195).
-// * complex128: rows at least 4096 elements (64 KB) apart, both
-//   directions: at 256^3 the n1 passes 0.490 -> 0.451 ms and 0.456 ->
-//   0.418 ms, where the n2 passes (4 KB apart) measured slower (0.382 ->
-//   0.394 and 0.384 -> 0.392 ms); the jump 2.26 -> 2.19 ms.
+// * complex128: rows at least 4096 elements apart, both directions. At
+//   256^3 the n1 passes 0.490 -> 0.451 ms and 0.456 -> 0.418 ms (the jump
+//   2.26 -> 2.19 ms), where the n2 passes (4 KB apart) measured slower
+//   (0.382 -> 0.394 and 0.384 -> 0.392 ms); at 512^3 the n1 passes 4.83 ->
+//   4.32 and 4.64 -> 4.32 ms (in XCD order 4.44 and 4.42), where the n2
+//   passes (8 KB apart) measured slower (3.05 -> 3.37 ms).
 static std::atomic<bool> g_staged{true};
 
 void set_fft_staged(bool on) { g_staged.store(on, std::memory_order_relaxed); }
 
-static bool use_staged512(bool dbl, int64_t L, int64_t O, int64_t I) {
-  if (!g_staged.load(std::memory_order_relaxed) || L != 512) return false;
-  const int cols = dbl ? kStaged512ColsD : kStaged512Cols;
-  if (I % cols != 0 || O * (I / cols) < kStagedMinTiles) return false;
-  return !dbl || I >= 4096;
-}
-
-static hipError_t run_staged512_c128(cx<double>* out, const cx<double>* in, int64_t O, int64_t I,
-                                     const OuterMap& om, const cx<double>* tw, hipStream_t st,
-                                     int sign) {
-  const int64_t nblk_i = I / kStaged512ColsD;
-  const int64_t nblk = O * nblk_i;
-  const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
-  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
-  auto kern = sign > 0 ? (om.nt ? k_fft_strided_staged512_c128<1, true> : k_fft_strided_staged512_c128<1, false>)
-                       : (om.nt ? k_fft_strided_staged512_c128<-1, true> : k_fft_strided_staged512_c128<-1, false>);
-  hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
-  return hipGetLastError();
-}
-
-static hipError_t run_staged512(cx<float>* out, const cx<float>* in, int64_t O, int64_t I,
-                                const OuterMap& om, const cx<float>* tw, hipStream_t st,
-                                int sign) {
-  const int64_t nblk_i = I / kStaged512Cols;
-  const int64_t nblk = O * nblk_i;
-  const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
-  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
-  auto kern = sign > 0 ? (om.nt ? k_fft_strided_staged512<1, true> : k_fft_strided_staged512<1, false>)
-                       : (om.nt ? k_fft_strided_staged512<-1, true> : k_fft_strided_staged512<-1, false>);
-  hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
-  return hipGetLastError();
-}
-
 static bool use_staged(bool dbl, int sign, int64_t L, int64_t O, int64_t I) {
-  if (!g_staged.load(std::memory_order_relaxed) || L != 256) return false;
-  const int cols = dbl ? kStagedColsD : kStagedCols;
+  if (!g_staged.load(std::memory_order_relaxed) || (L != 256 && L != 512)) return false;
+  const int cols = dbl ? (L == 256 ? Staged<double, 256>::COLS : Staged<double, 512>::COLS)
+                       : (L == 256 ? Staged<float, 256>::COLS : Staged<float, 512>::COLS);
   if (I % cols != 0 || O * (I / cols) < kStagedMinTiles) return false;
-  return dbl ? I >= 4096 : sign < 0;
+  if (dbl) return I >= 4096;
+  return L == 512 || sign < 0;
+}
+
+template <typename T, int L>
+static hipError_t run_staged(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
+                             const OuterMap& om, const cx<T>* tw, hipStream_t st, int sign) {
+  const int64_t nblk_i = I / Staged<T, L>::COLS;
+  const int64_t nblk = O * nblk_i;
+  const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
+  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
+  auto kern = sign > 0 ? (om.nt ? k_fft_strided_staged<T, L, 1, true>
+                                : k_fft_strided_staged<T, L, 1, false>)
+                       : (om.nt ? k_fft_strided_staged<T, L, -1, true>
+                                : k_fft_strided_staged<T, L, -1, false>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
+  return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t run_staged(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
-                             const OuterMap& om, const cx<T>* tw, hipStream_t st, int sign) {
-  constexpr int cols = sizeof(T) == 8 ? kStagedColsD : kStagedCols;
-  const int64_t nblk_i = I / cols;
-  const int64_t nblk = O * nblk_i;
-  const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
-  if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
-  if constexpr (sizeof(T) == 8) {
-    auto kern = sign > 0 ? (om.nt ? k_fft_strided_staged_c128<1, true> : k_fft_strided_staged_c128<1, false>)
-                         : (om.nt ? k_fft_strided_staged_c128<-1, true> : k_fft_strided_staged_c128<-1, false>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
-  } else {
-    if (sign > 0) return hipErrorInvalidValue;  // not instantiated: see use_staged
-    auto kern = om.nt ? k_fft_strided_staged<-1, true> : k_fft_strided_staged<-1, false>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
-  }
-  return hipGetLastError();
+static hipError_t dispatch_staged(int64_t L, cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
+                                  const OuterMap& om, const cx<T>* tw, hipStream_t st, int sign) {
+  return L == 256 ? run_staged<T, 256>(out, in, O, I, om, tw, st, sign)
+                  : run_staged<T, 512>(out, in, O, I, om, tw, st, sign);
 }
 
 // Columns per workgroup of a strided pass: 256 bytes of each row (32
@@ -878,16 +637,11 @@ hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, con
                                    int64_t I, const void* tw, hipStream_t st, bool nt) {
   const OuterMap om{ocount, o0, ostride, nt ? 1 : 0};
   const int64_t O = ncomp * ocount;
-  if (use_staged512(dbl, L, O, I))
-    return dbl ? run_staged512_c128((cx<double>*)out, (const cx<double>*)in, O, I, om,
-                                    (const cx<double>*)tw, st, sign)
-               : run_staged512((cx<float>*)out, (const cx<float>*)in, O, I, om,
-                               (const cx<float>*)tw, st, sign);
   if (use_staged(dbl, sign, L, O, I))
-    return dbl ? run_staged<double>((cx<double>*)out, (const cx<double>*)in, O, I, om,
-                                    (const cx<double>*)tw, st, sign)
-               : run_staged<float>((cx<float>*)out, (const cx<float>*)in, O, I, om,
-                                   (const cx<float>*)tw, st, sign);
+    return dbl ? dispatch_staged<double>(L, (cx<double>*)out, (const cx<double>*)in, O, I, om,
+                                         (const cx<double>*)tw, st, sign)
+               : dispatch_staged<float>(L, (cx<float>*)out, (const cx<float>*)in, O, I, om,
+                                        (const cx<float>*)tw, st, sign);
   if (dbl) {
     auto o = (cx<double>*)out;
     auto i = (const cx<double>*)in;
@@ -986,17 +740,10 @@ __device__ __forceinline__ void obs_column_fields(double c0, double c1, double c
 }
 
 // (3) over the columns: a shuffle sum over the 64 lanes of a wave (lane 0
-// takes the result); wave_sum32 the same steps after the first, for waves
-// whose lanes 32..63 hold zeros (that step then adds 0.0).
+// takes the result).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ double wave_sum32(double v) {
-#pragma unroll
-  for (int off = 16; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
 
@@ -1074,139 +821,61 @@ __global__ __launch_bounds__((strided_max_threads<T, L>())) void k_fft_strided_o
   }
 }
 
-// The same pass staged through LDS (see k_fft_strided_staged), for calls
-// with one origin (f.origins null): the same tiles and arithmetic, so the
-// same field and partial vectors. Its LDS accesses inside the tile loop are
-// written out with their waits (compiled ones would also wait for the next
-// tile's loads in flight), and the reduction area is LDS of its own, which
-// the loop's barriers order against the previous tile's readers. The 32
-// columns are one wave's: its lane 0 writes the tile's partial vector.
-typedef double qw_d2 __attribute__((ext_vector_type(2)));
+// The same pass staged through LDS (see k_fft_strided_staged), length 256,
+// for calls with one origin (f.origins null): the same tiles and
+// arithmetic, so the same field and partial vectors. Its LDS accesses inside
+// the tile loop are written out with their waits (compiled ones would also
+// wait for the next tile's loads in flight), and the reduction area is LDS
+// of its own, which the loop's barriers order against the previous tile's
+// readers. The reduction tail would stall the workgroup on one wave, so the
+// ten fields are spread over seven waves by the column sum they take: c0:
+// {0, 2}, {3, 5}, {6, 9}; c1: {1}, {7}, {8}; c2: {4}; the last wave writes
+// the zero fields. The COLS columns sit in lanes 0..COLS-1 of a reducing
+// wave and the other lanes hold zeros, so the register kernel's shuffle
+// steps over lanes COLS and up add 0.0.
 
-// c = sum over r = 0..15 (in that order) of the doubles at byte offsets
-// 256 r from LDS address a.
+// c = sum over the TT rows r (in that order) of the doubles at LDS bytes
+// a + 8 COLS r (COLS = 512 / TT).
+template <int TT>
 __device__ __forceinline__ double lds_column_sum(unsigned a) {
-  qw_d2 y0, y1, y2, y3, y4, y5, y6, y7;
-  asm volatile(
-      "ds_read2_b64 %0, %8 offset0:0 offset1:32\n\t"
-      "ds_read2_b64 %1, %8 offset0:64 offset1:96\n\t"
-      "ds_read2_b64 %2, %8 offset0:128 offset1:160\n\t"
-      "ds_read2_b64 %3, %8 offset0:192 offset1:224\n\t"
-      "ds_read2_b64 %4, %9 offset0:0 offset1:32\n\t"
-      "ds_read2_b64 %5, %9 offset0:64 offset1:96\n\t"
-      "ds_read2_b64 %6, %9 offset0:128 offset1:160\n\t"
-      "ds_read2_b64 %7, %9 offset0:192 offset1:224\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(y0), "=&v"(y1), "=&v"(y2), "=&v"(y3), "=&v"(y4), "=&v"(y5), "=&v"(y6), "=&v"(y7)
-      : "v"(a), "v"(a + 2048u)
-      : "memory");
-  const qw_d2 y[8] = {y0, y1, y2, y3, y4, y5, y6, y7};
-  double c = 0.0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    c += y[i].x;
-    c += y[i].y;
-  }
-  return c;
-}
-
-__global__ __launch_bounds__(512) void k_fft_strided_obs_staged(cx<float>* __restrict__ out,
-                                                                const cx<float>* __restrict__ in,
-                                                                int64_t I, int64_t nblk_i,
-                                                                int64_t nblk, ObsFuse f,
-                                                                const cx<float>* __restrict__ tw) {
-  __shared__ __align__(16) cx<float> buf[2 * 256 * kStagedCols];
-  __shared__ __align__(16) double red[3 * 512];
-  const int tid = threadIdx.x;
-  const int p = tid & (kStagedCols - 1), t = tid >> 5;
-  const OuterMap om{nblk / nblk_i, 0, 0, 0};
-  const AxisImage32 a0 = axis_image32(axis_image(f.c[0], f.N[0]));
-  const double org[3] = {f.c[0], f.c[1], f.c[2]};
-  typedef __attribute__((address_space(3))) double* lds_dptr;
-  const unsigned ra = (unsigned)(size_t)(lds_dptr)(red + tid);
-  const unsigned rl = (unsigned)(size_t)(lds_dptr)(red + (tid & 63));  // column lane
-  staged256_loop<-1>(buf, in, I, nblk_i, nblk, om, tw,
-                     [&](const cx<float>(&v)[16], int64_t blk, int64_t base) {
-                       if (f.store) {
-#pragma unroll
-                         for (int e = 0; e < 16; ++e)
-                           out[base + p + (int64_t)(t + 16 * e) * I] = v[e];
-                       }
-                       const int64_t o = blk / nblk_i;
-                       const int64_t col = base - o * 256 * I + p;
-                       double S0, S1, S11;
-                       obs_thread_moments<float, 256, 16>(v, t, I, col, f.dim, a0, S0, S1, S11);
-                       // red[tid], red[512 + tid], red[1024 + tid]; then all
-                       // threads' moments are there
-                       asm volatile(
-                           "ds_write_b64 %0, %1\n\t"
-                           "ds_write_b64 %0, %2 offset:4096\n\t"
-                           "ds_write_b64 %0, %3 offset:8192\n\t"
-                           "s_waitcnt lgkmcnt(0)\n\t"
-                           "s_barrier" ::"v"(ra),
-                           "v"(S0), "v"(S1), "v"(S11)
-                           : "memory");
-                       // Fields over the waves, by the column sum they take:
-                       // c0: {0, 2}, {3, 5}, {6, 9}; c1: {1}, {7}, {8}; c2: {4};
-                       // the last wave writes the zero fields. Lanes 0..31 hold
-                       // the columns, lanes 32..63 zeros: the first step of the
-                       // shuffle sum (adding lane i + 32) is v + 0.0.
-                       const int wave = tid >> 6, lane = tid & 63;
-                       if (wave < 7) {
-                         const int m = wave < 3 ? 0 : (wave < 6 ? 1 : 2);
-                         // (the wave's two fields as nibbles of one constant;
-                         // 15: none)
-                         const int k0 = (0x04871630 >> (4 * wave)) & 15;
-                         const int k1r = (0x0FFFF952 >> (4 * wave)) & 15;
-                         const int k1 = k1r == 15 ? -1 : k1r;
-                         double v0 = 0.0, v1 = 0.0;
-                         if (lane < kStagedCols) {
-                           const double c = lds_column_sum(rl + 4096u * m);
-                           double wb, wc;
-                           obs_column_disp(col - p + lane, org, f, wb, wc);
-                           v0 = obs_field(k0, c, c, c, wb, wc);
-                           if (k1 >= 0) v1 = obs_field(k1, c, c, c, wb, wc);
-                         }
-                         v0 = wave_sum32(v0 + 0.0);
-                         if (k1 >= 0) v1 = wave_sum32(v1 + 0.0);
-                         if (lane == 0) {
-                           double* dst = f.partials + blk * kObsFields;
-                           dst[k0] = 0.0 + v0;
-                           if (k1 >= 0) dst[k1] = 0.0 + v1;
-                         }
-                       } else if (lane == 0) {
-                         double* dst = f.partials + blk * kObsFields;
-                         for (int k = 10; k < kObsFields; ++k) dst[k] = 0.0;
-                       }
-                     });
-}
-
-// The complex128 form (16-column tiles; see k_fft_strided_staged_c128):
-// the register kernel's 16 columns sit in lanes 0..15 of a wave, lanes
-// 16..63 hold zeros, so the first two steps of the shuffle sum add 0.0.
-// c = sum over r = 0..31 (in that order) of the doubles at byte offsets
-// 128 r from LDS address a.
-__device__ __forceinline__ double lds_column_sum32(unsigned a) {
+  static_assert(TT == 16 || TT == 32, "rows of a column");
+  constexpr unsigned kHalf = 2048;  // bytes of TT / 2 rows
   double c = 0.0;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     qw_d2 y0, y1, y2, y3, y4, y5, y6, y7;
-    asm volatile(
-        "ds_read2_b64 %0, %8 offset0:0 offset1:16\n\t"
-        "ds_read2_b64 %1, %8 offset0:32 offset1:48\n\t"
-        "ds_read2_b64 %2, %8 offset0:64 offset1:80\n\t"
-        "ds_read2_b64 %3, %8 offset0:96 offset1:112\n\t"
-        "ds_read2_b64 %4, %8 offset0:128 offset1:144\n\t"
-        "ds_read2_b64 %5, %8 offset0:160 offset1:176\n\t"
-        "ds_read2_b64 %6, %8 offset0:192 offset1:208\n\t"
-        "ds_read2_b64 %7, %8 offset0:224 offset1:240\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(y0), "=&v"(y1), "=&v"(y2), "=&v"(y3), "=&v"(y4), "=&v"(y5), "=&v"(y6), "=&v"(y7)
-        : "v"(a + 2048u * h)
-        : "memory");
+    if constexpr (TT == 16) {
+      // 256-byte rows: four pairs per half
+      asm volatile(
+          "ds_read2_b64 %0, %4 offset0:0 offset1:32\n\t"
+          "ds_read2_b64 %1, %4 offset0:64 offset1:96\n\t"
+          "ds_read2_b64 %2, %4 offset0:128 offset1:160\n\t"
+          "ds_read2_b64 %3, %4 offset0:192 offset1:224\n\t"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(y0), "=&v"(y1), "=&v"(y2), "=&v"(y3)
+          : "v"(a + kHalf * h)
+          : "memory");
+      y4 = y5 = y6 = y7 = qw_d2{0.0, 0.0};
+    } else {
+      // 128-byte rows: eight pairs per half
+      asm volatile(
+          "ds_read2_b64 %0, %8 offset0:0 offset1:16\n\t"
+          "ds_read2_b64 %1, %8 offset0:32 offset1:48\n\t"
+          "ds_read2_b64 %2, %8 offset0:64 offset1:80\n\t"
+          "ds_read2_b64 %3, %8 offset0:96 offset1:112\n\t"
+          "ds_read2_b64 %4, %8 offset0:128 offset1:144\n\t"
+          "ds_read2_b64 %5, %8 offset0:160 offset1:176\n\t"
+          "ds_read2_b64 %6, %8 offset0:192 offset1:208\n\t"
+          "ds_read2_b64 %7, %8 offset0:224 offset1:240\n\t"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(y0), "=&v"(y1), "=&v"(y2), "=&v"(y3), "=&v"(y4), "=&v"(y5), "=&v"(y6),
+            "=&v"(y7)
+          : "v"(a + kHalf * h)
+          : "memory");
+    }
     const qw_d2 y[8] = {y0, y1, y2, y3, y4, y5, y6, y7};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < TT / 4; ++i) {
       c += y[i].x;
       c += y[i].y;
     }
@@ -1214,37 +883,46 @@ __device__ __forceinline__ double lds_column_sum32(unsigned a) {
   return c;
 }
 
-__device__ __forceinline__ double wave_sum16(double v) {
+// wave_sum for a wave whose lanes COLS..63 hold zeros.
+template <int COLS>
+__device__ __forceinline__ double wave_sum_cols(double v) {
 #pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  for (int off = 32; off >= COLS; off >>= 1) v = v + 0.0;
+#pragma unroll
+  for (int off = COLS / 2; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
 
-__global__ __launch_bounds__(512) void k_fft_strided_obs_staged_c128(
-    cx<double>* __restrict__ out, const cx<double>* __restrict__ in, int64_t I, int64_t nblk_i,
-    int64_t nblk, ObsFuse f, const cx<double>* __restrict__ tw) {
-  __shared__ __align__(16) cx<double> buf[2 * 256 * kStagedColsD];
+template <typename T>
+__global__ __launch_bounds__(512) void k_fft_strided_obs_staged(cx<T>* __restrict__ out,
+                                                                const cx<T>* __restrict__ in,
+                                                                int64_t I, int64_t nblk_i,
+                                                                int64_t nblk, ObsFuse f,
+                                                                const cx<T>* __restrict__ tw) {
+  using S = Staged<T, 256>;
+  constexpr int COLS = S::COLS, E = S::E, TT = 256 / E;
+  __shared__ __align__(16) cx<T> buf[2 * 256 * COLS];
   __shared__ __align__(16) double red[3 * 512];
   const int tid = threadIdx.x;
-  const int p = tid & (kStagedColsD - 1), t = tid >> 4;
+  const int p = tid % COLS, t = tid / COLS;
   const OuterMap om{nblk / nblk_i, 0, 0, 0};
   const AxisImage32 a0 = axis_image32(axis_image(f.c[0], f.N[0]));
   const double org[3] = {f.c[0], f.c[1], f.c[2]};
-  typedef __attribute__((address_space(3))) double* lds_dptr;
-  const unsigned ra = (unsigned)(size_t)(lds_dptr)(red + tid);
-  const unsigned rl = (unsigned)(size_t)(lds_dptr)(red + (tid & 63));  // column lane
-  staged256_loop_c128<-1>(buf, in, I, nblk_i, nblk, om, tw,
-                          [&](const cx<double>(&v)[8], int64_t blk, int64_t base) {
+  const unsigned ra = lds_addr(red + tid);
+  const unsigned rl = lds_addr(red + (tid & 63));  // the column of a reducing lane
+  staged_loop<T, 256, -1>(buf, in, I, nblk_i, nblk, om, tw,
+                          [&](const cx<T>(&v)[E], int64_t blk, int64_t base) {
                             if (f.store) {
 #pragma unroll
-                              for (int e = 0; e < 8; ++e)
-                                out[base + p + (int64_t)(t + 32 * e) * I] = v[e];
+                              for (int e = 0; e < E; ++e)
+                                out[base + p + (int64_t)(t + TT * e) * I] = v[e];
                             }
                             const int64_t o = blk / nblk_i;
                             const int64_t col = base - o * 256 * I + p;
                             double S0, S1, S11;
-                            obs_thread_moments<double, 256, 8>(v, t, I, col, f.dim, a0, S0, S1,
-                                                               S11);
+                            obs_thread_moments<T, 256, E>(v, t, I, col, f.dim, a0, S0, S1, S11);
+                            // red[tid], red[512 + tid], red[1024 + tid]; then
+                            // all threads' moments are there
                             asm volatile(
                                 "ds_write_b64 %0, %1\n\t"
                                 "ds_write_b64 %0, %2 offset:4096\n\t"
@@ -1253,23 +931,23 @@ __global__ __launch_bounds__(512) void k_fft_strided_obs_staged_c128(
                                 "s_barrier" ::"v"(ra),
                                 "v"(S0), "v"(S1), "v"(S11)
                                 : "memory");
-                            // fields over the waves as in k_fft_strided_obs_staged
                             const int wave = tid >> 6, lane = tid & 63;
                             if (wave < 7) {
                               const int m = wave < 3 ? 0 : (wave < 6 ? 1 : 2);
+                              // the wave's fields as nibbles of one constant (15: none)
                               const int k0 = (0x04871630 >> (4 * wave)) & 15;
                               const int k1r = (0x0FFFF952 >> (4 * wave)) & 15;
                               const int k1 = k1r == 15 ? -1 : k1r;
                               double v0 = 0.0, v1 = 0.0;
-                              if (lane < kStagedColsD) {
-                                const double c = lds_column_sum32(rl + 4096u * m);
+                              if (lane < COLS) {
+                                const double c = lds_column_sum<TT>(rl + 4096u * m);
                                 double wb, wc;
                                 obs_column_disp(col - p + lane, org, f, wb, wc);
                                 v0 = obs_field(k0, c, c, c, wb, wc);
                                 if (k1 >= 0) v1 = obs_field(k1, c, c, c, wb, wc);
                               }
-                              v0 = wave_sum16((v0 + 0.0) + 0.0);
-                              if (k1 >= 0) v1 = wave_sum16((v1 + 0.0) + 0.0);
+                              v0 = wave_sum_cols<COLS>(v0);
+                              if (k1 >= 0) v1 = wave_sum_cols<COLS>(v1);
                               if (lane == 0) {
                                 double* dst = f.partials + blk * kObsFields;
                                 dst[k0] = 0.0 + v0;
@@ -1296,15 +974,10 @@ static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   if constexpr (L == 256) {
     if (!f.origins && use_staged(sizeof(T) == 8, -1, L, (int64_t)s * B, I)) {
-      static_assert(TT * (sizeof(T) == 8 ? kStagedColsD : kStagedCols) == 512,
-                    "staged tiles are the register kernel's");
+      static_assert(TT * Staged<T, 256>::COLS == 512, "staged tiles are the register kernel's");
       const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL(k_fft_strided_obs_staged_c128, dim3((unsigned)ng), dim3(512), 0, st,
-                           out, in, I, nblk_i, nblk, f, tw);
-      else
-        hipLaunchKernelGGL(k_fft_strided_obs_staged, dim3((unsigned)ng), dim3(512), 0, st, out,
-                           in, I, nblk_i, nblk, f, tw);
+      hipLaunchKernelGGL(k_fft_strided_obs_staged<T>, dim3((unsigned)ng), dim3(512), 0, st, out,
+                         in, I, nblk_i, nblk, f, tw);
       return hipGetLastError();
     }
   }
