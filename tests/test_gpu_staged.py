@@ -178,3 +178,33 @@ def test_switch_arguments(qw):
     assert qw.LIB.qw_set_fft_kernel(2) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_set_fft_kernel(-1) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_set_fft_kernel(1) == qw.QW_OK
+
+
+def test_staged_passes_in_a_graph(qw):
+    """qw_evolve_fft at 256^3 complex64 (its inverse passes staged) captured
+    into a HIP graph: each replay, with eager work and synchronisations
+    between replays, gives bitwise the eager result."""
+    plan = qw.Plan(3, 256, 0.05, "c64")
+    x0 = _field(plan, 41)
+    want = plan.evolve_fft(x0, 99)
+    torch.cuda.synchronize()
+    out = plan.empty()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.evolve_fft(x0, 99, out=out, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    print("capturing the 256^3 jump", flush=True)
+    with torch.cuda.graph(g):
+        plan.evolve_fft(x0, 99, out=out, stream=torch.cuda.current_stream())
+    for r in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), r
+        e = plan.evolve_fft(x0, 7)  # eager work between replays
+        torch.cuda.synchronize()
+        del e
