@@ -6,13 +6,13 @@ length-256 inverse ones (32-column tiles; a 256^3 field of four components)
 and the length-512 ones of both directions (16-column tiles), at complex128
 the length-256 and -512 ones whose rows are at least 4096 elements apart,
 both directions (16- and 8-column tiles; the n1 passes at 256^3 and 512^3);
-with
-qw_set_fft_kernel(0) every pass keeps its loads in registers. Both run the
+with qw_set_fft_kernel(0) every pass keeps its loads in registers. Both run the
 same tiles through the same arithmetic, so every result must have the same
 bits: the field of a jump (Sec. 4: the Fourier evaluation of U^t), the
 reductions fused into its last pass (Sec. 5.2), the transforms, the time
 series, a batched jump whose instances together cross the size threshold,
-and the slab schedule (its n1 pass staged, its slab passes not)."""
+the slab schedule (its n1 pass staged, its slab passes not) and a graph
+replay of a staged jump."""
 import numpy as np
 import pytest
 import torch
