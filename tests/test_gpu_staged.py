@@ -82,14 +82,25 @@ def test_full_size_jump_and_reductions(qw):
     assert sa == sb
 
 
-def test_batched_instances_cross_the_threshold(qw):
+@pytest.mark.parametrize("B", [2, 3])
+def test_batched_instances_cross_the_threshold(qw, B):
     """256 x 128 x 256: one instance is 4096 tiles (register kernel), two
-    are 8192 (staged); per-instance masses and times."""
+    are 8192 and three 12288 (staged; tiles of one workgroup may belong to
+    two instances); per-instance masses and times."""
     plan = qw.Plan(3, [256, 128, 256], 0.2, "c64")
-    x = _field(plan, 9, B=2)
-    print("batched 2 x 256x128x256 complex64", flush=True)
-    a, b = _both(qw, lambda: plan.evolve_fft_batched(x, [0.2, 0.05], [333, -70]))
+    x = _field(plan, 9, B=B)
+    print("batched %d x 256x128x256 complex64" % B, flush=True)
+    m = [0.2, 0.05, 0.31][:B]
+    t = [333, -70, 100001][:B]
+    a, b = _both(qw, lambda: plan.evolve_fft_batched(x, m, t))
     assert torch.equal(a, b)
+    # each instance as a single jump at its own mass gives the same field to rounding
+    for i in range(B):
+        p1 = qw.Plan(3, [256, 128, 256], m[i], "c64")
+        one = p1.evolve_fft(x[i].contiguous(), t[i])
+        rel = (torch.linalg.vector_norm(one - a[i]) / torch.linalg.vector_norm(one)).item()
+        assert rel < 2e-5, (i, rel)
+        del one, p1
 
 
 @pytest.mark.parametrize("weyl,shape", [(True, [256, 512, 256]), (False, [256, 512, 128])])
