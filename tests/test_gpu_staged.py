@@ -219,3 +219,23 @@ def test_staged_passes_in_a_graph(qw):
         e = plan.evolve_fft(x0, 7)  # eager work between replays
         torch.cuda.synchronize()
         del e
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_full_size_series_matches_fused_jumps(qw, dtype):
+    """256^3: the series (staged reduction pass without a store, after the
+    staged n2 inverse pass) against the fused jump at each time (staged
+    reduction pass with a store), the same quantity to rounding."""
+    n = 256
+    plan = qw.Plan(3, n, 0.02, dtype)
+    x = plan.empty()
+    plan.prepare_state(x, [0.1, 0.1, 0.1], 20.0, [n // 2] * 3, 1 / np.sqrt(2), 1 / np.sqrt(2))
+    origin = [n / 2, n / 2, n / 2]
+    times = [1, 100, 4096, 100000]
+    print("256^3 %s series against fused jumps" % dtype, flush=True)
+    ser = plan.evolve_fft_series(x, times, origin)
+    tol = 4e-5 * n if dtype == "c64" else 1e-11 * n
+    for t, s in zip(times, ser):
+        o = plan.evolve_fft_observables(x, t, origin)
+        assert abs(s["norm2"] - o["norm2"]) < (2e-6 if dtype == "c64" else 1e-12), t
+        assert np.abs(np.array(s["mean"]) - np.array(o["mean"])).max() < tol, t
