@@ -251,9 +251,10 @@ __device__ __forceinline__ void lds_read8_b128(unsigned a, cx<double> (&y)[8]) {
 }
 
 // The staged shapes: each gives COLS and E (the register kernel's), whether
-// its workgroups go in XCD order (as the register kernel's at complex128,
-// where the staged n1 inverse pass gained nothing without it at 256^3 and
-// lost at 512^3 with it), its twiddles and its transform. fft(v, X, t, W):
+// its workgroups go in XCD order (measured per shape: at 256^3 complex128
+// the staged n1 inverse pass gained nothing without it; at 512^3, either
+// precision, it was slower with it), its twiddles and its transform.
+// fft(v, X, t, W):
 // the register kernel's Stockham stages for thread t's values v, with the
 // element at (position pos, this thread's column) at LDS bytes
 // X + pos * COLS * sizeof(cx<T>).
