@@ -71,6 +71,10 @@ struct qw_plan_s {
   double* d_series = nullptr;
   double* h_series = nullptr;
   int64_t series_cap = 0;
+  // Partial vectors of the fused reductions of up to kSeriesChunk times,
+  // reduced together (series_part_len doubles); it only grows.
+  double* d_series_part = nullptr;
+  int64_t series_part_len = 0;
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
   qw::InstParam* d_inst = nullptr;
@@ -110,6 +114,7 @@ struct qw_plan_s {
     if (d_result) (void)hipFree(d_result);
     if (h_result) (void)hipHostFree(h_result);
     if (d_series) (void)hipFree(d_series);
+    if (d_series_part) (void)hipFree(d_series_part);
     if (h_series) (void)hipHostFree(h_series);
     if (d_scratch) (void)hipFree(d_scratch);
     if (d_inst) (void)hipFree(d_inst);

@@ -1690,6 +1690,23 @@ static qw_status ensure_series(qw_plan_t p, int64_t n) {
   return QW_OK;
 }
 
+// Times of a series whose fused reductions are summed by one launch: their
+// partial vectors are kept side by side (at 256^3 complex64, 64 times of
+// 8192 partial vectors are 55 MB) and reduced as instances of a batch, each
+// in the fixed order of a single reduction.
+constexpr int64_t kSeriesChunk = 64;
+
+static qw_status ensure_series_part(qw_plan_t p, int64_t nb) {
+  const int64_t len = kSeriesChunk * (nb + 64) * kObsFields;
+  if (p->series_part_len >= len) return QW_OK;
+  double* d = nullptr;
+  HIP_TRY(hipMalloc((void**)&d, sizeof(double) * len));
+  if (p->d_series_part) p->retired_dev.push_back(p->d_series_part);
+  p->d_series_part = d;
+  p->series_part_len = len;
+  return QW_OK;
+}
+
 qw_status qw_evolve_fft_series(qw_plan_t p, const void* psi0, int64_t n, const int64_t* t,
                                const double* origin, qw_obs* out, void* stream) {
   return traced("qw_evolve_fft_series", stream, [&]() -> qw_status {
@@ -1707,6 +1724,10 @@ qw_status qw_evolve_fft_series(qw_plan_t p, const void* psi0, int64_t n, const i
     r = ensure_series(p, n);
     if (r != QW_OK) return r;
     const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
+    if (nb > 0) {
+      r = ensure_series_part(p, nb);
+      if (r != QW_OK) return r;
+    }
     // The spectrum of psi0 once, then per time the apply with the inverse
     // transform; that needs the natural-order spectrum and a strided pass
     // to take the reductions in (d = 2, 3), else each time is a full jump.
@@ -1722,35 +1743,40 @@ qw_status qw_evolve_fft_series(qw_plan_t p, const void* psi0, int64_t n, const i
       if (r != QW_OK) return r;
       omega = omega_table(p, st);
     }
+    double* part = p->d_series_part;  // [kSeriesChunk][nb][kObsFields], then the middle sums
+    double* mid = part + kSeriesChunk * nb * kObsFields;
     for (int64_t i = 0; i < n; ++i) {
       InstParam ip;
       ip.m = p->m;
       ip.n = p->n;
       ip.t = (double)t[i];
       double* res = p->d_series + (size_t)kObsFields * i;
+      double* my_part = part + (i % kSeriesChunk) * nb * kObsFields;
       if (spectral) {
         PassGeom g = pass_geom(p, L, 1);
         g.single = ip;
         g.omega = omega;
         const int mode = omega ? MODE_APPLY_INV_TAB : MODE_APPLY_INV;
         HIP_TRY(launch_fft_contig(p->dbl, mode, L, work, spec, g, p->d_tw, st, p->ce));
-        const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, false);
+        const ObsFuse f = make_fuse(p, origin, nullptr, my_part, false);
         r = strided_passes(p, -1, work, work, 1, st, &f);
         if (r != QW_OK) return r;
-        HIP_TRY(launch_reduce_partials(1, nb, p->d_partials, p->d_partials + nb * kObsFields,
-                                       res, st));
       } else if (nb > 0) {
-        const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, false);
+        const ObsFuse f = make_fuse(p, origin, nullptr, my_part, false);
         r = evolve_impl(p, 1, psi0, work, nullptr, ip, st, &f);
         if (r != QW_OK) return r;
-        HIP_TRY(launch_reduce_partials(1, nb, p->d_partials, p->d_partials + nb * kObsFields,
-                                       res, st));
       } else {
         r = evolve_impl(p, 1, psi0, work, nullptr, ip, st, nullptr);
         if (r != QW_OK) return r;
         ObsGeom og = obs_geom(p);
         for (int a = 0; a < p->dim; ++a) og.c[a] = origin[a];
         HIP_TRY(launch_observables(p->dbl, og, 1, work, nullptr, nullptr, p->d_partials, res, st));
+      }
+      // the chunk's reductions, once its last time is in
+      if (nb > 0 && (i % kSeriesChunk == kSeriesChunk - 1 || i == n - 1)) {
+        const int64_t c0 = i - i % kSeriesChunk;
+        HIP_TRY(launch_reduce_partials((int)(i - c0 + 1), nb, part, mid,
+                                       p->d_series + (size_t)kObsFields * c0, st));
       }
     }
     HIP_TRY(hipMemcpyAsync(p->h_series, p->d_series, sizeof(double) * kObsFields * (size_t)n,
