@@ -18,11 +18,11 @@ namespace qw {
 
 // Outer index o of a launch covers `ocount` consecutive planes o0.. of each
 // of several components, components `ostride` elements apart (a slab of the
-// lattice); a whole-field launch has ocount = O, o0 = 0. nt: the results are
-// written with non-temporal stores.
+// lattice); a whole-field launch has ocount = O, o0 = 0. hints: kNtStore,
+// kNtLoad bits (non-temporal stores of the results, loads of the input).
 struct OuterMap {
   int64_t ocount, o0, ostride;
-  int nt;
+  int hints;
 };
 
 // Workgroup b runs on XCD b % 8 (each XCD has its own L2 and translation
@@ -54,10 +54,15 @@ __global__ __launch_bounds__(1024) void k_fft_strided(cx<T>* __restrict__ out,
   const int64_t plane = om.o0 + (o - comp * om.ocount);
   const int64_t base = comp * om.ostride + plane * (int64_t)L * I + i0 + p;
   cx<T> v[E];
+  if (om.hints & kNtLoad) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = in[base + (int64_t)(t + TT * e) * I];
+    for (int e = 0; e < E; ++e) v[e] = load_nt(&in[base + (int64_t)(t + TT * e) * I]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = in[base + (int64_t)(t + TT * e) * I];
+  }
   fft_team<T, L, E, SIGN>(v, lds + p, P, t, tw);
-  if (om.nt) {
+  if (om.hints & kNtStore) {
 #pragma unroll
     for (int e = 0; e < E; ++e) store_nt(&out[base + (int64_t)(t + TT * e) * I], v[e]);
   } else {
@@ -538,10 +543,11 @@ static hipError_t run_staged(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
   const int64_t nblk = O * nblk_i;
   const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
   if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
-  auto kern = sign > 0 ? (om.nt ? k_fft_strided_staged<T, L, 1, true>
-                                : k_fft_strided_staged<T, L, 1, false>)
-                       : (om.nt ? k_fft_strided_staged<T, L, -1, true>
-                                : k_fft_strided_staged<T, L, -1, false>);
+  const bool nt = om.hints & kNtStore;
+  auto kern = sign > 0 ? (nt ? k_fft_strided_staged<T, L, 1, true>
+                             : k_fft_strided_staged<T, L, 1, false>)
+                       : (nt ? k_fft_strided_staged<T, L, -1, true>
+                             : k_fft_strided_staged<T, L, -1, false>);
   hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
   return hipGetLastError();
 }
@@ -635,8 +641,8 @@ static hipError_t dispatch_strided(int64_t L, cx<T>* out, const cx<T>* in, int64
 
 hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, const void* in,
                                    int64_t ncomp, int64_t ocount, int64_t o0, int64_t ostride,
-                                   int64_t I, const void* tw, hipStream_t st, bool nt) {
-  const OuterMap om{ocount, o0, ostride, nt ? 1 : 0};
+                                   int64_t I, const void* tw, hipStream_t st, int hints) {
+  const OuterMap om{ocount, o0, ostride, hints};
   const int64_t O = ncomp * ocount;
   if (use_staged(dbl, sign, L, O, I))
     return dbl ? dispatch_staged<double>(L, (cx<double>*)out, (const cx<double>*)in, O, I, om,
@@ -658,13 +664,13 @@ hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, con
 }
 
 hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
-                              int64_t I, const void* tw, hipStream_t st, bool nt) {
+                              int64_t I, const void* tw, hipStream_t st, int hints) {
   if (L == 1) {
     if (out != in)
       return hipMemcpyAsync(out, in, (dbl ? 16 : 8) * O * I, hipMemcpyDeviceToDevice, st);
     return hipSuccess;
   }
-  return launch_fft_strided_slab(dbl, sign, L, out, in, 1, O, 0, 0, I, tw, st, nt);
+  return launch_fft_strided_slab(dbl, sign, L, out, in, 1, O, 0, 0, I, tw, st, hints);
 }
 
 // Last inverse pass of an evolution with the Sec. 5.2 reductions fused: the

@@ -547,16 +547,27 @@ qw_status strided_passes(qw_plan_t p, int sign, void* out, const void* in, int B
     const int64_t N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
     // The n2 passes write with non-temporal stores when the field reaches
     // kNtBytes (256^3 complex64: 0.199 -> 0.191 ms and 0.197 -> 0.184 ms).
-    // The n1 forward pass keeps plain stores: the n2 pass after it reads the
-    // lines still cached (the same stores there cost 0.225 -> 0.243 ms).
+    // At complex64 the n1 forward pass, which reads the input once, also
+    // reads it and writes its results non-temporally: 256^3 n1 pass 0.231 ->
+    // 0.205 ms and the n2 pass after it 0.197 -> 0.181 ms (jump 1.035 ->
+    // 0.992 ms); 512^3 n1 pass (staged, stores only) 2.19 -> 2.14 ms. Either
+    // hint alone loses: the stores alone cost the n1 pass 0.231 -> 0.251 ms,
+    // the loads alone the n2 pass 0.197 -> 0.213 ms. At complex128 the same
+    // stores slow the staged n1 pass (256^3: 0.46 -> 0.48 ms, 512^3: 4.35 ->
+    // 5.3 ms), so it keeps plain ones.
     const bool nt = p->field_bytes * (size_t)B >= kNtBytes;
+    const int n2_hints = nt ? kNtStore : 0;
+    const int n1_hints = (nt && !p->dbl) ? kNtStore | kNtLoad : 0;
     if (sign > 0) {
-      HIP_TRY(launch_fft_strided(p->dbl, 1, N1, out, in, (int64_t)s * B, N2 * N3, p->d_tw, st));
+      HIP_TRY(launch_fft_strided(p->dbl, 1, N1, out, in, (int64_t)s * B, N2 * N3, p->d_tw, st,
+                                 n1_hints));
       mark();
-      HIP_TRY(launch_fft_strided(p->dbl, 1, N2, out, out, (int64_t)s * B * N1, N3, p->d_tw, st, nt));
+      HIP_TRY(launch_fft_strided(p->dbl, 1, N2, out, out, (int64_t)s * B * N1, N3, p->d_tw, st,
+                                 n2_hints));
       mark();
     } else {
-      HIP_TRY(launch_fft_strided(p->dbl, -1, N2, out, in, (int64_t)s * B * N1, N3, p->d_tw, st, nt));
+      HIP_TRY(launch_fft_strided(p->dbl, -1, N2, out, in, (int64_t)s * B * N1, N3, p->d_tw, st,
+                                 n2_hints));
       mark();
       return last_pass(p, N1, out, out, B, N2 * N3, st, fuse);
     }

@@ -127,17 +127,21 @@ constexpr size_t kNtBytes = size_t(256) << 20;
 // ---------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).
 // ---------------------------------------------------------------------------
-// nt: write the results with non-temporal stores (for fields larger than
-// the last-level cache whose next reader gains nothing from cached lines).
+// Cache hints of a strided pass (bit set): kNtStore writes the results with
+// non-temporal stores (for fields larger than the last-level cache whose next
+// reader gains nothing from cached lines); kNtLoad reads the input with
+// non-temporal loads (input read once by this pass and not again soon). The
+// LDS-staged kernels take kNtStore and ignore kNtLoad.
+enum : int { kNtStore = 1, kNtLoad = 2 };
 hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
-                              int64_t I, const void* tw, hipStream_t st, bool nt = false);
+                              int64_t I, const void* tw, hipStream_t st, int hints = 0);
 // Length-256 complex64 inverse passes of large fields staged through LDS
 // (on by default; the same bits either way).
 void set_fft_staged(bool on);
 // Planes o0 .. o0+ocount-1 of each of ncomp components (ostride elements apart).
 hipError_t launch_fft_strided_slab(bool dbl, int sign, int64_t L, void* out, const void* in,
                                    int64_t ncomp, int64_t ocount, int64_t o0, int64_t ostride,
-                                   int64_t I, const void* tw, hipStream_t st, bool nt = false);
+                                   int64_t I, const void* tw, hipStream_t st, int hints = 0);
 // E: elements per thread of the contiguous pass (4 or 8; 0 = default 8).
 hipError_t launch_fft_contig(bool dbl, int mode, int64_t L, void* out, const void* in,
                              const PassGeom& g, const void* tw, hipStream_t st, int E = 0);
@@ -360,6 +364,14 @@ __device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v) {
   w.x = v.x;
   w.y = v.y;
   __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
+}
+
+// Non-temporal load of one complex value.
+template <typename T>
+__device__ __forceinline__ cx<T> load_nt(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 w = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return mk(w.x, w.y);
 }
 
 // Kernel-side helpers shared by the apply and the state preparation:
