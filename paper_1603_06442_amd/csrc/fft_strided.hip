@@ -409,7 +409,11 @@ struct Staged<double, 512> {
 // One tile (L rows of COLS columns from `tile`, row stride I) into buf:
 // each instruction loads RPI whole rows, slots RPI j .. RPI j + RPI - 1 of
 // this wave.
-template <typename T, int L>
+// Cache policy of the global-to-LDS loads: 0, or kAuxNt (the nt bit of
+// gfx950's cache-policy field: the input's lines are not kept in the caches).
+constexpr int kAuxNt = 2;
+
+template <typename T, int L, int AUX = 0>
 struct StagedTile {
   __device__ __forceinline__ static void load(cx<T>* __restrict__ buf,
                                               const cx<T>* __restrict__ in, int64_t tile,
@@ -425,7 +429,7 @@ struct StagedTile {
       const int q = RPI * j + l / LPR;
       const int64_t r = TPW * w + q % TPW + TT * (q / TPW);
       __builtin_amdgcn_global_load_lds(in + tile + r * I + EPL * (l % LPR),
-                                       buf + (w * RPW + RPI * j) * S::COLS, 16, 0, 0);
+                                       buf + (w * RPW + RPI * j) * S::COLS, 16, 0, AUX);
     }
   }
 };
@@ -435,7 +439,7 @@ struct StagedTile {
 // transformed and handed to epi(v, tile, first element of the tile) with the
 // thread's E values, rows t + TT e of column p. buf: 2 L COLS elements of
 // LDS.
-template <typename T, int L, int SIGN, typename Epi>
+template <typename T, int L, int SIGN, int AUX = 0, typename Epi>
 __device__ __forceinline__ void staged_loop(cx<T>* __restrict__ buf,
                                             const cx<T>* __restrict__ in, int64_t I,
                                             int64_t nblk_i, int64_t nblk, const OuterMap& om,
@@ -457,7 +461,7 @@ __device__ __forceinline__ void staged_loop(cx<T>* __restrict__ buf,
   if (first >= nblk) return;
   const int n = nblk - first < kStagedTiles ? (int)(nblk - first) : kStagedTiles;
   int64_t cur = tile_base(first);
-  StagedTile<T, L>::load(buf, in, cur, I, tid);
+  StagedTile<T, L, AUX>::load(buf, in, cur, I, tid);
   const int s0 = (t / TPW) * RPW + t % TPW;
   for (int k = 0; k < n; ++k) {
     cx<T>* X = buf + (k & 1) * (L * COLS);
@@ -472,7 +476,7 @@ __device__ __forceinline__ void staged_loop(cx<T>* __restrict__ buf,
     int64_t nxt = 0;
     if (k + 1 < n) {
       nxt = tile_base(first + k + 1);
-      StagedTile<T, L>::load(Y, in, nxt, I, tid);
+      StagedTile<T, L, AUX>::load(Y, in, nxt, I, tid);
     }
     S::template fft<SIGN>(v, lds_addr(X + p), t, W);
     epi(v, first + k, cur);
@@ -482,7 +486,7 @@ __device__ __forceinline__ void staged_loop(cx<T>* __restrict__ buf,
 
 // NT: non-temporal stores (a template parameter: as a branch inside the
 // loop the two store forms were merged into plain stores).
-template <typename T, int L, int SIGN, bool NT>
+template <typename T, int L, int SIGN, bool NT, int AUX = 0>
 __global__ __launch_bounds__(512) void k_fft_strided_staged(cx<T>* __restrict__ out,
                                                             const cx<T>* __restrict__ in,
                                                             int64_t I, int64_t nblk_i,
@@ -492,7 +496,7 @@ __global__ __launch_bounds__(512) void k_fft_strided_staged(cx<T>* __restrict__ 
   constexpr int COLS = S::COLS, E = S::E, TT = L / E;
   __shared__ __align__(16) cx<T> buf[2 * L * COLS];
   const int p = threadIdx.x % COLS, t = threadIdx.x / COLS;
-  staged_loop<T, L, SIGN>(buf, in, I, nblk_i, nblk, om, tw,
+  staged_loop<T, L, SIGN, AUX>(buf, in, I, nblk_i, nblk, om, tw,
                           [&](const cx<T>(&v)[E], int64_t, int64_t base) {
                             const int64_t b = base + p;
 #pragma unroll
@@ -544,10 +548,17 @@ static hipError_t run_staged(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
   const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
   if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
   const bool nt = om.hints & kNtStore;
-  auto kern = sign > 0 ? (nt ? k_fft_strided_staged<T, L, 1, true>
-                             : k_fft_strided_staged<T, L, 1, false>)
-                       : (nt ? k_fft_strided_staged<T, L, -1, true>
-                             : k_fft_strided_staged<T, L, -1, false>);
+  auto kern = k_fft_strided_staged<T, L, 1, false>;
+  if (om.hints & kNtLoad)
+    kern = sign > 0 ? (nt ? k_fft_strided_staged<T, L, 1, true, kAuxNt>
+                          : k_fft_strided_staged<T, L, 1, false, kAuxNt>)
+                    : (nt ? k_fft_strided_staged<T, L, -1, true, kAuxNt>
+                          : k_fft_strided_staged<T, L, -1, false, kAuxNt>);
+  else
+    kern = sign > 0 ? (nt ? k_fft_strided_staged<T, L, 1, true>
+                          : k_fft_strided_staged<T, L, 1, false>)
+                    : (nt ? k_fft_strided_staged<T, L, -1, true>
+                          : k_fft_strided_staged<T, L, -1, false>);
   hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
   return hipGetLastError();
 }
@@ -900,7 +911,7 @@ __device__ __forceinline__ double wave_sum_cols(double v) {
   return v;
 }
 
-template <typename T>
+template <typename T, int AUX = 0>
 __global__ __launch_bounds__(512) void k_fft_strided_obs_staged(cx<T>* __restrict__ out,
                                                                 const cx<T>* __restrict__ in,
                                                                 int64_t I, int64_t nblk_i,
@@ -917,7 +928,7 @@ __global__ __launch_bounds__(512) void k_fft_strided_obs_staged(cx<T>* __restric
   const double org[3] = {f.c[0], f.c[1], f.c[2]};
   const unsigned ra = lds_addr(red + tid);
   const unsigned rl = lds_addr(red + (tid & 63));  // the column of a reducing lane
-  staged_loop<T, 256, -1>(buf, in, I, nblk_i, nblk, om, tw,
+  staged_loop<T, 256, -1, AUX>(buf, in, I, nblk_i, nblk, om, tw,
                           [&](const cx<T>(&v)[E], int64_t blk, int64_t base) {
                             if (f.store) {
 #pragma unroll
@@ -969,7 +980,7 @@ __global__ __launch_bounds__(512) void k_fft_strided_obs_staged(cx<T>* __restric
 
 template <typename T, int L>
 static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int64_t I,
-                                  const ObsFuse& f, const cx<T>* tw, hipStream_t st) {
+                                  const ObsFuse& f, const cx<T>* tw, hipStream_t st, int hints) {
   constexpr int Emax = sizeof(T) == 8 ? 8 : 16;
   constexpr int E = L < Emax ? L : Emax;
   constexpr int TT = L / E;
@@ -983,8 +994,10 @@ static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int
     if (!f.origins && use_staged(sizeof(T) == 8, -1, L, (int64_t)s * B, I)) {
       static_assert(TT * Staged<T, 256>::COLS == 512, "staged tiles are the register kernel's");
       const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
-      hipLaunchKernelGGL(k_fft_strided_obs_staged<T>, dim3((unsigned)ng), dim3(512), 0, st, out,
-                         in, I, nblk_i, nblk, f, tw);
+      auto kern = (hints & kNtLoad) ? k_fft_strided_obs_staged<T, kAuxNt>
+                                    : k_fft_strided_obs_staged<T>;
+      hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, f,
+                         tw);
       return hipGetLastError();
     }
   }
@@ -1031,29 +1044,30 @@ int64_t strided_obs_blocks(bool dbl, int64_t L, int64_t I) {
 template <typename T>
 static hipError_t dispatch_strided_obs(int64_t L, cx<T>* out, const cx<T>* in, int s, int B,
                                        int64_t I, const ObsFuse& f, const cx<T>* tw,
-                                       hipStream_t st) {
+                                       hipStream_t st, int hints) {
   switch (L) {
-    case 2: return run_strided_obs<T, 2>(out, in, s, B, I, f, tw, st);
-    case 4: return run_strided_obs<T, 4>(out, in, s, B, I, f, tw, st);
-    case 8: return run_strided_obs<T, 8>(out, in, s, B, I, f, tw, st);
-    case 16: return run_strided_obs<T, 16>(out, in, s, B, I, f, tw, st);
-    case 32: return run_strided_obs<T, 32>(out, in, s, B, I, f, tw, st);
-    case 64: return run_strided_obs<T, 64>(out, in, s, B, I, f, tw, st);
-    case 128: return run_strided_obs<T, 128>(out, in, s, B, I, f, tw, st);
-    case 256: return run_strided_obs<T, 256>(out, in, s, B, I, f, tw, st);
-    case 512: return run_strided_obs<T, 512>(out, in, s, B, I, f, tw, st);
-    case 1024: return run_strided_obs<T, 1024>(out, in, s, B, I, f, tw, st);
+    case 2: return run_strided_obs<T, 2>(out, in, s, B, I, f, tw, st, hints);
+    case 4: return run_strided_obs<T, 4>(out, in, s, B, I, f, tw, st, hints);
+    case 8: return run_strided_obs<T, 8>(out, in, s, B, I, f, tw, st, hints);
+    case 16: return run_strided_obs<T, 16>(out, in, s, B, I, f, tw, st, hints);
+    case 32: return run_strided_obs<T, 32>(out, in, s, B, I, f, tw, st, hints);
+    case 64: return run_strided_obs<T, 64>(out, in, s, B, I, f, tw, st, hints);
+    case 128: return run_strided_obs<T, 128>(out, in, s, B, I, f, tw, st, hints);
+    case 256: return run_strided_obs<T, 256>(out, in, s, B, I, f, tw, st, hints);
+    case 512: return run_strided_obs<T, 512>(out, in, s, B, I, f, tw, st, hints);
+    case 1024: return run_strided_obs<T, 1024>(out, in, s, B, I, f, tw, st, hints);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_fft_strided_obs(bool dbl, int64_t L, void* out, const void* in, int s, int B,
-                                  int64_t I, const ObsFuse& f, const void* tw, hipStream_t st) {
+                                  int64_t I, const ObsFuse& f, const void* tw, hipStream_t st,
+                                  int hints) {
   if (dbl)
     return dispatch_strided_obs<double>(L, (cx<double>*)out, (const cx<double>*)in, s, B, I, f,
-                                        (const cx<double>*)tw, st);
+                                        (const cx<double>*)tw, st, hints);
   return dispatch_strided_obs<float>(L, (cx<float>*)out, (const cx<float>*)in, s, B, I, f,
-                                     (const cx<float>*)tw, st);
+                                     (const cx<float>*)tw, st, hints);
 }
 
 // out[p][c][r] = in[p][r][c] for planes p of an R x C matrix (32 x 32 tiles).

@@ -130,8 +130,8 @@ constexpr size_t kNtBytes = size_t(256) << 20;
 // Cache hints of a strided pass (bit set): kNtStore writes the results with
 // non-temporal stores (for fields larger than the last-level cache whose next
 // reader gains nothing from cached lines); kNtLoad reads the input with
-// non-temporal loads (input read once by this pass and not again soon). The
-// LDS-staged kernels take kNtStore and ignore kNtLoad.
+// non-temporal loads (input read once by this pass and not again soon), in
+// the LDS-staged kernels with the nt cache policy on their global-to-LDS loads.
 enum : int { kNtStore = 1, kNtLoad = 2 };
 hipError_t launch_fft_strided(bool dbl, int sign, int64_t L, void* out, const void* in, int64_t O,
                               int64_t I, const void* tw, hipStream_t st, int hints = 0);
@@ -291,9 +291,11 @@ struct ObsFuse {
 // not a multiple of 64 threads).
 int64_t strided_obs_blocks(bool dbl, int64_t L, int64_t I);
 // Inverse transform along L (stride I) of B instances of s components,
-// whole fields, with the reductions of `f`.
+// whole fields, with the reductions of `f`. hints: kNtLoad, taken by the
+// LDS-staged form of the pass (the register forms ignore it).
 hipError_t launch_fft_strided_obs(bool dbl, int64_t L, void* out, const void* in, int s, int B,
-                                  int64_t I, const ObsFuse& f, const void* tw, hipStream_t st);
+                                  int64_t I, const ObsFuse& f, const void* tw, hipStream_t st,
+                                  int hints = 0);
 // Sums nb partial vectors of kObsFields doubles per instance into
 // result[B][kObsFields], through `mid` (B * 64 * kObsFields doubles), in a
 // fixed order.
