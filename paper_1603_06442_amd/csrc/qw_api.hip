@@ -551,19 +551,26 @@ qw_status strided_passes(qw_plan_t p, int sign, void* out, const void* in, int B
   const int s = p->s;
   if (p->dim == 3) {
     const int64_t N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
-    // The n2 passes write with non-temporal stores when the field reaches
-    // kNtBytes (256^3 complex64: 0.199 -> 0.191 ms and 0.197 -> 0.184 ms).
-    // At complex64 the n1 forward pass, which reads the input once, also
-    // reads it and writes its results non-temporally: 256^3 n1 pass 0.231 ->
-    // 0.205 ms and the n2 pass after it 0.197 -> 0.181 ms (jump 1.035 ->
-    // 0.992 ms); 512^3 n1 pass (staged, stores only) 2.19 -> 2.14 ms. Either
-    // hint alone loses: the stores alone cost the n1 pass 0.231 -> 0.251 ms,
-    // the loads alone the n2 pass 0.197 -> 0.213 ms. At complex128 the same
-    // stores slow the staged n1 pass (256^3: 0.46 -> 0.48 ms, 512^3: 4.35 ->
-    // 5.3 ms), so it keeps plain ones.
+    // Cache hints when the field reaches kNtBytes. The n2 passes write with
+    // non-temporal stores (256^3 complex64: 0.199 -> 0.191 ms and 0.197 ->
+    // 0.184 ms). At complex64 the n1 forward pass, which reads the input
+    // once, also reads it and writes its results non-temporally: 256^3 n1
+    // pass 0.231 -> 0.205 ms and the n2 pass after it 0.197 -> 0.181 ms (jump
+    // 1.035 -> 0.992 ms); 512^3 n1 pass (staged) 2.19 -> 2.14 ms. Either hint
+    // alone loses there: the stores alone cost the n1 pass 0.231 -> 0.251
+    // ms, the loads alone the n2 pass 0.197 -> 0.213 ms. At complex128 the
+    // same stores slow the staged n1 pass (256^3: 0.46 -> 0.48 ms, 512^3:
+    // 4.35 -> 5.3 ms), while non-temporal loads serve the n1 forward pass and
+    // both n2 passes: 256^3 jump 2.17 -> 2.08 ms (n1 forward 0.450 -> 0.430,
+    // n2 forward 0.391 -> 0.381, the fused pass after it 0.52 -> 0.50, n2
+    // inverse 0.395 -> 0.375, the n1 inverse pass after it 0.415 -> 0.395),
+    // 512^3 jump 19.4 -> 19.0 ms.
     const bool nt = p->field_bytes * (size_t)B >= kNtBytes;
-    const int n2_hints = nt ? kNtStore : 0;
-    const int n1_hints = (nt && !p->dbl) ? kNtStore | kNtLoad : 0;
+    int n1_hints = 0, n2_hints = 0;
+    if (nt) {
+      n1_hints = p->dbl ? kNtLoad : kNtStore | kNtLoad;
+      n2_hints = p->dbl ? kNtStore | kNtLoad : kNtStore;
+    }
     if (sign > 0) {
       HIP_TRY(launch_fft_strided(p->dbl, 1, N1, out, in, (int64_t)s * B, N2 * N3, p->d_tw, st,
                                  n1_hints));
