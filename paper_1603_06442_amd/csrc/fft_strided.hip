@@ -515,8 +515,10 @@ __global__ __launch_bounds__(512) void k_fft_strided_staged(cx<T>* __restrict__ 
 // * complex64, length 256: the inverse direction. The forward passes
 //   measured slower staged (0.246 and 0.210 ms against 0.226 and 0.190 at
 //   256^3; in XCD order 0.240 and 0.183, but the fused pass after them then
-//   took 0.245 against 0.238 ms), where the inverse ones went 0.187 -> 0.174
-//   ms and 0.213 -> 0.197 ms (in XCD order 0.190 and 0.195).
+//   took 0.245 against 0.238 ms; the n1 pass with its cache hints 0.223
+//   against 0.205 ms for the register kernel with the same hints), where the
+//   inverse ones went 0.187 -> 0.174 ms and 0.213 -> 0.197 ms (in XCD order
+//   0.190 and 0.195).
 // * complex64, length 512: both directions. At 512^3 the n1 forward pass
 //   2.82 -> 2.17 ms, n2 forward 1.77 -> 1.63, n2 inverse 1.83 -> 1.61, n1
 //   inverse 2.37 -> 2.08 (the jump 10.8 -> 9.5 ms); in XCD order slightly
