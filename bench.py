@@ -10,6 +10,10 @@ step is one pass over the whole hot path:
     log-spaced in [1, 1e5]) with the position/norm reduction of psi_t (the
     Zitterbewegung observable) taken inside its last inverse pass,
   * two position-space steps of a second field.
+Each step's reductions reach the host through a pinned record
+(qw_evolve_fft_observables_async) that is read while the next step runs, so
+the GPU is not left idle during the read; the same steps with the host
+waiting for each jump are timed beside them (ms_per_step_waiting).
 `value` is steps per second, i.e. Fourier evolutions per second with the
 reduction and the two stencil steps included in each. The JSON line also
 carries the stencil's own site-steps/s, the roofline of the dominant kernel
@@ -382,20 +386,50 @@ def main():
     V = N ** 3
     field_bytes = psi0.numel() * psi0.element_size()
 
+    # Each step queues its jump, whose reductions a copy leaves in a pinned
+    # record (qw_evolve_fft_observables_async), and its two stencil steps,
+    # then reads the previous step's record, complete by then: the GPU is
+    # not left idle while the host waits for a result.
+    raws = [torch.empty(qw.OBS_RAW_DOUBLES, dtype=torch.float64, pin_memory=True)
+            for _ in range(2)]
+    done = [torch.cuda.Event() for _ in range(2)]
+
     def step(i):
-        o = plan.evolve_fft_observables(psi0, times[i % len(times)], w["center"], out=psit)
+        k = i & 1
+        plan.evolve_fft_observables_async(psi0, times[i % len(times)], w["center"], raws[k],
+                                          out=psit)
+        done[k].record()
         plan.step(psis, 2)
-        return o
+        if i == 0:
+            return None
+        done[k ^ 1].synchronize()
+        return plan.obs_from_raw(raws[k ^ 1], w["center"])
 
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        obs = step(i)
+        step(i)
     torch.cuda.synchronize()
+    obs = plan.obs_from_raw(raws[(args.steps - 1) & 1], w["center"])  # the last step's
     el = time.perf_counter() - t0
     ms_per_step = 1e3 * el / args.steps
+
+    # The same steps with the host waiting for each jump's reductions.
+    def step_waiting(i):
+        o = plan.evolve_fft_observables(psi0, times[i % len(times)], w["center"], out=psit)
+        plan.step(psis, 2)
+        return o
+
+    if step_waiting(args.steps - 1) != obs:
+        raise RuntimeError("reductions read back late differ from the waiting call's")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step_waiting(i)
+    torch.cuda.synchronize()
+    ms_per_step_waiting = 1e3 * (time.perf_counter() - t0) / args.steps
 
     # Per-kernel durations, HIP events on the launch stream.
     reps = 10
@@ -478,8 +512,12 @@ def main():
                                "k0=(0.1,0.1,0.1) sigma=20, t over 64 log-spaced times in [1,1e5]",
                    "step": "one hot-path step = 1 Fourier jump psi_t = U^t psi_0 with the "
                            "<x>/norm reduction fused into its last pass + 2 stencil steps of a "
-                           "second field; value = such steps per second (wall clock)",
+                           "second field, each step's reductions read by the host while the next "
+                           "step runs (qw_evolve_fft_observables_async; ms_per_step_waiting: "
+                           "the host waiting for each jump's); value = such steps per second "
+                           "(wall clock)",
                    "lattice": [N, N, N], "spinor": 4, "global_batch": 1},
+        "ms_per_step_waiting": round(ms_per_step_waiting, 4),
         "fft_evolutions_per_s_kernels": round(1e3 / evo_ms, 2),
         "schedule": {"slab_planes": schedule[0], "contig_elems": schedule[1],
                      "contig_threads": schedule[2], "contig_groups": schedule[3],

@@ -308,6 +308,30 @@ qw_status qw_marginals(qw_plan_t plan, const void* psi, const int64_t* origin, d
 qw_status qw_evolve_fft_observables(qw_plan_t plan, const void* psi0, void* psi_t, int64_t t,
                                     const double* origin, qw_obs* out, void* stream);
 
+/* Doubles of the raw reduction record of qw_evolve_fft_observables_async. */
+#define QW_OBS_RAW_DOUBLES 13
+
+/* qw_evolve_fft_observables without the wait (the same jump and Sec. 5.2
+ * reductions, queued on `stream`): a copy on the stream leaves the record of
+ * the sums in raw[0..QW_OBS_RAW_DOUBLES) once the pass is done, and the call
+ * returns as soon as the work is queued. raw: HOST memory, pinned
+ * (hipHostMalloc; with pageable memory the copy, and so the call, waits).
+ * Once the stream has passed the call (hipStreamSynchronize, or an event
+ * recorded after it), qw_obs_from_raw turns the record into the qw_obs that
+ * qw_evolve_fft_observables returns, bit for bit. For loops that keep the
+ * GPU busy while the host reads an earlier result. The plan's reduction
+ * buffers are reused by every such call: calls on one plan must be issued on
+ * one stream (on different streams they race). Errors as
+ * qw_evolve_fft_observables; raw NULL is QW_ERR_INVALID. */
+qw_status qw_evolve_fft_observables_async(qw_plan_t plan, const void* psi0, void* psi_t,
+                                          int64_t t, const double* origin, double* raw,
+                                          void* stream);
+
+/* The qw_obs of a raw record written by qw_evolve_fft_observables_async
+ * (raw: HOST, QW_OBS_RAW_DOUBLES doubles, complete), about the origin passed
+ * to that call (dim HOST doubles). Host arithmetic only; no GPU work. */
+qw_status qw_obs_from_raw(qw_plan_t plan, const double* raw, const double* origin, qw_obs* out);
+
 /* The reductions of psi(t_i) = U^{t_i} psi0 about origin (as
  * qw_evolve_fft_observables) for n times t[0..n) (HOST int64, |t_i| <= 2^53,
  * any order), out[0..n) (HOST). The series of the position expectation of

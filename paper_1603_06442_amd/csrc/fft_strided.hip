@@ -913,7 +913,8 @@ __device__ __forceinline__ double wave_sum_cols(double v) {
   return v;
 }
 
-template <typename T, int AUX = 0>
+// NT: the field (when f.store) is written with non-temporal stores.
+template <typename T, int AUX = 0, bool NT = false>
 __global__ __launch_bounds__(512) void k_fft_strided_obs_staged(cx<T>* __restrict__ out,
                                                                 const cx<T>* __restrict__ in,
                                                                 int64_t I, int64_t nblk_i,
@@ -934,8 +935,12 @@ __global__ __launch_bounds__(512) void k_fft_strided_obs_staged(cx<T>* __restric
                           [&](const cx<T>(&v)[E], int64_t blk, int64_t base) {
                             if (f.store) {
 #pragma unroll
-                              for (int e = 0; e < E; ++e)
-                                out[base + p + (int64_t)(t + TT * e) * I] = v[e];
+                              for (int e = 0; e < E; ++e) {
+                                if constexpr (NT)
+                                  store_nt(&out[base + p + (int64_t)(t + TT * e) * I], v[e]);
+                                else
+                                  out[base + p + (int64_t)(t + TT * e) * I] = v[e];
+                              }
                             }
                             const int64_t o = blk / nblk_i;
                             const int64_t col = base - o * 256 * I + p;
@@ -996,8 +1001,11 @@ static hipError_t run_strided_obs(cx<T>* out, const cx<T>* in, int s, int B, int
     if (!f.origins && use_staged(sizeof(T) == 8, -1, L, (int64_t)s * B, I)) {
       static_assert(TT * Staged<T, 256>::COLS == 512, "staged tiles are the register kernel's");
       const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
-      auto kern = (hints & kNtLoad) ? k_fft_strided_obs_staged<T, kAuxNt>
-                                    : k_fft_strided_obs_staged<T>;
+      const bool ntl = hints & kNtLoad, nts = hints & kNtStore;
+      auto kern = ntl ? (nts ? k_fft_strided_obs_staged<T, kAuxNt, true>
+                             : k_fft_strided_obs_staged<T, kAuxNt, false>)
+                      : (nts ? k_fft_strided_obs_staged<T, 0, true>
+                             : k_fft_strided_obs_staged<T, 0, false>);
       hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, f,
                          tw);
       return hipGetLastError();

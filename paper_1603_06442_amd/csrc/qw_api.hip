@@ -507,11 +507,19 @@ PassGeom pass_geom(qw_plan_t p, int64_t L, int B) {
 // The complex64 3D n1 inverse pass reads its input non-temporally when the
 // field reaches kNtBytes (256^3, staged: 0.197 -> 0.188 ms, fused with the
 // reductions 1.031 -> 1.022 ms per jump). The same hint on the n2 inverse
-// pass before it made that pass 0.173 -> 0.198 ms, so it stays there.
+// pass before it made that pass 0.173 -> 0.198 ms, so it stays there. It
+// also writes the evolved field non-temporally, as the other streaming
+// passes do for fields beyond the last-level cache: with plain stores the
+// pass ends sooner (0.190 against 0.214 ms) but leaves its lines dirty in
+// that cache, and the next kernel pays for writing them back (the stencil
+// step after a jump 0.258 against 0.215 ms); the benchmark's step (fused
+// jump, two stencil steps) 1.493 -> 1.461 ms, a loop of fused jumps alone
+// 1.019 -> 1.034 ms per jump.
 static qw_status last_pass(qw_plan_t p, int64_t L, void* out, const void* in, int B, int64_t I,
                            hipStream_t st, const ObsFuse* fuse) {
-  const int hints =
-      (p->dim == 3 && !p->dbl && p->field_bytes * (size_t)B >= kNtBytes) ? kNtLoad : 0;
+  const int hints = (p->dim == 3 && !p->dbl && p->field_bytes * (size_t)B >= kNtBytes)
+                        ? kNtLoad | kNtStore
+                        : 0;
   if (fuse)
     HIP_TRY(launch_fft_strided_obs(p->dbl, L, out, in, p->s, B, I, *fuse, p->d_tw, st, hints));
   else
@@ -1646,42 +1654,54 @@ qw_status qw_bcc_evolve_fft(qw_plan_t p, const void* f0, void* f_t, double t, vo
   });
 }
 
+static_assert(kObsFields == QW_OBS_RAW_DOUBLES, "raw reduction record of the public header");
+
+// The jump and its reductions queued on st, the record of kObsFields sums
+// left in p->d_result (shared by the waiting and the non-waiting calls).
+static qw_status obs_jump_launch(qw_plan_t p, const void* psi0, void* psi_t, int64_t t,
+                                 const double* origin, hipStream_t st) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!psi0 || !origin) return fail(QW_ERR_INVALID, "NULL argument");
+  for (int i = 0; i < p->dim; ++i)
+    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+  r = check_time(t);
+  if (r != QW_OK) return r;
+  void* dst = psi_t;
+  if (!dst) {  // intermediate passes need a field; the result is not kept
+    r = ensure_scratch(p, p->field_bytes);
+    if (r != QW_OK) return r;
+    dst = p->d_scratch;
+  }
+  InstParam ip;
+  ip.m = p->m;
+  ip.n = p->n;
+  ip.t = (double)t;
+  const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
+  if (nb > 0) {
+    const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, psi_t != nullptr);
+    r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, &f);
+    if (r != QW_OK) return r;
+    HIP_TRY(launch_reduce_partials(1, nb, p->d_partials, p->d_partials + nb * kObsFields,
+                                   p->d_result, st));
+  } else {
+    r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, nullptr);
+    if (r != QW_OK) return r;
+    ObsGeom g = obs_geom(p);
+    for (int i = 0; i < p->dim; ++i) g.c[i] = origin[i];
+    HIP_TRY(launch_observables(p->dbl, g, 1, dst, nullptr, nullptr, p->d_partials, p->d_result,
+                               st));
+  }
+  return QW_OK;
+}
+
 qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, int64_t t,
                                     const double* origin, qw_obs* out, void* stream) {
   return traced("qw_evolve_fft_observables", stream, [&]() -> qw_status {
-    qw_status r = check_plan(p);
-    if (r != QW_OK) return r;
-    if (!psi0 || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
-    for (int i = 0; i < p->dim; ++i)
-      if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
-    r = check_time(t);
-    if (r != QW_OK) return r;
+    if (!out) return fail(QW_ERR_INVALID, "NULL argument");
     hipStream_t st = (hipStream_t)stream;
-    void* dst = psi_t;
-    if (!dst) {  // intermediate passes need a field; the result is not kept
-      r = ensure_scratch(p, p->field_bytes);
-      if (r != QW_OK) return r;
-      dst = p->d_scratch;
-    }
-    InstParam ip;
-    ip.m = p->m;
-    ip.n = p->n;
-    ip.t = (double)t;
-    const int64_t nb = (int64_t)p->s * fused_obs_blocks(p);
-    if (nb > 0) {
-      const ObsFuse f = make_fuse(p, origin, nullptr, p->d_partials, psi_t != nullptr);
-      r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, &f);
-      if (r != QW_OK) return r;
-      HIP_TRY(launch_reduce_partials(1, nb, p->d_partials, p->d_partials + nb * kObsFields,
-                                     p->d_result, st));
-    } else {
-      r = evolve_impl(p, 1, psi0, dst, nullptr, ip, st, nullptr);
-      if (r != QW_OK) return r;
-      ObsGeom g = obs_geom(p);
-      for (int i = 0; i < p->dim; ++i) g.c[i] = origin[i];
-      HIP_TRY(launch_observables(p->dbl, g, 1, dst, nullptr, nullptr, p->d_partials, p->d_result,
-                                 st));
-    }
+    qw_status r = obs_jump_launch(p, psi0, psi_t, t, origin, st);
+    if (r != QW_OK) return r;
     HIP_TRY(hipMemcpyAsync(p->h_result, p->d_result, sizeof(double) * kObsFields,
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1689,6 +1709,30 @@ qw_status qw_evolve_fft_observables(qw_plan_t p, const void* psi0, void* psi_t, 
     out->overlap_re = out->overlap_im = out->ref_norm2 = 0.0;
     return QW_OK;
   });
+}
+
+qw_status qw_evolve_fft_observables_async(qw_plan_t p, const void* psi0, void* psi_t, int64_t t,
+                                          const double* origin, double* raw, void* stream) {
+  return traced("qw_evolve_fft_observables_async", stream, [&]() -> qw_status {
+    if (!raw) return fail(QW_ERR_INVALID, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    qw_status r = obs_jump_launch(p, psi0, psi_t, t, origin, st);
+    if (r != QW_OK) return r;
+    HIP_TRY(hipMemcpyAsync(raw, p->d_result, sizeof(double) * kObsFields, hipMemcpyDeviceToHost,
+                           st));
+    return QW_OK;
+  });
+}
+
+qw_status qw_obs_from_raw(qw_plan_t p, const double* raw, const double* origin, qw_obs* out) {
+  qw_status r = check_plan(p);
+  if (r != QW_OK) return r;
+  if (!raw || !origin || !out) return fail(QW_ERR_INVALID, "NULL argument");
+  for (int i = 0; i < p->dim; ++i)
+    if (!isfinite(origin[i])) return fail(QW_ERR_INVALID, "origin is not finite");
+  finish_obs(p, raw, origin, out);
+  out->overlap_re = out->overlap_im = out->ref_norm2 = 0.0;
+  return QW_OK;
 }
 
 // Result slots of a time series: grow to n times (replaced buffers are kept

@@ -291,8 +291,8 @@ struct ObsFuse {
 // not a multiple of 64 threads).
 int64_t strided_obs_blocks(bool dbl, int64_t L, int64_t I);
 // Inverse transform along L (stride I) of B instances of s components,
-// whole fields, with the reductions of `f`. hints: kNtLoad, taken by the
-// LDS-staged form of the pass (the register forms ignore it).
+// whole fields, with the reductions of `f`. hints: kNtLoad, kNtStore, taken
+// by the LDS-staged form of the pass (the register forms ignore them).
 hipError_t launch_fft_strided_obs(bool dbl, int64_t L, void* out, const void* in, int s, int B,
                                   int64_t I, const ObsFuse& f, const void* tw, hipStream_t st,
                                   int hints = 0);

@@ -19,11 +19,12 @@ LIB_PATH = os.path.join(_HERE, "libqw.so")
 
 QW_OK, QW_ERR_INVALID, QW_ERR_UNSUPPORTED, QW_ERR_NOMEM, QW_ERR_DEVICE, QW_ERR_CANCELLED = range(6)
 QW_C64, QW_C128 = 0, 1
+OBS_RAW_DOUBLES = 13  # QW_OBS_RAW_DOUBLES
 DTYPES = {"c64": (QW_C64, torch.complex64), "c128": (QW_C128, torch.complex128)}
 EXPORTS = ("qw_plan", "qw_plan_weyl", "qw_destroy", "qw_step", "qw_step_noalloc",
            "qw_step_batched", "qw_evolve_fft", "qw_evolve_fft_real", "qw_evolve_fft_batched",
            "qw_evolve_fft_timed", "qw_transform", "qw_observables", "qw_evolve_fft_observables",
-           "qw_evolve_fft_series", "qw_newton_wigner",
+           "qw_evolve_fft_observables_async", "qw_obs_from_raw", "qw_evolve_fft_series", "qw_newton_wigner",
            "qw_marginals", "qw_bcc_transform", "qw_bcc_evolve_fft", "qw_bcc_step", "qw_bcc_observables",
            "qw_kspace_drift",
            "qw_prepare_state", "qw_evolve_dispersive", "qw_dispersion_taylor",
@@ -105,6 +106,8 @@ def _load():
                          ctypes.POINTER(i64), ctypes.POINTER(i64), vp],
         "qw_evolve_fft_observables": [vp, vp, vp, i64, ctypes.POINTER(dbl),
                                       ctypes.POINTER(QwObs), vp],
+        "qw_evolve_fft_observables_async": [vp, vp, vp, i64, ctypes.POINTER(dbl), vp, vp],
+        "qw_obs_from_raw": [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(QwObs)],
         "qw_prepare_state": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl, vp],
         "qw_evolve_dispersive": [vp, vp, ctypes.POINTER(dbl), dbl, ctypes.POINTER(dbl), dbl, dbl,
                                  cint, dbl, vp],
@@ -346,6 +349,37 @@ class Plan:
         _check(LIB.qw_evolve_fft_observables(self._h, self._field(psi0, name="psi0"), outp,
                                              int(t), _darr(origin, self.dim), ctypes.byref(o),
                                              _stream(stream)))
+        return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
+                "mean_cart": list(o.mean_cart)}
+
+    def evolve_fft_observables_async(self, psi0, t, origin, raw, out=None, stream=None):
+        """qw_evolve_fft_observables_async: queues psi_t = U^t psi0 (into
+        ``out``, not kept when out is None) and its reductions about origin,
+        whose raw record a copy on the stream leaves in ``raw`` (a pinned CPU
+        float64 tensor of at least OBS_RAW_DOUBLES elements). Returns without
+        waiting; read the record with obs_from_raw once the stream has passed
+        the call."""
+        if (not isinstance(raw, torch.Tensor) or raw.device.type != "cpu" or
+                raw.dtype != torch.float64 or not raw.is_contiguous() or
+                raw.numel() < OBS_RAW_DOUBLES or not raw.is_pinned()):
+            raise ValueError("raw must be a pinned, contiguous CPU float64 tensor of at least "
+                             "%d elements" % OBS_RAW_DOUBLES)
+        outp = self._field(out, name="out") if out is not None else ctypes.c_void_p(0)
+        _check(LIB.qw_evolve_fft_observables_async(self._h, self._field(psi0, name="psi0"), outp,
+                                                   int(t), _darr(origin, self.dim),
+                                                   ctypes.c_void_p(raw.data_ptr()),
+                                                   _stream(stream)))
+
+    def obs_from_raw(self, raw, origin):
+        """qw_obs_from_raw: the dict evolve_fft_observables returns, from a
+        complete raw record (a CPU float64 tensor)."""
+        if raw.device.type != "cpu" or raw.dtype != torch.float64 or raw.numel() < OBS_RAW_DOUBLES:
+            raise ValueError("raw must be a CPU float64 tensor of at least %d elements"
+                             % OBS_RAW_DOUBLES)
+        r = raw.contiguous()
+        o = QwObs()
+        _check(LIB.qw_obs_from_raw(self._h, ctypes.cast(r.data_ptr(), ctypes.POINTER(ctypes.c_double)),
+                                   _darr(origin, self.dim), ctypes.byref(o)))
         return {"norm2": o.norm2, "mean": list(o.mean), "second": list(o.second),
                 "mean_cart": list(o.mean_cart)}
 

@@ -76,6 +76,9 @@ def test_calls_reject_null_plan():
     assert qw.LIB.qw_evolve_fft(None, None, None, 1, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_evolve_fft_observables(None, None, None, 1, None, None, None) == \
         qw.QW_ERR_INVALID
+    assert qw.LIB.qw_evolve_fft_observables_async(None, None, None, 1, None, None, None) == \
+        qw.QW_ERR_INVALID
+    assert qw.LIB.qw_obs_from_raw(None, None, None, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_kspace_drift(None, None, None, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_bcc_step(None, None, 1, None) == qw.QW_ERR_INVALID
     assert qw.LIB.qw_bcc_observables(None, None, None, None, None) == qw.QW_ERR_INVALID
