@@ -82,6 +82,10 @@ static void host_checks() {
   EXPECT_STATUS(qw_newton_wigner(nullptr, f, origin, two, nw, nullptr), QW_ERR_INVALID);
   EXPECT_STATUS(qw_marginals(nullptr, f, io, c, 8, xmin, len, nullptr), QW_ERR_INVALID);
   EXPECT_STATUS(qw_evolve_fft_observables(nullptr, f, f, 1, origin, &obs, nullptr), QW_ERR_INVALID);
+  double raw[QW_OBS_RAW_DOUBLES] = {0};
+  EXPECT_STATUS(qw_evolve_fft_observables_async(nullptr, f, f, 1, origin, raw, nullptr),
+                QW_ERR_INVALID);
+  EXPECT_STATUS(qw_obs_from_raw(nullptr, raw, origin, &obs), QW_ERR_INVALID);
   EXPECT_STATUS(qw_prepare_state(nullptr, f, k0, 2.0, origin, 1, 0, nullptr), QW_ERR_INVALID);
   EXPECT_STATUS(qw_evolve_fft_timed(nullptr, f, f, 1, nullptr, ms, &n), QW_ERR_INVALID);
   EXPECT_STATUS(qw_set_schedule(nullptr, 0, 4, 128, 1), QW_ERR_INVALID);
@@ -138,6 +142,9 @@ static void plan_arg_checks(qw_plan_t p, void* field) {
   EXPECT_STATUS(qw_evolve_fft(p, field, field, (int64_t(1) << 53) + 1, nullptr), QW_ERR_UNSUPPORTED);
   EXPECT_STATUS(qw_evolve_fft_observables(p, field, field, 1, nullptr, &obs, nullptr),
                 QW_ERR_INVALID);
+  EXPECT_STATUS(qw_evolve_fft_observables_async(p, field, field, 1, origin, nullptr, nullptr),
+                QW_ERR_INVALID);
+  EXPECT_STATUS(qw_obs_from_raw(p, nullptr, origin, &obs), QW_ERR_INVALID);
   EXPECT_STATUS(qw_transform(p, field, field, 0, nullptr), QW_ERR_INVALID);
   EXPECT_STATUS(qw_prepare_state(p, field, k0, -1.0, origin, 1, 0, nullptr), QW_ERR_INVALID);
   EXPECT_STATUS(qw_prepare_state(p, field, k0, 2.0, origin, 0, 0, nullptr), QW_ERR_INVALID);
@@ -185,6 +192,17 @@ static void device_run() {
       EXPECT_STATUS(qw_evolve_fft_observables(p, x, z, 1000, ctr, &o1, st), QW_OK);
       EXPECT_STATUS(qw_evolve_fft_observables(p, x, nullptr, 1000, ctr, &o2, st), QW_OK);
       EXPECT(near(o1.norm2, 1.0, tol) && near(o1.mean[0], o2.mean[0], 1e-9));
+      {
+        // pageable record (the copy then completes within the call); pinned
+        // host memory allocated here trips the sanitizer runtime's device
+        // allocator when the HIP runtime unloads at exit
+        double raw[QW_OBS_RAW_DOUBLES];
+        qw_obs o3;
+        EXPECT_STATUS(qw_evolve_fft_observables_async(p, x, z, 1000, ctr, raw, st), QW_OK);
+        EXPECT(hipStreamSynchronize(st) == hipSuccess);
+        EXPECT_STATUS(qw_obs_from_raw(p, raw, ctr, &o3), QW_OK);
+        EXPECT(o3.norm2 == o1.norm2 && o3.mean[0] == o1.mean[0] && o3.second[0] == o1.second[0]);
+      }
       EXPECT_STATUS(qw_evolve_fft_real(p, x, z, 10.5, st), QW_OK);
       int64_t ts[3] = {1000, -3, 1000};
       qw_obs so[3];
