@@ -25,7 +25,8 @@
  * Execution: every call is enqueued on `stream` (a hipStream_t; NULL is the
  * null stream) and returns without waiting, except qw_observables,
  * qw_evolve_fft_observables and qw_prepare_state, which wait for their
- * results, and the batched calls, which wait for `stream` before staging
+ * results (qw_evolve_fft_observables_async is the non-waiting form of the
+ * second), and the batched calls, which wait for `stream` before staging
  * their per-instance parameters. A plan may be used by one stream at a
  * time; distinct plans are independent.
  *
