@@ -542,6 +542,15 @@ static bool use_staged(bool dbl, int sign, int64_t L, int64_t O, int64_t I) {
   return L == 512 || sign < 0;
 }
 
+// The staged kernel of a direction and store form, loads of cache policy AUX.
+template <typename T, int L, int AUX>
+static auto staged_kernel(int sign, bool nt) {
+  return sign > 0 ? (nt ? k_fft_strided_staged<T, L, 1, true, AUX>
+                        : k_fft_strided_staged<T, L, 1, false, AUX>)
+                  : (nt ? k_fft_strided_staged<T, L, -1, true, AUX>
+                        : k_fft_strided_staged<T, L, -1, false, AUX>);
+}
+
 template <typename T, int L>
 static hipError_t run_staged(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
                              const OuterMap& om, const cx<T>* tw, hipStream_t st, int sign) {
@@ -550,17 +559,8 @@ static hipError_t run_staged(cx<T>* out, const cx<T>* in, int64_t O, int64_t I,
   const int64_t ng = (nblk + kStagedTiles - 1) / kStagedTiles;
   if (ng > 0x7fffffffLL) return hipErrorInvalidValue;
   const bool nt = om.hints & kNtStore;
-  auto kern = k_fft_strided_staged<T, L, 1, false>;
-  if (om.hints & kNtLoad)
-    kern = sign > 0 ? (nt ? k_fft_strided_staged<T, L, 1, true, kAuxNt>
-                          : k_fft_strided_staged<T, L, 1, false, kAuxNt>)
-                    : (nt ? k_fft_strided_staged<T, L, -1, true, kAuxNt>
-                          : k_fft_strided_staged<T, L, -1, false, kAuxNt>);
-  else
-    kern = sign > 0 ? (nt ? k_fft_strided_staged<T, L, 1, true>
-                          : k_fft_strided_staged<T, L, 1, false>)
-                    : (nt ? k_fft_strided_staged<T, L, -1, true>
-                          : k_fft_strided_staged<T, L, -1, false>);
+  auto kern = (om.hints & kNtLoad) ? staged_kernel<T, L, kAuxNt>(sign, nt)
+                                   : staged_kernel<T, L, 0>(sign, nt);
   hipLaunchKernelGGL(kern, dim3((unsigned)ng), dim3(512), 0, st, out, in, I, nblk_i, nblk, om, tw);
   return hipGetLastError();
 }
