@@ -448,6 +448,16 @@ def main():
                  "slabs: fft_strided n2 fwd + fft_contig n3 fwd+apply+inv + fft_strided n2 inv",
                  "fft_strided n1 inv"]
         launches = [1, 3 * nslab, 1]
+    # Each pass against HBM peak: algorithmic bytes = the field read and
+    # written once (2 s V b), plus the 8 V bytes of the omega table that the
+    # fused n3 pass reads.
+    pass_roofline = {}
+    if len(pass_ms) == 5:
+        for n, v in zip(names, pass_ms):
+            nbytes = 2 * field_bytes + (8 * V if n.startswith("fft_contig") else 0)
+            gbs = nbytes / (v * 1e-3) / 1e9
+            pass_roofline[n] = {"bytes": nbytes, "GB/s": round(gbs, 1),
+                                "frac": round(gbs / PEAK_HBM_GBS, 4)}
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -523,6 +533,7 @@ def main():
                      "contig_threads": schedule[2], "contig_groups": schedule[3],
                      "autotune_ms_per_evolution": round(tuned_ms, 4)},
         "fft_pass_ms": {n: round(v, 4) for n, v in zip(names, pass_ms)},
+        "fft_pass_roofline": pass_roofline,
         "stencil_site_steps_per_s": round(V / (single_ms * 1e-3), 1),
         "stencil_ms_per_step": round(single_ms, 4),
         "stencil_gbs": round(2 * field_bytes / (single_ms * 1e-3) / 1e9, 1),
